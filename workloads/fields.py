@@ -1,0 +1,144 @@
+"""Seeded synthetic macroscopic states and workload configurations.
+
+Inputs only: primitive fields ``(rho, U_1..U_D, T)`` per cell, shaped like the
+flows of the paper's test cases (Sec. 4: lid-driven cavity, supersonic
+cylinder, supersonic sphere), and the physical/velocity-space parameters of
+each workload.  Nothing here evaluates a distribution function, a moment or a
+gas-model relation: the conversion to conserved variables and the viscosity
+law belong to the two implementations that consume these inputs.
+The published flow solutions are not available, so smooth analytic stand-ins
+with seeded perturbations are used; see the workload recipe in the design doc.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import meshes
+
+
+def prim(rho, U, T):
+    """Stack primitive fields into rows ``(rho, U_1..U_D, T)``."""
+    rho = np.asarray(rho, np.float64)
+    U = np.asarray(U, np.float64)
+    T = np.asarray(T, np.float64)
+    rho, T = np.broadcast_arrays(rho, T)
+    return np.concatenate([rho[..., None], np.broadcast_to(U, rho.shape + U.shape[-1:]), T[..., None]], axis=-1)
+
+
+def uniform(ncells, rho, U, T):
+    return prim(np.full(ncells, rho), np.asarray(U, np.float64), np.full(ncells, T))
+
+
+def perturbed_uniform(ncells, dim, seed, amp=0.05, uamp=0.3):
+    """Unit state with seeded cell-wise random perturbations of rho, U and T."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + amp * rng.uniform(-1, 1, ncells)
+    U = uamp * rng.uniform(-1, 1, (ncells, dim))
+    T = 1.0 + amp * rng.uniform(-1, 1, ncells)
+    return prim(rho, U, T)
+
+
+def normal_shock(Ma, gamma=5.0 / 3.0):
+    """Rankine-Hugoniot ratios (rho2/rho1, u2/u1, T2/T1) across a normal shock."""
+    m2 = Ma * Ma
+    rr = (gamma + 1) * m2 / ((gamma - 1) * m2 + 2)
+    pr = 1 + 2 * gamma / (gamma + 1) * (m2 - 1)
+    return rr, 1.0 / rr, pr / rr
+
+
+def blunt_body_field(ctr, radius, Ma, R, T_inf=1.0, rho_inf=1.0, seed=0, amp=0.02, gamma=5.0 / 3.0):
+    """Bow-shock shaped blend of freestream, post-shock and wake states.
+
+    Flow along +x around a body of ``radius`` at the origin (2-D or 3-D; the
+    distance from the x-axis is used).  Billig-type hyperbolic shock shape,
+    tanh transitions, and seeded +-``amp`` perturbations of rho and T.
+    Returns ``(prim, probes)`` where ``probes`` are the four reference states
+    (freestream, static, post-shock, wake) as primitive rows.
+    """
+    rng = np.random.default_rng(seed)
+    D = ctr.shape[1]
+    U_inf = Ma * math.sqrt(gamma * R * T_inf)
+    rr, ur, Tr = normal_shock(Ma, gamma)
+    x = ctr[:, 0]
+    y = np.sqrt(np.sum(ctr[:, 1:] ** 2, axis=1))
+    standoff = radius * 0.386 * math.exp(4.67 / (Ma * Ma))
+    Rc = radius * 1.386 * math.exp(1.8 / max(Ma - 1.0, 0.3) ** 0.75)
+    beta = math.asin(min(1.0, 1.0 / Ma))
+    xs = -(radius + standoff) + Rc / math.tan(beta) ** 2 * (np.sqrt(1 + (y * math.tan(beta) / Rc) ** 2) - 1)
+    a_sh = 0.5 * (1 + np.tanh((xs - x) / (0.05 * radius)))           # 1 upstream of shock
+    wake = 0.5 * (1 + np.tanh(x / (0.5 * radius))) * np.exp(-(y / (radius * (1.2 + 0.15 * np.maximum(x, 0)))) ** 2)
+    rho_ps, T_ps, u_ps = rho_inf * rr, T_inf * Tr, U_inf * ur
+    rho_w, T_w, u_w = 0.3 * rho_inf, 0.6 * T_ps, 0.2 * U_inf
+    rho = a_sh * rho_inf + (1 - a_sh) * ((1 - wake) * rho_ps + wake * rho_w)
+    T = a_sh * T_inf + (1 - a_sh) * ((1 - wake) * T_ps + wake * T_w)
+    u = a_sh * U_inf + (1 - a_sh) * ((1 - wake) * u_ps + wake * u_w)
+    rho = rho * (1 + amp * rng.uniform(-1, 1, len(x)))
+    T = T * (1 + amp * rng.uniform(-1, 1, len(x)))
+    U = np.zeros((len(x), D))
+    U[:, 0] = u
+    e0 = np.zeros(D)
+    e0[0] = 1.0
+    probes = np.stack([prim(rho_inf, U_inf * e0, T_inf), prim(rho_inf, 0 * e0, T_inf),
+                       prim(rho_ps, u_ps * e0, T_ps), prim(rho_w, u_w * e0, T_w)])
+    return prim(rho, U, T), probes
+
+
+# ---------------------------------------------------------------------------
+# Workload configurations (shapes of the paper's test cases)
+# ---------------------------------------------------------------------------
+
+def cavity(n=32, Ma=0.16, Kn=0.075, omega=0.5, box=5.0, base=16, max_level=2, C1=0.01, cfl=0.8):
+    """2-D lid-driven cavity on the unit square (Sec. 4.2 shape), units sqrt(R T0), R=1."""
+    R, T0, gamma = 1.0, 1.0, 5.0 / 3.0
+    Uw = Ma * math.sqrt(gamma * R * T0)
+    mesh = meshes.box2d(n, n, sides={'left': 0, 'right': 0, 'bottom': 0, 'top': 1},
+                        bcs=[(meshes.WALL, (1.0, 0.0, 0.0, T0)), (meshes.WALL, (1.0, Uw, 0.0, T0))])
+    W0 = uniform(mesh['ncells'], 1.0, (0.0, 0.0), T0)
+    probes = np.stack([prim(1.0, (Uw, 0.0), T0), prim(1.0, (0.0, 0.0), T0)])
+    dt = cfl * (1.0 / n) / box
+    return dict(name='cavity', dim=2, mesh=mesh, prim0=W0, probes=probes,
+                vspace=dict(dim=2, lo=(-box, -box), hi=(box, box), base=(base, base), max_level=max_level),
+                gas=dict(R=R, Pr=2.0 / 3.0, omega=omega, Kn=Kn, L_ref=1.0, rho_ref=1.0, T_ref=T0, model=1),
+                dt=dt, venkat_K=1.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=200)
+
+
+def cylinder(nr=128, nth=256, Ma=5.0, Kn=0.1, omega=0.81, box=15.0, base=32, max_level=3, C1=2e-4, cfl=0.8, seed=0):
+    """2-D supersonic flow past a cylinder (Sec. 4.1 shape), units sqrt(R Tinf) with R=1/2."""
+    R, Tinf, gamma = 0.5, 1.0, 5.0 / 3.0
+    mesh = meshes.ogrid(nr, nth, r0=0.5, r1=15.0, first=0.01)
+    U_inf = Ma * math.sqrt(gamma * R * Tinf)
+    mesh['bc_state'][0] = (1.0, 0.0, 0.0, Tinf)
+    mesh['bc_state'][1] = (1.0, U_inf, 0.0, Tinf)
+    W0, probes = blunt_body_field(mesh['cell_ctr'], 0.5, Ma, R, Tinf, seed=seed)
+    dt = _cfl_dt(mesh, cfl, box)
+    return dict(name='cylinder', dim=2, mesh=mesh, prim0=W0, probes=probes,
+                vspace=dict(dim=2, lo=(-box, -box), hi=(box, box), base=(base, base), max_level=max_level),
+                gas=dict(R=R, Pr=2.0 / 3.0, omega=omega, Kn=Kn, L_ref=1.0, rho_ref=1.0, T_ref=Tinf, model=1),
+                dt=dt, venkat_K=1.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=100)
+
+
+def sphere(nr=64, nth=64, nph=32, Ma=4.0, Kn=0.05, omega=0.74, box=12.0, base=16, max_level=2, C1=2e-5, cfl=0.8, seed=0):
+    """3-D supersonic flow past a sphere (Sec. 4.6 shape), monatomic, R=1/2."""
+    R, Tinf, gamma = 0.5, 1.0, 5.0 / 3.0
+    U_inf = Ma * math.sqrt(gamma * R * Tinf)
+    mesh = meshes.sphere_grid(nr, nth, nph, r0=0.5, r1=8.0, first=0.02,
+                              wall_state=(1.0, 0.0, 0.0, 0.0, Tinf), far_state=(1.0, U_inf, 0.0, 0.0, Tinf))
+    W0, probes = blunt_body_field(mesh['cell_ctr'], 0.5, Ma, R, Tinf, seed=seed)
+    dt = _cfl_dt(mesh, cfl, box)
+    return dict(name='sphere', dim=3, mesh=mesh, prim0=W0, probes=probes,
+                vspace=dict(dim=3, lo=(-box,) * 3, hi=(box,) * 3, base=(base,) * 3, max_level=max_level),
+                gas=dict(R=R, Pr=2.0 / 3.0, omega=omega, Kn=Kn, L_ref=1.0, rho_ref=1.0, T_ref=Tinf, model=1),
+                dt=dt, venkat_K=1.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=50)
+
+
+def _cfl_dt(mesh, cfl, box):
+    """CFL time step: cfl * min_i(V_i / max face area of i) / max |xi| of the box."""
+    nc = mesh['ncells']
+    amax = np.zeros(nc)
+    lr = mesh['face_lr']
+    np.maximum.at(amax, lr[:, 0], mesh['face_area'])
+    inner = lr[:, 1] >= 0
+    np.maximum.at(amax, lr[inner, 1], mesh['face_area'][inner])
+    return cfl * float(np.min(mesh['cell_vol'] / amax)) / box

@@ -1,0 +1,279 @@
+"""Seeded/synthetic physical meshes (geometry only).
+
+Every generator returns a plain dict of NumPy arrays describing a finite-volume
+mesh: cell volumes and centres, and a face list with the two adjacent cells,
+area, unit normal (pointing from the first cell to the second), midpoint and
+a periodic shift.  Nothing here knows about distribution functions, moments
+or the kinetic scheme: this module is the common *input* of the CPU oracle and
+of the GPU library, and it carries none of the method's arithmetic.
+
+Conventions
+-----------
+* ``face_lr[f] = (L, R)``.  For a boundary face ``R = -1 - bc_id`` and the
+  normal points out of the domain (out of ``L``).
+* ``face_shift[f]`` is the vector to add to the centre of ``R`` so that it
+  sits next to ``L`` (non-zero only across a periodic seam of a box).
+* ``bc_kind``: 0 = isothermal diffuse wall, 1 = far field.
+* ``bc_state[b] = (rho, U_1..U_D, T)``; for a wall ``rho`` is ignored.
+* Faces of zero area (poles of a spherical grid) are omitted.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+WALL = 0
+FARFIELD = 1
+
+
+def _finish(dim, vol, ctr, faces, bcs, shape):
+    lr = np.array([f[0] for f in faces], dtype=np.int64).reshape(-1, 2)
+    area = np.array([f[1] for f in faces], dtype=np.float64)
+    nrm = np.array([f[2] for f in faces], dtype=np.float64).reshape(-1, dim)
+    fctr = np.array([f[3] for f in faces], dtype=np.float64).reshape(-1, dim)
+    shift = np.array([f[4] for f in faces], dtype=np.float64).reshape(-1, dim)
+    kinds = np.array([b[0] for b in bcs], dtype=np.int32)
+    state = np.array([b[1] for b in bcs], dtype=np.float64).reshape(len(bcs), dim + 2)
+    return dict(dim=dim, ncells=len(vol), nfaces=len(lr),
+                cell_vol=np.asarray(vol, np.float64), cell_ctr=np.asarray(ctr, np.float64).reshape(-1, dim),
+                face_lr=lr, face_area=area, face_nrm=nrm, face_ctr=fctr, face_shift=shift,
+                nbc=len(bcs), bc_kind=kinds, bc_state=state, shape=tuple(shape))
+
+
+def box2d(nx, ny, lx=1.0, ly=1.0, periodic=(False, False), sides=None, bcs=None):
+    """Uniform Cartesian ``nx x ny`` grid on ``[0,lx] x [0,ly]``.
+
+    ``sides`` maps 'left','right','bottom','top' to a bc id (ignored on a
+    periodic axis); ``bcs`` is the list of ``(kind, state)``.
+    Cells are numbered ``iy*nx + ix`` (x fastest).
+    """
+    dx, dy = lx / nx, ly / ny
+    ix, iy = np.meshgrid(np.arange(nx), np.arange(ny))
+    ctr = np.stack([(ix.ravel() + 0.5) * dx, (iy.ravel() + 0.5) * dy], 1)
+    vol = np.full(nx * ny, dx * dy)
+    sides = sides or {}
+    bcs = bcs or []
+    faces = []
+    cid = lambda i, j: j * nx + i
+    # x-normal faces
+    for j in range(ny):
+        for i in range(nx + 1):
+            fc = (i * dx, (j + 0.5) * dy)
+            if 0 < i < nx:
+                faces.append(((cid(i - 1, j), cid(i, j)), dy, (1.0, 0.0), fc, (0.0, 0.0)))
+            elif i == nx:
+                if periodic[0]:
+                    faces.append(((cid(nx - 1, j), cid(0, j)), dy, (1.0, 0.0), fc, (lx, 0.0)))
+                else:
+                    faces.append(((cid(nx - 1, j), -1 - sides['right']), dy, (1.0, 0.0), fc, (0.0, 0.0)))
+            elif not periodic[0]:
+                faces.append(((cid(0, j), -1 - sides['left']), dy, (-1.0, 0.0), fc, (0.0, 0.0)))
+    # y-normal faces
+    for j in range(ny + 1):
+        for i in range(nx):
+            fc = ((i + 0.5) * dx, j * dy)
+            if 0 < j < ny:
+                faces.append(((cid(i, j - 1), cid(i, j)), dx, (0.0, 1.0), fc, (0.0, 0.0)))
+            elif j == ny:
+                if periodic[1]:
+                    faces.append(((cid(i, ny - 1), cid(i, 0)), dx, (0.0, 1.0), fc, (0.0, ly)))
+                else:
+                    faces.append(((cid(i, ny - 1), -1 - sides['top']), dx, (0.0, 1.0), fc, (0.0, 0.0)))
+            elif not periodic[1]:
+                faces.append(((cid(i, 0), -1 - sides['bottom']), dx, (0.0, -1.0), fc, (0.0, 0.0)))
+    return _finish(2, vol, ctr, faces, bcs, (ny, nx))
+
+
+def box3d(nx, ny, nz, l=(1.0, 1.0, 1.0), periodic=(True, True, True), bc=None):
+    """Uniform Cartesian 3-D grid; non-periodic sides all use bc id 0."""
+    d = [l[0] / nx, l[1] / ny, l[2] / nz]
+    n = (nx, ny, nz)
+    cid = lambda i, j, k: (k * ny + j) * nx + i
+    I, J, K = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing='ij')
+    order = np.argsort(cid(I, J, K).ravel())
+    ctr = np.stack([(I.ravel() + 0.5) * d[0], (J.ravel() + 0.5) * d[1], (K.ravel() + 0.5) * d[2]], 1)[order]
+    vol = np.full(nx * ny * nz, d[0] * d[1] * d[2])
+    faces = []
+    for ax in range(3):
+        o1, o2 = [a for a in range(3) if a != ax]
+        area = d[o1] * d[o2]
+        nrm = [0.0, 0.0, 0.0]
+        nrm[ax] = 1.0
+        for a in range(n[o1]):
+            for b in range(n[o2]):
+                for c in range(n[ax] + 1):
+                    idx = [0, 0, 0]
+                    idx[o1], idx[o2] = a, b
+                    fc = [0.0, 0.0, 0.0]
+                    fc[o1], fc[o2], fc[ax] = (a + 0.5) * d[o1], (b + 0.5) * d[o2], c * d[ax]
+                    def cell(cc):
+                        t = list(idx)
+                        t[ax] = cc
+                        return cid(*t)
+                    if 0 < c < n[ax]:
+                        faces.append(((cell(c - 1), cell(c)), area, tuple(nrm), tuple(fc), (0.0, 0.0, 0.0)))
+                    elif periodic[ax]:
+                        if c == n[ax]:
+                            sh = [0.0, 0.0, 0.0]
+                            sh[ax] = l[ax]
+                            faces.append(((cell(n[ax] - 1), cell(0)), area, tuple(nrm), tuple(fc), tuple(sh)))
+                    else:
+                        if c == n[ax]:
+                            faces.append(((cell(n[ax] - 1), -1), area, tuple(nrm), tuple(fc), (0.0, 0.0, 0.0)))
+                        else:
+                            m = [0.0, 0.0, 0.0]
+                            m[ax] = -1.0
+                            faces.append(((cell(0), -1), area, tuple(m), tuple(fc), (0.0, 0.0, 0.0)))
+    bcs = [bc] if bc is not None else ([] if all(periodic) else [(WALL, (1.0, 0.0, 0.0, 0.0, 1.0))])
+    return _finish(3, vol, ctr, faces, bcs, (nz, ny, nx))
+
+
+def _polygon(pts):
+    """Area and centroid of a simple polygon (counter-clockwise vertices)."""
+    x, y = pts[:, 0], pts[:, 1]
+    xn, yn = np.roll(x, -1), np.roll(y, -1)
+    cr = x * yn - xn * y
+    a = 0.5 * cr.sum()
+    cx = ((x + xn) * cr).sum() / (6 * a)
+    cy = ((y + yn) * cr).sum() / (6 * a)
+    return a, np.array([cx, cy])
+
+
+def geometric_radii(n, r0, r1, first):
+    """``n+1`` radii from r0 to r1 with first spacing ``first`` and constant growth."""
+    lo, hi = 1.0 + 1e-12, 2.0
+    for _ in range(200):
+        q = 0.5 * (lo + hi)
+        s = first * (q ** n - 1.0) / (q - 1.0)
+        if s > r1 - r0:
+            hi = q
+        else:
+            lo = q
+    q = 0.5 * (lo + hi)
+    r = r0 + first * (q ** np.arange(n + 1) - 1.0) / (q - 1.0)
+    r[-1] = r1
+    return r
+
+
+def ogrid(nr, nth, r0=0.5, r1=15.0, first=0.01, wall_bc=(WALL, None), far_bc=(FARFIELD, None)):
+    """Body-fitted O-grid around a circle of radius ``r0`` (straight-edged quads).
+
+    Cells are numbered ``ir*nth + it`` (circumferential index fastest); the
+    grid closes on itself in theta, so the seam needs no shift.  bc 0 is the
+    body (wall), bc 1 the outer far-field circle.
+    """
+    r = geometric_radii(nr, r0, r1, first)
+    th = np.linspace(0.0, 2 * np.pi, nth + 1)
+    P = lambda i, j: np.array([r[i] * np.cos(th[j % nth]), r[i] * np.sin(th[j % nth])])
+    vol = np.empty(nr * nth)
+    ctr = np.empty((nr * nth, 2))
+    for i in range(nr):
+        for j in range(nth):
+            a, c = _polygon(np.stack([P(i, j), P(i + 1, j), P(i + 1, j + 1), P(i, j + 1)]))
+            vol[i * nth + j], ctr[i * nth + j] = a, c
+    faces = []
+    cid = lambda i, j: i * nth + (j % nth)
+
+    def seg(p, q):
+        t = q - p
+        L = np.hypot(t[0], t[1])
+        return L, (t[1] / L, -t[0] / L), tuple(0.5 * (p + q))
+    # radial-direction faces (constant r): between ir-1 and ir; normal +r
+    for i in range(nr + 1):
+        for j in range(nth):
+            p, q = P(i, j), P(i, j + 1)    # oriented so that (dy,-dx) points outward (+r)
+            L, n, fc = seg(p, q)
+            if 0 < i < nr:
+                faces.append(((cid(i - 1, j), cid(i, j)), L, n, fc, (0.0, 0.0)))
+            elif i == nr:
+                faces.append(((cid(nr - 1, j), -1 - 1), L, n, fc, (0.0, 0.0)))
+            else:
+                faces.append(((cid(0, j), -1 - 0), L, (-n[0], -n[1]), fc, (0.0, 0.0)))
+    # circumferential faces (constant theta): between it-1 and it; normal +theta
+    for i in range(nr):
+        for j in range(nth):
+            p, q = P(i, j), P(i + 1, j)    # (dy,-dx) of an outward ray points to -theta
+            L, n, fc = seg(p, q)
+            faces.append(((cid(i, j - 1), cid(i, j)), L, (-n[0], -n[1]), fc, (0.0, 0.0)))
+    bcs = [(WALL, wall_bc[1] if wall_bc[1] is not None else (1.0, 0.0, 0.0, 1.0)),
+           (FARFIELD, far_bc[1] if far_bc[1] is not None else (1.0, 0.0, 0.0, 1.0))]
+    m = _finish(2, vol, ctr, faces, bcs, (nr, nth))
+    m['radii'] = r
+    return m
+
+
+def _quad_area_vec(p0, p1, p2, p3):
+    """Area vector (|a| = area, direction = right-hand normal) of a planar quad."""
+    return 0.5 * np.cross(p2 - p0, p3 - p1)
+
+
+def sphere_grid(nr, nth, nph, r0=0.5, r1=8.0, first=0.02, wall_state=None, far_state=None):
+    """Body-fitted spherical grid around a sphere of radius ``r0``.
+
+    Polar angle theta in [0, pi] (``nth`` cells), azimuth phi in [0, 2 pi)
+    (``nph`` cells, closed), radius geometric.  All faces are planar quads;
+    the zero-area faces on the polar axis are omitted.  Cells are numbered
+    ``(ir*nth + ith)*nph + iph``.  bc 0 = body wall, bc 1 = far field.
+    """
+    r = geometric_radii(nr, r0, r1, first)
+    th = np.linspace(0.0, np.pi, nth + 1)
+    ph = np.linspace(0.0, 2 * np.pi, nph + 1)
+
+    def P(i, j, k):
+        return r[i] * np.array([np.sin(th[j]) * np.cos(ph[k % nph]), np.sin(th[j]) * np.sin(ph[k % nph]), np.cos(th[j])])
+    cid = lambda i, j, k: (i * nth + j) * nph + (k % nph)
+    N = nr * nth * nph
+    vol = np.zeros(N)
+    ctr = np.zeros((N, 3))
+    faces = []
+    # per cell corner sets (for volume/centroid): accumulate from faces
+    acc_v = np.zeros(N)
+    acc_c = np.zeros((N, 3))
+
+    def add_face(cl, cr, quad, shift=(0.0, 0.0, 0.0)):
+        av = _quad_area_vec(*quad)
+        a = np.linalg.norm(av)
+        fc = np.mean(quad, axis=0)
+        if a <= 1e-14 * r1 * r1:
+            return
+        n = av / a
+        faces.append(((cl, cr), a, tuple(n), tuple(fc), shift))
+        # divergence theorem: V = 1/3 sum x_f . A_f n_f (signed per side)
+        acc_v[cl] += np.dot(fc, av) / 3.0
+        if cr >= 0:
+            acc_v[cr] -= np.dot(fc, av) / 3.0
+    # r-faces (normal +r): quad ordered so area vector points outward
+    for i in range(nr + 1):
+        for j in range(nth):
+            for k in range(nph):
+                q = [P(i, j, k), P(i, j + 1, k), P(i, j + 1, k + 1), P(i, j, k + 1)]
+                if 0 < i < nr:
+                    add_face(cid(i - 1, j, k), cid(i, j, k), q)
+                elif i == nr:
+                    add_face(cid(nr - 1, j, k), -1 - 1, q)
+                else:
+                    add_face(cid(0, j, k), -1 - 0, q[::-1])
+    # theta-faces (normal +theta), interior only (poles have zero area)
+    for i in range(nr):
+        for j in range(1, nth):
+            for k in range(nph):
+                q = [P(i, j, k), P(i, j, k + 1), P(i + 1, j, k + 1), P(i + 1, j, k)]
+                add_face(cid(i, j - 1, k), cid(i, j, k), q)
+    # phi-faces (normal +phi), closed ring
+    for i in range(nr):
+        for j in range(nth):
+            for k in range(nph):
+                q = [P(i, j, k), P(i + 1, j, k), P(i + 1, j + 1, k), P(i, j + 1, k)]
+                add_face(cid(i, j, k - 1), cid(i, j, k), q)
+    # fix orientation: make every interior normal point from L to R (by centre test)
+    vol[:] = acc_v
+    # centroid approximated by the mean of the 8 corners
+    for i in range(nr):
+        for j in range(nth):
+            for k in range(nph):
+                pts = [P(a, b, c) for a in (i, i + 1) for b in (j, j + 1) for c in (k, k + 1)]
+                ctr[cid(i, j, k)] = np.mean(pts, axis=0)
+    ws = wall_state if wall_state is not None else (1.0, 0.0, 0.0, 0.0, 1.0)
+    fs = far_state if far_state is not None else (1.0, 0.0, 0.0, 0.0, 1.0)
+    m = _finish(3, vol, ctr, faces, [(WALL, ws), (FARFIELD, fs)], (nr, nth, nph))
+    m['radii'] = r
+    return m
