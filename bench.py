@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Throughput of the adaptive-velocity-space sweep on one MI355X.
+
+Workload: 2-D Ma 5 flow past a cylinder (the shape of the paper's Sec. 4.1
+case): body-fitted O-grid 128 (r) x 256 (theta), outer radius 15 D, quadtree
+velocity mesh on [-15, 15]^2 with 32^2 roots and 3 levels, C1 calibrated so
+that the step-0 tree holds about ``--leaves`` leaves.  Synthetic seeded
+bow-shock state (no flow data is available).
+
+One timed step = one adaptation cycle of the hot path: ``--nu`` explicit
+sweeps (reconstruction, interface flux, moments, conservative Shakhov
+relaxation), then the criterion, the new tree and remap plan, and the
+consanguinity remap with its conservation correction.  ``value`` counts
+cells x leaves x sweeps per second of that whole cycle, inputs resident in
+HBM.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell×velocity-node updates/s, FP64 plain vs FP32/batched form; % HBM roofline"
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--nu", type=int, default=20, help="sweeps per adaptation cycle")
+    p.add_argument("--leaves", type=int, default=20000, help="target leaf count of the step-0 tree")
+    p.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    p.add_argument("--forms", action="store_true", help="also time the FP32 form")
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--nr", type=int, default=128)
+    p.add_argument("--nth", type=int, default=256)
+    p.add_argument("--C1", type=float, default=None, help="skip calibration and use this C1")
+    return p.parse_args()
+
+
+class Workload:
+    def __init__(self, args, precision):
+        import torch
+        from paper_2212_05645_amd import avs
+        from workloads import fields as F
+        self.torch, self.avs = torch, avs
+        self.cfg = F.cylinder(nr=args.nr, nth=args.nth)
+        c = self.cfg
+        cap = 32 * 32 * 64
+        self.cs = avs.Case(c['mesh'], c['vspace'], c['gas'], c['dt'], c['venkat_K'], c['prim0'],
+                           precision=avs.AVS_FP32 if precision == "fp32" else avs.AVS_FP64, leaf_capacity=cap)
+        L = self.cs.leaves()
+        self.base_level, self.base_idx = L['level'].copy(), L['idx'].copy()
+        self.W0 = self.cs.get_W()
+        self.nc = self.cs.nc
+
+    def tree(self, C1):
+        """Step-0 tree: roots, then one adaptation per level on cells and probes."""
+        cs, c = self.cs, self.cfg
+        cs.set_leaves(self.base_level, self.base_idx)
+        cs.set_state(None, self.W0)
+        for _ in range(c['vspace']['max_level']):
+            try:
+                cs.adapt(C1, math.exp(-8.0) * C1, probes=c['probes'])
+            except self.avs.AvsError as e:
+                if e.status == self.avs.AVS_E_CAPACITY:
+                    return None
+                raise
+            cs.remap(2)
+        cs.set_state(None, self.W0)
+        return cs.nleaves()
+
+    def calibrate(self, target):
+        lo, hi = -8.0, -1.0
+        best = None
+        for it in range(16):
+            mid = 0.5 * (lo + hi)
+            n = self.tree(10.0 ** mid)
+            log(f"calibrate: C1=1e{mid:.4f} -> {n} leaves")
+            if n is None or n > target:
+                lo = mid
+            else:
+                hi = mid
+                best = (10.0 ** mid, n)
+            if best and abs(best[1] - target) < 0.02 * target:
+                break
+        return best[0]
+
+
+def timed_cycles(w, C1, nu, steps, warmup):
+    torch, cs = w.torch, w.cs
+    stream = cs.stream
+    C2 = math.exp(-8.0) * C1
+    for k in range(warmup):
+        cs.step(nu)
+        cs.adapt(C1, C2)
+        cs.remap(2)
+        log(f"warmup cycle {k} done, {cs.nleaves()} leaves")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    updates = 0
+    leaves = []
+    e0.record(stream)
+    for k in range(steps):
+        nv = cs.nleaves()
+        leaves.append(nv)
+        cs.step(nu)
+        cs.adapt(C1, C2)
+        cs.remap(2)
+        updates += w.nc * nv * nu
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log(f"timed {steps} cycles: {ms:.1f} ms, leaves {leaves}")
+    return updates, ms, leaves
+
+
+def sweep_only(w, nsweep):
+    torch, cs = w.torch, w.cs
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nv = cs.nleaves()
+    e0.record(cs.stream)
+    cs.step(nsweep)
+    e1.record(cs.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return w.nc * nv * nsweep / (ms * 1e-3), ms / nsweep, nv
+
+
+def kernel_profile(w, C1, nu):
+    cs = w.cs
+    nv = cs.nleaves()
+    cs.profile(True)
+    cs.step(nu)
+    cs.adapt(C1, math.exp(-8.0) * C1)
+    cs.remap(2)
+    prof = cs.profile_read()
+    cs.profile(False)
+    return prof, nv
+
+
+def vdf_bytes_per_node(P, es):
+    """Algorithmic HBM bytes per (cell, leaf) per launch of each VDF kernel."""
+    return {"passA": P * es, "passC": 2 * P * es, "criterion": P * es, "remap_gather": 2 * P * es,
+            "remap_correct": 2 * P * es, "moments": P * es}
+
+
+def cpu_baseline(w, ncell_sample=16):
+    """Oracle (FP64 NumPy) updating a contiguous block of cells of the same
+    workload and leaf set, given its two-ring neighbourhood."""
+    import numpy as np
+    from oracle import avs_oracle as O
+    from workloads import meshes
+    c = w.cfg
+    L = w.cs.leaves()
+    mid = w.nc // 2
+    sample = list(range(mid, mid + ncell_sample))
+    sub, keep = meshes.submesh(c['mesh'], sample, halo=2)
+    o = O.Solver(sub, c['vspace'], c['gas'], c['dt'], c['venkat_K'], c['prim0'][keep])
+    o.tree = O.Tree(2, o.tree.lo, o.tree.hi, o.tree.base, o.tree.max_level, L['level'].astype(np.int64),
+                    L['idx'].astype(np.int64))
+    o.phi = o.initial_vdf(o.W)
+    loc = [int(np.searchsorted(keep, g)) for g in sample]
+    threads = os.environ.get("OMP_NUM_THREADS", "1")
+    t0 = time.perf_counter()
+    O.step(o.mesh, o.tree, o.gas, o.dt, o.Kv, o.phi, o.W, cells=loc)
+    dt = time.perf_counter() - t0
+    return {"value": len(sample) * L['n'] / dt, "unit": "cell-node updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one explicit step of {len(sample)} contiguous cells x {L['n']} leaves of the same workload "
+                      f"(NumPy FP64, single thread; BLAS threads={threads}), {dt:.2f} s"}
+
+
+def run_form(args, precision, C1=None):
+    w = Workload(args, precision)
+    if C1 is None:
+        C1 = args.C1 if args.C1 is not None else w.calibrate(args.leaves)
+    n0 = w.tree(C1)
+    log(f"{precision}: C1={C1:.6g}, step-0 tree {n0} leaves")
+    updates, ms, leaves = timed_cycles(w, C1, args.nu, args.steps, args.warmup)
+    sw_rate, sw_ms, sw_nv = sweep_only(w, args.nu)
+    prof, pnv = kernel_profile(w, C1, args.nu)
+    return w, C1, dict(updates=updates, ms=ms, leaves=leaves, sweep_rate=sw_rate, sweep_ms=sw_ms, sweep_leaves=sw_nv,
+                       prof=prof, prof_leaves=pnv)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is a design note, "
+              f"not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w, C1, r = run_form(args, args.precision)
+    P, es = 2, (8 if args.precision == "fp64" else 4)
+    prof = r["prof"]
+    nv = r["prof_leaves"]
+    kern = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1]} for k, v in prof.items()}
+    bpn = vdf_bytes_per_node(P, es)
+    dom = max(prof, key=lambda k: prof[k][0])
+    roof_k = dom if dom in bpn else "passC"
+    t_launch = prof[roof_k][0] / prof[roof_k][1] * 1e-3
+    alg = bpn[roof_k] * w.nc * nv
+    achieved = alg / t_launch
+    roofline = {"bound": "hbm", "kernel": roof_k, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": None,
+                "bytes_per_launch": alg, "algorithmic_bytes_per_node": bpn[roof_k], "dominant_kernel": dom}
+    for k in kern:
+        if k in bpn:
+            kern[k]["GB/s"] = bpn[k] * w.nc * nv / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
+    value = r["updates"] / (r["ms"] * 1e-3)
+    forms = {args.precision: {"cycle_updates_per_s": value, "sweep_updates_per_s": r["sweep_rate"],
+                              "sweep_ms": r["sweep_ms"], "leaves": r["sweep_leaves"]}}
+    if args.forms:
+        other = "fp32" if args.precision == "fp64" else "fp64"
+        del w
+        torch.cuda.empty_cache()
+        w2, _, r2 = run_form(args, other, C1=C1)
+        forms[other] = {"cycle_updates_per_s": r2["updates"] / (r2["ms"] * 1e-3), "sweep_updates_per_s": r2["sweep_rate"],
+                        "sweep_ms": r2["sweep_ms"], "leaves": r2["sweep_leaves"],
+                        "kernels": {k: v[0] / v[1] for k, v in r2["prof"].items()}}
+        w = w2
+    cpu = None
+    if not args.no_cpu:
+        try:
+            cpu = cpu_baseline(w)
+        except Exception as e:  # the baseline is informative only
+            cpu = {"error": repr(e)}
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-node updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms"] / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic (seeded bow-shock state; no flow data available)",
+        "config": {"workload": f"cylinder Ma 5, O-grid {args.nr}x{args.nth}, quadtree 32^2 roots x 3 levels on "
+                               f"[-15,15]^2, C1={C1:.4g}, {args.nu} sweeps + adapt + remap per step",
+                   "cells": w.nc, "leaves": r["leaves"], "precision": args.precision},
+        "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "kernels": kern,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * avs.h -- C ABI of the MI355X (gfx950) global adaptive-velocity-space sweep.
+ *
+ * The library advances the reduced distribution functions (G, H in 2-D; G in
+ * 3-D) of a monatomic gas on ONE velocity mesh shared by every physical cell
+ * (the paper's "global velocity mesh", Sec. 1 and Sec. 3), over a
+ * finite-volume physical mesh, and adapts that velocity mesh with the
+ * quadtree/octree split/merge rules of Sec. 3.
+ *
+ * Paper: J. Chen, S. Liu, R. Zhang, C. Zhong, Y. Yang, C. Zhuo, "A global
+ * adaptive velocity space for general discrete velocity framework in
+ * predictions of rarefied and multi-scale flows", arXiv:2212.05645.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  The library never allocates device memory.  The caller provides
+ *   two device regions at init: the VDF region (size avs_vdf_bytes) and a
+ *   workspace (size avs_workspace_bytes); both must stay alive and untouched
+ *   by the caller until avs_destroy.  Arguments named *_host are host
+ *   pointers, *_dev device pointers.
+ * Layout.  VDF values are stored component-major, cell-major, leaf-fastest:
+ *   vdf[comp][cell][leaf] with a row stride of avs_leaves().ld elements.
+ *   Leaves are kept in depth-first (Morton) order of the velocity forest.
+ *   Conserved variables W = (rho, rho U_1..U_D, rho E) (Eq. updat_W);
+ *   primitive rows are (rho, U_1..U_D, T).
+ * Streams.  All device work is enqueued on the stream given at init
+ *   (a hipStream_t passed as void*, NULL = default stream).  A call waits for
+ *   the device only when it returns a *_host output or says so below.
+ * Errors.  Arguments are validated before any device work.  On a non-OK
+ *   return the state is unchanged, except AVS_E_HIP and AVS_E_NUMERIC found
+ *   after device work, which leave the context in the failed state
+ *   (AVS_E_STATE on every later call except avs_destroy / avs_last_error).
+ *   avs_last_error() returns a message for the calling thread's last error.
+ * Threads.  A context is not thread-safe; separate contexts are independent.
+ * Units.  Non-dimensional; the gas constant R is a parameter.
+ */
+#ifndef AVS_H
+#define AVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t avs_status;
+#define AVS_OK 0
+#define AVS_E_INVALID (-1)   /* bad argument or unsupported mesh */
+#define AVS_E_CAPACITY (-2)  /* the adapted velocity mesh would exceed leaf_capacity */
+#define AVS_E_HIP (-3)       /* a HIP runtime call failed */
+#define AVS_E_STATE (-4)     /* call not valid in the current state */
+#define AVS_E_NUMERIC (-5)   /* non-positive density/temperature or singular moment system */
+
+#define AVS_BC_WALL 0        /* isothermal, fully diffuse wall (zero net mass flux) */
+#define AVS_BC_FARFIELD 1    /* incoming molecules from the far-field Maxwellian */
+
+#define AVS_FP64 0
+#define AVS_FP32 1
+
+#define AVS_COPY 0
+#define AVS_SPLIT 1
+#define AVS_MERGE 2
+
+typedef struct avs_ctx avs_ctx;
+
+/* Velocity space: a forest of base[0] x base[1] (x base[2]) level-0 roots on
+ * the box [lo, hi] (Sec. 3.1); each root may be split down max_level levels.
+ * leaf_capacity bounds the number of leaves any adaptation may produce. */
+typedef struct {
+  int32_t dim;             /* 2 or 3 */
+  int32_t max_level;       /* 0..12 */
+  int32_t base[3];         /* roots per axis, >= 1 */
+  double lo[3], hi[3];     /* velocity box */
+  int64_t leaf_capacity;   /* >= number of roots */
+} avs_vspace;
+
+/* Gas model (Sec. 2.1-2.2): relaxation time tau = mu_ref (T/T_ref)^omega /
+ * (rho R T) (Eq. equ3); model 0 = BGK target, 1 = Shakhov target with
+ * Prandtl number Pr (Eqs. equ14-equ17). */
+typedef struct {
+  double R, Pr, omega, mu_ref, T_ref;
+  int32_t model;
+} avs_gas;
+
+/* Finite-volume mesh, host arrays, copied at init.  face_lr[f] = (L, R); a
+ * boundary face has R = -1 - bc_id and its normal points out of L.  Normals
+ * are unit vectors from L to R.  face_shift (may be NULL) is added to the
+ * centre of R to place it next to L across a periodic seam.  Every cell may
+ * have at most 4 faces in 2-D and 6 in 3-D.  bc_state rows are primitive
+ * (rho, U, T); rho is ignored for walls. */
+typedef struct {
+  int32_t dim;
+  int64_t ncells, nfaces;
+  const double *cell_vol;   /* [ncells] */
+  const double *cell_ctr;   /* [ncells][dim] */
+  const int64_t *face_lr;   /* [nfaces][2] */
+  const double *face_area;  /* [nfaces] */
+  const double *face_nrm;   /* [nfaces][dim] */
+  const double *face_ctr;   /* [nfaces][dim] */
+  const double *face_shift; /* [nfaces][dim] or NULL */
+  int32_t nbc;
+  const int32_t *bc_kind;   /* [nbc] AVS_BC_* */
+  const double *bc_state;   /* [nbc][dim+2] */
+} avs_pmesh;
+
+/* Numerical options.  dt > 0 is the time step; venkat_K the constant of the
+ * Venkatakrishnan limiter, eps^2 = (K V^(1/D))^3.  precision selects the VDF
+ * storage/flux type (AVS_FP64, or AVS_FP32 with FP64 conserved variables). */
+typedef struct {
+  int32_t precision;
+  double dt;
+  double venkat_K;
+} avs_opts;
+
+/* Reference viscosity for a Knudsen number Kn = lambda / L_ref at the state
+ * (rho_ref, T_ref) (Eqs. equ4, equ5). */
+double avs_mu_ref_from_kn(double Kn, double omega, double R, double T_ref, double rho_ref, double L_ref);
+
+/* Bytes the caller must provide for the two VDF buffers / the workspace. */
+size_t avs_vdf_bytes(const avs_vspace *vs, const avs_pmesh *pm, const avs_opts *op);
+size_t avs_workspace_bytes(const avs_vspace *vs, const avs_pmesh *pm, const avs_opts *op);
+
+/* Create a context on the level-0 forest and set phi = closure(g_eq(W0), W0)
+ * per cell (conservative discrete Maxwellian of the initial state), with W0
+ * built from prim0_host [ncells][dim+2].  Copies every host array; waits for
+ * the device before returning. */
+avs_status avs_init_mesh(const avs_vspace *vs, const avs_pmesh *pm, const avs_gas *gas, const avs_opts *op,
+                         const double *prim0_host, void *vdf_dev, size_t vdf_bytes, void *workspace_dev,
+                         size_t workspace_bytes, void *hip_stream, avs_ctx **out);
+
+/* Advance nsteps explicit steps (Sec. 2.3 with the implicit flux increments
+ * dropped): upwind limited reconstruction at x_f - xi dt/2, interface
+ * moments and Shakhov equilibrium, interface VDF of Eq. equ28, finite-volume
+ * update of W (Eq. equ18), relaxation of every node towards the
+ * moment-closed Shakhov target.  residual_host (or NULL) receives
+ * |W^{n+1} - W^n|_2 / dt per conserved component for the last step; a
+ * non-NULL residual makes the call wait and report AVS_E_NUMERIC if any cell
+ * went non-physical. */
+avs_status avs_step(avs_ctx *ctx, int32_t nsteps, double *residual_host);
+
+/* Per-cell fields (rho, U_1..U_D, T, q_1..q_D) into fields_dev
+ * [ncells][2*dim+2] (rho, U, T from the authoritative W; q = heat flux of the
+ * VDF about U, Eq. equ8) and/or the FP64 totals sum_i V_i W_i into
+ * totals_host [dim+2] (waits).  Either pointer may be NULL. */
+avs_status avs_moments(avs_ctx *ctx, double *fields_dev, double *totals_host);
+
+/* Adaptation (Sec. 3.4): M_k = max over cells (and over the nprobes probe
+ * states, primitive rows whose VDF is the discrete Maxwellian) of
+ * max(M1, M2) (Eqs. criterion_rho, criterion_e, criterion_mk); split if
+ * M_k > C1 below max_level, merge a full brother group if all its members
+ * have M_k < C2 (Sec. 3.1), keep otherwise.  Builds the new leaf list and
+ * the remap plan on the device.  flags_dev (or NULL) receives the effective
+ * flag per current leaf (-1 merge, 0 keep, +1 split).  Waits; *n_new_host
+ * gets the new leaf count.  Returns AVS_E_CAPACITY (plan discarded) if it
+ * exceeds leaf_capacity. */
+avs_status avs_adapt(avs_ctx *ctx, double C1, double C2, const double *probes_host, int32_t nprobes,
+                     int8_t *flags_dev, int64_t *n_new_host);
+
+/* Apply the plan of the last avs_adapt: consanguinity remap (Sec. 3.2; a
+ * child copies its parent, a merged parent is the pairwise mean of its
+ * children), then correction 0 = none, 1 = f' + g_eq(W) - g_eq(W') (Sec. 3.3),
+ * 2 = that plus the closure that restores M[f] = W to round-off. */
+avs_status avs_remap(avs_ctx *ctx, int32_t correction);
+
+/* Current velocity mesh.  *n_host = leaf count, *ld_host = VDF row stride.
+ * Optional outputs (NULL to skip), host arrays of n entries: level, index at
+ * that level ([n][dim]), centre ([n][dim]) and weight (area/volume). */
+avs_status avs_leaves(avs_ctx *ctx, int64_t *n_host, int64_t *ld_host, int32_t *level_host, int32_t *idx_host,
+                      double *xi_host, double *w_host);
+
+/* Remap plan of the last avs_adapt (host arrays of n_new entries). */
+avs_status avs_plan(avs_ctx *ctx, int32_t *kind_host, int64_t *src_host, int32_t *child_host);
+
+/* M_k of the last avs_adapt, [n_old] host doubles. */
+avs_status avs_criterion(avs_ctx *ctx, double *Mk_host);
+
+/* Replace the velocity mesh by the given leaves (host, depth-first order,
+ * validated) and reset phi = closure(g_eq(W), W) from the current W. */
+avs_status avs_set_leaves(avs_ctx *ctx, int64_t n, const int32_t *level_host, const int32_t *idx_host);
+
+/* Copy the state out / in.  vdf_host is [P][ncells][n] FP64 (P = 2 in 2-D,
+ * 1 in 3-D; converted from/to the storage type), W_host is [ncells][dim+2].
+ * avs_set_state with vdf_host == NULL sets phi = closure(g_eq(W), W).
+ * Either pointer of avs_get_state may be NULL.  Both wait. */
+avs_status avs_get_state(avs_ctx *ctx, double *vdf_host, double *W_host);
+avs_status avs_set_state(avs_ctx *ctx, const double *vdf_host, const double *W_host);
+
+/* VDF rows of selected cells, [P][ncell_sel][n] FP64 host (waits). */
+avs_status avs_get_cells(avs_ctx *ctx, int64_t ncell_sel, const int64_t *cells_host, double *vdf_host);
+
+/* Measurement support (not part of the method).  avs_profile(ctx, 1) waits
+ * for the stream, clears earlier records and brackets every subsequent kernel
+ * group of the context with a pair of HIP events on its stream; 0 stops.
+ * avs_profile_read waits and writes, for at most nmax kernel groups that ran,
+ * a name (32 chars per entry in names_host), the summed milliseconds and the
+ * number of launches; it returns the number of entries or -1 on error. */
+avs_status avs_profile(avs_ctx *ctx, int32_t enable);
+int32_t avs_profile_read(avs_ctx *ctx, int32_t nmax, char *names_host, double *ms_host, int64_t *count_host);
+
+/* Release the context (never frees caller memory). */
+void avs_destroy(avs_ctx *ctx);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *avs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AVS_H */

@@ -329,13 +329,36 @@ def limited_gradient(i, phi, mesh, Kv):
     for s in slots:
         d2 = grad @ s.d
         d1 = np.where(d2 > 0, pmax - p_i, pmin - p_i)
-        with np.errstate(divide='ignore', invalid='ignore'):
-            psi = ((d1 * d1 + eps2) * d2 + 2.0 * d2 * d2 * d1) / (d2 * (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2))
-        psi = np.where(d2 == 0.0, 1.0, psi)
-        lim = np.minimum(lim, psi)
+        lim = np.minimum(lim, venkat_psi(d1, d2, eps2))
     if not slots:
         lim[:] = 1.0
     return lim[..., None] * grad
+
+
+def normal_speed(xi, n):
+    """s_k = xi_k . n as the ordered sum xi_1 n_1 + xi_2 n_2 (+ xi_3 n_3),
+    without fused multiply-adds: the sign of s decides the upwind side, so it
+    is evaluated exactly the same way wherever it is compared with zero."""
+    s = xi[:, 0] * n[0]
+    for d in range(1, xi.shape[1]):
+        s = s + xi[:, d] * n[d]
+    return s
+
+
+def venkat_psi(d1, d2, eps2):
+    """psi = [(D1^2+eps^2) D2 + 2 D2^2 D1] / [D2 (D1^2 + 2 D2^2 + D1 D2 + eps^2)], 1 if D2 = 0.
+
+    Evaluated after dividing through by D2, and for eps = 0 through the ratio
+    t = D2/D1 >= 0 as (1 + 2t) / (1 + t + 2t^2) (0 when D1 = 0): the same
+    function, but without the underflow of D2^3 for VDF values near 1e-300.
+    """
+    with np.errstate(divide='ignore', invalid='ignore', over='ignore'):
+        if eps2 > 0:
+            psi = (d1 * d1 + eps2 + 2.0 * d1 * d2) / (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2)
+        else:
+            t = d2 / d1
+            psi = np.where(d1 == 0.0, 0.0, (1.0 + 2.0 * t) / (1.0 + t + 2.0 * t * t))
+    return np.where(d2 == 0.0, 1.0, psi)
 
 
 def reconstruct(phi_c, lg_c, d, xi, h):
@@ -367,7 +390,7 @@ def face_vdf(f, phi, LG, mesh, xi, A, gas, dt):
     D = mesh.dim
     L, R = int(mesh.lr[f, 0]), int(mesh.lr[f, 1])
     n = mesh.nrm[f]
-    s = xi @ n
+    s = normal_speed(xi, n)
     slotL = next(sl for sl in mesh.slots[L] if sl.face == f and sl.sigma > 0)
     recL = reconstruct(phi[:, L, :], LG[L], slotL.d, xi, h)
     if R >= 0:
@@ -397,7 +420,7 @@ def face_vdf(f, phi, LG, mesh, xi, A, gas, dt):
 
 def flux_moments(phi_f, xi, A, n):
     """F = sum_k A_k (xi_k . n) (G, xi G, (|xi|^2 G + H)/2) at the face."""
-    s = xi @ n
+    s = normal_speed(xi, n)
     return moments(phi_f * s[None, :], xi, A)
 
 
@@ -447,7 +470,7 @@ def step(mesh, tree, gas, dt, Kv, phi, W, cells=None):
         for s in mesh.slots[i]:
             af = s.sigma * mesh.area[s.face]
             Fsum += af * F[s.face]
-            div += af * (xi @ mesh.nrm[s.face])[None, :] * phif[s.face]
+            div += af * normal_speed(xi, mesh.nrm[s.face])[None, :] * phif[s.face]
         Wn1 = W[i] - dt / mesh.vol[i] * Fsum
         rho, U, T = primitive(Wn1, gas.R)
         if not (rho > 0 and T > 0):

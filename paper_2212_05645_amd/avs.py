@@ -1,0 +1,275 @@
+"""ctypes binding of libavs (include/avs.h).
+
+Argument marshalling only: every computation runs in the HIP library.
+PyTorch provides the device memory (VDF region and workspace) and the HIP
+stream.  Importing this module loads ``libavs.so`` from this package
+directory and raises if it has not been built (``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libavs.so")
+
+AVS_OK, AVS_E_INVALID, AVS_E_CAPACITY, AVS_E_HIP, AVS_E_STATE, AVS_E_NUMERIC = 0, -1, -2, -3, -4, -5
+AVS_FP64, AVS_FP32 = 0, 1
+AVS_COPY, AVS_SPLIT, AVS_MERGE = 0, 1, 2
+
+EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_init_mesh", "avs_step",
+           "avs_moments", "avs_adapt", "avs_remap", "avs_leaves", "avs_plan", "avs_criterion",
+           "avs_set_leaves", "avs_get_state", "avs_set_state", "avs_get_cells", "avs_profile",
+           "avs_profile_read", "avs_destroy", "avs_last_error")
+
+
+class avs_vspace(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("max_level", C.c_int32), ("base", C.c_int32 * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("leaf_capacity", C.c_int64)]
+
+
+class avs_gas(C.Structure):
+    _fields_ = [("R", C.c_double), ("Pr", C.c_double), ("omega", C.c_double), ("mu_ref", C.c_double),
+                ("T_ref", C.c_double), ("model", C.c_int32)]
+
+
+class avs_pmesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("ncells", C.c_int64), ("nfaces", C.c_int64),
+                ("cell_vol", C.c_void_p), ("cell_ctr", C.c_void_p), ("face_lr", C.c_void_p),
+                ("face_area", C.c_void_p), ("face_nrm", C.c_void_p), ("face_ctr", C.c_void_p),
+                ("face_shift", C.c_void_p), ("nbc", C.c_int32), ("bc_kind", C.c_void_p), ("bc_state", C.c_void_p)]
+
+
+class avs_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("dt", C.c_double), ("venkat_K", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libavs.so not found at {LIB_PATH}: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D, VP = C.POINTER, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    sig = {
+        "avs_mu_ref_from_kn": (D, [D, D, D, D, D, D]),
+        "avs_vdf_bytes": (C.c_size_t, [P(avs_vspace), P(avs_pmesh), P(avs_opts)]),
+        "avs_workspace_bytes": (C.c_size_t, [P(avs_vspace), P(avs_pmesh), P(avs_opts)]),
+        "avs_init_mesh": (I32, [P(avs_vspace), P(avs_pmesh), P(avs_gas), P(avs_opts), VP, VP, C.c_size_t, VP,
+                                C.c_size_t, VP, P(VP)]),
+        "avs_step": (I32, [VP, I32, VP]),
+        "avs_moments": (I32, [VP, VP, VP]),
+        "avs_adapt": (I32, [VP, D, D, VP, I32, VP, P(I64)]),
+        "avs_remap": (I32, [VP, I32]),
+        "avs_leaves": (I32, [VP, P(I64), P(I64), VP, VP, VP, VP]),
+        "avs_plan": (I32, [VP, VP, VP, VP]),
+        "avs_criterion": (I32, [VP, VP]),
+        "avs_set_leaves": (I32, [VP, I64, VP, VP]),
+        "avs_get_state": (I32, [VP, VP, VP]),
+        "avs_set_state": (I32, [VP, VP, VP]),
+        "avs_get_cells": (I32, [VP, I64, VP, VP]),
+        "avs_profile": (I32, [VP, I32]),
+        "avs_profile_read": (I32, [VP, I32, VP, VP, VP]),
+        "avs_destroy": (None, [VP]),
+        "avs_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class AvsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"avs status {status}: {msg}")
+        self.status = status
+
+
+def _check(st):
+    if st != AVS_OK:
+        raise AvsError(st, lib.avs_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None else None
+
+
+def mu_ref_from_kn(Kn, omega, R, T_ref=1.0, rho_ref=1.0, L_ref=1.0):
+    return lib.avs_mu_ref_from_kn(Kn, omega, R, T_ref, rho_ref, L_ref)
+
+
+class Case:
+    """One context of the library plus the device memory it runs in."""
+
+    def __init__(self, mesh, vspace, gas, dt, venkat_K, prim0, precision=AVS_FP64, leaf_capacity=None,
+                 device="cuda:0"):
+        import torch
+        self._torch = torch
+        D = int(mesh["dim"])
+        self.dim = D
+        self.P = 2 if D == 2 else 1
+        self.nc = int(mesh["ncells"])
+        keep = {}
+
+        def arr(name, dtype):
+            a = np.ascontiguousarray(mesh[name], dtype=dtype)
+            keep[name] = a
+            return a.ctypes.data
+        pm = avs_pmesh()
+        pm.dim = D
+        pm.ncells = self.nc
+        pm.nfaces = int(mesh["nfaces"])
+        pm.cell_vol = arr("cell_vol", np.float64)
+        pm.cell_ctr = arr("cell_ctr", np.float64)
+        pm.face_lr = arr("face_lr", np.int64)
+        pm.face_area = arr("face_area", np.float64)
+        pm.face_nrm = arr("face_nrm", np.float64)
+        pm.face_ctr = arr("face_ctr", np.float64)
+        pm.face_shift = arr("face_shift", np.float64) if "face_shift" in mesh else None
+        pm.nbc = int(mesh["nbc"])
+        pm.bc_kind = arr("bc_kind", np.int32)
+        pm.bc_state = arr("bc_state", np.float64)
+        vs = avs_vspace()
+        vs.dim = D
+        vs.max_level = int(vspace["max_level"])
+        for d in range(D):
+            vs.base[d] = int(vspace["base"][d])
+            vs.lo[d] = float(vspace["lo"][d])
+            vs.hi[d] = float(vspace["hi"][d])
+        nroot = int(np.prod([vs.base[d] for d in range(D)]))
+        vs.leaf_capacity = int(leaf_capacity if leaf_capacity is not None else nroot * (2 ** D) ** vs.max_level)
+        g = avs_gas()
+        g.R, g.Pr, g.omega, g.T_ref = (float(gas[k]) for k in ("R", "Pr", "omega", "T_ref"))
+        g.mu_ref = float(gas["mu_ref"]) if gas.get("mu_ref") is not None else mu_ref_from_kn(
+            gas["Kn"], gas["omega"], gas["R"], gas["T_ref"], gas.get("rho_ref", 1.0), gas.get("L_ref", 1.0))
+        g.model = int(gas.get("model", 1))
+        op = avs_opts()
+        op.precision = int(precision)
+        op.dt = float(dt)
+        op.venkat_K = float(venkat_K)
+        self.gas, self.vs, self.opts, self.pm, self._keep = g, vs, op, pm, keep
+        vb = lib.avs_vdf_bytes(C.byref(vs), C.byref(pm), C.byref(op))
+        wb = lib.avs_workspace_bytes(C.byref(vs), C.byref(pm), C.byref(op))
+        if vb == 0 or wb == 0:
+            raise AvsError(AVS_E_INVALID, lib.avs_last_error().decode())
+        self.device = torch.device(device)
+        self.vdf_mem = torch.empty(vb, dtype=torch.uint8, device=self.device)
+        self.ws_mem = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        p0 = np.ascontiguousarray(prim0, dtype=np.float64)
+        ctx = C.c_void_p()
+        _check(lib.avs_init_mesh(C.byref(vs), C.byref(pm), C.byref(g), C.byref(op), p0.ctypes.data,
+                                 self.vdf_mem.data_ptr(), vb, self.ws_mem.data_ptr(), wb,
+                                 self.stream.cuda_stream, C.byref(ctx)))
+        self.ctx = ctx
+
+    # -- entry points -------------------------------------------------------
+    def step(self, n=1, residual=False):
+        res = np.zeros(self.dim + 2) if residual else None
+        _check(lib.avs_step(self.ctx, int(n), _ptr(res)))
+        return res
+
+    def moments(self, fields=True, totals=True):
+        f = self._torch.empty((self.nc, 2 * self.dim + 2), dtype=self._torch.float64, device=self.device) if fields else None
+        t = np.zeros(self.dim + 2) if totals else None
+        _check(lib.avs_moments(self.ctx, f.data_ptr() if f is not None else None, _ptr(t)))
+        return f, t
+
+    def adapt(self, C1, C2, probes=None):
+        n_old = self.nleaves()
+        flags = self._torch.empty(max(n_old, 1), dtype=self._torch.int8, device=self.device)
+        pr = np.ascontiguousarray(probes, dtype=np.float64) if probes is not None else None
+        nn = C.c_int64()
+        _check(lib.avs_adapt(self.ctx, float(C1), float(C2), _ptr(pr), 0 if pr is None else len(pr),
+                             flags.data_ptr(), C.byref(nn)))
+        self._torch.cuda.synchronize(self.device)
+        return flags[:n_old].cpu().numpy(), nn.value
+
+    def remap(self, correction=2):
+        _check(lib.avs_remap(self.ctx, int(correction)))
+
+    def nleaves(self):
+        n, ld = C.c_int64(), C.c_int64()
+        _check(lib.avs_leaves(self.ctx, C.byref(n), C.byref(ld), None, None, None, None))
+        return n.value
+
+    def leaves(self):
+        n, ld = C.c_int64(), C.c_int64()
+        _check(lib.avs_leaves(self.ctx, C.byref(n), C.byref(ld), None, None, None, None))
+        lev = np.zeros(n.value, np.int32)
+        idx = np.zeros((n.value, self.dim), np.int32)
+        xi = np.zeros((n.value, self.dim))
+        w = np.zeros(n.value)
+        _check(lib.avs_leaves(self.ctx, C.byref(n), C.byref(ld), lev.ctypes.data, idx.ctypes.data,
+                              xi.ctypes.data, w.ctypes.data))
+        return dict(n=n.value, ld=ld.value, level=lev, idx=idx, xi=xi, w=w)
+
+    def plan(self, n_new):
+        kind = np.zeros(n_new, np.int32)
+        src = np.zeros(n_new, np.int64)
+        child = np.zeros(n_new, np.int32)
+        _check(lib.avs_plan(self.ctx, kind.ctypes.data, src.ctypes.data, child.ctypes.data))
+        return kind, src, child
+
+    def criterion(self, n_old):
+        Mk = np.zeros(n_old)
+        _check(lib.avs_criterion(self.ctx, Mk.ctypes.data))
+        return Mk
+
+    def set_leaves(self, level, idx):
+        lev = np.ascontiguousarray(level, np.int32)
+        ix = np.ascontiguousarray(idx, np.int32)
+        _check(lib.avs_set_leaves(self.ctx, len(lev), lev.ctypes.data, ix.ctypes.data))
+
+    def get_state(self):
+        n = self.nleaves()
+        vdf = np.zeros((self.P, self.nc, n))
+        W = np.zeros((self.nc, self.dim + 2))
+        _check(lib.avs_get_state(self.ctx, vdf.ctypes.data, W.ctypes.data))
+        return vdf, W
+
+    def get_W(self):
+        W = np.zeros((self.nc, self.dim + 2))
+        _check(lib.avs_get_state(self.ctx, None, W.ctypes.data))
+        return W
+
+    def set_state(self, vdf, W):
+        v = None if vdf is None else np.ascontiguousarray(vdf, np.float64)
+        w = np.ascontiguousarray(W, np.float64)
+        _check(lib.avs_set_state(self.ctx, _ptr(v), w.ctypes.data))
+
+    def get_cells(self, cells):
+        c = np.ascontiguousarray(cells, np.int64)
+        out = np.zeros((self.P, len(c), self.nleaves()))
+        _check(lib.avs_get_cells(self.ctx, len(c), c.ctypes.data, out.ctypes.data))
+        return out
+
+    def profile(self, enable=True):
+        _check(lib.avs_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel group: (total ms, launches)} since profiling was enabled."""
+        nmax = 32
+        names = C.create_string_buffer(32 * nmax)
+        ms = np.zeros(nmax)
+        cnt = np.zeros(nmax, np.int64)
+        n = lib.avs_profile_read(self.ctx, nmax, names, ms.ctypes.data, cnt.ctypes.data)
+        if n < 0:
+            raise AvsError(AVS_E_STATE, lib.avs_last_error().decode())
+        raw = names.raw
+        return {raw[32 * i:32 * i + 32].split(b"\0")[0].decode(): (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib.avs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1068 @@
+// Host side of libavs: argument checking, mesh preprocessing, workspace
+// layout, kernel sequencing and the extern "C" entry points of avs.h.
+#include <algorithm>
+#include <cinttypes>
+#include <cstdarg>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/avs.h"
+#include "avs_kernels.hip"
+
+using namespace avs;
+
+namespace {
+
+thread_local std::string g_err;
+
+avs_status fail(avs_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+avs_status fail(avs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Bump allocator over the caller's workspace (base == nullptr: measure only).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+struct LeafBuf {
+  int* level;
+  int* idx;
+  int* u;
+  double* xi;
+  double* w;
+};
+
+}  // namespace
+
+struct avs_ctx {
+  int D, P, maxf, nm, prec;
+  int nc, nf, nbc, n_int, n_bnd;
+  int64_t cap;
+  int lmax, base[3];
+  double lo[3], hi[3];
+  GasP gas;
+  double dt, h, Kv;
+  VGrid vg;
+  hipStream_t stream;
+  bool failed = false;
+  std::vector<double> vol_host;
+
+  void* vdf[2];
+  size_t vdf_buf_bytes;
+  int cur = 0;
+
+  Geo geo;
+  LeafBuf lt[2];
+  int lcur = 0;
+  int nleaf[2] = {0, 0};
+  int ld[2] = {0, 0};
+
+  double *W, *Wn, *q, *mom, *tpar, *lam, *fpar, *Fbar, *F, *part, *bden, *bfin, *bcpair, *momp, *res, *tot;
+  double *cc, *crit_part, *Mk, *probe_cc, *probe_prim;
+  int8_t *raw, *eff;
+  int *cnt, *off, *pkind, *psrc, *pchild, *bad;
+  int ngrp;
+  int nprobe_max = 64;
+  int plan_n = 0;
+  bool plan_valid = false;
+
+  // optional per-kernel timing with HIP events (measurement only)
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  std::vector<std::pair<int, size_t>> evrec;   // (kernel id, index of its start event)
+
+  Leaves leaves(int t) const {
+    Leaves L;
+    L.n = nleaf[t];
+    L.ld = ld[t];
+    L.cap = (int)cap;
+    L.level = lt[t].level;
+    L.idx = lt[t].idx;
+    L.u = lt[t].u;
+    L.xi = lt[t].xi;
+    L.w = lt[t].w;
+    return L;
+  }
+  size_t esize() const { return prec == AVS_FP32 ? 4 : 8; }
+};
+
+namespace {
+
+enum KernelId { K_PASSA, K_FACE_PARAMS, K_FACE_EQFLUX, K_MACRO, K_TARGET, K_PASSC, K_RESIDUAL, K_CRITERION,
+                K_FLAGS, K_REMAP_GATHER, K_REMAP_CORRECT, K_BC_TABLES, K_MOMENTS, K_INIT, K_NKERNELS };
+const char* const kKernelNames[K_NKERNELS] = {"passA", "face_params", "face_eqflux", "macro", "target", "passC",
+                                              "residual", "criterion", "flags_plan", "remap_gather",
+                                              "remap_correct", "bc_tables", "moments", "init_vdf"};
+
+hipEvent_t next_event(avs_ctx* ctx) {
+  if (ctx->evused == ctx->evpool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->evpool.push_back(e);
+  }
+  return ctx->evpool[ctx->evused++];
+}
+
+// Brackets a group of launches with two events when profiling is on.
+struct ProfScope {
+  avs_ctx* ctx;
+  int id;
+  ProfScope(avs_ctx* c, int k) : ctx(c), id(k) {
+    if (ctx->prof) {
+      const size_t at = ctx->evused;
+      hipEvent_t a = next_event(ctx);
+      hipEvent_t b = next_event(ctx);
+      if (a && b && hipEventRecord(a, ctx->stream) == hipSuccess) ctx->evrec.push_back({id, at});
+      (void)b;
+    }
+  }
+  ~ProfScope() {
+    if (ctx->prof && !ctx->evrec.empty() && ctx->evrec.back().first == id)
+      (void)hipEventRecord(ctx->evpool[ctx->evrec.back().second + 1], ctx->stream);
+  }
+};
+
+#define CK(expr)                                                                                   \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) {                                                                        \
+      if (ctx) ctx->failed = true;                                                                 \
+      return fail(AVS_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    }                                                                                              \
+  } while (0)
+
+#define CKL()                                                                                      \
+  do {                                                                                             \
+    hipError_t e_ = hipGetLastError();                                                             \
+    if (e_ != hipSuccess) {                                                                        \
+      if (ctx) ctx->failed = true;                                                                 \
+      return fail(AVS_E_HIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), __FILE__, __LINE__); \
+    }                                                                                              \
+  } while (0)
+
+avs_status check_args(const avs_vspace* vs, const avs_pmesh* pm, const avs_opts* op) {
+  if (!vs || !pm || !op) return fail(AVS_E_INVALID, "null descriptor");
+  if (vs->dim != 2 && vs->dim != 3) return fail(AVS_E_INVALID, "vspace.dim must be 2 or 3 (got %d)", vs->dim);
+  if (pm->dim != vs->dim) return fail(AVS_E_INVALID, "pmesh.dim %d != vspace.dim %d", pm->dim, vs->dim);
+  if (vs->max_level < 0 || vs->max_level > 12) return fail(AVS_E_INVALID, "max_level %d outside [0, 12]", vs->max_level);
+  int64_t nroots = 1;
+  for (int d = 0; d < vs->dim; ++d) {
+    if (vs->base[d] < 1 || vs->base[d] > 4096) return fail(AVS_E_INVALID, "base[%d] = %d outside [1, 4096]", d, vs->base[d]);
+    if (!(vs->hi[d] > vs->lo[d])) return fail(AVS_E_INVALID, "velocity box empty on axis %d", d);
+    nroots *= vs->base[d];
+    if (((int64_t)vs->base[d] << (vs->max_level + 1)) > (1 << 20))
+      return fail(AVS_E_INVALID, "base[%d] * 2^max_level too large", d);
+  }
+  if (vs->leaf_capacity < nroots) return fail(AVS_E_INVALID, "leaf_capacity %" PRId64 " < number of roots %" PRId64, vs->leaf_capacity, nroots);
+  if (vs->leaf_capacity > (1 << 26)) return fail(AVS_E_INVALID, "leaf_capacity too large");
+  if (pm->ncells < 1 || pm->ncells > (1 << 28)) return fail(AVS_E_INVALID, "ncells %" PRId64 " out of range", pm->ncells);
+  if (pm->nfaces < 0 || pm->nfaces > (1 << 29)) return fail(AVS_E_INVALID, "nfaces %" PRId64 " out of range", pm->nfaces);
+  if (op->precision != AVS_FP64 && op->precision != AVS_FP32) return fail(AVS_E_INVALID, "precision must be AVS_FP64 or AVS_FP32");
+  if (!(op->dt > 0.0)) return fail(AVS_E_INVALID, "dt must be > 0");
+  if (!(op->venkat_K >= 0.0)) return fail(AVS_E_INVALID, "venkat_K must be >= 0");
+  return AVS_OK;
+}
+
+int numax_of(const avs_vspace* vs) {
+  int m = 0;
+  for (int d = 0; d < vs->dim; ++d) m = std::max(m, vs->base[d] << (vs->max_level + 1));
+  return m;
+}
+
+// Carve every device array of a context; with c.base == nullptr only sizes.
+void carve(avs_ctx& x, Carver& c) {
+  const int D = x.D, N = D + 2;
+  const size_t nc = x.nc, nf = x.nf, cap = x.cap, mf = x.maxf;
+  x.geo.vol = c.take<double>(nc);
+  x.geo.eps2 = c.take<double>(nc);
+  x.geo.dtv = c.take<double>(nc);
+  x.geo.nslot = c.take<int>(nc);
+  x.geo.s_face = c.take<int>(nc * mf);
+  x.geo.s_nbr = c.take<int>(nc * mf);
+  x.geo.s_sig = c.take<double>(nc * mf);
+  x.geo.s_sigA = c.take<double>(nc * mf);
+  x.geo.s_d = c.take<double>(nc * mf * D);
+  x.geo.s_dx = c.take<double>(nc * mf * D);
+  x.geo.s_lsq = c.take<double>(nc * mf * D);
+  x.geo.f_L = c.take<int>(nf + 1);
+  x.geo.f_R = c.take<int>(nf + 1);
+  x.geo.f_sL = c.take<int>(nf + 1);
+  x.geo.f_sR = c.take<int>(nf + 1);
+  x.geo.f_nrm = c.take<double>((nf + 1) * D);
+  x.geo.f_int = c.take<int>(nf + 1);
+  x.geo.f_bnd = c.take<int>(nf + 1);
+  x.geo.bc_kind = c.take<int>(x.nbc + 1);
+  x.geo.bc_prim = c.take<double>((x.nbc + 1) * N);
+  for (int t = 0; t < 2; ++t) {
+    x.lt[t].level = c.take<int>(cap);
+    x.lt[t].idx = c.take<int>(cap * D);
+    x.lt[t].u = c.take<int>(cap * D);
+    x.lt[t].xi = c.take<double>(cap * D);
+    x.lt[t].w = c.take<double>(cap);
+  }
+  x.W = c.take<double>(nc * N);
+  x.Wn = c.take<double>(nc * N);
+  x.q = c.take<double>(nc * D);
+  x.mom = c.take<double>(nc * N);
+  x.tpar = c.take<double>(nc * NPAR);
+  x.lam = c.take<double>(nc * N);
+  x.fpar = c.take<double>((nf + 1) * NPAR);
+  x.Fbar = c.take<double>((nf + 1) * N);
+  x.F = c.take<double>((nf + 1) * N);
+  x.part = c.take<double>(nc * mf * x.nm);
+  x.bden = c.take<double>(nf + 1);
+  x.bfin = c.take<double>((nf + 1) * N);
+  x.bcpair = c.take<double>((size_t)(x.nbc + 1) * x.P * cap);
+  x.momp = c.take<double>(nc * N);
+  x.res = c.take<double>(N);
+  x.tot = c.take<double>(N);
+  x.cc = c.take<double>(nc * N);
+  x.ngrp = (int)((nc + CRIT_CELLS - 1) / CRIT_CELLS);
+  x.crit_part = c.take<double>((size_t)x.ngrp * cap);
+  x.Mk = c.take<double>(cap);
+  x.probe_cc = c.take<double>((size_t)x.nprobe_max * N);
+  x.probe_prim = c.take<double>((size_t)x.nprobe_max * N);
+  x.raw = c.take<int8_t>(cap);
+  x.eff = c.take<int8_t>(cap);
+  x.cnt = c.take<int>(cap);
+  x.off = c.take<int>(cap + 1);
+  x.pkind = c.take<int>(cap);
+  x.psrc = c.take<int>(cap);
+  x.pchild = c.take<int>(cap);
+  x.bad = c.take<int>(4);
+}
+
+void fill_dims(avs_ctx& x, const avs_vspace* vs, const avs_pmesh* pm, const avs_opts* op) {
+  x.D = vs->dim;
+  x.P = x.D == 2 ? 2 : 1;
+  x.maxf = x.D == 2 ? MAXF2 : MAXF3;
+  x.nm = x.D == 2 ? NM2 : NM3;
+  x.prec = op->precision;
+  x.nc = (int)pm->ncells;
+  x.nf = (int)pm->nfaces;
+  x.nbc = pm->nbc;
+  x.cap = round_up(vs->leaf_capacity, 64);
+}
+
+// Morton key of a leaf's lower corner on the finest grid (x lowest bit).
+uint64_t morton(int D, int lmax, int level, const int* ix) {
+  uint64_t key = 0;
+  const int bits = 64 / D;
+  for (int b = 0; b < bits; ++b)
+    for (int d = 0; d < D; ++d) {
+      const uint64_t X = (uint64_t)ix[d] << (lmax - level);
+      key |= ((X >> b) & 1ull) << (D * b + d);
+    }
+  return key;
+}
+
+// Pseudo-inverse of a symmetric positive semi-definite DxD matrix (Jacobi).
+void pinv_sym(int D, const double* M, double* out) {
+  double a[3][3], v[3][3];
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) { a[i][j] = M[i * D + j]; v[i][j] = i == j; }
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < D; ++i)
+      for (int j = i + 1; j < D; ++j) off += a[i][j] * a[i][j];
+    if (off < 1e-300) break;
+    for (int p = 0; p < D; ++p)
+      for (int q = p + 1; q < D; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < D; ++k) {
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - s * akq;
+          a[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < D; ++k) {
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - s * aqk;
+          a[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < D; ++k) {
+          const double vkp = v[k][p], vkq = v[k][q];
+          v[k][p] = c * vkp - s * vkq;
+          v[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  double emax = 0.0;
+  for (int i = 0; i < D; ++i) emax = std::max(emax, fabs(a[i][i]));
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < D; ++k)
+        if (a[k][k] > 1e-12 * emax) s += v[i][k] * v[j][k] / a[k][k];
+      out[i * D + j] = s;
+    }
+}
+
+// W = (rho, rho U, rho|U|^2/2 + 3/2 rho R T); same operation order as the oracle.
+void conserved_host(int D, double R, const double* prim, double* W) {
+#pragma clang fp contract(off)
+  const double rho = prim[0];
+  double ss = prim[1] * prim[1];
+  for (int d = 1; d < D; ++d) ss = ss + prim[1 + d] * prim[1 + d];
+  const double ke = 0.5 * rho * ss;
+  W[0] = rho;
+  for (int d = 0; d < D; ++d) W[1 + d] = rho * prim[1 + d];
+  W[1 + D] = ke + 1.5 * rho * R * prim[1 + D];
+}
+
+void crit_consts_host(int D, const double* W, double* o) {
+#pragma clang fp contract(off)
+  const double rho = W[0];
+  double U[3];
+  for (int d = 0; d < D; ++d) U[d] = W[1 + d] / rho;
+  double ke = U[0] * U[0];
+  for (int d = 1; d < D; ++d) ke = ke + U[d] * U[d];
+  o[0] = rho;
+  for (int d = 0; d < D; ++d) o[1 + d] = U[d];
+  o[1 + D] = W[1 + D] - 0.5 * rho * ke;
+}
+
+template <typename T>
+void copy_from_host(std::vector<T>& tmp, const double* src, size_t n) {
+  tmp.resize(n);
+  for (size_t i = 0; i < n; ++i) tmp[i] = (T)src[i];
+}
+
+// ------------------------------------------------------------- launchers
+template <int D, typename T>
+avs_status launch_init_vdf(avs_ctx* ctx) {
+  constexpr int N = D + 2, NS = Cfg<D>::NS;
+  const size_t shm = (size_t)(D * ctx->vg.numax + 4 * (N + NS)) * sizeof(double);
+  k_init_vdf<D, T><<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, ctx->leaves(ctx->lcur), ctx->vg, ctx->gas, ctx->W,
+                                                       (T*)ctx->vdf[ctx->cur], ctx->bad);
+  CKL();
+  return AVS_OK;
+}
+
+template <int D, typename T>
+avs_status launch_moments(avs_ctx* ctx) {
+  ProfScope ps(ctx, K_MOMENTS);
+  k_cell_moments<D, T><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->leaves(ctx->lcur), (const T*)ctx->vdf[ctx->cur],
+                                                          ctx->W, ctx->mom, ctx->q);
+  CKL();
+  return AVS_OK;
+}
+
+template <int D>
+avs_status launch_bc_tables(avs_ctx* ctx) {
+  const Leaves L = ctx->leaves(ctx->lcur);
+  ProfScope ps(ctx, K_BC_TABLES);
+  if (ctx->nbc > 0) {
+    dim3 grid((L.n + BLOCK - 1) / BLOCK, ctx->nbc);
+    k_bc_pairs<D><<<grid, BLOCK, 0, ctx->stream>>>(L, ctx->gas, ctx->nbc, ctx->geo.bc_kind, ctx->geo.bc_prim, ctx->bcpair);
+    CKL();
+  }
+  if (ctx->n_bnd > 0) {
+    k_bnd_tables<D><<<ctx->n_bnd, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->bcpair, ctx->bden, ctx->bfin);
+    CKL();
+  }
+  return AVS_OK;
+}
+
+template <int D, typename T>
+avs_status launch_step(avs_ctx* ctx, bool last_residual) {
+  constexpr int MAXF = Cfg<D>::MAXF;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int nu = ctx->vg.numax;
+  const T* vin = (const T*)ctx->vdf[ctx->cur];
+  T* vout = (T*)ctx->vdf[ctx->cur ^ 1];
+  {
+    ProfScope ps(ctx, K_PASSA);
+    k_passA<D, T><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, vin, ctx->h, ctx->part);
+    CKL();
+  }
+  {
+    ProfScope ps(ctx, K_FACE_PARAMS);
+    k_face_params<D><<<(ctx->nf + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(
+        ctx->geo, ctx->gas, ctx->h, ctx->part, ctx->bden, ctx->bfin, ctx->fpar, ctx->Fbar, ctx->F, ctx->bad);
+    CKL();
+  }
+  if (ctx->n_int > 0) {
+    ProfScope ps(ctx, K_FACE_EQFLUX);
+    k_face_eqflux<D><<<ctx->n_int, BLOCK, (size_t)D * nu * sizeof(double), ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->fpar,
+                                                                                        ctx->Fbar, ctx->F);
+    CKL();
+  }
+  {
+    ProfScope ps(ctx, K_MACRO);
+    k_macro<D><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, ctx->dt, ctx->F, ctx->W,
+                                                                       ctx->Wn, ctx->q, ctx->tpar, ctx->bad);
+    CKL();
+  }
+  {
+    ProfScope ps(ctx, K_TARGET);
+    k_target<D><<<ctx->nc, BLOCK, (size_t)D * nu * sizeof(double), ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->tpar, ctx->Wn,
+                                                                                ctx->lam, ctx->bad);
+    CKL();
+  }
+  {
+    ProfScope ps(ctx, K_PASSC);
+    k_passC<D, T><<<ctx->nc, BLOCK, (size_t)(MAXF + 1) * D * nu * sizeof(double), ctx->stream>>>(
+        ctx->geo, L, ctx->vg, vin, vout, ctx->fpar, ctx->tpar, ctx->lam, ctx->bcpair, ctx->h, ctx->mom, ctx->q);
+    CKL();
+  }
+  if (last_residual) {
+    ProfScope ps(ctx, K_RESIDUAL);
+    k_residual<D><<<1, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->W, ctx->Wn, 1.0 / ctx->dt, ctx->res);
+    CKL();
+  }
+  std::swap(ctx->W, ctx->Wn);
+  ctx->cur ^= 1;
+  return AVS_OK;
+}
+
+template <int D>
+avs_status launch_leaf_geom(avs_ctx* ctx, int t) {
+  const int n = ctx->nleaf[t];
+  if (n == 0) return AVS_OK;
+  k_leaf_geom<D><<<(n + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(
+      n, (int)ctx->cap, ctx->lt[t].level, ctx->lt[t].idx, ctx->lt[t].u, ctx->lt[t].xi, ctx->lt[t].w, ctx->vg, ctx->lmax,
+      ctx->base[0], ctx->base[1], ctx->base[2], ctx->lo[0], ctx->lo[1], ctx->lo[2], ctx->hi[0], ctx->hi[1], ctx->hi[2]);
+  CKL();
+  return AVS_OK;
+}
+
+template <int D, typename T>
+avs_status launch_adapt(avs_ctx* ctx, double C1, double C2, int nprobe) {
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int nb = (L.n + BLOCK - 1) / BLOCK;
+  ProfScope ps(ctx, K_CRITERION);
+  k_crit_cells<D><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->W, ctx->cc);
+  CKL();
+  k_crit_partial<D, T><<<dim3(nb, ctx->ngrp), BLOCK, 0, ctx->stream>>>(L, ctx->nc, (const T*)ctx->vdf[ctx->cur], ctx->cc,
+                                                                      ctx->crit_part);
+  CKL();
+  k_crit_reduce<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->ngrp, ctx->crit_part, nprobe, ctx->probe_cc, ctx->probe_prim,
+                                                 ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
+  CKL();
+  k_resolve<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
+  CKL();
+  k_scan<<<1, BLOCK, 0, ctx->stream>>>(L.n, ctx->cnt, ctx->off);
+  CKL();
+  return AVS_OK;
+}
+
+template <int D>
+avs_status launch_scatter(avs_ctx* ctx) {
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int t = ctx->lcur ^ 1;
+  ProfScope ps(ctx, K_FLAGS);
+  k_scatter<D><<<(L.n + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(L, ctx->eff, ctx->off, (int)ctx->cap, ctx->lt[t].level,
+                                                                   ctx->lt[t].idx, ctx->pkind, ctx->psrc, ctx->pchild);
+  CKL();
+  return launch_leaf_geom<D>(ctx, t);
+}
+
+template <int D, typename T>
+avs_status launch_remap(avs_ctx* ctx, int correction) {
+  const Leaves Lo = ctx->leaves(ctx->lcur);
+  const Leaves Ln = ctx->leaves(ctx->lcur ^ 1);
+  T* vout = (T*)ctx->vdf[ctx->cur ^ 1];
+  {
+    ProfScope ps(ctx, K_REMAP_GATHER);
+    k_remap_gather<D, T><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, Lo, Ln, ctx->pkind, ctx->psrc,
+                                                            (const T*)ctx->vdf[ctx->cur], vout, ctx->momp);
+    CKL();
+  }
+  if (correction > 0) {
+    ProfScope ps(ctx, K_REMAP_CORRECT);
+    k_remap_correct<D, T><<<ctx->nc, BLOCK, (size_t)2 * D * ctx->vg.numax * sizeof(double), ctx->stream>>>(
+        ctx->geo, Ln, ctx->vg, ctx->gas, correction, ctx->W, ctx->momp, vout, ctx->bad);
+    CKL();
+  }
+  return AVS_OK;
+}
+
+// Dispatch on (dimension, storage type).
+#define DISPATCH(ctx, FN, ...)                                                       \
+  ((ctx)->D == 2 ? ((ctx)->prec == AVS_FP64 ? FN<2, double>(__VA_ARGS__) : FN<2, float>(__VA_ARGS__)) \
+                 : ((ctx)->prec == AVS_FP64 ? FN<3, double>(__VA_ARGS__) : FN<3, float>(__VA_ARGS__)))
+#define DISPATCH_D(ctx, FN, ...) ((ctx)->D == 2 ? FN<2>(__VA_ARGS__) : FN<3>(__VA_ARGS__))
+
+avs_status check_bad(avs_ctx* ctx) {
+  int bad = INT_MAX;
+  CK(hipMemcpyAsync(&bad, ctx->bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  if (bad != INT_MAX) {
+    ctx->failed = true;
+    if (bad < ctx->nc) return fail(AVS_E_NUMERIC, "non-physical state or singular moment system in cell %d", bad);
+    return fail(AVS_E_NUMERIC, "non-physical interface state at face %d", bad - ctx->nc);
+  }
+  return AVS_OK;
+}
+
+avs_status upload_leaves(avs_ctx* ctx, int t, int n, const int* level, const int* idx_nd /*[n][D]*/) {
+  std::vector<int> ix((size_t)ctx->D * ctx->cap, 0);
+  for (int k = 0; k < n; ++k)
+    for (int d = 0; d < ctx->D; ++d) ix[(size_t)d * ctx->cap + k] = idx_nd[(size_t)k * ctx->D + d];
+  CK(hipMemcpyAsync(ctx->lt[t].level, level, sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
+  CK(hipMemcpyAsync(ctx->lt[t].idx, ix.data(), sizeof(int) * ix.size(), hipMemcpyHostToDevice, ctx->stream));
+  ctx->nleaf[t] = n;
+  ctx->ld[t] = (int)round_up(n, 64);
+  avs_status st = DISPATCH_D(ctx, launch_leaf_geom, ctx, t);
+  if (st) return st;
+  CK(hipStreamSynchronize(ctx->stream));
+  return AVS_OK;
+}
+
+avs_status guard(avs_ctx* ctx) {
+  if (!ctx) return fail(AVS_E_INVALID, "null context");
+  if (ctx->failed) return fail(AVS_E_STATE, "context is in the failed state after an earlier device or numeric error");
+  return AVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+double avs_mu_ref_from_kn(double Kn, double omega, double R, double T_ref, double rho_ref, double L_ref) {
+  return Kn * L_ref * 15.0 * rho_ref * sqrt(2.0 * M_PI * R * T_ref) / (2.0 * (5.0 - 2.0 * omega) * (7.0 - 2.0 * omega));
+}
+
+size_t avs_vdf_bytes(const avs_vspace* vs, const avs_pmesh* pm, const avs_opts* op) {
+  if (check_args(vs, pm, op)) return 0;
+  avs_ctx x;
+  fill_dims(x, vs, pm, op);
+  return 2 * (size_t)x.P * x.nc * x.cap * x.esize();
+}
+
+size_t avs_workspace_bytes(const avs_vspace* vs, const avs_pmesh* pm, const avs_opts* op) {
+  if (check_args(vs, pm, op)) return 0;
+  avs_ctx x;
+  fill_dims(x, vs, pm, op);
+  Carver c{nullptr};
+  carve(x, c);
+  return round_up((int64_t)c.off, 256);
+}
+
+avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_gas* gas, const avs_opts* op,
+                         const double* prim0_host, void* vdf_dev, size_t vdf_bytes, void* workspace_dev,
+                         size_t workspace_bytes, void* hip_stream, avs_ctx** out) {
+  avs_ctx* ctx = nullptr;
+  if (!out) return fail(AVS_E_INVALID, "out is null");
+  *out = nullptr;
+  if (avs_status st = check_args(vs, pm, op)) return st;
+  if (!gas || !prim0_host || !vdf_dev || !workspace_dev) return fail(AVS_E_INVALID, "null gas/prim0/vdf/workspace pointer");
+  if (!(gas->R > 0 && gas->mu_ref > 0 && gas->T_ref > 0 && gas->Pr > 0) || (gas->model != 0 && gas->model != 1))
+    return fail(AVS_E_INVALID, "invalid gas parameters");
+  if (vdf_bytes < avs_vdf_bytes(vs, pm, op)) return fail(AVS_E_INVALID, "vdf region too small (%zu < %zu)", vdf_bytes, avs_vdf_bytes(vs, pm, op));
+  if (workspace_bytes < avs_workspace_bytes(vs, pm, op))
+    return fail(AVS_E_INVALID, "workspace too small (%zu < %zu)", workspace_bytes, avs_workspace_bytes(vs, pm, op));
+  if (((uintptr_t)vdf_dev & 255) || ((uintptr_t)workspace_dev & 255)) return fail(AVS_E_INVALID, "device regions must be 256-byte aligned");
+  const int D = vs->dim, N = D + 2;
+  const int64_t nc = pm->ncells, nf = pm->nfaces;
+  if (!pm->cell_vol || !pm->cell_ctr || (nf > 0 && (!pm->face_lr || !pm->face_area || !pm->face_nrm || !pm->face_ctr)))
+    return fail(AVS_E_INVALID, "null mesh array");
+  if (pm->nbc < 0 || (pm->nbc > 0 && (!pm->bc_kind || !pm->bc_state))) return fail(AVS_E_INVALID, "invalid bc arrays");
+  const int maxf = D == 2 ? MAXF2 : MAXF3;
+  // ---- validate mesh and build per-cell slot tables (host)
+  std::vector<int> nslot(nc, 0), s_face(nc * maxf, 0), s_nbr(nc * maxf, -1);
+  std::vector<double> s_sig(nc * maxf, 0.0), s_sigA(nc * maxf, 0.0), s_d(nc * maxf * D, 0.0), s_dx(nc * maxf * D, 0.0),
+      s_lsq(nc * maxf * D, 0.0);
+  std::vector<int> f_L(nf + 1, 0), f_R(nf + 1, 0), f_sL(nf + 1, 0), f_sR(nf + 1, 0), f_int, f_bnd;
+  std::vector<double> f_nrm((nf + 1) * D, 0.0);
+  for (int64_t i = 0; i < nc; ++i)
+    if (!(pm->cell_vol[i] > 0)) return fail(AVS_E_INVALID, "cell %" PRId64 " has non-positive volume", i);
+  for (int b = 0; b < pm->nbc; ++b)
+    if (pm->bc_kind[b] != AVS_BC_WALL && pm->bc_kind[b] != AVS_BC_FARFIELD) return fail(AVS_E_INVALID, "bc %d: unknown kind", b);
+  for (int64_t f = 0; f < nf; ++f) {
+    const int64_t L = pm->face_lr[2 * f], R = pm->face_lr[2 * f + 1];
+    if (L < 0 || L >= nc) return fail(AVS_E_INVALID, "face %" PRId64 ": L out of range", f);
+    if (R >= nc || (R < 0 && -1 - R >= pm->nbc)) return fail(AVS_E_INVALID, "face %" PRId64 ": R out of range", f);
+    if (!(pm->face_area[f] >= 0)) return fail(AVS_E_INVALID, "face %" PRId64 ": negative area", f);
+    const double* xf = pm->face_ctr + f * D;
+    double xR[3] = {0, 0, 0};
+    if (R >= 0)
+      for (int d = 0; d < D; ++d) xR[d] = pm->cell_ctr[R * D + d] + (pm->face_shift ? pm->face_shift[f * D + d] : 0.0);
+    if (nslot[L] >= maxf) return fail(AVS_E_INVALID, "cell %" PRId64 " has more than %d faces", L, maxf);
+    int s = nslot[L]++;
+    s_face[L * maxf + s] = (int)f;
+    s_nbr[L * maxf + s] = R >= 0 ? (int)R : -1;
+    s_sig[L * maxf + s] = 1.0;
+    s_sigA[L * maxf + s] = pm->face_area[f];
+    for (int d = 0; d < D; ++d) {
+      s_d[(L * maxf + s) * D + d] = xf[d] - pm->cell_ctr[L * D + d];
+      if (R >= 0) s_dx[(L * maxf + s) * D + d] = xR[d] - pm->cell_ctr[L * D + d];
+    }
+    f_L[f] = (int)L;
+    f_R[f] = (int)R;
+    f_sL[f] = s;
+    for (int d = 0; d < D; ++d) f_nrm[f * D + d] = pm->face_nrm[f * D + d];
+    if (R >= 0) {
+      if (nslot[R] >= maxf) return fail(AVS_E_INVALID, "cell %" PRId64 " has more than %d faces", R, maxf);
+      s = nslot[R]++;
+      s_face[R * maxf + s] = (int)f;
+      s_nbr[R * maxf + s] = (int)L;
+      s_sig[R * maxf + s] = -1.0;
+      s_sigA[R * maxf + s] = -pm->face_area[f];
+      for (int d = 0; d < D; ++d) {
+        s_d[(R * maxf + s) * D + d] = xf[d] - xR[d];
+        s_dx[(R * maxf + s) * D + d] = pm->cell_ctr[L * D + d] - xR[d];
+      }
+      f_sR[f] = s;
+      f_int.push_back((int)f);
+    } else {
+      f_bnd.push_back((int)f);
+    }
+  }
+  std::vector<double> eps2(nc), dtv(nc);
+  for (int64_t i = 0; i < nc; ++i) {
+    double M[9] = {0}, Mi[9];
+    for (int s = 0; s < nslot[i]; ++s) {
+      if (s_nbr[i * maxf + s] < 0) continue;
+      const double* dx = &s_dx[(i * maxf + s) * D];
+      double r2 = 0.0;
+      for (int d = 0; d < D; ++d) r2 += dx[d] * dx[d];
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) M[a * D + b] += dx[a] * dx[b] / r2;
+    }
+    pinv_sym(D, M, Mi);
+    for (int s = 0; s < nslot[i]; ++s) {
+      if (s_nbr[i * maxf + s] < 0) continue;
+      const double* dx = &s_dx[(i * maxf + s) * D];
+      double r2 = 0.0;
+      for (int d = 0; d < D; ++d) r2 += dx[d] * dx[d];
+      for (int a = 0; a < D; ++a) {
+        double v = 0.0;
+        for (int b = 0; b < D; ++b) v += Mi[a * D + b] * dx[b] / r2;
+        s_lsq[(i * maxf + s) * D + a] = v;
+      }
+    }
+    eps2[i] = pow(op->venkat_K * pow(pm->cell_vol[i], 1.0 / D), 3.0);
+    dtv[i] = op->dt / pm->cell_vol[i];
+  }
+  std::vector<double> W0(nc * N);
+  for (int64_t i = 0; i < nc; ++i) {
+    const double* pr = prim0_host + i * N;
+    if (!(pr[0] > 0 && pr[1 + D] > 0)) return fail(AVS_E_INVALID, "initial state of cell %" PRId64 " is not physical", i);
+    conserved_host(D, gas->R, pr, &W0[i * N]);
+  }
+  // ---- context
+  ctx = new avs_ctx();
+  avs_ctx& x = *ctx;
+  fill_dims(x, vs, pm, op);
+  x.n_int = (int)f_int.size();
+  x.n_bnd = (int)f_bnd.size();
+  x.lmax = vs->max_level;
+  for (int d = 0; d < 3; ++d) {
+    x.base[d] = d < D ? vs->base[d] : 1;
+    x.lo[d] = d < D ? vs->lo[d] : 0.0;
+    x.hi[d] = d < D ? vs->hi[d] : 1.0;
+    x.vg.nu[d] = d < D ? vs->base[d] << (vs->max_level + 1) : 1;
+    x.vg.x0[d] = x.lo[d];
+    x.vg.hh[d] = (x.hi[d] - x.lo[d]) / (double)((int64_t)x.base[d] << (vs->max_level + 1));
+  }
+  x.vg.numax = numax_of(vs);
+  x.gas = GasP{gas->R, gas->Pr, gas->omega, gas->mu_ref, gas->T_ref, gas->model};
+  x.dt = op->dt;
+  x.h = 0.5 * op->dt;
+  x.Kv = op->venkat_K;
+  x.stream = (hipStream_t)hip_stream;
+  x.vol_host.assign(pm->cell_vol, pm->cell_vol + nc);
+  x.vdf_buf_bytes = avs_vdf_bytes(vs, pm, op) / 2;
+  x.vdf[0] = vdf_dev;
+  x.vdf[1] = (char*)vdf_dev + x.vdf_buf_bytes;
+  Carver cv{(char*)workspace_dev};
+  carve(x, cv);
+  const int P = x.P;
+  // LDS budget of the sweep kernels
+  if ((size_t)(x.maxf + 1) * D * x.vg.numax * sizeof(double) + 8192 > 64 * 1024) {
+    delete ctx;
+    return fail(AVS_E_INVALID, "velocity grid too fine for the LDS tables (2 base 2^max_level = %d)", x.vg.numax);
+  }
+  auto H2D = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, x.stream);
+  };
+  std::vector<int> kinds(pm->bc_kind, pm->bc_kind + pm->nbc);
+  std::vector<double> bprim(pm->bc_state, pm->bc_state + (size_t)pm->nbc * N);
+  int badinit[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+#define CKI(e)                                  \
+  do {                                          \
+    hipError_t er_ = (e);                       \
+    if (er_ != hipSuccess) {                    \
+      delete ctx;                               \
+      return fail(AVS_E_HIP, "%s: %s", #e, hipGetErrorString(er_)); \
+    }                                           \
+  } while (0)
+  CKI(H2D((void*)x.geo.vol, pm->cell_vol, sizeof(double) * nc));
+  CKI(H2D((void*)x.geo.eps2, eps2.data(), sizeof(double) * nc));
+  CKI(H2D((void*)x.geo.dtv, dtv.data(), sizeof(double) * nc));
+  CKI(H2D((void*)x.geo.nslot, nslot.data(), sizeof(int) * nc));
+  CKI(H2D((void*)x.geo.s_face, s_face.data(), sizeof(int) * s_face.size()));
+  CKI(H2D((void*)x.geo.s_nbr, s_nbr.data(), sizeof(int) * s_nbr.size()));
+  CKI(H2D((void*)x.geo.s_sig, s_sig.data(), sizeof(double) * s_sig.size()));
+  CKI(H2D((void*)x.geo.s_sigA, s_sigA.data(), sizeof(double) * s_sigA.size()));
+  CKI(H2D((void*)x.geo.s_d, s_d.data(), sizeof(double) * s_d.size()));
+  CKI(H2D((void*)x.geo.s_dx, s_dx.data(), sizeof(double) * s_dx.size()));
+  CKI(H2D((void*)x.geo.s_lsq, s_lsq.data(), sizeof(double) * s_lsq.size()));
+  CKI(H2D((void*)x.geo.f_L, f_L.data(), sizeof(int) * f_L.size()));
+  CKI(H2D((void*)x.geo.f_R, f_R.data(), sizeof(int) * f_R.size()));
+  CKI(H2D((void*)x.geo.f_sL, f_sL.data(), sizeof(int) * f_sL.size()));
+  CKI(H2D((void*)x.geo.f_sR, f_sR.data(), sizeof(int) * f_sR.size()));
+  CKI(H2D((void*)x.geo.f_nrm, f_nrm.data(), sizeof(double) * f_nrm.size()));
+  if (!f_int.empty()) CKI(H2D((void*)x.geo.f_int, f_int.data(), sizeof(int) * f_int.size()));
+  if (!f_bnd.empty()) CKI(H2D((void*)x.geo.f_bnd, f_bnd.data(), sizeof(int) * f_bnd.size()));
+  if (pm->nbc > 0) {
+    CKI(H2D((void*)x.geo.bc_kind, kinds.data(), sizeof(int) * kinds.size()));
+    CKI(H2D((void*)x.geo.bc_prim, bprim.data(), sizeof(double) * bprim.size()));
+  }
+  CKI(H2D(x.W, W0.data(), sizeof(double) * W0.size()));
+  CKI(H2D(x.bad, badinit, sizeof badinit));
+  x.geo.D = D;
+  x.geo.P = P;
+  x.geo.nc = (int)nc;
+  x.geo.nf = (int)nf;
+  x.geo.maxf = maxf;
+  x.geo.nbc = pm->nbc;
+  x.geo.n_int = x.n_int;
+  x.geo.n_bnd = x.n_bnd;
+  // ---- level-0 forest in depth-first order
+  std::vector<std::pair<uint64_t, std::vector<int>>> roots;
+  const int b0 = x.base[0], b1 = x.base[1], b2 = D == 3 ? x.base[2] : 1;
+  for (int c = 0; c < b2; ++c)
+    for (int b = 0; b < b1; ++b)
+      for (int a = 0; a < b0; ++a) {
+        std::vector<int> ix = {a, b, c};
+        ix.resize(D);
+        roots.push_back({morton(D, x.lmax, 0, ix.data()), ix});
+      }
+  std::sort(roots.begin(), roots.end(), [](const auto& p, const auto& q) { return p.first < q.first; });
+  std::vector<int> lev(roots.size(), 0), idx(roots.size() * D);
+  for (size_t k = 0; k < roots.size(); ++k)
+    for (int d = 0; d < D; ++d) idx[k * D + d] = roots[k].second[d];
+  if (avs_status st = upload_leaves(ctx, 0, (int)roots.size(), lev.data(), idx.data())) { delete ctx; return st; }
+  x.lcur = 0;
+  x.cur = 0;
+  avs_status st = DISPATCH(ctx, launch_init_vdf, ctx);
+  if (!st) st = DISPATCH(ctx, launch_moments, ctx);
+  if (!st) st = DISPATCH_D(ctx, launch_bc_tables, ctx);
+  if (!st) st = check_bad(ctx);
+  if (st) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return AVS_OK;
+}
+
+avs_status avs_step(avs_ctx* ctx, int32_t nsteps, double* residual_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (nsteps < 0) return fail(AVS_E_INVALID, "nsteps < 0");
+  for (int n = 0; n < nsteps; ++n) {
+    const bool last = residual_host && n == nsteps - 1;
+    if (avs_status st = DISPATCH(ctx, launch_step, ctx, last)) return st;
+  }
+  if (residual_host) {
+    if (nsteps == 0) return fail(AVS_E_INVALID, "residual requested for zero steps");
+    CK(hipMemcpyAsync(residual_host, ctx->res, sizeof(double) * (ctx->D + 2), hipMemcpyDeviceToHost, ctx->stream));
+    if (avs_status st = check_bad(ctx)) return st;
+  }
+  return AVS_OK;
+}
+
+avs_status avs_moments(avs_ctx* ctx, double* fields_dev, double* totals_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (fields_dev) {
+    if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
+    if (ctx->D == 2)
+      k_fields<2><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->gas, ctx->W, ctx->q, fields_dev);
+    else
+      k_fields<3><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->gas, ctx->W, ctx->q, fields_dev);
+    CKL();
+  }
+  if (totals_host) {
+    if (ctx->D == 2)
+      k_totals<2><<<1, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->geo.vol, ctx->W, ctx->tot);
+    else
+      k_totals<3><<<1, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->geo.vol, ctx->W, ctx->tot);
+    CKL();
+    CK(hipMemcpyAsync(totals_host, ctx->tot, sizeof(double) * (ctx->D + 2), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+  }
+  return AVS_OK;
+}
+
+avs_status avs_adapt(avs_ctx* ctx, double C1, double C2, const double* probes_host, int32_t nprobes, int8_t* flags_dev,
+                     int64_t* n_new_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (nprobes < 0 || nprobes > ctx->nprobe_max) return fail(AVS_E_INVALID, "nprobes must be in [0, %d]", ctx->nprobe_max);
+  if (nprobes > 0 && !probes_host) return fail(AVS_E_INVALID, "probes_host is null");
+  if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
+  const int D = ctx->D, N = D + 2;
+  std::vector<double> pcc((size_t)std::max(nprobes, 1) * N), Wp(N);
+  for (int p = 0; p < nprobes; ++p) {
+    const double* pr = probes_host + (size_t)p * N;
+    if (!(pr[0] > 0 && pr[1 + D] > 0)) return fail(AVS_E_INVALID, "probe %d is not a physical state", p);
+    conserved_host(D, ctx->gas.R, pr, Wp.data());
+    crit_consts_host(D, Wp.data(), &pcc[(size_t)p * N]);
+  }
+  ctx->plan_valid = false;
+  if (nprobes > 0) {
+    CK(hipMemcpyAsync(ctx->probe_cc, pcc.data(), sizeof(double) * nprobes * N, hipMemcpyHostToDevice, ctx->stream));
+    CK(hipMemcpyAsync(ctx->probe_prim, probes_host, sizeof(double) * nprobes * N, hipMemcpyHostToDevice, ctx->stream));
+  }
+  if (avs_status st = DISPATCH(ctx, launch_adapt, ctx, C1, C2, nprobes)) return st;
+  int n_new = 0;
+  const int n_old = ctx->nleaf[ctx->lcur];
+  CK(hipMemcpyAsync(&n_new, ctx->off + n_old, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  if (flags_dev) CK(hipMemcpyAsync(flags_dev, ctx->eff, n_old, hipMemcpyDeviceToDevice, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  if (n_new_host) *n_new_host = n_new;
+  if (n_new > ctx->cap)
+    return fail(AVS_E_CAPACITY, "adaptation would produce %d leaves > leaf_capacity %" PRId64, n_new, ctx->cap);
+  const int t = ctx->lcur ^ 1;
+  ctx->nleaf[t] = n_new;
+  ctx->ld[t] = (int)round_up(n_new, 64);
+  if (avs_status st = DISPATCH_D(ctx, launch_scatter, ctx)) return st;
+  CK(hipStreamSynchronize(ctx->stream));
+  ctx->plan_n = n_new;
+  ctx->plan_valid = true;
+  return AVS_OK;
+}
+
+avs_status avs_remap(avs_ctx* ctx, int32_t correction) {
+  if (avs_status st = guard(ctx)) return st;
+  if (!ctx->plan_valid) return fail(AVS_E_STATE, "no adaptation plan (call avs_adapt first)");
+  if (correction < 0 || correction > 2) return fail(AVS_E_INVALID, "correction must be 0, 1 or 2");
+  if (avs_status st = DISPATCH(ctx, launch_remap, ctx, correction)) return st;
+  ctx->lcur ^= 1;
+  ctx->cur ^= 1;
+  ctx->plan_valid = false;
+  if (avs_status st = DISPATCH_D(ctx, launch_bc_tables, ctx)) return st;
+  if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
+  return check_bad(ctx);
+}
+
+avs_status avs_leaves(avs_ctx* ctx, int64_t* n_host, int64_t* ld_host, int32_t* level_host, int32_t* idx_host,
+                      double* xi_host, double* w_host) {
+  if (avs_status st = guard(ctx)) return st;
+  const int t = ctx->lcur, n = ctx->nleaf[t], D = ctx->D;
+  if (n_host) *n_host = n;
+  if (ld_host) *ld_host = ctx->ld[t];
+  std::vector<int> ib((size_t)D * n);
+  std::vector<double> xb((size_t)D * n);
+  if (level_host) CK(hipMemcpyAsync(level_host, ctx->lt[t].level, sizeof(int) * n, hipMemcpyDeviceToHost, ctx->stream));
+  if (w_host) CK(hipMemcpyAsync(w_host, ctx->lt[t].w, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+  for (int d = 0; d < D; ++d) {
+    if (idx_host)
+      CK(hipMemcpyAsync(ib.data() + (size_t)d * n, ctx->lt[t].idx + (size_t)d * ctx->cap, sizeof(int) * n,
+                        hipMemcpyDeviceToHost, ctx->stream));
+    if (xi_host)
+      CK(hipMemcpyAsync(xb.data() + (size_t)d * n, ctx->lt[t].xi + (size_t)d * ctx->cap, sizeof(double) * n,
+                        hipMemcpyDeviceToHost, ctx->stream));
+  }
+  CK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < n; ++k)
+    for (int d = 0; d < D; ++d) {
+      if (idx_host) idx_host[(size_t)k * D + d] = ib[(size_t)d * n + k];
+      if (xi_host) xi_host[(size_t)k * D + d] = xb[(size_t)d * n + k];
+    }
+  return AVS_OK;
+}
+
+avs_status avs_plan(avs_ctx* ctx, int32_t* kind_host, int64_t* src_host, int32_t* child_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (!ctx->plan_valid) return fail(AVS_E_STATE, "no adaptation plan");
+  const int n = ctx->plan_n;
+  std::vector<int> s(n);
+  if (kind_host) CK(hipMemcpyAsync(kind_host, ctx->pkind, sizeof(int) * n, hipMemcpyDeviceToHost, ctx->stream));
+  if (child_host) CK(hipMemcpyAsync(child_host, ctx->pchild, sizeof(int) * n, hipMemcpyDeviceToHost, ctx->stream));
+  if (src_host) CK(hipMemcpyAsync(s.data(), ctx->psrc, sizeof(int) * n, hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  if (src_host)
+    for (int j = 0; j < n; ++j) src_host[j] = s[j];
+  return AVS_OK;
+}
+
+avs_status avs_criterion(avs_ctx* ctx, double* Mk_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (!ctx->plan_valid) return fail(AVS_E_STATE, "no adaptation result");
+  if (!Mk_host) return fail(AVS_E_INVALID, "Mk_host is null");
+  CK(hipMemcpyAsync(Mk_host, ctx->Mk, sizeof(double) * ctx->nleaf[ctx->lcur], hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  return AVS_OK;
+}
+
+avs_status avs_set_leaves(avs_ctx* ctx, int64_t n, const int32_t* level_host, const int32_t* idx_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (n < 1 || n > ctx->cap) return fail(AVS_E_INVALID, "leaf count %" PRId64 " outside [1, capacity]", n);
+  if (!level_host || !idx_host) return fail(AVS_E_INVALID, "null leaf arrays");
+  const int D = ctx->D;
+  // a valid leaf set tiles the forest: in-range cells, increasing disjoint Morton ranges, full cover
+  uint64_t next = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    const int l = level_host[k];
+    if (l < 0 || l > ctx->lmax) return fail(AVS_E_INVALID, "leaf %" PRId64 ": level out of range", k);
+    for (int d = 0; d < D; ++d)
+      if (idx_host[k * D + d] < 0 || idx_host[k * D + d] >= (ctx->base[d] << l))
+        return fail(AVS_E_INVALID, "leaf %" PRId64 ": index out of range", k);
+    const uint64_t key = morton(D, ctx->lmax, l, idx_host + k * D);
+    if (k > 0 && key < next) return fail(AVS_E_INVALID, "leaf %" PRId64 " overlaps or is out of depth-first order", k);
+    next = key + (1ull << (D * (ctx->lmax - l)));
+  }
+  uint64_t total = 1;
+  for (int d = 0; d < D; ++d) total *= (uint64_t)ctx->base[d] << ctx->lmax;
+  // disjoint in-box cells whose volumes add up to the box tile it
+  uint64_t covered = 0;
+  for (int64_t k = 0; k < n; ++k) covered += 1ull << (D * (ctx->lmax - level_host[k]));
+  if (covered != total) return fail(AVS_E_INVALID, "leaves do not cover the velocity box");
+  std::vector<int> lev(level_host, level_host + n);
+  const int t = ctx->lcur ^ 1;
+  if (avs_status st = upload_leaves(ctx, t, (int)n, lev.data(), idx_host)) return st;
+  ctx->lcur = t;
+  ctx->plan_valid = false;
+  if (avs_status st = DISPATCH(ctx, launch_init_vdf, ctx)) return st;
+  if (avs_status st = DISPATCH_D(ctx, launch_bc_tables, ctx)) return st;
+  if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
+  return check_bad(ctx);
+}
+
+avs_status avs_get_state(avs_ctx* ctx, double* vdf_host, double* W_host) {
+  if (avs_status st = guard(ctx)) return st;
+  const int n = ctx->nleaf[ctx->lcur], ld = ctx->ld[ctx->lcur], N = ctx->D + 2;
+  if (W_host) CK(hipMemcpyAsync(W_host, ctx->W, sizeof(double) * ctx->nc * N, hipMemcpyDeviceToHost, ctx->stream));
+  if (vdf_host) {
+    const size_t es = ctx->esize(), cs = (size_t)ctx->nc * ld;
+    if (ctx->prec == AVS_FP64) {
+      CK(hipMemcpy2DAsync(vdf_host, n * es, ctx->vdf[ctx->cur], ld * es, n * es, (size_t)ctx->P * ctx->nc,
+                          hipMemcpyDeviceToHost, ctx->stream));
+    } else {
+      std::vector<float> tmp((size_t)ctx->P * ctx->nc * n);
+      CK(hipMemcpy2DAsync(tmp.data(), n * es, ctx->vdf[ctx->cur], ld * es, n * es, (size_t)ctx->P * ctx->nc,
+                          hipMemcpyDeviceToHost, ctx->stream));
+      CK(hipStreamSynchronize(ctx->stream));
+      for (size_t t = 0; t < tmp.size(); ++t) vdf_host[t] = tmp[t];
+    }
+    (void)cs;
+  }
+  CK(hipStreamSynchronize(ctx->stream));
+  return AVS_OK;
+}
+
+avs_status avs_set_state(avs_ctx* ctx, const double* vdf_host, const double* W_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (!W_host) return fail(AVS_E_INVALID, "W_host is required");
+  const int n = ctx->nleaf[ctx->lcur], ld = ctx->ld[ctx->lcur], D = ctx->D, N = D + 2;
+  for (int i = 0; i < ctx->nc; ++i) {
+    const double* w = W_host + (size_t)i * N;
+    double ke = 0;
+    for (int d = 0; d < D; ++d) ke += w[1 + d] * w[1 + d];
+    if (!(w[0] > 0) || !(w[1 + D] - 0.5 * ke / w[0] > 0)) return fail(AVS_E_INVALID, "W of cell %d is not physical", i);
+  }
+  CK(hipMemcpyAsync(ctx->W, W_host, sizeof(double) * ctx->nc * N, hipMemcpyHostToDevice, ctx->stream));
+  if (vdf_host) {
+    const size_t es = ctx->esize();
+    if (ctx->prec == AVS_FP64) {
+      CK(hipMemcpy2DAsync(ctx->vdf[ctx->cur], ld * es, vdf_host, n * es, n * es, (size_t)ctx->P * ctx->nc,
+                          hipMemcpyHostToDevice, ctx->stream));
+      CK(hipStreamSynchronize(ctx->stream));
+    } else {
+      std::vector<float> tmp;
+      copy_from_host(tmp, vdf_host, (size_t)ctx->P * ctx->nc * n);
+      CK(hipMemcpy2DAsync(ctx->vdf[ctx->cur], ld * es, tmp.data(), n * es, n * es, (size_t)ctx->P * ctx->nc,
+                          hipMemcpyHostToDevice, ctx->stream));
+      CK(hipStreamSynchronize(ctx->stream));
+    }
+  } else {
+    if (avs_status st = DISPATCH(ctx, launch_init_vdf, ctx)) return st;
+  }
+  ctx->plan_valid = false;
+  if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
+  return check_bad(ctx);
+}
+
+avs_status avs_get_cells(avs_ctx* ctx, int64_t ncell_sel, const int64_t* cells_host, double* vdf_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (ncell_sel < 0 || (ncell_sel > 0 && (!cells_host || !vdf_host))) return fail(AVS_E_INVALID, "bad selection");
+  const int n = ctx->nleaf[ctx->lcur], ld = ctx->ld[ctx->lcur];
+  const size_t es = ctx->esize(), cs = (size_t)ctx->nc * ld;
+  std::vector<char> tmp((size_t)n * es);
+  for (int64_t r = 0; r < ncell_sel; ++r) {
+    const int64_t c = cells_host[r];
+    if (c < 0 || c >= ctx->nc) return fail(AVS_E_INVALID, "cell %" PRId64 " out of range", c);
+    for (int p = 0; p < ctx->P; ++p) {
+      const char* src = (const char*)ctx->vdf[ctx->cur] + ((size_t)p * cs + (size_t)c * ld) * es;
+      CK(hipMemcpyAsync(tmp.data(), src, n * es, hipMemcpyDeviceToHost, ctx->stream));
+      CK(hipStreamSynchronize(ctx->stream));
+      double* o = vdf_host + ((size_t)p * ncell_sel + r) * n;
+      if (ctx->prec == AVS_FP64)
+        memcpy(o, tmp.data(), n * es);
+      else
+        for (int k = 0; k < n; ++k) o[k] = ((const float*)tmp.data())[k];
+    }
+  }
+  return AVS_OK;
+}
+
+avs_status avs_profile(avs_ctx* ctx, int32_t enable) {
+  if (avs_status st = guard(ctx)) return st;
+  CK(hipStreamSynchronize(ctx->stream));
+  if (enable) {
+    ctx->evused = 0;
+    ctx->evrec.clear();
+  }
+  ctx->prof = enable != 0;
+  return AVS_OK;
+}
+
+int32_t avs_profile_read(avs_ctx* ctx, int32_t nmax, char* names_host, double* ms_host, int64_t* count_host) {
+  if (guard(ctx)) return -1;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return -1;
+  double ms[K_NKERNELS] = {0};
+  int64_t cnt[K_NKERNELS] = {0};
+  for (const auto& r : ctx->evrec) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ctx->evpool[r.second], ctx->evpool[r.second + 1]) == hipSuccess) {
+      ms[r.first] += t;
+      cnt[r.first] += 1;
+    }
+  }
+  int n = 0;
+  for (int k = 0; k < K_NKERNELS && n < nmax; ++k) {
+    if (!cnt[k]) continue;
+    if (names_host) snprintf(names_host + 32 * n, 32, "%s", kKernelNames[k]);
+    if (ms_host) ms_host[n] = ms[k];
+    if (count_host) count_host[n] = cnt[k];
+    ++n;
+  }
+  return n;
+}
+
+void avs_destroy(avs_ctx* ctx) {
+  if (!ctx) return;
+  for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* avs_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,1232 @@
+// HIP kernels of the global adaptive-velocity-space sweep (gfx950).
+//
+// Layout: vdf[comp][cell][leaf], leaf fastest, row stride L.ld.  One
+// workgroup of 256 threads (4 wave64) owns one physical cell and streams its
+// velocity row in chunks of 256 consecutive leaves, so every VDF access is a
+// coalesced 256-element segment and all per-cell data are wave-uniform.
+// Maxwellians are evaluated from separable per-axis exponential tables held
+// in LDS: every leaf centre lies on the half-finest grid of the velocity box,
+// so exp(-|xi-U|^2/2RT) = prod_d t_d[u_d] with t_d tabulated once per
+// face/cell instead of one exp per (cell, leaf).
+#include "avs_internal.h"
+
+namespace avs {
+
+template <typename T>
+__device__ __forceinline__ double ld_(const T* p) { return (double)(*p); }
+
+template <int D>
+struct Cfg {
+  static constexpr int P = (D == 2) ? 2 : 1;
+  static constexpr int MAXF = (D == 2) ? MAXF2 : MAXF3;
+  static constexpr int NM = (D == 2) ? NM2 : NM3;
+  static constexpr int NS = (D + 2) * (D + 3) / 2;   // symmetric Gram entries
+};
+
+// ---------------------------------------------------------------- reductions
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[m] += __shfl_xor(v[m], o);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) red[w * N + m] = v[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] = (red[m] + red[N + m]) + (red[2 * N + m] + red[3 * N + m]);
+  __syncthreads();
+}
+
+// ------------------------------------------------------------- equilibria
+template <int D>
+__device__ __forceinline__ void build_tab(double* tab, const double* par, const VGrid& vg) {
+  const double i2rt = par[P_I2RT];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double x0 = vg.x0[d], hh = vg.hh[d], U = par[P_U + d];
+    for (int u = threadIdx.x; u < vg.numax; u += BLOCK) {
+      const double c = (x0 + u * hh) - U;
+      tab[d * vg.numax + u] = exp(-(c * c) * i2rt);
+    }
+  }
+}
+
+template <int D>
+__device__ __forceinline__ double maxw(const double* par, const double* tab, int numax, const int (&u)[D]) {
+  double g = par[P_COEF];
+#pragma unroll
+  for (int d = 0; d < D; ++d) g *= tab[d * numax + u[d]];
+  return g;
+}
+
+// Shakhov pair (G, H) from the Maxwellian value g (Eqs. equ14-equ17, K = 0).
+template <int D>
+__device__ __forceinline__ void shakhov(const double* par, double g, const double (&xi)[D], double& G, double& H) {
+  double c2 = 0.0, cq = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double c = xi[d] - par[P_U + d];
+    c2 += c * c;
+    cq += c * par[P_Q + d];
+  }
+  const double sk = par[P_SHK] * cq, irt = par[P_IRT];
+  G = g + sk * (c2 * irt - (D + 2)) * g;
+  if (D == 2) {
+    const double rtg = par[P_RT] * g;
+    H = rtg + sk * (c2 * irt - D) * rtg;
+  } else {
+    H = 0.0;
+  }
+}
+
+// Fill an NPAR record from conserved W (cell target or face state).
+template <int D>
+__device__ __forceinline__ bool prim_from_W(const double* W, const GasP& gas, double& rho, double (&U)[D], double& T) {
+  rho = W[0];
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    U[d] = W[1 + d] / rho;
+    ke += U[d] * U[d];
+  }
+  T = (W[1 + D] - 0.5 * rho * ke) / (1.5 * rho * gas.R);
+  return rho > 0.0 && T > 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ void eq_record(double* par, double rho, const double (&U)[D], double T, const double* q,
+                                          const GasP& gas) {
+  const double RT = gas.R * T;
+  par[P_COEF] = rho * pow(2.0 * M_PI * RT, -0.5 * D);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) par[P_U + d] = d < D ? U[d] : 0.0;
+  par[P_RT] = RT;
+  par[P_I2RT] = 0.5 / RT;
+  par[P_IRT] = 1.0 / RT;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) par[P_Q + d] = (d < D && q) ? q[d] : 0.0;
+  par[P_SHK] = gas.model == 1 ? (1.0 - gas.Pr) / (5.0 * rho * RT * RT) : 0.0;
+}
+
+__device__ __forceinline__ double tau_of(double rho, double T, const GasP& gas) {
+  return gas.mu_ref * pow(T / gas.T_ref, gas.omega) / (rho * gas.R * T);
+}
+
+// Solve J x = b ((D+2)x(D+2)) by Gaussian elimination with partial pivoting.
+template <int N>
+__device__ bool solve_small(double (&J)[N][N], double (&b)[N], double (&x)[N]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    int p = c;
+    double best = fabs(J[c][c]);
+#pragma unroll
+    for (int r = c + 1; r < N; ++r)
+      if (fabs(J[r][c]) > best) { best = fabs(J[r][c]); p = r; }
+    if (!(best > 0.0)) return false;
+    if (p != c) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) { double t = J[c][k]; J[c][k] = J[p][k]; J[p][k] = t; }
+      double t = b[c]; b[c] = b[p]; b[p] = t;
+    }
+#pragma unroll
+    for (int r = c + 1; r < N; ++r) {
+      const double f = J[r][c] / J[c][c];
+#pragma unroll
+      for (int k = c; k < N; ++k) J[r][k] -= f * J[c][k];
+      b[r] -= f * b[c];
+    }
+  }
+#pragma unroll
+  for (int r = N - 1; r >= 0; --r) {
+    double s = b[r];
+#pragma unroll
+    for (int k = r + 1; k < N; ++k) s -= J[r][k] * x[k];
+    x[r] = s / J[r][r];
+  }
+  return true;
+}
+
+// Gram matrix of the equilibrium directions: S = sum_k A_k b_a b_b g_k with
+// b = (1, c_1..c_D, |c|^2) about the record's U (accumulated per node).
+template <int D>
+__device__ __forceinline__ void gram_acc(double* S, double Ag, const double (&c)[D], double c2) {
+  double b[D + 2];
+  b[0] = 1.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) b[1 + d] = c[d];
+  b[D + 1] = c2;
+  int m = 0;
+#pragma unroll
+  for (int a = 0; a < D + 2; ++a) {
+#pragma unroll
+    for (int e = a; e < D + 2; ++e) S[m++] += Ag * b[a] * b[e];
+  }
+}
+
+// J_lm = M_l[e_m] for e_m = (b_m g, (3-D) RT b_m g), from S (see closure).
+template <int D>
+__device__ __forceinline__ void gram_to_J(const double* S, const double* par, double (&J)[D + 2][D + 2]) {
+  double Sf[D + 2][D + 2];
+  int m = 0;
+#pragma unroll
+  for (int a = 0; a < D + 2; ++a) {
+#pragma unroll
+    for (int e = a; e < D + 2; ++e) { Sf[a][e] = S[m]; Sf[e][a] = S[m]; ++m; }
+  }
+  double U2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) U2 += par[P_U + d] * par[P_U + d];
+  const double hidden = (D == 2) ? par[P_RT] : 0.0;
+#pragma unroll
+  for (int c = 0; c < D + 2; ++c) {
+    J[0][c] = Sf[0][c];
+    double e = 0.5 * Sf[D + 1][c] + 0.5 * (U2 + hidden) * Sf[0][c];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      J[1 + d][c] = Sf[1 + d][c] + par[P_U + d] * Sf[0][c];
+      e += par[P_U + d] * Sf[1 + d][c];
+    }
+    J[D + 1][c] = e;
+  }
+}
+
+// s = xi . n as the ordered sum of products without contraction: its sign
+// picks the upwind side, so it must be reproducible bit for bit.
+template <int D>
+__device__ __forceinline__ double normal_speed(const double (&xi)[D], const double* n) {
+#pragma clang fp contract(off)
+  double s = xi[0] * n[0];
+#pragma unroll
+  for (int d = 1; d < D; ++d) s = s + xi[d] * n[d];
+  return s;
+}
+
+// Moment contribution sum A (G, xi G, (|xi|^2 G + H)/2).
+template <int D>
+__device__ __forceinline__ void mom_acc(double* M, double A, const double (&xi)[D], double xi2, double G, double H) {
+  const double aG = A * G;
+  M[0] += aG;
+#pragma unroll
+  for (int d = 0; d < D; ++d) M[1 + d] += aG * xi[d];
+  M[D + 1] += 0.5 * A * (xi2 * G + H);
+}
+
+template <int D>
+__device__ __forceinline__ void leaf_load(const Leaves& L, int k, double (&xi)[D], double& A, int (&u)[D]) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    xi[d] = L.xi[d * L.cap + k];
+    u[d] = L.u[d * L.cap + k];
+  }
+  A = L.w[k];
+}
+
+// ---------------------------------------------------------- leaf geometry
+// xi = lo + (idx + 1/2) h_l, A = prod h_l, h_l = (hi - lo)/(base 2^l); the
+// operation order matches the oracle exactly (no contraction) so that the
+// criterion can be compared bit for bit.
+template <int D>
+__global__ void k_leaf_geom(int n, int cap, const int* __restrict__ level, const int* __restrict__ idx,
+                            int* __restrict__ u, double* __restrict__ xi, double* __restrict__ w, VGrid vg,
+                            int lmax, int b0, int b1, int b2, double lo0, double lo1, double lo2, double hi0,
+                            double hi1, double hi2) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= n) return;
+  const int l = level[k];
+  const int base[3] = {b0, b1, b2};
+  const double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+  double a = 1.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double h = (hi[d] - lo[d]) / (double)(base[d] << l);
+    const int ix = idx[d * cap + k];
+    xi[d * cap + k] = lo[d] + ((double)ix + 0.5) * h;
+    u[d * cap + k] = (2 * ix + 1) << (lmax - l);
+    a = (d == 0) ? h : a * h;
+  }
+  w[k] = a;
+}
+
+// ------------------------------------------------ initial state / closure
+// phi = closure(g_eq(W), W): discrete Maxwellian corrected along its own
+// equilibrium directions so that its moments equal W.
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_init_vdf(Geo g, Leaves L, VGrid vg, GasP gas, const double* __restrict__ W,
+                                                     T* __restrict__ vdf, int* __restrict__ bad) {
+  constexpr int N = D + 2, NS = Cfg<D>::NS;
+  extern __shared__ double lds[];
+  double* tab = lds;
+  double* red = lds + D * vg.numax;
+  __shared__ double par[NPAR];
+  __shared__ double lam[N];
+  const int i = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double rho, U[D], T_;
+    if (!prim_from_W<D>(W + (size_t)i * N, gas, rho, U, T_)) atomicMin(bad, i);
+    eq_record<D>(par, rho, U, T_, nullptr, gas);
+  }
+  __syncthreads();
+  build_tab<D>(tab, par, vg);
+  __syncthreads();
+  double acc[N + NS];
+#pragma unroll
+  for (int m = 0; m < N + NS; ++m) acc[m] = 0.0;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    const double gv = maxw<D>(par, tab, vg.numax, u);
+    double c[D], c2 = 0.0, xi2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) { c[d] = xi[d] - par[P_U + d]; c2 += c[d] * c[d]; xi2 += xi[d] * xi[d]; }
+    mom_acc<D>(acc, A, xi, xi2, gv, D == 2 ? par[P_RT] * gv : 0.0);
+    gram_acc<D>(acc + N, A * gv, c, c2);
+  }
+  block_sum<N + NS>(acc, red);
+  if (threadIdx.x == 0) {
+    double J[N][N], b[N], x[N];
+    gram_to_J<D>(acc + N, par, J);
+    for (int m = 0; m < N; ++m) b[m] = W[(size_t)i * N + m] - acc[m];
+    if (!solve_small<N>(J, b, x)) atomicMin(bad, i);
+    for (int m = 0; m < N; ++m) lam[m] = x[m];
+  }
+  __syncthreads();
+  const size_t cs = (size_t)g.nc * L.ld;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    const double gv = maxw<D>(par, tab, vg.numax, u);
+    double c2 = 0.0, poly = lam[0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double c = xi[d] - par[P_U + d];
+      c2 += c * c;
+      poly += lam[1 + d] * c;
+    }
+    poly += lam[D + 1] * c2;
+    const double G = gv + poly * gv;
+    vdf[(size_t)i * L.ld + k] = (T)G;
+    if (D == 2) vdf[cs + (size_t)i * L.ld + k] = (T)(par[P_RT] * G);
+  }
+}
+
+// ------------------------------------------------------- cell moments / q
+// M[phi_i] and q_i = 1/2 sum A c (c^2 G + H), c = xi - U(W_i) (Eqs. updat_W, equ8).
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf,
+                                                         const double* __restrict__ W, double* __restrict__ mom,
+                                                         double* __restrict__ q) {
+  constexpr int N = D + 2;
+  __shared__ double red[4 * (N + D)];
+  const int i = blockIdx.x;
+  const size_t cs = (size_t)g.nc * L.ld;
+  double U[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) U[d] = W[(size_t)i * N + 1 + d] / W[(size_t)i * N];
+  double acc[N + D];
+#pragma unroll
+  for (int m = 0; m < N + D; ++m) acc[m] = 0.0;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    const double G = ld_(vdf + (size_t)i * L.ld + k);
+    const double H = (D == 2) ? ld_(vdf + cs + (size_t)i * L.ld + k) : 0.0;
+    double xi2 = 0.0, c[D], c2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) { xi2 += xi[d] * xi[d]; c[d] = xi[d] - U[d]; c2 += c[d] * c[d]; }
+    mom_acc<D>(acc, A, xi, xi2, G, H);
+    const double e = 0.5 * A * (c2 * G + H);
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[N + d] += e * c[d];
+  }
+  block_sum<N + D>(acc, red);
+  if (threadIdx.x == 0) {
+    for (int m = 0; m < N; ++m) mom[(size_t)i * N + m] = acc[m];
+    for (int d = 0; d < D; ++d) q[(size_t)i * D + d] = acc[N + d];
+  }
+}
+
+// ------------------------------------------------- limited gradient (S2-S3)
+// Least-squares gradient and Venkatakrishnan limiter of cell c at leaf k.
+template <int D, typename T>
+__device__ __forceinline__ void lim_grad(const Geo& g, const T* __restrict__ vdf, size_t cs, int ld, int c, int k,
+                                         double (&phi)[Cfg<D>::P], double (&lg)[Cfg<D>::P][D]) {
+  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+  const int ns = g.nslot[c];
+  double pmax[P], pmin[P], grad[P][D];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    phi[p] = ld_(vdf + p * cs + (size_t)c * ld + k);
+    pmax[p] = phi[p];
+    pmin[p] = phi[p];
+#pragma unroll
+    for (int d = 0; d < D; ++d) grad[p][d] = 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) {
+    if (s < ns) {
+      const int j = g.s_nbr[c * MAXF + s];
+      if (j >= 0) {
+        const double* cf = g.s_lsq + (size_t)(c * MAXF + s) * D;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const double v = ld_(vdf + p * cs + (size_t)j * ld + k);
+          const double dv = v - phi[p];
+#pragma unroll
+          for (int d = 0; d < D; ++d) grad[p][d] += dv * cf[d];
+          pmax[p] = fmax(pmax[p], v);
+          pmin[p] = fmin(pmin[p], v);
+        }
+      }
+    }
+  }
+  const double eps2 = g.eps2[c];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    double lim = ns > 0 ? INFINITY : 1.0;
+#pragma unroll
+    for (int s = 0; s < MAXF; ++s) {
+      if (s < ns) {
+        const double* dd = g.s_d + (size_t)(c * MAXF + s) * D;
+        double d2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) d2 += grad[p][d] * dd[d];
+        double psi = 1.0;
+        if (d2 != 0.0) {
+          // Venkatakrishnan psi, divided through by D2 (and by D1 when eps = 0)
+          // so that VDF values near the bottom of the FP64 range do not underflow.
+          const double d1 = d2 > 0.0 ? pmax[p] - phi[p] : pmin[p] - phi[p];
+          if (eps2 > 0.0) {
+            psi = (d1 * d1 + eps2 + 2.0 * d1 * d2) / (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2);
+          } else if (d1 == 0.0) {
+            psi = 0.0;
+          } else {
+            const double t = d2 / d1;
+            psi = (1.0 + 2.0 * t) / (1.0 + t + 2.0 * t * t);
+          }
+        }
+        lim = fmin(lim, psi);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) lg[p][d] = lim * grad[p][d];
+  }
+}
+
+// ------------------------------------------------------- pass A (S4, S5 part)
+// Per cell, per face of the cell: raw moments of the upwind reconstruction
+// over the leaves for which this cell is upwind.  Summed with the other
+// side's partial, they give the interface moments (Eq. w_interface).
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_passA(Geo g, Leaves L, const T* __restrict__ vdf, double h,
+                                                  double* __restrict__ part) {
+  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF, NM = Cfg<D>::NM;
+  __shared__ double red[4 * NM];
+  const int i = blockIdx.x;
+  const int ns = g.nslot[i];
+  const size_t cs = (size_t)g.nc * L.ld;
+  double nrm[MAXF][D], dd[MAXF][D], sig[MAXF];
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) {
+    const int f = s < ns ? g.s_face[i * MAXF + s] : 0;
+    sig[s] = s < ns ? g.s_sig[i * MAXF + s] : 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      nrm[s][d] = g.f_nrm[(size_t)f * D + d];
+      dd[s][d] = g.s_d[(size_t)(i * MAXF + s) * D + d];
+    }
+  }
+  double acc[MAXF][NM];
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[s][m] = 0.0;
+  }
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    double phi[P], lg[P][D];
+    lim_grad<D, T>(g, vdf, cs, L.ld, i, k, phi, lg);
+    double xi2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+#pragma unroll
+    for (int s = 0; s < MAXF; ++s) {
+      if (s < ns) {
+        const double sn = normal_speed<D>(xi, nrm[s]);
+        const bool up = sig[s] > 0.0 ? (sn >= 0.0) : (sn < 0.0);
+        if (up) {
+          double pb[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            double v = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) v += lg[p][d] * (dd[s][d] - xi[d] * h);
+            pb[p] = phi[p] + v;
+          }
+          const double aG = A * pb[0];
+          int m = 0;
+          acc[s][m++] += aG;
+#pragma unroll
+          for (int d = 0; d < D; ++d) acc[s][m++] += aG * xi[d];
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+#pragma unroll
+            for (int e = d; e < D; ++e) acc[s][m++] += aG * xi[d] * xi[e];
+          }
+          const double eh = 0.5 * A * (xi2 * pb[0] + (P == 2 ? pb[P - 1] : 0.0));
+          acc[s][m++] += eh;
+#pragma unroll
+          for (int d = 0; d < D; ++d) acc[s][m++] += eh * xi[d];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) {
+    block_sum<NM>(acc[s], red);
+    if (threadIdx.x == 0 && s < ns) {
+#pragma unroll
+      for (int m = 0; m < NM; ++m) part[((size_t)i * MAXF + s) * NM + m] = acc[s][m];
+    }
+  }
+}
+
+// Flux of a raw-moment set through normal n: (n.m1, n.m2, n.e1).
+template <int D>
+__device__ __forceinline__ void raw_flux(const double* m, const double* n, double* F) {
+  F[0] = 0.0;
+  for (int d = 0; d < D; ++d) F[0] += n[d] * m[1 + d];
+  int idx[3][3];
+  int t = 1 + D;
+  for (int d = 0; d < D; ++d)
+    for (int e = d; e < D; ++e) { idx[d][e] = t; idx[e][d] = t; ++t; }
+  for (int d = 0; d < D; ++d) {
+    double v = 0.0;
+    for (int e = 0; e < D; ++e) v += n[e] * m[idx[d][e]];
+    F[1 + d] = v;
+  }
+  const int e1 = 2 + D + D * (D + 1) / 2;
+  double v = 0.0;
+  for (int d = 0; d < D; ++d) v += n[d] * m[e1 + d];
+  F[D + 1] = v;
+}
+
+// ---------------------------------------------------- face parameters (S5)
+// Interior faces: W_f, q_f, tau_f, Shakhov record and blend weights, and
+// the flux of the reconstructed VDF.  Boundary faces: final flux (outgoing
+// reconstruction + incoming wall/far-field Maxwellian) and rho_w.
+template <int D>
+__global__ void k_face_params(Geo g, GasP gas, double h, const double* __restrict__ part,
+                              const double* __restrict__ bden, const double* __restrict__ bfin,
+                              double* __restrict__ fpar, double* __restrict__ Fbar, double* __restrict__ F,
+                              int* __restrict__ bad) {
+  constexpr int MAXF = Cfg<D>::MAXF, NM = Cfg<D>::NM, N = D + 2;
+  const int f = blockIdx.x * BLOCK + threadIdx.x;
+  if (f >= g.nf) return;
+  const int L = g.f_L[f], R = g.f_R[f];
+  const double* n = g.f_nrm + (size_t)f * D;
+  double m[NM];
+  const double* pl = part + ((size_t)L * MAXF + g.f_sL[f]) * NM;
+  if (R >= 0) {
+    const double* pr = part + ((size_t)R * MAXF + g.f_sR[f]) * NM;
+    for (int t = 0; t < NM; ++t) m[t] = pl[t] + pr[t];
+    const double rho = m[0];
+    double U[D], ke = 0.0;
+    for (int d = 0; d < D; ++d) { U[d] = m[1 + d] / rho; ke += U[d] * U[d]; }
+    const int ie = 1 + D + D * (D + 1) / 2;
+    const double E = m[ie];
+    const double T = (E - 0.5 * rho * ke) / (1.5 * rho * gas.R);
+    if (!(rho > 0.0 && T > 0.0)) atomicMin(bad, g.nc + f);
+    // q about U from raw moments: e1_d - U_d E - sum_e U_e (m2_de - rho U_d U_e) + |U|^2/2 (m1_d - U_d rho)
+    int idx[3][3];
+    int t = 1 + D;
+    for (int d = 0; d < D; ++d)
+      for (int e = d; e < D; ++e) { idx[d][e] = t; idx[e][d] = t; ++t; }
+    double q[D];
+    for (int d = 0; d < D; ++d) {
+      double v = m[ie + 1 + d] - U[d] * E;
+      for (int e = 0; e < D; ++e) v -= U[e] * (m[idx[d][e]] - rho * U[d] * U[e]);
+      v += 0.5 * ke * (m[1 + d] - U[d] * rho);
+      q[d] = v;
+    }
+    const double tf = tau_of(rho, T, gas);
+    const double qs = tf / (tf + h * gas.Pr);
+    for (int d = 0; d < D; ++d) q[d] *= qs;
+    double* par = fpar + (size_t)f * NPAR;
+    eq_record<D>(par, rho, U, T, q, gas);
+    par[P_A] = tf / (tf + h);
+    par[P_B] = h / (tf + h);
+    raw_flux<D>(m, n, Fbar + (size_t)f * N);
+  } else {
+    const int bc = -1 - R;
+    double Fo[N];
+    raw_flux<D>(pl, n, Fo);
+    const double* fin = bfin + (size_t)f * N;
+    double scale = 1.0;
+    if (g.bc_kind[bc] == 0) {
+      scale = Fo[0] / bden[f];
+      fpar[(size_t)f * NPAR] = scale;
+    }
+    for (int t = 0; t < N; ++t) F[(size_t)f * N + t] = Fo[t] + scale * fin[t];
+  }
+}
+
+// ------------------------------------ interface equilibrium flux (S6, S8)
+// F_f = a sum A s psi phibar + b sum A s psi g_f for interior faces.
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_face_eqflux(Geo g, Leaves L, VGrid vg, const double* __restrict__ fpar,
+                                                        const double* __restrict__ Fbar, double* __restrict__ F) {
+  constexpr int N = D + 2;
+  extern __shared__ double lds[];
+  double* tab = lds;
+  __shared__ double red[4 * N];
+  const int f = g.f_int[blockIdx.x];
+  const double* par = fpar + (size_t)f * NPAR;
+  build_tab<D>(tab, par, vg);
+  double n[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
+  __syncthreads();
+  double acc[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) acc[m] = 0.0;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    const double gv = maxw<D>(par, tab, vg.numax, u);
+    double G, H;
+    shakhov<D>(par, gv, xi, G, H);
+    const double sn = normal_speed<D>(xi, n);
+    double xi2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+    mom_acc<D>(acc, A * sn, xi, xi2, G, H);
+  }
+  block_sum<N>(acc, red);
+  if (threadIdx.x == 0) {
+    const double a = par[P_A], b = par[P_B];
+    for (int m = 0; m < N; ++m) F[(size_t)f * N + m] = a * Fbar[(size_t)f * N + m] + b * acc[m];
+  }
+}
+
+// ------------------------------------------------------ macro update (S8-S9)
+template <int D>
+__global__ void k_macro(Geo g, GasP gas, double dt, const double* __restrict__ F, const double* __restrict__ W,
+                        double* __restrict__ Wn, const double* __restrict__ qcur, double* __restrict__ tpar,
+                        int* __restrict__ bad) {
+  constexpr int MAXF = Cfg<D>::MAXF, N = D + 2;
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= g.nc) return;
+  const int ns = g.nslot[i];
+  double Fs[N];
+  for (int m = 0; m < N; ++m) Fs[m] = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    const int f = g.s_face[i * MAXF + s];
+    const double sa = g.s_sigA[i * MAXF + s];
+    for (int m = 0; m < N; ++m) Fs[m] += sa * F[(size_t)f * N + m];
+  }
+  double w[N];
+  const double dtv = g.dtv[i];
+  for (int m = 0; m < N; ++m) {
+    w[m] = W[(size_t)i * N + m] - dtv * Fs[m];
+    Wn[(size_t)i * N + m] = w[m];
+  }
+  double rho, U[D], T;
+  if (!prim_from_W<D>(w, gas, rho, U, T)) { atomicMin(bad, i); rho = 1.0; T = 1.0; }
+  double* par = tpar + (size_t)i * NPAR;
+  eq_record<D>(par, rho, U, T, qcur + (size_t)i * D, gas);
+  par[P_A] = dt / tau_of(rho, T, gas);
+  par[P_RHO] = rho;
+  par[P_T] = T;
+}
+
+// --------------------------------------- conservative relaxation target (S9)
+// lambda such that closure(Shakhov(W^{n+1}, q^n)) has moments W^{n+1}.
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, const double* __restrict__ tpar,
+                                                   const double* __restrict__ Wn, double* __restrict__ lam,
+                                                   int* __restrict__ bad) {
+  constexpr int N = D + 2, NS = Cfg<D>::NS;
+  extern __shared__ double lds[];
+  double* tab = lds;
+  __shared__ double red[4 * (N + NS)];
+  const int i = blockIdx.x;
+  const double* par = tpar + (size_t)i * NPAR;
+  build_tab<D>(tab, par, vg);
+  __syncthreads();
+  double acc[N + NS];
+#pragma unroll
+  for (int m = 0; m < N + NS; ++m) acc[m] = 0.0;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    const double gv = maxw<D>(par, tab, vg.numax, u);
+    double G, H;
+    shakhov<D>(par, gv, xi, G, H);
+    double c[D], c2 = 0.0, xi2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) { c[d] = xi[d] - par[P_U + d]; c2 += c[d] * c[d]; xi2 += xi[d] * xi[d]; }
+    mom_acc<D>(acc, A, xi, xi2, G, H);
+    gram_acc<D>(acc + N, A * gv, c, c2);
+  }
+  block_sum<N + NS>(acc, red);
+  if (threadIdx.x == 0) {
+    double J[N][N], b[N], x[N];
+    gram_to_J<D>(acc + N, par, J);
+    for (int m = 0; m < N; ++m) b[m] = Wn[(size_t)i * N + m] - acc[m];
+    if (!solve_small<N>(J, b, x)) { atomicMin(bad, i); for (int m = 0; m < N; ++m) x[m] = 0.0; }
+    for (int m = 0; m < N; ++m) lam[(size_t)i * N + m] = x[m];
+  }
+}
+
+// -------------------------------------------------- pass C (S6, S7, S10)
+// Interface VDFs of every face of the cell (own reconstruction for outgoing
+// leaves, the neighbour's for incoming ones), flux divergence, relaxation
+// towards the closed Shakhov target, store phi^{n+1}, and the moments and
+// heat flux of phi^{n+1} for the next step.
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
+                                                  T* __restrict__ vout, const double* __restrict__ fpar,
+                                                  const double* __restrict__ tpar, const double* __restrict__ lam,
+                                                  const double* __restrict__ bcpair, double h,
+                                                  double* __restrict__ mom, double* __restrict__ qout) {
+  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF, N = D + 2;
+  extern __shared__ double lds[];
+  __shared__ double red[4 * (N + D)];
+  __shared__ double spar[(MAXF + 1) * NPAR];
+  __shared__ double slam[N];
+  const int i = blockIdx.x;
+  const int ns = g.nslot[i];
+  const int nu = vg.numax;
+  const size_t cs = (size_t)g.nc * L.ld;
+  for (int t = threadIdx.x; t < (MAXF + 1) * NPAR; t += BLOCK) {
+    const int s = t / NPAR, m = t - s * NPAR;
+    double v = 0.0;
+    if (s < MAXF) {
+      if (s < ns) v = fpar[(size_t)g.s_face[i * MAXF + s] * NPAR + m];
+    } else {
+      v = tpar[(size_t)i * NPAR + m];
+    }
+    spar[t] = v;
+  }
+  if (threadIdx.x < N) slam[threadIdx.x] = lam[(size_t)i * N + threadIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) {
+    if (s < ns && g.s_nbr[i * MAXF + s] >= 0) build_tab<D>(lds + s * D * nu, spar + s * NPAR, vg);
+  }
+  build_tab<D>(lds + MAXF * D * nu, spar + MAXF * NPAR, vg);
+  __syncthreads();
+  const double* tp = spar + MAXF * NPAR;
+  const double dtt = tp[P_A], dtv = g.dtv[i];
+  double acc[N + D];
+#pragma unroll
+  for (int m = 0; m < N + D; ++m) acc[m] = 0.0;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    double phi[P], lg[P][D];
+    lim_grad<D, T>(g, vin, cs, L.ld, i, k, phi, lg);
+    double div[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) div[p] = 0.0;
+#pragma unroll
+    for (int s = 0; s < MAXF; ++s) {
+      if (s < ns) {
+        const int f = g.s_face[i * MAXF + s];
+        const int j = g.s_nbr[i * MAXF + s];
+        const double sg = g.s_sig[i * MAXF + s];
+        const double sn = normal_speed<D>(xi, g.f_nrm + (size_t)f * D);
+        const bool up = sg > 0.0 ? (sn >= 0.0) : (sn < 0.0);
+        double pf[P];
+        if (up) {
+          const double* dd = g.s_d + (size_t)(i * MAXF + s) * D;
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            double v = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) v += lg[p][d] * (dd[d] - xi[d] * h);
+            pf[p] = phi[p] + v;
+          }
+        } else if (j >= 0) {
+          double pj[P], lj[P][D];
+          lim_grad<D, T>(g, vin, cs, L.ld, j, k, pj, lj);
+          const int sj = sg > 0.0 ? g.f_sR[f] : g.f_sL[f];
+          const double* dd = g.s_d + (size_t)(j * MAXF + sj) * D;
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            double v = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) v += lj[p][d] * (dd[d] - xi[d] * h);
+            pf[p] = pj[p] + v;
+          }
+        } else {
+          const int bc = -1 - g.f_R[f];
+          const double sc = g.bc_kind[bc] == 0 ? spar[s * NPAR] : 1.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p) pf[p] = sc * bcpair[((size_t)bc * P + p) * L.cap + k];
+        }
+        if (j >= 0) {
+          const double* par = spar + s * NPAR;
+          const double gv = maxw<D>(par, lds + s * D * nu, nu, u);
+          double G, H;
+          shakhov<D>(par, gv, xi, G, H);
+          pf[0] = par[P_A] * pf[0] + par[P_B] * G;
+          if (P == 2) pf[P - 1] = par[P_A] * pf[P - 1] + par[P_B] * H;
+        }
+        const double w = g.s_sigA[i * MAXF + s] * sn;
+#pragma unroll
+        for (int p = 0; p < P; ++p) div[p] += w * pf[p];
+      }
+    }
+    // closed Shakhov target
+    const double gv = maxw<D>(tp, lds + MAXF * D * nu, nu, u);
+    double G, H;
+    shakhov<D>(tp, gv, xi, G, H);
+    double c[D], c2 = 0.0, poly = slam[0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      c[d] = xi[d] - tp[P_U + d];
+      c2 += c[d] * c[d];
+      poly += slam[1 + d] * c[d];
+    }
+    poly += slam[D + 1] * c2;
+    const double tgt[2] = {G + poly * gv, H + poly * tp[P_RT] * gv};
+    const double inv = 1.0 / (1.0 + dtt);
+    double nv[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      nv[p] = (phi[p] + dtt * tgt[p] - dtv * div[p]) * inv;
+      const T st = (T)nv[p];
+      vout[p * cs + (size_t)i * L.ld + k] = st;
+      nv[p] = (double)st;
+    }
+    double xi2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+    const double Hn = (P == 2) ? nv[P - 1] : 0.0;
+    mom_acc<D>(acc, A, xi, xi2, nv[0], Hn);
+    const double e = 0.5 * A * (c2 * nv[0] + Hn);
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[N + d] += e * c[d];
+  }
+  block_sum<N + D>(acc, red);
+  if (threadIdx.x == 0) {
+    for (int m = 0; m < N; ++m) mom[(size_t)i * N + m] = acc[m];
+    for (int d = 0; d < D; ++d) qout[(size_t)i * D + d] = acc[N + d];
+  }
+}
+
+// ----------------------------------------------- boundary Maxwellians (S7)
+// Per bc and leaf: the incoming Maxwellian pair (unit density for walls).
+template <int D>
+__global__ void k_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ kind, const double* __restrict__ prim,
+                           double* __restrict__ pair) {
+  constexpr int P = Cfg<D>::P;
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  const int b = blockIdx.y;
+  if (k >= L.n) return;
+  const double* st = prim + (size_t)b * (D + 2);
+  const double rho = kind[b] == 0 ? 1.0 : st[0];
+  const double T = st[1 + D], RT = gas.R * T;
+  double c2 = 0.0;
+  for (int d = 0; d < D; ++d) {
+    const double c = L.xi[d * L.cap + k] - st[1 + d];
+    c2 += c * c;
+  }
+  const double gv = rho * pow(2.0 * M_PI * RT, -0.5 * D) * exp(-c2 / (2.0 * RT));
+  pair[((size_t)b * P + 0) * L.cap + k] = gv;
+  if (P == 2) pair[((size_t)b * P + 1) * L.cap + k] = RT * gv;
+}
+
+// Per boundary face: den = sum_{s<0} A |s| g_wall and Fin = sum_{s<0} A s psi pair.
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_bnd_tables(Geo g, Leaves L, const double* __restrict__ pair,
+                                                       double* __restrict__ bden, double* __restrict__ bfin) {
+  constexpr int P = Cfg<D>::P, N = D + 2;
+  __shared__ double red[4 * (N + 1)];
+  const int f = g.f_bnd[blockIdx.x];
+  const int bc = -1 - g.f_R[f];
+  double n[D];
+  for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
+  double acc[N + 1];
+  for (int m = 0; m < N + 1; ++m) acc[m] = 0.0;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    const double sn = normal_speed<D>(xi, n);
+    double xi2 = 0.0;
+    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+    if (sn < 0.0) {
+      const double G = pair[((size_t)bc * P) * L.cap + k];
+      const double H = P == 2 ? pair[((size_t)bc * P + 1) * L.cap + k] : 0.0;
+      mom_acc<D>(acc, A * sn, xi, xi2, G, H);
+      acc[N] += A * (-sn) * G;
+    }
+  }
+  block_sum<N + 1>(acc, red);
+  if (threadIdx.x == 0) {
+    for (int m = 0; m < N; ++m) bfin[(size_t)f * N + m] = acc[m];
+    bden[f] = acc[N];
+  }
+}
+
+// ----------------------------------------------------- criterion (Sec. 3.4)
+// Per-cell constants of the criterion, same operation order as the oracle.
+template <int D>
+__global__ void k_crit_cells(int nc, const double* __restrict__ W, double* __restrict__ cc) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  const double* w = W + (size_t)i * (D + 2);
+  const double rho = w[0];
+  double U[D];
+  for (int d = 0; d < D; ++d) U[d] = w[1 + d] / rho;
+  double ke = U[0] * U[0];
+  for (int d = 1; d < D; ++d) ke = ke + U[d] * U[d];
+  const double eint = w[1 + D] - 0.5 * rho * ke;
+  double* o = cc + (size_t)i * (D + 2);
+  o[0] = rho;
+  for (int d = 0; d < D; ++d) o[1 + d] = U[d];
+  o[1 + D] = eint;
+}
+
+template <int D>
+__device__ __forceinline__ double crit_one(const double (&xi)[D], double A, double G, double H, const double* cc) {
+#pragma clang fp contract(off)
+  double c = xi[0] - cc[1];
+  double c2 = c * c;
+  for (int d = 1; d < D; ++d) {
+    c = xi[d] - cc[1 + d];
+    c2 = c2 + c * c;
+  }
+  const double M1 = (A * G) / cc[0];
+  const double M2 = (0.5 * (A * (c2 * G + H))) / cc[1 + D];
+  return fmax(M1, M2);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_crit_partial(Leaves L, int nc, const T* __restrict__ vdf,
+                                                         const double* __restrict__ cc, double* __restrict__ part) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  const int grp = blockIdx.y;
+  if (k >= L.n) return;
+  const size_t cs = (size_t)nc * L.ld;
+  double xi[D], A;
+  int u[D];
+  leaf_load<D>(L, k, xi, A, u);
+  double m = -INFINITY;
+  const int i1 = min(nc, (grp + 1) * CRIT_CELLS);
+  for (int i = grp * CRIT_CELLS; i < i1; ++i) {
+    const double G = ld_(vdf + (size_t)i * L.ld + k);
+    const double H = D == 2 ? ld_(vdf + cs + (size_t)i * L.ld + k) : 0.0;
+    m = fmax(m, crit_one<D>(xi, A, G, H, cc + (size_t)i * (D + 2)));
+  }
+  part[(size_t)grp * L.cap + k] = m;
+}
+
+// Max over cell groups and probe states; raw split/merge flags.
+template <int D>
+__global__ void k_crit_reduce(Leaves L, int ngrp, const double* __restrict__ part, int nprobe,
+                              const double* __restrict__ probe_cc, const double* __restrict__ probe_prim, GasP gas,
+                              double C1, double C2, int lmax, double* __restrict__ Mk, int8_t* __restrict__ raw) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= L.n) return;
+  double m = -INFINITY;
+  for (int t = 0; t < ngrp; ++t) m = fmax(m, part[(size_t)t * L.cap + k]);
+  double xi[D], A;
+  int u[D];
+  leaf_load<D>(L, k, xi, A, u);
+  for (int p = 0; p < nprobe; ++p) {
+    const double* pr = probe_prim + (size_t)p * (D + 2);
+    const double rho = pr[0], T = pr[1 + D], RT = gas.R * T;
+    double c2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const double c = xi[d] - pr[1 + d];
+      c2 += c * c;
+    }
+    const double gv = rho * pow(2.0 * M_PI * RT, -0.5 * D) * exp(-c2 / (2.0 * RT));
+    m = fmax(m, crit_one<D>(xi, A, gv, D == 2 ? RT * gv : 0.0, probe_cc + (size_t)p * (D + 2)));
+  }
+  Mk[k] = m;
+  const int l = L.level[k];
+  int8_t r = 0;
+  if (m > C1 && l < lmax) r = 1;
+  if (m < C2 && l > 0) r = -1;
+  raw[k] = r;
+}
+
+// Effective flags (a brother group merges only if complete and unanimous)
+// and the number of new leaves each old leaf produces.
+template <int D>
+__global__ void k_resolve(Leaves L, const int8_t* __restrict__ raw, int8_t* __restrict__ eff, int* __restrict__ cnt) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= L.n) return;
+  const int8_t r = raw[k];
+  const int l = L.level[k];
+  int cnum = 0;
+  for (int d = 0; d < D; ++d) cnum |= (L.idx[d * L.cap + k] & 1) << d;
+  int8_t e = r;
+  if (r == -1) {
+    const int first = k - cnum;
+    bool ok = first >= 0 && first + (1 << D) <= L.n;
+    for (int c = 0; ok && c < (1 << D); ++c) {
+      const int m = first + c;
+      if (raw[m] != -1 || L.level[m] != l) { ok = false; break; }
+      int cm = 0;
+      for (int d = 0; d < D; ++d) {
+        const int a = L.idx[d * L.cap + m], b = L.idx[d * L.cap + k];
+        if ((a >> 1) != (b >> 1)) ok = false;
+        cm |= (a & 1) << d;
+      }
+      if (cm != c) ok = false;
+    }
+    e = ok ? -1 : 0;
+  }
+  eff[k] = e;
+  cnt[k] = e == 0 ? 1 : (e == 1 ? (1 << D) : (cnum == 0 ? 1 : 0));
+}
+
+// Exclusive scan of n counts in one workgroup (deterministic, any n).
+__global__ __launch_bounds__(BLOCK) void k_scan(int n, const int* __restrict__ cnt, int* __restrict__ off) {
+  __shared__ int part[BLOCK];
+  const int per = (n + BLOCK - 1) / BLOCK;
+  const int b = threadIdx.x * per, e = min(n, b + per);
+  int s = 0;
+  for (int k = b; k < e; ++k) s += cnt[k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < BLOCK; ++t) { const int v = part[t]; part[t] = run; run += v; }
+    off[n] = run;
+  }
+  __syncthreads();
+  int run = part[threadIdx.x];
+  for (int k = b; k < e; ++k) { off[k] = run; run += cnt[k]; }
+}
+
+template <int D>
+__global__ void k_scatter(Leaves L, const int8_t* __restrict__ eff, const int* __restrict__ off, int ncap,
+                          int* __restrict__ nlevel, int* __restrict__ nidx, int* __restrict__ kind,
+                          int* __restrict__ src, int* __restrict__ child) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= L.n) return;
+  const int e = eff[k], l = L.level[k], o = off[k];
+  int ix[D], cnum = 0;
+  for (int d = 0; d < D; ++d) { ix[d] = L.idx[d * L.cap + k]; cnum |= (ix[d] & 1) << d; }
+  if (e == 0) {
+    if (o >= ncap) return;
+    nlevel[o] = l;
+    for (int d = 0; d < D; ++d) nidx[d * ncap + o] = ix[d];
+    kind[o] = 0; src[o] = k; child[o] = 0;
+  } else if (e == 1) {
+    for (int c = 0; c < (1 << D); ++c) {
+      if (o + c >= ncap) return;
+      nlevel[o + c] = l + 1;
+      for (int d = 0; d < D; ++d) nidx[d * ncap + o + c] = 2 * ix[d] + ((c >> d) & 1);
+      kind[o + c] = 1; src[o + c] = k; child[o + c] = c;
+    }
+  } else if (cnum == 0) {
+    if (o >= ncap) return;
+    nlevel[o] = l - 1;
+    for (int d = 0; d < D; ++d) nidx[d * ncap + o] = ix[d] >> 1;
+    kind[o] = 2; src[o] = k; child[o] = 0;
+  }
+}
+
+// ------------------------------------------------------- remap (Sec. 3.2)
+// Gather the new rows (copy or pairwise mean of 2^D brothers) and the
+// moments W' of the result.
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_remap_gather(Geo g, Leaves Lo, Leaves Ln, const int* __restrict__ kind,
+                                                         const int* __restrict__ src, const T* __restrict__ vin,
+                                                         T* __restrict__ vout, double* __restrict__ momp) {
+#pragma clang fp contract(off)
+  constexpr int P = Cfg<D>::P, N = D + 2;
+  __shared__ double red[4 * N];
+  const int i = blockIdx.x;
+  const size_t cso = (size_t)g.nc * Lo.ld, csn = (size_t)g.nc * Ln.ld;
+  double acc[N];
+  for (int m = 0; m < N; ++m) acc[m] = 0.0;
+  for (int j = threadIdx.x; j < Ln.n; j += BLOCK) {
+    const int k = src[j];
+    const bool mg = kind[j] == 2;
+    T v[P];
+    for (int p = 0; p < P; ++p) {
+      const T* r = vin + p * cso + (size_t)i * Lo.ld + k;
+      if (mg) {
+        if (D == 2) {
+          v[p] = ((r[0] + r[1]) + (r[2] + r[3])) * (T)0.25;
+        } else {
+          v[p] = (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]))) * (T)0.125;
+        }
+      } else {
+        v[p] = r[0];
+      }
+      vout[p * csn + (size_t)i * Ln.ld + j] = v[p];
+    }
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(Ln, j, xi, A, u);
+    double xi2 = 0.0;
+    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+    mom_acc<D>(acc, A, xi, xi2, (double)v[0], P == 2 ? (double)v[P - 1] : 0.0);
+  }
+  block_sum<N>(acc, red);
+  if (threadIdx.x == 0)
+    for (int m = 0; m < N; ++m) momp[(size_t)i * N + m] = acc[m];
+}
+
+// Conservation correction of Sec. 3.3: f = f' + g_eq(W) - g_eq(W'), then
+// (mode 2) the closure that restores M[f] = W.  In place on the new rows.
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode,
+                                                          const double* __restrict__ W,
+                                                          const double* __restrict__ momp, T* __restrict__ vdf,
+                                                          int* __restrict__ bad) {
+  constexpr int P = Cfg<D>::P, N = D + 2, NS = Cfg<D>::NS;
+  extern __shared__ double lds[];
+  double* tabA = lds;
+  double* tabB = lds + D * vg.numax;
+  __shared__ double red[4 * (2 * N + NS)];
+  __shared__ double parA[NPAR], parB[NPAR];
+  __shared__ double lam[N];
+  const int i = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double rho, U[D], T_;
+    if (!prim_from_W<D>(W + (size_t)i * N, gas, rho, U, T_)) atomicMin(bad, i);
+    eq_record<D>(parA, rho, U, T_, nullptr, gas);
+    if (!prim_from_W<D>(momp + (size_t)i * N, gas, rho, U, T_)) atomicMin(bad, i);
+    eq_record<D>(parB, rho, U, T_, nullptr, gas);
+  }
+  __syncthreads();
+  build_tab<D>(tabA, parA, vg);
+  build_tab<D>(tabB, parB, vg);
+  __syncthreads();
+  if (mode == 2) {
+    double acc[2 * N + NS];
+    for (int m = 0; m < 2 * N + NS; ++m) acc[m] = 0.0;
+    for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+      double xi[D], A;
+      int u[D];
+      leaf_load<D>(L, k, xi, A, u);
+      const double ga = maxw<D>(parA, tabA, vg.numax, u), gb = maxw<D>(parB, tabB, vg.numax, u);
+      double c[D], c2 = 0.0, xi2 = 0.0;
+      for (int d = 0; d < D; ++d) { c[d] = xi[d] - parA[P_U + d]; c2 += c[d] * c[d]; xi2 += xi[d] * xi[d]; }
+      mom_acc<D>(acc, A, xi, xi2, ga, D == 2 ? parA[P_RT] * ga : 0.0);
+      mom_acc<D>(acc + N, A, xi, xi2, gb, D == 2 ? parB[P_RT] * gb : 0.0);
+      gram_acc<D>(acc + 2 * N, A * ga, c, c2);
+    }
+    block_sum<2 * N + NS>(acc, red);
+    if (threadIdx.x == 0) {
+      double J[N][N], b[N], x[N];
+      gram_to_J<D>(acc + 2 * N, parA, J);
+      for (int m = 0; m < N; ++m) b[m] = W[(size_t)i * N + m] - (momp[(size_t)i * N + m] + acc[m] - acc[N + m]);
+      if (!solve_small<N>(J, b, x)) { atomicMin(bad, i); for (int m = 0; m < N; ++m) x[m] = 0.0; }
+      for (int m = 0; m < N; ++m) lam[m] = x[m];
+    }
+  } else if (threadIdx.x < N) {
+    lam[threadIdx.x] = 0.0;
+  }
+  __syncthreads();
+  const size_t cs = (size_t)g.nc * L.ld;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    const double ga = maxw<D>(parA, tabA, vg.numax, u), gb = maxw<D>(parB, tabB, vg.numax, u);
+    double c2 = 0.0, poly = lam[0];
+    for (int d = 0; d < D; ++d) {
+      const double c = xi[d] - parA[P_U + d];
+      c2 += c * c;
+      poly += lam[1 + d] * c;
+    }
+    poly += lam[D + 1] * c2;
+    T* r = vdf + (size_t)i * L.ld + k;
+    r[0] = (T)(ld_(r) + (ga - gb) + poly * ga);
+    if (P == 2) r[cs] = (T)(ld_(r + cs) + (parA[P_RT] * ga - parB[P_RT] * gb) + poly * parA[P_RT] * ga);
+  }
+}
+
+// -------------------------------------------------- residual, totals, fields
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_residual(int nc, const double* __restrict__ W, const double* __restrict__ Wn,
+                                                     double invdt, double* __restrict__ out) {
+  constexpr int N = D + 2;
+  __shared__ double red[4 * N];
+  double acc[N];
+  for (int m = 0; m < N; ++m) acc[m] = 0.0;
+  for (int i = threadIdx.x; i < nc; i += BLOCK)
+    for (int m = 0; m < N; ++m) {
+      const double d = Wn[(size_t)i * N + m] - W[(size_t)i * N + m];
+      acc[m] += d * d;
+    }
+  block_sum<N>(acc, red);
+  if (threadIdx.x == 0)
+    for (int m = 0; m < N; ++m) out[m] = sqrt(acc[m]) * invdt;
+}
+
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_totals(int nc, const double* __restrict__ vol, const double* __restrict__ W,
+                                                   double* __restrict__ out) {
+  constexpr int N = D + 2;
+  __shared__ double red[4 * N];
+  double acc[N];
+  for (int m = 0; m < N; ++m) acc[m] = 0.0;
+  for (int i = threadIdx.x; i < nc; i += BLOCK)
+    for (int m = 0; m < N; ++m) acc[m] += vol[i] * W[(size_t)i * N + m];
+  block_sum<N>(acc, red);
+  if (threadIdx.x == 0)
+    for (int m = 0; m < N; ++m) out[m] = acc[m];
+}
+
+template <int D>
+__global__ void k_fields(int nc, GasP gas, const double* __restrict__ W, const double* __restrict__ q,
+                         double* __restrict__ out) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= nc) return;
+  double rho, U[D], T;
+  prim_from_W<D>(W + (size_t)i * (D + 2), gas, rho, U, T);
+  double* o = out + (size_t)i * (2 * D + 2);
+  o[0] = rho;
+  for (int d = 0; d < D; ++d) o[1 + d] = U[d];
+  o[1 + D] = T;
+  for (int d = 0; d < D; ++d) o[2 + D + d] = q[(size_t)i * D + d];
+}
+
+// Copy rows between the storage type and FP64 host staging [P][rows][n].
+template <typename T>
+__global__ void k_pack(int P, int nrow, int n, int ld, size_t cs, const int64_t* __restrict__ rows,
+                       const T* __restrict__ vdf, double* __restrict__ out) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  const int r = blockIdx.y, p = blockIdx.z;
+  if (k >= n) return;
+  const size_t c = rows ? (size_t)rows[r] : (size_t)r;
+  out[((size_t)p * nrow + r) * n + k] = (double)vdf[p * cs + c * ld + k];
+}
+
+template <typename T>
+__global__ void k_unpack(int P, int nrow, int n, int ld, size_t cs, const double* __restrict__ in, T* __restrict__ vdf) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  const int r = blockIdx.y, p = blockIdx.z;
+  if (k >= n) return;
+  vdf[p * cs + (size_t)r * ld + k] = (T)in[((size_t)p * nrow + r) * n + k];
+}
+
+}  // namespace avs

@@ -118,14 +118,16 @@ def strip(values, K):
 
 
 def test_venkatakrishnan_properties():
-    """Limiter properties (K -> 0 so eps -> 0):
-    * a linear profile is not limited (psi = 1 on both faces);
+    """Limiter properties:
+    * a linear profile is not limited (psi = 1 on both faces) for any eps;
     * a smooth extremum has zero gradient, so nothing is reconstructed;
-    * when the slope would overshoot a neighbour by far, the limited increment
-      tends to the distance to that neighbour (L * D2 -> D1)."""
-    mesh, phi = strip([0.0, 1.0, 2.0, 3.0], 0.0)
-    lg = O.limited_gradient(1, phi, mesh, 0.0)
-    assert abs(lg[0, 0, 0] - 1.0) < 1e-15 and abs(lg[0, 0, 1]) < 1e-15
+    * (eps = 0) when the slope would overshoot a neighbour by far, the limited
+      increment tends to the distance to that neighbour (L * D2 -> D1), and it
+      never exceeds it, also for VDF values near the bottom of the FP64 range."""
+    for K in (0.0, 0.7, 2.0):          # linear data is never limited, whatever eps
+        mesh, phi = strip([0.0, 1.0, 2.0, 3.0], K)
+        lg = O.limited_gradient(1, phi, mesh, K)
+        assert abs(lg[0, 0, 0] - 1.0) < 1e-15 and abs(lg[0, 0, 1]) < 1e-15
     mesh, phi = strip([0.0, 1.0, 0.0], 0.0)
     assert np.all(O.limited_gradient(1, phi, mesh, 0.0) == 0.0)
     for delta in (1e-3, 1e-5):
@@ -133,6 +135,10 @@ def test_venkatakrishnan_properties():
         lg = O.limited_gradient(1, phi, mesh, 0.0)
         inc = lg[0, 0, 0] * 0.5          # limited increment to the east face
         assert abs(inc / delta - 1.0) < 10 * delta ** 0.5
+    for scale in (1.0, 1e-200, 1e-300):
+        mesh, phi = strip([0.0, scale, 1.3 * scale, 0.2 * scale], 0.0)
+        lg = O.limited_gradient(1, phi, mesh, 0.0)
+        assert np.isfinite(lg).all() and 0.0 < lg[0, 0, 0] * 0.5 <= 0.3 * scale
     # eps -> infinity switches the limiter off (psi -> 1)
     mesh, phi = strip([0.0, 1.0, 1.2, 0.1], 1e6)
     lg = O.limited_gradient(1, phi, mesh, 1e6)

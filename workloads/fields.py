@@ -104,10 +104,11 @@ def cavity(n=32, Ma=0.16, Kn=0.075, omega=0.5, box=5.0, base=16, max_level=2, C1
                 dt=dt, venkat_K=1.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=200)
 
 
-def cylinder(nr=128, nth=256, Ma=5.0, Kn=0.1, omega=0.81, box=15.0, base=32, max_level=3, C1=2e-4, cfl=0.8, seed=0):
+def cylinder(nr=128, nth=256, Ma=5.0, Kn=0.1, omega=0.81, box=15.0, base=32, max_level=3, C1=2e-4, cfl=0.8, seed=0,
+             r1=15.0, first=0.01):
     """2-D supersonic flow past a cylinder (Sec. 4.1 shape), units sqrt(R Tinf) with R=1/2."""
     R, Tinf, gamma = 0.5, 1.0, 5.0 / 3.0
-    mesh = meshes.ogrid(nr, nth, r0=0.5, r1=15.0, first=0.01)
+    mesh = meshes.ogrid(nr, nth, r0=0.5, r1=r1, first=first)
     U_inf = Ma * math.sqrt(gamma * R * Tinf)
     mesh['bc_state'][0] = (1.0, 0.0, 0.0, Tinf)
     mesh['bc_state'][1] = (1.0, U_inf, 0.0, Tinf)
@@ -116,21 +117,22 @@ def cylinder(nr=128, nth=256, Ma=5.0, Kn=0.1, omega=0.81, box=15.0, base=32, max
     return dict(name='cylinder', dim=2, mesh=mesh, prim0=W0, probes=probes,
                 vspace=dict(dim=2, lo=(-box, -box), hi=(box, box), base=(base, base), max_level=max_level),
                 gas=dict(R=R, Pr=2.0 / 3.0, omega=omega, Kn=Kn, L_ref=1.0, rho_ref=1.0, T_ref=Tinf, model=1),
-                dt=dt, venkat_K=1.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=100)
+                dt=dt, venkat_K=0.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=100)
 
 
-def sphere(nr=64, nth=64, nph=32, Ma=4.0, Kn=0.05, omega=0.74, box=12.0, base=16, max_level=2, C1=2e-5, cfl=0.8, seed=0):
+def sphere(nr=64, nth=64, nph=32, Ma=4.0, Kn=0.05, omega=0.74, box=12.0, base=16, max_level=2, C1=2e-5, cfl=0.8, seed=0,
+           r1=8.0, first=0.02):
     """3-D supersonic flow past a sphere (Sec. 4.6 shape), monatomic, R=1/2."""
     R, Tinf, gamma = 0.5, 1.0, 5.0 / 3.0
     U_inf = Ma * math.sqrt(gamma * R * Tinf)
-    mesh = meshes.sphere_grid(nr, nth, nph, r0=0.5, r1=8.0, first=0.02,
+    mesh = meshes.sphere_grid(nr, nth, nph, r0=0.5, r1=r1, first=first,
                               wall_state=(1.0, 0.0, 0.0, 0.0, Tinf), far_state=(1.0, U_inf, 0.0, 0.0, Tinf))
     W0, probes = blunt_body_field(mesh['cell_ctr'], 0.5, Ma, R, Tinf, seed=seed)
     dt = _cfl_dt(mesh, cfl, box)
     return dict(name='sphere', dim=3, mesh=mesh, prim0=W0, probes=probes,
                 vspace=dict(dim=3, lo=(-box,) * 3, hi=(box,) * 3, base=(base,) * 3, max_level=max_level),
                 gas=dict(R=R, Pr=2.0 / 3.0, omega=omega, Kn=Kn, L_ref=1.0, rho_ref=1.0, T_ref=Tinf, model=1),
-                dt=dt, venkat_K=1.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=50)
+                dt=dt, venkat_K=0.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=50)
 
 
 def _cfl_dt(mesh, cfl, box):

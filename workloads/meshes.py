@@ -277,3 +277,36 @@ def sphere_grid(nr, nth, nph, r0=0.5, r1=8.0, first=0.02, wall_state=None, far_s
     m = _finish(3, vol, ctr, faces, [(WALL, ws), (FARFIELD, fs)], (nr, nth, nph))
     m['radii'] = r
     return m
+
+
+def submesh(desc, cells, halo=2):
+    """The cells within ``halo`` face-neighbour rings of ``cells``, as a mesh.
+
+    Faces between two kept cells and boundary faces of kept cells are kept;
+    faces to dropped cells are dropped, so only the outermost ring has an
+    incomplete face list.  Returns ``(sub, keep)`` with ``keep`` the global
+    ids of the kept cells (sub cell j is global cell keep[j]).
+    """
+    lr = np.asarray(desc['face_lr'])
+    nbrs = [[] for _ in range(desc['ncells'])]
+    for L, R in lr:
+        if R >= 0:
+            nbrs[L].append(R)
+            nbrs[R].append(L)
+    keep = set(int(c) for c in cells)
+    ring = set(keep)
+    for _ in range(halo):
+        ring = {n for c in ring for n in nbrs[c]} - keep
+        keep |= ring
+    keep = np.array(sorted(keep), dtype=np.int64)
+    loc = {int(g): j for j, g in enumerate(keep)}
+    fsel = [f for f, (L, R) in enumerate(lr) if L in loc and (R < 0 or R in loc)]
+    fsel = np.array(fsel, dtype=np.int64)
+    sub_lr = lr[fsel].copy()
+    sub_lr[:, 0] = [loc[int(L)] for L in sub_lr[:, 0]]
+    sub_lr[:, 1] = [loc[int(R)] if R >= 0 else int(R) for R in sub_lr[:, 1]]
+    sub = dict(desc)
+    sub.update(ncells=len(keep), nfaces=len(fsel), cell_vol=desc['cell_vol'][keep], cell_ctr=desc['cell_ctr'][keep],
+               face_lr=sub_lr, face_area=desc['face_area'][fsel], face_nrm=desc['face_nrm'][fsel],
+               face_ctr=desc['face_ctr'][fsel], face_shift=desc['face_shift'][fsel])
+    return sub, keep
