@@ -42,9 +42,14 @@ def parse():
     p.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     p.add_argument("--forms", action="store_true", help="also time the FP32 form")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--no-sweep", action="store_true", help="skip the extra sweep-only timing (profiling runs)")
+    p.add_argument("--copy-probe", type=float, default=0.0,
+                   help="GiB copied device-to-device by torch before the run (calibrates HBM byte counters)")
     p.add_argument("--nr", type=int, default=128)
     p.add_argument("--nth", type=int, default=256)
-    p.add_argument("--C1", type=float, default=None, help="skip calibration and use this C1")
+    # C1 for a ~2e4-leaf step-0 tree on this workload, found once by the --calibrate bisection
+    p.add_argument("--C1", type=float, default=1.74658e-06, help="splitting threshold (C2 = e^-8 C1)")
+    p.add_argument("--calibrate", action="store_true", help="bisect C1 for --leaves instead of using --C1")
     return p.parse_args()
 
 
@@ -109,7 +114,9 @@ def timed_cycles(w, C1, nu, steps, warmup):
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     updates = 0
+    node_launches = 0
     leaves = []
+    cs.profile(True)          # HIP events around every kernel group, on the library's stream
     e0.record(stream)
     for k in range(steps):
         nv = cs.nleaves()
@@ -120,9 +127,11 @@ def timed_cycles(w, C1, nu, steps, warmup):
         updates += w.nc * nv * nu
     e1.record(stream)
     torch.cuda.synchronize()
+    prof = cs.profile_read()
+    cs.profile(False)
     ms = e0.elapsed_time(e1)
     log(f"timed {steps} cycles: {ms:.1f} ms, leaves {leaves}")
-    return updates, ms, leaves
+    return updates, ms, leaves, prof
 
 
 def sweep_only(w, nsweep):
@@ -136,18 +145,6 @@ def sweep_only(w, nsweep):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     return w.nc * nv * nsweep / (ms * 1e-3), ms / nsweep, nv
-
-
-def kernel_profile(w, C1, nu):
-    cs = w.cs
-    nv = cs.nleaves()
-    cs.profile(True)
-    cs.step(nu)
-    cs.adapt(C1, math.exp(-8.0) * C1)
-    cs.remap(2)
-    prof = cs.profile_read()
-    cs.profile(False)
-    return prof, nv
 
 
 def vdf_bytes_per_node(P, es):
@@ -184,14 +181,15 @@ def cpu_baseline(w, ncell_sample=16):
 def run_form(args, precision, C1=None):
     w = Workload(args, precision)
     if C1 is None:
-        C1 = args.C1 if args.C1 is not None else w.calibrate(args.leaves)
+        C1 = w.calibrate(args.leaves) if args.calibrate else args.C1
     n0 = w.tree(C1)
     log(f"{precision}: C1={C1:.6g}, step-0 tree {n0} leaves")
-    updates, ms, leaves = timed_cycles(w, C1, args.nu, args.steps, args.warmup)
-    sw_rate, sw_ms, sw_nv = sweep_only(w, args.nu)
-    prof, pnv = kernel_profile(w, C1, args.nu)
-    return w, C1, dict(updates=updates, ms=ms, leaves=leaves, sweep_rate=sw_rate, sweep_ms=sw_ms, sweep_leaves=sw_nv,
-                       prof=prof, prof_leaves=pnv)
+    updates, ms, leaves, prof = timed_cycles(w, C1, args.nu, args.steps, args.warmup)
+    sw = sweep_only(w, args.nu) if not args.no_sweep else (None, None, None)
+    # kernels of the sweep run once per sweep at the leaf count of their cycle
+    mean_leaves = sum(leaves) / len(leaves)
+    return w, C1, dict(updates=updates, ms=ms, leaves=leaves, sweep_rate=sw[0], sweep_ms=sw[1], sweep_leaves=sw[2],
+                       prof=prof, prof_leaves=mean_leaves)
 
 
 def main():
@@ -202,6 +200,13 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * 2 ** 30)
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w, C1, r = run_form(args, args.precision)
     P, es = 2, (8 if args.precision == "fp64" else 4)
     prof = r["prof"]

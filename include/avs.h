@@ -14,9 +14,10 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Memory.  The library never allocates device memory.  The caller provides
- *   two device regions at init: the VDF region (size avs_vdf_bytes) and a
- *   workspace (size avs_workspace_bytes); both must stay alive and untouched
- *   by the caller until avs_destroy.  Arguments named *_host are host
+ *   two device regions at init: the VDF region (size avs_vdf_bytes: the
+ *   current and next VDF plus one interface row per face) and a workspace
+ *   (size avs_workspace_bytes); both must stay alive and untouched by the
+ *   caller until avs_destroy.  Arguments named *_host are host
  *   pointers, *_dev device pointers.
  * Layout.  VDF values are stored component-major, cell-major, leaf-fastest:
  *   vdf[comp][cell][leaf] with a row stride of avs_leaves().ld elements.
@@ -117,7 +118,7 @@ typedef struct {
  * (rho_ref, T_ref) (Eqs. equ4, equ5). */
 double avs_mu_ref_from_kn(double Kn, double omega, double R, double T_ref, double rho_ref, double L_ref);
 
-/* Bytes the caller must provide for the two VDF buffers / the workspace. */
+/* Bytes the caller must provide for the VDF region / the workspace. */
 size_t avs_vdf_bytes(const avs_vspace *vs, const avs_pmesh *pm, const avs_opts *op);
 size_t avs_workspace_bytes(const avs_vspace *vs, const avs_pmesh *pm, const avs_opts *op);
 

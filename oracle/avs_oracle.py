@@ -349,15 +349,18 @@ def venkat_psi(d1, d2, eps2):
     """psi = [(D1^2+eps^2) D2 + 2 D2^2 D1] / [D2 (D1^2 + 2 D2^2 + D1 D2 + eps^2)], 1 if D2 = 0.
 
     Evaluated after dividing through by D2, and for eps = 0 through the ratio
-    t = D2/D1 >= 0 as (1 + 2t) / (1 + t + 2t^2) (0 when D1 = 0): the same
-    function, but without the underflow of D2^3 for VDF values near 1e-300.
+    t = D2/D1 >= 0 as (1 + 2t) / (1 + t + 2t^2) when t <= 1, or through
+    u = 1/t as u (u + 2) / (u^2 + u + 2) when t > 1: the same function, but
+    free of underflow and overflow for VDF values near the ends of the range.
     """
     with np.errstate(divide='ignore', invalid='ignore', over='ignore'):
         if eps2 > 0:
             psi = (d1 * d1 + eps2 + 2.0 * d1 * d2) / (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2)
         else:
+            small = np.abs(d2) <= np.abs(d1)
             t = d2 / d1
-            psi = np.where(d1 == 0.0, 0.0, (1.0 + 2.0 * t) / (1.0 + t + 2.0 * t * t))
+            u = d1 / d2
+            psi = np.where(small, (1.0 + 2.0 * t) / (1.0 + t + 2.0 * t * t), u * (u + 2.0) / (u * u + u + 2.0))
     return np.where(d2 == 0.0, 1.0, psi)
 
 

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libavs.so")
+# AVS_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("AVS_LIBRARY", os.path.join(_HERE, "libavs.so"))
 
 AVS_OK, AVS_E_INVALID, AVS_E_CAPACITY, AVS_E_HIP, AVS_E_STATE, AVS_E_NUMERIC = 0, -1, -2, -3, -4, -5
 AVS_FP64, AVS_FP32 = 0, 1

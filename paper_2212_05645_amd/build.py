@@ -16,16 +16,19 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
+def build(verbose=False, out=OUT, defines=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc, *FLAGS, SRC, "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *FLAGS, *[f"-D{d}" for d in defines], SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    args = [a for a in sys.argv[1:] if a != "-v"]
+    out = next((a.split("=", 1)[1] for a in args if a.startswith("--out=")), OUT)
+    defs = [a[2:] for a in args if a.startswith("-D")]
+    build(verbose="-v" in sys.argv, out=out, defines=defs)

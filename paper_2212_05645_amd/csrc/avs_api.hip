@@ -69,6 +69,7 @@ struct avs_ctx {
   std::vector<double> vol_host;
 
   void* vdf[2];
+  void* fv;               // interface buffer: upwind reconstruction per (face, leaf)
   size_t vdf_buf_bytes;
   int cur = 0;
 
@@ -110,9 +111,9 @@ struct avs_ctx {
 
 namespace {
 
-enum KernelId { K_PASSA, K_FACE_PARAMS, K_FACE_EQFLUX, K_MACRO, K_TARGET, K_PASSC, K_RESIDUAL, K_CRITERION,
+enum KernelId { K_PASSA, K_FACE, K_FACE_EQFLUX, K_MACRO, K_TARGET, K_PASSC, K_RESIDUAL, K_CRITERION,
                 K_FLAGS, K_REMAP_GATHER, K_REMAP_CORRECT, K_BC_TABLES, K_MOMENTS, K_INIT, K_NKERNELS };
-const char* const kKernelNames[K_NKERNELS] = {"passA", "face_params", "face_eqflux", "macro", "target", "passC",
+const char* const kKernelNames[K_NKERNELS] = {"passA", "face", "face_eqflux", "macro", "target", "passC",
                                               "residual", "criterion", "flags_plan", "remap_gather",
                                               "remap_correct", "bc_tables", "moments", "init_vdf"};
 
@@ -195,6 +196,7 @@ int numax_of(const avs_vspace* vs) {
 void carve(avs_ctx& x, Carver& c) {
   const int D = x.D, N = D + 2;
   const size_t nc = x.nc, nf = x.nf, cap = x.cap, mf = x.maxf;
+  x.geo.order = c.take<int>(nc);
   x.geo.vol = c.take<double>(nc);
   x.geo.eps2 = c.take<double>(nc);
   x.geo.dtv = c.take<double>(nc);
@@ -397,19 +399,15 @@ avs_status launch_step(avs_ctx* ctx, bool last_residual) {
   T* vout = (T*)ctx->vdf[ctx->cur ^ 1];
   {
     ProfScope ps(ctx, K_PASSA);
-    k_passA<D, T><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, vin, ctx->h, ctx->part);
+    const int nch = (L.n + CHUNK - 1) / CHUNK;
+    const int gx = (int)round_up(ctx->nc, 8);
+    k_passA<D, T><<<dim3(gx, nch), BLOCK, 0, ctx->stream>>>(ctx->geo, L, vin, ctx->h, (T*)ctx->fv, CHUNK);
     CKL();
   }
   {
-    ProfScope ps(ctx, K_FACE_PARAMS);
-    k_face_params<D><<<(ctx->nf + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(
-        ctx->geo, ctx->gas, ctx->h, ctx->part, ctx->bden, ctx->bfin, ctx->fpar, ctx->Fbar, ctx->F, ctx->bad);
-    CKL();
-  }
-  if (ctx->n_int > 0) {
-    ProfScope ps(ctx, K_FACE_EQFLUX);
-    k_face_eqflux<D><<<ctx->n_int, BLOCK, (size_t)D * nu * sizeof(double), ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->fpar,
-                                                                                        ctx->Fbar, ctx->F);
+    ProfScope ps(ctx, K_FACE);
+    k_face<D, T><<<ctx->nf, BLOCK, (size_t)D * nu * sizeof(T), ctx->stream>>>(
+        ctx->geo, L, ctx->vg, ctx->gas, ctx->h, (const T*)ctx->fv, ctx->bden, ctx->bfin, ctx->fpar, ctx->F, ctx->bad);
     CKL();
   }
   {
@@ -420,14 +418,15 @@ avs_status launch_step(avs_ctx* ctx, bool last_residual) {
   }
   {
     ProfScope ps(ctx, K_TARGET);
-    k_target<D><<<ctx->nc, BLOCK, (size_t)D * nu * sizeof(double), ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->tpar, ctx->Wn,
-                                                                                ctx->lam, ctx->bad);
+    k_target<D, T><<<ctx->nc, BLOCK, (size_t)D * nu * sizeof(T), ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->tpar, ctx->Wn,
+                                                                               ctx->lam, ctx->bad);
     CKL();
   }
   {
     ProfScope ps(ctx, K_PASSC);
-    k_passC<D, T><<<ctx->nc, BLOCK, (size_t)(MAXF + 1) * D * nu * sizeof(double), ctx->stream>>>(
-        ctx->geo, L, ctx->vg, vin, vout, ctx->fpar, ctx->tpar, ctx->lam, ctx->bcpair, ctx->h, ctx->mom, ctx->q);
+    k_passC<D, T><<<(unsigned)round_up(ctx->nc, 8), BLOCK, (size_t)(MAXF + 1) * D * nu * sizeof(T), ctx->stream>>>(
+        ctx->geo, L, ctx->vg, vin, (const T*)ctx->fv, vout, ctx->fpar, ctx->tpar, ctx->lam, ctx->bcpair, ctx->mom,
+        ctx->q);
     CKL();
   }
   if (last_residual) {
@@ -552,7 +551,7 @@ size_t avs_vdf_bytes(const avs_vspace* vs, const avs_pmesh* pm, const avs_opts* 
   if (check_args(vs, pm, op)) return 0;
   avs_ctx x;
   fill_dims(x, vs, pm, op);
-  return 2 * (size_t)x.P * x.nc * x.cap * x.esize();
+  return (2 * (size_t)x.nc + (size_t)std::max(x.nf, 1)) * x.P * x.cap * x.esize();
 }
 
 size_t avs_workspace_bytes(const avs_vspace* vs, const avs_pmesh* pm, const avs_opts* op) {
@@ -660,6 +659,30 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
     eps2[i] = pow(op->venkat_K * pow(pm->cell_vol[i], 1.0 / D), 3.0);
     dtv[i] = op->dt / pm->cell_vol[i];
   }
+  // locality order: Morton key of the centres quantised on 2^(60/D) steps per axis
+  std::vector<int> order(nc);
+  {
+    double lo_[3] = {1e300, 1e300, 1e300}, hi_[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < nc; ++i)
+      for (int d = 0; d < D; ++d) {
+        lo_[d] = std::min(lo_[d], pm->cell_ctr[i * D + d]);
+        hi_[d] = std::max(hi_[d], pm->cell_ctr[i * D + d]);
+      }
+    const int bits = 60 / D;
+    std::vector<std::pair<uint64_t, int>> key(nc);
+    for (int64_t i = 0; i < nc; ++i) {
+      uint64_t q[3] = {0, 0, 0}, kk = 0;
+      for (int d = 0; d < D; ++d) {
+        const double span = hi_[d] > lo_[d] ? hi_[d] - lo_[d] : 1.0;
+        q[d] = (uint64_t)std::min((double)((1ull << bits) - 1), (pm->cell_ctr[i * D + d] - lo_[d]) / span * (double)(1ull << bits));
+      }
+      for (int b = 0; b < bits; ++b)
+        for (int d = 0; d < D; ++d) kk |= ((q[d] >> b) & 1ull) << (D * b + d);
+      key[i] = {kk, (int)i};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t i = 0; i < nc; ++i) order[i] = key[i].second;
+  }
   std::vector<double> W0(nc * N);
   for (int64_t i = 0; i < nc; ++i) {
     const double* pr = prim0_host + i * N;
@@ -688,9 +711,10 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   x.Kv = op->venkat_K;
   x.stream = (hipStream_t)hip_stream;
   x.vol_host.assign(pm->cell_vol, pm->cell_vol + nc);
-  x.vdf_buf_bytes = avs_vdf_bytes(vs, pm, op) / 2;
+  x.vdf_buf_bytes = (size_t)x.P * x.nc * x.cap * x.esize();
   x.vdf[0] = vdf_dev;
   x.vdf[1] = (char*)vdf_dev + x.vdf_buf_bytes;
+  x.fv = (char*)vdf_dev + 2 * x.vdf_buf_bytes;
   Carver cv{(char*)workspace_dev};
   carve(x, cv);
   const int P = x.P;
@@ -713,6 +737,7 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
       return fail(AVS_E_HIP, "%s: %s", #e, hipGetErrorString(er_)); \
     }                                           \
   } while (0)
+  CKI(H2D((void*)x.geo.order, order.data(), sizeof(int) * nc));
   CKI(H2D((void*)x.geo.vol, pm->cell_vol, sizeof(double) * nc));
   CKI(H2D((void*)x.geo.eps2, eps2.data(), sizeof(double) * nc));
   CKI(H2D((void*)x.geo.dtv, dtv.data(), sizeof(double) * nc));

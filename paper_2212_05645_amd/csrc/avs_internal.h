@@ -15,6 +15,10 @@ constexpr int NM2 = 9;           // raw face moments, 2-D: m0, m1[2], m2[3], e, 
 constexpr int NM3 = 14;          // raw face moments, 3-D: m0, m1[3], m2[6], e, e1[3]
 constexpr int NPAR = 16;         // doubles per equilibrium parameter record
 constexpr int CRIT_CELLS = 256;  // cells per criterion partial
+#ifndef AVS_CHUNK
+#define AVS_CHUNK 2048
+#endif
+constexpr int CHUNK = AVS_CHUNK;  // leaves per workgroup of pass A
 
 // Equilibrium parameter record (face or cell), NPAR doubles:
 //   [0] coef = rho (2 pi R T)^(-D/2)   [1..3] U   [4] RT   [5] 1/(2RT)   [6] 1/RT
@@ -27,6 +31,7 @@ enum { P_COEF = 0, P_U = 1, P_RT = 4, P_I2RT = 5, P_IRT = 6, P_Q = 7, P_SHK = 10
 struct Geo {
   int D, P, nc, nf, maxf, nbc;
   int n_int, n_bnd;
+  const int* order;      // [nc] cells along a space-filling curve of their centres
   const double* vol;     // [nc]
   const double* eps2;    // [nc]  (K V^(1/D))^3
   const double* dtv;     // [nc]  dt / V

@@ -10,7 +10,19 @@
 // face/cell instead of one exp per (cell, leaf).
 #include "avs_internal.h"
 
+// Minimum waves per SIMD requested for the two streaming passes, per form
+// (FP64 kernels keep their registers, FP32 kernels ask for occupancy).
+#ifndef AVS_WAVES_F64
+#define AVS_WAVES_F64 1
+#endif
+#ifndef AVS_WAVES_F32
+#define AVS_WAVES_F32 4
+#endif
+
 namespace avs {
+
+template <int D, typename T>
+constexpr int waves_hint() { return (D == 3 || sizeof(T) == 8) ? AVS_WAVES_F64 : AVS_WAVES_F32; }
 
 template <typename T>
 __device__ __forceinline__ double ld_(const T* p) { return (double)(*p); }
@@ -22,6 +34,17 @@ struct Cfg {
   static constexpr int NM = (D == 2) ? NM2 : NM3;
   static constexpr int NS = (D + 2) * (D + 3) / 2;   // symmetric Gram entries
 };
+
+// Workgroups are dealt to the 8 XCDs round-robin by linear id.  Block x of a
+// grid of round_up(nc, 8) blocks takes position (x % 8) * ceil(nc/8) + x / 8
+// of the locality order of the cells (a space-filling curve through the cell
+// centres), so each XCD walks a compact patch of the mesh and neighbouring
+// cells share its L2.  Returns -1 for the padding blocks.
+__device__ __forceinline__ int xcd_cell(const Geo& g, int x) {
+  const int per = (g.nc + 7) >> 3;
+  const int i = (x & 7) * per + (x >> 3);
+  return i < g.nc ? g.order[i] : -1;
+}
 
 // ---------------------------------------------------------------- reductions
 template <int N>
@@ -82,6 +105,49 @@ __device__ __forceinline__ void shakhov(const double* par, double g, const doubl
     H = rtg + sk * (c2 * irt - D) * rtg;
   } else {
     H = 0.0;
+  }
+}
+
+// Compute-type variants used by the sweep kernels: R = double in the FP64
+// form, float in the FP32 form (records stay FP64 in memory and are
+// converted once per workgroup).
+template <int D, typename R>
+__device__ __forceinline__ void build_tab_r(R* tab, const double* par, const VGrid& vg) {
+  const double i2rt = par[P_I2RT];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double x0 = vg.x0[d], hh = vg.hh[d], U = par[P_U + d];
+    for (int u = threadIdx.x; u < vg.numax; u += BLOCK) {
+      const double c = (x0 + u * hh) - U;
+      tab[d * vg.numax + u] = (R)exp(-(c * c) * i2rt);
+    }
+  }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ R maxw_r(const R* par, const R* tab, int numax, const int (&u)[D]) {
+  R g = par[P_COEF];
+#pragma unroll
+  for (int d = 0; d < D; ++d) g *= tab[d * numax + u[d]];
+  return g;
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void shakhov_r(const R* par, R g, const R (&xi)[D], R& G, R& H) {
+  R c2 = 0, cq = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const R c = xi[d] - par[P_U + d];
+    c2 += c * c;
+    cq += c * par[P_Q + d];
+  }
+  const R sk = par[P_SHK] * cq, irt = par[P_IRT];
+  G = g + sk * (c2 * irt - (R)(D + 2)) * g;
+  if (D == 2) {
+    const R rtg = par[P_RT] * g;
+    H = rtg + sk * (c2 * irt - (R)D) * rtg;
+  } else {
+    H = 0;
   }
 }
 
@@ -356,148 +422,172 @@ __global__ __launch_bounds__(BLOCK) void k_cell_moments(Geo g, Leaves L, const T
 }
 
 // ------------------------------------------------- limited gradient (S2-S3)
-// Least-squares gradient and Venkatakrishnan limiter of cell c at leaf k.
+// The stencil of one cell, loaded once per workgroup: row pointers of the
+// cell and of its neighbours (the cell's own row for a boundary face, whose
+// difference is then zero), least-squares coefficients and face offsets.
 template <int D, typename T>
-__device__ __forceinline__ void lim_grad(const Geo& g, const T* __restrict__ vdf, size_t cs, int ld, int c, int k,
-                                         double (&phi)[Cfg<D>::P], double (&lg)[Cfg<D>::P][D]) {
+struct Stencil {
+  static constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+  int ns;
+  unsigned nbmask;            // bit s: face s has an interior neighbour
+  const T* own[P];
+  const T* nb[MAXF][P];
+  T cf[MAXF][D];
+  T dd[MAXF][D];
+  T eps2;
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void load_stencil(const Geo& g, const T* __restrict__ vdf, size_t cs, int ld, int c,
+                                             Stencil<D, T>& st) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
-  const int ns = g.nslot[c];
-  double pmax[P], pmin[P], grad[P][D];
+  st.ns = g.nslot[c];
+  st.nbmask = 0;
+  st.eps2 = (T)g.eps2[c];
+#pragma unroll
+  for (int p = 0; p < P; ++p) st.own[p] = vdf + p * cs + (size_t)c * ld;
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) {
+    const int j = s < st.ns ? g.s_nbr[c * MAXF + s] : -1;
+    if (j >= 0) st.nbmask |= 1u << s;
+#pragma unroll
+    for (int p = 0; p < P; ++p) st.nb[s][p] = j >= 0 ? vdf + p * cs + (size_t)j * ld : st.own[p];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      st.cf[s][d] = j >= 0 ? (T)g.s_lsq[(size_t)(c * MAXF + s) * D + d] : (T)0;
+      st.dd[s][d] = s < st.ns ? (T)g.s_d[(size_t)(c * MAXF + s) * D + d] : (T)0;
+    }
+  }
+}
+
+// Least-squares gradient and Venkatakrishnan limiter at leaf k, in T.
+template <int D, typename T>
+__device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi)[Cfg<D>::P],
+                                         T (&lg)[Cfg<D>::P][D]) {
+  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+  const int ns = st.ns;
+  T pmax[P], pmin[P], grad[P][D];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    phi[p] = ld_(vdf + p * cs + (size_t)c * ld + k);
+    phi[p] = st.own[p][k];
     pmax[p] = phi[p];
     pmin[p] = phi[p];
 #pragma unroll
-    for (int d = 0; d < D; ++d) grad[p][d] = 0.0;
+    for (int d = 0; d < D; ++d) grad[p][d] = 0;
   }
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
-    if (s < ns) {
-      const int j = g.s_nbr[c * MAXF + s];
-      if (j >= 0) {
-        const double* cf = g.s_lsq + (size_t)(c * MAXF + s) * D;
+    if (st.nbmask & (1u << s)) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-          const double v = ld_(vdf + p * cs + (size_t)j * ld + k);
-          const double dv = v - phi[p];
+      for (int p = 0; p < P; ++p) {
+        const T v = st.nb[s][p][k];
+        const T dv = v - phi[p];
 #pragma unroll
-          for (int d = 0; d < D; ++d) grad[p][d] += dv * cf[d];
-          pmax[p] = fmax(pmax[p], v);
-          pmin[p] = fmin(pmin[p], v);
-        }
+        for (int d = 0; d < D; ++d) grad[p][d] += dv * st.cf[s][d];
+        pmax[p] = v > pmax[p] ? v : pmax[p];
+        pmin[p] = v < pmin[p] ? v : pmin[p];
       }
     }
   }
-  const double eps2 = g.eps2[c];
+  // Venkatakrishnan: psi_f = N/Dn with, for a = |D2| and b = |D1| (same sign),
+  //   N = b^2 + eps^2 + 2ab,  Dn = b^2 + 2a^2 + ab + eps^2   (psi = 1 if D2 = 0),
+  // which is the paper's expression divided through by D2.  a, b and eps are
+  // scaled by the largest of them (one division), the minimum over faces is
+  // kept as a fraction by cross-multiplication, and one division ends it.
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    double lim = ns > 0 ? INFINITY : 1.0;
+    T d2s[MAXF];
+    const T up0 = pmax[p] - phi[p], dn0 = phi[p] - pmin[p];
+    T m = up0 > dn0 ? up0 : dn0;
 #pragma unroll
     for (int s = 0; s < MAXF; ++s) {
-      if (s < ns) {
-        const double* dd = g.s_d + (size_t)(c * MAXF + s) * D;
-        double d2 = 0.0;
+      T d2 = 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) d2 += grad[p][d] * dd[d];
-        double psi = 1.0;
-        if (d2 != 0.0) {
-          // Venkatakrishnan psi, divided through by D2 (and by D1 when eps = 0)
-          // so that VDF values near the bottom of the FP64 range do not underflow.
-          const double d1 = d2 > 0.0 ? pmax[p] - phi[p] : pmin[p] - phi[p];
-          if (eps2 > 0.0) {
-            psi = (d1 * d1 + eps2 + 2.0 * d1 * d2) / (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2);
-          } else if (d1 == 0.0) {
-            psi = 0.0;
-          } else {
-            const double t = d2 / d1;
-            psi = (1.0 + 2.0 * t) / (1.0 + t + 2.0 * t * t);
+      for (int d = 0; d < D; ++d) d2 += grad[p][d] * st.dd[s][d];
+      d2s[s] = d2;
+      const T a = fabs(d2);
+      m = a > m ? a : m;
+    }
+    T lim = 1;
+    // below the smallest normal number the stencil differences carry no
+    // information (and 1/m would overflow): leave the slope unlimited
+    if (ns > 0 && m > (sizeof(T) == 8 ? (T)1e-300 : (T)1e-36)) {
+      const T inv = (T)1 / m;
+      // eps^2 beyond this makes psi = 1 to working precision; the clamp keeps
+      // the cross products below the overflow threshold of T
+      const T e2 = fmin(st.eps2 * inv * inv, sizeof(T) == 8 ? (T)1e30 : (T)1e15);
+      const T up = up0 * inv, dn = dn0 * inv;
+      T Nm = 1, Dm = 0;                                // running minimum, starts at +inf
+#pragma unroll
+      for (int s = 0; s < MAXF; ++s) {
+        if (s < ns) {
+          T Nn = 1, Dd = 1;                            // psi = 1 where D2 = 0
+          if (d2s[s] != (T)0) {
+            const T a = fabs(d2s[s]) * inv;
+            const T b = d2s[s] > (T)0 ? up : dn;
+            Nn = b * b + e2 + (T)2 * a * b;
+            Dd = b * b + (T)2 * a * a + a * b + e2;
           }
+          if (Nn * Dm < Nm * Dd) { Nm = Nn; Dm = Dd; }
         }
-        lim = fmin(lim, psi);
       }
+      lim = Nm / Dm;
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) lg[p][d] = lim * grad[p][d];
   }
 }
 
-// ------------------------------------------------------- pass A (S4, S5 part)
-// Per cell, per face of the cell: raw moments of the upwind reconstruction
-// over the leaves for which this cell is upwind.  Summed with the other
-// side's partial, they give the interface moments (Eq. w_interface).
+// ------------------------------------------------------------ pass A (S4)
+// Per cell and leaf: limited gradient, and the upwind reconstruction at
+// x_f - xi h for every face where this cell is upwind, stored to the
+// interface buffer (exactly one writer per face and leaf).  Grid (cells,
+// leaf chunks) with cells fastest, so that a cell and its neighbours read
+// the same chunk of their rows at about the same time.
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void k_passA(Geo g, Leaves L, const T* __restrict__ vdf, double h,
-                                                  double* __restrict__ part) {
-  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF, NM = Cfg<D>::NM;
-  __shared__ double red[4 * NM];
-  const int i = blockIdx.x;
-  const int ns = g.nslot[i];
+__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passA(Geo g, Leaves L, const T* __restrict__ vdf,
+                                                                      double h, T* __restrict__ fv, int chunk) {
+  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+  const int i = xcd_cell(g, blockIdx.x);
+  if (i < 0) return;
+  const int k0 = blockIdx.y * chunk, k1 = min(L.n, k0 + chunk);
   const size_t cs = (size_t)g.nc * L.ld;
-  double nrm[MAXF][D], dd[MAXF][D], sig[MAXF];
+  const size_t fs = (size_t)g.nf * L.ld;   // component stride of the interface buffer
+  Stencil<D, T> st;
+  load_stencil<D, T>(g, vdf, cs, L.ld, i, st);
+  double nrm[MAXF][D], sig[MAXF];
+  T* row[MAXF][P];
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
-    const int f = s < ns ? g.s_face[i * MAXF + s] : 0;
-    sig[s] = s < ns ? g.s_sig[i * MAXF + s] : 0.0;
+    const int f = s < st.ns ? g.s_face[i * MAXF + s] : 0;
+    sig[s] = s < st.ns ? g.s_sig[i * MAXF + s] : 0.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      nrm[s][d] = g.f_nrm[(size_t)f * D + d];
-      dd[s][d] = g.s_d[(size_t)(i * MAXF + s) * D + d];
-    }
+    for (int d = 0; d < D; ++d) nrm[s][d] = g.f_nrm[(size_t)f * D + d];
+#pragma unroll
+    for (int p = 0; p < P; ++p) row[s][p] = fv + p * fs + (size_t)f * L.ld;
   }
-  double acc[MAXF][NM];
+  const T th = (T)h;
+  for (int k = k0 + threadIdx.x; k < k1; k += BLOCK) {
+    double xi[D];
 #pragma unroll
-  for (int s = 0; s < MAXF; ++s) {
-#pragma unroll
-    for (int m = 0; m < NM; ++m) acc[s][m] = 0.0;
-  }
-  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[D], A;
-    int u[D];
-    leaf_load<D>(L, k, xi, A, u);
-    double phi[P], lg[P][D];
-    lim_grad<D, T>(g, vdf, cs, L.ld, i, k, phi, lg);
-    double xi2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+    for (int d = 0; d < D; ++d) xi[d] = L.xi[d * L.cap + k];
+    T phi[P], lg[P][D];
+    lim_grad<D, T>(st, k, phi, lg);
 #pragma unroll
     for (int s = 0; s < MAXF; ++s) {
-      if (s < ns) {
+      if (s < st.ns) {
         const double sn = normal_speed<D>(xi, nrm[s]);
         const bool up = sig[s] > 0.0 ? (sn >= 0.0) : (sn < 0.0);
         if (up) {
-          double pb[P];
 #pragma unroll
           for (int p = 0; p < P; ++p) {
-            double v = 0.0;
+            T v = 0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) v += lg[p][d] * (dd[s][d] - xi[d] * h);
-            pb[p] = phi[p] + v;
+            for (int d = 0; d < D; ++d) v += lg[p][d] * (st.dd[s][d] - (T)xi[d] * th);
+            row[s][p][k] = phi[p] + v;
           }
-          const double aG = A * pb[0];
-          int m = 0;
-          acc[s][m++] += aG;
-#pragma unroll
-          for (int d = 0; d < D; ++d) acc[s][m++] += aG * xi[d];
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-#pragma unroll
-            for (int e = d; e < D; ++e) acc[s][m++] += aG * xi[d] * xi[e];
-          }
-          const double eh = 0.5 * A * (xi2 * pb[0] + (P == 2 ? pb[P - 1] : 0.0));
-          acc[s][m++] += eh;
-#pragma unroll
-          for (int d = 0; d < D; ++d) acc[s][m++] += eh * xi[d];
         }
       }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < MAXF; ++s) {
-    block_sum<NM>(acc[s], red);
-    if (threadIdx.x == 0 && s < ns) {
-#pragma unroll
-      for (int m = 0; m < NM; ++m) part[((size_t)i * MAXF + s) * NM + m] = acc[s][m];
     }
   }
 }
@@ -522,102 +612,139 @@ __device__ __forceinline__ void raw_flux(const double* m, const double* n, doubl
   F[D + 1] = v;
 }
 
-// ---------------------------------------------------- face parameters (S5)
-// Interior faces: W_f, q_f, tau_f, Shakhov record and blend weights, and
-// the flux of the reconstructed VDF.  Boundary faces: final flux (outgoing
-// reconstruction + incoming wall/far-field Maxwellian) and rho_w.
-template <int D>
-__global__ void k_face_params(Geo g, GasP gas, double h, const double* __restrict__ part,
-                              const double* __restrict__ bden, const double* __restrict__ bfin,
-                              double* __restrict__ fpar, double* __restrict__ Fbar, double* __restrict__ F,
-                              int* __restrict__ bad) {
-  constexpr int MAXF = Cfg<D>::MAXF, NM = Cfg<D>::NM, N = D + 2;
-  const int f = blockIdx.x * BLOCK + threadIdx.x;
-  if (f >= g.nf) return;
-  const int L = g.f_L[f], R = g.f_R[f];
-  const double* n = g.f_nrm + (size_t)f * D;
-  double m[NM];
-  const double* pl = part + ((size_t)L * MAXF + g.f_sL[f]) * NM;
-  if (R >= 0) {
-    const double* pr = part + ((size_t)R * MAXF + g.f_sR[f]) * NM;
-    for (int t = 0; t < NM; ++t) m[t] = pl[t] + pr[t];
-    const double rho = m[0];
-    double U[D], ke = 0.0;
-    for (int d = 0; d < D; ++d) { U[d] = m[1 + d] / rho; ke += U[d] * U[d]; }
-    const int ie = 1 + D + D * (D + 1) / 2;
-    const double E = m[ie];
-    const double T = (E - 0.5 * rho * ke) / (1.5 * rho * gas.R);
-    if (!(rho > 0.0 && T > 0.0)) atomicMin(bad, g.nc + f);
-    // q about U from raw moments: e1_d - U_d E - sum_e U_e (m2_de - rho U_d U_e) + |U|^2/2 (m1_d - U_d rho)
-    int idx[3][3];
-    int t = 1 + D;
-    for (int d = 0; d < D; ++d)
-      for (int e = d; e < D; ++e) { idx[d][e] = t; idx[e][d] = t; ++t; }
-    double q[D];
-    for (int d = 0; d < D; ++d) {
-      double v = m[ie + 1 + d] - U[d] * E;
-      for (int e = 0; e < D; ++e) v -= U[e] * (m[idx[d][e]] - rho * U[d] * U[e]);
-      v += 0.5 * ke * (m[1 + d] - U[d] * rho);
-      q[d] = v;
-    }
-    const double tf = tau_of(rho, T, gas);
-    const double qs = tf / (tf + h * gas.Pr);
-    for (int d = 0; d < D; ++d) q[d] *= qs;
-    double* par = fpar + (size_t)f * NPAR;
-    eq_record<D>(par, rho, U, T, q, gas);
-    par[P_A] = tf / (tf + h);
-    par[P_B] = h / (tf + h);
-    raw_flux<D>(m, n, Fbar + (size_t)f * N);
-  } else {
-    const int bc = -1 - R;
-    double Fo[N];
-    raw_flux<D>(pl, n, Fo);
-    const double* fin = bfin + (size_t)f * N;
-    double scale = 1.0;
-    if (g.bc_kind[bc] == 0) {
-      scale = Fo[0] / bden[f];
-      fpar[(size_t)f * NPAR] = scale;
-    }
-    for (int t = 0; t < N; ++t) F[(size_t)f * N + t] = Fo[t] + scale * fin[t];
-  }
-}
-
-// ------------------------------------ interface equilibrium flux (S6, S8)
-// F_f = a sum A s psi phibar + b sum A s psi g_f for interior faces.
-template <int D>
-__global__ __launch_bounds__(BLOCK) void k_face_eqflux(Geo g, Leaves L, VGrid vg, const double* __restrict__ fpar,
-                                                        const double* __restrict__ Fbar, double* __restrict__ F) {
-  constexpr int N = D + 2;
-  extern __shared__ double lds[];
-  double* tab = lds;
-  __shared__ double red[4 * N];
-  const int f = g.f_int[blockIdx.x];
-  const double* par = fpar + (size_t)f * NPAR;
-  build_tab<D>(tab, par, vg);
+// ------------------------------------------------------ interface (S5-S8)
+// One workgroup per face streams the face's row of the interface buffer:
+// raw moments of the reconstructed VDF (Eq. w_interface; on a boundary face
+// over the outgoing leaves only).  Interior face: interface state, tau,
+// heat flux relaxed over h at rate Pr/tau, Shakhov record and blend weights,
+// then the flux F = a sum A s psi phibar + b sum A s psi g_f with g_f
+// evaluated in R from the record.  Boundary face: outgoing flux plus the
+// incoming wall (zero net mass flux, rho_w) or far-field Maxwellian flux.
+template <int D, typename R>
+__global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, VGrid vg, GasP gas, double h, const R* __restrict__ fv,
+                                               const double* __restrict__ bden, const double* __restrict__ bfin,
+                                               double* __restrict__ fpar, double* __restrict__ F,
+                                               int* __restrict__ bad) {
+  constexpr int P = Cfg<D>::P, NM = Cfg<D>::NM, N = D + 2;
+  extern __shared__ double lds_d[];
+  R* tab = reinterpret_cast<R*>(lds_d);
+  __shared__ double red[4 * NM];
+  __shared__ double spar[NPAR];
+  __shared__ R rp[NPAR];
+  __shared__ double sF[N];
+  __shared__ int interior_ok;
+  const int f = blockIdx.x;
+  const int Rc = g.f_R[f];
+  const size_t fs = (size_t)g.nf * L.ld;
   double n[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
-  __syncthreads();
-  double acc[N];
+  double m[NM];
 #pragma unroll
-  for (int m = 0; m < N; ++m) acc[m] = 0.0;
+  for (int t = 0; t < NM; ++t) m[t] = 0.0;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
     double xi[D], A;
     int u[D];
     leaf_load<D>(L, k, xi, A, u);
-    const double gv = maxw<D>(par, tab, vg.numax, u);
-    double G, H;
-    shakhov<D>(par, gv, xi, G, H);
+    if (Rc < 0 && normal_speed<D>(xi, n) < 0.0) continue;     // incoming leaf of a boundary face
+    const double G = (double)fv[(size_t)f * L.ld + k];
+    const double H = P == 2 ? (double)fv[fs + (size_t)f * L.ld + k] : 0.0;
+    double xi2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+    const double aG = A * G;
+    int t = 0;
+    m[t++] += aG;
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[t++] += aG * xi[d];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+      for (int e = d; e < D; ++e) m[t++] += aG * xi[d] * xi[e];
+    }
+    const double eh = 0.5 * A * (xi2 * G + H);
+    m[t++] += eh;
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[t++] += eh * xi[d];
+  }
+  block_sum<NM>(m, red);
+  if (threadIdx.x == 0) {
+    interior_ok = 0;
+    if (Rc >= 0) {
+      const double rho = m[0];
+      double U[D], ke = 0.0;
+      for (int d = 0; d < D; ++d) { U[d] = m[1 + d] / rho; ke += U[d] * U[d]; }
+      const int ie = 1 + D + D * (D + 1) / 2;
+      const double E = m[ie];
+      const double T = (E - 0.5 * rho * ke) / (1.5 * rho * gas.R);
+      if (!(rho > 0.0 && T > 0.0)) {
+        atomicMin(bad, g.nc + f);
+      } else {
+        // q about U from raw moments: e1_d - U_d E - sum_e U_e (m2_de - rho U_d U_e) + |U|^2/2 (m1_d - U_d rho)
+        int idx[3][3];
+        int t = 1 + D;
+        for (int d = 0; d < D; ++d)
+          for (int e = d; e < D; ++e) { idx[d][e] = t; idx[e][d] = t; ++t; }
+        double q[D];
+        for (int d = 0; d < D; ++d) {
+          double v = m[ie + 1 + d] - U[d] * E;
+          for (int e = 0; e < D; ++e) v -= U[e] * (m[idx[d][e]] - rho * U[d] * U[e]);
+          v += 0.5 * ke * (m[1 + d] - U[d] * rho);
+          q[d] = v;
+        }
+        const double tf = tau_of(rho, T, gas);
+        const double qs = tf / (tf + h * gas.Pr);
+        for (int d = 0; d < D; ++d) q[d] *= qs;
+        eq_record<D>(spar, rho, U, T, q, gas);
+        spar[P_A] = tf / (tf + h);
+        spar[P_B] = h / (tf + h);
+        raw_flux<D>(m, n, sF);
+        interior_ok = 1;
+      }
+    } else {
+      const int bc = -1 - Rc;
+      double Fo[N];
+      raw_flux<D>(m, n, Fo);
+      const double* fin = bfin + (size_t)f * N;
+      double scale = 1.0;
+      if (g.bc_kind[bc] == 0) {
+        scale = Fo[0] / bden[f];
+        fpar[(size_t)f * NPAR] = scale;
+      }
+      for (int t = 0; t < N; ++t) F[(size_t)f * N + t] = Fo[t] + scale * fin[t];
+    }
+  }
+  __syncthreads();
+  if (!interior_ok) return;
+  if (threadIdx.x < NPAR) {
+    fpar[(size_t)f * NPAR + threadIdx.x] = spar[threadIdx.x];
+    rp[threadIdx.x] = (R)spar[threadIdx.x];
+  }
+  build_tab_r<D, R>(tab, spar, vg);
+  __syncthreads();
+  double acc[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) acc[t] = 0.0;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    R xr[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xr[d] = (R)xi[d];
+    const R gv = maxw_r<D, R>(rp, tab, vg.numax, u);
+    R G, H;
+    shakhov_r<D, R>(rp, gv, xr, G, H);
     const double sn = normal_speed<D>(xi, n);
     double xi2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
-    mom_acc<D>(acc, A * sn, xi, xi2, G, H);
+    mom_acc<D>(acc, A * sn, xi, xi2, (double)G, (double)H);
   }
   block_sum<N>(acc, red);
   if (threadIdx.x == 0) {
-    const double a = par[P_A], b = par[P_B];
-    for (int m = 0; m < N; ++m) F[(size_t)f * N + m] = a * Fbar[(size_t)f * N + m] + b * acc[m];
+    const double a = spar[P_A], b = spar[P_B];
+    for (int t = 0; t < N; ++t) F[(size_t)f * N + t] = a * sF[t] + b * acc[t];
   }
 }
 
@@ -653,18 +780,22 @@ __global__ void k_macro(Geo g, GasP gas, double dt, const double* __restrict__ F
 }
 
 // --------------------------------------- conservative relaxation target (S9)
-// lambda such that closure(Shakhov(W^{n+1}, q^n)) has moments W^{n+1}.
-template <int D>
+// lambda such that closure(Shakhov(W^{n+1}, q^n)) has moments W^{n+1}; the
+// Shakhov values are evaluated in R, the moment and Gram sums in FP64 and
+// the (D+2)x(D+2) solve in FP64.
+template <int D, typename R>
 __global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, const double* __restrict__ tpar,
                                                    const double* __restrict__ Wn, double* __restrict__ lam,
                                                    int* __restrict__ bad) {
   constexpr int N = D + 2, NS = Cfg<D>::NS;
-  extern __shared__ double lds[];
-  double* tab = lds;
+  extern __shared__ double lds_d[];
+  R* tab = reinterpret_cast<R*>(lds_d);
   __shared__ double red[4 * (N + NS)];
+  __shared__ R rp[NPAR];
   const int i = blockIdx.x;
   const double* par = tpar + (size_t)i * NPAR;
-  build_tab<D>(tab, par, vg);
+  if (threadIdx.x < NPAR) rp[threadIdx.x] = (R)par[threadIdx.x];
+  build_tab_r<D, R>(tab, par, vg);
   __syncthreads();
   double acc[N + NS];
 #pragma unroll
@@ -673,13 +804,17 @@ __global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, con
     double xi[D], A;
     int u[D];
     leaf_load<D>(L, k, xi, A, u);
-    const double gv = maxw<D>(par, tab, vg.numax, u);
-    double G, H;
-    shakhov<D>(par, gv, xi, G, H);
+    R xr[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xr[d] = (R)xi[d];
+    const R gr = maxw_r<D, R>(rp, tab, vg.numax, u);
+    R Gr, Hr;
+    shakhov_r<D, R>(rp, gr, xr, Gr, Hr);
+    const double gv = gr;
     double c[D], c2 = 0.0, xi2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) { c[d] = xi[d] - par[P_U + d]; c2 += c[d] * c[d]; xi2 += xi[d] * xi[d]; }
-    mom_acc<D>(acc, A, xi, xi2, G, H);
+    mom_acc<D>(acc, A, xi, xi2, (double)Gr, (double)Hr);
     gram_acc<D>(acc + N, A * gv, c, c2);
   }
   block_sum<N + NS>(acc, red);
@@ -693,25 +828,33 @@ __global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, con
 }
 
 // -------------------------------------------------- pass C (S6, S7, S10)
-// Interface VDFs of every face of the cell (own reconstruction for outgoing
-// leaves, the neighbour's for incoming ones), flux divergence, relaxation
-// towards the closed Shakhov target, store phi^{n+1}, and the moments and
-// heat flux of phi^{n+1} for the next step.
+// Interface VDFs of every face of the cell (upwind reconstruction from the
+// interface buffer, blended with the interface Shakhov equilibrium; wall or
+// far-field Maxwellian on incoming leaves of boundary faces), flux
+// divergence, relaxation towards the closed Shakhov target, store
+// phi^{n+1}, and the moments and heat flux of phi^{n+1} for the next step.
+// Arithmetic in T, sums in FP64; the upwind sign in FP64 in both forms.
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void k_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
-                                                  T* __restrict__ vout, const double* __restrict__ fpar,
-                                                  const double* __restrict__ tpar, const double* __restrict__ lam,
-                                                  const double* __restrict__ bcpair, double h,
-                                                  double* __restrict__ mom, double* __restrict__ qout) {
+__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
+                                                     const T* __restrict__ fv, T* __restrict__ vout,
+                                                     const double* __restrict__ fpar, const double* __restrict__ tpar,
+                                                     const double* __restrict__ lam, const double* __restrict__ bcpair,
+                                                     double* __restrict__ mom, double* __restrict__ qout) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF, N = D + 2;
-  extern __shared__ double lds[];
+  extern __shared__ double lds_d[];
+  T* lds = reinterpret_cast<T*>(lds_d);
   __shared__ double red[4 * (N + D)];
-  __shared__ double spar[(MAXF + 1) * NPAR];
-  __shared__ double slam[N];
-  const int i = blockIdx.x;
+  __shared__ T spar[(MAXF + 1) * NPAR];
+  __shared__ double snrm[MAXF][D];
+  __shared__ int sface[MAXF], snbr[MAXF], sbc[MAXF];
+  __shared__ T ssa[MAXF];
+  __shared__ T slam[N];
+  const int i = xcd_cell(g, blockIdx.x);
+  if (i < 0) return;
   const int ns = g.nslot[i];
   const int nu = vg.numax;
   const size_t cs = (size_t)g.nc * L.ld;
+  const size_t fs = (size_t)g.nf * L.ld;
   for (int t = threadIdx.x; t < (MAXF + 1) * NPAR; t += BLOCK) {
     const int s = t / NPAR, m = t - s * NPAR;
     double v = 0.0;
@@ -720,18 +863,28 @@ __global__ __launch_bounds__(BLOCK) void k_passC(Geo g, Leaves L, VGrid vg, cons
     } else {
       v = tpar[(size_t)i * NPAR + m];
     }
-    spar[t] = v;
+    spar[t] = (T)v;
   }
-  if (threadIdx.x < N) slam[threadIdx.x] = lam[(size_t)i * N + threadIdx.x];
+  if (threadIdx.x < MAXF) {
+    const int s = threadIdx.x;
+    const int f = s < ns ? g.s_face[i * MAXF + s] : 0;
+    sface[s] = f;
+    snbr[s] = s < ns ? g.s_nbr[i * MAXF + s] : -1;
+    sbc[s] = (s < ns && g.f_R[f] < 0) ? -1 - g.f_R[f] : 0;
+    ssa[s] = s < ns ? (T)g.s_sigA[i * MAXF + s] : (T)0;
+    for (int d = 0; d < D; ++d) snrm[s][d] = g.f_nrm[(size_t)f * D + d];
+  }
+  if (threadIdx.x < N) slam[threadIdx.x] = (T)lam[(size_t)i * N + threadIdx.x];
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
-    if (s < ns && g.s_nbr[i * MAXF + s] >= 0) build_tab<D>(lds + s * D * nu, spar + s * NPAR, vg);
+    if (s < ns && snbr[s] >= 0) build_tab_r<D, T>(lds + s * D * nu, fpar + (size_t)sface[s] * NPAR, vg);
   }
-  build_tab<D>(lds + MAXF * D * nu, spar + MAXF * NPAR, vg);
+  build_tab_r<D, T>(lds + MAXF * D * nu, tpar + (size_t)i * NPAR, vg);
   __syncthreads();
-  const double* tp = spar + MAXF * NPAR;
-  const double dtt = tp[P_A], dtv = g.dtv[i];
+  const T* tp = spar + MAXF * NPAR;
+  const T dtt = tp[P_A], dtv = (T)g.dtv[i];
+  const T inv = (T)1 / ((T)1 + dtt);
   double acc[N + D];
 #pragma unroll
   for (int m = 0; m < N + D; ++m) acc[m] = 0.0;
@@ -739,90 +892,76 @@ __global__ __launch_bounds__(BLOCK) void k_passC(Geo g, Leaves L, VGrid vg, cons
     double xi[D], A;
     int u[D];
     leaf_load<D>(L, k, xi, A, u);
-    double phi[P], lg[P][D];
-    lim_grad<D, T>(g, vin, cs, L.ld, i, k, phi, lg);
-    double div[P];
+    T xr[D];
 #pragma unroll
-    for (int p = 0; p < P; ++p) div[p] = 0.0;
+    for (int d = 0; d < D; ++d) xr[d] = (T)xi[d];
+    T phi[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) phi[p] = vin[p * cs + (size_t)i * L.ld + k];
+    T div[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) div[p] = 0;
 #pragma unroll
     for (int s = 0; s < MAXF; ++s) {
       if (s < ns) {
-        const int f = g.s_face[i * MAXF + s];
-        const int j = g.s_nbr[i * MAXF + s];
-        const double sg = g.s_sig[i * MAXF + s];
-        const double sn = normal_speed<D>(xi, g.f_nrm + (size_t)f * D);
-        const bool up = sg > 0.0 ? (sn >= 0.0) : (sn < 0.0);
-        double pf[P];
-        if (up) {
-          const double* dd = g.s_d + (size_t)(i * MAXF + s) * D;
+        const int f = sface[s];
+        const double sn = normal_speed<D>(xi, snrm[s]);
+        T pf[P];
+        if (snbr[s] >= 0 || sn >= 0.0) {
+          // upwind reconstruction stored by pass A (outgoing side of a boundary face)
 #pragma unroll
-          for (int p = 0; p < P; ++p) {
-            double v = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) v += lg[p][d] * (dd[d] - xi[d] * h);
-            pf[p] = phi[p] + v;
-          }
-        } else if (j >= 0) {
-          double pj[P], lj[P][D];
-          lim_grad<D, T>(g, vin, cs, L.ld, j, k, pj, lj);
-          const int sj = sg > 0.0 ? g.f_sR[f] : g.f_sL[f];
-          const double* dd = g.s_d + (size_t)(j * MAXF + sj) * D;
-#pragma unroll
-          for (int p = 0; p < P; ++p) {
-            double v = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) v += lj[p][d] * (dd[d] - xi[d] * h);
-            pf[p] = pj[p] + v;
-          }
+          for (int p = 0; p < P; ++p) pf[p] = fv[p * fs + (size_t)f * L.ld + k];
         } else {
-          const int bc = -1 - g.f_R[f];
-          const double sc = g.bc_kind[bc] == 0 ? spar[s * NPAR] : 1.0;
+          const int bc = sbc[s];
+          const T sc = g.bc_kind[bc] == 0 ? spar[s * NPAR] : (T)1;
 #pragma unroll
-          for (int p = 0; p < P; ++p) pf[p] = sc * bcpair[((size_t)bc * P + p) * L.cap + k];
+          for (int p = 0; p < P; ++p) pf[p] = sc * (T)bcpair[((size_t)bc * P + p) * L.cap + k];
         }
-        if (j >= 0) {
-          const double* par = spar + s * NPAR;
-          const double gv = maxw<D>(par, lds + s * D * nu, nu, u);
-          double G, H;
-          shakhov<D>(par, gv, xi, G, H);
+        if (snbr[s] >= 0) {
+          const T* par = spar + s * NPAR;
+          const T gv = maxw_r<D, T>(par, lds + s * D * nu, nu, u);
+          T G, H;
+          shakhov_r<D, T>(par, gv, xr, G, H);
           pf[0] = par[P_A] * pf[0] + par[P_B] * G;
           if (P == 2) pf[P - 1] = par[P_A] * pf[P - 1] + par[P_B] * H;
         }
-        const double w = g.s_sigA[i * MAXF + s] * sn;
+        const T w = ssa[s] * (T)sn;
 #pragma unroll
         for (int p = 0; p < P; ++p) div[p] += w * pf[p];
       }
     }
     // closed Shakhov target
-    const double gv = maxw<D>(tp, lds + MAXF * D * nu, nu, u);
-    double G, H;
-    shakhov<D>(tp, gv, xi, G, H);
-    double c[D], c2 = 0.0, poly = slam[0];
+    const T gv = maxw_r<D, T>(tp, lds + MAXF * D * nu, nu, u);
+    T G, H;
+    shakhov_r<D, T>(tp, gv, xr, G, H);
+    T c[D], c2 = 0, poly = slam[0];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      c[d] = xi[d] - tp[P_U + d];
+      c[d] = xr[d] - tp[P_U + d];
       c2 += c[d] * c[d];
       poly += slam[1 + d] * c[d];
     }
     poly += slam[D + 1] * c2;
-    const double tgt[2] = {G + poly * gv, H + poly * tp[P_RT] * gv};
-    const double inv = 1.0 / (1.0 + dtt);
+    const T tgt[2] = {G + poly * gv, H + poly * tp[P_RT] * gv};
     double nv[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      nv[p] = (phi[p] + dtt * tgt[p] - dtv * div[p]) * inv;
-      const T st = (T)nv[p];
+      const T st = (phi[p] + dtt * tgt[p] - dtv * div[p]) * inv;
       vout[p * cs + (size_t)i * L.ld + k] = st;
       nv[p] = (double)st;
     }
-    double xi2 = 0.0;
+    double xi2 = 0.0, cd[D], c2d = 0.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+    for (int d = 0; d < D; ++d) {
+      xi2 += xi[d] * xi[d];
+      cd[d] = xi[d] - (double)tp[P_U + d];
+      c2d += cd[d] * cd[d];
+    }
     const double Hn = (P == 2) ? nv[P - 1] : 0.0;
     mom_acc<D>(acc, A, xi, xi2, nv[0], Hn);
-    const double e = 0.5 * A * (c2 * nv[0] + Hn);
+    const double e = 0.5 * A * (c2d * nv[0] + Hn);
 #pragma unroll
-    for (int d = 0; d < D; ++d) acc[N + d] += e * c[d];
+    for (int d = 0; d < D; ++d) acc[N + d] += e * cd[d];
   }
   block_sum<N + D>(acc, red);
   if (threadIdx.x == 0) {

@@ -63,9 +63,10 @@ def test_buffer_sizes(avs, dim):
     vs, pm, op, keep, mesh = descriptors(avs, dim=dim)
     P = 2 if dim == 2 else 1
     cap = -(-vs.leaf_capacity // 64) * 64
-    assert avs.lib.avs_vdf_bytes(C.byref(vs), C.byref(pm), C.byref(op)) == 2 * P * mesh["ncells"] * cap * 8
+    rows = 2 * mesh["ncells"] + mesh["nfaces"]        # current, next and one interface row per face
+    assert avs.lib.avs_vdf_bytes(C.byref(vs), C.byref(pm), C.byref(op)) == rows * P * cap * 8
     op.precision = 1
-    assert avs.lib.avs_vdf_bytes(C.byref(vs), C.byref(pm), C.byref(op)) == 2 * P * mesh["ncells"] * cap * 4
+    assert avs.lib.avs_vdf_bytes(C.byref(vs), C.byref(pm), C.byref(op)) == rows * P * cap * 4
     assert avs.lib.avs_workspace_bytes(C.byref(vs), C.byref(pm), C.byref(op)) > 0
 
 
