@@ -40,7 +40,8 @@ def parse():
     p.add_argument("--nu", type=int, default=20, help="sweeps per adaptation cycle")
     p.add_argument("--leaves", type=int, default=20000, help="target leaf count of the step-0 tree")
     p.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    p.add_argument("--forms", action="store_true", help="also time the FP32 form")
+    p.add_argument("--forms", action="store_true", help="also time the FP32 form and the batched form")
+    p.add_argument("--ncase", type=int, default=64, help="cases of the batched form")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-sweep", action="store_true", help="skip the extra sweep-only timing (profiling runs)")
     p.add_argument("--copy-probe", type=float, default=0.0,
@@ -68,6 +69,7 @@ class Workload:
         self.base_level, self.base_idx = L['level'].copy(), L['idx'].copy()
         self.W0 = self.cs.get_W()
         self.nc = self.cs.nc
+        self.nf = int(c['mesh']['nfaces'])
 
     def tree(self, C1):
         """Step-0 tree: roots, then one adaptation per level on cells and probes."""
@@ -147,10 +149,15 @@ def sweep_only(w, nsweep):
     return w.nc * nv * nsweep / (ms * 1e-3), ms / nsweep, nv
 
 
-def vdf_bytes_per_node(P, es):
-    """Algorithmic HBM bytes per (cell, leaf) per launch of each VDF kernel."""
-    return {"passA": P * es, "passC": 2 * P * es, "criterion": P * es, "remap_gather": 2 * P * es,
-            "remap_correct": 2 * P * es, "moments": P * es}
+def vdf_bytes_per_node(P, es, rows_per_cell):
+    """Algorithmic HBM bytes per (cell, leaf) of one launch of each VDF
+    kernel: every distinct byte it must read or write, once.  A leaf row of
+    one cell holds P*es bytes; ``rows_per_cell`` = interface rows (faces)
+    per cell, each written once by pass A and read by the face reduction and
+    by pass C."""
+    r = P * es
+    return {"passA": r * (1.0 + rows_per_cell), "face": r * rows_per_cell, "passC": r * (2.0 + rows_per_cell),
+            "criterion": r, "remap_gather": 2 * r, "remap_correct": 2 * r, "moments": r}
 
 
 def cpu_baseline(w, ncell_sample=16):
@@ -176,6 +183,92 @@ def cpu_baseline(w, ncell_sample=16):
     return {"value": len(sample) * L['n'] / dt, "unit": "cell-node updates/s", "cores": 1, "kind": "oracle",
             "sample": f"one explicit step of {len(sample)} contiguous cells x {L['n']} leaves of the same workload "
                       f"(NumPy FP64, single thread; BLAS threads={threads}), {dt:.2f} s"}
+
+
+def run_batched(args):
+    """The batched form: 64 seeded independent cases (FP32) advanced by the
+    batched kernels through one captured graph per adaptation cycle."""
+    import torch
+    from paper_2212_05645_amd import avs
+    from workloads import fields as F
+    specs = F.batch_cases(seed=0, ncase=args.ncase)
+    stream = torch.cuda.Stream()
+    cases, W0s, bases = [], [], []
+    with torch.cuda.stream(stream):
+        for c in specs:
+            cap = max(256, int(1.5 * c['target_leaves']))
+            cs = avs.Case(c['mesh'], c['vspace'], c['gas'], c['dt'], c['venkat_K'], c['prim0'], precision=avs.AVS_FP32,
+                          leaf_capacity=cap, stream=stream)
+            L = cs.leaves()
+            cases.append(cs)
+            W0s.append(cs.get_W())
+            bases.append((L['level'].copy(), L['idx'].copy()))
+
+        def tree(i, C1):
+            cs, c = cases[i], specs[i]
+            cs.set_leaves(*bases[i])
+            cs.set_state(None, W0s[i])
+            for _ in range(c['vspace']['max_level']):
+                try:
+                    cs.adapt(C1, math.exp(-8.0) * C1, probes=c['probes'])
+                except avs.AvsError as e:
+                    if e.status == avs.AVS_E_CAPACITY:
+                        return None
+                    raise
+                cs.remap(2)
+            cs.set_state(None, W0s[i])
+            return cs.nleaves()
+        C1s = []
+        for i, c in enumerate(specs):
+            lo, hi, best = -9.0, 0.0, None
+            for _ in range(12):
+                mid = 0.5 * (lo + hi)
+                n = tree(i, 10.0 ** mid)
+                if n is None or n > c['target_leaves']:
+                    lo = mid
+                else:
+                    hi, best = mid, 10.0 ** mid
+            C1s.append(best if best is not None else 10.0 ** hi)
+            tree(i, C1s[-1])
+        log(f"batched: {len(cases)} cases, leaves {[cs.nleaves() for cs in cases]}")
+        batch = avs.Batch(cases)
+        chunk = batch.tune()
+        log(f"batched: tuned pass-A chunk {chunk}")
+
+        def cycle():
+            batch.step(args.nu, graph=True)
+            for cs, C1 in zip(cases, C1s):
+                try:
+                    cs.adapt(C1, math.exp(-8.0) * C1)
+                    cs.remap(2)
+                except avs.AvsError as e:
+                    if e.status != avs.AVS_E_CAPACITY:
+                        raise
+        for _ in range(args.warmup):
+            cycle()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        updates = 0
+        for _ in range(args.steps):
+            updates += sum(cs.nc * cs.nleaves() for cs in cases) * args.nu
+            cycle()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        batch.check()
+        # sweep-only rate of the captured graph
+        nodes = sum(cs.nc * cs.nleaves() for cs in cases)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        batch.step(args.nu, graph=True)
+        e0.record(stream)
+        batch.step(args.nu, graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sweep_ms = e0.elapsed_time(e1) / args.nu
+        batch.close()
+    return {"cycle_updates_per_s": updates / (ms * 1e-3), "sweep_updates_per_s": nodes / (sweep_ms * 1e-3),
+            "sweep_ms": sweep_ms, "cases": len(cases), "cell_leaf_nodes": nodes, "tuned_chunk": chunk,
+            "workload": "64 seeded cavity/cylinder cases, Kn 1e-3..1, Ma 0.1..6, grids 32^2..96^2, "
+                        "256..16k leaves, FP32, one graph per adaptation cycle"}
 
 
 def run_form(args, precision, C1=None):
@@ -212,7 +305,7 @@ def main():
     prof = r["prof"]
     nv = r["prof_leaves"]
     kern = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1]} for k, v in prof.items()}
-    bpn = vdf_bytes_per_node(P, es)
+    bpn = vdf_bytes_per_node(P, es, w.nf / w.nc)
     dom = max(prof, key=lambda k: prof[k][0])
     roof_k = dom if dom in bpn else "passC"
     t_launch = prof[roof_k][0] / prof[roof_k][1] * 1e-3
@@ -236,6 +329,12 @@ def main():
                         "sweep_ms": r2["sweep_ms"], "leaves": r2["sweep_leaves"],
                         "kernels": {k: v[0] / v[1] for k, v in r2["prof"].items()}}
         w = w2
+        del w2
+        torch.cuda.empty_cache()
+        try:
+            forms["batched_fp32"] = run_batched(args)
+        except Exception as e:
+            forms["batched_fp32"] = {"error": repr(e)}
     cpu = None
     if not args.no_cpu:
         try:

@@ -199,6 +199,26 @@ avs_status avs_get_cells(avs_ctx *ctx, int64_t ncell_sel, const int64_t *cells_h
 avs_status avs_profile(avs_ctx *ctx, int32_t enable);
 int32_t avs_profile_read(avs_ctx *ctx, int32_t nmax, char *names_host, double *ms_host, int64_t *count_host);
 
+/* Batched form: many independent contexts (same dimension, precision and
+ * non-default stream) advance in the same launches -- one launch per step
+ * kernel covers the workgroups of every case -- and avs_batch_step with
+ * use_graph != 0 captures the whole nsteps sequence in one HIP graph that
+ * is replayed until a case's leaf count or the tile choice changes.  The
+ * members stay usable on their own (adapt, remap, moments) between batch
+ * steps.  The batch workspace (device, avs_batch_workspace_bytes) holds the
+ * per-case argument tables.  avs_batch_tune times two steps per candidate
+ * leaf chunk of pass A (512..8192 leaves per workgroup; the batch advances
+ * 10 steps) and keeps the fastest.  avs_batch_check waits and reports a
+ * non-physical state in any member. */
+typedef struct avs_batch avs_batch;
+size_t avs_batch_workspace_bytes(int32_t ncase);
+avs_status avs_batch_create(int32_t ncase, avs_ctx *const *ctxs, void *workspace_dev, size_t workspace_bytes,
+                            avs_batch **out);
+avs_status avs_batch_step(avs_batch *batch, int32_t nsteps, int32_t use_graph);
+avs_status avs_batch_check(avs_batch *batch);
+avs_status avs_batch_tune(avs_batch *batch, int32_t *chunk_host);
+void avs_batch_destroy(avs_batch *batch);
+
 /* Release the context (never frees caller memory). */
 void avs_destroy(avs_ctx *ctx);
 

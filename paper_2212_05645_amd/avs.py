@@ -23,7 +23,8 @@ AVS_COPY, AVS_SPLIT, AVS_MERGE = 0, 1, 2
 EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_init_mesh", "avs_step",
            "avs_moments", "avs_adapt", "avs_remap", "avs_leaves", "avs_plan", "avs_criterion",
            "avs_set_leaves", "avs_get_state", "avs_set_state", "avs_get_cells", "avs_profile",
-           "avs_profile_read", "avs_destroy", "avs_last_error")
+           "avs_profile_read", "avs_batch_workspace_bytes", "avs_batch_create", "avs_batch_step",
+           "avs_batch_check", "avs_batch_tune", "avs_batch_destroy", "avs_destroy", "avs_last_error")
 
 
 class avs_vspace(C.Structure):
@@ -71,6 +72,12 @@ def _load():
         "avs_get_cells": (I32, [VP, I64, VP, VP]),
         "avs_profile": (I32, [VP, I32]),
         "avs_profile_read": (I32, [VP, I32, VP, VP, VP]),
+        "avs_batch_workspace_bytes": (C.c_size_t, [I32]),
+        "avs_batch_create": (I32, [I32, VP, VP, C.c_size_t, P(VP)]),
+        "avs_batch_step": (I32, [VP, I32, I32]),
+        "avs_batch_check": (I32, [VP]),
+        "avs_batch_tune": (I32, [VP, P(I32)]),
+        "avs_batch_destroy": (None, [VP]),
         "avs_destroy": (None, [VP]),
         "avs_last_error": (C.c_char_p, []),
     }
@@ -107,7 +114,7 @@ class Case:
     """One context of the library plus the device memory it runs in."""
 
     def __init__(self, mesh, vspace, gas, dt, venkat_K, prim0, precision=AVS_FP64, leaf_capacity=None,
-                 device="cuda:0"):
+                 device="cuda:0", stream=None):
         import torch
         self._torch = torch
         D = int(mesh["dim"])
@@ -160,7 +167,7 @@ class Case:
         self.device = torch.device(device)
         self.vdf_mem = torch.empty(vb, dtype=torch.uint8, device=self.device)
         self.ws_mem = torch.empty(wb, dtype=torch.uint8, device=self.device)
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         p0 = np.ascontiguousarray(prim0, dtype=np.float64)
         ctx = C.c_void_p()
         _check(lib.avs_init_mesh(C.byref(vs), C.byref(pm), C.byref(g), C.byref(op), p0.ctypes.data,
@@ -268,6 +275,44 @@ class Case:
         if getattr(self, "ctx", None):
             lib.avs_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several Cases (same dimension, precision and non-default stream)
+    advanced together by the batched kernels, optionally through a graph."""
+
+    def __init__(self, cases):
+        import torch
+        self.cases = list(cases)
+        n = len(self.cases)
+        ptrs = (C.c_void_p * n)(*[c.ctx.value for c in self.cases])
+        wb = lib.avs_batch_workspace_bytes(n)
+        self.ws = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.cases[0].device)
+        b = C.c_void_p()
+        _check(lib.avs_batch_create(n, ptrs, self.ws.data_ptr(), wb, C.byref(b)))
+        self.b = b
+
+    def step(self, n=1, graph=True):
+        _check(lib.avs_batch_step(self.b, int(n), 1 if graph else 0))
+
+    def check(self):
+        _check(lib.avs_batch_check(self.b))
+
+    def tune(self):
+        ch = C.c_int32()
+        _check(lib.avs_batch_tune(self.b, C.byref(ch)))
+        return ch.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib.avs_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

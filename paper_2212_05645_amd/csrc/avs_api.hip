@@ -541,6 +541,152 @@ avs_status guard(avs_ctx* ctx) {
 
 }  // namespace
 
+
+// ------------------------------------------------------------ batched form
+struct avs_batch {
+  std::vector<avs_ctx*> cases;
+  int D = 2, prec = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  int chunk = CHUNK;
+  int nblk[BK_N] = {0, 0, 0, 0, 0};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_steps = -1;
+  int graph_nblk[BK_N] = {-1, -1, -1, -1, -1};
+  int graph_chunk = -1;
+  std::vector<char> host_args;
+  ~avs_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace {
+
+size_t batch_args_bytes(int ncase) { return (size_t)round_up(2 * (size_t)ncase * sizeof(CaseArgs<double>), 256); }
+
+template <typename T>
+CaseArgs<T> case_args(avs_ctx* c, int flip, int chunk) {
+  CaseArgs<T> a;
+  a.g = c->geo;
+  a.L = c->leaves(c->lcur);
+  a.vg = c->vg;
+  a.gas = c->gas;
+  a.h = c->h;
+  a.dt = c->dt;
+  const int cur = c->cur ^ flip;
+  a.vin = (const T*)c->vdf[cur];
+  a.vout = (T*)c->vdf[cur ^ 1];
+  a.fv = (T*)c->fv;
+  a.bden = c->bden;
+  a.bfin = c->bfin;
+  a.fpar = c->fpar;
+  a.F = c->F;
+  a.W = flip ? c->Wn : c->W;
+  a.Wn = flip ? c->W : c->Wn;
+  a.q = c->q;
+  a.tpar = c->tpar;
+  a.lam = c->lam;
+  a.bcpair = c->bcpair;
+  a.mom = c->mom;
+  a.bad = c->bad;
+  a.chunk = chunk;
+  a.gx = (int)round_up(c->nc, 8);
+  return a;
+}
+
+// Upload both orientations of every case and the workgroup offsets.
+template <typename T>
+avs_status batch_upload(avs_batch* b) {
+  avs_ctx* ctx = nullptr;
+  const int n = (int)b->cases.size();
+  b->host_args.resize(batch_args_bytes(n) + sizeof(int) * BK_N * (n + 1));
+  CaseArgs<T>* args = reinterpret_cast<CaseArgs<T>*>(b->host_args.data());
+  int* off = reinterpret_cast<int*>(b->host_args.data() + batch_args_bytes(n));
+  for (int k = 0; k < BK_N; ++k) off[k * (n + 1)] = 0;
+  for (int i = 0; i < n; ++i) {
+    avs_ctx* c = b->cases[i];
+    args[i] = case_args<T>(c, 0, b->chunk);
+    args[n + i] = case_args<T>(c, 1, b->chunk);
+    const int nl = c->nleaf[c->lcur];
+    const int gx = (int)round_up(c->nc, 8);
+    const int cnt[BK_N] = {gx * ((nl + b->chunk - 1) / b->chunk), c->nf, (c->nc + BLOCK - 1) / BLOCK, c->nc, gx};
+    for (int k = 0; k < BK_N; ++k) off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + cnt[k];
+  }
+  for (int k = 0; k < BK_N; ++k) b->nblk[k] = off[k * (n + 1) + n];
+  CK(hipMemcpyAsync(b->ws, b->host_args.data(), b->host_args.size(), hipMemcpyHostToDevice, b->stream));
+  CK(hipStreamSynchronize(b->stream));
+  return AVS_OK;
+}
+
+template <int D, typename T>
+avs_status batch_launch(avs_batch* b, int nsteps) {
+  avs_ctx* ctx = nullptr;
+  const int n = (int)b->cases.size();
+  const CaseArgs<T>* args = reinterpret_cast<const CaseArgs<T>*>(b->ws);
+  const int* off = reinterpret_cast<const int*>(b->ws + batch_args_bytes(n));
+  int numax = 0;
+  for (avs_ctx* c : b->cases) numax = std::max(numax, c->vg.numax);
+  constexpr int MAXF = Cfg<D>::MAXF;
+  for (int s = 0; s < nsteps; ++s) {
+    const CaseArgs<T>* a = args + (s & 1) * n;
+    kb_passA<D, T><<<b->nblk[BK_PASSA], BLOCK, 0, b->stream>>>(a, off + BK_PASSA * (n + 1), n);
+    CKL();
+    kb_face<D, T><<<b->nblk[BK_FACE], BLOCK, (size_t)D * numax * sizeof(T), b->stream>>>(a, off + BK_FACE * (n + 1), n);
+    CKL();
+    kb_macro<D, T><<<b->nblk[BK_MACRO], BLOCK, 0, b->stream>>>(a, off + BK_MACRO * (n + 1), n);
+    CKL();
+    kb_target<D, T><<<b->nblk[BK_TARGET], BLOCK, (size_t)D * numax * sizeof(T), b->stream>>>(a, off + BK_TARGET * (n + 1), n);
+    CKL();
+    kb_passC<D, T><<<b->nblk[BK_PASSC], BLOCK, (size_t)(MAXF + 1) * D * numax * sizeof(T), b->stream>>>(
+        a, off + BK_PASSC * (n + 1), n);
+    CKL();
+  }
+  return AVS_OK;
+}
+
+avs_status batch_run(avs_batch* b, int nsteps, bool graph) {
+  avs_ctx* ctx = nullptr;
+  const bool f64 = b->prec == AVS_FP64;
+  avs_status st = f64 ? batch_upload<double>(b) : batch_upload<float>(b);
+  if (st) return st;
+  if (!graph) {
+    st = b->D == 2 ? (f64 ? batch_launch<2, double>(b, nsteps) : batch_launch<2, float>(b, nsteps))
+                   : (f64 ? batch_launch<3, double>(b, nsteps) : batch_launch<3, float>(b, nsteps));
+  } else {
+    bool same = b->exec && b->graph_steps == nsteps && b->graph_chunk == b->chunk;
+    for (int k = 0; k < BK_N; ++k) same = same && b->graph_nblk[k] == b->nblk[k];
+    if (!same) {
+      if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+      if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+      CK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      st = b->D == 2 ? (f64 ? batch_launch<2, double>(b, nsteps) : batch_launch<2, float>(b, nsteps))
+                     : (f64 ? batch_launch<3, double>(b, nsteps) : batch_launch<3, float>(b, nsteps));
+      hipGraph_t gr = nullptr;
+      const hipError_t ec = hipStreamEndCapture(b->stream, &gr);
+      if (st) { if (gr) (void)hipGraphDestroy(gr); return st; }
+      CK(ec);
+      b->graph = gr;
+      CK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->graph_steps = nsteps;
+      b->graph_chunk = b->chunk;
+      for (int k = 0; k < BK_N; ++k) b->graph_nblk[k] = b->nblk[k];
+    }
+    CK(hipGraphLaunch(b->exec, b->stream));
+  }
+  if (st) return st;
+  // the members now hold their state in the other buffers after an odd count
+  if (nsteps & 1)
+    for (avs_ctx* c : b->cases) {
+      std::swap(c->W, c->Wn);
+      c->cur ^= 1;
+    }
+  return AVS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 double avs_mu_ref_from_kn(double Kn, double omega, double R, double T_ref, double rho_ref, double L_ref) {
@@ -1081,6 +1227,86 @@ int32_t avs_profile_read(avs_ctx* ctx, int32_t nmax, char* names_host, double* m
   }
   return n;
 }
+
+
+size_t avs_batch_workspace_bytes(int32_t ncase) {
+  if (ncase < 1 || ncase > 4096) return 0;
+  return batch_args_bytes(ncase) + round_up(sizeof(int) * BK_N * (ncase + 1), 256);
+}
+
+avs_status avs_batch_create(int32_t ncase, avs_ctx* const* ctxs, void* workspace_dev, size_t workspace_bytes,
+                            avs_batch** out) {
+  if (!out) return fail(AVS_E_INVALID, "out is null");
+  *out = nullptr;
+  if (ncase < 1 || ncase > 4096 || !ctxs) return fail(AVS_E_INVALID, "ncase must be in [1, 4096]");
+  if (!workspace_dev || workspace_bytes < avs_batch_workspace_bytes(ncase))
+    return fail(AVS_E_INVALID, "batch workspace too small (%zu < %zu)", workspace_bytes, avs_batch_workspace_bytes(ncase));
+  for (int i = 0; i < ncase; ++i) {
+    avs_ctx* c = ctxs[i];
+    if (avs_status st = guard(c)) return st;
+    if (c->D != ctxs[0]->D || c->prec != ctxs[0]->prec)
+      return fail(AVS_E_INVALID, "case %d: all cases of a batch need the same dimension and precision", i);
+    if (c->stream != ctxs[0]->stream) return fail(AVS_E_INVALID, "case %d: all cases of a batch need the same stream", i);
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(AVS_E_INVALID, "case %d appears twice", i);
+  }
+  if (ctxs[0]->stream == nullptr) return fail(AVS_E_INVALID, "a batch needs a non-default stream (graph capture)");
+  avs_batch* b = new avs_batch();
+  b->cases.assign(ctxs, ctxs + ncase);
+  b->D = ctxs[0]->D;
+  b->prec = ctxs[0]->prec;
+  b->stream = ctxs[0]->stream;
+  b->ws = (char*)workspace_dev;
+  *out = b;
+  return AVS_OK;
+}
+
+avs_status avs_batch_step(avs_batch* b, int32_t nsteps, int32_t use_graph) {
+  if (!b) return fail(AVS_E_INVALID, "null batch");
+  if (nsteps < 0) return fail(AVS_E_INVALID, "nsteps < 0");
+  for (avs_ctx* c : b->cases)
+    if (avs_status st = guard(c)) return st;
+  if (nsteps == 0) return AVS_OK;
+  avs_status st = batch_run(b, nsteps, use_graph != 0);
+  if (st)
+    for (avs_ctx* c : b->cases) c->failed = true;
+  return st;
+}
+
+avs_status avs_batch_check(avs_batch* b) {
+  if (!b) return fail(AVS_E_INVALID, "null batch");
+  for (avs_ctx* c : b->cases)
+    if (avs_status st = check_bad(c)) return st;
+  return AVS_OK;
+}
+
+avs_status avs_batch_tune(avs_batch* b, int32_t* chunk_host) {
+  if (!b) return fail(AVS_E_INVALID, "null batch");
+  avs_ctx* ctx = nullptr;
+  const int cand[] = {512, 1024, 2048, 4096, 8192};
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int arg = b->chunk;
+  for (int c : cand) {
+    b->chunk = c;
+    CK(hipEventRecord(e0, b->stream));
+    if (avs_status st = batch_run(b, 2, false)) return st;
+    CK(hipEventRecord(e1, b->stream));
+    CK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; arg = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->chunk = arg;
+  if (chunk_host) *chunk_host = arg;
+  return AVS_OK;
+}
+
+void avs_batch_destroy(avs_batch* b) { delete b; }
 
 void avs_destroy(avs_ctx* ctx) {
   if (!ctx) return;

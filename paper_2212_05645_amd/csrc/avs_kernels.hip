@@ -545,12 +545,12 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
 // leaf chunks) with cells fastest, so that a cell and its neighbours read
 // the same chunk of their rows at about the same time.
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passA(Geo g, Leaves L, const T* __restrict__ vdf,
-                                                                      double h, T* __restrict__ fv, int chunk) {
+__device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ vdf,
+                                                                      double h, T* __restrict__ fv, int chunk, int bx, int by) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
-  const int i = xcd_cell(g, blockIdx.x);
+  const int i = xcd_cell(g, bx);
   if (i < 0) return;
-  const int k0 = blockIdx.y * chunk, k1 = min(L.n, k0 + chunk);
+  const int k0 = by * chunk, k1 = min(L.n, k0 + chunk);
   const size_t cs = (size_t)g.nc * L.ld;
   const size_t fs = (size_t)g.nf * L.ld;   // component stride of the interface buffer
   Stencil<D, T> st;
@@ -592,6 +592,12 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passA(Geo g, Le
   }
 }
 
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passA(Geo g, Leaves L, const T* __restrict__ vdf,
+                                                                      double h, T* __restrict__ fv, int chunk) {
+  d_passA<D, T>(g, L, vdf, h, fv, chunk, blockIdx.x, blockIdx.y);
+}
+
 // Flux of a raw-moment set through normal n: (n.m1, n.m2, n.e1).
 template <int D>
 __device__ __forceinline__ void raw_flux(const double* m, const double* n, double* F) {
@@ -621,10 +627,10 @@ __device__ __forceinline__ void raw_flux(const double* m, const double* n, doubl
 // evaluated in R from the record.  Boundary face: outgoing flux plus the
 // incoming wall (zero net mass flux, rho_w) or far-field Maxwellian flux.
 template <int D, typename R>
-__global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, VGrid vg, GasP gas, double h, const R* __restrict__ fv,
+__device__ __forceinline__ void d_face(Geo g, Leaves L, VGrid vg, GasP gas, double h, const R* __restrict__ fv,
                                                const double* __restrict__ bden, const double* __restrict__ bfin,
                                                double* __restrict__ fpar, double* __restrict__ F,
-                                               int* __restrict__ bad) {
+                                               int* __restrict__ bad, int bx, int by) {
   constexpr int P = Cfg<D>::P, NM = Cfg<D>::NM, N = D + 2;
   extern __shared__ double lds_d[];
   R* tab = reinterpret_cast<R*>(lds_d);
@@ -633,7 +639,7 @@ __global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, VGrid vg, GasP 
   __shared__ R rp[NPAR];
   __shared__ double sF[N];
   __shared__ int interior_ok;
-  const int f = blockIdx.x;
+  const int f = bx;
   const int Rc = g.f_R[f];
   const size_t fs = (size_t)g.nf * L.ld;
   double n[D];
@@ -748,13 +754,21 @@ __global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, VGrid vg, GasP 
   }
 }
 
+template <int D, typename R>
+__global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, VGrid vg, GasP gas, double h, const R* __restrict__ fv,
+                                               const double* __restrict__ bden, const double* __restrict__ bfin,
+                                               double* __restrict__ fpar, double* __restrict__ F,
+                                               int* __restrict__ bad) {
+  d_face<D, R>(g, L, vg, gas, h, fv, bden, bfin, fpar, F, bad, blockIdx.x, blockIdx.y);
+}
+
 // ------------------------------------------------------ macro update (S8-S9)
 template <int D>
-__global__ void k_macro(Geo g, GasP gas, double dt, const double* __restrict__ F, const double* __restrict__ W,
+__device__ __forceinline__ void d_macro(Geo g, GasP gas, double dt, const double* __restrict__ F, const double* __restrict__ W,
                         double* __restrict__ Wn, const double* __restrict__ qcur, double* __restrict__ tpar,
-                        int* __restrict__ bad) {
+                        int* __restrict__ bad, int bx, int by) {
   constexpr int MAXF = Cfg<D>::MAXF, N = D + 2;
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const int i = bx * BLOCK + threadIdx.x;
   if (i >= g.nc) return;
   const int ns = g.nslot[i];
   double Fs[N];
@@ -779,20 +793,27 @@ __global__ void k_macro(Geo g, GasP gas, double dt, const double* __restrict__ F
   par[P_T] = T;
 }
 
+template <int D>
+__global__ void k_macro(Geo g, GasP gas, double dt, const double* __restrict__ F, const double* __restrict__ W,
+                        double* __restrict__ Wn, const double* __restrict__ qcur, double* __restrict__ tpar,
+                        int* __restrict__ bad) {
+  d_macro<D>(g, gas, dt, F, W, Wn, qcur, tpar, bad, blockIdx.x, blockIdx.y);
+}
+
 // --------------------------------------- conservative relaxation target (S9)
 // lambda such that closure(Shakhov(W^{n+1}, q^n)) has moments W^{n+1}; the
 // Shakhov values are evaluated in R, the moment and Gram sums in FP64 and
 // the (D+2)x(D+2) solve in FP64.
 template <int D, typename R>
-__global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, const double* __restrict__ tpar,
+__device__ __forceinline__ void d_target(Geo g, Leaves L, VGrid vg, const double* __restrict__ tpar,
                                                    const double* __restrict__ Wn, double* __restrict__ lam,
-                                                   int* __restrict__ bad) {
+                                                   int* __restrict__ bad, int bx, int by) {
   constexpr int N = D + 2, NS = Cfg<D>::NS;
   extern __shared__ double lds_d[];
   R* tab = reinterpret_cast<R*>(lds_d);
   __shared__ double red[4 * (N + NS)];
   __shared__ R rp[NPAR];
-  const int i = blockIdx.x;
+  const int i = bx;
   const double* par = tpar + (size_t)i * NPAR;
   if (threadIdx.x < NPAR) rp[threadIdx.x] = (R)par[threadIdx.x];
   build_tab_r<D, R>(tab, par, vg);
@@ -827,6 +848,13 @@ __global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, con
   }
 }
 
+template <int D, typename R>
+__global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, const double* __restrict__ tpar,
+                                                   const double* __restrict__ Wn, double* __restrict__ lam,
+                                                   int* __restrict__ bad) {
+  d_target<D, R>(g, L, vg, tpar, Wn, lam, bad, blockIdx.x, blockIdx.y);
+}
+
 // -------------------------------------------------- pass C (S6, S7, S10)
 // Interface VDFs of every face of the cell (upwind reconstruction from the
 // interface buffer, blended with the interface Shakhov equilibrium; wall or
@@ -835,11 +863,11 @@ __global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, con
 // phi^{n+1}, and the moments and heat flux of phi^{n+1} for the next step.
 // Arithmetic in T, sums in FP64; the upwind sign in FP64 in both forms.
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
+__device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
                                                      const T* __restrict__ fv, T* __restrict__ vout,
                                                      const double* __restrict__ fpar, const double* __restrict__ tpar,
                                                      const double* __restrict__ lam, const double* __restrict__ bcpair,
-                                                     double* __restrict__ mom, double* __restrict__ qout) {
+                                                     double* __restrict__ mom, double* __restrict__ qout, int bx, int by) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF, N = D + 2;
   extern __shared__ double lds_d[];
   T* lds = reinterpret_cast<T*>(lds_d);
@@ -849,7 +877,7 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passC(Geo g, Le
   __shared__ int sface[MAXF], snbr[MAXF], sbc[MAXF];
   __shared__ T ssa[MAXF];
   __shared__ T slam[N];
-  const int i = xcd_cell(g, blockIdx.x);
+  const int i = xcd_cell(g, bx);
   if (i < 0) return;
   const int ns = g.nslot[i];
   const int nu = vg.numax;
@@ -968,6 +996,15 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passC(Geo g, Le
     for (int m = 0; m < N; ++m) mom[(size_t)i * N + m] = acc[m];
     for (int d = 0; d < D; ++d) qout[(size_t)i * D + d] = acc[N + d];
   }
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
+                                                     const T* __restrict__ fv, T* __restrict__ vout,
+                                                     const double* __restrict__ fpar, const double* __restrict__ tpar,
+                                                     const double* __restrict__ lam, const double* __restrict__ bcpair,
+                                                     double* __restrict__ mom, double* __restrict__ qout) {
+  d_passC<D, T>(g, L, vg, vin, fv, vout, fpar, tpar, lam, bcpair, mom, qout, blockIdx.x, blockIdx.y);
 }
 
 // ----------------------------------------------- boundary Maxwellians (S7)
@@ -1366,6 +1403,94 @@ __global__ void k_unpack(int P, int nrow, int n, int ld, size_t cs, const double
   const int r = blockIdx.y, p = blockIdx.z;
   if (k >= n) return;
   vdf[p * cs + (size_t)r * ld + k] = (T)in[((size_t)p * nrow + r) * n + k];
+}
+
+}  // namespace avs
+
+namespace avs {
+
+// ----------------------------------------------------------- batched form
+// Many independent cases advance in the same launches: one launch per step
+// kernel covers the workgroups of every case.  Per-case arguments live in
+// device memory (two orientations: even and odd steps swap the state
+// buffers), and prefix sums of per-case workgroup counts map a workgroup to
+// its case, so the launch sequence can be captured once in a graph.
+template <typename T>
+struct CaseArgs {
+  Geo g;
+  Leaves L;
+  VGrid vg;
+  GasP gas;
+  double h, dt;
+  const T* vin;
+  T* vout;
+  T* fv;
+  const double* bden;
+  const double* bfin;
+  double* fpar;
+  double* F;
+  const double* W;
+  double* Wn;
+  double* q;
+  double* tpar;
+  double* lam;
+  const double* bcpair;
+  double* mom;
+  int* bad;
+  int chunk, gx;   // pass A: leaves per workgroup, round_up(nc, 8)
+};
+
+enum { BK_PASSA, BK_FACE, BK_MACRO, BK_TARGET, BK_PASSC, BK_N };
+
+// Largest c with off[c] <= b (off has ncase + 1 increasing entries).
+__device__ __forceinline__ int find_case(const int* __restrict__ off, int ncase, int b) {
+  int lo = 0, hi = ncase - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passA(const CaseArgs<T>* __restrict__ args,
+                                                                       const int* __restrict__ off, int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const CaseArgs<T>* a = args + c;
+  const int lb = blockIdx.x - off[c];
+  d_passA<D, T>(a->g, a->L, a->vin, a->h, a->fv, a->chunk, lb % a->gx, lb / a->gx);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void kb_face(const CaseArgs<T>* __restrict__ args, const int* __restrict__ off,
+                                                int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const CaseArgs<T>* a = args + c;
+  d_face<D, T>(a->g, a->L, a->vg, a->gas, a->h, a->fv, a->bden, a->bfin, a->fpar, a->F, a->bad, blockIdx.x - off[c], 0);
+}
+
+template <int D, typename T>
+__global__ void kb_macro(const CaseArgs<T>* __restrict__ args, const int* __restrict__ off, int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const CaseArgs<T>* a = args + c;
+  d_macro<D>(a->g, a->gas, a->dt, a->F, a->W, a->Wn, a->q, a->tpar, a->bad, blockIdx.x - off[c], 0);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void kb_target(const CaseArgs<T>* __restrict__ args, const int* __restrict__ off,
+                                                  int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const CaseArgs<T>* a = args + c;
+  d_target<D, T>(a->g, a->L, a->vg, a->tpar, a->Wn, a->lam, a->bad, blockIdx.x - off[c], 0);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passC(const CaseArgs<T>* __restrict__ args,
+                                                                       const int* __restrict__ off, int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const CaseArgs<T>* a = args + c;
+  d_passC<D, T>(a->g, a->L, a->vg, a->vin, a->fv, a->vout, a->fpar, a->tpar, a->lam, a->bcpair, a->mom, a->q,
+                blockIdx.x - off[c], 0);
 }
 
 }  // namespace avs

@@ -60,14 +60,20 @@ def blunt_body_field(ctr, radius, Ma, R, T_inf=1.0, rho_inf=1.0, seed=0, amp=0.0
     rng = np.random.default_rng(seed)
     D = ctr.shape[1]
     U_inf = Ma * math.sqrt(gamma * R * T_inf)
-    rr, ur, Tr = normal_shock(Ma, gamma)
+    rr, ur, Tr = normal_shock(max(Ma, 1.0), gamma)
     x = ctr[:, 0]
     y = np.sqrt(np.sum(ctr[:, 1:] ** 2, axis=1))
-    standoff = radius * 0.386 * math.exp(4.67 / (Ma * Ma))
-    Rc = radius * 1.386 * math.exp(1.8 / max(Ma - 1.0, 0.3) ** 0.75)
-    beta = math.asin(min(1.0, 1.0 / Ma))
+    if Ma <= 1.05:                       # subsonic: no bow shock, freestream plus wake
+        Ma_s = 1.05
+    else:
+        Ma_s = Ma
+    standoff = radius * 0.386 * math.exp(4.67 / (Ma_s * Ma_s))
+    Rc = radius * 1.386 * math.exp(1.8 / max(Ma_s - 1.0, 0.3) ** 0.75)
+    beta = math.asin(min(1.0, 1.0 / Ma_s))
     xs = -(radius + standoff) + Rc / math.tan(beta) ** 2 * (np.sqrt(1 + (y * math.tan(beta) / Rc) ** 2) - 1)
     a_sh = 0.5 * (1 + np.tanh((xs - x) / (0.05 * radius)))           # 1 upstream of shock
+    if Ma <= 1.05:
+        a_sh = np.where(x < 0, 1.0, a_sh)
     wake = 0.5 * (1 + np.tanh(x / (0.5 * radius))) * np.exp(-(y / (radius * (1.2 + 0.15 * np.maximum(x, 0)))) ** 2)
     rho_ps, T_ps, u_ps = rho_inf * rr, T_inf * Tr, U_inf * ur
     rho_w, T_w, u_w = 0.3 * rho_inf, 0.6 * T_ps, 0.2 * U_inf
@@ -144,3 +150,34 @@ def _cfl_dt(mesh, cfl, box):
     inner = lr[:, 1] >= 0
     np.maximum.at(amax, lr[inner, 1], mesh['face_area'][inner])
     return cfl * float(np.min(mesh['cell_vol'] / amax)) / box
+
+
+def batch_cases(seed=0, ncase=64):
+    """Independent 2-D cases for the batched form: Kn log-uniform in
+    [1e-3, 1], Ma uniform in [0.1, 6], cavity or cylinder with equal
+    probability, grid side uniform in {32..96}, quadtree with 16^2 roots and
+    3 levels, target step-0 leaf count log-uniform in [256, 16384].  Cylinder
+    velocity boxes follow the paper's sizing (Sec. 3.5): radius 4 sigma_0 with
+    T0 = Tinf (1 + (gamma-1)/2 Ma^2), centred at (0.4 Uinf, 0)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(ncase):
+        Kn = 10.0 ** rng.uniform(-3.0, 0.0)
+        Ma = rng.uniform(0.1, 6.0)
+        geo = 'cavity' if rng.random() < 0.5 else 'cylinder'
+        side = int(rng.integers(32, 97))
+        target = int(round(10.0 ** rng.uniform(math.log10(256), math.log10(16384))))
+        if geo == 'cavity':
+            lid = Ma * math.sqrt(5.0 / 3.0)
+            cfg = cavity(n=side, Ma=Ma, Kn=Kn, omega=0.5, box=5.0 + lid, base=16, max_level=3)
+        else:
+            gamma, R = 5.0 / 3.0, 0.5
+            T0 = 1.0 + 0.5 * (gamma - 1.0) * Ma * Ma
+            rdv = 4.0 * math.sqrt(R * T0)
+            cx = 0.4 * Ma * math.sqrt(gamma * R)
+            cfg = cylinder(nr=side, nth=side, Ma=Ma, Kn=Kn, box=rdv, base=16, max_level=3, seed=seed * 1000 + c)
+            cfg['vspace'] = dict(dim=2, lo=(cx - rdv, -rdv), hi=(cx + rdv, rdv), base=(16, 16), max_level=3)
+            cfg['dt'] = _cfl_dt(cfg['mesh'], 0.8, cx + rdv)
+        cfg.update(case=c, Kn=Kn, Ma=Ma, geometry=geo, side=side, target_leaves=target)
+        out.append(cfg)
+    return out
