@@ -264,9 +264,17 @@ def run_batched(args):
         e1.record(stream)
         torch.cuda.synchronize()
         sweep_ms = e0.elapsed_time(e1) / args.nu
+        # the same cases one after another through the single-case entry point
+        e0.record(stream)
+        for cs in cases:
+            cs.step(args.nu)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        seq_ms = e0.elapsed_time(e1) / args.nu
         batch.close()
     return {"cycle_updates_per_s": updates / (ms * 1e-3), "sweep_updates_per_s": nodes / (sweep_ms * 1e-3),
-            "sweep_ms": sweep_ms, "cases": len(cases), "cell_leaf_nodes": nodes, "tuned_chunk": chunk,
+            "sweep_ms": sweep_ms, "sequential_sweep_updates_per_s": nodes / (seq_ms * 1e-3),
+            "sequential_sweep_ms": seq_ms, "cases": len(cases), "cell_leaf_nodes": nodes, "tuned_chunk": chunk,
             "workload": "64 seeded cavity/cylinder cases, Kn 1e-3..1, Ma 0.1..6, grids 32^2..96^2, "
                         "256..16k leaves, FP32, one graph per adaptation cycle"}
 
