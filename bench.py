@@ -149,6 +149,30 @@ def sweep_only(w, nsweep):
     return w.nc * nv * nsweep / (ms * 1e-3), ms / nsweep, nv
 
 
+def measured_traffic(tag, kernel):
+    """HBM bytes per (cell, leaf) node of ``kernel`` from the rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary kept in profiles/, or None when the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{tag}.md")
+    if not os.path.exists(path):
+        return None
+    sha, per = None, {}
+    for line in open(path):
+        f = line.split()
+        if len(f) == 2 and f[0] == "kernel_source_sha256":
+            sha = f[1]
+        elif len(f) == 6 and f[0] == "traffic_per_node":
+            per[f[1]] = float(f[3]) + float(f[5])
+    h = hashlib.sha256()
+    for name in ("avs_kernels.hip", "avs_internal.h"):
+        with open(os.path.join(ROOT, "paper_2212_05645_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    if sha != h.hexdigest():
+        return None
+    return per.get(kernel)
+
+
 def vdf_bytes_per_node(P, es, rows_per_cell):
     """Algorithmic HBM bytes per (cell, leaf) of one launch of each VDF
     kernel: every distinct byte it must read or write, once.  A leaf row of
@@ -319,8 +343,10 @@ def main():
     t_launch = prof[roof_k][0] / prof[roof_k][1] * 1e-3
     alg = bpn[roof_k] * w.nc * nv
     achieved = alg / t_launch
+    tpn = measured_traffic(f"cylinder_{args.precision}", roof_k)
     roofline = {"bound": "hbm", "kernel": roof_k, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None,
+                "frac": achieved / HBM_PEAK, "traffic": None if tpn is None else tpn * w.nc * nv / 1e9,
+                "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "bytes_per_launch": alg, "algorithmic_bytes_per_node": bpn[roof_k], "dominant_kernel": dom}
     for k in kern:
         if k in bpn:
