@@ -25,8 +25,8 @@ adaptive velocity space for general discrete velocity framework", arXiv
   criterion_e, criterion_mk), "consanguinity" remap (Sec. 3.2) and the
   conservation correction f = f' + g(W) - g(W') (Sec. 3.3).
 
-Readings of points the paper leaves open are listed in the design doc; each
-function below names the passage it follows.  Every array is float64.
+Where the paper leaves a point open, the docstring states the reading
+taken; each function below names the passage it follows.  Every array is float64.
 Nothing here is blocked, fused or reordered for speed: loops run over cells
 and faces, NumPy vectorises over the velocity axis only.
 """

@@ -7,7 +7,7 @@ each workload.  Nothing here evaluates a distribution function, a moment or a
 gas-model relation: the conversion to conserved variables and the viscosity
 law belong to the two implementations that consume these inputs.
 The published flow solutions are not available, so smooth analytic stand-ins
-with seeded perturbations are used; see the workload recipe in the design doc.
+with seeded perturbations are used.
 """
 from __future__ import annotations
 
@@ -92,7 +92,7 @@ def blunt_body_field(ctr, radius, Ma, R, T_inf=1.0, rho_inf=1.0, seed=0, amp=0.0
 
 
 # ---------------------------------------------------------------------------
-# Workload configurations (shapes of the paper's test cases; see DESIGN.md)
+# Workload configurations (shapes of the paper's test cases)
 # ---------------------------------------------------------------------------
 
 def cavity(n=32, Ma=0.16, Kn=0.075, omega=0.5, box=5.0, base=16, max_level=2, C1=0.01, cfl=0.8):
