@@ -219,6 +219,71 @@ avs_status avs_batch_check(avs_batch *batch);
 avs_status avs_batch_tune(avs_batch *batch, int32_t *chunk_host);
 void avs_batch_destroy(avs_batch *batch);
 
+/* Learned refinement proposal (not part of the paper; 2-D only).  A network
+ * predicts, for every leaf, the decision of the criterion of Sec. 3.4 after
+ * the brother-group rule of Sec. 3.1 (class 0 keep, 1 split, 2 merge) from
+ * 28 features: the leaf centre relative to the box centre over the box
+ * half-width (2), its width over the box width (1), level / max_level (1),
+ * and the lower quantiles at 0, 1/5, .., 1 (element j (ncells-1)/5 of the
+ * sorted values) of rho/rho_ref, U_x/sqrt(R T_ref), U_y/sqrt(R T_ref) and
+ * T/T_ref over the cells (24).  Network 28 -> 128 -> 128 -> 3, ReLU; inputs,
+ * weights and hidden activations in bfloat16 (nearest, ties to even), MFMA
+ * products accumulated in float32, biases and logits float32.  Training
+ * minimises the mean softmax cross-entropy with Adam; the backward deltas
+ * are rounded to bfloat16 where the forward rounds.
+ *
+ * Parameters: one float32 vector of avs_mlp_param_count() = 20611 values,
+ * W1 [28][128], b1 [128], W2 [128][128], b2 [128], W3 [128][3], b3 [3]
+ * (row-major, input index first).  The network's device state (parameters,
+ * Adam moments, bfloat16 weights, per-tile gradients for batches of up to
+ * max_batch samples) lives in caller memory of avs_mlp_state_bytes(max_batch)
+ * bytes; all its work runs on the stream given at creation.  Feature rows
+ * are bfloat16 [n][32] (28 used, the rest zero); labels are effective flags
+ * (-1 merge, 0 keep, +1 split) as avs_adapt writes them; rows_dev (int32
+ * [n], or NULL for 0..n-1) selects the dataset rows of a batch. */
+typedef struct avs_mlp avs_mlp;
+typedef struct {
+  double lr, beta1, beta2, eps;   /* Adam (Kingma and Ba, 2015) */
+} avs_adam;
+int64_t avs_mlp_param_count(void);
+size_t avs_mlp_state_bytes(int64_t max_batch);
+/* Copies params_host [20611]; rho_ref, T_ref normalise the field features. */
+avs_status avs_mlp_create(const float *params_host, int64_t max_batch, double rho_ref, double T_ref, void *state_dev,
+                          size_t state_bytes, void *hip_stream, avs_mlp **out);
+/* Parameters out / in (waits); set also clears the Adam moments and step. */
+avs_status avs_mlp_get_params(avs_mlp *mlp, float *params_host);
+avs_status avs_mlp_set_params(avs_mlp *mlp, const float *params_host);
+/* Logits [n][3] float32 of the feature rows (n <= max_batch not required). */
+avs_status avs_mlp_forward(avs_mlp *mlp, const uint16_t *feat_dev, int64_t n, float *logits_dev);
+/* Mean loss (loss_host, waits; NULL to skip) and its gradient grad_dev
+ * [20611] float32 over a batch of n <= max_batch rows. */
+avs_status avs_mlp_grad(avs_mlp *mlp, const uint16_t *feat_dev, const int8_t *flags_dev, const int32_t *rows_dev,
+                        int64_t n, float *grad_dev, double *loss_host);
+/* One Adam step with a given gradient grad_dev [20611]. */
+avs_status avs_mlp_adam(avs_mlp *mlp, const float *grad_dev, const avs_adam *hp);
+/* avs_mlp_grad into the state's own buffer, then avs_mlp_adam. */
+avs_status avs_mlp_train_step(avs_mlp *mlp, const uint16_t *feat_dev, const int8_t *flags_dev, const int32_t *rows_dev,
+                              int64_t n, const avs_adam *hp, double *loss_host);
+void avs_mlp_destroy(avs_mlp *mlp);
+
+/* Feature rows of the context's current leaves into feat_dev [nleaves][32]
+ * (enqueued on the context's stream). */
+avs_status avs_features(avs_ctx *ctx, const avs_mlp *mlp, uint16_t *feat_dev);
+
+/* Adaptation with the learned proposal: features, network, arg max (lowest
+ * class on ties; split only below max_level, merge only above the roots),
+ * the brother-group rule, the new leaf list and remap plan.  Judge: for each
+ * probe state (the nprobes given primitive rows, then the cells holding the
+ * minimum and the maximum of rho, U_x, U_y and T, lowest index on ties) the
+ * relative error of the discrete density and energy of its Maxwellian on the
+ * proposed leaves must not exceed tail_tol; otherwise, or if the proposal
+ * would exceed leaf_capacity, the plain criterion (avs_adapt with C1, C2 and
+ * the same probes) decides.  *fallback_host = 1 when it did.  Outputs and
+ * errors as avs_adapt; waits for the network's stream first. */
+avs_status avs_adapt_learned(avs_ctx *ctx, avs_mlp *mlp, double C1, double C2, const double *probes_host,
+                             int32_t nprobes, double tail_tol, int8_t *flags_dev, int64_t *n_new_host,
+                             int32_t *fallback_host);
+
 /* Release the context (never frees caller memory). */
 void avs_destroy(avs_ctx *ctx);
 

@@ -24,7 +24,10 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_moments", "avs_adapt", "avs_remap", "avs_leaves", "avs_plan", "avs_criterion",
            "avs_set_leaves", "avs_get_state", "avs_set_state", "avs_get_cells", "avs_profile",
            "avs_profile_read", "avs_batch_workspace_bytes", "avs_batch_create", "avs_batch_step",
-           "avs_batch_check", "avs_batch_tune", "avs_batch_destroy", "avs_destroy", "avs_last_error")
+           "avs_batch_check", "avs_batch_tune", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
+           "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
+           "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
+           "avs_destroy", "avs_last_error")
 
 
 class avs_vspace(C.Structure):
@@ -46,6 +49,10 @@ class avs_pmesh(C.Structure):
 
 class avs_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dt", C.c_double), ("venkat_K", C.c_double)]
+
+
+class avs_adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
 
 
 def _load():
@@ -78,6 +85,18 @@ def _load():
         "avs_batch_check": (I32, [VP]),
         "avs_batch_tune": (I32, [VP, P(I32)]),
         "avs_batch_destroy": (None, [VP]),
+        "avs_mlp_param_count": (I64, []),
+        "avs_mlp_state_bytes": (C.c_size_t, [I64]),
+        "avs_mlp_create": (I32, [VP, I64, D, D, VP, C.c_size_t, VP, P(VP)]),
+        "avs_mlp_get_params": (I32, [VP, VP]),
+        "avs_mlp_set_params": (I32, [VP, VP]),
+        "avs_mlp_forward": (I32, [VP, VP, I64, VP]),
+        "avs_mlp_grad": (I32, [VP, VP, VP, VP, I64, VP, VP]),
+        "avs_mlp_adam": (I32, [VP, VP, P(avs_adam)]),
+        "avs_mlp_train_step": (I32, [VP, VP, VP, VP, I64, P(avs_adam), VP]),
+        "avs_mlp_destroy": (None, [VP]),
+        "avs_features": (I32, [VP, VP, VP]),
+        "avs_adapt_learned": (I32, [VP, VP, D, D, VP, I32, D, VP, P(I64), P(I32)]),
         "avs_destroy": (None, [VP]),
         "avs_last_error": (C.c_char_p, []),
     }
@@ -187,15 +206,44 @@ class Case:
         _check(lib.avs_moments(self.ctx, f.data_ptr() if f is not None else None, _ptr(t)))
         return f, t
 
-    def adapt(self, C1, C2, probes=None):
+    def adapt(self, C1, C2, probes=None, flags_out=None):
+        """Plain adaptation.  Returns (effective flags as numpy, n_new); with
+        ``flags_out`` (device int8 tensor of >= nleaves entries) the flags
+        stay on the device and None is returned in their place."""
         n_old = self.nleaves()
-        flags = self._torch.empty(max(n_old, 1), dtype=self._torch.int8, device=self.device)
+        flags = flags_out if flags_out is not None else self._torch.empty(max(n_old, 1), dtype=self._torch.int8,
+                                                                           device=self.device)
         pr = np.ascontiguousarray(probes, dtype=np.float64) if probes is not None else None
         nn = C.c_int64()
         _check(lib.avs_adapt(self.ctx, float(C1), float(C2), _ptr(pr), 0 if pr is None else len(pr),
                              flags.data_ptr(), C.byref(nn)))
+        if flags_out is not None:
+            return None, nn.value
         self._torch.cuda.synchronize(self.device)
         return flags[:n_old].cpu().numpy(), nn.value
+
+    def features(self, mlp, out=None):
+        """Feature rows of the current leaves, int16 tensor [nleaves, 32]
+        holding bfloat16 bit patterns (written on this case's stream)."""
+        n = self.nleaves()
+        if out is None:
+            out = self._torch.empty((max(n, 1), 32), dtype=self._torch.int16, device=self.device)
+        _check(lib.avs_features(self.ctx, mlp.h, out.data_ptr()))
+        return out[:n]
+
+    def adapt_learned(self, mlp, C1, C2, probes=None, tail_tol=1e-4, flags_out=None):
+        """Adaptation with the learned proposal; returns (flags or None, n_new, fallback)."""
+        n_old = self.nleaves()
+        flags = flags_out if flags_out is not None else self._torch.empty(max(n_old, 1), dtype=self._torch.int8,
+                                                                           device=self.device)
+        pr = np.ascontiguousarray(probes, dtype=np.float64) if probes is not None else None
+        nn, fb = C.c_int64(), C.c_int32()
+        _check(lib.avs_adapt_learned(self.ctx, mlp.h, float(C1), float(C2), _ptr(pr), 0 if pr is None else len(pr),
+                                     float(tail_tol), flags.data_ptr(), C.byref(nn), C.byref(fb)))
+        if flags_out is not None:
+            return None, nn.value, bool(fb.value)
+        self._torch.cuda.synchronize(self.device)
+        return flags[:n_old].cpu().numpy(), nn.value, bool(fb.value)
 
     def remap(self, correction=2):
         _check(lib.avs_remap(self.ctx, int(correction)))
@@ -275,6 +323,80 @@ class Case:
         if getattr(self, "ctx", None):
             lib.avs_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The learned refinement proposal's network and its device state."""
+
+    def __init__(self, params, max_batch=16384, rho_ref=1.0, T_ref=1.0, device="cuda:0", stream=None):
+        import torch
+        self._torch = torch
+        self.device = torch.device(device)
+        self.nparam = int(lib.avs_mlp_param_count())
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (self.nparam,):
+            raise AvsError(AVS_E_INVALID, f"expected {self.nparam} parameters")
+        nb = lib.avs_mlp_state_bytes(int(max_batch))
+        if nb == 0:
+            raise AvsError(AVS_E_INVALID, lib.avs_last_error().decode())
+        self.state = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.max_batch = int(max_batch)
+        h = C.c_void_p()
+        _check(lib.avs_mlp_create(p.ctypes.data, int(max_batch), float(rho_ref), float(T_ref), self.state.data_ptr(),
+                                  nb, self.stream.cuda_stream, C.byref(h)))
+        self.h = h
+
+    def get_params(self):
+        p = np.zeros(self.nparam, np.float32)
+        _check(lib.avs_mlp_get_params(self.h, p.ctypes.data))
+        return p
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib.avs_mlp_set_params(self.h, p.ctypes.data))
+
+    def forward(self, feat, n=None):
+        n = feat.shape[0] if n is None else int(n)
+        out = self._torch.empty((max(n, 1), 3), dtype=self._torch.float32, device=self.device)
+        _check(lib.avs_mlp_forward(self.h, feat.data_ptr(), n, out.data_ptr()))
+        return out[:n]
+
+    def grad(self, feat, flags, rows=None, n=None):
+        n = (rows.shape[0] if rows is not None else feat.shape[0]) if n is None else int(n)
+        g = self._torch.empty(self.nparam, dtype=self._torch.float32, device=self.device)
+        loss = C.c_double()
+        _check(lib.avs_mlp_grad(self.h, feat.data_ptr(), flags.data_ptr(), None if rows is None else rows.data_ptr(),
+                                n, g.data_ptr(), C.byref(loss)))
+        return g, loss.value
+
+    @staticmethod
+    def _hp(lr, beta1, beta2, eps):
+        return avs_adam(lr=float(lr), beta1=float(beta1), beta2=float(beta2), eps=float(eps))
+
+    def adam(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        hp = self._hp(lr, beta1, beta2, eps)
+        _check(lib.avs_mlp_adam(self.h, grad.data_ptr(), C.byref(hp)))
+
+    def train_step(self, feat, flags, rows=None, n=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss=False):
+        n = (rows.shape[0] if rows is not None else feat.shape[0]) if n is None else int(n)
+        hp = self._hp(lr, beta1, beta2, eps)
+        out = C.c_double()
+        _check(lib.avs_mlp_train_step(self.h, feat.data_ptr(), flags.data_ptr(),
+                                      None if rows is None else rows.data_ptr(), n, C.byref(hp),
+                                      C.byref(out) if loss else None))
+        return out.value if loss else None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.avs_mlp_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

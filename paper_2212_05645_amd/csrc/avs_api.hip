@@ -12,6 +12,7 @@
 
 #include "../../include/avs.h"
 #include "avs_kernels.hip"
+#include "avs_mlp.hip"
 
 using namespace avs;
 
@@ -83,6 +84,8 @@ struct avs_ctx {
   double *cc, *crit_part, *Mk, *probe_cc, *probe_prim;
   int8_t *raw, *eff;
   int *cnt, *off, *pkind, *psrc, *pchild, *bad;
+  uint16_t* feat = nullptr;                      // learned proposal (2-D): feature rows [cap][32]
+  double *quant = nullptr, *tprobe = nullptr, *terr = nullptr;
   int ngrp;
   int nprobe_max = 64;
   int plan_n = 0;
@@ -112,10 +115,10 @@ struct avs_ctx {
 namespace {
 
 enum KernelId { K_PASSA, K_FACE, K_FACE_EQFLUX, K_MACRO, K_TARGET, K_PASSC, K_RESIDUAL, K_CRITERION,
-                K_FLAGS, K_REMAP_GATHER, K_REMAP_CORRECT, K_BC_TABLES, K_MOMENTS, K_INIT, K_NKERNELS };
+                K_FLAGS, K_REMAP_GATHER, K_REMAP_CORRECT, K_BC_TABLES, K_MOMENTS, K_INIT, K_LEARNED, K_NKERNELS };
 const char* const kKernelNames[K_NKERNELS] = {"passA", "face", "face_eqflux", "macro", "target", "passC",
                                               "residual", "criterion", "flags_plan", "remap_gather",
-                                              "remap_correct", "bc_tables", "moments", "init_vdf"};
+                                              "remap_correct", "bc_tables", "moments", "init_vdf", "learned"};
 
 hipEvent_t next_event(avs_ctx* ctx) {
   if (ctx->evused == ctx->evpool.size()) {
@@ -254,6 +257,12 @@ void carve(avs_ctx& x, Carver& c) {
   x.psrc = c.take<int>(cap);
   x.pchild = c.take<int>(cap);
   x.bad = c.take<int>(4);
+  if (D == 2) {
+    x.feat = c.take<uint16_t>(cap * mlp::NINP);
+    x.quant = c.take<double>(24);
+    x.tprobe = c.take<double>((size_t)(x.nprobe_max + 8) * 4);
+    x.terr = c.take<double>((size_t)x.nprobe_max + 8);
+  }
 }
 
 void fill_dims(avs_ctx& x, const avs_vspace* vs, const avs_pmesh* pm, const avs_opts* op) {
@@ -982,12 +991,9 @@ avs_status avs_moments(avs_ctx* ctx, double* fields_dev, double* totals_host) {
   return AVS_OK;
 }
 
-avs_status avs_adapt(avs_ctx* ctx, double C1, double C2, const double* probes_host, int32_t nprobes, int8_t* flags_dev,
-                     int64_t* n_new_host) {
-  if (avs_status st = guard(ctx)) return st;
+static avs_status upload_probes(avs_ctx* ctx, const double* probes_host, int32_t nprobes) {
   if (nprobes < 0 || nprobes > ctx->nprobe_max) return fail(AVS_E_INVALID, "nprobes must be in [0, %d]", ctx->nprobe_max);
   if (nprobes > 0 && !probes_host) return fail(AVS_E_INVALID, "probes_host is null");
-  if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
   const int D = ctx->D, N = D + 2;
   std::vector<double> pcc((size_t)std::max(nprobes, 1) * N), Wp(N);
   for (int p = 0; p < nprobes; ++p) {
@@ -996,20 +1002,31 @@ avs_status avs_adapt(avs_ctx* ctx, double C1, double C2, const double* probes_ho
     conserved_host(D, ctx->gas.R, pr, Wp.data());
     crit_consts_host(D, Wp.data(), &pcc[(size_t)p * N]);
   }
-  ctx->plan_valid = false;
   if (nprobes > 0) {
     CK(hipMemcpyAsync(ctx->probe_cc, pcc.data(), sizeof(double) * nprobes * N, hipMemcpyHostToDevice, ctx->stream));
     CK(hipMemcpyAsync(ctx->probe_prim, probes_host, sizeof(double) * nprobes * N, hipMemcpyHostToDevice, ctx->stream));
   }
-  if (avs_status st = DISPATCH(ctx, launch_adapt, ctx, C1, C2, nprobes)) return st;
+  return AVS_OK;
+}
+
+// After the effective flags and their scan: new leaf count, capacity check,
+// new leaf table and remap plan.  capacity_ok == nullptr: exceeding the
+// capacity is an error; otherwise it is reported there and nothing is built.
+static avs_status finish_plan(avs_ctx* ctx, int8_t* flags_dev, int64_t* n_new_host, bool* capacity_ok = nullptr) {
   int n_new = 0;
   const int n_old = ctx->nleaf[ctx->lcur];
   CK(hipMemcpyAsync(&n_new, ctx->off + n_old, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   if (flags_dev) CK(hipMemcpyAsync(flags_dev, ctx->eff, n_old, hipMemcpyDeviceToDevice, ctx->stream));
   CK(hipStreamSynchronize(ctx->stream));
   if (n_new_host) *n_new_host = n_new;
-  if (n_new > ctx->cap)
+  if (n_new > ctx->cap) {
+    if (capacity_ok) {
+      *capacity_ok = false;
+      return AVS_OK;
+    }
     return fail(AVS_E_CAPACITY, "adaptation would produce %d leaves > leaf_capacity %" PRId64, n_new, ctx->cap);
+  }
+  if (capacity_ok) *capacity_ok = true;
   const int t = ctx->lcur ^ 1;
   ctx->nleaf[t] = n_new;
   ctx->ld[t] = (int)round_up(n_new, 64);
@@ -1018,6 +1035,16 @@ avs_status avs_adapt(avs_ctx* ctx, double C1, double C2, const double* probes_ho
   ctx->plan_n = n_new;
   ctx->plan_valid = true;
   return AVS_OK;
+}
+
+avs_status avs_adapt(avs_ctx* ctx, double C1, double C2, const double* probes_host, int32_t nprobes, int8_t* flags_dev,
+                     int64_t* n_new_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
+  if (avs_status st = upload_probes(ctx, probes_host, nprobes)) return st;
+  ctx->plan_valid = false;
+  if (avs_status st = DISPATCH(ctx, launch_adapt, ctx, C1, C2, nprobes)) return st;
+  return finish_plan(ctx, flags_dev, n_new_host);
 }
 
 avs_status avs_remap(avs_ctx* ctx, int32_t correction) {
@@ -1307,6 +1334,292 @@ avs_status avs_batch_tune(avs_batch* b, int32_t* chunk_host) {
 }
 
 void avs_batch_destroy(avs_batch* b) { delete b; }
+
+// ------------------------------------------------------------ learned proposal
+struct avs_mlp {
+  float *prm, *m, *v, *grad;
+  uint16_t* wbf;
+  float* gpart;
+  double *lossp, *loss;
+  int64_t max_batch;
+  int maxtile;
+  double rho_ref, T_ref;
+  hipStream_t stream;
+  int64_t t = 0;
+  bool failed = false;
+};
+
+static void mlp_carve(avs_mlp& x, Carver& c) {
+  using namespace mlp;
+  x.prm = c.take<float>(NPARAM);
+  x.m = c.take<float>(NPARAM);
+  x.v = c.take<float>(NPARAM);
+  x.grad = c.take<float>(NPARAM);
+  x.wbf = c.take<uint16_t>(PWN);
+  x.gpart = c.take<float>((size_t)x.maxtile * GN);
+  x.lossp = c.take<double>(x.maxtile);
+  x.loss = c.take<double>(1);
+}
+
+#define MCK(expr)                                                                                  \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) {                                                                        \
+      mlp->failed = true;                                                                          \
+      return fail(AVS_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    }                                                                                              \
+  } while (0)
+
+static avs_status mlp_guard(const avs_mlp* mlp) {
+  if (!mlp) return fail(AVS_E_INVALID, "null network");
+  if (mlp->failed) return fail(AVS_E_STATE, "network is in the failed state after an earlier device error");
+  return AVS_OK;
+}
+
+// Dynamic LDS above the default limit for the fused tile kernel.
+static hipError_t mlp_lds_attr() {
+  using namespace mlp;
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_mlp_tile<FWD_LOGITS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)LDS_BYTES);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_mlp_tile<FWD_FLAGS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_BYTES);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_mlp_tile<TRAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_BYTES);
+  done = e == hipSuccess;
+  return e;
+}
+
+static avs_status mlp_upload(avs_mlp* mlp, const float* params_host) {
+  using namespace mlp;
+  MCK(hipMemcpyAsync(mlp->prm, params_host, sizeof(float) * NPARAM, hipMemcpyHostToDevice, mlp->stream));
+  MCK(hipMemsetAsync(mlp->m, 0, sizeof(float) * NPARAM, mlp->stream));
+  MCK(hipMemsetAsync(mlp->v, 0, sizeof(float) * NPARAM, mlp->stream));
+  k_mlp_pack<<<(PWN + TPB - 1) / TPB, TPB, 0, mlp->stream>>>(mlp->prm, mlp->wbf);
+  MCK(hipGetLastError());
+  MCK(hipStreamSynchronize(mlp->stream));
+  mlp->t = 0;
+  return AVS_OK;
+}
+
+static avs_status mlp_grad_into(avs_mlp* mlp, const uint16_t* feat, const int8_t* flags, const int32_t* rows, int64_t n,
+                                float* grad) {
+  using namespace mlp;
+  const int nt = (int)((n + TILE - 1) / TILE);
+  MCK(mlp_lds_attr());
+  k_mlp_tile<TRAIN><<<nt, TPB, LDS_BYTES, mlp->stream>>>((int)n, feat, rows, mlp->wbf, mlp->prm, nullptr, nullptr, 0,
+                                                         nullptr, flags, (float)(1.0 / (double)n), mlp->gpart,
+                                                         mlp->lossp);
+  MCK(hipGetLastError());
+  k_mlp_reduce<<<(NPARAM + TPB - 1) / TPB, TPB, 0, mlp->stream>>>(nt, mlp->gpart, mlp->lossp, 1.0 / (double)n, grad,
+                                                                  mlp->loss);
+  MCK(hipGetLastError());
+  return AVS_OK;
+}
+
+static avs_status mlp_check_batch(const avs_mlp* mlp, const uint16_t* feat, const int8_t* flags, int64_t n) {
+  if (!feat || !flags) return fail(AVS_E_INVALID, "null features or labels");
+  if (n < 1 || n > mlp->max_batch) return fail(AVS_E_INVALID, "batch of %" PRId64 " rows outside [1, %" PRId64 "]", n, mlp->max_batch);
+  return AVS_OK;
+}
+
+static avs_status mlp_check_adam(const avs_adam* hp) {
+  if (!hp) return fail(AVS_E_INVALID, "null Adam parameters");
+  if (!(hp->lr > 0) || !(hp->beta1 >= 0 && hp->beta1 < 1) || !(hp->beta2 >= 0 && hp->beta2 < 1) || !(hp->eps > 0))
+    return fail(AVS_E_INVALID, "Adam parameters need lr > 0, 0 <= beta < 1, eps > 0");
+  return AVS_OK;
+}
+
+static avs_status mlp_adam_launch(avs_mlp* mlp, const float* grad, const avs_adam* hp) {
+  using namespace mlp;
+  const int64_t t = mlp->t + 1;
+  const double c1 = 1.0 / (1.0 - std::pow(hp->beta1, (double)t)), c2 = 1.0 / (1.0 - std::pow(hp->beta2, (double)t));
+  k_mlp_adam<<<(NPARAM + TPB - 1) / TPB, TPB, 0, mlp->stream>>>(grad, mlp->prm, mlp->m, mlp->v, hp->lr, hp->beta1,
+                                                                hp->beta2, hp->eps, c1, c2, mlp->wbf);
+  MCK(hipGetLastError());
+  k_mlp_pack<<<(PWN + TPB - 1) / TPB, TPB, 0, mlp->stream>>>(mlp->prm, mlp->wbf);
+  MCK(hipGetLastError());
+  mlp->t = t;
+  return AVS_OK;
+}
+
+int64_t avs_mlp_param_count(void) { return mlp::NPARAM; }
+
+size_t avs_mlp_state_bytes(int64_t max_batch) {
+  if (max_batch < 1 || max_batch > ((int64_t)1 << 26)) {
+    fail(AVS_E_INVALID, "max_batch must be in [1, 2^26]");
+    return 0;
+  }
+  avs_mlp x{};
+  x.maxtile = (int)((max_batch + mlp::TILE - 1) / mlp::TILE);
+  Carver c{nullptr};
+  mlp_carve(x, c);
+  return c.off;
+}
+
+avs_status avs_mlp_create(const float* params_host, int64_t max_batch, double rho_ref, double T_ref, void* state_dev,
+                          size_t state_bytes, void* hip_stream, avs_mlp** out) {
+  if (!out) return fail(AVS_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!params_host || !state_dev) return fail(AVS_E_INVALID, "null parameters or state");
+  const size_t need = avs_mlp_state_bytes(max_batch);
+  if (need == 0) return AVS_E_INVALID;
+  if (state_bytes < need) return fail(AVS_E_INVALID, "network state too small (%zu < %zu)", state_bytes, need);
+  if ((uintptr_t)state_dev % 256) return fail(AVS_E_INVALID, "network state must be 256-byte aligned");
+  if (!(rho_ref > 0) || !(T_ref > 0)) return fail(AVS_E_INVALID, "rho_ref and T_ref must be positive");
+  avs_mlp* mlp = new avs_mlp();
+  mlp->max_batch = max_batch;
+  mlp->maxtile = (int)((max_batch + mlp::TILE - 1) / mlp::TILE);
+  mlp->rho_ref = rho_ref;
+  mlp->T_ref = T_ref;
+  mlp->stream = (hipStream_t)hip_stream;
+  Carver c{(char*)state_dev};
+  mlp_carve(*mlp, c);
+  if (avs_status st = mlp_upload(mlp, params_host)) {
+    delete mlp;
+    return st;
+  }
+  *out = mlp;
+  return AVS_OK;
+}
+
+avs_status avs_mlp_get_params(avs_mlp* mlp, float* params_host) {
+  if (avs_status st = mlp_guard(mlp)) return st;
+  if (!params_host) return fail(AVS_E_INVALID, "params_host is null");
+  MCK(hipMemcpyAsync(params_host, mlp->prm, sizeof(float) * mlp::NPARAM, hipMemcpyDeviceToHost, mlp->stream));
+  MCK(hipStreamSynchronize(mlp->stream));
+  return AVS_OK;
+}
+
+avs_status avs_mlp_set_params(avs_mlp* mlp, const float* params_host) {
+  if (avs_status st = mlp_guard(mlp)) return st;
+  if (!params_host) return fail(AVS_E_INVALID, "params_host is null");
+  return mlp_upload(mlp, params_host);
+}
+
+avs_status avs_mlp_forward(avs_mlp* mlp, const uint16_t* feat_dev, int64_t n, float* logits_dev) {
+  using namespace mlp;
+  if (avs_status st = mlp_guard(mlp)) return st;
+  if (!feat_dev || !logits_dev) return fail(AVS_E_INVALID, "null features or logits");
+  if (n < 0 || n > INT32_MAX - TILE) return fail(AVS_E_INVALID, "n outside [0, 2^31 - 64]");
+  if (n == 0) return AVS_OK;
+  MCK(mlp_lds_attr());
+  k_mlp_tile<FWD_LOGITS><<<(int)((n + TILE - 1) / TILE), TPB, LDS_BYTES, mlp->stream>>>(
+      (int)n, feat_dev, nullptr, mlp->wbf, mlp->prm, logits_dev, nullptr, 0, nullptr, nullptr, 0.f, nullptr, nullptr);
+  MCK(hipGetLastError());
+  return AVS_OK;
+}
+
+avs_status avs_mlp_grad(avs_mlp* mlp, const uint16_t* feat_dev, const int8_t* flags_dev, const int32_t* rows_dev,
+                        int64_t n, float* grad_dev, double* loss_host) {
+  if (avs_status st = mlp_guard(mlp)) return st;
+  if (avs_status st = mlp_check_batch(mlp, feat_dev, flags_dev, n)) return st;
+  if (!grad_dev) return fail(AVS_E_INVALID, "grad_dev is null");
+  if (avs_status st = mlp_grad_into(mlp, feat_dev, flags_dev, rows_dev, n, grad_dev)) return st;
+  if (loss_host) {
+    MCK(hipMemcpyAsync(loss_host, mlp->loss, sizeof(double), hipMemcpyDeviceToHost, mlp->stream));
+    MCK(hipStreamSynchronize(mlp->stream));
+  }
+  return AVS_OK;
+}
+
+avs_status avs_mlp_adam(avs_mlp* mlp, const float* grad_dev, const avs_adam* hp) {
+  if (avs_status st = mlp_guard(mlp)) return st;
+  if (!grad_dev) return fail(AVS_E_INVALID, "grad_dev is null");
+  if (avs_status st = mlp_check_adam(hp)) return st;
+  return mlp_adam_launch(mlp, grad_dev, hp);
+}
+
+avs_status avs_mlp_train_step(avs_mlp* mlp, const uint16_t* feat_dev, const int8_t* flags_dev, const int32_t* rows_dev,
+                              int64_t n, const avs_adam* hp, double* loss_host) {
+  if (avs_status st = mlp_guard(mlp)) return st;
+  if (avs_status st = mlp_check_batch(mlp, feat_dev, flags_dev, n)) return st;
+  if (avs_status st = mlp_check_adam(hp)) return st;
+  if (avs_status st = mlp_grad_into(mlp, feat_dev, flags_dev, rows_dev, n, mlp->grad)) return st;
+  if (avs_status st = mlp_adam_launch(mlp, mlp->grad, hp)) return st;
+  if (loss_host) {
+    MCK(hipMemcpyAsync(loss_host, mlp->loss, sizeof(double), hipMemcpyDeviceToHost, mlp->stream));
+    MCK(hipStreamSynchronize(mlp->stream));
+  }
+  return AVS_OK;
+}
+
+void avs_mlp_destroy(avs_mlp* mlp) { delete mlp; }
+
+static avs_status launch_features(avs_ctx* ctx, const avs_mlp* mlp, uint16_t* feat) {
+  using namespace mlp;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const double c_ref = std::sqrt(ctx->gas.R * mlp->T_ref);
+  k_quantiles<<<24, TPB, 0, ctx->stream>>>(ctx->nc, ctx->W, ctx->gas.R, mlp->rho_ref, c_ref, mlp->T_ref, ctx->quant);
+  CKL();
+  k_features<<<(L.n + TPB - 1) / TPB, TPB, 0, ctx->stream>>>(L, ctx->base[0], ctx->base[1], ctx->lmax, ctx->quant, feat);
+  CKL();
+  return AVS_OK;
+}
+
+avs_status avs_features(avs_ctx* ctx, const avs_mlp* mlp, uint16_t* feat_dev) {
+  if (avs_status st = guard(ctx)) return st;
+  if (avs_status st = mlp_guard(mlp)) return st;
+  if (ctx->D != 2) return fail(AVS_E_INVALID, "the learned proposal is defined for 2-D velocity spaces only");
+  if (!feat_dev) return fail(AVS_E_INVALID, "feat_dev is null");
+  return launch_features(ctx, mlp, feat_dev);
+}
+
+avs_status avs_adapt_learned(avs_ctx* ctx, avs_mlp* mlp, double C1, double C2, const double* probes_host,
+                             int32_t nprobes, double tail_tol, int8_t* flags_dev, int64_t* n_new_host,
+                             int32_t* fallback_host) {
+  using namespace mlp;
+  if (avs_status st = guard(ctx)) return st;
+  if (avs_status st = mlp_guard(mlp)) return st;
+  if (ctx->D != 2) return fail(AVS_E_INVALID, "the learned proposal is defined for 2-D velocity spaces only");
+  if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
+  if (!(tail_tol >= 0)) return fail(AVS_E_INVALID, "tail_tol must be >= 0");
+  if (avs_status st = upload_probes(ctx, probes_host, nprobes)) return st;
+  if (mlp->stream != ctx->stream) MCK(hipStreamSynchronize(mlp->stream));
+  ctx->plan_valid = false;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int nb = (L.n + BLOCK - 1) / BLOCK;
+  {
+    ProfScope ps(ctx, K_LEARNED);
+    if (avs_status st = launch_features(ctx, mlp, ctx->feat)) return st;
+    CK(mlp_lds_attr());
+    k_mlp_tile<FWD_FLAGS><<<(L.n + TILE - 1) / TILE, TPB, LDS_BYTES, ctx->stream>>>(
+        L.n, ctx->feat, nullptr, mlp->wbf, mlp->prm, nullptr, L.level, ctx->lmax, ctx->raw, nullptr, 0.f, nullptr,
+        nullptr);
+    CKL();
+    k_resolve<2><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
+    CKL();
+    k_scan<<<1, BLOCK, 0, ctx->stream>>>(L.n, ctx->cnt, ctx->off);
+    CKL();
+  }
+  bool fits = false;
+  if (avs_status st = finish_plan(ctx, flags_dev, n_new_host, &fits)) return st;
+  bool accept = false;
+  if (fits) {
+    // judge on the proposed leaves
+    const int np = nprobes + 8;
+    if (nprobes > 0)
+      for (int p = 0; p < nprobes; ++p)
+        CK(hipMemcpyAsync(ctx->tprobe + (size_t)p * 4, probes_host + (size_t)p * 4, sizeof(double) * 4,
+                          hipMemcpyHostToDevice, ctx->stream));
+    k_extremes<<<8, TPB, 0, ctx->stream>>>(ctx->nc, ctx->W, ctx->gas.R, ctx->tprobe + (size_t)nprobes * 4);
+    CKL();
+    k_tail<<<np, TPB, 0, ctx->stream>>>(ctx->leaves(ctx->lcur ^ 1), ctx->tprobe, ctx->gas.R, ctx->terr);
+    CKL();
+    std::vector<double> err(np);
+    CK(hipMemcpyAsync(err.data(), ctx->terr, sizeof(double) * np, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    accept = true;
+    for (int p = 0; p < np; ++p)
+      if (!(err[p] <= tail_tol)) accept = false;
+  }
+  if (fallback_host) *fallback_host = accept ? 0 : 1;
+  if (accept) return AVS_OK;
+  ctx->plan_valid = false;
+  if (avs_status st = DISPATCH(ctx, launch_adapt, ctx, C1, C2, nprobes)) return st;
+  return finish_plan(ctx, flags_dev, n_new_host);
+}
 
 void avs_destroy(avs_ctx* ctx) {
   if (!ctx) return;

@@ -1,0 +1,230 @@
+"""Learned refinement proposal on the GPU (through the C ABI) against its FP64
+oracle on identical seeded inputs.
+
+Tolerances.  Features: both sides round the same float64 expression to
+bfloat16, so they agree bit for bit except where the two float64 values
+straddle a rounding boundary (at most one bfloat16 ulp, on a vanishing
+fraction of entries).  Network: the kernel accumulates in float32 where the
+oracle accumulates in float64; hidden activations are rounded to bfloat16 on
+both sides, so a float32 accumulation error of ~1e-7 relative flips a
+rounding with probability ~1e-7 / 2^-8 per activation: logits agree to
+~1e-6 of their scale on 99% of rows and to a few 1e-3 on the rest, and
+per-tensor gradients to 1e-3 relative (L2).  Adam: float32 storage of
+p, m, v against float64, 1e-6 relative.  Integer decisions (flags, plan)
+are compared where the oracle's decision is not within a rounding margin.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from oracle import avs_oracle as O
+from oracle import mlp_oracle as M
+from workloads import fields as F
+
+from test_gpu_parity import make_pair, resolved_tree
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def avs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_05645_amd import avs as mod
+    return mod
+
+
+def small_cylinder():
+    return F.cylinder(nr=8, nth=32, Ma=3.0, box=8.0, base=16, max_level=2, r1=2.5, first=0.1, seed=4)
+
+
+def params(seed, bias=0.1):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shp in M.SHAPES:
+        if len(shp) == 2:
+            b = math.sqrt(6.0 / shp[0])
+            parts.append(rng.uniform(-b, b, shp[0] * shp[1]))
+        else:
+            parts.append(rng.uniform(-bias, bias, shp[0]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def to_bits(x):
+    """float64 values already representable in bfloat16 -> int16 bit patterns."""
+    u = (np.asarray(x, np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    return u.view(np.int16)
+
+
+def from_bits(b):
+    return (np.asarray(b).view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t.to(dtype) if dtype is not None else t).to("cuda:0")
+
+
+def test_features_match_oracle(avs):
+    c = small_cylinder()
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=resolved_tree(c['vspace'], 3))
+    mlp = avs.Mlp(params(0), max_batch=1024, rho_ref=1.2, T_ref=1.5)
+    f = cs.features(mlp).cpu().numpy()
+    assert f.shape == (o.tree.n, 32)
+    assert np.all(f[:, 28:] == 0)
+    got = from_bits(f[:, :28])
+    prim = M.primitive_2d(o.W, o.gas.R)
+    ref = M.bf16_round(M.features(o.tree.level, o.tree.idx, o.tree.base, o.tree.max_level, prim, o.gas.R, 1.2, 1.5))
+    ulp = np.abs(f[:, :28].view(np.uint16).astype(np.int64) - to_bits(ref).view(np.uint16).astype(np.int64))
+    assert np.mean(got == ref) > 0.999
+    assert np.all(ulp <= 1)
+
+
+@pytest.mark.parametrize("n", [1, 64, 333])
+def test_forward_matches_oracle(avs, n):
+    p = params(1)
+    rng = np.random.default_rng(10 + n)
+    X = M.bf16_round(rng.uniform(-1.5, 1.5, (n, 28)))
+    Xb = np.zeros((n, 32), np.int16)
+    Xb[:, :28] = to_bits(X)
+    mlp = avs.Mlp(p, max_batch=512)
+    z = mlp.forward(dev(Xb)).cpu().numpy().astype(np.float64)
+    zr, _ = M.forward(p.astype(np.float64), X)
+    scale = float(np.max(np.abs(zr)))
+    err = np.max(np.abs(z - zr), axis=1) / scale
+    assert np.quantile(err, 0.99) <= 1e-5
+    assert np.max(err) <= 5e-3
+
+
+def test_gradient_matches_oracle(avs):
+    p = params(2)
+    rng = np.random.default_rng(11)
+    n = 301
+    X = M.bf16_round(rng.uniform(-1.5, 1.5, (n, 28)))
+    flags = rng.choice(np.array([-1, 0, 1], np.int8), n, p=[0.2, 0.5, 0.3])
+    Xb = np.zeros((n, 32), np.int16)
+    Xb[:, :28] = to_bits(X)
+    mlp = avs.Mlp(p, max_batch=512)
+    # a permuted row selection: the batch is X[rows]
+    rows = rng.permutation(n)[:257].astype(np.int32)
+    g, loss = mlp.grad(dev(Xb), dev(flags), rows=dev(rows))
+    g = g.cpu().numpy().astype(np.float64)
+    lr, gr = M.loss_and_grad(p.astype(np.float64), X[rows], M.labels_from_flags(flags[rows]))
+    assert abs(loss - lr) <= 1e-5 * abs(lr)
+    G, R = M.unpack(g), M.unpack(gr)
+    for name, _ in M.SHAPES:
+        assert np.linalg.norm(G[name] - R[name]) <= 1e-3 * np.linalg.norm(R[name]), name
+
+
+def test_adam_matches_oracle(avs):
+    p = params(3)
+    mlp = avs.Mlp(p, max_batch=64)
+    rng = np.random.default_rng(12)
+    pr, m, v = p.astype(np.float64), np.zeros(M.NPARAM), np.zeros(M.NPARAM)
+    for t in range(1, 4):
+        g = (rng.standard_normal(M.NPARAM) * 10.0 ** rng.uniform(-4, 0, M.NPARAM)).astype(np.float32)
+        mlp.adam(dev(g), lr=3e-3, beta1=0.9, beta2=0.99, eps=1e-8)
+        pr, m, v = M.adam(pr, m, v, g.astype(np.float64), t, 3e-3, 0.9, 0.99, 1e-8)
+    got = mlp.get_params().astype(np.float64)
+    np.testing.assert_allclose(got, pr, rtol=1e-6, atol=1e-9)
+    # the network evaluates with the updated weights
+    X = M.bf16_round(rng.uniform(-1, 1, (70, 28)))
+    Xb = np.zeros((70, 32), np.int16)
+    Xb[:, :28] = to_bits(X)
+    z = mlp.forward(dev(Xb)).cpu().numpy()
+    zr, _ = M.forward(got, X)
+    assert np.quantile(np.max(np.abs(z - zr), axis=1), 0.99) <= 1e-5 * np.max(np.abs(zr))
+
+
+def test_fallback_equals_plain_adaptation(avs):
+    # tail_tol = 0: no proposal can pass the judge, so the plain criterion decides
+    c = small_cylinder()
+    t = resolved_tree(c['vspace'], 4)
+    a, _ = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=t, cap=4096)
+    b, _ = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=t, cap=4096)
+    mlp = avs.Mlp(params(5), max_batch=256)
+    C1 = 1e-3
+    fa, na, fb_used = a.adapt_learned(mlp, C1, math.exp(-8) * C1, probes=c['probes'], tail_tol=0.0)
+    fb, nb = b.adapt(C1, math.exp(-8) * C1, probes=c['probes'])
+    assert fb_used and na == nb
+    np.testing.assert_array_equal(fa, fb)
+    np.testing.assert_array_equal(a.plan(na)[1], b.plan(nb)[1])
+    a.remap(2)
+    b.remap(2)
+    va, Wa = a.get_state()
+    vb, Wb = b.get_state()
+    np.testing.assert_array_equal(va, vb)
+    np.testing.assert_array_equal(Wa, Wb)
+
+
+def brother_groups_sure(tree, sure):
+    """A leaf's decision is comparable if it and all its brothers are sure."""
+    key = [(int(l),) + tuple(int(v) >> 1 for v in ix) if l > 0 else ('root', k)
+           for k, (l, ix) in enumerate(zip(tree.level, tree.idx))]
+    ok = {}
+    for k, kk in enumerate(key):
+        ok[kk] = ok.get(kk, True) and bool(sure[k])
+    return np.array([ok[kk] for kk in key])
+
+
+def test_learned_proposal_matches_oracle(avs):
+    c = small_cylinder()
+    t = resolved_tree(c['vspace'], 6)
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=t, cap=16384)
+    p = params(7, bias=0.5)
+    p[-2:] += 0.5                                          # favour split and merge: all three decisions occur
+    mlp = avs.Mlp(p, max_batch=256, rho_ref=1.0, T_ref=1.0)
+    flags, n_new, fb = cs.adapt_learned(mlp, 1e-3, math.exp(-8) * 1e-3, probes=c['probes'], tail_tol=1.0)
+    assert not fb
+    # oracle: its own features, network, proposal rules and brother-group rule
+    prim = M.primitive_2d(o.W, o.gas.R)
+    X = M.features(o.tree.level, o.tree.idx, o.tree.base, o.tree.max_level, prim, o.gas.R, 1.0, 1.0)
+    Z, _ = M.forward(p.astype(np.float64), X)
+    raw = M.proposal_raw(Z, o.tree.level, o.tree.max_level)
+    eff = O.resolve_merges(raw, o.tree)
+    assert len(np.unique(eff)) == 3                        # the seeded network splits, keeps and merges
+    zs = np.sort(Z, axis=1)
+    sure = brother_groups_sure(o.tree, (zs[:, 2] - zs[:, 1]) > 1e-4 * np.max(np.abs(Z)))
+    assert np.mean(sure) > 0.95
+    assert np.all((flags == eff) | ~sure)
+    if not np.all(flags == eff):
+        pytest.skip("a decision within the rounding margin differs; judge comparison needs identical trees")
+    nt = O.make_plan(eff, o.tree).tree
+    assert n_new == nt.n
+    # the judge on the proposed leaves: reject just below the largest probe error, accept just above
+    err = M.tail_errors(nt.centres(), nt.weights(), M.probe_states(prim, given=c['probes']), o.gas.R)
+    emax = float(np.max(err))
+    assert emax > 0
+    for tol, expect_fallback in ((0.5 * emax, True), (2.0 * emax, False)):
+        b, _ = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=t, cap=16384)
+        _, _, fbk = b.adapt_learned(mlp, 1e-3, math.exp(-8) * 1e-3, probes=c['probes'], tail_tol=tol)
+        assert fbk == expect_fallback, (tol, err)
+
+
+def test_training_reduces_loss_and_learns_labels(avs):
+    from paper_2212_05645_amd import learned
+    c = small_cylinder()
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], cap=8192, Kv=c['venkat_K'])
+    L0 = cs.leaves()
+    base = (L0['level'].copy(), L0['idx'].copy())
+    mlp = avs.Mlp(learned.init_params(0), max_batch=2048)
+    ds = learned.Dataset(200000)
+    C1 = 2e-4
+    for _ in range(2):                                # step-0 cascade with probes
+        cs.adapt(C1, math.exp(-8) * C1, probes=c['probes'])
+        cs.remap(2)
+    learned.collect(cs, mlp, ds, C1, math.exp(-8) * C1, events=8, sweeps_between=3, base=base)
+    assert ds.n > 10000
+    cm0 = learned.confusion(mlp, ds)
+    losses = learned.train(mlp, ds, epochs=20, batch=2048, lr=3e-3, seed=1, log_every=10)
+    cm = learned.confusion(mlp, ds)
+    acc0, acc = np.trace(cm0) / cm0.sum(), np.trace(cm) / cm.sum()
+    print("confusion before", cm0.tolist(), "after", cm.tolist(), "loss", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+    assert acc > max(acc0, 0.9)
+    recall = np.diag(cm) / np.maximum(cm.sum(axis=1), 1)
+    assert np.all(cm.sum(axis=1) > 100) and np.all(recall > 0.8), recall
