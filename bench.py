@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     p.add_argument("--forms", action="store_true", help="also time the FP32 form and the batched form")
     p.add_argument("--ncase", type=int, default=64, help="cases of the batched form")
+    p.add_argument("--train-events", type=int, default=24, help="adaptation events labelled for the learned form")
+    p.add_argument("--train-rows", type=int, default=1_200_000, help="label capacity of the learned form")
+    p.add_argument("--train-epochs", type=int, default=4)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-sweep", action="store_true", help="skip the extra sweep-only timing (profiling runs)")
     p.add_argument("--copy-probe", type=float, default=0.0,
@@ -303,6 +306,77 @@ def run_batched(args):
                         "256..16k leaves, FP32, one graph per adaptation cycle"}
 
 
+def run_learned(args, w, C1):
+    """The learned proposal on the same workload: collect plain-criterion
+    labels while the case runs, train the network with the library's
+    kernels, then time adaptation cycles that use the judged proposal."""
+    import numpy as np
+    import torch
+    from paper_2212_05645_amd import learned
+    avs, cs = w.avs, w.cs
+    C2 = math.exp(-8.0) * C1
+    base = (w.base_level, w.base_idx)
+    w.tree(C1)
+    mlp = avs.Mlp(learned.init_params(0), max_batch=16384, rho_ref=1.0, T_ref=1.0, stream=cs.stream)
+    ds = learned.Dataset(args.train_rows)
+    t0 = time.perf_counter()
+    learned.collect(cs, mlp, ds, C1, C2, events=args.train_events, sweeps_between=args.nu // 4, base=base,
+                    levels=(0, 1, 2), probes=w.cfg['probes'], exact_restore=False)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    nev = len(ds.events)
+    split = ds.events[int(0.9 * nev)][0] if nev > 1 else ds.n
+    t0 = time.perf_counter()
+    losses = learned.train(mlp, ds, epochs=args.train_epochs, batch=8192, lr=2e-3, seed=0,
+                           rows=np.arange(split), log_every=50)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    cm = learned.confusion(mlp, ds, rows=np.arange(split, ds.n))
+    log(f"learned: {ds.n} labels in {nev} events ({t_collect:.1f} s), trained {args.train_epochs} epochs on {split} "
+        f"rows in {t_train:.2f} s, loss {losses[0]:.3f} -> {losses[-1]:.4f}, held-out confusion {cm.tolist()}")
+    # timed cycles: plain adaptation, then the learned proposal, from the same step-0 tree
+    out = {}
+    for mode in ("plain", "learned"):
+        w.tree(C1)
+        fallbacks, t_adapt, updates = 0, 0.0, 0
+        for k in range(args.warmup + args.steps):
+            timed = k >= args.warmup
+            nv = cs.nleaves()
+            if k == args.warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            cs.step(args.nu)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            if mode == "plain":
+                cs.adapt(C1, C2)
+            else:
+                _, _, fb = cs.adapt_learned(mlp, C1, C2, tail_tol=1e-4)
+                fallbacks += int(fb and timed)
+            tb = time.perf_counter()
+            cs.remap(2)
+            if timed:
+                t_adapt += tb - ta
+                updates += w.nc * nv * args.nu
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[mode] = dict(cycle_updates_per_s=updates / (ms * 1e-3), adapt_ms=1e3 * t_adapt / args.steps,
+                         fallbacks=fallbacks, leaves=cs.nleaves())
+        log(f"learned form, {mode} adaptation: {out[mode]}")
+    recall = [float(cm[i, i] / max(cm[i].sum(), 1)) for i in range(3)]
+    flop = 3 * 2 * (32 * 128 + 128 * 128 + 128 * 16) * split * args.train_epochs
+    mlp.close()
+    return {"cycle_updates_per_s": out["learned"]["cycle_updates_per_s"],
+            "cycle_updates_per_s_plain_same_run": out["plain"]["cycle_updates_per_s"],
+            "adapt_ms_learned": out["learned"]["adapt_ms"], "adapt_ms_plain": out["plain"]["adapt_ms"],
+            "fallbacks": out["learned"]["fallbacks"], "cycles": args.steps,
+            "leaves_after": {m: out[m]["leaves"] for m in out},
+            "labels": ds.n, "train_rows": split, "train_s": t_train, "collect_s": t_collect,
+            "train_TFLOP_per_s": flop / t_train / 1e12,
+            "heldout_confusion_keep_split_merge": cm.tolist(), "heldout_recall": recall,
+            "loss_first_last": [losses[0], losses[-1]]}
+
+
 def run_form(args, precision, C1=None):
     w = Workload(args, precision)
     if C1 is None:
@@ -355,6 +429,11 @@ def main():
     forms = {args.precision: {"cycle_updates_per_s": value, "sweep_updates_per_s": r["sweep_rate"],
                               "sweep_ms": r["sweep_ms"], "leaves": r["sweep_leaves"]}}
     if args.forms:
+        if args.precision == "fp64":
+            try:
+                forms["learned_fp64"] = run_learned(args, w, C1)
+            except Exception as e:
+                forms["learned_fp64"] = {"error": repr(e)}
         other = "fp32" if args.precision == "fp64" else "fp64"
         del w
         torch.cuda.empty_cache()
