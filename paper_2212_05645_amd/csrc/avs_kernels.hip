@@ -1452,13 +1452,36 @@ __device__ __forceinline__ int find_case(const int* __restrict__ off, int ncase,
   return lo;
 }
 
+// Pointers read from device memory are generic to the compiler; the batched
+// kernels declare every pointer of a case record global so that uniform
+// loads through it become scalar loads, as for kernel arguments.
+template <typename E>
+__device__ __forceinline__ E* gptr(E* p) {
+  typedef __attribute__((address_space(1))) E GE;
+  GE* q = (GE*)(uintptr_t)p;
+  return (E*)q;
+}
+#define AVS_G(x) x = gptr(x)
+__device__ __forceinline__ Geo global_geo(Geo g) {
+  AVS_G(g.order); AVS_G(g.vol); AVS_G(g.eps2); AVS_G(g.dtv); AVS_G(g.nslot); AVS_G(g.s_face); AVS_G(g.s_nbr);
+  AVS_G(g.s_sig); AVS_G(g.s_sigA); AVS_G(g.s_d); AVS_G(g.s_dx); AVS_G(g.s_lsq); AVS_G(g.f_L); AVS_G(g.f_R);
+  AVS_G(g.f_sL); AVS_G(g.f_sR); AVS_G(g.f_nrm); AVS_G(g.f_int); AVS_G(g.f_bnd); AVS_G(g.bc_kind); AVS_G(g.bc_prim);
+  return g;
+}
+__device__ __forceinline__ Leaves global_leaves(Leaves L) {
+  AVS_G(L.level); AVS_G(L.idx); AVS_G(L.u); AVS_G(L.xi); AVS_G(L.w);
+  return L;
+}
+#undef AVS_G
+
 template <int D, typename T>
 __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passA(const CaseArgs<T>* __restrict__ args,
                                                                        const int* __restrict__ off, int ncase) {
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
   const int lb = blockIdx.x - off[c];
-  d_passA<D, T>(a->g, a->L, a->vin, a->h, a->fv, a->chunk, lb % a->gx, lb / a->gx);
+  d_passA<D, T>(global_geo(a->g), global_leaves(a->L), gptr(a->vin), a->h, gptr(a->fv), a->chunk, lb % a->gx,
+                lb / a->gx);
 }
 
 template <int D, typename T>
@@ -1466,14 +1489,16 @@ __global__ __launch_bounds__(BLOCK) void kb_face(const CaseArgs<T>* __restrict__
                                                 int ncase) {
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
-  d_face<D, T>(a->g, a->L, a->vg, a->gas, a->h, a->fv, a->bden, a->bfin, a->fpar, a->F, a->bad, blockIdx.x - off[c], 0);
+  d_face<D, T>(global_geo(a->g), global_leaves(a->L), a->vg, a->gas, a->h, gptr(a->fv), gptr(a->bden), gptr(a->bfin),
+               gptr(a->fpar), gptr(a->F), gptr(a->bad), blockIdx.x - off[c], 0);
 }
 
 template <int D, typename T>
 __global__ void kb_macro(const CaseArgs<T>* __restrict__ args, const int* __restrict__ off, int ncase) {
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
-  d_macro<D>(a->g, a->gas, a->dt, a->F, a->W, a->Wn, a->q, a->tpar, a->bad, blockIdx.x - off[c], 0);
+  d_macro<D>(global_geo(a->g), a->gas, a->dt, gptr(a->F), gptr(a->W), gptr(a->Wn), gptr(a->q), gptr(a->tpar),
+             gptr(a->bad), blockIdx.x - off[c], 0);
 }
 
 template <int D, typename T>
@@ -1481,7 +1506,8 @@ __global__ __launch_bounds__(BLOCK) void kb_target(const CaseArgs<T>* __restrict
                                                   int ncase) {
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
-  d_target<D, T>(a->g, a->L, a->vg, a->tpar, a->Wn, a->lam, a->bad, blockIdx.x - off[c], 0);
+  d_target<D, T>(global_geo(a->g), global_leaves(a->L), a->vg, gptr(a->tpar), gptr(a->Wn), gptr(a->lam), gptr(a->bad),
+                 blockIdx.x - off[c], 0);
 }
 
 template <int D, typename T>
@@ -1489,8 +1515,8 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passC(const Ca
                                                                        const int* __restrict__ off, int ncase) {
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
-  d_passC<D, T>(a->g, a->L, a->vg, a->vin, a->fv, a->vout, a->fpar, a->tpar, a->lam, a->bcpair, a->mom, a->q,
-                blockIdx.x - off[c], 0);
+  d_passC<D, T>(global_geo(a->g), global_leaves(a->L), a->vg, gptr(a->vin), gptr(a->fv), gptr(a->vout), gptr(a->fpar),
+                gptr(a->tpar), gptr(a->lam), gptr(a->bcpair), gptr(a->mom), gptr(a->q), blockIdx.x - off[c], 0);
 }
 
 }  // namespace avs
