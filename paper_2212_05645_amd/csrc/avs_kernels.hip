@@ -929,9 +929,11 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
     T div[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) div[p] = 0;
-#pragma unroll
-    for (int s = 0; s < MAXF; ++s) {
-      if (s < ns) {
+    // one face at a time: its record is read from LDS inside the loop, so
+    // only one face's parameters are live in registers
+#pragma unroll 1
+    for (int s = 0; s < ns; ++s) {
+      {
         const int f = sface[s];
         const double sn = normal_speed<D>(xi, snrm[s]);
         T pf[P];
