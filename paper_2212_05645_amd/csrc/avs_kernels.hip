@@ -484,35 +484,37 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
         const T dv = v - phi[p];
 #pragma unroll
         for (int d = 0; d < D; ++d) grad[p][d] += dv * st.cf[s][d];
-        pmax[p] = v > pmax[p] ? v : pmax[p];
-        pmin[p] = v < pmin[p] ? v : pmin[p];
+        pmax[p] = fmax(v, pmax[p]);
+        pmin[p] = fmin(v, pmin[p]);
       }
     }
   }
   // Venkatakrishnan: psi_f = N/Dn with, for a = |D2| and b = |D1| (same sign),
   //   N = b^2 + eps^2 + 2ab,  Dn = b^2 + 2a^2 + ab + eps^2   (psi = 1 if D2 = 0),
   // which is the paper's expression divided through by D2.  a, b and eps are
-  // scaled by the largest of them (one division), the minimum over faces is
-  // kept as a fraction by cross-multiplication, and one division ends it.
+  // scaled by the power of two just above the largest of them (exact), the
+  // minimum over faces is kept as a fraction by cross-multiplication, and
+  // one division ends it.
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     T d2s[MAXF];
     const T up0 = pmax[p] - phi[p], dn0 = phi[p] - pmin[p];
-    T m = up0 > dn0 ? up0 : dn0;
+    T m = fmax(up0, dn0);
 #pragma unroll
     for (int s = 0; s < MAXF; ++s) {
       T d2 = 0;
 #pragma unroll
       for (int d = 0; d < D; ++d) d2 += grad[p][d] * st.dd[s][d];
       d2s[s] = d2;
-      const T a = fabs(d2);
-      m = a > m ? a : m;
+      m = fmax(fabs(d2), m);
     }
     T lim = 1;
     // below the smallest normal number the stencil differences carry no
-    // information (and 1/m would overflow): leave the slope unlimited
+    // information (and the scale would overflow): leave the slope unlimited
     if (ns > 0 && m > (sizeof(T) == 8 ? (T)1e-300 : (T)1e-36)) {
-      const T inv = (T)1 / m;
+      int ex;
+      (void)frexp(m, &ex);                             // m = f 2^ex, f in [0.5, 1)
+      const T inv = ldexp((T)1, -ex);                  // scaled values lie in [0, 1)
       // eps^2 beyond this makes psi = 1 to working precision; the clamp keeps
       // the cross products below the overflow threshold of T
       const T e2 = fmin(st.eps2 * inv * inv, sizeof(T) == 8 ? (T)1e30 : (T)1e15);
