@@ -415,8 +415,13 @@ avs_status launch_step(avs_ctx* ctx, bool last_residual) {
   }
   {
     ProfScope ps(ctx, K_FACE);
-    k_face<D, T><<<ctx->nf, BLOCK, (size_t)D * nu * sizeof(T), ctx->stream>>>(
-        ctx->geo, L, ctx->vg, ctx->gas, ctx->h, (const T*)ctx->fv, ctx->bden, ctx->bfin, ctx->fpar, ctx->F, ctx->bad);
+    k_face<D, T><<<ctx->nf, BLOCK, 0, ctx->stream>>>(ctx->geo, L, (const T*)ctx->fv, ctx->fpar);
+    CKL();
+  }
+  {
+    ProfScope ps(ctx, K_FACE_EQFLUX);
+    k_face_eq<D, T><<<ctx->nf, BLOCK, (size_t)D * nu * sizeof(T), ctx->stream>>>(
+        ctx->geo, L, ctx->vg, ctx->gas, ctx->h, ctx->bden, ctx->bfin, ctx->fpar, ctx->F, ctx->bad);
     CKL();
   }
   {
@@ -558,11 +563,11 @@ struct avs_batch {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   int chunk = CHUNK;
-  int nblk[BK_N] = {0, 0, 0, 0, 0};
+  int nblk[BK_N] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_steps = -1;
-  int graph_nblk[BK_N] = {-1, -1, -1, -1, -1};
+  int graph_nblk[BK_N] = {};   // compared only once a graph exists
   int graph_chunk = -1;
   std::vector<char> host_args;
   ~avs_batch() {
@@ -620,7 +625,7 @@ avs_status batch_upload(avs_batch* b) {
     args[n + i] = case_args<T>(c, 1, b->chunk);
     const int nl = c->nleaf[c->lcur];
     const int gx = (int)round_up(c->nc, 8);
-    const int cnt[BK_N] = {gx * ((nl + b->chunk - 1) / b->chunk), c->nf, (c->nc + BLOCK - 1) / BLOCK, c->nc, gx};
+    const int cnt[BK_N] = {gx * ((nl + b->chunk - 1) / b->chunk), c->nf, c->nf, (c->nc + BLOCK - 1) / BLOCK, c->nc, gx};
     for (int k = 0; k < BK_N; ++k) off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + cnt[k];
   }
   for (int k = 0; k < BK_N; ++k) b->nblk[k] = off[k * (n + 1) + n];
@@ -642,7 +647,9 @@ avs_status batch_launch(avs_batch* b, int nsteps) {
     const CaseArgs<T>* a = args + (s & 1) * n;
     kb_passA<D, T><<<b->nblk[BK_PASSA], BLOCK, 0, b->stream>>>(a, off + BK_PASSA * (n + 1), n);
     CKL();
-    kb_face<D, T><<<b->nblk[BK_FACE], BLOCK, (size_t)D * numax * sizeof(T), b->stream>>>(a, off + BK_FACE * (n + 1), n);
+    kb_face<D, T><<<b->nblk[BK_FACE], BLOCK, 0, b->stream>>>(a, off + BK_FACE * (n + 1), n);
+    CKL();
+    kb_face_eq<D, T><<<b->nblk[BK_FACEQ], BLOCK, (size_t)D * numax * sizeof(T), b->stream>>>(a, off + BK_FACEQ * (n + 1), n);
     CKL();
     kb_macro<D, T><<<b->nblk[BK_MACRO], BLOCK, 0, b->stream>>>(a, off + BK_MACRO * (n + 1), n);
     CKL();

@@ -621,26 +621,20 @@ __device__ __forceinline__ void raw_flux(const double* m, const double* n, doubl
 }
 
 // ------------------------------------------------------ interface (S5-S8)
-// One workgroup per face streams the face's row of the interface buffer:
-// raw moments of the reconstructed VDF (Eq. w_interface; on a boundary face
-// over the outgoing leaves only).  Interior face: interface state, tau,
-// heat flux relaxed over h at rate Pr/tau, Shakhov record and blend weights,
-// then the flux F = a sum A s psi phibar + b sum A s psi g_f with g_f
-// evaluated in R from the record.  Boundary face: outgoing flux plus the
-// incoming wall (zero net mass flux, rho_w) or far-field Maxwellian flux.
+// Two kernels per step.  d_face: one workgroup per face streams the face's
+// row of the interface buffer and sums the raw moments of the reconstructed
+// VDF (Eq. w_interface; on a boundary face over the outgoing leaves only)
+// into the face's record slot.  d_face_eq: from those moments, interior
+// face: interface state, tau, heat flux relaxed over h at rate Pr/tau,
+// Shakhov record and blend weights, then the flux F = a sum A s psi phibar
+// + b sum A s psi g_f with g_f evaluated in R from the record.  Boundary
+// face: outgoing flux plus the incoming wall (zero net mass flux, rho_w) or
+// far-field Maxwellian flux.  Splitting the reduction from the record and
+// the equilibrium sum keeps both kernels at a small register footprint.
 template <int D, typename R>
-__device__ __forceinline__ void d_face(Geo g, Leaves L, VGrid vg, GasP gas, double h, const R* __restrict__ fv,
-                                               const double* __restrict__ bden, const double* __restrict__ bfin,
-                                               double* __restrict__ fpar, double* __restrict__ F,
-                                               int* __restrict__ bad, int bx, int by) {
-  constexpr int P = Cfg<D>::P, NM = Cfg<D>::NM, N = D + 2;
-  extern __shared__ double lds_d[];
-  R* tab = reinterpret_cast<R*>(lds_d);
+__device__ __forceinline__ void d_face(Geo g, Leaves L, const R* __restrict__ fv, double* __restrict__ fpar, int bx) {
+  constexpr int P = Cfg<D>::P, NM = Cfg<D>::NM;
   __shared__ double red[4 * NM];
-  __shared__ double spar[NPAR];
-  __shared__ R rp[NPAR];
-  __shared__ double sF[N];
-  __shared__ int interior_ok;
   const int f = bx;
   const int Rc = g.f_R[f];
   const size_t fs = (size_t)g.nf * L.ld;
@@ -676,6 +670,30 @@ __device__ __forceinline__ void d_face(Geo g, Leaves L, VGrid vg, GasP gas, doub
     for (int d = 0; d < D; ++d) m[t++] += eh * xi[d];
   }
   block_sum<NM>(m, red);
+  if (threadIdx.x == 0)
+    for (int t = 0; t < NM; ++t) fpar[(size_t)f * NPAR + t] = m[t];
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, double h, const double* __restrict__ bden,
+                                          const double* __restrict__ bfin, double* __restrict__ fpar,
+                                          double* __restrict__ F, int* __restrict__ bad, int bx) {
+  constexpr int NM = Cfg<D>::NM, N = D + 2;
+  extern __shared__ double lds_d[];
+  R* tab = reinterpret_cast<R*>(lds_d);
+  __shared__ double red[4 * N];
+  __shared__ double spar[NPAR];
+  __shared__ R rp[NPAR];
+  __shared__ double sF[N];
+  __shared__ int interior_ok;
+  const int f = bx;
+  const int Rc = g.f_R[f];
+  double n[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
+  double m[NM];
+  if (threadIdx.x == 0)
+    for (int t = 0; t < NM; ++t) m[t] = fpar[(size_t)f * NPAR + t];
   if (threadIdx.x == 0) {
     interior_ok = 0;
     if (Rc >= 0) {
@@ -757,11 +775,16 @@ __device__ __forceinline__ void d_face(Geo g, Leaves L, VGrid vg, GasP gas, doub
 }
 
 template <int D, typename R>
-__global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, VGrid vg, GasP gas, double h, const R* __restrict__ fv,
-                                               const double* __restrict__ bden, const double* __restrict__ bfin,
-                                               double* __restrict__ fpar, double* __restrict__ F,
-                                               int* __restrict__ bad) {
-  d_face<D, R>(g, L, vg, gas, h, fv, bden, bfin, fpar, F, bad, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(BLOCK) void k_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, double h,
+                                                  const double* __restrict__ bden, const double* __restrict__ bfin,
+                                                  double* __restrict__ fpar, double* __restrict__ F,
+                                                  int* __restrict__ bad) {
+  d_face_eq<D, R>(g, L, vg, gas, h, bden, bfin, fpar, F, bad, blockIdx.x);
+}
+
+template <int D, typename R>
+__global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, const R* __restrict__ fv, double* __restrict__ fpar) {
+  d_face<D, R>(g, L, fv, fpar, blockIdx.x);
 }
 
 // ------------------------------------------------------ macro update (S8-S9)
@@ -1444,7 +1467,7 @@ struct CaseArgs {
   int chunk, gx;   // pass A: leaves per workgroup, round_up(nc, 8)
 };
 
-enum { BK_PASSA, BK_FACE, BK_MACRO, BK_TARGET, BK_PASSC, BK_N };
+enum { BK_PASSA, BK_FACE, BK_FACEQ, BK_MACRO, BK_TARGET, BK_PASSC, BK_N };
 
 // Largest c with off[c] <= b (off has ncase + 1 increasing entries).
 __device__ __forceinline__ int find_case(const int* __restrict__ off, int ncase, int b) {
@@ -1493,8 +1516,16 @@ __global__ __launch_bounds__(BLOCK) void kb_face(const CaseArgs<T>* __restrict__
                                                 int ncase) {
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
-  d_face<D, T>(global_geo(a->g), global_leaves(a->L), a->vg, a->gas, a->h, gptr(a->fv), gptr(a->bden), gptr(a->bfin),
-               gptr(a->fpar), gptr(a->F), gptr(a->bad), blockIdx.x - off[c], 0);
+  d_face<D, T>(global_geo(a->g), global_leaves(a->L), gptr(a->fv), gptr(a->fpar), blockIdx.x - off[c]);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void kb_face_eq(const CaseArgs<T>* __restrict__ args, const int* __restrict__ off,
+                                                   int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const CaseArgs<T>* a = args + c;
+  d_face_eq<D, T>(global_geo(a->g), global_leaves(a->L), a->vg, a->gas, a->h, gptr(a->bden), gptr(a->bfin),
+                  gptr(a->fpar), gptr(a->F), gptr(a->bad), blockIdx.x - off[c]);
 }
 
 template <int D, typename T>
