@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--train-events", type=int, default=24, help="adaptation events labelled for the learned form")
     p.add_argument("--train-rows", type=int, default=1_200_000, help="label capacity of the learned form")
     p.add_argument("--train-epochs", type=int, default=4)
+    p.add_argument("--sphere-C1", type=float, default=1.0076e-4, help="splitting threshold of the 3-D form (~20k leaves)")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-sweep", action="store_true", help="skip the extra sweep-only timing (profiling runs)")
     p.add_argument("--copy-probe", type=float, default=0.0,
@@ -187,7 +188,7 @@ def vdf_bytes_per_node(P, es, rows_per_cell):
             "criterion": r, "remap_gather": 2 * r, "remap_correct": 2 * r, "moments": r}
 
 
-def cpu_baseline(w, ncell_sample=16):
+def cpu_baseline(w, ncell_sample=512):
     """Oracle (FP64 NumPy) updating a contiguous block of cells of the same
     workload and leaf set, given its two-ring neighbourhood."""
     import numpy as np
@@ -203,13 +204,14 @@ def cpu_baseline(w, ncell_sample=16):
                     L['idx'].astype(np.int64))
     o.phi = o.initial_vdf(o.W)
     loc = [int(np.searchsorted(keep, g)) for g in sample]
-    threads = os.environ.get("OMP_NUM_THREADS", "1")
-    t0 = time.perf_counter()
-    O.step(o.mesh, o.tree, o.gas, o.dt, o.Kv, o.phi, o.W, cells=loc)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):          # the oracle runs on one core, BLAS included
+        t0 = time.perf_counter()
+        O.step(o.mesh, o.tree, o.gas, o.dt, o.Kv, o.phi, o.W, cells=loc)
+        dt = time.perf_counter() - t0
     return {"value": len(sample) * L['n'] / dt, "unit": "cell-node updates/s", "cores": 1, "kind": "oracle",
             "sample": f"one explicit step of {len(sample)} contiguous cells x {L['n']} leaves of the same workload "
-                      f"(NumPy FP64, single thread; BLAS threads={threads}), {dt:.2f} s"}
+                      f"(NumPy FP64, one thread, BLAS limited to one thread), {dt:.2f} s"}
 
 
 def run_batched(args):
@@ -377,6 +379,50 @@ def run_learned(args, w, C1):
             "loss_first_last": [losses[0], losses[-1]]}
 
 
+def run_sphere(args):
+    """The 3-D form: supersonic sphere (64 x 64 x 32 cells), octree of 16^3
+    roots and 2 levels, FP32 storage; C1 for a step-0 tree of about 20 000
+    leaves (bisected once with the same step-0 cascade)."""
+    import torch
+    from paper_2212_05645_amd import avs
+    from workloads import fields as F
+    c = F.sphere()
+    cs = avs.Case(c['mesh'], c['vspace'], c['gas'], c['dt'], c['venkat_K'], c['prim0'], precision=avs.AVS_FP32,
+                  leaf_capacity=49152)
+    C1, C2 = args.sphere_C1, math.exp(-8.0) * args.sphere_C1
+    for _ in range(c['vspace']['max_level']):
+        cs.adapt(C1, C2, probes=c['probes'])
+        cs.remap(2)
+    cs.set_state(None, cs.get_W())
+    n0 = cs.nleaves()
+    nu = max(1, args.nu // 4)
+    for _ in range(args.warmup):
+        cs.step(nu)
+        cs.adapt(C1, C2)
+        cs.remap(2)
+    torch.cuda.synchronize()
+    cs.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    updates = 0
+    e0.record(cs.stream)
+    for _ in range(args.steps):
+        updates += cs.nc * cs.nleaves() * nu
+        cs.step(nu)
+        cs.adapt(C1, C2)
+        cs.remap(2)
+    e1.record(cs.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = cs.profile_read()
+    cs.profile(False)
+    out = {"cycle_updates_per_s": updates / (ms * 1e-3), "cells": cs.nc, "leaves_step0": n0,
+           "leaves_end": cs.nleaves(), "sweeps_per_cycle": nu, "C1": C1,
+           "kernels_ms_per_launch": {k: v[0] / v[1] for k, v in prof.items()},
+           "workload": "sphere Ma 4, 64x64x32 cells, octree 16^3 roots x 2 levels on [-12,12]^3, FP32"}
+    cs.close()
+    return out
+
+
 def run_form(args, precision, C1=None):
     w = Workload(args, precision)
     if C1 is None:
@@ -448,6 +494,11 @@ def main():
             forms["batched_fp32"] = run_batched(args)
         except Exception as e:
             forms["batched_fp32"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        try:
+            forms["sphere_fp32"] = run_sphere(args)
+        except Exception as e:
+            forms["sphere_fp32"] = {"error": repr(e)}
     cpu = None
     if not args.no_cpu:
         try:
