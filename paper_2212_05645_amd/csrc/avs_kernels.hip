@@ -523,13 +523,13 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
 #pragma unroll
       for (int s = 0; s < MAXF; ++s) {
         if (s < ns) {
-          T Nn = 1, Dd = 1;                            // psi = 1 where D2 = 0
-          if (d2s[s] != (T)0) {
-            const T a = fabs(d2s[s]) * inv;
-            const T b = d2s[s] > (T)0 ? up : dn;
-            Nn = b * b + e2 + (T)2 * a * b;
-            Dd = b * b + (T)2 * a * a + a * b + e2;
-          }
+          // D2 = 0 gives a = 0 and N = Dn = c exactly (psi = 1); the tiny term
+          // keeps c > 0 where b and eps vanish too
+          const T a = fabs(d2s[s]) * inv;
+          const T b = d2s[s] > (T)0 ? up : dn;
+          const T c = b * b + e2 + (sizeof(T) == 8 ? (T)1e-300 : (T)1e-30);
+          const T Nn = c + (T)2 * a * b;
+          const T Dd = c + a * ((T)2 * a + b);
           if (Nn * Dm < Nm * Dd) { Nm = Nn; Dm = Dd; }
         }
       }
@@ -586,7 +586,7 @@ __device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ v
             T v = 0;
 #pragma unroll
             for (int d = 0; d < D; ++d) v += lg[p][d] * (st.dd[s][d] - (T)xi[d] * th);
-            row[s][p][k] = phi[p] + v;
+            __builtin_nontemporal_store((T)(phi[p] + v), &row[s][p][k]);   // read by later kernels only
           }
         }
       }
