@@ -437,9 +437,13 @@ struct Stencil {
   T eps2;
 };
 
+// The per-cell constants come from global memory (uniform loads, scalar
+// registers) or, with lcf/ldd non-null, from LDS (vector registers): 2-D FP32
+// has vector registers to spare and runs faster with them there, the other
+// forms would lose occupancy.
 template <int D, typename T>
 __device__ __forceinline__ void load_stencil(const Geo& g, const T* __restrict__ vdf, size_t cs, int ld, int c,
-                                             Stencil<D, T>& st) {
+                                             Stencil<D, T>& st, const T* lcf = nullptr, const T* ldd = nullptr) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
   st.ns = g.nslot[c];
   st.nbmask = 0;
@@ -454,8 +458,13 @@ __device__ __forceinline__ void load_stencil(const Geo& g, const T* __restrict__
     for (int p = 0; p < P; ++p) st.nb[s][p] = j >= 0 ? vdf + p * cs + (size_t)j * ld : st.own[p];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      st.cf[s][d] = j >= 0 ? (T)g.s_lsq[(size_t)(c * MAXF + s) * D + d] : (T)0;
-      st.dd[s][d] = s < st.ns ? (T)g.s_d[(size_t)(c * MAXF + s) * D + d] : (T)0;
+      if (lcf) {
+        st.cf[s][d] = lcf[s * D + d];
+        st.dd[s][d] = ldd[s * D + d];
+      } else {
+        st.cf[s][d] = j >= 0 ? (T)g.s_lsq[(size_t)(c * MAXF + s) * D + d] : (T)0;
+        st.dd[s][d] = s < st.ns ? (T)g.s_d[(size_t)(c * MAXF + s) * D + d] : (T)0;
+      }
     }
   }
 }
@@ -555,16 +564,40 @@ __device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ v
   const int k0 = by * chunk, k1 = min(L.n, k0 + chunk);
   const size_t cs = (size_t)g.nc * L.ld;
   const size_t fs = (size_t)g.nf * L.ld;   // component stride of the interface buffer
+  constexpr bool lds_consts = D == 2 && sizeof(T) == 4;
+  __shared__ T s_cf[MAXF * D], s_dd[MAXF * D];
+  __shared__ double s_nrm[MAXF * D], s_sig[MAXF];
   Stencil<D, T> st;
-  load_stencil<D, T>(g, vdf, cs, L.ld, i, st);
   double nrm[MAXF][D], sig[MAXF];
   T* row[MAXF][P];
+  if constexpr (lds_consts) {
+    const int ns = g.nslot[i];
+    if (threadIdx.x < MAXF * D) {
+      const int s = threadIdx.x / D, d = threadIdx.x % D;
+      const int j = s < ns ? g.s_nbr[i * MAXF + s] : -1;
+      const int f = s < ns ? g.s_face[i * MAXF + s] : 0;
+      s_cf[threadIdx.x] = j >= 0 ? (T)g.s_lsq[(size_t)i * MAXF * D + threadIdx.x] : (T)0;
+      s_dd[threadIdx.x] = s < ns ? (T)g.s_d[(size_t)i * MAXF * D + threadIdx.x] : (T)0;
+      s_nrm[threadIdx.x] = g.f_nrm[(size_t)f * D + d];
+      if (d == 0) s_sig[s] = s < ns ? g.s_sig[i * MAXF + s] : 0.0;
+    }
+    __syncthreads();
+    load_stencil<D, T>(g, vdf, cs, L.ld, i, st, s_cf, s_dd);
+  } else {
+    load_stencil<D, T>(g, vdf, cs, L.ld, i, st);
+  }
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
     const int f = s < st.ns ? g.s_face[i * MAXF + s] : 0;
-    sig[s] = s < st.ns ? g.s_sig[i * MAXF + s] : 0.0;
+    if constexpr (lds_consts) {
+      sig[s] = s_sig[s];
 #pragma unroll
-    for (int d = 0; d < D; ++d) nrm[s][d] = g.f_nrm[(size_t)f * D + d];
+      for (int d = 0; d < D; ++d) nrm[s][d] = s_nrm[s * D + d];
+    } else {
+      sig[s] = s < st.ns ? g.s_sig[i * MAXF + s] : 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) nrm[s][d] = g.f_nrm[(size_t)f * D + d];
+    }
 #pragma unroll
     for (int p = 0; p < P; ++p) row[s][p] = fv + p * fs + (size_t)f * L.ld;
   }
