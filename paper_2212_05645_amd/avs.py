@@ -24,7 +24,7 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_moments", "avs_adapt", "avs_remap", "avs_leaves", "avs_plan", "avs_criterion",
            "avs_set_leaves", "avs_get_state", "avs_set_state", "avs_get_cells", "avs_profile",
            "avs_profile_read", "avs_batch_workspace_bytes", "avs_batch_create", "avs_batch_step",
-           "avs_batch_check", "avs_batch_tune", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
+           "avs_batch_check", "avs_batch_tune", "avs_batch_adapt", "avs_batch_remap", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
            "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
            "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
            "avs_destroy", "avs_last_error")
@@ -84,6 +84,8 @@ def _load():
         "avs_batch_step": (I32, [VP, I32, I32]),
         "avs_batch_check": (I32, [VP]),
         "avs_batch_tune": (I32, [VP, P(I32)]),
+        "avs_batch_adapt": (I32, [VP, VP, VP, VP]),
+        "avs_batch_remap": (I32, [VP, I32]),
         "avs_batch_destroy": (None, [VP]),
         "avs_mlp_param_count": (I64, []),
         "avs_mlp_state_bytes": (C.c_size_t, [I64]),
@@ -425,6 +427,18 @@ class Batch:
 
     def check(self):
         _check(lib.avs_batch_check(self.b))
+
+    def adapt(self, C1, C2):
+        """Adapt every member (per-case thresholds); returns the new leaf counts."""
+        n = len(self.cases)
+        c1 = np.ascontiguousarray(np.broadcast_to(np.asarray(C1, np.float64), (n,)))
+        c2 = np.ascontiguousarray(np.broadcast_to(np.asarray(C2, np.float64), (n,)))
+        nn = np.zeros(n, np.int64)
+        _check(lib.avs_batch_adapt(self.b, c1.ctypes.data, c2.ctypes.data, nn.ctypes.data))
+        return nn
+
+    def remap(self, correction=2):
+        _check(lib.avs_batch_remap(self.b, int(correction)))
 
     def tune(self):
         ch = C.c_int32()

@@ -1307,6 +1307,69 @@ avs_status avs_batch_step(avs_batch* b, int32_t nsteps, int32_t use_graph) {
   return st;
 }
 
+avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2_host, int64_t* n_new_host) {
+  avs_ctx* ctx = nullptr;
+  if (!b) return fail(AVS_E_INVALID, "null batch");
+  if (!C1_host || !C2_host) return fail(AVS_E_INVALID, "null C1/C2 arrays");
+  const int n = (int)b->cases.size();
+  for (int i = 0; i < n; ++i) {
+    if (avs_status st = guard(b->cases[i])) return st;
+    if (std::isnan(C1_host[i]) || std::isnan(C2_host[i])) return fail(AVS_E_INVALID, "case %d: C1/C2 must not be NaN", i);
+  }
+  // criterion, flags, scan of every case back to back; one wait for the counts
+  for (avs_ctx* c : b->cases) c->plan_valid = false;
+  for (int i = 0; i < n; ++i) {
+    avs_ctx* c = b->cases[i];
+    if (avs_status st = DISPATCH(c, launch_adapt, c, C1_host[i], C2_host[i], 0)) return st;
+  }
+  std::vector<int> nn(n, 0);
+  for (int i = 0; i < n; ++i) {
+    avs_ctx* c = b->cases[i];
+    CK(hipMemcpyAsync(&nn[i], c->off + c->nleaf[c->lcur], sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  }
+  CK(hipStreamSynchronize(b->stream));
+  for (int i = 0; i < n; ++i) {
+    if (n_new_host) n_new_host[i] = nn[i];
+    if (nn[i] > b->cases[i]->cap)
+      return fail(AVS_E_CAPACITY, "case %d: adaptation would produce %d leaves > leaf_capacity %" PRId64, i, nn[i],
+                  b->cases[i]->cap);
+  }
+  for (int i = 0; i < n; ++i) {
+    avs_ctx* c = b->cases[i];
+    const int t = c->lcur ^ 1;
+    c->nleaf[t] = nn[i];
+    c->ld[t] = (int)round_up(nn[i], 64);
+    if (avs_status st = DISPATCH_D(c, launch_scatter, c)) return st;
+  }
+  CK(hipStreamSynchronize(b->stream));
+  for (int i = 0; i < n; ++i) {
+    b->cases[i]->plan_n = nn[i];
+    b->cases[i]->plan_valid = true;
+  }
+  return AVS_OK;
+}
+
+avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
+  if (!b) return fail(AVS_E_INVALID, "null batch");
+  if (correction < 0 || correction > 2) return fail(AVS_E_INVALID, "correction must be 0, 1 or 2");
+  const int n = (int)b->cases.size();
+  for (int i = 0; i < n; ++i) {
+    if (avs_status st = guard(b->cases[i])) return st;
+    if (!b->cases[i]->plan_valid) return fail(AVS_E_STATE, "case %d: no adaptation plan", i);
+  }
+  for (avs_ctx* c : b->cases) {
+    if (avs_status st = DISPATCH(c, launch_remap, c, correction)) return st;
+    c->lcur ^= 1;
+    c->cur ^= 1;
+    c->plan_valid = false;
+    if (avs_status st = DISPATCH_D(c, launch_bc_tables, c)) return st;
+    if (avs_status st = DISPATCH(c, launch_moments, c)) return st;
+  }
+  for (avs_ctx* c : b->cases)
+    if (avs_status st = check_bad(c)) return st;
+  return AVS_OK;
+}
+
 avs_status avs_batch_check(avs_batch* b) {
   if (!b) return fail(AVS_E_INVALID, "null batch");
   for (avs_ctx* c : b->cases)

@@ -389,4 +389,19 @@ def test_batch_matches_single_cases_bit_for_bit(avs, prec):
             cs.step(2)
         for a, b in zip(solo, grouped):
             assert np.array_equal(a.get_state()[0], b.get_state()[0])
+        # batched adaptation and remap equal the per-case calls (per-case thresholds)
+        C1 = [0.02, 1e-3, 0.005]
+        nn_solo = []
+        for cs, c1 in zip(solo, C1):
+            nn_solo.append(cs.adapt(c1, math.exp(-8) * c1)[1])
+            cs.remap(2)
+        nn = batch.adapt(C1, [math.exp(-8) * c1 for c1 in C1])
+        batch.remap(2)
+        assert list(nn) == nn_solo
+        for a, b in zip(solo, grouped):
+            la, lb = a.leaves(), b.leaves()
+            assert np.array_equal(la['level'], lb['level']) and np.array_equal(la['idx'], lb['idx'])
+            va, Wa = a.get_state()
+            vb, Wb = b.get_state()
+            assert np.array_equal(va, vb) and np.array_equal(Wa, Wb)
         batch.close()
