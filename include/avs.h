@@ -182,8 +182,10 @@ avs_status avs_set_leaves(avs_ctx *ctx, int64_t n, const int32_t *level_host, co
 
 /* Copy the state out / in.  vdf_host is [P][ncells][n] FP64 (P = 2 in 2-D,
  * 1 in 3-D; converted from/to the storage type), W_host is [ncells][dim+2].
- * avs_set_state with vdf_host == NULL sets phi = closure(g_eq(W), W).
- * Either pointer of avs_get_state may be NULL.  Both wait. */
+ * avs_set_state with vdf_host == NULL sets phi = closure(g_eq(W), W); with
+ * W_host == NULL it sets W to the moments of the given VDF (Eq. updat_W,
+ * AVS_E_NUMERIC if they are not physical).  Either pointer of avs_get_state
+ * may be NULL.  Both wait. */
 avs_status avs_get_state(avs_ctx *ctx, double *vdf_host, double *W_host);
 avs_status avs_set_state(avs_ctx *ctx, const double *vdf_host, const double *W_host);
 

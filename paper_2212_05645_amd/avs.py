@@ -296,9 +296,10 @@ class Case:
         return W
 
     def set_state(self, vdf, W):
+        """vdf None: closed Maxwellian of W; W None: W = moments of vdf."""
         v = None if vdf is None else np.ascontiguousarray(vdf, np.float64)
-        w = np.ascontiguousarray(W, np.float64)
-        _check(lib.avs_set_state(self.ctx, _ptr(v), w.ctypes.data))
+        w = None if W is None else np.ascontiguousarray(W, np.float64)
+        _check(lib.avs_set_state(self.ctx, _ptr(v), _ptr(w)))
 
     def get_cells(self, cells):
         c = np.ascontiguousarray(cells, np.int64)

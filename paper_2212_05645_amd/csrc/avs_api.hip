@@ -1175,15 +1175,22 @@ avs_status avs_get_state(avs_ctx* ctx, double* vdf_host, double* W_host) {
 
 avs_status avs_set_state(avs_ctx* ctx, const double* vdf_host, const double* W_host) {
   if (avs_status st = guard(ctx)) return st;
-  if (!W_host) return fail(AVS_E_INVALID, "W_host is required");
+  if (!W_host && !vdf_host) return fail(AVS_E_INVALID, "W_host or vdf_host is required");
   const int n = ctx->nleaf[ctx->lcur], ld = ctx->ld[ctx->lcur], D = ctx->D, N = D + 2;
-  for (int i = 0; i < ctx->nc; ++i) {
-    const double* w = W_host + (size_t)i * N;
-    double ke = 0;
-    for (int d = 0; d < D; ++d) ke += w[1 + d] * w[1 + d];
-    if (!(w[0] > 0) || !(w[1 + D] - 0.5 * ke / w[0] > 0)) return fail(AVS_E_INVALID, "W of cell %d is not physical", i);
+  auto physical = [&](const double* W) {
+    for (int i = 0; i < ctx->nc; ++i) {
+      const double* w = W + (size_t)i * N;
+      double ke = 0;
+      for (int d = 0; d < D; ++d) ke += w[1 + d] * w[1 + d];
+      if (!(w[0] > 0) || !(w[1 + D] - 0.5 * ke / w[0] > 0)) return i;
+    }
+    return -1;
+  };
+  if (W_host) {
+    const int bad_cell = physical(W_host);
+    if (bad_cell >= 0) return fail(AVS_E_INVALID, "W of cell %d is not physical", bad_cell);
+    CK(hipMemcpyAsync(ctx->W, W_host, sizeof(double) * ctx->nc * N, hipMemcpyHostToDevice, ctx->stream));
   }
-  CK(hipMemcpyAsync(ctx->W, W_host, sizeof(double) * ctx->nc * N, hipMemcpyHostToDevice, ctx->stream));
   if (vdf_host) {
     const size_t es = ctx->esize();
     if (ctx->prec == AVS_FP64) {
@@ -1202,6 +1209,19 @@ avs_status avs_set_state(avs_ctx* ctx, const double* vdf_host, const double* W_h
   }
   ctx->plan_valid = false;
   if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
+  if (!W_host) {
+    // W from the moments of the given VDF
+    std::vector<double> Wm((size_t)ctx->nc * N);
+    CK(hipMemcpyAsync(Wm.data(), ctx->mom, sizeof(double) * Wm.size(), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    const int bad_cell = physical(Wm.data());
+    if (bad_cell >= 0) {
+      ctx->failed = true;
+      return fail(AVS_E_NUMERIC, "moments of the given VDF are not physical in cell %d", bad_cell);
+    }
+    CK(hipMemcpyAsync(ctx->W, Wm.data(), sizeof(double) * Wm.size(), hipMemcpyHostToDevice, ctx->stream));
+    if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;   // q and the target's moments about the new W
+  }
   return check_bad(ctx);
 }
 

@@ -14,6 +14,7 @@ import pytest
 from oracle import avs_oracle as O
 from workloads import fields as F
 from workloads import meshes as MM
+from workloads import trees as TR
 
 pytestmark = pytest.mark.gpu
 
@@ -38,21 +39,21 @@ def fieldrel(a, b):
                for j in range(b.shape[1]))
 
 
+def otree(vspace, level, idx):
+    """The oracle's view of a generated leaf list."""
+    D = vspace['dim']
+    return O.Tree(D, np.asarray(vspace['lo'], np.float64)[:D], np.asarray(vspace['hi'], np.float64)[:D],
+                  np.asarray(vspace['base'], np.int64)[:D], int(vspace['max_level']),
+                  np.asarray(level, np.int64), np.asarray(idx, np.int64))
+
+
 def random_tree(vspace, seed, rounds, p=0.35):
-    t = O.base_forest(vspace['dim'], vspace['lo'], vspace['hi'], vspace['base'], vspace['max_level'])
-    rng = np.random.default_rng(seed)
-    for _ in range(rounds):
-        eff = np.where((rng.random(t.n) < p) & (t.level < t.max_level), 1, 0).astype(np.int8)
-        t = O.make_plan(eff, t).tree
-    return t
+    return otree(vspace, *TR.random_tree(vspace['dim'], vspace['base'], vspace['max_level'], seed, rounds, p))
 
 
 def resolved_tree(vspace, seed, p=0.35):
     """Every root split once, then a random fraction split again."""
-    t = O.base_forest(vspace['dim'], vspace['lo'], vspace['hi'], vspace['base'], vspace['max_level'])
-    t = O.make_plan(np.ones(t.n, np.int8), t).tree
-    rng = np.random.default_rng(seed)
-    return O.make_plan(np.where((rng.random(t.n) < p) & (t.level < t.max_level), 1, 0).astype(np.int8), t).tree
+    return otree(vspace, *TR.resolved_tree(vspace['dim'], vspace['base'], vspace['max_level'], seed, p))
 
 
 def make_pair(avs, mesh, vspace, gas, dt, prim0, tree=None, precision=0, noise=0.0, seed=0, Kv=1.0, cap=None):
@@ -64,10 +65,13 @@ def make_pair(avs, mesh, vspace, gas, dt, prim0, tree=None, precision=0, noise=0
         o.phi = o.initial_vdf(o.W)
         cs.set_leaves(tree.level, tree.idx)
     if noise > 0:
-        rng = np.random.default_rng(seed)
-        o.phi = o.phi * (1.0 + noise * rng.standard_normal(o.phi.shape))
+        # the same seeded relative perturbation of each side's own initial state;
+        # W follows as the moments of the perturbed VDF on each side
+        fac = 1.0 + noise * np.random.default_rng(seed).standard_normal(o.phi.shape)
+        o.phi = o.phi * fac
         o.W = o.vdf_moments()
-        cs.set_state(o.phi, o.W)
+        v0, _ = cs.get_state()
+        cs.set_state(v0 * fac, None)
     return cs, o
 
 
@@ -147,6 +151,39 @@ def test_3d_steps(avs, which):
     cs, o = make_pair(avs, mesh, vs, gas, dt, prim, tree=tree, noise=0.01, seed=6, Kv=0.0 if which == "sphere" else 1.0)
     cs.step(3)
     o.step(3)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+
+
+def test_3d_fp32_form_against_fp64_oracle(avs):
+    """The 3-D FP32 form (the sphere workload's form) on a small spherical
+    grid: fields within 1e-5 field-normalised after 5 steps, FP64 totals."""
+    c = F.sphere(nr=3, nth=4, nph=4, Ma=2.0, box=5.0, base=8, max_level=1, r1=1.5, first=0.2)
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=resolved_tree(c['vspace'], 8),
+                      precision=1, noise=0.01, seed=8, Kv=0.0)
+    cs.step(5)
+    o.step(5)
+    f, tot = cs.moments()
+    assert fieldrel(f.cpu().numpy(), o.fields()) < 1e-5
+    ot = o.totals()
+    assert np.max(np.abs(tot - ot)) < 1e-5 * np.max(np.abs(ot))
+
+
+def test_capacity_error_leaves_state_usable(avs):
+    """An adaptation that would exceed leaf_capacity reports AVS_E_CAPACITY,
+    builds no plan, and leaves the case stepping exactly as before."""
+    c = F.cavity(n=8, base=8, max_level=2)
+    tree = random_tree(c['vspace'], 12, 1, p=0.2)
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=tree, cap=tree.n + 10)
+    with pytest.raises(avs.AvsError) as e:
+        cs.adapt(-1.0, -2.0)                 # split everything: far beyond the capacity
+    assert e.value.status == avs.AVS_E_CAPACITY
+    with pytest.raises(avs.AvsError) as e:
+        cs.remap(2)
+    assert e.value.status == avs.AVS_E_STATE
+    assert cs.nleaves() == tree.n
+    cs.step(2)
+    o.step(2)
     v, W = cs.get_state()
     assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
 
@@ -287,7 +324,7 @@ def test_cavity_workload_with_adaptation(avs):
         o.adapt(c['C1'], c['C2'], probes=c['probes'])
         cs.remap(2)
         o.remap(2)
-    cs.set_state(None, o.W)
+    cs.set_state(None, cs.get_W())          # re-close from the GPU's own (unchanged) W
     o.phi = o.initial_vdf(o.W)
     cs.step(20)
     o.step(20)
@@ -306,18 +343,14 @@ def test_cavity_workload_with_adaptation(avs):
 # ----------------------------------------- full size, sampled outputs ------
 def test_full_size_cylinder_sampled(avs):
     """The cylinder workload at full size (O-grid 128 x 256, 32^2 roots, 3
-    levels), one step in the launch configuration the benchmark times.  The
-    tree is the paper's step-0 tree built by the oracle from the probe states
-    alone; both sides start from the same primitive field.  Sampled cells
-    (wall, shock layer, wake, far field) are recomputed by the oracle from
-    their two-ring neighbourhood and compared element by element."""
+    levels), one step in the launch configuration the benchmark times, on a
+    seeded random tree of all three levels (about 16 k leaves); both sides
+    start from the same primitive field.  Sampled cells (wall, shock layer,
+    wake, far field) are recomputed by the oracle from their two-ring
+    neighbourhood and compared element by element."""
     c = F.cylinder()
     vs = c['vspace']
-    t = O.base_forest(2, vs['lo'], vs['hi'], vs['base'], vs['max_level'])
-    for _ in range(vs['max_level']):
-        Mk = O.criterion(np.zeros((2, 0, t.n)), np.zeros((0, 4)), t, c['gas']['R'], probes=c['probes'])
-        eff = O.resolve_merges(O.raw_flags(Mk, t, c['C1'], c['C2']), t)
-        t = O.make_plan(eff, t).tree
+    t = random_tree(vs, 77, 3, p=0.5)
     assert 2000 < t.n < 40000
     gas = O.gas_from(c['gas'])
     g = dict(R=gas.R, Pr=gas.Pr, omega=gas.omega, mu_ref=gas.mu_ref, T_ref=gas.T_ref, model=gas.model)
