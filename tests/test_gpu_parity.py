@@ -58,8 +58,8 @@ def resolved_tree(vspace, seed, p=0.35):
 
 def make_pair(avs, mesh, vspace, gas, dt, prim0, tree=None, precision=0, noise=0.0, seed=0, Kv=1.0, cap=None):
     o = O.Solver(mesh, vspace, gas, dt, Kv, prim0)
-    g = dict(R=o.gas.R, Pr=o.gas.Pr, omega=o.gas.omega, mu_ref=o.gas.mu_ref, T_ref=o.gas.T_ref, model=o.gas.model)
-    cs = avs.Case(mesh, vspace, g, dt, Kv, prim0, precision=precision, leaf_capacity=cap)
+    # each side derives mu_ref from Kn itself (the gas dict carries Kn, or mu_ref directly)
+    cs = avs.Case(mesh, vspace, gas, dt, Kv, prim0, precision=precision, leaf_capacity=cap)
     if tree is not None:
         o.tree = tree
         o.phi = o.initial_vdf(o.W)
@@ -353,8 +353,7 @@ def test_full_size_cylinder_sampled(avs):
     t = random_tree(vs, 77, 3, p=0.5)
     assert 2000 < t.n < 40000
     gas = O.gas_from(c['gas'])
-    g = dict(R=gas.R, Pr=gas.Pr, omega=gas.omega, mu_ref=gas.mu_ref, T_ref=gas.T_ref, model=gas.model)
-    cs = avs.Case(c['mesh'], vs, g, c['dt'], c['venkat_K'], c['prim0'], leaf_capacity=t.n)
+    cs = avs.Case(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'], leaf_capacity=t.n)
     cs.set_leaves(t.level, t.idx)
     cs.step(1)
     nth = c['mesh']['shape'][1]
@@ -394,10 +393,7 @@ def test_batch_matches_single_cases_bit_for_bit(avs, prec):
     def build():
         out = []
         for mesh, vs, gas, dt, K, prim, tree in specs:
-            g = dict(gas)
-            if g.get('mu_ref') is None:
-                g['mu_ref'] = O.gas_from(gas).mu_ref
-            cs = avs.Case(mesh, vs, g, dt, K, prim, precision=prec, stream=stream)
+            cs = avs.Case(mesh, vs, gas, dt, K, prim, precision=prec, stream=stream)
             cs.set_leaves(tree.level, tree.idx)
             out.append(cs)
         return out
