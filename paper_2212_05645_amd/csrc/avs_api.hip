@@ -57,7 +57,7 @@ struct LeafBuf {
 }  // namespace
 
 struct avs_ctx {
-  int D, P, maxf, nm, prec;
+  int D, P, maxf, prec;
   int nc, nf, nbc, n_int, n_bnd;
   int64_t cap;
   int lmax, base[3];
@@ -80,7 +80,7 @@ struct avs_ctx {
   int nleaf[2] = {0, 0};
   int ld[2] = {0, 0};
 
-  double *W, *Wn, *q, *mom, *tpar, *lam, *fpar, *Fbar, *F, *part, *bden, *bfin, *bcpair, *momp, *res, *tot;
+  double *W, *Wn, *q, *mom, *tpar, *lam, *fpar, *F, *bden, *bfin, *bcpair, *momp, *res, *tot;
   double *cc, *crit_part, *Mk, *probe_cc, *probe_prim;
   int8_t *raw, *eff;
   int *cnt, *off, *pkind, *psrc, *pchild, *bad;
@@ -234,9 +234,7 @@ void carve(avs_ctx& x, Carver& c) {
   x.tpar = c.take<double>(nc * NPAR);
   x.lam = c.take<double>(nc * N);
   x.fpar = c.take<double>((nf + 1) * NPAR);
-  x.Fbar = c.take<double>((nf + 1) * N);
   x.F = c.take<double>((nf + 1) * N);
-  x.part = c.take<double>(nc * mf * x.nm);
   x.bden = c.take<double>(nf + 1);
   x.bfin = c.take<double>((nf + 1) * N);
   x.bcpair = c.take<double>((size_t)(x.nbc + 1) * x.P * cap);
@@ -269,7 +267,6 @@ void fill_dims(avs_ctx& x, const avs_vspace* vs, const avs_pmesh* pm, const avs_
   x.D = vs->dim;
   x.P = x.D == 2 ? 2 : 1;
   x.maxf = x.D == 2 ? MAXF2 : MAXF3;
-  x.nm = x.D == 2 ? NM2 : NM3;
   x.prec = op->precision;
   x.nc = (int)pm->ncells;
   x.nf = (int)pm->nfaces;

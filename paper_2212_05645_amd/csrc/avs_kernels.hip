@@ -1446,25 +1446,6 @@ __global__ void k_fields(int nc, GasP gas, const double* __restrict__ W, const d
   for (int d = 0; d < D; ++d) o[2 + D + d] = q[(size_t)i * D + d];
 }
 
-// Copy rows between the storage type and FP64 host staging [P][rows][n].
-template <typename T>
-__global__ void k_pack(int P, int nrow, int n, int ld, size_t cs, const int64_t* __restrict__ rows,
-                       const T* __restrict__ vdf, double* __restrict__ out) {
-  const int k = blockIdx.x * BLOCK + threadIdx.x;
-  const int r = blockIdx.y, p = blockIdx.z;
-  if (k >= n) return;
-  const size_t c = rows ? (size_t)rows[r] : (size_t)r;
-  out[((size_t)p * nrow + r) * n + k] = (double)vdf[p * cs + c * ld + k];
-}
-
-template <typename T>
-__global__ void k_unpack(int P, int nrow, int n, int ld, size_t cs, const double* __restrict__ in, T* __restrict__ vdf) {
-  const int k = blockIdx.x * BLOCK + threadIdx.x;
-  const int r = blockIdx.y, p = blockIdx.z;
-  if (k >= n) return;
-  vdf[p * cs + (size_t)r * ld + k] = (T)in[((size_t)p * nrow + r) * n + k];
-}
-
 }  // namespace avs
 
 namespace avs {
