@@ -252,7 +252,9 @@ void avs_batch_destroy(avs_batch *batch);
  * bytes; all its work runs on the stream given at creation.  Feature rows
  * are bfloat16 [n][32] (28 used, the rest zero); labels are effective flags
  * (-1 merge, 0 keep, +1 split) as avs_adapt writes them; rows_dev (int32
- * [n], or NULL for 0..n-1) selects the dataset rows of a batch. */
+ * [n], or NULL for 0..n-1) selects the dataset rows of a batch: every entry
+ * must index a row that exists in feat_dev and flags_dev (device data, not
+ * checked). */
 typedef struct avs_mlp avs_mlp;
 typedef struct {
   double lr, beta1, beta2, eps;   /* Adam (Kingma and Ba, 2015) */

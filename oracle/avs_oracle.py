@@ -26,7 +26,14 @@ adaptive velocity space for general discrete velocity framework", arXiv
   conservation correction f = f' + g(W) - g(W') (Sec. 3.3).
 
 Where the paper leaves a point open, the docstring states the reading
-taken; each function below names the passage it follows.  Every array is float64.
+taken; each function below names the passage it follows.
+
+Parity unpinned (readings that no closed form, invariant or printed value
+of the paper can check; both implementations share them as conventions):
+the interface heat-flux factor tau/(tau + h Pr) in ``face_vdf``, the
+Venkatakrishnan constant K of ``venkat_psi`` (eps^2 = (K V^(1/D))^3), the
+wall and far-field treatment of incoming leaves in ``face_vdf`` beyond zero
+net mass flux, and the threshold C1 of ``raw_flags``.  Every array is float64.
 Nothing here is blocked, fused or reordered for speed: loops run over cells
 and faces, NumPy vectorises over the velocity axis only.
 """
