@@ -228,3 +228,53 @@ def test_training_reduces_loss_and_learns_labels(avs):
     assert acc > max(acc0, 0.9)
     recall = np.diag(cm) / np.maximum(cm.sum(axis=1), 1)
     assert np.all(cm.sum(axis=1) > 100) and np.all(recall > 0.8), recall
+
+
+def test_trained_proposal_gains_over_the_criterion_scan(avs):
+    """What the trained network gains: on a 64 x 128 cylinder with about 20 k
+    leaves, the judged proposal adapts faster than the criterion scan (which
+    reads every (cell, leaf) value), passes the judge at 1e-4 without falling
+    back, and lands within 15 % of the criterion's leaf count."""
+    import torch
+    from paper_2212_05645_amd import learned
+    c = F.cylinder(nr=64, nth=128, seed=3)
+    C1 = 1.74658e-06
+    C2 = math.exp(-8) * C1
+    cs = avs.Case(c['mesh'], c['vspace'], c['gas'], c['dt'], c['venkat_K'], c['prim0'], leaf_capacity=65536)
+    L0 = cs.leaves()
+    base = (L0['level'].copy(), L0['idx'].copy())
+    W0 = cs.get_W()
+
+    def step0():
+        cs.set_leaves(*base)
+        cs.set_state(None, W0)
+        for _ in range(3):
+            cs.adapt(C1, C2, probes=c['probes'])
+            cs.remap(2)
+        cs.set_state(None, W0)
+    step0()
+    mlp = avs.Mlp(learned.init_params(0), max_batch=16384)
+    ds = learned.Dataset(800000)
+    learned.collect(cs, mlp, ds, C1, C2, events=8, sweeps_between=5, base=base, levels=(0, 1, 2),
+                    exact_restore=False)
+    learned.train(mlp, ds, epochs=6, batch=8192, lr=2e-3, seed=0)
+    # the same state for both: step-0 tree, 10 sweeps
+    times = {}
+    counts = {}
+    for mode in ("plain", "learned"):
+        step0()
+        cs.step(10)
+        torch.cuda.synchronize()
+        best = 1e9
+        for _ in range(3):
+            t0 = time.perf_counter()
+            if mode == "plain":
+                _, n_new = cs.adapt(C1, C2)
+            else:
+                _, n_new, fb = cs.adapt_learned(mlp, C1, C2, tail_tol=1e-4)
+                assert not fb
+            best = min(best, time.perf_counter() - t0)
+        times[mode], counts[mode] = best, n_new
+    print("adapt s", times, "leaves", counts)
+    assert times["learned"] < times["plain"]
+    assert abs(counts["learned"] - counts["plain"]) <= 0.15 * counts["plain"]
