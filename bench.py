@@ -177,6 +177,25 @@ def measured_traffic(tag, kernel):
     return per.get(kernel)
 
 
+def measured_copy_bandwidth(torch, nbytes=2 ** 31, reps=5):
+    """Read + write GB/s of a plain device-to-device copy on this GPU (the
+    practical HBM ceiling the sweep kernels are compared with)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def vdf_bytes_per_node(P, es, rows_per_cell):
     """Algorithmic HBM bytes per (cell, leaf) of one launch of each VDF
     kernel: every distinct byte it must read or write, once.  A leaf row of
@@ -449,6 +468,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    copy_gbps = measured_copy_bandwidth(torch)
     w, C1, r = run_form(args, args.precision)
     P, es = 2, (8 if args.precision == "fp64" else 4)
     prof = r["prof"]
@@ -468,6 +488,18 @@ def main():
     for k in kern:
         if k in bpn:
             kern[k]["GB/s"] = bpn[k] * w.nc * nv / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
+    roofline["measured_copy_GBps"] = copy_gbps
+    roofline["frac_of_copy"] = achieved / 1e9 / copy_gbps
+    # the whole sweep (all step kernels of one step) against two byte counts:
+    # this design's (interface rows written once, read twice) and the minimum
+    # of any implementation (read the VDF twice, write it once)
+    sweep_k = [k for k in ("passA", "face", "face_eqflux", "macro", "target", "passC") if k in kern]
+    sweep_s = sum(kern[k]["ms_per_launch"] for k in sweep_k) * 1e-3
+    design_b = sum(bpn.get(k, 0.0) for k in sweep_k)
+    min_b = 3 * P * es
+    roofline["sweep"] = {"ms": sweep_s * 1e3, "kernels": sweep_k,
+                         "design_bytes_per_node": design_b, "design_frac": design_b * w.nc * nv / sweep_s / HBM_PEAK,
+                         "min_bytes_per_node": min_b, "min_frac": min_b * w.nc * nv / sweep_s / HBM_PEAK}
     value = r["updates"] / (r["ms"] * 1e-3)
     forms = {args.precision: {"cycle_updates_per_s": value, "sweep_updates_per_s": r["sweep_rate"],
                               "sweep_ms": r["sweep_ms"], "leaves": r["sweep_leaves"]}}
