@@ -83,7 +83,7 @@ def _load():
         "avs_batch_create": (I32, [I32, VP, VP, C.c_size_t, P(VP)]),
         "avs_batch_step": (I32, [VP, I32, I32]),
         "avs_batch_check": (I32, [VP]),
-        "avs_batch_tune": (I32, [VP, P(I32)]),
+        "avs_batch_tune": (I32, [VP, VP]),
         "avs_batch_adapt": (I32, [VP, VP, VP, VP]),
         "avs_batch_remap": (I32, [VP, I32]),
         "avs_batch_destroy": (None, [VP]),
@@ -442,9 +442,10 @@ class Batch:
         _check(lib.avs_batch_remap(self.b, int(correction)))
 
     def tune(self):
-        ch = C.c_int32()
-        _check(lib.avs_batch_tune(self.b, C.byref(ch)))
-        return ch.value
+        """Pass-A leaf chunk per leaf-count bucket (<1024, <4096, <16384, more)."""
+        ch = (C.c_int32 * 4)()
+        _check(lib.avs_batch_tune(self.b, ch))
+        return list(ch)
 
     def close(self):
         if getattr(self, "b", None):

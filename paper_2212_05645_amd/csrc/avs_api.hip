@@ -559,13 +559,13 @@ struct avs_batch {
   int D = 2, prec = 0;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
-  int chunk = CHUNK;
+  int chunk[4] = {CHUNK, CHUNK, CHUNK, CHUNK};   // pass-A leaves per workgroup, per leaf-count bucket
   int nblk[BK_N] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_steps = -1;
   int graph_nblk[BK_N] = {};   // compared only once a graph exists
-  int graph_chunk = -1;
+  int graph_chunk[4] = {-1, -1, -1, -1};
   std::vector<char> host_args;
   ~avs_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -574,6 +574,9 @@ struct avs_batch {
 };
 
 namespace {
+
+// Leaf-count bucket of a case for the pass-A tile choice.
+int leaf_bucket(int nleaves) { return nleaves < 1024 ? 0 : nleaves < 4096 ? 1 : nleaves < 16384 ? 2 : 3; }
 
 size_t batch_args_bytes(int ncase) { return (size_t)round_up(2 * (size_t)ncase * sizeof(CaseArgs<double>), 256); }
 
@@ -618,11 +621,12 @@ avs_status batch_upload(avs_batch* b) {
   for (int k = 0; k < BK_N; ++k) off[k * (n + 1)] = 0;
   for (int i = 0; i < n; ++i) {
     avs_ctx* c = b->cases[i];
-    args[i] = case_args<T>(c, 0, b->chunk);
-    args[n + i] = case_args<T>(c, 1, b->chunk);
+    const int ch = b->chunk[leaf_bucket(c->nleaf[c->lcur])];
+    args[i] = case_args<T>(c, 0, ch);
+    args[n + i] = case_args<T>(c, 1, ch);
     const int nl = c->nleaf[c->lcur];
     const int gx = (int)round_up(c->nc, 8);
-    const int cnt[BK_N] = {gx * ((nl + b->chunk - 1) / b->chunk), c->nf, c->nf, (c->nc + BLOCK - 1) / BLOCK, c->nc, gx};
+    const int cnt[BK_N] = {gx * ((nl + ch - 1) / ch), c->nf, c->nf, (c->nc + BLOCK - 1) / BLOCK, c->nc, gx};
     for (int k = 0; k < BK_N; ++k) off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + cnt[k];
   }
   for (int k = 0; k < BK_N; ++k) b->nblk[k] = off[k * (n + 1) + n];
@@ -668,7 +672,8 @@ avs_status batch_run(avs_batch* b, int nsteps, bool graph) {
     st = b->D == 2 ? (f64 ? batch_launch<2, double>(b, nsteps) : batch_launch<2, float>(b, nsteps))
                    : (f64 ? batch_launch<3, double>(b, nsteps) : batch_launch<3, float>(b, nsteps));
   } else {
-    bool same = b->exec && b->graph_steps == nsteps && b->graph_chunk == b->chunk;
+    bool same = b->exec && b->graph_steps == nsteps;
+    for (int q = 0; q < 4; ++q) same = same && b->graph_chunk[q] == b->chunk[q];
     for (int k = 0; k < BK_N; ++k) same = same && b->graph_nblk[k] == b->nblk[k];
     if (!same) {
       if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
@@ -683,7 +688,7 @@ avs_status batch_run(avs_batch* b, int nsteps, bool graph) {
       b->graph = gr;
       CK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
       b->graph_steps = nsteps;
-      b->graph_chunk = b->chunk;
+      for (int q = 0; q < 4; ++q) b->graph_chunk[q] = b->chunk[q];
       for (int k = 0; k < BK_N; ++k) b->graph_nblk[k] = b->nblk[k];
     }
     CK(hipGraphLaunch(b->exec, b->stream));
@@ -1398,25 +1403,35 @@ avs_status avs_batch_tune(avs_batch* b, int32_t* chunk_host) {
   if (!b) return fail(AVS_E_INVALID, "null batch");
   avs_ctx* ctx = nullptr;
   const int cand[] = {512, 1024, 2048, 4096, 8192};
+  bool present[4] = {false, false, false, false};
+  for (avs_ctx* c : b->cases) present[leaf_bucket(c->nleaf[c->lcur])] = true;
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  float best = 1e30f;
-  int arg = b->chunk;
-  for (int c : cand) {
-    b->chunk = c;
-    CK(hipEventRecord(e0, b->stream));
-    if (avs_status st = batch_run(b, 2, false)) return st;
-    CK(hipEventRecord(e1, b->stream));
-    CK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    CK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) { best = ms; arg = c; }
+  // one bucket at a time, the others at their current choice
+  for (int q = 0; q < 4; ++q) {
+    if (!present[q]) continue;
+    float best = 1e30f;
+    int arg = b->chunk[q];
+    for (int c : cand) {
+      b->chunk[q] = c;
+      CK(hipEventRecord(e0, b->stream));
+      if (avs_status st = batch_run(b, 2, false)) return st;
+      CK(hipEventRecord(e1, b->stream));
+      CK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        arg = c;
+      }
+    }
+    b->chunk[q] = arg;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->chunk = arg;
-  if (chunk_host) *chunk_host = arg;
+  if (chunk_host)
+    for (int q = 0; q < 4; ++q) chunk_host[q] = b->chunk[q];
   return AVS_OK;
 }
 
