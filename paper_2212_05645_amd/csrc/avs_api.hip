@@ -407,7 +407,7 @@ avs_status launch_step(avs_ctx* ctx, bool last_residual) {
     ProfScope ps(ctx, K_PASSA);
     const int nch = (L.n + CHUNK - 1) / CHUNK;
     const int gx = (int)round_up(ctx->nc, 8);
-    k_passA<D, T><<<dim3(gx, nch), BLOCK, 0, ctx->stream>>>(ctx->geo, L, vin, ctx->h, (T*)ctx->fv, CHUNK);
+    k_passA<D, T><<<dim3(gx, nch), BLOCK, 0, ctx->stream>>>(ctx->geo, L, vin, ctx->bcpair, ctx->h, (T*)ctx->fv, CHUNK);
     CKL();
   }
   {
@@ -436,8 +436,7 @@ avs_status launch_step(avs_ctx* ctx, bool last_residual) {
   {
     ProfScope ps(ctx, K_PASSC);
     k_passC<D, T><<<(unsigned)round_up(ctx->nc, 8), BLOCK, (size_t)(MAXF + 1) * D * nu * sizeof(T), ctx->stream>>>(
-        ctx->geo, L, ctx->vg, vin, (const T*)ctx->fv, vout, ctx->fpar, ctx->tpar, ctx->lam, ctx->bcpair, ctx->mom,
-        ctx->q);
+        ctx->geo, L, ctx->vg, vin, (const T*)ctx->fv, vout, ctx->fpar, ctx->tpar, ctx->lam, ctx->mom, ctx->q);
     CKL();
   }
   if (last_residual) {

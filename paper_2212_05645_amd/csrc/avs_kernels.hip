@@ -27,6 +27,18 @@ constexpr int waves_hint() { return (D == 3 || sizeof(T) == 8) ? AVS_WAVES_F64 :
 template <typename T>
 __device__ __forceinline__ double ld_(const T* p) { return (double)(*p); }
 
+// Element at a 32-bit byte offset from a workgroup-uniform row pointer: the
+// offset stays in one vector register and the row pointer in scalar
+// registers (no per-lane 64-bit address arithmetic).  Rows are < 4 GiB.
+template <typename T>
+__device__ __forceinline__ T at_(const T* row, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + off);
+}
+template <typename T>
+__device__ __forceinline__ T* ptr_at_(T* row, unsigned off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(row) + off);
+}
+
 template <int D>
 struct Cfg {
   static constexpr int P = (D == 2) ? 2 : 1;
@@ -474,27 +486,39 @@ template <int D, typename T>
 __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi)[Cfg<D>::P],
                                          T (&lg)[Cfg<D>::P][D]) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+  const unsigned ko = (unsigned)k * (unsigned)sizeof(T);
   const int ns = st.ns;
-  T pmax[P], pmin[P], grad[P][D];
+  // the neighbour extrema are kept as differences from phi (rounding is
+  // monotone, so max_j(v_j - phi) equals max_j(v_j) - phi exactly, and the
+  // differences, being arithmetic results, need no NaN canonicalisation)
+  T dmax[P], dmin[P], grad[P][D];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    phi[p] = st.own[p][k];
-    pmax[p] = phi[p];
-    pmin[p] = phi[p];
+    phi[p] = at_(st.own[p], ko);
+    dmax[p] = 0;
+    dmin[p] = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d) grad[p][d] = 0;
   }
+  // every neighbour value is loaded before any is used, so that the loads of
+  // a leaf are in flight together (a slot without an interior neighbour
+  // points at the cell's own row and is skipped below)
+  T nv[MAXF][P];
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s)
+#pragma unroll
+    for (int p = 0; p < P; ++p) nv[s][p] = at_(st.nb[s][p], ko);
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
     if (st.nbmask & (1u << s)) {
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        const T v = st.nb[s][p][k];
+        const T v = nv[s][p];
         const T dv = v - phi[p];
 #pragma unroll
         for (int d = 0; d < D; ++d) grad[p][d] += dv * st.cf[s][d];
-        pmax[p] = fmax(v, pmax[p]);
-        pmin[p] = fmin(v, pmin[p]);
+        dmax[p] = fmax(dv, dmax[p]);
+        dmin[p] = fmin(dv, dmin[p]);
       }
     }
   }
@@ -507,7 +531,7 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     T d2s[MAXF];
-    const T up0 = pmax[p] - phi[p], dn0 = phi[p] - pmin[p];
+    const T up0 = dmax[p], dn0 = -dmin[p];
     T m = fmax(up0, dn0);
 #pragma unroll
     for (int s = 0; s < MAXF; ++s) {
@@ -556,32 +580,43 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
 // leaf chunks) with cells fastest, so that a cell and its neighbours read
 // the same chunk of their rows at about the same time.
 template <int D, typename T>
-__device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ vdf,
-                                                                      double h, T* __restrict__ fv, int chunk, int bx, int by) {
+__device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ vdf, const double* __restrict__ bcpair,
+                                        double h, T* __restrict__ fv, int chunk, int bx, int by) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
   const int i = xcd_cell(g, bx);
   if (i < 0) return;
   const int k0 = by * chunk, k1 = min(L.n, k0 + chunk);
   const size_t cs = (size_t)g.nc * L.ld;
   const size_t fs = (size_t)g.nf * L.ld;   // component stride of the interface buffer
+  // where the per-cell constants live: scalar registers (loaded from global
+  // memory) or vector registers (staged through LDS).  In 2-D the face
+  // normals go through LDS (fewer scalar spills), and in 2-D FP32 also the
+  // LSQ coefficients and face offsets; 3-D keeps them all scalar (its vector
+  // registers bound the occupancy).
   constexpr bool lds_consts = D == 2 && sizeof(T) == 4;
+  constexpr bool lds_nrm = D == 2;
   __shared__ T s_cf[MAXF * D], s_dd[MAXF * D];
   __shared__ double s_nrm[MAXF * D], s_sig[MAXF];
   Stencil<D, T> st;
-  double nrm[MAXF][D], sig[MAXF];
+  double nrm[MAXF][D];
+  unsigned lside = 0;          // bit s: the cell is the L side of face s
   T* row[MAXF][P];
-  if constexpr (lds_consts) {
+  if constexpr (lds_nrm) {
     const int ns = g.nslot[i];
     if (threadIdx.x < MAXF * D) {
       const int s = threadIdx.x / D, d = threadIdx.x % D;
       const int j = s < ns ? g.s_nbr[i * MAXF + s] : -1;
       const int f = s < ns ? g.s_face[i * MAXF + s] : 0;
-      s_cf[threadIdx.x] = j >= 0 ? (T)g.s_lsq[(size_t)i * MAXF * D + threadIdx.x] : (T)0;
-      s_dd[threadIdx.x] = s < ns ? (T)g.s_d[(size_t)i * MAXF * D + threadIdx.x] : (T)0;
+      if constexpr (lds_consts) {
+        s_cf[threadIdx.x] = j >= 0 ? (T)g.s_lsq[(size_t)i * MAXF * D + threadIdx.x] : (T)0;
+        s_dd[threadIdx.x] = s < ns ? (T)g.s_d[(size_t)i * MAXF * D + threadIdx.x] : (T)0;
+      }
       s_nrm[threadIdx.x] = g.f_nrm[(size_t)f * D + d];
       if (d == 0) s_sig[s] = s < ns ? g.s_sig[i * MAXF + s] : 0.0;
     }
     __syncthreads();
+  }
+  if constexpr (lds_consts) {
     load_stencil<D, T>(g, vdf, cs, L.ld, i, st, s_cf, s_dd);
   } else {
     load_stencil<D, T>(g, vdf, cs, L.ld, i, st);
@@ -589,12 +624,12 @@ __device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ v
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
     const int f = s < st.ns ? g.s_face[i * MAXF + s] : 0;
-    if constexpr (lds_consts) {
-      sig[s] = s_sig[s];
+    if constexpr (lds_nrm) {
+      if (s_sig[s] > 0.0) lside |= 1u << s;
 #pragma unroll
       for (int d = 0; d < D; ++d) nrm[s][d] = s_nrm[s * D + d];
     } else {
-      sig[s] = s < st.ns ? g.s_sig[i * MAXF + s] : 0.0;
+      if (s < st.ns && g.s_sig[i * MAXF + s] > 0.0) lside |= 1u << s;
 #pragma unroll
       for (int d = 0; d < D; ++d) nrm[s][d] = g.f_nrm[(size_t)f * D + d];
     }
@@ -605,22 +640,30 @@ __device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ v
   for (int k = k0 + threadIdx.x; k < k1; k += BLOCK) {
     double xi[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) xi[d] = L.xi[d * L.cap + k];
+    for (int d = 0; d < D; ++d) xi[d] = at_(L.xi + (size_t)d * L.cap, (unsigned)k * 8u);
     T phi[P], lg[P][D];
     lim_grad<D, T>(st, k, phi, lg);
 #pragma unroll
     for (int s = 0; s < MAXF; ++s) {
       if (s < st.ns) {
         const double sn = normal_speed<D>(xi, nrm[s]);
-        const bool up = sig[s] > 0.0 ? (sn >= 0.0) : (sn < 0.0);
+        const bool up = (lside >> s) & 1u ? (sn >= 0.0) : (sn < 0.0);
         if (up) {
 #pragma unroll
           for (int p = 0; p < P; ++p) {
             T v = 0;
 #pragma unroll
             for (int d = 0; d < D; ++d) v += lg[p][d] * (st.dd[s][d] - (T)xi[d] * th);
-            __builtin_nontemporal_store((T)(phi[p] + v), &row[s][p][k]);   // read by later kernels only
+            __builtin_nontemporal_store((T)(phi[p] + v), ptr_at_(row[s][p], (unsigned)k * (unsigned)sizeof(T)));   // read by later kernels only
           }
+        } else if (!((st.nbmask >> s) & 1u)) {
+          // incoming leaf of a boundary face: the wall or far-field
+          // Maxwellian, unscaled (the wall density ratio is applied in pass C)
+          const int bc = -1 - g.f_R[g.s_face[i * MAXF + s]];
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            __builtin_nontemporal_store((T)bcpair[((size_t)bc * P + p) * L.cap + k],
+                                        ptr_at_(row[s][p], (unsigned)k * (unsigned)sizeof(T)));
         }
       }
     }
@@ -629,8 +672,9 @@ __device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ v
 
 template <int D, typename T>
 __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passA(Geo g, Leaves L, const T* __restrict__ vdf,
-                                                                      double h, T* __restrict__ fv, int chunk) {
-  d_passA<D, T>(g, L, vdf, h, fv, chunk, blockIdx.x, blockIdx.y);
+                                                                      const double* __restrict__ bcpair, double h,
+                                                                      T* __restrict__ fv, int chunk) {
+  d_passA<D, T>(g, L, vdf, bcpair, h, fv, chunk, blockIdx.x, blockIdx.y);
 }
 
 // Flux of a raw-moment set through normal n: (n.m1, n.m2, n.e1).
@@ -681,9 +725,10 @@ __device__ __forceinline__ void d_face(Geo g, Leaves L, const R* __restrict__ fv
     double xi[D], A;
     int u[D];
     leaf_load<D>(L, k, xi, A, u);
-    if (Rc < 0 && normal_speed<D>(xi, n) < 0.0) continue;     // incoming leaf of a boundary face
+    // loaded with the leaf data, before the test, so both are in flight together
     const double G = (double)fv[(size_t)f * L.ld + k];
     const double H = P == 2 ? (double)fv[fs + (size_t)f * L.ld + k] : 0.0;
+    if (Rc < 0 && normal_speed<D>(xi, n) < 0.0) continue;     // incoming leaf of a boundary face
     double xi2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
@@ -915,25 +960,44 @@ __global__ __launch_bounds__(BLOCK) void k_target(Geo g, Leaves L, VGrid vg, con
 
 // -------------------------------------------------- pass C (S6, S7, S10)
 // Interface VDFs of every face of the cell (upwind reconstruction from the
-// interface buffer, blended with the interface Shakhov equilibrium; wall or
-// far-field Maxwellian on incoming leaves of boundary faces), flux
-// divergence, relaxation towards the closed Shakhov target, store
-// phi^{n+1}, and the moments and heat flux of phi^{n+1} for the next step.
-// Arithmetic in T, sums in FP64; the upwind sign in FP64 in both forms.
+// interface buffer, blended with the interface Shakhov equilibrium; on
+// incoming leaves of a boundary face the wall or far-field Maxwellian that
+// pass A stored there, times the wall density ratio), flux divergence,
+// relaxation towards the closed Shakhov target, store phi^{n+1}, and the
+// moments and heat flux of phi^{n+1} for the next step.  Arithmetic in T,
+// sums in FP64; the upwind sign in FP64 in both forms.
+//
+// All loads of a leaf (leaf table, phi, every interface row) are issued
+// before any of them is used.  In 2-D FP64 the loads of leaf k + BLOCK are
+// also issued before leaf k is processed (two register sets used in turn),
+// so that a wave keeps two leaves of memory traffic in flight; the other
+// forms have fewer spare registers and run faster with one.
+template <int D, typename T>
+constexpr bool passc_two_leaves() { return D == 2 && sizeof(T) == 8; }
+
+template <int D, typename T>
+struct LeafIn {
+  static constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+  double xi[D], A;
+  int u[D];
+  T phi[P];
+  T row[MAXF][P];
+};
+
 template <int D, typename T>
 __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
-                                                     const T* __restrict__ fv, T* __restrict__ vout,
-                                                     const double* __restrict__ fpar, const double* __restrict__ tpar,
-                                                     const double* __restrict__ lam, const double* __restrict__ bcpair,
-                                                     double* __restrict__ mom, double* __restrict__ qout, int bx, int by) {
+                                        const T* __restrict__ fv, T* __restrict__ vout,
+                                        const double* __restrict__ fpar, const double* __restrict__ tpar,
+                                        const double* __restrict__ lam, double* __restrict__ mom,
+                                        double* __restrict__ qout, int bx) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF, N = D + 2;
   extern __shared__ double lds_d[];
   T* lds = reinterpret_cast<T*>(lds_d);
   __shared__ double red[4 * (N + D)];
   __shared__ T spar[(MAXF + 1) * NPAR];
   __shared__ double snrm[MAXF][D];
-  __shared__ int sface[MAXF], snbr[MAXF], sbc[MAXF];
-  __shared__ T ssa[MAXF];
+  __shared__ int sface[MAXF], snbr[MAXF];
+  __shared__ T ssa[MAXF], ssc[MAXF];
   __shared__ T slam[N];
   const int i = xcd_cell(g, bx);
   if (i < 0) return;
@@ -956,8 +1020,11 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
     const int f = s < ns ? g.s_face[i * MAXF + s] : 0;
     sface[s] = f;
     snbr[s] = s < ns ? g.s_nbr[i * MAXF + s] : -1;
-    sbc[s] = (s < ns && g.f_R[f] < 0) ? -1 - g.f_R[f] : 0;
     ssa[s] = s < ns ? (T)g.s_sigA[i * MAXF + s] : (T)0;
+    // wall: density ratio of the incoming Maxwellian (first record slot of a
+    // boundary face); far field and interior faces: 1
+    const bool wall = s < ns && g.f_R[f] < 0 && g.bc_kind[-1 - g.f_R[f]] == 0;
+    ssc[s] = wall ? (T)fpar[(size_t)f * NPAR] : (T)1;
     for (int d = 0; d < D; ++d) snrm[s][d] = g.f_nrm[(size_t)f * D + d];
   }
   if (threadIdx.x < N) slam[threadIdx.x] = (T)lam[(size_t)i * N + threadIdx.x];
@@ -974,62 +1041,53 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
   double acc[N + D];
 #pragma unroll
   for (int m = 0; m < N + D; ++m) acc[m] = 0.0;
-  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[D], A;
-    int u[D];
-    leaf_load<D>(L, k, xi, A, u);
+
+  auto load = [&](int k, LeafIn<D, T>& x) {
+    leaf_load<D>(L, k, x.xi, x.A, x.u);
+#pragma unroll
+    for (int p = 0; p < P; ++p) x.phi[p] = vin[p * cs + (size_t)i * L.ld + k];
+    // unconditional, so that all rows of the leaf are in flight together (a
+    // slot beyond the cell's faces reads face 0 and is never used)
+#pragma unroll
+    for (int s = 0; s < MAXF; ++s)
+#pragma unroll
+      for (int p = 0; p < P; ++p) x.row[s][p] = fv[p * fs + (size_t)sface[s] * L.ld + k];
+  };
+  auto process = [&](int k, const LeafIn<D, T>& x) {
     T xr[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) xr[d] = (T)xi[d];
-    T phi[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) phi[p] = vin[p * cs + (size_t)i * L.ld + k];
+    for (int d = 0; d < D; ++d) xr[d] = (T)x.xi[d];
     T div[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) div[p] = 0;
-    // all interface rows of the leaf are loaded first (one memory latency per
-    // leaf instead of one per face); 2-D FP32 runs faster loading them face by
-    // face, with fewer registers live
-    constexpr bool prefetch = !(D == 2 && sizeof(T) == 4);
-    T rowv[MAXF][P];
-    if constexpr (prefetch) {
-#pragma unroll
-      for (int s = 0; s < MAXF; ++s)
-#pragma unroll
-        for (int p = 0; p < P; ++p) rowv[s][p] = s < ns ? fv[p * fs + (size_t)sface[s] * L.ld + k] : (T)0;
-    }
-    // then one face at a time: its record is read from LDS inside the loop,
-    // so only one face's parameters are live in registers
+    // one face at a time: its record is read from LDS inside the loop, so
+    // only one face's parameters are live in registers
 #pragma unroll 1
     for (int s = 0; s < ns; ++s) {
-      {
-        const double sn = normal_speed<D>(xi, snrm[s]);
-        T pf[P];
-        if (snbr[s] >= 0 || sn >= 0.0) {
-          // upwind reconstruction stored by pass A (outgoing side of a boundary face)
+      const double sn = normal_speed<D>(x.xi, snrm[s]);
+      // static indices only (a dynamic index would move the rows to scratch memory)
+      T pf[P];
 #pragma unroll
-          for (int p = 0; p < P; ++p) pf[p] = prefetch ? rowv[s][p] : fv[p * fs + (size_t)sface[s] * L.ld + k];
-        } else {
-          const int bc = sbc[s];
-          const T sc = g.bc_kind[bc] == 0 ? spar[s * NPAR] : (T)1;
+      for (int q = 0; q < MAXF; ++q)
 #pragma unroll
-          for (int p = 0; p < P; ++p) pf[p] = sc * (T)bcpair[((size_t)bc * P + p) * L.cap + k];
-        }
-        if (snbr[s] >= 0) {
-          const T* par = spar + s * NPAR;
-          const T gv = maxw_r<D, T>(par, lds + s * D * nu, nu, u);
-          T G, H;
-          shakhov_r<D, T>(par, gv, xr, G, H);
-          pf[0] = par[P_A] * pf[0] + par[P_B] * G;
-          if (P == 2) pf[P - 1] = par[P_A] * pf[P - 1] + par[P_B] * H;
-        }
-        const T w = ssa[s] * (T)sn;
+        for (int p = 0; p < P; ++p) pf[p] = q == s ? x.row[q][p] : (q == 0 ? (T)0 : pf[p]);
+      if (snbr[s] >= 0) {
+        const T* par = spar + s * NPAR;
+        const T gv = maxw_r<D, T>(par, lds + s * D * nu, nu, x.u);
+        T G, H;
+        shakhov_r<D, T>(par, gv, xr, G, H);
+        pf[0] = par[P_A] * pf[0] + par[P_B] * G;
+        if (P == 2) pf[P - 1] = par[P_A] * pf[P - 1] + par[P_B] * H;
+      } else if (sn < 0.0) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) div[p] += w * pf[p];
+        for (int p = 0; p < P; ++p) pf[p] = ssc[s] * pf[p];
       }
+      const T w = ssa[s] * (T)sn;
+#pragma unroll
+      for (int p = 0; p < P; ++p) div[p] += w * pf[p];
     }
     // closed Shakhov target
-    const T gv = maxw_r<D, T>(tp, lds + MAXF * D * nu, nu, u);
+    const T gv = maxw_r<D, T>(tp, lds + MAXF * D * nu, nu, x.u);
     T G, H;
     shakhov_r<D, T>(tp, gv, xr, G, H);
     T c[D], c2 = 0, poly = slam[0];
@@ -1044,22 +1102,41 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
     double nv[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const T st = (phi[p] + dtt * tgt[p] - dtv * div[p]) * inv;
+      const T st = (x.phi[p] + dtt * tgt[p] - dtv * div[p]) * inv;
       vout[p * cs + (size_t)i * L.ld + k] = st;
       nv[p] = (double)st;
     }
     double xi2 = 0.0, cd[D], c2d = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      xi2 += xi[d] * xi[d];
-      cd[d] = xi[d] - (double)tp[P_U + d];
+      xi2 += x.xi[d] * x.xi[d];
+      cd[d] = x.xi[d] - (double)tp[P_U + d];
       c2d += cd[d] * cd[d];
     }
     const double Hn = (P == 2) ? nv[P - 1] : 0.0;
-    mom_acc<D>(acc, A, xi, xi2, nv[0], Hn);
-    const double e = 0.5 * A * (c2d * nv[0] + Hn);
+    mom_acc<D>(acc, x.A, x.xi, xi2, nv[0], Hn);
+    const double e = 0.5 * x.A * (c2d * nv[0] + Hn);
 #pragma unroll
     for (int d = 0; d < D; ++d) acc[N + d] += e * cd[d];
+  };
+
+  if constexpr (!passc_two_leaves<D, T>()) {
+    for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+      LeafIn<D, T> x;
+      load(k, x);
+      process(k, x);
+    }
+  } else {
+    LeafIn<D, T> x0, x1;
+    int k = threadIdx.x;
+    if (k < L.n) load(k, x0);
+    for (; k < L.n; k += 2 * BLOCK) {
+      if (k + BLOCK < L.n) load(k + BLOCK, x1);
+      process(k, x0);
+      if (k + BLOCK >= L.n) break;
+      if (k + 2 * BLOCK < L.n) load(k + 2 * BLOCK, x0);
+      process(k + BLOCK, x1);
+    }
   }
   block_sum<N + D>(acc, red);
   if (threadIdx.x == 0) {
@@ -1072,9 +1149,9 @@ template <int D, typename T>
 __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
                                                      const T* __restrict__ fv, T* __restrict__ vout,
                                                      const double* __restrict__ fpar, const double* __restrict__ tpar,
-                                                     const double* __restrict__ lam, const double* __restrict__ bcpair,
-                                                     double* __restrict__ mom, double* __restrict__ qout) {
-  d_passC<D, T>(g, L, vg, vin, fv, vout, fpar, tpar, lam, bcpair, mom, qout, blockIdx.x, blockIdx.y);
+                                                     const double* __restrict__ lam, double* __restrict__ mom,
+                                                     double* __restrict__ qout) {
+  d_passC<D, T>(g, L, vg, vin, fv, vout, fpar, tpar, lam, mom, qout, blockIdx.x);
 }
 
 // ----------------------------------------------- boundary Maxwellians (S7)
@@ -1531,8 +1608,8 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passA(const Ca
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
   const int lb = blockIdx.x - off[c];
-  d_passA<D, T>(global_geo(a->g), global_leaves(a->L), gptr(a->vin), a->h, gptr(a->fv), a->chunk, lb % a->gx,
-                lb / a->gx);
+  d_passA<D, T>(global_geo(a->g), global_leaves(a->L), gptr(a->vin), gptr(a->bcpair), a->h, gptr(a->fv), a->chunk,
+                lb % a->gx, lb / a->gx);
 }
 
 template <int D, typename T>
@@ -1575,7 +1652,7 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passC(const Ca
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
   d_passC<D, T>(global_geo(a->g), global_leaves(a->L), a->vg, gptr(a->vin), gptr(a->fv), gptr(a->vout), gptr(a->fpar),
-                gptr(a->tpar), gptr(a->lam), gptr(a->bcpair), gptr(a->mom), gptr(a->q), blockIdx.x - off[c], 0);
+                gptr(a->tpar), gptr(a->lam), gptr(a->mom), gptr(a->q), blockIdx.x - off[c]);
 }
 
 }  // namespace avs
