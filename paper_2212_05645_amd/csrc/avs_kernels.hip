@@ -299,10 +299,10 @@ template <int D>
 __device__ __forceinline__ void leaf_load(const Leaves& L, int k, double (&xi)[D], double& A, int (&u)[D]) {
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    xi[d] = L.xi[d * L.cap + k];
-    u[d] = L.u[d * L.cap + k];
+    xi[d] = at_(L.xi + (size_t)d * L.cap, (unsigned)k * 8u);
+    u[d] = at_(L.u + (size_t)d * L.cap, (unsigned)k * 4u);
   }
-  A = L.w[k];
+  A = at_(L.w, (unsigned)k * 8u);
 }
 
 // ---------------------------------------------------------- leaf geometry
@@ -708,6 +708,12 @@ __device__ __forceinline__ void raw_flux(const double* m, const double* n, doubl
 // face: outgoing flux plus the incoming wall (zero net mass flux, rho_w) or
 // far-field Maxwellian flux.  Splitting the reduction from the record and
 // the equilibrium sum keeps both kernels at a small register footprint.
+#ifndef AVS_FACE_LEAVES
+#define AVS_FACE_LEAVES 2
+#endif
+template <int D, typename R>
+constexpr int face_leaves() { return AVS_FACE_LEAVES; }
+
 template <int D, typename R>
 __device__ __forceinline__ void d_face(Geo g, Leaves L, const R* __restrict__ fv, double* __restrict__ fpar, int bx) {
   constexpr int P = Cfg<D>::P, NM = Cfg<D>::NM;
@@ -721,31 +727,47 @@ __device__ __forceinline__ void d_face(Geo g, Leaves L, const R* __restrict__ fv
   double m[NM];
 #pragma unroll
   for (int t = 0; t < NM; ++t) m[t] = 0.0;
-  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[D], A;
-    int u[D];
-    leaf_load<D>(L, k, xi, A, u);
-    // loaded with the leaf data, before the test, so both are in flight together
-    const double G = (double)fv[(size_t)f * L.ld + k];
-    const double H = P == 2 ? (double)fv[fs + (size_t)f * L.ld + k] : 0.0;
-    if (Rc < 0 && normal_speed<D>(xi, n) < 0.0) continue;     // incoming leaf of a boundary face
-    double xi2 = 0.0;
+  // U leaves per thread and iteration, all loaded before any is summed (the
+  // tail reads leaf n-1 again and skips it), so that a wave keeps U rows of
+  // memory traffic in flight; each thread still adds its leaves in
+  // increasing order, so the sums do not depend on U
+  constexpr int U = face_leaves<D, R>();
+  const unsigned rs = (unsigned)sizeof(R);
+  const R* row0 = fv + (size_t)f * L.ld;
+  const R* row1 = fv + fs + (size_t)f * L.ld;
+  for (int k0 = threadIdx.x; k0 < L.n; k0 += U * BLOCK) {
+    double xi[U][D], A[U], G[U], H[U];
 #pragma unroll
-    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
-    const double aG = A * G;
-    int t = 0;
-    m[t++] += aG;
+    for (int v = 0; v < U; ++v) {
+      const unsigned kk = (unsigned)min(k0 + v * BLOCK, L.n - 1);
 #pragma unroll
-    for (int d = 0; d < D; ++d) m[t++] += aG * xi[d];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-#pragma unroll
-      for (int e = d; e < D; ++e) m[t++] += aG * xi[d] * xi[e];
+      for (int d = 0; d < D; ++d) xi[v][d] = at_(L.xi + (size_t)d * L.cap, kk * 8u);
+      A[v] = at_(L.w, kk * 8u);
+      G[v] = (double)at_(row0, kk * rs);
+      H[v] = P == 2 ? (double)at_(row1, kk * rs) : 0.0;
     }
-    const double eh = 0.5 * A * (xi2 * G + H);
-    m[t++] += eh;
 #pragma unroll
-    for (int d = 0; d < D; ++d) m[t++] += eh * xi[d];
+    for (int v = 0; v < U; ++v) {
+      if (k0 + v * BLOCK >= L.n) break;
+      if (Rc < 0 && normal_speed<D>(xi[v], n) < 0.0) continue;     // incoming leaf of a boundary face
+      double xi2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) xi2 += xi[v][d] * xi[v][d];
+      const double aG = A[v] * G[v];
+      int t = 0;
+      m[t++] += aG;
+#pragma unroll
+      for (int d = 0; d < D; ++d) m[t++] += aG * xi[v][d];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int e = d; e < D; ++e) m[t++] += aG * xi[v][d] * xi[v][e];
+      }
+      const double eh = 0.5 * A[v] * (xi2 * G[v] + H[v]);
+      m[t++] += eh;
+#pragma unroll
+      for (int d = 0; d < D; ++d) m[t++] += eh * xi[v][d];
+    }
   }
   block_sum<NM>(m, red);
   if (threadIdx.x == 0)
@@ -996,6 +1018,7 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
   __shared__ double red[4 * (N + D)];
   __shared__ T spar[(MAXF + 1) * NPAR];
   __shared__ double snrm[MAXF][D];
+  __shared__ T snrt[MAXF][D];
   __shared__ int sface[MAXF], snbr[MAXF];
   __shared__ T ssa[MAXF], ssc[MAXF];
   __shared__ T slam[N];
@@ -1025,9 +1048,28 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
     // boundary face); far field and interior faces: 1
     const bool wall = s < ns && g.f_R[f] < 0 && g.bc_kind[-1 - g.f_R[f]] == 0;
     ssc[s] = wall ? (T)fpar[(size_t)f * NPAR] : (T)1;
-    for (int d = 0; d < D; ++d) snrm[s][d] = g.f_nrm[(size_t)f * D + d];
+    for (int d = 0; d < D; ++d) {
+      snrm[s][d] = g.f_nrm[(size_t)f * D + d];
+      snrt[s][d] = (T)snrm[s][d];
+    }
   }
   if (threadIdx.x < N) slam[threadIdx.x] = (T)lam[(size_t)i * N + threadIdx.x];
+  // row pointers from global memory (scalar registers), so that every load
+  // and store of the leaf loop is a scalar base plus one 32-bit lane offset
+  const T* frow[MAXF][P];
+  const T* vrow[P];
+  T* orow[P];
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) {
+    const size_t f = s < ns ? (size_t)g.s_face[i * MAXF + s] : 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) frow[s][p] = fv + p * fs + f * L.ld;
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    vrow[p] = vin + p * cs + (size_t)i * L.ld;
+    orow[p] = vout + p * cs + (size_t)i * L.ld;
+  }
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
@@ -1043,15 +1085,16 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
   for (int m = 0; m < N + D; ++m) acc[m] = 0.0;
 
   auto load = [&](int k, LeafIn<D, T>& x) {
+    const unsigned ko = (unsigned)k * (unsigned)sizeof(T);
     leaf_load<D>(L, k, x.xi, x.A, x.u);
 #pragma unroll
-    for (int p = 0; p < P; ++p) x.phi[p] = vin[p * cs + (size_t)i * L.ld + k];
+    for (int p = 0; p < P; ++p) x.phi[p] = at_(vrow[p], ko);
     // unconditional, so that all rows of the leaf are in flight together (a
     // slot beyond the cell's faces reads face 0 and is never used)
 #pragma unroll
     for (int s = 0; s < MAXF; ++s)
 #pragma unroll
-      for (int p = 0; p < P; ++p) x.row[s][p] = fv[p * fs + (size_t)sface[s] * L.ld + k];
+      for (int p = 0; p < P; ++p) x.row[s][p] = at_(frow[s][p], ko);
   };
   auto process = [&](int k, const LeafIn<D, T>& x) {
     T xr[D];
@@ -1064,13 +1107,13 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
     // only one face's parameters are live in registers
 #pragma unroll 1
     for (int s = 0; s < ns; ++s) {
-      const double sn = normal_speed<D>(x.xi, snrm[s]);
       // static indices only (a dynamic index would move the rows to scratch memory)
       T pf[P];
 #pragma unroll
       for (int q = 0; q < MAXF; ++q)
 #pragma unroll
         for (int p = 0; p < P; ++p) pf[p] = q == s ? x.row[q][p] : (q == 0 ? (T)0 : pf[p]);
+      T sw;     // xi . n, the flux weight
       if (snbr[s] >= 0) {
         const T* par = spar + s * NPAR;
         const T gv = maxw_r<D, T>(par, lds + s * D * nu, nu, x.u);
@@ -1078,11 +1121,25 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
         shakhov_r<D, T>(par, gv, xr, G, H);
         pf[0] = par[P_A] * pf[0] + par[P_B] * G;
         if (P == 2) pf[P - 1] = par[P_A] * pf[P - 1] + par[P_B] * H;
-      } else if (sn < 0.0) {
+        // no side is chosen here, so the weight is formed in T (both cells
+        // of the face form the same value: the flux stays antisymmetric)
+        if constexpr (sizeof(T) == 8) {
+          sw = normal_speed<D>(x.xi, snrm[s]);
+        } else {
+          sw = xr[0] * snrt[s][0];
 #pragma unroll
-        for (int p = 0; p < P; ++p) pf[p] = ssc[s] * pf[p];
+          for (int d = 1; d < D; ++d) sw += xr[d] * snrt[s][d];
+        }
+      } else {
+        // boundary face: the incoming side is taken in FP64, as in pass A
+        const double sn = normal_speed<D>(x.xi, snrm[s]);
+        if (sn < 0.0) {
+#pragma unroll
+          for (int p = 0; p < P; ++p) pf[p] = ssc[s] * pf[p];
+        }
+        sw = (T)sn;
       }
-      const T w = ssa[s] * (T)sn;
+      const T w = ssa[s] * sw;
 #pragma unroll
       for (int p = 0; p < P; ++p) div[p] += w * pf[p];
     }
@@ -1103,7 +1160,7 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const T st = (x.phi[p] + dtt * tgt[p] - dtv * div[p]) * inv;
-      vout[p * cs + (size_t)i * L.ld + k] = st;
+      *ptr_at_(orow[p], (unsigned)k * (unsigned)sizeof(T)) = st;
       nv[p] = (double)st;
     }
     double xi2 = 0.0, cd[D], c2d = 0.0;
