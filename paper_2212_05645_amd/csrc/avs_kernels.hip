@@ -198,34 +198,37 @@ __device__ __forceinline__ double tau_of(double rho, double T, const GasP& gas) 
 
 // Solve J x = b ((D+2)x(D+2)) by Gaussian elimination with partial pivoting.
 template <int N>
-__device__ bool solve_small(double (&J)[N][N], double (&b)[N], double (&x)[N]) {
-#pragma unroll
+__device__ bool solve_small(double* J, double* b, double* x) {
+  // J (row-major N x N), b and x in LDS, one thread: the loops are not
+  // unrolled, so the solve costs the kernel no registers (held in registers
+  // it bounded the occupancy of the whole per-cell kernel)
+#pragma unroll 1
   for (int c = 0; c < N; ++c) {
     int p = c;
-    double best = fabs(J[c][c]);
-#pragma unroll
+    double best = fabs(J[c * N + c]);
+#pragma unroll 1
     for (int r = c + 1; r < N; ++r)
-      if (fabs(J[r][c]) > best) { best = fabs(J[r][c]); p = r; }
+      if (fabs(J[r * N + c]) > best) { best = fabs(J[r * N + c]); p = r; }
     if (!(best > 0.0)) return false;
     if (p != c) {
-#pragma unroll
-      for (int k = 0; k < N; ++k) { double t = J[c][k]; J[c][k] = J[p][k]; J[p][k] = t; }
+#pragma unroll 1
+      for (int k = 0; k < N; ++k) { double t = J[c * N + k]; J[c * N + k] = J[p * N + k]; J[p * N + k] = t; }
       double t = b[c]; b[c] = b[p]; b[p] = t;
     }
-#pragma unroll
+#pragma unroll 1
     for (int r = c + 1; r < N; ++r) {
-      const double f = J[r][c] / J[c][c];
-#pragma unroll
-      for (int k = c; k < N; ++k) J[r][k] -= f * J[c][k];
+      const double f = J[r * N + c] / J[c * N + c];
+#pragma unroll 1
+      for (int k = c; k < N; ++k) J[r * N + k] -= f * J[c * N + k];
       b[r] -= f * b[c];
     }
   }
-#pragma unroll
+#pragma unroll 1
   for (int r = N - 1; r >= 0; --r) {
     double s = b[r];
-#pragma unroll
-    for (int k = r + 1; k < N; ++k) s -= J[r][k] * x[k];
-    x[r] = s / J[r][r];
+#pragma unroll 1
+    for (int k = r + 1; k < N; ++k) s -= J[r * N + k] * x[k];
+    x[r] = s / J[r * N + r];
   }
   return true;
 }
@@ -248,31 +251,41 @@ __device__ __forceinline__ void gram_acc(double* S, double Ag, const double (&c)
 }
 
 // J_lm = M_l[e_m] for e_m = (b_m g, (3-D) RT b_m g), from S (see closure).
+// S holds the upper triangle of the symmetric Gram matrix row by row; J is
+// written row-major (N x N, N = D + 2).
 template <int D>
-__device__ __forceinline__ void gram_to_J(const double* S, const double* par, double (&J)[D + 2][D + 2]) {
-  double Sf[D + 2][D + 2];
-  int m = 0;
-#pragma unroll
-  for (int a = 0; a < D + 2; ++a) {
-#pragma unroll
-    for (int e = a; e < D + 2; ++e) { Sf[a][e] = S[m]; Sf[e][a] = S[m]; ++m; }
-  }
+__device__ __forceinline__ int sym_index(int a, int e) {
+  if (a > e) { const int t = a; a = e; e = t; }
+  return a * (D + 2) - a * (a - 1) / 2 + (e - a);
+}
+
+template <int D>
+__device__ void gram_to_J(const double* S, const double* par, double* J) {
+  constexpr int N = D + 2;
   double U2 = 0.0;
 #pragma unroll
   for (int d = 0; d < D; ++d) U2 += par[P_U + d] * par[P_U + d];
   const double hidden = (D == 2) ? par[P_RT] : 0.0;
-#pragma unroll
-  for (int c = 0; c < D + 2; ++c) {
-    J[0][c] = Sf[0][c];
-    double e = 0.5 * Sf[D + 1][c] + 0.5 * (U2 + hidden) * Sf[0][c];
+#pragma unroll 1
+  for (int c = 0; c < N; ++c) {
+    const double s0 = S[sym_index<D>(0, c)];
+    J[c] = s0;
+    double e = 0.5 * S[sym_index<D>(D + 1, c)] + 0.5 * (U2 + hidden) * s0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      J[1 + d][c] = Sf[1 + d][c] + par[P_U + d] * Sf[0][c];
-      e += par[P_U + d] * Sf[1 + d][c];
+      const double sd = S[sym_index<D>(1 + d, c)];
+      J[(1 + d) * N + c] = sd + par[P_U + d] * s0;
+      e += par[P_U + d] * sd;
     }
-    J[D + 1][c] = e;
+    J[(D + 1) * N + c] = e;
   }
 }
+
+// LDS work space of the one-thread closure solve of a per-cell kernel.
+template <int D>
+struct ClosureWork {
+  double S[Cfg<D>::NS], J[(D + 2) * (D + 2)], b[D + 2], x[D + 2];
+};
 
 // s = xi . n as the ordered sum of products without contraction: its sign
 // picks the upwind side, so it must be reproducible bit for bit.
@@ -344,6 +357,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_vdf(Geo g, Leaves L, VGrid vg, G
   double* red = lds + D * vg.numax;
   __shared__ double par[NPAR];
   __shared__ double lam[N];
+  __shared__ ClosureWork<D> cw;
   const int i = blockIdx.x;
   if (threadIdx.x == 0) {
     double rho, U[D], T_;
@@ -369,11 +383,13 @@ __global__ __launch_bounds__(BLOCK) void k_init_vdf(Geo g, Leaves L, VGrid vg, G
   }
   block_sum<N + NS>(acc, red);
   if (threadIdx.x == 0) {
-    double J[N][N], b[N], x[N];
-    gram_to_J<D>(acc + N, par, J);
-    for (int m = 0; m < N; ++m) b[m] = W[(size_t)i * N + m] - acc[m];
-    if (!solve_small<N>(J, b, x)) atomicMin(bad, i);
-    for (int m = 0; m < N; ++m) lam[m] = x[m];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) cw.S[m] = acc[N + m];
+    gram_to_J<D>(cw.S, par, cw.J);
+#pragma unroll
+    for (int m = 0; m < N; ++m) cw.b[m] = W[(size_t)i * N + m] - acc[m];
+    if (!solve_small<N>(cw.J, cw.b, cw.x)) atomicMin(bad, i);
+    for (int m = 0; m < N; ++m) lam[m] = cw.x[m];
   }
   __syncthreads();
   const size_t cs = (size_t)g.nc * L.ld;
@@ -938,6 +954,7 @@ __device__ __forceinline__ void d_target(Geo g, Leaves L, VGrid vg, const double
   R* tab = reinterpret_cast<R*>(lds_d);
   __shared__ double red[4 * (N + NS)];
   __shared__ R rp[NPAR];
+  __shared__ ClosureWork<D> cw;
   const int i = bx;
   const double* par = tpar + (size_t)i * NPAR;
   if (threadIdx.x < NPAR) rp[threadIdx.x] = (R)par[threadIdx.x];
@@ -965,11 +982,13 @@ __device__ __forceinline__ void d_target(Geo g, Leaves L, VGrid vg, const double
   }
   block_sum<N + NS>(acc, red);
   if (threadIdx.x == 0) {
-    double J[N][N], b[N], x[N];
-    gram_to_J<D>(acc + N, par, J);
-    for (int m = 0; m < N; ++m) b[m] = Wn[(size_t)i * N + m] - acc[m];
-    if (!solve_small<N>(J, b, x)) { atomicMin(bad, i); for (int m = 0; m < N; ++m) x[m] = 0.0; }
-    for (int m = 0; m < N; ++m) lam[(size_t)i * N + m] = x[m];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) cw.S[m] = acc[N + m];
+    gram_to_J<D>(cw.S, par, cw.J);
+#pragma unroll
+    for (int m = 0; m < N; ++m) cw.b[m] = Wn[(size_t)i * N + m] - acc[m];
+    if (!solve_small<N>(cw.J, cw.b, cw.x)) { atomicMin(bad, i); for (int m = 0; m < N; ++m) cw.x[m] = 0.0; }
+    for (int m = 0; m < N; ++m) lam[(size_t)i * N + m] = cw.x[m];
   }
 }
 
@@ -1487,6 +1506,7 @@ __global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid 
   __shared__ double red[4 * (2 * N + NS)];
   __shared__ double parA[NPAR], parB[NPAR];
   __shared__ double lam[N];
+  __shared__ ClosureWork<D> cw;
   const int i = blockIdx.x;
   if (threadIdx.x == 0) {
     double rho, U[D], T_;
@@ -1515,11 +1535,14 @@ __global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid 
     }
     block_sum<2 * N + NS>(acc, red);
     if (threadIdx.x == 0) {
-      double J[N][N], b[N], x[N];
-      gram_to_J<D>(acc + 2 * N, parA, J);
-      for (int m = 0; m < N; ++m) b[m] = W[(size_t)i * N + m] - (momp[(size_t)i * N + m] + acc[m] - acc[N + m]);
-      if (!solve_small<N>(J, b, x)) { atomicMin(bad, i); for (int m = 0; m < N; ++m) x[m] = 0.0; }
-      for (int m = 0; m < N; ++m) lam[m] = x[m];
+#pragma unroll
+      for (int m = 0; m < NS; ++m) cw.S[m] = acc[2 * N + m];
+      gram_to_J<D>(cw.S, parA, cw.J);
+#pragma unroll
+      for (int m = 0; m < N; ++m)
+        cw.b[m] = W[(size_t)i * N + m] - (momp[(size_t)i * N + m] + acc[m] - acc[N + m]);
+      if (!solve_small<N>(cw.J, cw.b, cw.x)) { atomicMin(bad, i); for (int m = 0; m < N; ++m) cw.x[m] = 0.0; }
+      for (int m = 0; m < N; ++m) lam[m] = cw.x[m];
     }
   } else if (threadIdx.x < N) {
     lam[threadIdx.x] = 0.0;

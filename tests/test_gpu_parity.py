@@ -136,6 +136,31 @@ def test_ogrid_wall_and_farfield(avs):
     assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
 
 
+@pytest.mark.parametrize("D", [2, 3])
+def test_cells_with_fewer_faces_than_slots(avs, D):
+    """A cut-out block of a body-fitted grid whose outermost ring has
+    incomplete face lists (cells with 1-3 of 4, or 2-5 of 6, faces; the
+    dropped faces carry no flux on either side), so every slot kind is
+    exercised: interior, wall or far-field boundary, and unused."""
+    if D == 2:
+        c = F.cylinder(nr=8, nth=24, Ma=2.0, box=8.0, base=16, max_level=2, r1=2.5, first=0.1)
+        block = [r * 24 + t for r in range(0, 3) for t in range(5, 9)] + [7 * 24 + 15]
+    else:
+        c = F.sphere(nr=4, nth=6, nph=6, Ma=2.0, box=5.0, base=8, max_level=1, r1=1.5, first=0.2)
+        block = [0, 1, 7, 40, 41]
+    sub, keep = MM.submesh(c['mesh'], block, halo=1)
+    nslot = np.bincount(np.asarray(sub['face_lr'])[:, 0], minlength=sub['ncells']) + \
+        np.bincount(np.asarray(sub['face_lr'])[:, 1][np.asarray(sub['face_lr'])[:, 1] >= 0], minlength=sub['ncells'])
+    assert nslot.min() < 2 * D and (nslot == 2 * D).any()
+    tree = resolved_tree(c['vspace'], 8)
+    cs, o = make_pair(avs, sub, c['vspace'], c['gas'], c['dt'], c['prim0'][keep], tree=tree, noise=0.01, seed=8,
+                      Kv=c['venkat_K'])
+    cs.step(3)
+    o.step(3)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+
+
 @pytest.mark.parametrize("which", ["box", "sphere"])
 def test_3d_steps(avs, which):
     if which == "box":
