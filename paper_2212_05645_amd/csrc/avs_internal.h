@@ -16,7 +16,7 @@ constexpr int NM3 = 14;          // raw face moments, 3-D: m0, m1[3], m2[6], e, 
 constexpr int NPAR = 16;         // doubles per equilibrium parameter record
 constexpr int CRIT_CELLS = 256;  // cells per criterion partial
 #ifndef AVS_CHUNK
-#define AVS_CHUNK 2048
+#define AVS_CHUNK 8192
 #endif
 constexpr int CHUNK = AVS_CHUNK;  // leaves per workgroup of pass A
 
