@@ -1,0 +1,135 @@
+"""Pins of the adaptive-parameter oracle (Sec. 3.5) against the values the
+paper prints: tables and quoted numbers of Sec. 4, stored in tests/golden
+with their citations.  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import avs_params as AP
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rows(name):
+    out = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            out.append(line.split())
+    return out
+
+
+def decimals(s):
+    return len(s.split(".")[1]) if "." in s else 0
+
+
+# The paper's nondimensional unit: velocities in sqrt(2 R T_inf), so R = 1/2
+# and T_inf = 1 (Sec. 4.1 quotes the Ma 5 reference box in that unit).
+R_PAPER = 0.5
+
+
+@pytest.mark.parametrize("row", rows("cylinder_adaptive_test.txt"), ids=lambda r: f"Ma{r[0]}")
+def test_cylinder_table_lmax(row):
+    """L_max column of the cylinder table (argon, gamma 5/3, R_dv = 4 sigma_0)."""
+    Ma, L_max = float(row[0]), int(row[2])
+    p = AP.auto_params(AP.Flow(dim=2, R=R_PAPER, gamma=5.0 / 3.0, Ma=Ma, T_inf=1.0, T_wall=1.0))
+    assert p['L_max'] == L_max
+    # h_inf lies in [h_std / 2, h_std] (Sec. 3.5)
+    assert 0.5 * AP.H_STD <= p['h_min'] <= AP.H_STD
+
+
+@pytest.mark.parametrize("row", rows("sphere_rdv.txt"), ids=lambda r: f"Rdv{r[1]}")
+def test_sphere_table_hinf(row):
+    """h_inf column of the sphere table (nitrogen, gamma 7/5) to the printed
+    three decimals."""
+    Ma, k, h = float(row[0]), float(row[1]), row[2]
+    p = AP.auto_params(AP.Flow(dim=3, R=R_PAPER, gamma=1.4, Ma=Ma, T_inf=1.0, T_wall=315.0 / 43.22, rdv_sigmas=k))
+    assert round(p['h_min'], decimals(h)) == float(h)
+
+
+@pytest.mark.parametrize("row", rows("c1_fit.txt"), ids=lambda r: f"Ma{r[0]}")
+def test_c1_fit_values(row):
+    Ma, printed = float(row[0]), row[1]
+    assert round(AP.c1_of_ma(Ma), decimals(printed)) == float(printed)
+
+
+def test_normal_density_constants():
+    vals = {r[0]: r[1] for r in rows("normal_constants.txt")}
+    assert round(AP.normal_pdf(0.0), 4) == float(vals['f_max'])
+    assert float(f"{AP.normal_pdf(4.0):.4e}") == float(vals['f_4sigma'])
+    assert float(f"{AP.k_sigma():.4e}") == float(vals['k_sigma'])
+    # k_sigma = exp(-8): the ratio of the density at 4 sigma to its peak
+    assert abs(AP.k_sigma() - math.exp(-8.0)) < 1e-18
+
+
+@pytest.mark.parametrize("row", rows("sphere_temperatures.txt"), ids=lambda r: f"Ma{r[0]}")
+def test_sphere_total_temperature(row):
+    Ma, T_inf, T0, Tw, ratio = (float(x) for x in row)
+    got = AP.total_temperature(T_inf, 1.4, Ma)
+    # T_inf is printed to 0.01 K, so T_0 is known to 0.005 (1 + 0.2 Ma^2)
+    assert abs(got - T0) <= 0.005 * (1.0 + 0.2 * Ma * Ma)
+    assert round(Tw / T0, 3) == ratio
+
+
+def test_cavity_sound_speed_and_lid():
+    """Sec. 4.2: argon at 273 K, R = 208 J/(kg K): a = sqrt(gamma R T) =
+    307.64 m/s and the lid moves at Ma 0.16, U_w = 49.22 m/s."""
+    a = AP.sound_speed(208.0, 5.0 / 3.0, 273.0)
+    assert round(a, 2) == 307.64
+    assert round(0.16 * a, 2) == 49.22
+
+
+def test_ma5_box_and_full_mesh():
+    """Sec. 4.1: at Ma 5 the AVS has maximum level 5 and the complete mesh of
+    that level has 1024 elements."""
+    p = AP.auto_params(AP.Flow(dim=2, R=R_PAPER, gamma=5.0 / 3.0, Ma=5.0, T_inf=1.0, T_wall=1.0))
+    assert p['L_max'] == 5 and 4 ** p['L_max'] == 1024
+    vs = AP.vspace_of(p, 2)
+    # 2^L_min roots per axis and L_max - L_min levels below them
+    assert vs['base'] == (8, 8) and vs['max_level'] == 2
+    assert np.allclose(vs['hi'] - vs['lo'], 2 * p['R_dv'])
+    assert abs(0.5 * (vs['lo'][0] + vs['hi'][0]) - 0.4 * p['U_inf']) < 1e-12
+
+
+def test_level_rules():
+    """L_w drops one level for hot walls (T_w / T_inf >= 4); L_min is 4 only
+    for D = 2 above Ma 5; the separated zone is max(L_min, L_w - 1)."""
+    cold = AP.auto_params(AP.Flow(dim=2, R=R_PAPER, gamma=5.0 / 3.0, Ma=10.0, T_inf=1.0, T_wall=3.99))
+    hot = AP.auto_params(AP.Flow(dim=2, R=R_PAPER, gamma=5.0 / 3.0, Ma=10.0, T_inf=1.0, T_wall=4.0))
+    assert cold['L_w'] == cold['L_max'] and hot['L_w'] == hot['L_max'] - 1
+    assert AP.min_level(2, 5.0) == 3 and AP.min_level(2, 5.01) == 4 and AP.min_level(3, 8.0) == 3
+    assert cold['L_sep'] == max(cold['L_min'], cold['L_w'] - 1)
+    # the smallest level that covers the box at h_std, and not one less
+    for R_dv in (0.1, 0.3, 0.31, 1.0, 7.2, 100.0):
+        L = AP.level_std(R_dv)
+        assert 2.0 ** L >= 2 * R_dv / AP.H_STD and (L == 0 or 2.0 ** (L - 1) < 2 * R_dv / AP.H_STD)
+
+
+@pytest.mark.parametrize("dim,Ma", [(2, 2.0), (2, 6.0), (3, 4.25)])
+def test_initial_tree_structure(dim, Ma):
+    """The step-0 space tiles the box, lies within the levels, splits where
+    the two probe Maxwellians carry mass or energy and coarsens far from
+    both (invariants; the element count itself is parity unpinned).  C1 =
+    1e-3 suits the criterion as printed (the fitted C1 never splits)."""
+    gamma = 5.0 / 3.0 if dim == 2 else 1.4
+    f = AP.Flow(dim=dim, R=R_PAPER, gamma=gamma, Ma=Ma, T_inf=1.0, T_wall=1.0)
+    p = AP.auto_params(f)
+    t0, eff, t1 = AP.initial_tree(f, p, C1=1e-3)
+    vs = AP.vspace_of(p, dim)
+    lr = min(p['L_min'], p['L_max'])
+    lev0 = max(p['L_w'] - 1, lr) - lr
+    assert t0.n == (2 ** lev0 * vs['base'][0]) ** dim
+    cover = np.sum(2.0 ** (-dim * t1.level.astype(np.float64)))
+    assert abs(cover - np.prod(vs['base'])) < 1e-9
+    assert t1.level.min() >= 0 and t1.level.max() <= vs['max_level']
+    assert (eff == 1).any() and ((eff == -1).any() or lev0 == 0)
+    # the fitted C1 is far above every M_k of the printed criterion
+    _, eff_fit, _ = AP.initial_tree(f, p)
+    assert not (eff_fit == 1).any()
+    xi = t0.centres()
+    e = np.asarray(f.direction)[:dim]
+    near = np.minimum(np.linalg.norm(xi - p['U_inf'] * e, axis=1), np.linalg.norm(xi, axis=1))
+    s = p['sigma_inf']
+    assert np.all(near[eff == 1] < 4 * s) and np.all(near[eff == -1] > 2 * s)
