@@ -300,6 +300,53 @@ avs_status avs_adapt_learned(avs_ctx *ctx, avs_mlp *mlp, double C1, double C2, c
                              int32_t nprobes, double tail_tol, int8_t *flags_dev, int64_t *n_new_host,
                              int32_t *fallback_host);
 
+/* ---- Automatic velocity space (Sec. 3.5) -------------------------------
+ * The adaptive parameters of Sec. 3.5 from the freestream, and the step-0
+ * velocity space.  Host computation, except for the adaptation of
+ * avs_initial_avs, which runs on the context's stream. */
+typedef struct {
+  int32_t dim;            /* 2 or 3 */
+  double R, gamma;        /* gas constant (solver units) and ratio of specific heats, > 0 and > 1 */
+  double Ma;              /* freestream Mach number, >= 0 */
+  double T_inf, T_wall;   /* freestream static and wall temperatures, > 0 */
+  double rho_inf;         /* freestream density, > 0 */
+  double direction[3];    /* freestream direction, normalised here; non-zero when Ma > 0 */
+  double rdv_sigmas;      /* R_dv in units of sigma_0 (> 0; the paper uses 4, up to 7 for hot walls) */
+  double h_std;           /* standard velocity interval (> 0; the paper uses 0.6) */
+} avs_flow;
+
+typedef struct {
+  double T0;                            /* total temperature, Eq. totaltemperature */
+  double sigma_inf, sigma_0, sigma_w;   /* sqrt(R T) of T_inf, T0, T_wall */
+  double U_inf;                         /* Ma sqrt(gamma R T_inf) */
+  double centre[3], R_dv;               /* box centre 0.4 U_inf e and half-width rdv_sigmas sigma_0 */
+  double h_min;                         /* 2 R_dv / 2^L_max */
+  int32_t L_max;                        /* smallest L with 2^L >= 2 R_dv / h_std */
+  int32_t L_w;                          /* L_max, or L_max - 1 when T_wall / T_inf >= 4 */
+  int32_t L_min;                        /* 4 for dim 2 and Ma > 5, else 3 */
+  int32_t L_sep;                        /* separated zone, max(L_min, L_w - 1) */
+  double C1, C2, k_sigma;               /* 13.749 Ma^-1.465 (Eq. C1_Ma), k_sigma C1, k_sigma = e^-8 (Eq. c2c1) */
+} avs_auto;
+
+/* Parameters of Sec. 3.5 for flow, and the velocity space that realises
+ * them on the solver's forest: 2^min(L_min, L_max) roots per axis on the box
+ * centre -/+ R_dv, L_max - min(L_min, L_max) levels below them, and
+ * leaf_capacity = leaves of the complete tree (at most 2^26).  Either output
+ * may be NULL.  AVS_E_INVALID for out-of-range inputs or a box that needs
+ * more levels than the solver supports. */
+avs_status avs_auto_params(const avs_flow *flow, avs_auto *params_out, avs_vspace *vspace_out);
+
+/* Step-0 velocity space (Sec. 3.5, steps 1-3) on a context created with the
+ * avs_vspace that avs_auto_params returned for flow (checked): the uniform
+ * mesh after L_w - 1 splits of the box (the roots when that is fewer than
+ * their level), one adaptation whose criterion runs over the freestream
+ * (rho_inf, U_inf e, T_inf) and the static state (rho_inf, 0, T_inf) only,
+ * with thresholds C1, C2 (the fit of Eq. C1_Ma is far above every M_k of
+ * the criterion as printed, so the caller chooses them), then phi =
+ * closure(g_eq(W), W) on the new leaves for the current W.  Writes the leaf
+ * count to *n_leaves_host (may be NULL).  Waits for the device. */
+avs_status avs_initial_avs(avs_ctx *ctx, const avs_flow *flow, double C1, double C2, int64_t *n_leaves_host);
+
 /* Release the context (never frees caller memory). */
 void avs_destroy(avs_ctx *ctx);
 

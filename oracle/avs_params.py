@@ -112,8 +112,8 @@ def k_sigma():
 
 
 def c1_of_ma(Ma):
-    """Eq. C1_Ma: C1 = 13.749 Ma^-1.465."""
-    return 13.749 * Ma ** -1.465
+    """Eq. C1_Ma: C1 = 13.749 Ma^-1.465 (infinite at Ma = 0: nothing splits)."""
+    return math.inf if Ma == 0.0 else 13.749 * Ma ** -1.465
 
 
 def auto_params(flow: Flow):

@@ -27,7 +27,7 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_batch_check", "avs_batch_tune", "avs_batch_adapt", "avs_batch_remap", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
            "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
            "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
-           "avs_destroy", "avs_last_error")
+           "avs_auto_params", "avs_initial_avs", "avs_destroy", "avs_last_error")
 
 
 class avs_vspace(C.Structure):
@@ -55,9 +55,26 @@ class avs_adam(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
 
 
+class avs_flow(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("R", C.c_double), ("gamma", C.c_double), ("Ma", C.c_double),
+                ("T_inf", C.c_double), ("T_wall", C.c_double), ("rho_inf", C.c_double),
+                ("direction", C.c_double * 3), ("rdv_sigmas", C.c_double), ("h_std", C.c_double)]
+
+
+class avs_auto(C.Structure):
+    _fields_ = [("T0", C.c_double), ("sigma_inf", C.c_double), ("sigma_0", C.c_double), ("sigma_w", C.c_double),
+                ("U_inf", C.c_double), ("centre", C.c_double * 3), ("R_dv", C.c_double), ("h_min", C.c_double),
+                ("L_max", C.c_int32), ("L_w", C.c_int32), ("L_min", C.c_int32), ("L_sep", C.c_int32),
+                ("C1", C.c_double), ("C2", C.c_double), ("k_sigma", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libavs.so not found at {LIB_PATH}: build it with __graft_entry__.build()")
+    # torch's HIP runtime must be the first one in the process: a HIP runtime
+    # loaded ahead of it by this library would leave torch's, or ours, without
+    # a device
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I32, I64, D, VP = C.POINTER, C.c_int32, C.c_int64, C.c_double, C.c_void_p
     sig = {
@@ -99,6 +116,8 @@ def _load():
         "avs_mlp_destroy": (None, [VP]),
         "avs_features": (I32, [VP, VP, VP]),
         "avs_adapt_learned": (I32, [VP, VP, D, D, VP, I32, D, VP, P(I64), P(I32)]),
+        "avs_auto_params": (I32, [P(avs_flow), P(avs_auto), P(avs_vspace)]),
+        "avs_initial_avs": (I32, [VP, P(avs_flow), D, D, P(I64)]),
         "avs_destroy": (None, [VP]),
         "avs_last_error": (C.c_char_p, []),
     }
@@ -129,6 +148,24 @@ def _ptr(a):
 
 def mu_ref_from_kn(Kn, omega, R, T_ref=1.0, rho_ref=1.0, L_ref=1.0):
     return lib.avs_mu_ref_from_kn(Kn, omega, R, T_ref, rho_ref, L_ref)
+
+
+def _flow(dim, R, gamma, Ma, T_inf, T_wall, rho_inf=1.0, direction=(1.0, 0.0, 0.0), rdv_sigmas=4.0, h_std=0.6):
+    d = tuple(float(x) for x in direction) + (0.0,) * (3 - len(direction))
+    return avs_flow(int(dim), float(R), float(gamma), float(Ma), float(T_inf), float(T_wall), float(rho_inf),
+                    (C.c_double * 3)(*d[:3]), float(rdv_sigmas), float(h_std))
+
+
+def auto_params(**flow):
+    """Adaptive parameters of the freestream ``flow`` (keywords of avs_flow)
+    and the velocity space that realises them: (params dict, vspace dict)."""
+    a, v = avs_auto(), avs_vspace()
+    _check(lib.avs_auto_params(C.byref(_flow(**flow)), C.byref(a), C.byref(v)))
+    D = int(flow['dim'])
+    params = {k: (list(getattr(a, k))[:D] if k == 'centre' else getattr(a, k)) for k, _ in avs_auto._fields_}
+    vs = dict(dim=v.dim, max_level=v.max_level, base=tuple(v.base[:D]), lo=tuple(v.lo[:D]), hi=tuple(v.hi[:D]),
+              leaf_capacity=v.leaf_capacity)
+    return params, vs
 
 
 class Case:
@@ -277,6 +314,14 @@ class Case:
         Mk = np.zeros(n_old)
         _check(lib.avs_criterion(self.ctx, Mk.ctypes.data))
         return Mk
+
+    def initial_avs(self, C1, C2, **flow):
+        """Step-0 velocity space for the freestream ``flow`` (keywords of
+        avs_flow; the case must use the velocity space auto_params gives for
+        it); returns the leaf count."""
+        n = C.c_int64()
+        _check(lib.avs_initial_avs(self.ctx, C.byref(_flow(**flow)), float(C1), float(C2), C.byref(n)))
+        return n.value
 
     def set_leaves(self, level, idx):
         lev = np.ascontiguousarray(level, np.int32)

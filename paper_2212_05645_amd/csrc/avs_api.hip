@@ -460,18 +460,22 @@ avs_status launch_leaf_geom(avs_ctx* ctx, int t) {
   return AVS_OK;
 }
 
+// Criterion, raw and effective flags, and their scan.  cells == false: the
+// criterion runs over the probe states only (step-0 velocity space).
 template <int D, typename T>
-avs_status launch_adapt(avs_ctx* ctx, double C1, double C2, int nprobe) {
+avs_status launch_adapt(avs_ctx* ctx, double C1, double C2, int nprobe, bool cells = true) {
   const Leaves L = ctx->leaves(ctx->lcur);
   const int nb = (L.n + BLOCK - 1) / BLOCK;
   ProfScope ps(ctx, K_CRITERION);
-  k_crit_cells<D><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->W, ctx->cc);
-  CKL();
-  k_crit_partial<D, T><<<dim3(nb, ctx->ngrp), BLOCK, 0, ctx->stream>>>(L, ctx->nc, (const T*)ctx->vdf[ctx->cur], ctx->cc,
-                                                                      ctx->crit_part);
-  CKL();
-  k_crit_reduce<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->ngrp, ctx->crit_part, nprobe, ctx->probe_cc, ctx->probe_prim,
-                                                 ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
+  if (cells) {
+    k_crit_cells<D><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->W, ctx->cc);
+    CKL();
+    k_crit_partial<D, T><<<dim3(nb, ctx->ngrp), BLOCK, 0, ctx->stream>>>(L, ctx->nc, (const T*)ctx->vdf[ctx->cur],
+                                                                        ctx->cc, ctx->crit_part);
+    CKL();
+  }
+  k_crit_reduce<D><<<nb, BLOCK, 0, ctx->stream>>>(L, cells ? ctx->ngrp : 0, ctx->crit_part, nprobe, ctx->probe_cc,
+                                                 ctx->probe_prim, ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
   CKL();
   k_resolve<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
   CKL();
@@ -703,6 +707,63 @@ avs_status batch_run(avs_batch* b, int nsteps, bool graph) {
 }
 
 }  // namespace
+
+// ---------------------------------------------- automatic velocity space
+// Sec. 3.5: parameters of the velocity space from the freestream.
+avs_status auto_params_host(const avs_flow* f, avs_auto* p, avs_vspace* vs) {
+  if (!f) return fail(AVS_E_INVALID, "null flow descriptor");
+  if (f->dim != 2 && f->dim != 3) return fail(AVS_E_INVALID, "flow.dim must be 2 or 3 (got %d)", f->dim);
+  auto pos = [](double x) { return std::isfinite(x) && x > 0.0; };
+  if (!pos(f->R) || !(std::isfinite(f->gamma) && f->gamma > 1.0)) return fail(AVS_E_INVALID, "need R > 0 and gamma > 1");
+  if (!(std::isfinite(f->Ma) && f->Ma >= 0.0)) return fail(AVS_E_INVALID, "Ma must be finite and >= 0");
+  if (!pos(f->T_inf) || !pos(f->T_wall) || !pos(f->rho_inf)) return fail(AVS_E_INVALID, "T_inf, T_wall and rho_inf must be > 0");
+  if (!pos(f->rdv_sigmas) || !pos(f->h_std)) return fail(AVS_E_INVALID, "rdv_sigmas and h_std must be > 0");
+  const int D = f->dim;
+  double e[3] = {0.0, 0.0, 0.0}, norm = 0.0;
+  for (int d = 0; d < D; ++d) norm += f->direction[d] * f->direction[d];
+  norm = std::sqrt(norm);
+  if (f->Ma > 0.0 && !(norm > 0.0 && std::isfinite(norm))) return fail(AVS_E_INVALID, "flow.direction must be non-zero");
+  if (norm > 0.0)
+    for (int d = 0; d < D; ++d) e[d] = f->direction[d] / norm;
+  avs_auto a{};
+  a.T0 = f->T_inf * (1.0 + 0.5 * (f->gamma - 1.0) * f->Ma * f->Ma);
+  a.sigma_inf = std::sqrt(f->R * f->T_inf);
+  a.sigma_0 = std::sqrt(f->R * a.T0);
+  a.sigma_w = std::sqrt(f->R * f->T_wall);
+  a.U_inf = f->Ma * std::sqrt(f->gamma * f->R * f->T_inf);
+  a.R_dv = f->rdv_sigmas * a.sigma_0;
+  for (int d = 0; d < D; ++d) a.centre[d] = 0.4 * a.U_inf * e[d];
+  const double span = 2.0 * a.R_dv / f->h_std;   // elements per axis needed at h_std
+  int L = 0;
+  while (std::ldexp(1.0, L) < span) {
+    if (++L > 30) return fail(AVS_E_INVALID, "velocity box needs more than 2^30 elements per axis at h_std");
+  }
+  a.L_max = L;
+  a.h_min = 2.0 * a.R_dv / std::ldexp(1.0, L);
+  a.L_w = (f->T_wall / f->T_inf < 4.0) ? a.L_max : a.L_max - 1;
+  a.L_min = (D == 2 && f->Ma > 5.0) ? 4 : 3;
+  a.L_sep = std::max(a.L_min, a.L_w - 1);
+  a.k_sigma = std::exp(-8.0);                   // f(4) / f(0) of the standard normal density
+  a.C1 = 13.749 * std::pow(f->Ma, -1.465);      // +inf at Ma = 0: nothing splits
+  a.C2 = a.k_sigma * a.C1;
+  const int lr = std::min(a.L_min, a.L_max);
+  const int ml = a.L_max - lr;
+  if (ml > 12) return fail(AVS_E_INVALID, "velocity space needs %d levels below the roots (at most 12)", ml);
+  if (p) *p = a;
+  if (vs) {
+    avs_vspace v{};
+    v.dim = D;
+    v.max_level = ml;
+    for (int d = 0; d < 3; ++d) {
+      v.base[d] = d < D ? (1 << lr) : 1;
+      v.lo[d] = d < D ? a.centre[d] - a.R_dv : 0.0;
+      v.hi[d] = d < D ? a.centre[d] + a.R_dv : 1.0;
+    }
+    v.leaf_capacity = std::min<int64_t>(int64_t(1) << std::min(D * a.L_max, 26), int64_t(1) << 26);
+    *vs = v;
+  }
+  return AVS_OK;
+}
 
 extern "C" {
 
@@ -1720,6 +1781,70 @@ avs_status avs_adapt_learned(avs_ctx* ctx, avs_mlp* mlp, double C1, double C2, c
   ctx->plan_valid = false;
   if (avs_status st = DISPATCH(ctx, launch_adapt, ctx, C1, C2, nprobes)) return st;
   return finish_plan(ctx, flags_dev, n_new_host);
+}
+
+avs_status avs_auto_params(const avs_flow* flow, avs_auto* params_out, avs_vspace* vspace_out) {
+  return auto_params_host(flow, params_out, vspace_out);
+}
+
+avs_status avs_initial_avs(avs_ctx* ctx, const avs_flow* flow, double C1, double C2, int64_t* n_leaves_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
+  avs_auto a;
+  avs_vspace vs;
+  if (avs_status st = auto_params_host(flow, &a, &vs)) return st;
+  const int D = ctx->D;
+  bool same = flow->dim == D && vs.max_level == ctx->lmax && flow->R == ctx->gas.R;
+  for (int d = 0; d < D; ++d)
+    same = same && vs.base[d] == ctx->base[d] && vs.lo[d] == ctx->lo[d] && vs.hi[d] == ctx->hi[d];
+  if (!same) return fail(AVS_E_INVALID, "the context's velocity space or gas constant is not the one avs_auto_params gives for this flow");
+  // step 2: the box split L_w - 1 times (relative to the roots at level min(L_min, L_max))
+  const int lr = std::min(a.L_min, a.L_max);
+  const int lev = std::min(std::max(a.L_w - 1 - lr, 0), ctx->lmax);
+  int64_t n = 1;
+  int cnt[3] = {1, 1, 1};
+  for (int d = 0; d < D; ++d) {
+    cnt[d] = ctx->base[d] << lev;
+    n *= cnt[d];
+  }
+  if (n > ctx->cap) return fail(AVS_E_CAPACITY, "uniform step-0 mesh of %" PRId64 " leaves exceeds leaf_capacity", n);
+  std::vector<std::pair<uint64_t, int64_t>> order((size_t)n);
+  std::vector<int> ix((size_t)n * D);
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t r = k;
+    for (int d = 0; d < D; ++d) {
+      ix[(size_t)k * D + d] = (int)(r % cnt[d]);
+      r /= cnt[d];
+    }
+    order[(size_t)k] = {morton(D, ctx->lmax, lev, &ix[(size_t)k * D]), k};
+  }
+  std::sort(order.begin(), order.end());
+  std::vector<int32_t> lvl((size_t)n, lev), idx((size_t)n * D);
+  for (int64_t j = 0; j < n; ++j)
+    for (int d = 0; d < D; ++d) idx[(size_t)j * D + d] = ix[(size_t)order[(size_t)j].second * D + d];
+  if (avs_status st = avs_set_leaves(ctx, n, lvl.data(), idx.data())) return st;
+  // step 3: one adaptation over the freestream and static states only
+  std::vector<double> probes(2 * (size_t)(D + 2), 0.0);
+  probes[0] = flow->rho_inf;
+  probes[D + 1] = flow->T_inf;
+  probes[D + 2] = flow->rho_inf;
+  probes[2 * (D + 2) - 1] = flow->T_inf;
+  double norm = 0.0;
+  for (int d = 0; d < D; ++d) norm += flow->direction[d] * flow->direction[d];
+  norm = std::sqrt(norm);
+  for (int d = 0; d < D; ++d) probes[1 + d] = norm > 0.0 ? a.U_inf * (flow->direction[d] / norm) : 0.0;
+  if (avs_status st = upload_probes(ctx, probes.data(), 2)) return st;
+  ctx->plan_valid = false;
+  if (avs_status st = DISPATCH(ctx, launch_adapt, ctx, C1, C2, 2, false)) return st;
+  int64_t n_new = 0;
+  if (avs_status st = finish_plan(ctx, nullptr, &n_new)) return st;
+  // commit the new leaves, then the conservative discrete Maxwellian of W on them
+  if (avs_status st = avs_remap(ctx, 0)) return st;
+  if (avs_status st = DISPATCH(ctx, launch_init_vdf, ctx)) return st;
+  if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
+  if (avs_status st = check_bad(ctx)) return st;
+  if (n_leaves_host) *n_leaves_host = n_new;
+  return AVS_OK;
 }
 
 void avs_destroy(avs_ctx* ctx) {

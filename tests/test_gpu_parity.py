@@ -161,6 +161,41 @@ def test_cells_with_fewer_faces_than_slots(avs, D):
     assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
 
 
+@pytest.mark.parametrize("dim,Ma", [(2, 2.0), (2, 6.0), (3, 4.25)])
+def test_initial_avs_matches_oracle(avs, dim, Ma):
+    """Step-0 velocity space of Sec. 3.5 through the C ABI: the leaves after
+    the uniform splits and the probes-only adaptation equal the oracle's bit
+    for bit, and the state is the closed Maxwellian of W on them."""
+    from oracle import avs_params as AP
+    if dim == 2:
+        c = F.cylinder(nr=6, nth=16, Ma=Ma, box=8.0, base=16, max_level=2, r1=2.5, first=0.1)
+        gamma = 5.0 / 3.0
+    else:
+        c = F.sphere(nr=3, nth=4, nph=4, Ma=Ma, box=5.0, base=8, max_level=1, r1=1.5, first=0.2)
+        gamma = 1.4
+    flow = dict(dim=dim, R=c['gas']['R'], gamma=gamma, Ma=Ma, T_inf=1.0, T_wall=1.0)
+    params, vs = avs.auto_params(**flow)
+    C1 = 1e-3
+    C2 = params['k_sigma'] * C1
+    cs = avs.Case(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'], leaf_capacity=vs['leaf_capacity'])
+    n = cs.initial_avs(C1, C2, **flow)
+    f = AP.Flow(**flow)
+    t0, eff, t1 = AP.initial_tree(f, C1=C1, C2=C2)
+    L = cs.leaves()
+    assert n == t1.n == len(L['level'])
+    assert np.array_equal(L['level'], t1.level) and np.array_equal(L['idx'], t1.idx)
+    assert (eff == 1).any()
+    o = O.Solver(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'])
+    o.tree = t1
+    o.phi = o.initial_vdf(o.W)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    # a velocity space that is not the one of this flow is refused
+    with pytest.raises(avs.AvsError):
+        cs.initial_avs(C1, C2, **dict(flow, Ma=Ma + 1.0))
+    cs.close()
+
+
 @pytest.mark.parametrize("which", ["box", "sphere"])
 def test_3d_steps(avs, which):
     if which == "box":
