@@ -413,6 +413,32 @@ def run_learned(args, w, C1):
             "loss_first_last": [losses[0], losses[-1]]}
 
 
+def run_initial_avs(args, Ma=5.0, C1=1e-3):
+    """The automatic velocity space of Sec. 3.5 on the cylinder mesh at Ma 5:
+    host parameters (avs_auto_params), then the step-0 build (uniform
+    splits, one probes-only adaptation, closed Maxwellian of W on the new
+    leaves, avs_initial_avs), timed end to end.  C1 = 1e-3 suits the
+    criterion as printed (the fit of Eq. C1_Ma never splits)."""
+    import torch
+    from paper_2212_05645_amd import avs
+    from workloads import fields as F
+    c = F.cylinder(nr=args.nr, nth=args.nth)
+    flow = dict(dim=2, R=c['gas']['R'], gamma=5.0 / 3.0, Ma=Ma, T_inf=1.0, T_wall=1.0)
+    t0 = time.perf_counter()
+    params, vs = avs.auto_params(**flow)
+    t_params = time.perf_counter() - t0
+    cs = avs.Case(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'], leaf_capacity=vs['leaf_capacity'])
+    cs.initial_avs(C1, params['k_sigma'] * C1, **flow)      # warm-up (first launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = cs.initial_avs(C1, params['k_sigma'] * C1, **flow)
+    t_build = time.perf_counter() - t0
+    cs.close()
+    return {"params_ms": t_params * 1e3, "initial_avs_ms": t_build * 1e3, "leaves": n, "cells": int(c['mesh']['ncells']),
+            "L_max": params['L_max'], "L_min": params['L_min'], "L_w": params['L_w'], "R_dv": params['R_dv'],
+            "C1": C1, "workload": f"cylinder O-grid {args.nr}x{args.nth}, Ma {Ma}, automatic velocity space (Sec. 3.5)"}
+
+
 def run_sphere(args):
     """The 3-D form: supersonic sphere (64 x 64 x 32 cells), octree of 16^3
     roots and 2 levels, FP32 storage; C1 for a step-0 tree of about 20 000
@@ -565,6 +591,11 @@ def main():
             forms["sphere_fp32"] = run_sphere(args)
         except Exception as e:
             forms["sphere_fp32"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        try:
+            forms["initial_avs"] = run_initial_avs(args)
+        except Exception as e:
+            forms["initial_avs"] = {"error": repr(e)}
     cpu = None
     if not args.no_cpu:
         try:
