@@ -128,6 +128,8 @@ class Gas:
     mu_ref: float
     T_ref: float
     model: int = 1               # 0 BGK, 1 Shakhov
+    law: int = 0                 # viscosity: 0 power law (VHS, Eq. equ3), 1 Sutherland (Eq. Sutherland)
+    C_s: float = 0.0             # Sutherland constant, in the units of T
 
 
 def mu_ref_from_kn(Kn, omega, R, T_ref=1.0, rho_ref=1.0, L_ref=1.0):
@@ -159,9 +161,19 @@ def primitive(W, R):
     return rho, U, T
 
 
+def viscosity(T, gas):
+    """mu(T): power law mu_ref (T/T_ref)^omega of the VHS model (Eq. equ3), or
+    Sutherland's law mu_ref (T/T_ref)^(3/2) (T_ref + C_s)/(T + C_s) (Eq.
+    Sutherland, Sec. 4.6, with the reference state in place of the
+    freestream)."""
+    if gas.law == 1:
+        return gas.mu_ref * (T / gas.T_ref) ** 1.5 * (gas.T_ref + gas.C_s) / (T + gas.C_s)
+    return gas.mu_ref * (T / gas.T_ref) ** gas.omega
+
+
 def tau(rho, T, gas):
-    """VHS relaxation time tau = mu / p, mu = mu_ref (T/T_ref)^omega (Eq. equ3)."""
-    return gas.mu_ref * (T / gas.T_ref) ** gas.omega / (rho * gas.R * T)
+    """Relaxation time tau = mu / p (Eq. equ3)."""
+    return viscosity(T, gas) / (rho * gas.R * T)
 
 
 def maxwell(rho, U, T, xi, R):
@@ -653,7 +665,8 @@ def gas_from(cfg):
     mu = cfg.get('mu_ref')
     if mu is None:
         mu = mu_ref_from_kn(cfg['Kn'], cfg['omega'], cfg['R'], cfg['T_ref'], cfg.get('rho_ref', 1.0), cfg.get('L_ref', 1.0))
-    return Gas(R=cfg['R'], Pr=cfg['Pr'], omega=cfg['omega'], mu_ref=mu, T_ref=cfg['T_ref'], model=cfg.get('model', 1))
+    return Gas(R=cfg['R'], Pr=cfg['Pr'], omega=cfg['omega'], mu_ref=mu, T_ref=cfg['T_ref'], model=cfg.get('model', 1),
+               law=cfg.get('law', 0), C_s=cfg.get('C_s', 0.0))
 
 
 class Solver:
