@@ -654,6 +654,21 @@ def correct(phi_p, W, tree, R, close=True):
     return out
 
 
+def bypass(W, tree, R, close=False):
+    """Equilibrium bypass of the reconstruction (end of Sec. 3.3): f =
+    g_eq(W) on the new leaves (H paired as (3-D) R T g), conserving only to
+    quadrature error; with ``close`` followed by the closure C(., W)."""
+    xi = tree.centres()
+    A = tree.weights()
+    D = tree.dim
+    out = np.empty((2 if D == 2 else 1, W.shape[0], tree.n))
+    for i in range(W.shape[0]):
+        rho, U, T = primitive(W[i], R)
+        f = eq_pair(rho, U, T, xi, R)
+        out[:, i] = closure(f, W[i], xi, A, R) if close else f
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Driver mirroring the library's entry points
 # ---------------------------------------------------------------------------
@@ -729,10 +744,17 @@ class Solver:
         return eff, self.plan, Mk
 
     def remap(self, correction=2):
+        """Commit the plan.  correction 0: consanguinity only (Sec. 3.2); 1:
+        plus f' + g(W) - g(W'); 2: plus the closure (Sec. 3.3); 3: the
+        equilibrium bypass f = g_eq(W) for weakly non-equilibrium flow (end
+        of Sec. 3.3); 4: the bypass closed onto W."""
         p = self.plan
-        phi_p = remap(self.phi, p, self.dim)
         self.tree = p.tree
-        if correction:
-            phi_p = correct(phi_p, self.W, self.tree, self.gas.R, close=(correction == 2))
-        self.phi = phi_p
+        if correction in (3, 4):
+            self.phi = bypass(self.W, self.tree, self.gas.R, close=(correction == 4))
+        else:
+            phi_p = remap(self.phi, p, self.dim)
+            if correction:
+                phi_p = correct(phi_p, self.W, self.tree, self.gas.R, close=(correction == 2))
+            self.phi = phi_p
         self.plan = None
