@@ -76,12 +76,16 @@ typedef struct {
   int64_t leaf_capacity;   /* >= number of roots */
 } avs_vspace;
 
-/* Gas model (Sec. 2.1-2.2): relaxation time tau = mu_ref (T/T_ref)^omega /
- * (rho R T) (Eq. equ3); model 0 = BGK target, 1 = Shakhov target with
- * Prandtl number Pr (Eqs. equ14-equ17). */
+/* Gas model (Sec. 2.1-2.2): relaxation time tau = mu(T) / (rho R T) (Eq.
+ * equ3) with mu(T) = mu_ref (T/T_ref)^omega (law 0, VHS power law) or
+ * mu_ref (T/T_ref)^(3/2) (T_ref + C_s)/(T + C_s) (law 1, Sutherland, Eq.
+ * Sutherland of Sec. 4.6; C_s >= 0 in the units of T); model 0 = BGK
+ * target, 1 = Shakhov target with Prandtl number Pr (Eqs. equ14-equ17). */
 typedef struct {
   double R, Pr, omega, mu_ref, T_ref;
   int32_t model;
+  int32_t law;     /* 0 power law, 1 Sutherland */
+  double C_s;      /* Sutherland constant (law 1) */
 } avs_gas;
 
 /* Finite-volume mesh, host arrays, copied at init.  face_lr[f] = (L, R); a
@@ -161,7 +165,12 @@ avs_status avs_adapt(avs_ctx *ctx, double C1, double C2, const double *probes_ho
 /* Apply the plan of the last avs_adapt: consanguinity remap (Sec. 3.2; a
  * child copies its parent, a merged parent is the pairwise mean of its
  * children), then correction 0 = none, 1 = f' + g_eq(W) - g_eq(W') (Sec. 3.3),
- * 2 = that plus the closure that restores M[f] = W to round-off. */
+ * 2 = that plus the closure that restores M[f] = W to round-off.
+ * correction 3 = the equilibrium bypass for weakly non-equilibrium flow (end
+ * of Sec. 3.3): the new leaves take the discrete Maxwellian g_eq(W) of each
+ * cell's W (H = (3 - D) R T G) and the old distribution is not read, so mass,
+ * momentum and energy hold only to quadrature error; 4 = that Maxwellian
+ * closed onto W like the initial state.  Other values: AVS_E_INVALID. */
 avs_status avs_remap(avs_ctx *ctx, int32_t correction);
 
 /* Current velocity mesh.  *n_host = leaf count, *ld_host = VDF row stride.

@@ -37,7 +37,7 @@ class avs_vspace(C.Structure):
 
 class avs_gas(C.Structure):
     _fields_ = [("R", C.c_double), ("Pr", C.c_double), ("omega", C.c_double), ("mu_ref", C.c_double),
-                ("T_ref", C.c_double), ("model", C.c_int32)]
+                ("T_ref", C.c_double), ("model", C.c_int32), ("law", C.c_int32), ("C_s", C.c_double)]
 
 
 class avs_pmesh(C.Structure):
@@ -213,6 +213,8 @@ class Case:
         g.mu_ref = float(gas["mu_ref"]) if gas.get("mu_ref") is not None else mu_ref_from_kn(
             gas["Kn"], gas["omega"], gas["R"], gas["T_ref"], gas.get("rho_ref", 1.0), gas.get("L_ref", 1.0))
         g.model = int(gas.get("model", 1))
+        g.law = int(gas.get("law", 0))           # viscosity: 0 power law, 1 Sutherland
+        g.C_s = float(gas.get("C_s", 0.0))
         op = avs_opts()
         op.precision = int(precision)
         op.dt = float(dt)

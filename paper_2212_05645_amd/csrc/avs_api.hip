@@ -362,11 +362,11 @@ void copy_from_host(std::vector<T>& tmp, const double* src, size_t n) {
 
 // ------------------------------------------------------------- launchers
 template <int D, typename T>
-avs_status launch_init_vdf(avs_ctx* ctx) {
+avs_status launch_init_vdf(avs_ctx* ctx, bool close = true) {
   constexpr int N = D + 2, NS = Cfg<D>::NS;
   const size_t shm = (size_t)(D * ctx->vg.numax + 4 * (N + NS)) * sizeof(double);
   k_init_vdf<D, T><<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, ctx->leaves(ctx->lcur), ctx->vg, ctx->gas, ctx->W,
-                                                       (T*)ctx->vdf[ctx->cur], ctx->bad);
+                                                       (T*)ctx->vdf[ctx->cur], ctx->bad, close ? 1 : 0);
   CKL();
   return AVS_OK;
 }
@@ -497,6 +497,17 @@ avs_status launch_scatter(avs_ctx* ctx) {
 
 template <int D, typename T>
 avs_status launch_remap(avs_ctx* ctx, int correction) {
+  if (correction >= 3) {
+    // Equilibrium bypass: the new leaves take g_eq(W) (closed onto W for 4);
+    // the old distribution is not read.
+    ProfScope ps(ctx, K_REMAP_CORRECT);
+    ctx->lcur ^= 1;
+    ctx->cur ^= 1;
+    avs_status st = launch_init_vdf<D, T>(ctx, correction == 4);
+    ctx->lcur ^= 1;
+    ctx->cur ^= 1;
+    return st;
+  }
   const Leaves Lo = ctx->leaves(ctx->lcur);
   const Leaves Ln = ctx->leaves(ctx->lcur ^ 1);
   T* vout = (T*)ctx->vdf[ctx->cur ^ 1];
@@ -797,6 +808,8 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   if (!gas || !prim0_host || !vdf_dev || !workspace_dev) return fail(AVS_E_INVALID, "null gas/prim0/vdf/workspace pointer");
   if (!(gas->R > 0 && gas->mu_ref > 0 && gas->T_ref > 0 && gas->Pr > 0) || (gas->model != 0 && gas->model != 1))
     return fail(AVS_E_INVALID, "invalid gas parameters");
+  if ((gas->law != 0 && gas->law != 1) || !(gas->C_s >= 0.0 && std::isfinite(gas->C_s)))
+    return fail(AVS_E_INVALID, "viscosity law must be 0 (power) or 1 (Sutherland, C_s >= 0)");
   if (vdf_bytes < avs_vdf_bytes(vs, pm, op)) return fail(AVS_E_INVALID, "vdf region too small (%zu < %zu)", vdf_bytes, avs_vdf_bytes(vs, pm, op));
   if (workspace_bytes < avs_workspace_bytes(vs, pm, op))
     return fail(AVS_E_INVALID, "workspace too small (%zu < %zu)", workspace_bytes, avs_workspace_bytes(vs, pm, op));
@@ -929,7 +942,7 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
     x.vg.hh[d] = (x.hi[d] - x.lo[d]) / (double)((int64_t)x.base[d] << (vs->max_level + 1));
   }
   x.vg.numax = numax_of(vs);
-  x.gas = GasP{gas->R, gas->Pr, gas->omega, gas->mu_ref, gas->T_ref, gas->model};
+  x.gas = GasP{gas->R, gas->Pr, gas->omega, gas->mu_ref, gas->T_ref, gas->model, gas->law, gas->C_s};
   x.dt = op->dt;
   x.h = 0.5 * op->dt;
   x.Kv = op->venkat_K;
@@ -1119,7 +1132,7 @@ avs_status avs_adapt(avs_ctx* ctx, double C1, double C2, const double* probes_ho
 avs_status avs_remap(avs_ctx* ctx, int32_t correction) {
   if (avs_status st = guard(ctx)) return st;
   if (!ctx->plan_valid) return fail(AVS_E_STATE, "no adaptation plan (call avs_adapt first)");
-  if (correction < 0 || correction > 2) return fail(AVS_E_INVALID, "correction must be 0, 1 or 2");
+  if (correction < 0 || correction > 4) return fail(AVS_E_INVALID, "correction must be 0 to 4");
   if (avs_status st = DISPATCH(ctx, launch_remap, ctx, correction)) return st;
   ctx->lcur ^= 1;
   ctx->cur ^= 1;
@@ -1433,7 +1446,7 @@ avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2
 
 avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
   if (!b) return fail(AVS_E_INVALID, "null batch");
-  if (correction < 0 || correction > 2) return fail(AVS_E_INVALID, "correction must be 0, 1 or 2");
+  if (correction < 0 || correction > 4) return fail(AVS_E_INVALID, "correction must be 0 to 4");
   const int n = (int)b->cases.size();
   for (int i = 0; i < n; ++i) {
     if (avs_status st = guard(b->cases[i])) return st;

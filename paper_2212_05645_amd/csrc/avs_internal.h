@@ -75,6 +75,8 @@ struct VGrid {          // the half-finest grid that carries every leaf centre
 struct GasP {
   double R, Pr, omega, mu_ref, T_ref;
   int model;
+  int law;         // viscosity: 0 power law, 1 Sutherland
+  double C_s;      // Sutherland constant
 };
 
 }  // namespace avs

@@ -192,8 +192,13 @@ __device__ __forceinline__ void eq_record(double* par, double rho, const double 
   par[P_SHK] = gas.model == 1 ? (1.0 - gas.Pr) / (5.0 * rho * RT * RT) : 0.0;
 }
 
+// tau = mu(T) / p (Eq. equ3): VHS power law, or Sutherland's law (Eq.
+// Sutherland) with the reference state in place of the freestream.
 __device__ __forceinline__ double tau_of(double rho, double T, const GasP& gas) {
-  return gas.mu_ref * pow(T / gas.T_ref, gas.omega) / (rho * gas.R * T);
+  const double mu = gas.law == 1
+                        ? gas.mu_ref * pow(T / gas.T_ref, 1.5) * (gas.T_ref + gas.C_s) / (T + gas.C_s)
+                        : gas.mu_ref * pow(T / gas.T_ref, gas.omega);
+  return mu / (rho * gas.R * T);
 }
 
 // Solve J x = b ((D+2)x(D+2)) by Gaussian elimination with partial pivoting.
@@ -350,7 +355,7 @@ __global__ void k_leaf_geom(int n, int cap, const int* __restrict__ level, const
 // equilibrium directions so that its moments equal W.
 template <int D, typename T>
 __global__ __launch_bounds__(BLOCK) void k_init_vdf(Geo g, Leaves L, VGrid vg, GasP gas, const double* __restrict__ W,
-                                                     T* __restrict__ vdf, int* __restrict__ bad) {
+                                                     T* __restrict__ vdf, int* __restrict__ bad, int close) {
   constexpr int N = D + 2, NS = Cfg<D>::NS;
   extern __shared__ double lds[];
   double* tab = lds;
@@ -367,29 +372,33 @@ __global__ __launch_bounds__(BLOCK) void k_init_vdf(Geo g, Leaves L, VGrid vg, G
   __syncthreads();
   build_tab<D>(tab, par, vg);
   __syncthreads();
-  double acc[N + NS];
+  if (close) {
+    double acc[N + NS];
 #pragma unroll
-  for (int m = 0; m < N + NS; ++m) acc[m] = 0.0;
-  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[D], A;
-    int u[D];
-    leaf_load<D>(L, k, xi, A, u);
-    const double gv = maxw<D>(par, tab, vg.numax, u);
-    double c[D], c2 = 0.0, xi2 = 0.0;
+    for (int m = 0; m < N + NS; ++m) acc[m] = 0.0;
+    for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+      double xi[D], A;
+      int u[D];
+      leaf_load<D>(L, k, xi, A, u);
+      const double gv = maxw<D>(par, tab, vg.numax, u);
+      double c[D], c2 = 0.0, xi2 = 0.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) { c[d] = xi[d] - par[P_U + d]; c2 += c[d] * c[d]; xi2 += xi[d] * xi[d]; }
-    mom_acc<D>(acc, A, xi, xi2, gv, D == 2 ? par[P_RT] * gv : 0.0);
-    gram_acc<D>(acc + N, A * gv, c, c2);
-  }
-  block_sum<N + NS>(acc, red);
-  if (threadIdx.x == 0) {
+      for (int d = 0; d < D; ++d) { c[d] = xi[d] - par[P_U + d]; c2 += c[d] * c[d]; xi2 += xi[d] * xi[d]; }
+      mom_acc<D>(acc, A, xi, xi2, gv, D == 2 ? par[P_RT] * gv : 0.0);
+      gram_acc<D>(acc + N, A * gv, c, c2);
+    }
+    block_sum<N + NS>(acc, red);
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int m = 0; m < NS; ++m) cw.S[m] = acc[N + m];
-    gram_to_J<D>(cw.S, par, cw.J);
+      for (int m = 0; m < NS; ++m) cw.S[m] = acc[N + m];
+      gram_to_J<D>(cw.S, par, cw.J);
 #pragma unroll
-    for (int m = 0; m < N; ++m) cw.b[m] = W[(size_t)i * N + m] - acc[m];
-    if (!solve_small<N>(cw.J, cw.b, cw.x)) atomicMin(bad, i);
-    for (int m = 0; m < N; ++m) lam[m] = cw.x[m];
+      for (int m = 0; m < N; ++m) cw.b[m] = W[(size_t)i * N + m] - acc[m];
+      if (!solve_small<N>(cw.J, cw.b, cw.x)) atomicMin(bad, i);
+      for (int m = 0; m < N; ++m) lam[m] = cw.x[m];
+    }
+  } else if (threadIdx.x < N) {
+    lam[threadIdx.x] = 0.0;     // the discrete Maxwellian as it is
   }
   __syncthreads();
   const size_t cs = (size_t)g.nc * L.ld;

@@ -136,6 +136,31 @@ def test_ogrid_wall_and_farfield(avs):
     assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sutherland_viscosity(avs, prec):
+    """Sutherland's law for tau (Eq. Sutherland; C_s = 111 K over a 43.22 K
+    freestream, the sphere's nitrogen at Ma 5.45) on the O-grid with walls
+    and far field: FP64 to 1e-12 per step, FP32 form within 1e-5."""
+    c = F.cylinder(nr=6, nth=24, Ma=2.0, box=8.0, base=16, max_level=2, r1=2.5, first=0.1)
+    gas = dict(c['gas'], law=1, C_s=111.0 / 43.22)
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], gas, c['dt'], c['prim0'], tree=resolved_tree(c['vspace'], 5),
+                      noise=0.01, seed=5, precision=prec)
+    assert o.gas.law == 1
+    nstep = 3 if prec == 0 else 5
+    cs.step(nstep)
+    o.step(nstep)
+    v, W = cs.get_state()
+    if prec == 0:
+        assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    else:
+        assert fieldrel(W, o.W) < 1e-5
+    # the power law on the same state gives a different result
+    cp, op = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=resolved_tree(c['vspace'], 5),
+                       noise=0.01, seed=5, precision=prec)
+    cp.step(nstep)
+    assert rel(cp.get_state()[1], W) > 1e-9
+
+
 @pytest.mark.parametrize("D", [2, 3])
 def test_cells_with_fewer_faces_than_slots(avs, D):
     """A cut-out block of a body-fitted grid whose outermost ring has
@@ -300,8 +325,10 @@ def test_adapt_with_probe_states(avs):
     assert o.tree.n == 496 and cs.nleaves() == 496
 
 
-@pytest.mark.parametrize("correction", [1, 2])
+@pytest.mark.parametrize("correction", [1, 2, 3, 4])
 def test_remap_correction(avs, correction):
+    """Corrections 1/2 of Sec. 3.3 and the equilibrium bypass 3/4 (end of
+    Sec. 3.3) against the oracle's remap of the same plan."""
     mesh = MM.box2d(5, 4, periodic=(True, True))
     vs = dict(dim=2, lo=(-6, -6), hi=(6, 6), base=(8, 8), max_level=3)
     gas = dict(R=1.0, Pr=2 / 3, omega=0.5, mu_ref=0.05, T_ref=1.0, model=1)
@@ -309,11 +336,33 @@ def test_remap_correction(avs, correction):
     cs, o = make_pair(avs, mesh, vs, gas, 1e-3, prim, tree=random_tree(vs, 22, 2), noise=0.05, seed=23)
     cs.adapt(5e-3, 1e-4)
     o.adapt(5e-3, 1e-4)
+    with pytest.raises(avs.AvsError):
+        cs.remap(5)
     cs.remap(correction)
     o.remap(correction)
     v, W = cs.get_state()
     assert rel(v, o.phi) < 1e-12
-    if correction == 2:
+    if correction in (2, 4):
+        np.testing.assert_allclose(o.vdf_moments(), W, rtol=1e-12, atol=1e-13)
+    # W is the cell state; only the closed forms reproduce it from the new VDF
+    np.testing.assert_allclose(W, o.W, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("correction", [3, 4])
+def test_bypass_remap_3d(avs, correction):
+    mesh = MM.box3d(3, 3, 2, periodic=(True, True, True))
+    vs = dict(dim=3, lo=(-5, -5, -5), hi=(5, 5, 5), base=(4, 4, 4), max_level=2)
+    gas = dict(R=1.0, Pr=2 / 3, omega=0.5, mu_ref=0.05, T_ref=1.0, model=1)
+    prim = F.perturbed_uniform(mesh['ncells'], 3, 31, amp=0.2, uamp=0.6)
+    cs, o = make_pair(avs, mesh, vs, gas, 1e-3, prim, tree=random_tree(vs, 32, 2), noise=0.05, seed=33)
+    cs.adapt(5e-3, 1e-4)
+    o.adapt(5e-3, 1e-4)
+    cs.remap(correction)
+    o.remap(correction)
+    v, W = cs.get_state()
+    assert cs.nleaves() == o.tree.n
+    assert rel(v, o.phi) < 1e-12
+    if correction == 4:
         np.testing.assert_allclose(o.vdf_moments(), W, rtol=1e-12, atol=1e-13)
 
 
