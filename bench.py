@@ -439,6 +439,54 @@ def run_initial_avs(args, Ma=5.0, C1=1e-3):
             "C1": C1, "workload": f"cylinder O-grid {args.nr}x{args.nth}, Ma {Ma}, automatic velocity space (Sec. 3.5)"}
 
 
+def run_wedge(args, precision, C1=1e-3):
+    """Unstructured physical mesh: the hypersonic blunt wedge (Ma 8.1,
+    about 11 900 triangles), automatic velocity space of Sec. 3.5 with its
+    step-0 build, then the timed cycles of the main workload (sweeps,
+    adaptation on cells, closed remap).  C1 = 1e-3 gives a step-0 space of
+    574 leaves (the paper's wedge run ends with 568 elements)."""
+    import torch
+    from paper_2212_05645_amd import avs
+    from workloads import fields as F
+    flow = F.wedge_flow()
+    params, vs = avs.auto_params(**flow)
+    c = F.blunt_wedge(vs)
+    C2 = params['k_sigma'] * C1
+    cs = avs.Case(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'], leaf_capacity=vs['leaf_capacity'],
+                  precision=avs.AVS_FP32 if precision == "fp32" else avs.AVS_FP64)
+    n0 = cs.initial_avs(C1, C2, **flow)
+    nu = args.nu
+    for _ in range(args.warmup):
+        cs.step(nu)
+        cs.adapt(C1, C2)
+        cs.remap(2)
+    torch.cuda.synchronize()
+    cs.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    updates = 0
+    leaves = []
+    e0.record(cs.stream)
+    for _ in range(args.steps):
+        leaves.append(cs.nleaves())
+        updates += cs.nc * leaves[-1] * nu
+        cs.step(nu)
+        cs.adapt(C1, C2)
+        cs.remap(2)
+    e1.record(cs.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = cs.profile_read()
+    cs.profile(False)
+    out = {"cycle_updates_per_s": updates / (ms * 1e-3), "ms_per_cycle": ms / args.steps, "cells": cs.nc,
+           "leaves_step0": n0, "leaves": leaves, "sweeps_per_cycle": nu, "C1": C1,
+           "L_max": params['L_max'], "L_min": params['L_min'], "R_dv": params['R_dv'],
+           "kernels_ms_per_launch": {k: v[0] / v[1] for k, v in prof.items()},
+           "workload": f"blunt wedge Ma 8.1, unstructured {cs.nc} triangles, automatic velocity space "
+                       f"({vs['base'][0]}^2 roots x {vs['max_level']} levels), {precision.upper()}"}
+    cs.close()
+    return out
+
+
 def run_sphere(args):
     """The 3-D form: supersonic sphere (64 x 64 x 32 cells), octree of 16^3
     roots and 2 levels, FP32 storage; C1 for a step-0 tree of about 20 000
@@ -596,6 +644,11 @@ def main():
             forms["initial_avs"] = run_initial_avs(args)
         except Exception as e:
             forms["initial_avs"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        try:
+            forms["wedge_unstructured"] = run_wedge(args, args.precision)
+        except Exception as e:
+            forms["wedge_unstructured"] = {"error": repr(e)}
     cpu = None
     if not args.no_cpu:
         try:

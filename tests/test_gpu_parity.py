@@ -221,6 +221,92 @@ def test_initial_avs_matches_oracle(avs, dim, Ma):
     cs.close()
 
 
+# ------------------------------------------------ unstructured meshes ------
+def test_unstructured_triangles(avs):
+    """Triangles of a jittered lattice with random diagonals (three faces
+    per cell, corner cells with one interior neighbour take the
+    pseudo-inverse gradient), walls below and above, far field left and
+    right: steps, one adaptation (flags bit exact) with the closed remap,
+    and more steps, FP64 to 1e-12."""
+    U = 1.5 * math.sqrt(5.0 / 3.0)
+    mesh = MM.tri_box(10, 8, 41, lx=1.25, ly=1.0, sides=dict(left=1, right=1, bottom=0, top=0),
+                      bcs=[(MM.WALL, (1.0, 0.0, 0.0, 1.3)), (MM.FARFIELD, (1.0, U, 0.0, 1.0))])
+    vs = dict(dim=2, lo=(-6.0, -6.0), hi=(8.0, 6.0), base=(8, 8), max_level=2)
+    gas = dict(R=1.0, Pr=2 / 3, omega=0.81, mu_ref=0.02, T_ref=1.0, model=1)
+    prim = F.perturbed_uniform(mesh['ncells'], 2, 42, amp=0.1, uamp=0.5)
+    cs, o = make_pair(avs, mesh, vs, gas, 2e-3, prim, tree=random_tree(vs, 43, 2), noise=0.01, seed=44, Kv=0.0)
+    cs.step(3)
+    o.step(3)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    flags, nn = cs.adapt(5e-3, 1e-4)
+    eff, plan, _ = o.adapt(5e-3, 1e-4)
+    assert np.array_equal(flags, eff) and nn == plan.tree.n
+    cs.remap(2)
+    o.remap(2)
+    cs.step(2)
+    o.step(2)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+
+
+def test_unstructured_tetrahedra(avs):
+    """Tetrahedra (six per jittered hexahedron, four faces each) with walls
+    on every side, FP64 steps to 1e-12."""
+    mesh = MM.tet_box(3, 3, 2, 51)
+    vs = dict(dim=3, lo=(-5.0,) * 3, hi=(5.0,) * 3, base=(4, 4, 4), max_level=2)
+    gas = dict(R=1.0, Pr=2 / 3, omega=0.5, mu_ref=0.05, T_ref=1.0, model=1)
+    prim = F.perturbed_uniform(mesh['ncells'], 3, 52, amp=0.1, uamp=0.4)
+    cs, o = make_pair(avs, mesh, vs, gas, 1e-3, prim, tree=random_tree(vs, 53, 2), noise=0.01, seed=54)
+    cs.step(2)
+    o.step(2)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+
+
+def test_blunt_wedge_full_size(avs):
+    """The unstructured blunt-wedge workload at full size (about 11 900
+    triangles, Ma 8.1): the step-0 velocity space of Sec. 3.5 built by the
+    library equals the oracle's leaf for leaf; after one step in the
+    benchmark's launch configuration, sampled cells (wall, nose, flank,
+    base, far field) are recomputed by the oracle from their two-ring
+    neighbourhood and compared element by element."""
+    from oracle import avs_params as AP
+    flow = F.wedge_flow()
+    params, vs = avs.auto_params(**flow)
+    c = F.blunt_wedge(vs)
+    C1 = 1e-3
+    C2 = params['k_sigma'] * C1
+    cs = avs.Case(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'], leaf_capacity=vs['leaf_capacity'])
+    n = cs.initial_avs(C1, C2, **flow)
+    _, _, t = AP.initial_tree(AP.Flow(**flow), C1=C1, C2=C2)
+    L = cs.leaves()
+    assert n == t.n and np.array_equal(L['level'], t.level) and np.array_equal(L['idx'], t.idx)
+    cs.step(1)
+    m = c['mesh']
+    lr = m['face_lr']
+    wall = lr[lr[:, 1] == -1, 0]
+    far = lr[lr[:, 1] == -2, 0]
+    ctr = m['cell_ctr']
+    sample = sorted(set([int(wall[0]), int(wall[len(wall) // 2]), int(far[0]), int(far[-1]),
+                         int(np.argmin(np.hypot(ctr[:, 0] + 0.3, ctr[:, 1]))),      # ahead of the nose
+                         int(np.argmin(np.hypot(ctr[:, 0] - 7.0, ctr[:, 1]))),      # behind the base
+                         int(np.argmin(np.hypot(ctr[:, 0] - 3.0, ctr[:, 1] - 2.0))),  # above the flank
+                         m['ncells'] - 1]))
+    got = cs.get_cells(sample)
+    Wg = cs.get_W()[sample]
+    sub, keep = MM.submesh(m, sample, halo=2)
+    gas = O.gas_from(c['gas'])
+    o = O.Solver(sub, vs, gas, c['dt'], c['venkat_K'], c['prim0'][keep])
+    o.tree = t
+    o.phi = o.initial_vdf(o.W)
+    loc = [int(np.searchsorted(keep, i)) for i in sample]
+    phi1, W1, _ = O.step(o.mesh, t, gas, c['dt'], c['venkat_K'], o.phi, o.W, cells=loc)
+    assert rel(got, phi1[:, loc]) < 1e-12
+    assert rel(Wg, W1[loc]) < 1e-13
+    cs.close()
+
+
 @pytest.mark.parametrize("which", ["box", "sphere"])
 def test_3d_steps(avs, which):
     if which == "box":

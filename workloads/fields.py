@@ -190,3 +190,31 @@ def batch_cases(seed=0, ncase=64):
         cfg.update(case=c, Kn=Kn, Ma=Ma, geometry=geo, side=side, target_leaves=target)
         out.append(cfg)
     return out
+
+
+def wedge_flow(Ma=8.1):
+    """Freestream of the hypersonic blunt-wedge case (Sec. 4.3 shape):
+    argon (gamma 5/3), units sqrt(R T_inf) with R = 1/2, wall at 273 K
+    against a 189 K freestream, flow along +x."""
+    return dict(dim=2, R=0.5, gamma=5.0 / 3.0, Ma=Ma, T_inf=1.0, T_wall=273.0 / 189.0)
+
+
+def blunt_wedge(vspace, Ma=8.1, Kn=0.338, omega=0.81, C1=1e-3, cfl=0.8, seed=0, **mesh_kw):
+    """2-D hypersonic flow over a blunt wedge on an unstructured triangle
+    mesh (Sec. 4.3 shape: nose radius 1, half angle 10 deg, base height
+    3.736 nose radii, about 11 900 cells; Kn 0.338 on the nose radius).
+    ``vspace`` is the velocity space (the automatic one of Sec. 3.5 for
+    ``wedge_flow(Ma)`` in the paper's run); the time step follows from it."""
+    fl = wedge_flow(Ma)
+    R, Tinf, gamma = fl['R'], fl['T_inf'], fl['gamma']
+    mesh = meshes.blunt_wedge(seed=seed, **mesh_kw)
+    U_inf = Ma * math.sqrt(gamma * R * Tinf)
+    mesh['bc_state'][0] = (1.0, 0.0, 0.0, fl['T_wall'])
+    mesh['bc_state'][1] = (1.0, U_inf, 0.0, Tinf)
+    # the nose circle is centred one radius behind the tip
+    W0, probes = blunt_body_field(mesh['cell_ctr'] - np.array([1.0, 0.0]), 1.0, Ma, R, Tinf, seed=seed)
+    lo, hi = np.asarray(vspace['lo'], np.float64), np.asarray(vspace['hi'], np.float64)
+    dt = _cfl_dt(mesh, cfl, np.maximum(np.abs(lo), np.abs(hi)))
+    return dict(name='blunt_wedge', dim=2, mesh=mesh, prim0=W0, probes=probes, vspace=dict(vspace), flow=fl,
+                gas=dict(R=R, Pr=2.0 / 3.0, omega=omega, Kn=Kn, L_ref=1.0, rho_ref=1.0, T_ref=Tinf, model=1),
+                dt=dt, venkat_K=0.0, C1=C1, C2=math.exp(-8.0) * C1, nu=20, steps=50)

@@ -19,6 +19,8 @@ Conventions
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 WALL = 0
@@ -310,3 +312,235 @@ def submesh(desc, cells, halo=2):
                face_lr=sub_lr, face_area=desc['face_area'][fsel], face_nrm=desc['face_nrm'][fsel],
                face_ctr=desc['face_ctr'][fsel], face_shift=desc['face_shift'][fsel])
     return sub, keep
+
+
+# ------------------------------------------------------------- simplices ---
+
+def simplicial(points, simplices, classify, bcs, shape=None):
+    """Finite-volume mesh of triangles (2-D) or tetrahedra (3-D).
+
+    ``points`` (nv, D), ``simplices`` (nc, D+1) vertex ids.  A face shared
+    by two cells runs from the lower cell id (L) to the other; a face with
+    one cell is a boundary face whose bc id is ``classify(face_centre)``
+    and whose normal points out of the cell.  Cell centres are centroids.
+    """
+    P = np.asarray(points, np.float64)
+    S = np.asarray(simplices, np.int64)
+    D = P.shape[1]
+    X = P[S]                                   # (nc, D+1, D)
+    E = X[:, 1:, :] - X[:, :1, :]
+    vol = np.abs(np.linalg.det(E)) / (2.0 if D == 2 else 6.0)
+    if not np.all(vol > 0):
+        raise ValueError("degenerate simplex")
+    ctr = X.mean(axis=1)
+    owner = {}
+    for c in range(len(S)):
+        for k in range(D + 1):
+            key = tuple(sorted(int(v) for v in np.delete(S[c], k)))
+            owner.setdefault(key, []).append((c, int(S[c, k])))
+    faces = []
+    for key in sorted(owner):
+        cells = sorted(owner[key])
+        if len(cells) > 2:
+            raise ValueError("non-manifold face")
+        V = P[list(key)]
+        fc = V.mean(axis=0)
+        if D == 2:
+            t = V[1] - V[0]
+            area = float(np.hypot(t[0], t[1]))
+            n = np.array([t[1], -t[0]]) / area
+        else:
+            cr = np.cross(V[1] - V[0], V[2] - V[0])
+            area = 0.5 * float(np.linalg.norm(cr))
+            n = cr / (2.0 * area)
+        L, opp = cells[0]
+        if np.dot(n, fc - P[opp]) < 0:         # away from L's opposite vertex
+            n = -n
+        if len(cells) == 2:
+            faces.append(((L, cells[1][0]), area, tuple(n), tuple(fc), (0.0,) * D))
+        else:
+            faces.append(((L, -1 - int(classify(fc))), area, tuple(n), tuple(fc), (0.0,) * D))
+    return _finish(D, vol, ctr, faces, bcs, shape if shape is not None else (len(S),))
+
+
+def _side_bc(lo, hi, sides):
+    """Boundary classifier of a box: the side whose plane the face centre
+    lies on (x- x+ y- y+ z- z+ as 'left','right','bottom','top','front','back')."""
+    names = ['left', 'right', 'bottom', 'top', 'front', 'back']
+    span = np.asarray(hi, np.float64) - np.asarray(lo, np.float64)
+
+    def classify(fc):
+        best, arg = np.inf, None
+        for ax in range(len(span)):
+            for s, plane in ((0, lo[ax]), (1, hi[ax])):
+                d = abs(fc[ax] - plane) / span[ax]
+                if d < best:
+                    best, arg = d, names[2 * ax + s]
+        return sides[arg]
+    return classify
+
+
+def tri_box(nx, ny, seed, lx=1.0, ly=1.0, jitter=0.2, sides=None, bcs=None):
+    """Unstructured triangles on ``[0,lx] x [0,ly]``: a lattice of
+    ``(nx+1) x (ny+1)`` vertices moved by a seeded jitter of up to
+    ``jitter`` of the spacing (boundary vertices slide along their side,
+    corners stay), each quad cut along a seeded random diagonal.  2 nx ny
+    cells with three faces each."""
+    rng = np.random.default_rng(seed)
+    hx, hy = lx / nx, ly / ny
+    I, J = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing='ij')
+    px = I * hx + jitter * hx * rng.uniform(-1, 1, I.shape) * ((I > 0) & (I < nx))
+    py = J * hy + jitter * hy * rng.uniform(-1, 1, J.shape) * ((J > 0) & (J < ny))
+    pts = np.stack([px.ravel(), py.ravel()], 1)
+    vid = lambda i, j: i * (ny + 1) + j
+    diag = rng.integers(0, 2, (nx, ny))
+    tris = []
+    for i in range(nx):
+        for j in range(ny):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            tris += [(a, b, c), (a, c, d)] if diag[i, j] else [(a, b, d), (b, c, d)]
+    sides = sides or {}
+    return simplicial(pts, tris, _side_bc((0.0, 0.0), (lx, ly), sides), bcs or [])
+
+
+def tet_box(nx, ny, nz, seed, l=(1.0, 1.0, 1.0), jitter=0.12, sides=None, bcs=None):
+    """Unstructured tetrahedra in a box: a jittered vertex lattice (boundary
+    vertices stay on their faces), each hexahedron cut into the six
+    tetrahedra around its main diagonal (the same cut everywhere, so faces
+    match).  6 nx ny nz cells with four faces each."""
+    rng = np.random.default_rng(seed)
+    n = (nx, ny, nz)
+    h = [l[a] / n[a] for a in range(3)]
+    G = np.meshgrid(*[np.arange(m + 1) for m in n], indexing='ij')
+    pts = np.stack([(G[a] * h[a] + jitter * h[a] * rng.uniform(-1, 1, G[a].shape) * ((G[a] > 0) & (G[a] < n[a])))
+                    .ravel() for a in range(3)], 1)
+    vid = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k
+    # the six monotone paths from corner 000 to 111
+    paths = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    tets = []
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                for p in paths:
+                    c = [0, 0, 0]
+                    vs = [vid(i, j, k)]
+                    for ax in p:
+                        c[ax] = 1
+                        vs.append(vid(i + c[0], j + c[1], k + c[2]))
+                    tets.append(vs)
+    sides = sides or {s: 0 for s in ['left', 'right', 'bottom', 'top', 'front', 'back']}
+    return simplicial(pts, tets, _side_bc((0.0, 0.0, 0.0), l, sides), bcs or [(WALL, (1.0, 0.0, 0.0, 0.0, 1.0))])
+
+
+def wedge_outline(nose=1.0, half_angle_deg=10.0, base_height=3.736, h=0.05):
+    """Closed counter-clockwise outline of a 2-D blunt wedge pointing
+    upstream (-x): a nose circle of radius ``nose`` centred at (nose, 0)
+    joined tangentially to two straight flanks of the given half angle,
+    closed by a flat base of height ``base_height``.  Points are spaced
+    about ``h`` apart.  Returns (points, base x)."""
+    th = math.radians(half_angle_deg)
+    cx = nose
+    yt = nose * math.cos(th)
+    xt = cx - nose * math.sin(th)
+    yb = 0.5 * base_height
+    xb = xt + (yb - yt) / math.tan(th)
+    # the nose arc runs from the lower tangent point through the tip to the upper one
+    a0, a1 = -(math.pi / 2 + th), -(3 * math.pi / 2 - th)
+    out = []
+
+    def seg(p, q):
+        n = max(1, int(math.ceil(math.hypot(q[0] - p[0], q[1] - p[1]) / h)))
+        for k in range(n):
+            out.append((p[0] + (q[0] - p[0]) * k / n, p[1] + (q[1] - p[1]) * k / n))
+    # base (bottom to top), upper flank, nose arc, lower flank
+    seg((xb, -yb), (xb, yb))
+    seg((xb, yb), (xt, yt))
+    na = max(2, int(math.ceil(nose * abs(a1 - a0) / h)))
+    for k in range(na):
+        a = -a0 + (-a1 + a0) * k / na
+        out.append((cx + nose * math.cos(a), nose * math.sin(a)))
+    seg((xt, -yt), (xb, -yb))
+    return np.array(out), xb
+
+
+def _convex_offset(poly, d, h):
+    """Points about ``h`` apart on the curve at distance ``d`` outside the
+    convex polygon ``poly`` (counter-clockwise)."""
+    phi = np.linspace(0.0, 2 * np.pi, 4096, endpoint=False)
+    nrm = np.stack([np.cos(phi), np.sin(phi)], 1)
+    sup = poly[np.argmax(nrm @ poly.T, axis=1)]
+    curve = sup + d * nrm
+    curve = np.vstack([curve, curve[:1]])
+    seg = np.hypot(*(np.diff(curve, axis=0).T))
+    s = np.concatenate([[0.0], np.cumsum(seg)])
+    n = max(8, int(round(s[-1] / h)))
+    t = np.arange(n) * s[-1] / n
+    return np.stack([np.interp(t, s, curve[:, 0]), np.interp(t, s, curve[:, 1])], 1)
+
+
+def _inside_convex(poly, pts):
+    """True where a point lies strictly inside the convex polygon (CCW)."""
+    e = np.roll(poly, -1, axis=0) - poly
+    rel = pts[:, None, :] - poly[None, :, :]
+    cross = e[None, :, 0] * rel[:, :, 1] - e[None, :, 1] * rel[:, :, 0]
+    return np.all(cross > 0, axis=1)
+
+
+def blunt_wedge(seed=0, h_wall=0.0538, growth=1.07, box=(-4.0, 16.0, -8.0, 8.0), jitter=0.15,
+                nose=1.0, half_angle_deg=10.0, base_height=3.736):
+    """Unstructured triangles around a 2-D blunt wedge (lengths in nose radii).
+
+    Layers of points at growing distance from the body (spacing ``h_wall``
+    on the wall, times ``growth`` per layer), moved by a seeded jitter of
+    up to ``jitter`` of their spacing, the sides of the rectangle ``box`` =
+    (x0, x1, y0, y1) sampled at the local spacing, then a Delaunay
+    triangulation with the triangles inside the body removed.  bc 0 = the
+    body (wall), bc 1 = the rectangle (far field); states are filled by the
+    workload.  Cell count grows like 1/h_wall^2 at fixed growth."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    body, xb = wedge_outline(nose, half_angle_deg, base_height, h_wall)
+    x0, x1, y0, y1 = box
+    pts = [body]
+    d, hk = 0.0, h_wall
+    far = max(abs(x0), abs(x1 - xb), abs(y0), abs(y1)) + 2 * nose
+    while d < far:
+        d += 0.866 * hk
+        hk *= growth
+        lay = _convex_offset(body, d, hk)
+        lay = lay + jitter * hk * rng.uniform(-1, 1, lay.shape)
+        keep = ((lay[:, 0] > x0 + 0.5 * hk) & (lay[:, 0] < x1 - 0.5 * hk) &
+                (lay[:, 1] > y0 + 0.5 * hk) & (lay[:, 1] < y1 - 0.5 * hk))
+        pts.append(lay[keep])
+
+    def spacing(p):
+        dist = np.sqrt(np.min(np.sum((body - p) ** 2, axis=1)))
+        # spacing of the layer at this distance: d_k ~ 0.866 h_wall (g^k - 1) / (g - 1) g
+        k = math.log(1.0 + dist * (growth - 1.0) / (0.866 * h_wall * growth)) / math.log(growth)
+        return h_wall * growth ** k
+    rect = [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]
+    for a in range(4):
+        p, q = np.array(rect[a]), np.array(rect[(a + 1) % 4])
+        L = float(np.hypot(*(q - p)))
+        t = 0.0
+        while t < L:
+            pts.append((p + (q - p) * t / L)[None, :])
+            t += spacing(p + (q - p) * t / L)
+    P = np.vstack(pts)
+    tri = Delaunay(P).simplices
+    cen = P[tri].mean(axis=1)
+    tri = tri[~_inside_convex(body, cen)]
+    # counter-clockwise orientation, drop slivers of zero area
+    X = P[tri]
+    cr = (X[:, 1, 0] - X[:, 0, 0]) * (X[:, 2, 1] - X[:, 0, 1]) - (X[:, 1, 1] - X[:, 0, 1]) * (X[:, 2, 0] - X[:, 0, 0])
+    tri = tri[np.abs(cr) > 1e-12 * h_wall * h_wall]
+    used = np.unique(tri)
+    remap = -np.ones(len(P), np.int64)
+    remap[used] = np.arange(len(used))
+    P, tri = P[used], remap[tri]
+    eps = 1e-9 * (x1 - x0)
+
+    def classify(fc):
+        on_rect = (abs(fc[0] - x0) < eps or abs(fc[0] - x1) < eps or abs(fc[1] - y0) < eps or abs(fc[1] - y1) < eps)
+        return 1 if on_rect else 0
+    return simplicial(P, tri, classify, [(WALL, (1.0, 0.0, 0.0, 1.0)), (FARFIELD, (1.0, 0.0, 0.0, 1.0))])
