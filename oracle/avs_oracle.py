@@ -446,6 +446,32 @@ def flux_moments(phi_f, xi, A, n):
     return moments(phi_f * s[None, :], xi, A)
 
 
+def interfaces(mesh, tree, gas, dt, Kv, phi, want):
+    """S2-S7 for the faces of the cells ``want``: limited gradients of the
+    cells those faces touch, interface VDFs (face_vdf) and their flux
+    moments.  Returns (phi_f, F, diag) keyed by face."""
+    xi = tree.centres()
+    A = tree.weights()
+    need_faces = sorted({s.face for i in want for s in mesh.slots[i]})
+    need_lg = set()
+    for f in need_faces:
+        L, R = mesh.lr[f]
+        need_lg.add(int(L))
+        if R >= 0:
+            need_lg.add(int(R))
+    LG = {c: limited_gradient(c, phi, mesh, Kv) for c in sorted(need_lg)}
+    phif, F, diag = {}, {}, StepDiag(face_W={}, face_tau={})
+    for f in need_faces:
+        pf, dg = face_vdf(f, phi, LG, mesh, xi, A, gas, dt)
+        phif[f] = pf
+        F[f] = flux_moments(pf, xi, A, mesh.nrm[f])
+        if dg[0] == 'wall':
+            diag.rho_w[f] = dg[1]
+        elif dg[0] == 'face':
+            diag.face_W[f], diag.face_tau[f] = dg[1]
+    return phif, F, diag
+
+
 def step(mesh, tree, gas, dt, Kv, phi, W, cells=None):
     """Advance (phi, W) by one step; returns (phi_new, W_new, diag).
 
@@ -465,23 +491,7 @@ def step(mesh, tree, gas, dt, Kv, phi, W, cells=None):
     xi = tree.centres()
     A = tree.weights()
     want = range(mesh.nc) if cells is None else list(cells)
-    need_faces = sorted({s.face for i in want for s in mesh.slots[i]})
-    need_lg = set()
-    for f in need_faces:
-        L, R = mesh.lr[f]
-        need_lg.add(int(L))
-        if R >= 0:
-            need_lg.add(int(R))
-    LG = {c: limited_gradient(c, phi, mesh, Kv) for c in sorted(need_lg)}
-    phif, F, diag = {}, {}, StepDiag(face_W={}, face_tau={})
-    for f in need_faces:
-        pf, dg = face_vdf(f, phi, LG, mesh, xi, A, gas, dt)
-        phif[f] = pf
-        F[f] = flux_moments(pf, xi, A, mesh.nrm[f])
-        if dg[0] == 'wall':
-            diag.rho_w[f] = dg[1]
-        elif dg[0] == 'face':
-            diag.face_W[f], diag.face_tau[f] = dg[1]
+    phif, F, diag = interfaces(mesh, tree, gas, dt, Kv, phi, want)
     phi_new = np.full(phi.shape, np.nan)
     W_new = np.full(W.shape, np.nan)
     for i in want:
