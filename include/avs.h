@@ -144,6 +144,30 @@ avs_status avs_init_mesh(const avs_vspace *vs, const avs_pmesh *pm, const avs_ga
  * went non-physical. */
 avs_status avs_step(avs_ctx *ctx, int32_t nsteps, double *residual_host);
 
+/* Bytes of the device region avs_step_implicit needs for the right-hand
+ * side of the micro system: one VDF buffer (components x cells x leaf
+ * capacity x element size). */
+avs_status avs_implicit_bytes(const avs_ctx *ctx, size_t *bytes);
+
+/* Advance nsteps implicit steps (IUGKS, Sec. 2.3.1-2.3.2) with the context's
+ * dt (no explicit stability bound applies to it).  Interface VDFs and
+ * fluxes F^n as in avs_step; then the macroscopic predictor of Eqs.
+ * equ_delw, delta_Flux, Roe and SGS_w (Roe-type flux increment with
+ * r = |U.n| + a + 2 mu/(rho dl) from the interface state, a boundary face
+ * holding the outside increment at zero) solved by macro_sweeps symmetric
+ * point-relaxation Gauss-Seidel sweeps; the closed Shakhov target and tau
+ * from the predicted W; the upwind micro system of Eq. SGS_phi solved by
+ * micro_sweeps symmetric Gauss-Seidel sweeps; phi^{n+1} = phi^n + dphi and
+ * W^{n+1} = the predicted W.  Each sweep runs the colours of a greedy
+ * colouring of the cells in cell order (smallest colour no lower-numbered
+ * face neighbour holds) up, then down; the paper recommends 60 macro and 2
+ * micro sweeps.  res_dev: device scratch of avs_implicit_bytes bytes,
+ * 256-byte aligned, owned by the caller, overwritten.  residual_host as in
+ * avs_step.  Waits for the device; AVS_E_NUMERIC if a predicted state is
+ * non-physical, AVS_E_INVALID for negative counts or a short region. */
+avs_status avs_step_implicit(avs_ctx *ctx, int32_t nsteps, int32_t macro_sweeps, int32_t micro_sweeps, void *res_dev,
+                             size_t res_bytes, double *residual_host);
+
 /* Per-cell fields (rho, U_1..U_D, T, q_1..q_D) into fields_dev
  * [ncells][2*dim+2] (rho, U, T from the authoritative W; q = heat flux of the
  * VDF about U, Eq. equ8) and/or the FP64 totals sum_i V_i W_i into

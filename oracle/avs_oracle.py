@@ -728,6 +728,16 @@ class Solver:
             res = d.residual
         return res
 
+    def step_implicit(self, n=1, macro=60, micro=2):
+        """Implicit steps (oracle.avs_implicit.step_implicit)."""
+        from .avs_implicit import step_implicit
+        res = None
+        for _ in range(n):
+            self.phi, self.W, d = step_implicit(self.mesh, self.tree, self.gas, self.dt, self.Kv, self.phi, self.W,
+                                                macro, micro)
+            res = d.residual
+        return res
+
     def fields(self):
         """rho, U, T from the authoritative W and q from phi about U."""
         xi, A = self.tree.centres(), self.tree.weights()

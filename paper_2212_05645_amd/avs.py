@@ -27,7 +27,8 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_batch_check", "avs_batch_tune", "avs_batch_adapt", "avs_batch_remap", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
            "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
            "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
-           "avs_auto_params", "avs_initial_avs", "avs_destroy", "avs_last_error")
+           "avs_auto_params", "avs_initial_avs", "avs_implicit_bytes", "avs_step_implicit", "avs_destroy",
+           "avs_last_error")
 
 
 class avs_vspace(C.Structure):
@@ -118,6 +119,8 @@ def _load():
         "avs_adapt_learned": (I32, [VP, VP, D, D, VP, I32, D, VP, P(I64), P(I32)]),
         "avs_auto_params": (I32, [P(avs_flow), P(avs_auto), P(avs_vspace)]),
         "avs_initial_avs": (I32, [VP, P(avs_flow), D, D, P(I64)]),
+        "avs_implicit_bytes": (I32, [VP, P(C.c_size_t)]),
+        "avs_step_implicit": (I32, [VP, I32, I32, I32, VP, C.c_size_t, VP]),
         "avs_destroy": (None, [VP]),
         "avs_last_error": (C.c_char_p, []),
     }
@@ -239,6 +242,18 @@ class Case:
     def step(self, n=1, residual=False):
         res = np.zeros(self.dim + 2) if residual else None
         _check(lib.avs_step(self.ctx, int(n), _ptr(res)))
+        return res
+
+    def step_implicit(self, n=1, macro=60, micro=2, residual=False):
+        """Implicit steps (IUGKS) with ``macro`` and ``micro`` symmetric
+        sweeps; the right-hand-side region is allocated once per case."""
+        if getattr(self, "_imp_res", None) is None:
+            nb = C.c_size_t()
+            _check(lib.avs_implicit_bytes(self.ctx, C.byref(nb)))
+            self._imp_res = self._torch.empty(max(nb.value, 256), dtype=self._torch.uint8, device=self.device)
+        res = np.zeros(self.dim + 2) if residual else None
+        _check(lib.avs_step_implicit(self.ctx, int(n), int(macro), int(micro), self._imp_res.data_ptr(),
+                                     self._imp_res.numel(), _ptr(res)))
         return res
 
     def moments(self, fields=True, totals=True):

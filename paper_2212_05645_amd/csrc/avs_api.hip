@@ -12,6 +12,7 @@
 
 #include "../../include/avs.h"
 #include "avs_kernels.hip"
+#include "avs_implicit.hip"
 #include "avs_mlp.hip"
 
 using namespace avs;
@@ -84,6 +85,9 @@ struct avs_ctx {
   double *cc, *crit_part, *Mk, *probe_cc, *probe_prim;
   int8_t *raw, *eff;
   int *cnt, *off, *pkind, *psrc, *pchild, *bad;
+  double *rA, *irhs, *idiag, *dW;                // implicit predictor: A r/2 per face, rhs, diagonal, increment
+  int* col_cells;                                // cells in colour-major order
+  std::vector<int> col_off;                      // colour c holds col_cells[col_off[c] .. col_off[c+1])
   uint16_t* feat = nullptr;                      // learned proposal (2-D): feature rows [cap][32]
   double *quant = nullptr, *tprobe = nullptr, *terr = nullptr;
   int ngrp;
@@ -115,10 +119,12 @@ struct avs_ctx {
 namespace {
 
 enum KernelId { K_PASSA, K_FACE, K_FACE_EQFLUX, K_MACRO, K_TARGET, K_PASSC, K_RESIDUAL, K_CRITERION,
-                K_FLAGS, K_REMAP_GATHER, K_REMAP_CORRECT, K_BC_TABLES, K_MOMENTS, K_INIT, K_LEARNED, K_NKERNELS };
+                K_FLAGS, K_REMAP_GATHER, K_REMAP_CORRECT, K_BC_TABLES, K_MOMENTS, K_INIT, K_LEARNED,
+                K_IMP_MACRO, K_IMP_RES, K_IMP_MICRO, K_NKERNELS };
 const char* const kKernelNames[K_NKERNELS] = {"passA", "face", "face_eqflux", "macro", "target", "passC",
                                               "residual", "criterion", "flags_plan", "remap_gather",
-                                              "remap_correct", "bc_tables", "moments", "init_vdf", "learned"};
+                                              "remap_correct", "bc_tables", "moments", "init_vdf", "learned",
+                                              "imp_macro", "imp_res", "imp_micro"};
 
 hipEvent_t next_event(avs_ctx* ctx) {
   if (ctx->evused == ctx->evpool.size()) {
@@ -255,6 +261,11 @@ void carve(avs_ctx& x, Carver& c) {
   x.psrc = c.take<int>(cap);
   x.pchild = c.take<int>(cap);
   x.bad = c.take<int>(4);
+  x.rA = c.take<double>(nf + 1);
+  x.irhs = c.take<double>(nc * N);
+  x.idiag = c.take<double>(nc);
+  x.dW = c.take<double>(nc * N);
+  x.col_cells = c.take<int>(nc);
   if (D == 2) {
     x.feat = c.take<uint16_t>(cap * mlp::NINP);
     x.quant = c.take<double>(24);
@@ -396,13 +407,13 @@ avs_status launch_bc_tables(avs_ctx* ctx) {
   return AVS_OK;
 }
 
+// Interface stage of a step: reconstruction into the interface buffer,
+// interface moments and records, fluxes F_f.
 template <int D, typename T>
-avs_status launch_step(avs_ctx* ctx, bool last_residual) {
-  constexpr int MAXF = Cfg<D>::MAXF;
+avs_status launch_interfaces(avs_ctx* ctx) {
   const Leaves L = ctx->leaves(ctx->lcur);
   const int nu = ctx->vg.numax;
   const T* vin = (const T*)ctx->vdf[ctx->cur];
-  T* vout = (T*)ctx->vdf[ctx->cur ^ 1];
   {
     ProfScope ps(ctx, K_PASSA);
     const int nch = (L.n + CHUNK - 1) / CHUNK;
@@ -421,6 +432,17 @@ avs_status launch_step(avs_ctx* ctx, bool last_residual) {
         ctx->geo, L, ctx->vg, ctx->gas, ctx->h, ctx->bden, ctx->bfin, ctx->fpar, ctx->F, ctx->bad);
     CKL();
   }
+  return AVS_OK;
+}
+
+template <int D, typename T>
+avs_status launch_step(avs_ctx* ctx, bool last_residual) {
+  constexpr int MAXF = Cfg<D>::MAXF;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int nu = ctx->vg.numax;
+  const T* vin = (const T*)ctx->vdf[ctx->cur];
+  T* vout = (T*)ctx->vdf[ctx->cur ^ 1];
+  if (avs_status st = launch_interfaces<D, T>(ctx)) return st;
   {
     ProfScope ps(ctx, K_MACRO);
     k_macro<D><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, ctx->dt, ctx->F, ctx->W,
@@ -446,6 +468,83 @@ avs_status launch_step(avs_ctx* ctx, bool last_residual) {
   }
   std::swap(ctx->W, ctx->Wn);
   ctx->cur ^= 1;
+  return AVS_OK;
+}
+
+// One implicit step (IUGKS): interfaces as in the explicit step, then the
+// PRSGS predictor (n_macro symmetric sweeps, colours up then down), the
+// target from the predicted state, the micro right-hand side from pass C,
+// n_micro symmetric sweeps of the upwind micro system into the second VDF
+// buffer, phi^{n+1} = phi^n + dphi, and the moments of phi^{n+1}.
+template <int D, typename T>
+avs_status launch_step_implicit(avs_ctx* ctx, int n_macro, int n_micro, T* res, bool last_residual) {
+  constexpr int MAXF = Cfg<D>::MAXF;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int nu = ctx->vg.numax;
+  const T* vin = (const T*)ctx->vdf[ctx->cur];
+  T* dphi = (T*)ctx->vdf[ctx->cur ^ 1];
+  const int ncol = (int)ctx->col_off.size() - 1;
+  const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK);
+  if (avs_status st = launch_interfaces<D, T>(ctx)) return st;
+  {
+    ProfScope ps(ctx, K_IMP_MACRO);
+    k_imp_rface<D><<<(unsigned)((ctx->nf + BLOCK - 1) / BLOCK), BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, ctx->h, ctx->W,
+                                                                                       ctx->fpar, ctx->rA);
+    CKL();
+    k_imp_rhs<D><<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->F, ctx->rA, ctx->irhs, ctx->idiag, ctx->dW);
+    CKL();
+    for (int sw = 0; sw < n_macro; ++sw)
+      for (int t = 0; t < 2 * ncol; ++t) {
+        const int c = t < ncol ? t : 2 * ncol - 1 - t;
+        const int cnt = ctx->col_off[c + 1] - ctx->col_off[c];
+        k_imp_macro<D><<<(unsigned)((cnt + BLOCK - 1) / BLOCK), BLOCK, 0, ctx->stream>>>(
+            ctx->geo, ctx->gas, ctx->col_cells + ctx->col_off[c], cnt, ctx->W, ctx->rA, ctx->irhs, ctx->idiag, ctx->dW);
+        CKL();
+      }
+    k_imp_apply<D><<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, ctx->dt, ctx->W, ctx->dW, ctx->Wn, ctx->q,
+                                                  ctx->tpar, ctx->bad);
+    CKL();
+  }
+  {
+    ProfScope ps(ctx, K_TARGET);
+    k_target<D, T><<<ctx->nc, BLOCK, (size_t)D * nu * sizeof(T), ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->tpar, ctx->Wn,
+                                                                               ctx->lam, ctx->bad);
+    CKL();
+  }
+  {
+    ProfScope ps(ctx, K_IMP_RES);
+    k_passC_res<D, T><<<(unsigned)round_up(ctx->nc, 8), BLOCK, (size_t)(MAXF + 1) * D * nu * sizeof(T), ctx->stream>>>(
+        ctx->geo, L, ctx->vg, vin, (const T*)ctx->fv, res, ctx->fpar, ctx->tpar, ctx->lam);
+    CKL();
+  }
+  {
+    ProfScope ps(ctx, K_IMP_MICRO);
+    k_imp_zero<T><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->P, ctx->nc, L, dphi);
+    CKL();
+    for (int sw = 0; sw < n_micro; ++sw)
+      for (int t = 0; t < 2 * ncol; ++t) {
+        const int c = t < ncol ? t : 2 * ncol - 1 - t;
+        const int cnt = ctx->col_off[c + 1] - ctx->col_off[c];
+        k_imp_micro<D, T><<<(unsigned)cnt, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->col_cells + ctx->col_off[c], res,
+                                                                     dphi, ctx->tpar);
+        CKL();
+      }
+    k_imp_finish<T><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->P, ctx->nc, L, vin, dphi);
+    CKL();
+  }
+  if (last_residual) {
+    ProfScope ps(ctx, K_RESIDUAL);
+    k_residual<D><<<1, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->W, ctx->Wn, 1.0 / ctx->dt, ctx->res);
+    CKL();
+  }
+  std::swap(ctx->W, ctx->Wn);
+  ctx->cur ^= 1;
+  {
+    ProfScope ps(ctx, K_MOMENTS);
+    k_cell_moments<D, T><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, (const T*)ctx->vdf[ctx->cur], ctx->W, ctx->mom,
+                                                            ctx->q);
+    CKL();
+  }
   return AVS_OK;
 }
 
@@ -896,6 +995,30 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
     eps2[i] = pow(op->venkat_K * pow(pm->cell_vol[i], 1.0 / D), 3.0);
     dtv[i] = op->dt / pm->cell_vol[i];
   }
+  // greedy colouring of the face-neighbour graph in cell order (each cell
+  // takes the smallest colour no lower-numbered neighbour holds); the cells
+  // of one colour share no face, so a Gauss-Seidel sweep updates a colour at once
+  std::vector<int> colour(nc, 0), col_cells;
+  int ncol = 0;
+  for (int64_t i = 0; i < nc; ++i) {
+    unsigned used = 0;
+    for (int s = 0; s < nslot[i]; ++s) {
+      const int j = s_nbr[i * maxf + s];
+      if (j >= 0 && j < i) used |= 1u << colour[j];
+    }
+    int c = 0;
+    while (used & (1u << c)) ++c;
+    colour[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  std::vector<int> col_off(ncol + 1, 0);
+  for (int64_t i = 0; i < nc; ++i) ++col_off[colour[i] + 1];
+  for (int c = 0; c < ncol; ++c) col_off[c + 1] += col_off[c];
+  col_cells.resize(nc);
+  {
+    std::vector<int> fillp(col_off.begin(), col_off.end() - 1);
+    for (int64_t i = 0; i < nc; ++i) col_cells[fillp[colour[i]]++] = (int)i;
+  }
   // locality order: Morton key of the centres quantised on 2^(60/D) steps per axis
   std::vector<int> order(nc);
   {
@@ -999,6 +1122,8 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   }
   CKI(H2D(x.W, W0.data(), sizeof(double) * W0.size()));
   CKI(H2D(x.bad, badinit, sizeof badinit));
+  CKI(H2D(x.col_cells, col_cells.data(), sizeof(int) * nc));
+  x.col_off = col_off;
   x.geo.D = D;
   x.geo.P = P;
   x.geo.nc = (int)nc;
@@ -1049,6 +1174,35 @@ avs_status avs_step(avs_ctx* ctx, int32_t nsteps, double* residual_host) {
     if (avs_status st = check_bad(ctx)) return st;
   }
   return AVS_OK;
+}
+
+avs_status avs_implicit_bytes(const avs_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return fail(AVS_E_INVALID, "null argument");
+  *bytes = ctx->vdf_buf_bytes;
+  return AVS_OK;
+}
+
+avs_status avs_step_implicit(avs_ctx* ctx, int32_t nsteps, int32_t macro_sweeps, int32_t micro_sweeps, void* res_dev,
+                             size_t res_bytes, double* residual_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (nsteps < 0 || macro_sweeps < 0 || micro_sweeps < 0) return fail(AVS_E_INVALID, "negative step or sweep count");
+  if (!res_dev || ((uintptr_t)res_dev & 255)) return fail(AVS_E_INVALID, "res_dev must be a 256-byte aligned device region");
+  if (res_bytes < ctx->vdf_buf_bytes)
+    return fail(AVS_E_INVALID, "res region too small (%zu < %zu)", res_bytes, ctx->vdf_buf_bytes);
+  for (int n = 0; n < nsteps; ++n) {
+    const bool last = residual_host && n == nsteps - 1;
+    avs_status st = ctx->D == 2
+                        ? (ctx->prec == AVS_FP64 ? launch_step_implicit<2, double>(ctx, macro_sweeps, micro_sweeps, (double*)res_dev, last)
+                                                 : launch_step_implicit<2, float>(ctx, macro_sweeps, micro_sweeps, (float*)res_dev, last))
+                        : (ctx->prec == AVS_FP64 ? launch_step_implicit<3, double>(ctx, macro_sweeps, micro_sweeps, (double*)res_dev, last)
+                                                 : launch_step_implicit<3, float>(ctx, macro_sweeps, micro_sweeps, (float*)res_dev, last));
+    if (st) return st;
+  }
+  if (residual_host) {
+    if (nsteps == 0) return fail(AVS_E_INVALID, "residual requested for zero steps");
+    CK(hipMemcpyAsync(residual_host, ctx->res, sizeof(double) * (ctx->D + 2), hipMemcpyDeviceToHost, ctx->stream));
+  }
+  return check_bad(ctx);
 }
 
 avs_status avs_moments(avs_ctx* ctx, double* fields_dev, double* totals_host) {

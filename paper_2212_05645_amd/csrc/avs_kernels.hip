@@ -913,6 +913,21 @@ __global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, const R* __rest
 }
 
 // ------------------------------------------------------ macro update (S8-S9)
+// Cell record of the relaxation target from the new state w of cell i:
+// Shakhov parameters with q^n, dt/tau, rho and T.
+template <int D>
+__device__ __forceinline__ void target_record(int i, const double* w, const GasP& gas, double dt,
+                                              const double* __restrict__ qcur, double* __restrict__ tpar,
+                                              int* __restrict__ bad) {
+  double rho, U[D], T;
+  if (!prim_from_W<D>(w, gas, rho, U, T)) { atomicMin(bad, i); rho = 1.0; T = 1.0; }
+  double* par = tpar + (size_t)i * NPAR;
+  eq_record<D>(par, rho, U, T, qcur + (size_t)i * D, gas);
+  par[P_A] = dt / tau_of(rho, T, gas);
+  par[P_RHO] = rho;
+  par[P_T] = T;
+}
+
 template <int D>
 __device__ __forceinline__ void d_macro(Geo g, GasP gas, double dt, const double* __restrict__ F, const double* __restrict__ W,
                         double* __restrict__ Wn, const double* __restrict__ qcur, double* __restrict__ tpar,
@@ -934,13 +949,7 @@ __device__ __forceinline__ void d_macro(Geo g, GasP gas, double dt, const double
     w[m] = W[(size_t)i * N + m] - dtv * Fs[m];
     Wn[(size_t)i * N + m] = w[m];
   }
-  double rho, U[D], T;
-  if (!prim_from_W<D>(w, gas, rho, U, T)) { atomicMin(bad, i); rho = 1.0; T = 1.0; }
-  double* par = tpar + (size_t)i * NPAR;
-  eq_record<D>(par, rho, U, T, qcur + (size_t)i * D, gas);
-  par[P_A] = dt / tau_of(rho, T, gas);
-  par[P_RHO] = rho;
-  par[P_T] = T;
+  target_record<D>(i, w, gas, dt, qcur, tpar, bad);
 }
 
 template <int D>
@@ -1034,7 +1043,10 @@ struct LeafIn {
   T row[MAXF][P];
 };
 
-template <int D, typename T>
+// With RES set, the kernel stores the explicit increment of the implicit
+// micro system instead, (dt/tau~)(g~ - phi^n) - (dt/V) sum_f sigma A xi.n
+// phi_f (Eq. SGS_phi's right-hand side times dt/V), and skips the moments.
+template <int D, typename T, bool RES = false>
 __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
                                         const T* __restrict__ fv, T* __restrict__ vout,
                                         const double* __restrict__ fpar, const double* __restrict__ tpar,
@@ -1184,6 +1196,12 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
     }
     poly += slam[D + 1] * c2;
     const T tgt[2] = {G + poly * gv, H + poly * tp[P_RT] * gv};
+    if constexpr (RES) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        *ptr_at_(orow[p], (unsigned)k * (unsigned)sizeof(T)) = dtt * (tgt[p] - x.phi[p]) - dtv * div[p];
+      return;
+    }
     double nv[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -1223,6 +1241,7 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
       process(k + BLOCK, x1);
     }
   }
+  if constexpr (RES) return;
   block_sum<N + D>(acc, red);
   if (threadIdx.x == 0) {
     for (int m = 0; m < N; ++m) mom[(size_t)i * N + m] = acc[m];
