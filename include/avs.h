@@ -135,10 +135,14 @@ avs_status avs_init_mesh(const avs_vspace *vs, const avs_pmesh *pm, const avs_ga
                          size_t workspace_bytes, void *hip_stream, avs_ctx **out);
 
 /* Advance nsteps explicit steps (Sec. 2.3 with the implicit flux increments
- * dropped): upwind limited reconstruction at x_f - xi dt/2, interface
+ * dropped): upwind limited reconstruction at x_f - xi h, interface
  * moments and Shakhov equilibrium, interface VDF of Eq. equ28, finite-volume
  * update of W (Eq. equ18), relaxation of every node towards the
- * moment-closed Shakhov target.  residual_host (or NULL) receives
+ * moment-closed Shakhov target.  h = dt/2, capped at half of the largest
+ * step for which no cell's outflow over the velocity box exceeds its
+ * content (min_i V_i / (1/2 sum_f A_f sum_d |n_fd| max(|lo_d|, |hi_d|))),
+ * so that x_f - xi h stays within reach of the upwind cell (Sec. 2.3.3);
+ * the cap only binds for steps beyond that explicit bound.  residual_host (or NULL) receives
  * |W^{n+1} - W^n|_2 / dt per conserved component for the last step; a
  * non-NULL residual makes the call wait and report AVS_E_NUMERIC if any cell
  * went non-physical. */
@@ -156,9 +160,14 @@ avs_status avs_implicit_bytes(const avs_ctx *ctx, size_t *bytes);
  * r = |U.n| + a + 2 mu/(rho dl) from the interface state, a boundary face
  * holding the outside increment at zero) solved by macro_sweeps symmetric
  * point-relaxation Gauss-Seidel sweeps; the closed Shakhov target and tau
- * from the predicted W; the upwind micro system of Eq. SGS_phi solved by
- * micro_sweeps symmetric Gauss-Seidel sweeps; phi^{n+1} = phi^n + dphi and
- * W^{n+1} = the predicted W.  Each sweep runs the colours of a greedy
+ * from W^{n+1}; the upwind micro system of Eq. SGS_phi solved by
+ * micro_sweeps symmetric Gauss-Seidel sweeps; phi^{n+1} = phi^n + dphi.
+ * W^{n+1} takes the flux form of Eq. equ18 with the Roe-type implicit flux
+ * of the predicted increment on interior faces and the explicit flux on
+ * boundary faces (exactly conservative after any number of sweeps, no
+ * increment through walls, the predicted W on a periodic mesh once the
+ * sweeps converge), and the target and tau are built from it.  The interface half step is min(dt/2, the cap of avs_step)
+ * whatever dt is.  Each sweep runs the colours of a greedy
  * colouring of the cells in cell order (smallest colour no lower-numbered
  * face neighbour holds) up, then down; the paper recommends 60 macro and 2
  * micro sweeps.  res_dev: device scratch of avs_implicit_bytes bytes,

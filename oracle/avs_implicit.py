@@ -8,8 +8,8 @@ code with the GPU library and imports nothing from it; the interface stage
 
 One step, in the paper's order:
 
-1. interface VDFs phi_ij^n and fluxes F_ij^n at t_n + h, h = dt/2, as in
-   the explicit step (Sec. 2.3.3);
+1. interface VDFs phi_ij^n and fluxes F_ij^n at t_n + h, as in the
+   explicit step (Sec. 2.3.3; h = dt/2 capped by ``avs_oracle.half_step``);
 2. macroscopic predictor (Eqs. equ_delw, delta_Flux, Roe, SGS_w): the
    increment dW solves
        (V_i/dt + 1/2 sum_j A_ij r_ij) dW_i - 1/2 sum_j A_ij r_ij dW_j
@@ -17,14 +17,25 @@ One step, in the paper's order:
    with G the Euler flux through the outward normal of i and
    r_ij = |U_ij . n_ij| + a_ij + 2 mu_ij / (rho_ij dl_ij); it is solved by
    point-relaxation symmetric Gauss-Seidel sweeps (PRSGS); W~ = W^n + dW;
-3. target g~ = closure(Shakhov(W~, q^n), W~) and tau~ = tau(W~), as the
-   explicit step takes them from W^{n+1};
+3. W^{n+1} (below), target g~ = closure(Shakhov(W^{n+1}, q^n), W^{n+1})
+   and tau~ = tau(W^{n+1}), as in the explicit step;
 4. microscopic increment (Eqs. delta_phi, SGS_phi): per velocity node,
        (V_i/dt + V_i/tau~_i + sum_{j in N+} A_ij xi.n_ij) dphi_i
            + sum_{j in N-} A_ij xi.n_ij dphi_j = Res_i,
        Res_i = V_i (g~_i - phi_i^n)/tau~_i - sum_j A_ij xi.n_ij phi_ij^n,
    N+ the faces with xi.n_ij >= 0, solved by symmetric Gauss-Seidel sweeps;
-5. phi^{n+1} = phi^n + dphi and W^{n+1} = W~.
+5. phi^{n+1} = phi^n + dphi.
+
+W^{n+1} follows from the flux form of Eq. equ18 with the implicit flux of
+Eqs. delta_Flux and Roe: W_i^{n+1} = W_i^n - dt/V_i sum_j A_ij Fh_ij,
+    Fh_ij = F_ij^n + 1/2 [G_ij(W~_i) - G_ij(W_i) + G_ij(W~_j) - G_ij(W_j)]
+            + 1/2 r_ij (dW_i - dW_j)
+with the outside state of a boundary face described below.  With converged
+sweeps and no boundary face this is W~ exactly (the terms dropped from Eq.
+SGS_w sum to zero over a closed cell); after any number of sweeps it
+conserves mass, momentum and energy between cells exactly, and no mass
+crosses a wall, which W~ does not guarantee.  The target (step 3) is built
+from this W^{n+1}.
 
 Readings (the paper leaves these open):
 * sweep order: the cells in colour-major order of the greedy colouring of
@@ -35,13 +46,21 @@ Readings (the paper leaves these open):
 * the interface state of r_ij is the interface moment state W_ij of Eq.
   w_interface (the state the interface equilibrium is built from); a
   boundary face takes its cell's W^n and dl = 2 (x_f - x_i) . n;
-* a boundary face holds its increments at zero: dW and dphi of the outside
-  are 0, so the face contributes r to the diagonal of the predictor and,
-  on outgoing nodes, A xi.n to the diagonal of the micro system;
+* outside a boundary face, in the predictor and in Fh: a far-field face
+  holds the outside at W^n (increment 0); a wall face takes the mirror
+  state (normal momentum reversed) of the cell's own W and dW, so that the
+  mass and energy increments through the wall cancel and only the
+  pressure increment acts.  The micro system holds the outside increment
+  at zero on every boundary face, so an outgoing node adds A xi.n to its
+  diagonal;
 * a = sqrt(gamma R T) with gamma = 5/3 (three translational degrees of
   freedom, the gas of Eq. updat_W);
-* W^{n+1} is the predicted state; the micro system takes q^n about U^n
-  like the explicit step.
+* W^{n+1} is the conservative update above: the predicted state itself
+  drifts in mass when the sweeps stop short, and a Roe increment against
+  a fixed outside state would carry mass through walls during the
+  transient; either way the steady state of a closed domain would depend
+  on the path to it.
+  The micro system takes q^n about U^n like the explicit step.
 
 Pins (tests/test_implicit_pins.py): the converged micro sweeps against the
 Fourier solution of the circulant upwind system on a periodic strip; the
@@ -49,7 +68,8 @@ converged predictor against the Fourier solution of its linearisation about
 a uniform state (Euler Jacobian in closed form) and, on periodic meshes,
 its exact conservation; r_ij against the spectral radius of a numerical
 Euler Jacobian in the inviscid limit; the explicit update as the small-dt
-limit of the predictor.
+limit of the predictor; the step's W^{n+1} conserving the totals after two
+sweeps and equal to W~ after converged sweeps.
 """
 from __future__ import annotations
 
@@ -116,6 +136,20 @@ def face_radii(mesh, gas, W, face_W):
     return r
 
 
+def mirror(W, n):
+    """W reflected in a wall of unit normal n (normal momentum reversed)."""
+    D = len(n)
+    out = np.array(W, dtype=np.float64)
+    m = out[1:1 + D].copy()
+    out[1:1 + D] = m - 2.0 * float(np.dot(m, n)) * np.asarray(n)
+    return out
+
+
+def is_wall(mesh, f):
+    Rc = int(mesh.lr[f, 1])
+    return Rc < 0 and mesh.bc_kind[-1 - Rc] == O.WALL
+
+
 def macro_sgs(mesh, dt, R, W, rhs, r, n_sweeps, order):
     """PRSGS sweeps on the predictor (Eq. SGS_w).  ``rhs[i]`` = -sum_j A_ij
     F_ij^n (outward normals).  Returns dW."""
@@ -127,13 +161,16 @@ def macro_sgs(mesh, dt, R, W, rhs, r, n_sweeps, order):
         for i in list(order) + list(reversed(order)):
             acc = rhs[i].copy()
             for s in mesh.slots[i]:
-                if s.nbr < 0:
-                    continue
-                j = s.nbr
                 A = mesh.area[s.face]
                 n_out = s.sigma * mesh.nrm[s.face]
-                acc -= 0.5 * A * (euler_flux(W[j] + dW[j], n_out, R) - euler_flux(W[j], n_out, R))
-                acc += 0.5 * A * r[s.face] * dW[j]
+                if s.nbr >= 0:
+                    Wj, dWj = W[s.nbr], dW[s.nbr]
+                elif is_wall(mesh, s.face):
+                    Wj, dWj = mirror(W[i], n_out), mirror(dW[i], n_out)
+                else:
+                    continue
+                acc -= 0.5 * A * (euler_flux(Wj + dWj, n_out, R) - euler_flux(Wj, n_out, R))
+                acc += 0.5 * A * r[s.face] * dWj
             dW[i] = acc / diag[i]
     return dW
 
@@ -163,6 +200,28 @@ def micro_sgs(mesh, xi, dt, tau_c, res, n_sweeps, order):
     return dphi
 
 
+def implicit_flux(mesh, gas, W, dW, F, r):
+    """Fh_f = F_f + 1/2 [G(W~_L) - G(W_L) + G(W~_R) - G(W_R)] + 1/2 r_f (dW_L - dW_R)
+    through the face normal (L to R); the outside of a boundary face as in
+    the predictor (mirror state at a wall, increment 0 at the far field)."""
+    Fh = {}
+    for f in F:
+        L, Rc = int(mesh.lr[f, 0]), int(mesh.lr[f, 1])
+        n = mesh.nrm[f]
+        if Rc >= 0:
+            WR, dWR = W[Rc], dW[Rc]
+        elif is_wall(mesh, f):
+            WR, dWR = mirror(W[L], n), mirror(dW[L], n)
+        else:
+            WR, dWR = None, np.zeros_like(dW[L])
+        v = F[f] + 0.5 * (euler_flux(W[L] + dW[L], n, gas.R) - euler_flux(W[L], n, gas.R))
+        if WR is not None:
+            v = v + 0.5 * (euler_flux(WR + dWR, n, gas.R) - euler_flux(WR, n, gas.R))
+        v = v + 0.5 * r[f] * (dW[L] - dWR)
+        Fh[f] = v
+    return Fh
+
+
 def step_implicit(mesh, tree, gas, dt, Kv, phi, W, n_macro, n_micro, order=None):
     """One implicit step; returns (phi_new, W_new, diag) with diag.residual =
     |W^{n+1} - W^n| / dt per component, like the explicit step."""
@@ -180,7 +239,15 @@ def step_implicit(mesh, tree, gas, dt, Kv, phi, W, n_macro, n_micro, order=None)
             rhs[i] -= af * F[s.face]
             div[:, i, :] += af * O.normal_speed(xi, mesh.nrm[s.face])[None, :] * phif[s.face]
     r = face_radii(mesh, gas, W, diag.face_W)
-    Wt = W + macro_sgs(mesh, dt, gas.R, W, rhs, r, n_macro, order)
+    dW = macro_sgs(mesh, dt, gas.R, W, rhs, r, n_macro, order)
+    Fh = implicit_flux(mesh, gas, W, dW, F, r)
+    Wt = np.empty_like(W)
+    for i in range(mesh.nc):
+        Fs = np.zeros(D + 2)
+        for s in mesh.slots[i]:
+            Fs += s.sigma * mesh.area[s.face] * Fh[s.face]
+        Wt[i] = W[i] - dt / mesh.vol[i] * Fs
+    diag.predicted = W + dW
     res = np.empty_like(phi)
     tau_c = np.empty(mesh.nc)
     for i in range(mesh.nc):
@@ -188,7 +255,7 @@ def step_implicit(mesh, tree, gas, dt, Kv, phi, W, n_macro, n_micro, order=None)
         q_n = O.heat_flux(phi[:, i, :], xi, A, U_n)
         rho, U, T = O.primitive(Wt[i], gas.R)
         if not (rho > 0 and T > 0):
-            raise FloatingPointError(f'non-physical predicted state in cell {i}: rho={rho} T={T}')
+            raise FloatingPointError(f'non-physical state in cell {i}: rho={rho} T={T}')
         tau_c[i] = O.tau(rho, T, gas)
         gt = O.closure(O.shakhov(rho, U, T, q_n, xi, gas), Wt[i], xi, A, gas.R)
         res[:, i, :] = mesh.vol[i] * (gt - phi[:, i, :]) / tau_c[i] - div[:, i, :]

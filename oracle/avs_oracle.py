@@ -397,7 +397,24 @@ class StepDiag:
     residual: np.ndarray = None
 
 
-def face_vdf(f, phi, LG, mesh, xi, A, gas, dt):
+def half_step(mesh, tree, dt):
+    """h of the interface VDF (Eq. equ27): dt/2, but at most half of the
+    step at which the outflow of every cell, for every node of the velocity
+    box, equals its content: h <= 1/2 min_i V_i / (1/2 sum_f A_f sum_d
+    |n_fd| X_d), X_d = max(|lo_d|, |hi_d|).  The Taylor expansion of the
+    reconstruction holds for x_ij - xi h inside the upwind cell (Sec.
+    2.3.3); an implicit step longer than the explicit bound would move that
+    point cells away, so the flux keeps the largest half step for which
+    the point stays within reach of its cell (below the bound, h = dt/2)."""
+    X = np.maximum(np.abs(tree.lo), np.abs(tree.hi))
+    out = np.zeros(mesh.nc)
+    for i in range(mesh.nc):
+        for s in mesh.slots[i]:
+            out[i] += 0.5 * mesh.area[s.face] * float(np.dot(np.abs(mesh.nrm[s.face]), X))
+    return min(0.5 * dt, 0.5 * float(np.min(mesh.vol / out)))
+
+
+def face_vdf(f, phi, LG, mesh, xi, A, gas, h):
     """Interface VDF at t_n + h for face f (S4-S7).
 
     Interior face: upwind reconstruction (C = L if xi.n >= 0 else R), face
@@ -406,9 +423,9 @@ def face_vdf(f, phi, LG, mesh, xi, A, gas, dt):
     characteristic-line blend of Eq. equ28.  Boundary face: outgoing nodes
     keep the reconstructed VDF; incoming nodes take the diffuse-wall
     Maxwellian with zero net mass flux, or the far-field Maxwellian.
+    ``h`` is the half step of ``half_step``.
     Returns (phi_f [P,Nv], diag): ('face', (W_f, tau_f)), ('wall', rho_w) or ('far', None).
     """
-    h = 0.5 * dt
     D = mesh.dim
     L, R = int(mesh.lr[f, 0]), int(mesh.lr[f, 1])
     n = mesh.nrm[f]
@@ -461,8 +478,9 @@ def interfaces(mesh, tree, gas, dt, Kv, phi, want):
             need_lg.add(int(R))
     LG = {c: limited_gradient(c, phi, mesh, Kv) for c in sorted(need_lg)}
     phif, F, diag = {}, {}, StepDiag(face_W={}, face_tau={})
+    h = half_step(mesh, tree, dt)
     for f in need_faces:
-        pf, dg = face_vdf(f, phi, LG, mesh, xi, A, gas, dt)
+        pf, dg = face_vdf(f, phi, LG, mesh, xi, A, gas, h)
         phif[f] = pf
         F[f] = flux_moments(pf, xi, A, mesh.nrm[f])
         if dg[0] == 'wall':

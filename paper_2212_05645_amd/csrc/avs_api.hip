@@ -85,7 +85,7 @@ struct avs_ctx {
   double *cc, *crit_part, *Mk, *probe_cc, *probe_prim;
   int8_t *raw, *eff;
   int *cnt, *off, *pkind, *psrc, *pchild, *bad;
-  double *rA, *irhs, *idiag, *dW;                // implicit predictor: A r/2 per face, rhs, diagonal, increment
+  double *rA, *irhs, *idiag, *dW;                // implicit predictor: r per face, rhs, diagonal, increment
   int* col_cells;                                // cells in colour-major order
   std::vector<int> col_off;                      // colour c holds col_cells[col_off[c] .. col_off[c+1])
   uint16_t* feat = nullptr;                      // learned proposal (2-D): feature rows [cap][32]
@@ -472,8 +472,9 @@ avs_status launch_step(avs_ctx* ctx, bool last_residual) {
 }
 
 // One implicit step (IUGKS): interfaces as in the explicit step, then the
-// PRSGS predictor (n_macro symmetric sweeps, colours up then down), the
-// target from the predicted state, the micro right-hand side from pass C,
+// PRSGS predictor (n_macro symmetric sweeps, colours up then down), W^{n+1}
+// in flux form with the implicit flux of the predicted increment, the
+// target from W^{n+1}, the micro right-hand side from pass C,
 // n_micro symmetric sweeps of the upwind micro system into the second VDF
 // buffer, phi^{n+1} = phi^n + dphi, and the moments of phi^{n+1}.
 template <int D, typename T>
@@ -501,8 +502,11 @@ avs_status launch_step_implicit(avs_ctx* ctx, int n_macro, int n_micro, T* res, 
             ctx->geo, ctx->gas, ctx->col_cells + ctx->col_off[c], cnt, ctx->W, ctx->rA, ctx->irhs, ctx->idiag, ctx->dW);
         CKL();
       }
-    k_imp_apply<D><<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, ctx->dt, ctx->W, ctx->dW, ctx->Wn, ctx->q,
-                                                  ctx->tpar, ctx->bad);
+    k_imp_fhat<D><<<(unsigned)((ctx->nf + BLOCK - 1) / BLOCK), BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, ctx->W,
+                                                                                      ctx->dW, ctx->rA, ctx->F);
+    CKL();
+    k_macro<D><<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, ctx->dt, ctx->F, ctx->W, ctx->Wn, ctx->q, ctx->tpar,
+                                              ctx->bad);
     CKL();
   }
   {
@@ -995,6 +999,23 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
     eps2[i] = pow(op->venkat_K * pow(pm->cell_vol[i], 1.0 / D), 3.0);
     dtv[i] = op->dt / pm->cell_vol[i];
   }
+  // Half step of the interface VDF: dt/2, capped at half of the step at
+  // which some cell's outflow over the whole velocity box equals its
+  // content (min_i V_i / (1/2 sum_f A_f sum_d |n_fd| X_d), X_d = max(|lo_d|,
+  // |hi_d|)), so that x_f - xi h stays within reach of the upwind cell when
+  // an implicit step is longer than the explicit bound (Sec. 2.3.3).
+  double hcap = INFINITY;
+  for (int64_t i = 0; i < nc; ++i) {
+    double out = 0.0;
+    for (int s = 0; s < nslot[i]; ++s) {
+      const int f = s_face[i * maxf + s];
+      double nx = 0.0;
+      for (int d = 0; d < D; ++d) nx += fabs(pm->face_nrm[(size_t)f * D + d]) * std::max(fabs(vs->lo[d]), fabs(vs->hi[d]));
+      out += 0.5 * pm->face_area[f] * nx;
+    }
+    if (out > 0.0) hcap = std::min(hcap, pm->cell_vol[i] / out);
+  }
+  const double h_flux = std::min(0.5 * op->dt, 0.5 * hcap);
   // greedy colouring of the face-neighbour graph in cell order (each cell
   // takes the smallest colour no lower-numbered neighbour holds); the cells
   // of one colour share no face, so a Gauss-Seidel sweep updates a colour at once
@@ -1067,7 +1088,7 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   x.vg.numax = numax_of(vs);
   x.gas = GasP{gas->R, gas->Pr, gas->omega, gas->mu_ref, gas->T_ref, gas->model, gas->law, gas->C_s};
   x.dt = op->dt;
-  x.h = 0.5 * op->dt;
+  x.h = h_flux;
   x.Kv = op->venkat_K;
   x.stream = (hipStream_t)hip_stream;
   x.vol_host.assign(pm->cell_vol, pm->cell_vol + nc);

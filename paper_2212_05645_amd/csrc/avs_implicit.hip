@@ -11,20 +11,19 @@
 
 namespace avs {
 
-// r_ij = |U.n| + a + 2 mu / (rho dl) per face, stored as A r / 2.  Interior
+// r_ij = |U.n| + a + 2 mu / (rho dl) per face.  Interior
 // faces take the interface state of Eq. w_interface (its record: U, RT and
 // tau = h a / b with a = tau/(tau+h), b = h/(tau+h); mu/rho = tau R T);
 // boundary faces take the cell's W^n and the mirrored distance
 // dl = 2 (x_f - x_i) . n.  gamma = 5/3.
 template <int D>
 __global__ void k_imp_rface(Geo g, GasP gas, double h, const double* __restrict__ W, const double* __restrict__ fpar,
-                            double* __restrict__ rA) {
+                            double* __restrict__ rf) {
   constexpr int MAXF = Cfg<D>::MAXF;
   const int f = blockIdx.x * BLOCK + threadIdx.x;
   if (f >= g.nf) return;
   const int L = g.f_L[f], R = g.f_R[f], sl = g.f_sL[f];
   const size_t so = (size_t)L * MAXF + sl;
-  const double area = g.s_sigA[so];           // sigma = +1 on the L side
   const double* n = g.f_nrm + (size_t)f * D;
   double un = 0.0, RT, nu_over_dl;
   if (R >= 0) {
@@ -44,32 +43,31 @@ __global__ void k_imp_rface(Geo g, GasP gas, double h, const double* __restrict_
     for (int d = 0; d < D; ++d) dn += g.s_d[so * D + d] * n[d];
     nu_over_dl = tau_of(rho, T, gas) * RT / (2.0 * dn);
   }
-  const double r = fabs(un) + sqrt(5.0 / 3.0 * RT) + 2.0 * nu_over_dl;
-  rA[f] = 0.5 * area * r;
+  rf[f] = fabs(un) + sqrt(5.0 / 3.0 * RT) + 2.0 * nu_over_dl;
 }
 
-// Right-hand side -sum_f sigma A F_f^n, diagonal V/dt + sum_f A r / 2, and
+// Right-hand side -sum_f sigma A F_f^n, diagonal V/dt + 1/2 sum_f A r, and
 // dW = 0.
 template <int D>
-__global__ void k_imp_rhs(Geo g, const double* __restrict__ F, const double* __restrict__ rA, double* __restrict__ rhs,
+__global__ void k_imp_rhs(Geo g, const double* __restrict__ F, const double* __restrict__ rf, double* __restrict__ rhs,
                           double* __restrict__ diag, double* __restrict__ dW) {
   constexpr int MAXF = Cfg<D>::MAXF, N = D + 2;
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= g.nc) return;
   const int ns = g.nslot[i];
-  double acc[N], dg = 1.0 / g.dtv[i];
+  double acc[N], ar = 0.0;
   for (int m = 0; m < N; ++m) acc[m] = 0.0;
   for (int s = 0; s < ns; ++s) {
     const int f = g.s_face[i * MAXF + s];
     const double sa = g.s_sigA[i * MAXF + s];
     for (int m = 0; m < N; ++m) acc[m] -= sa * F[(size_t)f * N + m];
-    dg += rA[f];
+    ar += (sa * g.s_sig[i * MAXF + s]) * rf[f];
   }
   for (int m = 0; m < N; ++m) {
     rhs[(size_t)i * N + m] = acc[m];
     dW[(size_t)i * N + m] = 0.0;
   }
-  diag[i] = dg;
+  diag[i] = 1.0 / g.dtv[i] + 0.5 * ar;
 }
 
 // Euler flux of W through the unit normal n: (rho U.n, rho U U.n + p n,
@@ -92,12 +90,31 @@ __device__ __forceinline__ void euler_flux(const double (&w)[D + 2], const doubl
   G[1 + D] = (w[1 + D] + p) * un;
 }
 
+// W reflected in a wall of unit normal n (normal momentum reversed).
+template <int D>
+__device__ __forceinline__ void mirror_state(const double (&w)[D + 2], const double (&n)[D], double (&o)[D + 2]) {
+  double mn = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) mn += w[1 + d] * n[d];
+  o[0] = w[0];
+#pragma unroll
+  for (int d = 0; d < D; ++d) o[1 + d] = w[1 + d] - 2.0 * mn * n[d];
+  o[1 + D] = w[1 + D];
+}
+
+__device__ __forceinline__ bool wall_face(const Geo& g, int f) {
+  const int R = g.f_R[f];
+  return R < 0 && g.bc_kind[-1 - R] == 0;
+}
+
 // One colour of a PRSGS sweep on Eq. SGS_w: for each cell i of the colour,
 // dW_i = (rhs_i - sum_j A/2 [G(W_j + dW_j) - G(W_j)] + sum_j A r/2 dW_j) / diag_i
-// over interior neighbours j, with the outward normal of i.
+// over interior neighbours j and wall faces (whose outside is the mirror of
+// the cell's own W and current dW), with the outward normal of i; a
+// far-field face holds the outside increment at zero.
 template <int D>
 __global__ void k_imp_macro(Geo g, GasP gas, const int* __restrict__ cells, int ncells, const double* __restrict__ W,
-                            const double* __restrict__ rA, const double* __restrict__ rhs, const double* __restrict__ diag,
+                            const double* __restrict__ rf, const double* __restrict__ rhs, const double* __restrict__ diag,
                             double* __restrict__ dW) {
   constexpr int MAXF = Cfg<D>::MAXF, N = D + 2;
   const int t = blockIdx.x * BLOCK + threadIdx.x;
@@ -108,22 +125,32 @@ __global__ void k_imp_macro(Geo g, GasP gas, const int* __restrict__ cells, int 
   for (int m = 0; m < N; ++m) acc[m] = rhs[(size_t)i * N + m];
   for (int s = 0; s < ns; ++s) {
     const int j = g.s_nbr[i * MAXF + s];
-    if (j < 0) continue;
     const int f = g.s_face[i * MAXF + s];
+    if (j < 0 && !wall_face(g, f)) continue;
     const double sa = g.s_sigA[i * MAXF + s];
     const double sig = g.s_sig[i * MAXF + s];
     const double halfA = 0.5 * (sa * sig);
     double n[D];
     for (int d = 0; d < D; ++d) n[d] = sig * g.f_nrm[(size_t)f * D + d];
     double w0[N], w1[N], dj[N], G0[N], G1[N];
-    for (int m = 0; m < N; ++m) {
-      w0[m] = W[(size_t)j * N + m];
-      dj[m] = dW[(size_t)j * N + m];
-      w1[m] = w0[m] + dj[m];
+    if (j >= 0) {
+      for (int m = 0; m < N; ++m) {
+        w0[m] = W[(size_t)j * N + m];
+        dj[m] = dW[(size_t)j * N + m];
+      }
+    } else {
+      double wi[N], di[N];
+      for (int m = 0; m < N; ++m) {
+        wi[m] = W[(size_t)i * N + m];
+        di[m] = dW[(size_t)i * N + m];
+      }
+      mirror_state<D>(wi, n, w0);
+      mirror_state<D>(di, n, dj);
     }
+    for (int m = 0; m < N; ++m) w1[m] = w0[m] + dj[m];
     euler_flux<D>(w1, n, gas.R, G1);
     euler_flux<D>(w0, n, gas.R, G0);
-    const double ra = rA[f];
+    const double ra = halfA * rf[f];
     for (int m = 0; m < N; ++m) {
       acc[m] -= halfA * (G1[m] - G0[m]);
       acc[m] += ra * dj[m];
@@ -133,21 +160,55 @@ __global__ void k_imp_macro(Geo g, GasP gas, const int* __restrict__ cells, int 
   for (int m = 0; m < N; ++m) dW[(size_t)i * N + m] = acc[m] / inv;
 }
 
-// W~ = W^n + dW into Wn and the target record from W~ (as the explicit
-// macro update does from W^{n+1}).
+// Implicit flux of a face, in place over F^n (Eqs. delta_Flux, Roe):
+// F_f + 1/2 [G(W_L + dW_L) - G(W_L) + G(W_R + dW_R) - G(W_R)]
+// + 1/2 r (dW_L - dW_R) through the face normal, the outside of a boundary
+// face as in the predictor (mirror state at a wall, so that no mass crosses
+// it; increment 0 at the far field).  The explicit macro update then gives
+// W^{n+1} in flux form: exactly conservative after any number of sweeps.
 template <int D>
-__global__ void k_imp_apply(Geo g, GasP gas, double dt, const double* __restrict__ W, const double* __restrict__ dW,
-                            double* __restrict__ Wn, const double* __restrict__ qcur, double* __restrict__ tpar,
-                            int* __restrict__ bad) {
+__global__ void k_imp_fhat(Geo g, GasP gas, const double* __restrict__ W, const double* __restrict__ dW,
+                           const double* __restrict__ rf, double* __restrict__ F) {
   constexpr int N = D + 2;
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= g.nc) return;
-  double w[N];
+  const int f = blockIdx.x * BLOCK + threadIdx.x;
+  if (f >= g.nf) return;
+  const int L = g.f_L[f], R = g.f_R[f];
+  const bool wall = R < 0 && g.bc_kind[-1 - R] == 0;
+  double n[D];
+  for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
+  double v[N], w0[N], w1[N], dL[N], G0[N], G1[N];
   for (int m = 0; m < N; ++m) {
-    w[m] = W[(size_t)i * N + m] + dW[(size_t)i * N + m];
-    Wn[(size_t)i * N + m] = w[m];
+    v[m] = F[(size_t)f * N + m];
+    w0[m] = W[(size_t)L * N + m];
+    dL[m] = dW[(size_t)L * N + m];
+    w1[m] = w0[m] + dL[m];
   }
-  target_record<D>(i, w, gas, dt, qcur, tpar, bad);
+  euler_flux<D>(w1, n, gas.R, G1);
+  euler_flux<D>(w0, n, gas.R, G0);
+  for (int m = 0; m < N; ++m) v[m] = v[m] + 0.5 * (G1[m] - G0[m]);
+  const double hr = 0.5 * rf[f];
+  double dR[N];
+  if (R >= 0 || wall) {
+    if (R >= 0) {
+      for (int m = 0; m < N; ++m) {
+        w0[m] = W[(size_t)R * N + m];
+        dR[m] = dW[(size_t)R * N + m];
+      }
+    } else {
+      double wl[N];
+      for (int m = 0; m < N; ++m) wl[m] = W[(size_t)L * N + m];
+      mirror_state<D>(wl, n, w0);
+      mirror_state<D>(dL, n, dR);
+    }
+    for (int m = 0; m < N; ++m) w1[m] = w0[m] + dR[m];
+    euler_flux<D>(w1, n, gas.R, G1);
+    euler_flux<D>(w0, n, gas.R, G0);
+    for (int m = 0; m < N; ++m) v[m] = v[m] + 0.5 * (G1[m] - G0[m]);
+  } else {
+    for (int m = 0; m < N; ++m) dR[m] = 0.0;
+  }
+  for (int m = 0; m < N; ++m) v[m] = v[m] + hr * (dL[m] - dR[m]);
+  for (int m = 0; m < N; ++m) F[(size_t)f * N + m] = v[m];
 }
 
 template <int D, typename T>

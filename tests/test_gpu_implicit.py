@@ -116,3 +116,33 @@ def test_implicit_arguments(avs):
     assert avs.lib.avs_step_implicit(cs.ctx, 1, 2, 2, small.data_ptr(), 256, None) == avs.AVS_E_INVALID
     cs.step_implicit(1, 2, 2)
     cs.close()
+
+
+def test_implicit_steady_state_is_the_explicit_one(avs):
+    """At a steady state phi^{n+1} = phi^n and W^{n+1} = W^n the implicit
+    equations (Eqs. SGS_w, SGS_phi with zero increments) reduce to the
+    explicit ones with the same interface half step.  A small cavity run to
+    steady state explicitly at the stability bound (h = dt/2 = the cap) and
+    implicitly at 50 times that step reaches the same fields."""
+    c = F.cavity(n=12, Kn=0.02, base=8, max_level=1, cfl=1.0)
+    cs = avs.Case(c['mesh'], c['vspace'], c['gas'], c['dt'], 1.0, c['prim0'])
+    ci = avs.Case(c['mesh'], c['vspace'], c['gas'], 50.0 * c['dt'], 1.0, c['prim0'])
+    for k in (cs, ci):
+        k.adapt(-1.0, -2.0)
+        k.remap(2)
+    r0 = None
+    for it in range(200):
+        r = cs.step(500, residual=True)
+        r0 = r0 if r0 is not None else np.max(r)
+        if np.max(r) < 1e-9 * r0:
+            break
+    assert np.max(r) < 1e-9 * r0, (it, np.max(r) / r0)
+    for it in range(100):
+        ri = ci.step_implicit(20, 30, 4, residual=True)
+        if np.max(ri) < 1e-9 * r0:
+            break
+    assert np.max(ri) < 1e-9 * r0, (it, np.max(ri) / r0)
+    We, Wi = cs.get_W(), ci.get_W()
+    assert fieldrel(Wi, We) < 1e-6
+    cs.close()
+    ci.close()

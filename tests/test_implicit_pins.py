@@ -202,3 +202,65 @@ def test_uniform_periodic_state_keeps_W():
     assert np.abs(phi - phi[:, :1]).max() < 1e-12 * np.abs(phi).max()
     phi2, _, _ = I.step_implicit(s.mesh, s.tree, s.gas, s.dt, s.Kv, s.phi, s.W, 10, 2)
     assert np.abs(phi2 - phi2[:, :1]).max() > 1e-10 * np.abs(phi2).max()
+
+
+def test_half_step_cap_closed_form():
+    """On a Cartesian box of dx x dy cells and a velocity box reaching X_d,
+    every cell's outflow over the box is (dy X_x + dx X_y) per unit content
+    dx dy, so the interface half step is min(dt/2, dx dy / (2 (dy X_x + dx X_y)));
+    below that bound it is dt/2 exactly."""
+    nx, ny, lx, ly = 6, 4, 1.5, 1.0
+    mesh = O.Mesh(MM.box2d(nx, ny, lx=lx, ly=ly, periodic=(True, False), sides={'bottom': 0, 'top': 0},
+                           bcs=[(0, (1, 0, 0, 1))]))
+    tree = O.base_forest(2, [-3.0, -5.0], [7.0, 4.0], [4, 4], 0)
+    dx, dy = lx / nx, ly / ny
+    cap = dx * dy / (2.0 * (dy * 7.0 + dx * 5.0))
+    assert abs(O.half_step(mesh, tree, 1.0) - cap) < 1e-15
+    assert O.half_step(mesh, tree, 0.5 * cap) == 0.25 * cap
+
+
+def test_step_conserves_and_converged_step_is_the_prediction():
+    """W^{n+1} from the flux form of Eq. equ18 with the Roe-type implicit
+    flux: on a periodic mesh the totals sum_i V_i W_i are kept to round-off
+    even after two predictor sweeps (W~ = W^n + dW is not); with converged
+    sweeps W^{n+1} equals W~."""
+    from oracle import avs_implicit as II
+    desc = MM.box2d(5, 4, periodic=(True, True))
+    vs = dict(dim=2, lo=(-5.0, -5.0), hi=(5.0, 5.0), base=(8, 8), max_level=1)
+    gas = dict(R=1.0, Pr=2 / 3, omega=0.81, mu_ref=0.03, T_ref=1.0, model=1)
+    prim = F.perturbed_uniform(desc['ncells'], 2, 12, amp=0.15, uamp=0.5)
+    s = O.Solver(desc, vs, gas, 0.05, 1.0, prim)
+    tot0 = s.totals()
+    _, W2, d2 = II.step_implicit(s.mesh, s.tree, s.gas, s.dt, s.Kv, s.phi, s.W, 2, 2)
+    tot2 = np.sum(s.mesh.vol[:, None] * W2, axis=0)
+    np.testing.assert_allclose(tot2, tot0, rtol=1e-14, atol=1e-14)
+    drift = np.sum(s.mesh.vol[:, None] * d2.predicted, axis=0) - tot0
+    assert np.abs(drift).max() > 1e-8
+    _, W60, d60 = II.step_implicit(s.mesh, s.tree, s.gas, s.dt, s.Kv, s.phi, s.W, 120, 2)
+    assert np.abs(W60 - d60.predicted).max() < 1e-12 * np.abs(W60).max()
+
+
+def test_walls_pass_no_mass():
+    """In a box closed by isothermal walls the implicit step keeps the total
+    mass to round-off after two predictor sweeps: the explicit wall flux has
+    zero net mass flux (diffuse reflection) and the mirror state cancels the
+    mass and energy increments through the wall, leaving only the normal
+    momentum flux p + rho (U.n)^2 from each side."""
+    from oracle import avs_implicit as II
+    n = np.array([0.6, -0.8])
+    Wc = O.conserved(np.array([1.3, 0.4, -0.25, 0.9]), 1.0)
+    Wm = II.mirror(Wc, n)
+    assert np.allclose(II.mirror(Wm, n), Wc, rtol=0, atol=1e-15)
+    Gc, Gm = II.euler_flux(Wc, n, 1.0), II.euler_flux(Wm, n, 1.0)
+    assert abs(Gc[0] + Gm[0]) < 1e-15 and abs(Gc[3] + Gm[3]) < 1e-14
+    # the normal momentum flux doubles, p + rho (U.n)^2 from each side
+    un = 0.4 * 0.6 + (-0.25) * (-0.8)
+    np.testing.assert_allclose(Gc[1:3] + Gm[1:3], 2.0 * (1.3 * 0.9 + 1.3 * un * un) * n, rtol=1e-14)
+    desc = MM.box2d(5, 4, sides={'left': 0, 'right': 0, 'bottom': 0, 'top': 1},
+                    bcs=[(0, (1.0, 0.0, 0.0, 1.0)), (0, (1.0, 0.3, 0.0, 1.2))])
+    vs = dict(dim=2, lo=(-5.0, -5.0), hi=(5.0, 5.0), base=(8, 8), max_level=1)
+    gas = dict(R=1.0, Pr=2 / 3, omega=0.81, mu_ref=0.03, T_ref=1.0, model=1)
+    s = O.Solver(desc, vs, gas, 0.05, 1.0, F.perturbed_uniform(desc['ncells'], 2, 13, amp=0.15, uamp=0.4))
+    m0 = s.totals()[0]
+    _, W2, d2 = II.step_implicit(s.mesh, s.tree, s.gas, s.dt, s.Kv, s.phi, s.W, 2, 2)
+    assert abs(np.sum(s.mesh.vol * W2[:, 0]) - m0) < 1e-14 * m0
