@@ -146,3 +146,33 @@ def test_implicit_steady_state_is_the_explicit_one(avs):
     assert fieldrel(Wi, We) < 1e-6
     cs.close()
     ci.close()
+
+
+def test_implicit_with_adaptation_sutherland_and_bypass(avs):
+    """Implicit steps interleaved with the adaptation of Sec. 3: flags
+    bit exact, closed remap, then the equilibrium bypass, on an O-grid gas
+    with Sutherland's viscosity; FP64 to 1e-12 throughout."""
+    c = F.cylinder(nr=6, nth=16, Ma=2.0, box=8.0, base=16, max_level=2, r1=2.5, first=0.1)
+    gas = dict(c['gas'], law=1, C_s=2.5)
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], gas, 4.0 * c['dt'], c['prim0'], tree=resolved_tree(c['vspace'], 80),
+                      noise=0.01, seed=81, Kv=c['venkat_K'])
+    cs.step_implicit(2, 20, 2)
+    o.step_implicit(2, 20, 2)
+    flags, nn = cs.adapt(2e-3, 1e-5)
+    eff, plan, _ = o.adapt(2e-3, 1e-5)
+    assert np.array_equal(flags, eff) and nn == plan.tree.n
+    assert (eff == 1).any() or (eff == -1).any()
+    cs.remap(2)
+    o.remap(2)
+    cs.step_implicit(1, 20, 2)
+    o.step_implicit(1, 20, 2)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    cs.adapt(2e-3, 1e-5)
+    o.adapt(2e-3, 1e-5)
+    cs.remap(4)
+    o.remap(4)
+    cs.step_implicit(1, 20, 2)
+    o.step_implicit(1, 20, 2)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
