@@ -176,3 +176,42 @@ def test_implicit_with_adaptation_sutherland_and_bypass(avs):
     o.step_implicit(1, 20, 2)
     v, W = cs.get_state()
     assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+
+
+def test_single_cell_periodic_mesh(avs):
+    """Degenerate mesh: one cell whose two faces both join it to itself
+    (periodic in x and y).  Explicit and implicit steps against the oracle;
+    W cannot change."""
+    mesh = MM.box2d(1, 1, periodic=(True, True))
+    vs = dict(dim=2, lo=(-5, -5), hi=(5, 5), base=(8, 8), max_level=2)
+    gas = dict(R=1.0, Pr=2 / 3, omega=0.81, mu_ref=0.05, T_ref=1.0, model=1)
+    prim = F.perturbed_uniform(1, 2, 3, amp=0.1, uamp=0.3)
+    for implicit in (False, True):
+        cs, o = make_pair(avs, mesh, vs, gas, 0.01, prim, tree=random_tree(vs, 4, 2), noise=0.02, seed=5)
+        W0 = o.W.copy()
+        if implicit:
+            cs.step_implicit(2, 10, 2)
+            o.step_implicit(2, 10, 2)
+        else:
+            cs.step(2)
+            o.step(2)
+        v, W = cs.get_state()
+        assert rel(v, o.phi) < 1e-12
+        np.testing.assert_allclose(W, W0, rtol=1e-14, atol=1e-15)
+        cs.close()
+
+
+def test_zero_sweeps_reduce_to_the_explicit_macro_update(avs):
+    """With no predictor sweep the increment is zero, the implicit flux is
+    F^n and W^{n+1} is the explicit finite-volume update, bit for bit; with
+    no micro sweep phi is unchanged."""
+    c = F.cavity(n=8, base=8, max_level=2)
+    t = random_tree(c['vspace'], 90, 2)
+    a, _ = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=t, noise=0.02, seed=91)
+    b, _ = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], tree=t, noise=0.02, seed=91)
+    v0, _ = a.get_state()
+    a.step(1)
+    b.step_implicit(1, 0, 0)
+    assert np.array_equal(a.get_W(), b.get_W())
+    vb, _ = b.get_state()
+    assert np.array_equal(vb, v0)
