@@ -1,0 +1,117 @@
+"""Pins of the Rykov diatomic-model oracle (Eqs. GHR_equ, equ11-equ13,
+updat_W, equ8, equ19) against closed forms of Gaussian moments, reached to
+round-off by the mid-point rule on a fine velocity mesh.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import avs_oracle as O
+from oracle import avs_rykov as RY
+
+
+def fine(D):
+    n, half = (160, 10.0) if D == 2 else (56, 9.0)
+    t = O.base_forest(D, [-half] * D, [half] * D, [n] * D, 0)
+    return t.centres(), t.weights()
+
+
+def state(D):
+    rho, Tt, Tr = 1.3, 1.1, 0.8
+    U = np.array([0.4, -0.3, 0.2][:D])
+    qt = np.array([0.06, -0.09, 0.04][:D])
+    qr = np.array([-0.05, 0.03, 0.07][:D])
+    return rho, U, Tt, Tr, qt, qr
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_parts_moments_closed_form(D):
+    """t part: mass rho, momentum rho U, translational energy 3/2 rho R T_t,
+    int R^t = rho R T_r; r part the same at T (T_r replaced by T); the
+    Shakhov-type corrections carry no mass, momentum or energy."""
+    gas = RY.RykovGas(R=0.5)
+    xi, A = fine(D)
+    rho, U, Tt, Tr, qt, qr = state(D)
+    T = (3 * Tt + 2 * Tr) / 5
+    t, r = RY.rykov_parts(rho, U, Tt, Tr, qt, qr, xi, gas)
+    for part, Ttr, Trot in ((t, Tt, Tr), (r, T, T)):
+        m = RY.moments(part, xi, A)
+        np.testing.assert_allclose(m[0], rho, rtol=1e-12)
+        np.testing.assert_allclose(m[1:1 + D], rho * U, rtol=1e-12, atol=1e-13)
+        e_tr = 0.5 * rho * U @ U + 1.5 * rho * gas.R * Ttr
+        np.testing.assert_allclose(m[1 + D] - m[2 + D], e_tr, rtol=1e-12)
+        np.testing.assert_allclose(m[2 + D], rho * gas.R * Trot, rtol=1e-12)
+    if D == 3:
+        assert np.all(t[1] == 0) and np.all(r[1] == 0)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_parts_heat_fluxes_closed_form(D):
+    """q_t of the t part is q_t/3 and of the r part omega_0 q_t/3 (a
+    Shakhov correction with coefficient 1/15 = (1 - 2/3)/5); int c R^t =
+    (1 - delta)(T_r/T_t) q_r and int c R^r = omega_1 (1 - delta) q_r."""
+    gas = RY.RykovGas(R=0.5)
+    xi, A = fine(D)
+    rho, U, Tt, Tr, qt, qr = state(D)
+    t, r = RY.rykov_parts(rho, U, Tt, Tr, qt, qr, xi, gas)
+    qtt, qrt = RY.heat_fluxes(t, xi, A, U)
+    qtr, qrr = RY.heat_fluxes(r, xi, A, U)
+    np.testing.assert_allclose(qtt, qt / 3, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(qtr, gas.omega0 * qt / 3, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(qrt, (1 - gas.delta) * (Tr / Tt) * qr, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(qrr, gas.omega1 * (1 - gas.delta) * qr, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_collision_conserves_and_exchanges_rotational_energy(D):
+    """The Rykov equilibrium has the mass, momentum and total energy of the
+    state (the collision conserves them), and its rotational energy moves
+    1/Z of the way from rho R T_r to rho R T: (int g^R - rho E_rot)/tau is
+    the source (rho R T - rho E_rot)/(Z tau) of Eq. equ19."""
+    gas = RY.RykovGas(R=0.5, Z_rot=3.5)
+    xi, A = fine(D)
+    rho, U, Tt, Tr, qt, qr = state(D)
+    W = RY.conserved(rho, U, Tt, Tr, gas.R)
+    g = RY.rykov_equilibrium(rho, U, Tt, Tr, qt, qr, xi, gas)
+    m = RY.moments(g, xi, A)
+    np.testing.assert_allclose(m[:2 + D], W[:2 + D], rtol=1e-12, atol=1e-13)
+    tau = 0.37
+    np.testing.assert_allclose((m[2 + D] - W[2 + D]) / tau, RY.rotational_source(W, tau, gas), rtol=1e-11)
+    rho_, U_, Tt_, Tr_, T_ = RY.temperatures(W, gas.R)
+    assert abs(Tt_ - Tt) < 1e-14 and abs(Tr_ - Tr) < 1e-14 and abs(T_ - (3 * Tt + 2 * Tr) / 5) < 1e-14
+
+
+def test_relaxation_number_limits():
+    """Z = 1: the equilibrium is the r part alone (full exchange at every
+    collision); Z -> infinity: the t part (no exchange)."""
+    xi, A = fine(2)
+    rho, U, Tt, Tr, qt, qr = state(2)
+    t, r = RY.rykov_parts(rho, U, Tt, Tr, qt, qr, xi, RY.RykovGas(R=0.5))
+    g1 = RY.rykov_equilibrium(rho, U, Tt, Tr, qt, qr, xi, RY.RykovGas(R=0.5, Z_rot=1.0))
+    assert np.array_equal(g1, r)
+    ginf = RY.rykov_equilibrium(rho, U, Tt, Tr, qt, qr, xi, RY.RykovGas(R=0.5, Z_rot=1e300))
+    assert np.allclose(ginf, t, rtol=0, atol=1e-300 + 1e-15 * np.abs(t).max())
+
+
+def test_equal_temperatures_and_zero_heat_flux_give_maxwellians():
+    """At T_t = T_r and zero heat fluxes every part is the Maxwellian pair:
+    G = g(T), H = (3 - D) R T g(T), R = R T g(T)."""
+    gas = RY.RykovGas(R=0.7)
+    xi, A = fine(2)
+    rho, U, T = 0.9, np.array([0.2, 0.5]), 1.3
+    z = np.zeros(2)
+    g = RY.rykov_equilibrium(rho, U, T, T, z, z, xi, gas)
+    m = O.maxwell(rho, U, T, xi, gas.R)
+    np.testing.assert_allclose(g[0], m, rtol=1e-14, atol=1e-300)
+    np.testing.assert_allclose(g[1], gas.R * T * m, rtol=1e-14, atol=1e-300)
+    np.testing.assert_allclose(g[2], gas.R * T * m, rtol=1e-14, atol=1e-300)
+
+
+def test_interface_rotational_relaxation_limits():
+    gas = RY.RykovGas(R=0.5, Z_rot=4.0)
+    assert RY.interface_rotational_energy(2.0, 3.0, 0.0, 0.1, gas) == 2.0
+    assert abs(RY.interface_rotational_energy(2.0, 3.0, 1e12, 0.1, gas) - 3.0) < 1e-9
+    # linear in its inputs: the weights sum to one
+    a = RY.interface_rotational_energy(1.0, 0.0, 0.3, 0.1, gas)
+    b = RY.interface_rotational_energy(0.0, 1.0, 0.3, 0.1, gas)
+    assert abs(a + b - 1.0) < 1e-15 and abs(b - 0.3 / (0.4 + 0.3)) < 1e-15
