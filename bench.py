@@ -559,6 +559,44 @@ def run_implicit_cavity(args, n=64, Kn=6.6e-4, cfl=64.0, macro=60, micro=2, drop
                         f"implicit CFL {cfl:g} with {macro}/{micro} sweeps vs explicit CFL 0.8"}
 
 
+def run_rykov(args, reps=5):
+    """Rykov equilibrium of the diatomic model (G, H, R on every leaf) for
+    one seeded state per cell of the cylinder workload, on its step-0 tree,
+    FP64: rate and the write bandwidth against the HBM roofline (3 x 8 B
+    written per node; the state rows are read once per cell)."""
+    import numpy as np
+    import torch
+    w = Workload(args, "fp64")
+    n0 = w.tree(args.C1)
+    cs = w.cs
+    rng = np.random.default_rng(3)
+    nc = cs.nc
+    states = np.concatenate([rng.uniform(0.5, 3.0, (nc, 1)), rng.uniform(-2.0, 2.0, (nc, 2)),
+                             rng.uniform(0.5, 8.0, (nc, 2)), 0.1 * rng.standard_normal((nc, 4))], axis=1)
+    out = cs.rykov_equilibrium(states)          # first launch (allocates the output)
+    st = torch.as_tensor(states, device=cs.device)
+    from paper_2212_05645_amd import avs
+    g = avs.avs_rykov(3.5, 1.0 / 1.55, 0.2354, 0.3049)
+    import ctypes as C
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(cs.stream)
+    for _ in range(reps):
+        avs._check(avs.lib.avs_rykov_equilibrium(cs.ctx, C.byref(g), st.data_ptr(), nc, out.data_ptr(),
+                                                 out.numel() * out.element_size()))
+    e1.record(cs.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nodes = nc * n0
+    gbs = 3 * 8 * nodes / (ms * 1e-3) / 1e9
+    res = {"ms_per_launch": ms, "nodes": nodes, "leaves": n0, "cells": nc, "node_rate_per_s": nodes / (ms * 1e-3),
+           "write_GBps": gbs, "hbm_frac": gbs * 1e9 / HBM_PEAK,
+           "workload": f"Rykov equilibrium (G, H, R), cylinder O-grid {args.nr}x{args.nth}, step-0 tree, FP64"}
+    del out, st
+    del w
+    return res
+
+
 def run_sphere(args):
     """The 3-D form: supersonic sphere (64 x 64 x 32 cells), octree of 16^3
     roots and 2 levels, FP32 storage; C1 for a step-0 tree of about 20 000
@@ -726,6 +764,11 @@ def main():
             forms["implicit_cavity"] = run_implicit_cavity(args)
         except Exception as e:
             forms["implicit_cavity"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        try:
+            forms["rykov_equilibrium"] = run_rykov(args)
+        except Exception as e:
+            forms["rykov_equilibrium"] = {"error": repr(e)}
     cpu = None
     if not args.no_cpu:
         try:

@@ -148,6 +148,28 @@ avs_status avs_init_mesh(const avs_vspace *vs, const avs_pmesh *pm, const avs_ga
  * went non-physical. */
 avs_status avs_step(avs_ctx *ctx, int32_t nsteps, double *residual_host);
 
+/* Rykov model constants of a diatomic gas (Sec. 2.2; nitrogen: delta =
+ * 1/1.55, omega_0 = 0.2354, omega_1 = 0.3049); Z_rot, the rotational
+ * collision number, is the gas's (the paper gives no value). */
+typedef struct {
+  double Z_rot, delta, omega0, omega1;
+} avs_rykov;
+
+/* Rykov equilibrium of the diatomic model (Eqs. GHR_equ, equ11-equ13) on the
+ * context's current leaves: for each of n states, g^phi = (1 - 1/Z_rot)
+ * phi^t + (1/Z_rot) phi^r for phi = G, H (the 3 - D hidden translational
+ * degrees of freedom, zero in 3-D) and R (rotational energy, two degrees of
+ * freedom), with T = (3 T_t + 2 T_r)/5, p_t = rho R T_t, p = rho R T and the
+ * context's gas constant R.  states_dev: device array [n][3 + 3D] of
+ * (rho, U[D], T_t, T_r, q_t[D], q_r[D]) in FP64, read only.  out_dev:
+ * device array [3][n][ld] (ld = the row stride avs_leaves reports) in the
+ * context's precision, written for the first nleaves entries of each row;
+ * out_bytes >= 3 n ld element size, else AVS_E_INVALID.  Asynchronous on the
+ * context's stream.  A building block of the diatomic model: the sweep of
+ * avs_step is monatomic. */
+avs_status avs_rykov_equilibrium(avs_ctx *ctx, const avs_rykov *gas, const double *states_dev, int64_t n,
+                                 void *out_dev, size_t out_bytes);
+
 /* Bytes of the device region avs_step_implicit needs for the right-hand
  * side of the micro system: one VDF buffer (components x cells x leaf
  * capacity x element size). */

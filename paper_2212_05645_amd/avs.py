@@ -27,8 +27,12 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_batch_check", "avs_batch_tune", "avs_batch_adapt", "avs_batch_remap", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
            "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
            "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
-           "avs_auto_params", "avs_initial_avs", "avs_implicit_bytes", "avs_step_implicit", "avs_destroy",
-           "avs_last_error")
+           "avs_auto_params", "avs_initial_avs", "avs_implicit_bytes", "avs_step_implicit",
+           "avs_rykov_equilibrium", "avs_destroy", "avs_last_error")
+
+
+class avs_rykov(C.Structure):
+    _fields_ = [("Z_rot", C.c_double), ("delta", C.c_double), ("omega0", C.c_double), ("omega1", C.c_double)]
 
 
 class avs_vspace(C.Structure):
@@ -120,6 +124,7 @@ def _load():
         "avs_auto_params": (I32, [P(avs_flow), P(avs_auto), P(avs_vspace)]),
         "avs_initial_avs": (I32, [VP, P(avs_flow), D, D, P(I64)]),
         "avs_implicit_bytes": (I32, [VP, P(C.c_size_t)]),
+        "avs_rykov_equilibrium": (I32, [VP, P(avs_rykov), VP, I64, VP, C.c_size_t]),
         "avs_step_implicit": (I32, [VP, I32, I32, I32, VP, C.c_size_t, VP]),
         "avs_destroy": (None, [VP]),
         "avs_last_error": (C.c_char_p, []),
@@ -255,6 +260,25 @@ class Case:
         _check(lib.avs_step_implicit(self.ctx, int(n), int(macro), int(micro), self._imp_res.data_ptr(),
                                      self._imp_res.numel(), _ptr(res)))
         return res
+
+    def rykov_equilibrium(self, states, Z_rot=3.5, delta=1.0 / 1.55, omega0=0.2354, omega1=0.3049, out=None):
+        """Rykov equilibrium (G, H, R) on the current leaves for states
+        [n][3 + 3D] = (rho, U, T_t, T_r, q_t, q_r); returns a device tensor
+        [3, n, ld] in the context's precision."""
+        t = self._torch
+        st = t.as_tensor(np.ascontiguousarray(states, np.float64), device=self.device)
+        n = st.shape[0]
+        ld = C.c_int64()
+        nn = C.c_int64()
+        _check(lib.avs_leaves(self.ctx, C.byref(nn), C.byref(ld), None, None, None, None))
+        dt = t.float64 if self.opts.precision == AVS_FP64 else t.float32
+        if out is None:
+            out = t.empty((3, n, ld.value), dtype=dt, device=self.device)
+        g = avs_rykov(float(Z_rot), float(delta), float(omega0), float(omega1))
+        _check(lib.avs_rykov_equilibrium(self.ctx, C.byref(g), st.data_ptr(), n, out.data_ptr(),
+                                         out.numel() * out.element_size()))
+        t.cuda.synchronize(self.device)
+        return out
 
     def moments(self, fields=True, totals=True):
         f = self._torch.empty((self.nc, 2 * self.dim + 2), dtype=self._torch.float64, device=self.device) if fields else None

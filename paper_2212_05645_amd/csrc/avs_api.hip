@@ -1226,6 +1226,33 @@ avs_status avs_step_implicit(avs_ctx* ctx, int32_t nsteps, int32_t macro_sweeps,
   return check_bad(ctx);
 }
 
+avs_status avs_rykov_equilibrium(avs_ctx* ctx, const avs_rykov* gas, const double* states_dev, int64_t n, void* out_dev,
+                                 size_t out_bytes) {
+  if (avs_status st = guard(ctx)) return st;
+  if (!gas || !states_dev || !out_dev) return fail(AVS_E_INVALID, "null argument");
+  if (n < 0 || n > INT_MAX) return fail(AVS_E_INVALID, "n out of range");
+  if (!(gas->Z_rot >= 1.0 && std::isfinite(gas->Z_rot)) || !(gas->delta > 0.0 && gas->delta <= 1.0) ||
+      !std::isfinite(gas->omega0) || !std::isfinite(gas->omega1))
+    return fail(AVS_E_INVALID, "Rykov parameters: Z_rot >= 1, 0 < delta <= 1, finite omega_0 and omega_1");
+  const int ld = ctx->ld[ctx->lcur];
+  const size_t need = (size_t)3 * (size_t)n * ld * ctx->esize();
+  if (out_bytes < need) return fail(AVS_E_INVALID, "out region too small (%zu < %zu)", out_bytes, need);
+  if (n == 0) return AVS_OK;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const RykovP gp{ctx->gas.R, gas->Z_rot, gas->delta, gas->omega0, gas->omega1};
+  const size_t shm = (size_t)2 * ctx->D * ctx->vg.numax * sizeof(double);
+  if (shm > 60 * 1024) return fail(AVS_E_INVALID, "velocity grid too fine for the equilibrium tables");
+  if (ctx->D == 2) {
+    if (ctx->prec == AVS_FP64) k_rykov_eq<2, double><<<(unsigned)n, BLOCK, shm, ctx->stream>>>(L, ctx->vg, gp, (int)n, states_dev, (double*)out_dev);
+    else k_rykov_eq<2, float><<<(unsigned)n, BLOCK, shm, ctx->stream>>>(L, ctx->vg, gp, (int)n, states_dev, (float*)out_dev);
+  } else {
+    if (ctx->prec == AVS_FP64) k_rykov_eq<3, double><<<(unsigned)n, BLOCK, shm, ctx->stream>>>(L, ctx->vg, gp, (int)n, states_dev, (double*)out_dev);
+    else k_rykov_eq<3, float><<<(unsigned)n, BLOCK, shm, ctx->stream>>>(L, ctx->vg, gp, (int)n, states_dev, (float*)out_dev);
+  }
+  CKL();
+  return AVS_OK;
+}
+
 avs_status avs_moments(avs_ctx* ctx, double* fields_dev, double* totals_host) {
   if (avs_status st = guard(ctx)) return st;
   if (fields_dev) {

@@ -291,3 +291,89 @@ __global__ void k_imp_finish(int P, int nc, Leaves L, const T* __restrict__ vin,
 }
 
 }  // namespace avs
+
+namespace avs {
+
+// ------------------------------------------- Rykov diatomic equilibrium
+// g^phi = (1 - 1/Z) phi^t + (1/Z) phi^r for phi = G, H, R (Eqs. GHR_equ,
+// equ11-equ13) at every leaf, for one state per block: st = (rho, U[D],
+// T_t, T_r, q_t[D], q_r[D]).  T = (3 T_t + 2 T_r)/5, p_t = rho R T_t,
+// p = rho R T; H carries the 3 - D hidden translational degrees of freedom
+// (zero in 3-D).  Out: [3][n][ld] in T.
+struct RykovP {
+  double R, Z, delta, omega0, omega1;
+};
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_rykov_eq(Leaves L, VGrid vg, RykovP gp, int n, const double* __restrict__ states,
+                                                   T* __restrict__ out) {
+  // the two Maxwellians (at T_t and at T) from separable per-axis tables of
+  // the half-finest grid (exact products of one-dimensional factors)
+  extern __shared__ double lds_d[];
+  double* tabt = lds_d;
+  double* tabr = lds_d + D * vg.numax;
+  __shared__ double part[NPAR], parr[NPAR];
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const double* st = states + (size_t)i * (3 + 3 * D);
+  const double rho = st[0], Tt = st[1 + D], Tr = st[2 + D];
+  double U[D], qt[D], qr[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    U[d] = st[1 + d];
+    qt[d] = st[3 + D + d];
+    qr[d] = st[3 + 2 * D + d];
+  }
+  const double R = gp.R;
+  const double Teq = (3.0 * Tt + 2.0 * Tr) / 5.0;
+  const double RTt = R * Tt, RT = R * Teq;
+  const double pt = rho * RTt, p = rho * RT;
+  if (threadIdx.x == 0) {
+    part[P_COEF] = rho * pow(2.0 * M_PI * RTt, -0.5 * D);
+    parr[P_COEF] = rho * pow(2.0 * M_PI * RT, -0.5 * D);
+    for (int d = 0; d < 3; ++d) {
+      part[P_U + d] = d < D ? U[d] : 0.0;
+      parr[P_U + d] = d < D ? U[d] : 0.0;
+    }
+    part[P_I2RT] = 0.5 / RTt;
+    parr[P_I2RT] = 0.5 / RT;
+  }
+  __syncthreads();
+  build_tab<D>(tabt, part, vg);
+  build_tab<D>(tabr, parr, vg);
+  __syncthreads();
+  const double wt = 1.0 - 1.0 / gp.Z, wr = 1.0 / gp.Z;
+  const double kt = 1.0 / (15.0 * pt * RTt), kr = gp.omega0 / (15.0 * p * RT);
+  const double irt_t = 1.0 / RTt, irt = 1.0 / RT;
+  const double mt = (1.0 - gp.delta) / (pt * RTt), mr = gp.omega1 * (1.0 - gp.delta) / (p * RT);
+  const double RTr = R * Tr;
+  const size_t cs = (size_t)n * L.ld;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    double c2 = 0.0, cqt = 0.0, cqr = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double c = xi[d] - U[d];
+      c2 += c * c;
+      cqt += c * qt[d];
+      cqr += c * qr[d];
+    }
+    const double gt = maxw<D>(part, tabt, vg.numax, u);
+    const double g = maxw<D>(parr, tabr, vg.numax, u);
+    const double at = cqt * kt, ar = cqt * kr;
+    const double Gt = gt * (1.0 + at * (c2 * irt_t - D - 2));
+    const double Gr = g * (1.0 + ar * (c2 * irt - D - 2));
+    const double Ht = RTt * gt * (3 - D) * (1.0 + at * (c2 * irt_t - D));
+    const double Hr = RT * g * (3 - D) * (1.0 + ar * (c2 * irt - D));
+    const double Rt = RTr * (Gt + mt * cqr * gt);
+    const double Rr = RT * (Gr + mr * cqr * g);
+    const size_t o = (size_t)i * L.ld + k;
+    out[o] = (T)(wt * Gt + wr * Gr);
+    out[cs + o] = (T)(wt * Ht + wr * Hr);
+    out[2 * cs + o] = (T)(wt * Rt + wr * Rr);
+  }
+}
+
+}  // namespace avs

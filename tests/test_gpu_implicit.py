@@ -215,3 +215,40 @@ def test_zero_sweeps_reduce_to_the_explicit_macro_update(avs):
     assert np.array_equal(a.get_W(), b.get_W())
     vb, _ = b.get_state()
     assert np.array_equal(vb, v0)
+
+
+@pytest.mark.parametrize("D,prec", [(2, 0), (3, 0), (2, 1)])
+def test_rykov_equilibrium_matches_oracle(avs, D, prec):
+    """Rykov equilibrium (G, H, R) of the diatomic model on a random tree
+    of several hundred leaves (ragged row), for seeded states with unequal
+    translational and rotational temperatures and both heat fluxes: FP64 to
+    1e-12 of each component's scale, FP32 to 1e-6."""
+    from oracle import avs_rykov as RY
+    if D == 2:
+        mesh = MM.box2d(3, 2, periodic=(True, True))
+        vs = dict(dim=2, lo=(-6, -5), hi=(7, 6), base=(8, 8), max_level=2)
+    else:
+        mesh = MM.box3d(2, 2, 1, periodic=(True, True, True))
+        vs = dict(dim=3, lo=(-5.0,) * 3, hi=(5.0,) * 3, base=(4, 4, 4), max_level=2)
+    gas = dict(R=0.5, Pr=2 / 3, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+    prim = F.perturbed_uniform(mesh['ncells'], D, 95, amp=0.1, uamp=0.3)
+    t = random_tree(vs, 96, 2)
+    cs = avs.Case(mesh, vs, gas, 1e-3, 1.0, prim, precision=prec)
+    cs.set_leaves(t.level, t.idx)
+    rng = np.random.default_rng(97)
+    n = 37
+    states = np.concatenate([rng.uniform(0.5, 2.0, (n, 1)), rng.uniform(-1.0, 1.0, (n, D)),
+                             rng.uniform(0.6, 2.5, (n, 2)), 0.1 * rng.standard_normal((n, 2 * D))], axis=1)
+    out = cs.rykov_equilibrium(states, Z_rot=3.5).cpu().numpy()[:, :, :t.n]
+    g = RY.RykovGas(R=0.5, Z_rot=3.5)
+    xi = t.centres()
+    tol = 1e-12 if prec == 0 else 1e-6
+    for i in range(n):
+        s = states[i]
+        ref = RY.rykov_equilibrium(s[0], s[1:1 + D], s[1 + D], s[2 + D], s[3 + D:3 + 2 * D], s[3 + 2 * D:], xi, g)
+        for p in range(3):
+            scale = max(np.abs(ref[p]).max(), 1e-300)
+            assert np.abs(out[p, i] - ref[p]).max() <= tol * scale, (i, p)
+    with pytest.raises(avs.AvsError):
+        cs.rykov_equilibrium(states, Z_rot=0.5)
+    cs.close()
