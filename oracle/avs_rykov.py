@@ -147,3 +147,191 @@ def interface_rotational_energy(int_R, rhoRT, h, tau, gas):
     read with its relaxation factor as a divisor)."""
     k = h / (gas.Z_rot * tau)
     return (int_R + k * rhoRT) / (1.0 + k)
+
+
+# ---------------------------------------------------------------------------
+# One explicit step of the diatomic model (Sec. 2.3 in its explicit limit,
+# with the Rykov equilibrium of Eq. GHR_equ and the source of Eq. equ19)
+# ---------------------------------------------------------------------------
+#
+# Further readings for the step (the paper states them for the monatomic
+# case or not at all):
+# * interface heat fluxes relax over h at the rates the collision gives
+#   them: the Rykov equilibrium carries lambda_t q_t and lambda_r q_r with
+#   lambda_t = (1 - 1/Z)/3 + omega_0/(3Z) and lambda_r = (1 - delta)
+#   ((1 - 1/Z) T_r/T_t + omega_1/Z), so q_f = q_bar / (1 + (1 - lambda) h/tau)
+#   (for a monatomic Shakhov gas this is the factor tau/(tau + h Pr) of the
+#   explicit step);
+# * the interface translational temperature follows from the rotational
+#   relaxation at fixed internal energy;
+# * the rotational exchange is point-implicit with tau from the state after
+#   transport, W*: rho E_rot^{n+1} = (rho E_rot* + k rho R T) / (1 + k),
+#   k = dt/(Z tau*), and the relaxation of phi uses the same tau, so that the
+#   moments of phi^{n+1} equal W^{n+1} exactly;
+# * the target's rotational moment is (1 - 1/Z) rho E_rot^{n+1} + rho R T / Z
+#   (the rotational energy of the Rykov equilibrium of W^{n+1}), its other
+#   moments those of W^{n+1}; the closure spans (1, c, |c|^2) times the
+#   Maxwellian triple (g, (3 - D) R T g, R T g) at T and the rotational
+#   direction (0, 0, R T g);
+# * boundary Maxwellians are in equilibrium (T_t = T_r = the wall's or the
+#   far field's temperature): (g, (3 - D) R T g, R T g);
+# * the initial state is the translational part at (T_t, T_r) with zero
+#   heat fluxes, closed onto W.
+
+from . import avs_oracle as _O
+
+
+def tau_t(rho, Tt, vgas):
+    """tau = mu(T_t) / p_t (reading)."""
+    return _O.viscosity(Tt, vgas) / (rho * vgas.R * Tt)
+
+
+def triple(rho, U, T, xi, R):
+    """Equilibrium triple (g, (3 - D) R T g, R T g) at one temperature."""
+    D = xi.shape[1]
+    g = maxwell(rho, np.asarray(U, np.float64), T, xi, R)
+    return np.stack([g, (3 - D) * R * T * g, R * T * g])
+
+
+def closure_dia(f_hat, target, W, xi, A, R):
+    """f_hat + sum_m lambda_m e_m with moments equal to ``target``; the e_m
+    are (1, c, |c|^2) times the equilibrium triple at T of W, and (0, 0, R T g)."""
+    D = xi.shape[1]
+    rho, U, Tt, Tr, T = temperatures(W, R)
+    tri = triple(rho, U, T, xi, R)
+    c = xi - U[None, :]
+    basis = [np.ones(len(A))] + [c[:, d] for d in range(D)] + [np.sum(c * c, axis=1)]
+    E = [b[None, :] * tri for b in basis]
+    E.append(np.stack([np.zeros(len(A)), np.zeros(len(A)), tri[2]]))
+    J = np.stack([moments(e, xi, A) for e in E], axis=1)
+    lam = np.linalg.solve(J, np.asarray(target, np.float64) - moments(f_hat, xi, A))
+    out = np.array(f_hat, dtype=np.float64, copy=True)
+    for m, e in enumerate(E):
+        out = out + lam[m] * e
+    return out
+
+
+def heat_rates(Tt, Tr, gas):
+    lt = (1.0 - 1.0 / gas.Z_rot) / 3.0 + gas.omega0 / (3.0 * gas.Z_rot)
+    lr = (1.0 - gas.delta) * ((1.0 - 1.0 / gas.Z_rot) * Tr / Tt + gas.omega1 / gas.Z_rot)
+    return lt, lr
+
+
+def face_vdf_dia(f, phi, LG, mesh, xi, A, vgas, gas, h):
+    """Interface VDF (3 components) of face f at t_n + h."""
+    D = mesh.dim
+    R = gas.R
+    L, Rc = int(mesh.lr[f, 0]), int(mesh.lr[f, 1])
+    n = mesh.nrm[f]
+    s = _O.normal_speed(xi, n)
+    slotL = next(sl for sl in mesh.slots[L] if sl.face == f and sl.sigma > 0)
+    recL = _O.reconstruct(phi[:, L, :], LG[L], slotL.d, xi, h)
+    if Rc >= 0:
+        slotR = next(sl for sl in mesh.slots[Rc] if sl.face == f and sl.sigma < 0)
+        recR = _O.reconstruct(phi[:, Rc, :], LG[Rc], slotR.d, xi, h)
+        pbar = np.where((s >= 0)[None, :], recL, recR)
+        Wf = moments(pbar, xi, A)
+        rho, U, Tt_b, Tr_b, T = temperatures(Wf, R)
+        qt_b, qr_b = heat_fluxes(pbar, xi, A, U)
+        tf = tau_t(rho, Tt_b, vgas)
+        ERf = interface_rotational_energy(Wf[2 + D], rho * R * T, h, tf, gas)
+        Tr = ERf / (rho * R)
+        Tt = Tt_b + (2.0 / 3.0) * (Tr_b - Tr)
+        lt, lr = heat_rates(Tt, Tr, gas)
+        qt = qt_b / (1.0 + (1.0 - lt) * h / tf)
+        qr = qr_b / (1.0 + (1.0 - lr) * h / tf)
+        g = rykov_equilibrium(rho, U, Tt, Tr, qt, qr, xi, gas)
+        return tf / (tf + h) * pbar + h / (tf + h) * g
+    b = -1 - Rc
+    st = mesh.bc_state[b]
+    Ub, Tb = st[1:1 + D], st[1 + D]
+    out = (s >= 0)[None, :]
+    if mesh.bc_kind[b] == _O.WALL:
+        gw = triple(1.0, Ub, Tb, xi, R)
+        num = np.sum(np.where(s > 0, A * s * recL[0], 0.0))
+        den = np.sum(np.where(s < 0, A * (-s) * gw[0], 0.0))
+        return np.where(out, recL, (num / den) * gw)
+    return np.where(out, recL, triple(st[0], Ub, Tb, xi, R))
+
+
+def flux_moments(phi_f, xi, A, n):
+    return moments(phi_f * _O.normal_speed(xi, n)[None, :], xi, A)
+
+
+def step_dia(mesh, tree, vgas, gas, dt, Kv, phi, W):
+    """One explicit step of the diatomic model; phi [3, Nc, Nv], W [Nc, D+3]."""
+    D = mesh.dim
+    R = gas.R
+    xi, A = tree.centres(), tree.weights()
+    h = _O.half_step(mesh, tree, dt)
+    LG = {c: _O.limited_gradient(c, phi, mesh, Kv) for c in range(mesh.nc)}
+    phif, F = {}, {}
+    for f in range(mesh.nf):
+        phif[f] = face_vdf_dia(f, phi, LG, mesh, xi, A, vgas, gas, h)
+        F[f] = flux_moments(phif[f], xi, A, mesh.nrm[f])
+    phi_new = np.empty_like(phi)
+    W_new = np.empty_like(W)
+    for i in range(mesh.nc):
+        _, U_n, _, _, _ = temperatures(W[i], R)
+        qt_n, qr_n = heat_fluxes(phi[:, i, :], xi, A, U_n)
+        Fs = np.zeros(D + 3)
+        div = np.zeros(phi.shape[0::2])
+        for s in mesh.slots[i]:
+            af = s.sigma * mesh.area[s.face]
+            Fs += af * F[s.face]
+            div += af * _O.normal_speed(xi, mesh.nrm[s.face])[None, :] * phif[s.face]
+        Ws = W[i] - dt / mesh.vol[i] * Fs
+        rho, U, Tt_s, Tr_s, T = temperatures(Ws, R)
+        if not (rho > 0 and Tt_s > 0 and Tr_s > 0):
+            raise FloatingPointError(f'non-physical state in cell {i}')
+        tt = tau_t(rho, Tt_s, vgas)
+        k = dt / (gas.Z_rot * tt)
+        Wn = Ws.copy()
+        Wn[2 + D] = (Ws[2 + D] + k * rho * R * T) / (1.0 + k)
+        _, _, Tt, Tr, _ = temperatures(Wn, R)
+        target = Wn.copy()
+        target[2 + D] = (1.0 - 1.0 / gas.Z_rot) * Wn[2 + D] + rho * R * T / gas.Z_rot
+        g = rykov_equilibrium(rho, U, Tt, Tr, qt_n, qr_n, xi, gas)
+        gt = closure_dia(g, target, Wn, xi, A, R)
+        phi_new[:, i, :] = (phi[:, i, :] + dt / tt * gt - dt / mesh.vol[i] * div) / (1.0 + dt / tt)
+        W_new[i] = Wn
+    return phi_new, W_new
+
+
+class DiatomicSolver:
+    """Explicit diatomic steps on a fixed velocity tree, in FP64.
+    ``prim0`` rows are (rho, U, T_t, T_r); the physical gas ``vgas`` gives R
+    and the viscosity law; ``gas`` the Rykov constants."""
+
+    def __init__(self, desc, tree, vgas, gas, dt, venkat_K, prim0):
+        self.mesh = _O.Mesh(desc)
+        self.tree = tree
+        self.vgas = _O.gas_from(vgas)
+        self.gas = gas
+        self.dt = float(dt)
+        self.Kv = float(venkat_K)
+        D = self.mesh.dim
+        P0 = np.asarray(prim0, np.float64)
+        self.W = np.stack([conserved(p[0], p[1:1 + D], p[1 + D], p[2 + D], gas.R) for p in P0])
+        self.phi = self.initial_vdf(self.W)
+
+    def initial_vdf(self, W):
+        xi, A = self.tree.centres(), self.tree.weights()
+        out = np.empty((3, self.mesh.nc, self.tree.n))
+        z = np.zeros(self.mesh.dim)
+        for i in range(self.mesh.nc):
+            rho, U, Tt, Tr, _ = temperatures(W[i], self.gas.R)
+            t, _ = rykov_parts(rho, U, Tt, Tr, z, z, xi, self.gas)
+            out[:, i] = closure_dia(t, W[i], W[i], xi, A, self.gas.R)
+        return out
+
+    def step(self, n=1):
+        for _ in range(n):
+            self.phi, self.W = step_dia(self.mesh, self.tree, self.vgas, self.gas, self.dt, self.Kv, self.phi, self.W)
+
+    def vdf_moments(self):
+        xi, A = self.tree.centres(), self.tree.weights()
+        return np.stack([moments(self.phi[:, i], xi, A) for i in range(self.mesh.nc)])
+
+    def totals(self):
+        return np.sum(self.mesh.vol[:, None] * self.W, axis=0)

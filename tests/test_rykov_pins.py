@@ -115,3 +115,51 @@ def test_interface_rotational_relaxation_limits():
     a = RY.interface_rotational_energy(1.0, 0.0, 0.3, 0.1, gas)
     b = RY.interface_rotational_energy(0.0, 1.0, 0.3, 0.1, gas)
     assert abs(a + b - 1.0) < 1e-15 and abs(b - 0.3 / (0.4 + 0.3)) < 1e-15
+
+
+def periodic_case(nx=5, ny=4, seed=1, omega=0.74, dt=2e-3, Tr_amp=0.1, uamp=0.3):
+    from workloads import meshes as MM
+    mesh = MM.box2d(nx, ny, periodic=(True, True))
+    tree = O.base_forest(2, [-6.0, -6.0], [6.0, 6.0], [16, 16], 0)
+    vgas = dict(R=0.5, Pr=2 / 3, omega=omega, mu_ref=0.05, T_ref=1.0, model=1)
+    gas = RY.RykovGas(R=0.5, Z_rot=3.5)
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    prim = np.concatenate([1 + 0.1 * rng.uniform(-1, 1, (n, 1)), uamp * rng.uniform(-1, 1, (n, 2)),
+                           1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.8 + Tr_amp * rng.uniform(-1, 1, (n, 1))], axis=1)
+    return RY.DiatomicSolver(mesh, tree, vgas, gas, dt, 1.0, prim)
+
+
+def test_diatomic_step_conserves_and_keeps_moments():
+    """Periodic box: mass, momentum and total energy are kept to round-off
+    (the rotational energy is exchanged with the translational one), and the
+    moments of phi equal W after every step (the closed target and the
+    point-implicit exchange use the same tau)."""
+    s = periodic_case()
+    tot0 = s.totals()
+    np.testing.assert_allclose(s.vdf_moments(), s.W, rtol=0, atol=1e-14)
+    for _ in range(3):
+        s.step(1)
+        np.testing.assert_allclose(s.vdf_moments(), s.W, rtol=0, atol=1e-13)
+    tot = s.totals()
+    np.testing.assert_allclose(tot[:4], tot0[:4], rtol=1e-14, atol=1e-14)
+    assert abs(tot[4] - tot0[4]) > 1e-5             # energy does move into rotation
+
+
+def test_homogeneous_rotational_relaxation_closed_form():
+    """A uniform gas at rest with T_r < T_t: with omega = 1 the relaxation
+    time mu(T_t)/p_t is constant, so the rotational energy obeys implicit
+    Euler on dE/dt = (rho R T - E)/(Z tau) exactly:
+    E_n = rho R T + (E_0 - rho R T) (1 + dt/(Z tau))^-n, T fixed by the
+    internal energy."""
+    s = periodic_case(nx=2, ny=2, omega=1.0, dt=0.01, Tr_amp=0.0, uamp=0.0)
+    s.W[:] = s.W[0]
+    s.phi[:] = s.phi[:, :1]
+    rho, U, Tt, Tr, T = RY.temperatures(s.W[0], 0.5)
+    tau = 0.05 / (rho * 0.5 * 1.0)                   # mu_ref (T/T_ref)^1 / (rho R T)
+    E0, Eeq = s.W[0, 4], rho * 0.5 * T
+    k = 0.01 / (3.5 * tau)
+    for nstep in range(1, 6):
+        s.step(1)
+        np.testing.assert_allclose(s.W[:, 4], Eeq + (E0 - Eeq) * (1 + k) ** -nstep, rtol=1e-13)
+        assert abs(RY.temperatures(s.W[0], 0.5)[4] - T) < 1e-14
