@@ -170,6 +170,36 @@ typedef struct {
 avs_status avs_rykov_equilibrium(avs_ctx *ctx, const avs_rykov *gas, const double *states_dev, int64_t n,
                                  void *out_dev, size_t out_bytes);
 
+/* Explicit steps of the Rykov diatomic model on a context's mesh and current
+ * leaves: two-dimensional, FP64 contexts only.  Three reduced distributions
+ * G, H, R (Eq. equ6) and W = (rho, rho U, rho E, rho E_rot) (Eq. updat_W).
+ * One step: limited upwind reconstruction at x_f - xi h (h as in avs_step);
+ * interface moments, the rotational energy relaxed over h towards rho R T
+ * (the relation after Eq. w_interface, read with its factor as a divisor)
+ * and heat fluxes relaxed at the rates the Rykov equilibrium gives them;
+ * the interface VDF of Eq. equ28 with the Rykov equilibrium (Eqs. GHR_equ,
+ * equ11-equ13); W* = W - dt/V sum A F and the rotational exchange of Eq.
+ * equ19, point-implicit with tau = mu(T_t)/p_t of W*; relaxation of G, H, R
+ * towards the Rykov equilibrium of W^{n+1} closed onto (rho, rho U, rho E,
+ * (1 - 1/Z) rho E_rot + rho R T / Z).  Walls and far field take equilibrium
+ * triples (g, R T g, R T g) of their state; the wall's density gives zero net
+ * mass flux.  The state lives in a caller region of avs_dia_bytes bytes
+ * (device, 256-byte aligned, owned by the caller until avs_dia_destroy).
+ * prim0_host: [ncells][5] = (rho, U_x, U_y, T_t, T_r); the initial VDF is
+ * the translational part of the Rykov equilibrium at (T_t, T_r) closed onto
+ * W.  The context's leaves must not change while the state is used
+ * (AVS_E_STATE otherwise); the monatomic state of the context is not
+ * touched.  avs_dia_step waits for the device and reports AVS_E_NUMERIC for
+ * a non-physical state.  avs_dia_get_state copies [3][ncells][nleaves] and
+ * [ncells][5] (either may be NULL). */
+typedef struct avs_dia avs_dia;
+avs_status avs_dia_bytes(const avs_ctx *ctx, size_t *bytes);
+avs_status avs_dia_create(avs_ctx *ctx, const avs_rykov *gas, const double *prim0_host, void *mem_dev,
+                          size_t mem_bytes, avs_dia **out);
+avs_status avs_dia_step(avs_dia *dia, int32_t nsteps);
+avs_status avs_dia_get_state(avs_dia *dia, double *vdf_host, double *W_host);
+void avs_dia_destroy(avs_dia *dia);
+
 /* Bytes of the device region avs_step_implicit needs for the right-hand
  * side of the micro system: one VDF buffer (components x cells x leaf
  * capacity x element size). */

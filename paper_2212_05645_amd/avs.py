@@ -28,7 +28,8 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
            "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
            "avs_auto_params", "avs_initial_avs", "avs_implicit_bytes", "avs_step_implicit",
-           "avs_rykov_equilibrium", "avs_destroy", "avs_last_error")
+           "avs_rykov_equilibrium", "avs_dia_bytes", "avs_dia_create", "avs_dia_step", "avs_dia_get_state",
+           "avs_dia_destroy", "avs_destroy", "avs_last_error")
 
 
 class avs_rykov(C.Structure):
@@ -125,6 +126,11 @@ def _load():
         "avs_initial_avs": (I32, [VP, P(avs_flow), D, D, P(I64)]),
         "avs_implicit_bytes": (I32, [VP, P(C.c_size_t)]),
         "avs_rykov_equilibrium": (I32, [VP, P(avs_rykov), VP, I64, VP, C.c_size_t]),
+        "avs_dia_bytes": (I32, [VP, P(C.c_size_t)]),
+        "avs_dia_create": (I32, [VP, P(avs_rykov), VP, VP, C.c_size_t, P(VP)]),
+        "avs_dia_step": (I32, [VP, I32]),
+        "avs_dia_get_state": (I32, [VP, VP, VP]),
+        "avs_dia_destroy": (None, [VP]),
         "avs_step_implicit": (I32, [VP, I32, I32, I32, VP, C.c_size_t, VP]),
         "avs_destroy": (None, [VP]),
         "avs_last_error": (C.c_char_p, []),
@@ -485,6 +491,45 @@ class Mlp:
     def close(self):
         if getattr(self, "h", None):
             lib.avs_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+
+class Diatomic:
+    """Explicit steps of the Rykov diatomic model on a Case's mesh and
+    current leaves (2-D, FP64).  prim0 rows are (rho, U_x, U_y, T_t, T_r)."""
+
+    def __init__(self, case, prim0, Z_rot=3.5, delta=1.0 / 1.55, omega0=0.2354, omega1=0.3049):
+        t = case._torch
+        self.case = case
+        nb = C.c_size_t()
+        _check(lib.avs_dia_bytes(case.ctx, C.byref(nb)))
+        self.mem = t.empty(nb.value, dtype=t.uint8, device=case.device)
+        p0 = np.ascontiguousarray(prim0, dtype=np.float64)
+        g = avs_rykov(float(Z_rot), float(delta), float(omega0), float(omega1))
+        h = C.c_void_p()
+        _check(lib.avs_dia_create(case.ctx, C.byref(g), p0.ctypes.data, self.mem.data_ptr(), nb.value, C.byref(h)))
+        self.h = h
+
+    def step(self, n=1):
+        _check(lib.avs_dia_step(self.h, int(n)))
+
+    def get_state(self):
+        n = self.case.nleaves()
+        vdf = np.zeros((3, self.case.nc, n))
+        W = np.zeros((self.case.nc, 5))
+        _check(lib.avs_dia_get_state(self.h, vdf.ctypes.data, W.ctypes.data))
+        return vdf, W
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.avs_dia_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -13,6 +13,7 @@
 #include "../../include/avs.h"
 #include "avs_kernels.hip"
 #include "avs_implicit.hip"
+#include "avs_dia.hip"
 #include "avs_mlp.hip"
 
 using namespace avs;
@@ -86,6 +87,7 @@ struct avs_ctx {
   int8_t *raw, *eff;
   int *cnt, *off, *pkind, *psrc, *pchild, *bad;
   double *rA, *irhs, *idiag, *dW;                // implicit predictor: r per face, rhs, diagonal, increment
+  int64_t leaf_gen = 0;                          // bumped whenever the leaf set changes
   int* col_cells;                                // cells in colour-major order
   std::vector<int> col_off;                      // colour c holds col_cells[col_off[c] .. col_off[c+1])
   uint16_t* feat = nullptr;                      // learned proposal (2-D): feature rows [cap][32]
@@ -648,6 +650,7 @@ avs_status check_bad(avs_ctx* ctx) {
 }
 
 avs_status upload_leaves(avs_ctx* ctx, int t, int n, const int* level, const int* idx_nd /*[n][D]*/) {
+  ++ctx->leaf_gen;
   std::vector<int> ix((size_t)ctx->D * ctx->cap, 0);
   for (int k = 0; k < n; ++k)
     for (int d = 0; d < ctx->D; ++d) ix[(size_t)d * ctx->cap + k] = idx_nd[(size_t)k * ctx->D + d];
@@ -1253,6 +1256,149 @@ avs_status avs_rykov_equilibrium(avs_ctx* ctx, const avs_rykov* gas, const doubl
   return AVS_OK;
 }
 
+// ------------------------------------------------ diatomic (Rykov) path
+struct avs_dia {
+  avs_ctx* ctx = nullptr;
+  DiaGas gp{};
+  double *v[2] = {nullptr, nullptr}, *fv = nullptr, *W[2] = {nullptr, nullptr};
+  double *q = nullptr, *F = nullptr, *tp = nullptr, *lam = nullptr;
+  int* bad = nullptr;
+  int cur = 0;
+  int64_t gen = 0;
+};
+
+namespace {
+size_t dia_layout(const avs_ctx* c, avs_dia* d, char* base) {
+  Carver cv{base};
+  const size_t nc = c->nc, nf = c->nf, cap = c->cap;
+  for (int t = 0; t < 2; ++t) {
+    double* p = cv.take<double>(3 * nc * cap);
+    if (d) d->v[t] = p;
+  }
+  double* fv = cv.take<double>(3 * (nf + 1) * cap);
+  double* W0 = cv.take<double>(nc * DG_N);
+  double* W1 = cv.take<double>(nc * DG_N);
+  double* q = cv.take<double>(nc * 4);
+  double* F = cv.take<double>((nf + 1) * DG_N);
+  double* tp = cv.take<double>(nc * DG_NT);
+  double* lam = cv.take<double>(nc * DG_N);
+  int* bad = cv.take<int>(4);
+  if (d) {
+    d->fv = fv; d->W[0] = W0; d->W[1] = W1; d->q = q; d->F = F; d->tp = tp; d->lam = lam; d->bad = bad;
+  }
+  return cv.off;
+}
+
+avs_status dia_check_bad(avs_dia* d) {
+  avs_ctx* ctx = d->ctx;
+  int bad = INT_MAX;
+  CK(hipMemcpyAsync(&bad, d->bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  if (bad != INT_MAX) return fail(AVS_E_NUMERIC, "diatomic path: non-physical state or singular closure at %d", bad);
+  return AVS_OK;
+}
+}  // namespace
+
+avs_status avs_dia_bytes(const avs_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return fail(AVS_E_INVALID, "null argument");
+  *bytes = dia_layout(ctx, nullptr, nullptr);
+  return AVS_OK;
+}
+
+avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim0_host, void* mem_dev, size_t mem_bytes,
+                          avs_dia** out) {
+  if (!out) return fail(AVS_E_INVALID, "out is null");
+  *out = nullptr;
+  if (avs_status st = guard(ctx)) return st;
+  if (ctx->D != 2 || ctx->prec != AVS_FP64) return fail(AVS_E_INVALID, "the diatomic path is two-dimensional FP64");
+  if (!gas || !prim0_host || !mem_dev) return fail(AVS_E_INVALID, "null argument");
+  if (((uintptr_t)mem_dev & 255)) return fail(AVS_E_INVALID, "mem_dev must be 256-byte aligned");
+  if (!(gas->Z_rot >= 1.0 && std::isfinite(gas->Z_rot)) || !(gas->delta > 0.0 && gas->delta <= 1.0) ||
+      !std::isfinite(gas->omega0) || !std::isfinite(gas->omega1))
+    return fail(AVS_E_INVALID, "Rykov parameters: Z_rot >= 1, 0 < delta <= 1, finite omega_0 and omega_1");
+  const size_t need = dia_layout(ctx, nullptr, nullptr);
+  if (mem_bytes < need) return fail(AVS_E_INVALID, "mem region too small (%zu < %zu)", mem_bytes, need);
+  const int nc = ctx->nc;
+  const double R = ctx->gas.R;
+  std::vector<double> W0((size_t)nc * DG_N);
+  for (int i = 0; i < nc; ++i) {
+    const double* p = prim0_host + (size_t)i * 5;
+    const double rho = p[0], u0 = p[1], u1 = p[2], Tt = p[3], Tr = p[4];
+    if (!(rho > 0 && Tt > 0 && Tr > 0) || !std::isfinite(u0) || !std::isfinite(u1))
+      return fail(AVS_E_INVALID, "cell %d: non-physical initial state", i);
+    double* w = W0.data() + (size_t)i * DG_N;
+    w[0] = rho;
+    w[1] = rho * u0;
+    w[2] = rho * u1;
+    w[4] = rho * R * Tr;
+    w[3] = 0.5 * rho * (u0 * u0 + u1 * u1) + 1.5 * rho * R * Tt + w[4];
+  }
+  avs_dia* d = new avs_dia();
+  d->ctx = ctx;
+  d->gp = DiaGas{R, gas->Z_rot, gas->delta, gas->omega0, gas->omega1};
+  dia_layout(ctx, d, (char*)mem_dev);
+  d->gen = ctx->leaf_gen;
+  const int badinit[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+  const Leaves L = ctx->leaves(ctx->lcur);
+  auto fin = [&](avs_status st) { if (st) delete d; else *out = d; return st; };
+  if (hipMemcpyAsync(d->W[0], W0.data(), sizeof(double) * W0.size(), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+      hipMemcpyAsync(d->bad, badinit, sizeof badinit, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+    return fin(fail(AVS_E_HIP, "upload of the diatomic state failed"));
+  const unsigned gc = (unsigned)((nc + BLOCK - 1) / BLOCK);
+  k_dg_initrec<<<gc, BLOCK, 0, ctx->stream>>>(nc, d->gp, d->W[0], d->tp, d->bad);
+  k_dg_target<<<nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->gp, d->tp, d->W[0], d->lam, 1, d->bad);
+  k_dg_update<<<nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->gp, nullptr, nullptr, d->v[0], d->tp, d->lam, d->q, 1);
+  if (hipGetLastError() != hipSuccess) return fin(fail(AVS_E_HIP, "diatomic initialisation launch failed"));
+  return fin(dia_check_bad(d));
+}
+
+avs_status avs_dia_step(avs_dia* d, int32_t nsteps) {
+  if (!d) return fail(AVS_E_INVALID, "null diatomic state");
+  avs_ctx* ctx = d->ctx;
+  if (avs_status st = guard(ctx)) return st;
+  if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
+  if (nsteps < 0) return fail(AVS_E_INVALID, "nsteps < 0");
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK);
+  for (int s = 0; s < nsteps; ++s) {
+    const int c = d->cur;
+    k_dg_recon<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->h, d->v[c], d->fv, d->gp);
+    CKL();
+    k_dg_face<<<ctx->nf, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->gas, d->gp, ctx->h, d->fv, d->F, d->bad);
+    CKL();
+    k_dg_macro<<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, d->gp, ctx->dt, d->F, d->W[c], d->W[c ^ 1], d->q,
+                                              d->tp, d->bad);
+    CKL();
+    k_dg_target<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->gp, d->tp, d->W[c ^ 1], d->lam, 0, d->bad);
+    CKL();
+    k_dg_update<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->gp, d->v[c], d->fv, d->v[c ^ 1], d->tp, d->lam,
+                                                    d->q, 0);
+    CKL();
+    d->cur ^= 1;
+  }
+  return dia_check_bad(d);
+}
+
+avs_status avs_dia_get_state(avs_dia* d, double* vdf_host, double* W_host) {
+  if (!d) return fail(AVS_E_INVALID, "null diatomic state");
+  avs_ctx* ctx = d->ctx;
+  if (avs_status st = guard(ctx)) return st;
+  if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
+  const int n = ctx->nleaf[ctx->lcur], ld = ctx->ld[ctx->lcur];
+  if (W_host)
+    CK(hipMemcpyAsync(W_host, d->W[d->cur], sizeof(double) * ctx->nc * DG_N, hipMemcpyDeviceToHost, ctx->stream));
+  if (vdf_host) {
+    for (int p = 0; p < 3; ++p)
+      CK(hipMemcpy2DAsync(vdf_host + (size_t)p * ctx->nc * n, n * sizeof(double),
+                          d->v[d->cur] + (size_t)p * ctx->nc * ld, ld * sizeof(double), n * sizeof(double),
+                          (size_t)ctx->nc, hipMemcpyDeviceToHost, ctx->stream));
+  }
+  CK(hipStreamSynchronize(ctx->stream));
+  return AVS_OK;
+}
+
+void avs_dia_destroy(avs_dia* d) { delete d; }
+
 avs_status avs_moments(avs_ctx* ctx, double* fields_dev, double* totals_host) {
   if (avs_status st = guard(ctx)) return st;
   if (fields_dev) {
@@ -1338,6 +1484,7 @@ avs_status avs_remap(avs_ctx* ctx, int32_t correction) {
   if (avs_status st = DISPATCH(ctx, launch_remap, ctx, correction)) return st;
   ctx->lcur ^= 1;
   ctx->cur ^= 1;
+  ++ctx->leaf_gen;
   ctx->plan_valid = false;
   if (avs_status st = DISPATCH_D(ctx, launch_bc_tables, ctx)) return st;
   if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
@@ -1658,6 +1805,7 @@ avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
     if (avs_status st = DISPATCH(c, launch_remap, c, correction)) return st;
     c->lcur ^= 1;
     c->cur ^= 1;
+    ++c->leaf_gen;
     c->plan_valid = false;
     if (avs_status st = DISPATCH_D(c, launch_bc_tables, c)) return st;
     if (avs_status st = DISPATCH(c, launch_moments, c)) return st;

@@ -252,3 +252,61 @@ def test_rykov_equilibrium_matches_oracle(avs, D, prec):
     with pytest.raises(avs.AvsError):
         cs.rykov_equilibrium(states, Z_rot=0.5)
     cs.close()
+
+
+def dia_pair(avs, mesh, vs, vgas, dt, prim5, tree, Kv=1.0, Z=3.5):
+    from oracle import avs_rykov as RY
+    prim4 = np.concatenate([prim5[:, :1], prim5[:, 1:3], prim5[:, 3:4]], axis=1)
+    cs = avs.Case(mesh, vs, vgas, dt, Kv, prim4)
+    cs.set_leaves(tree.level, tree.idx)
+    dia = avs.Diatomic(cs, prim5, Z_rot=Z)
+    o = RY.DiatomicSolver(mesh, tree, vgas, RY.RykovGas(R=vgas['R'], Z_rot=Z), dt, Kv, prim5)
+    return cs, dia, o
+
+
+def test_diatomic_periodic_against_oracle(avs):
+    """Rykov diatomic steps (2-D FP64) on a periodic box with a random tree
+    and unequal translational and rotational temperatures: the closed
+    initial state and three steps equal the oracle's to 1e-12; mass,
+    momentum and total energy are kept."""
+    mesh = MM.box2d(5, 4, periodic=(True, True))
+    vs = dict(dim=2, lo=(-6.0, -6.0), hi=(6.0, 6.0), base=(8, 8), max_level=2)
+    vgas = dict(R=0.5, Pr=0.72, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+    rng = np.random.default_rng(101)
+    n = mesh['ncells']
+    prim = np.concatenate([1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.3 * rng.uniform(-1, 1, (n, 2)),
+                           1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.8 + 0.1 * rng.uniform(-1, 1, (n, 1))], axis=1)
+    cs, dia, o = dia_pair(avs, mesh, vs, vgas, 2e-3, prim, random_tree(vs, 102, 2))
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-13
+    tot0 = np.sum(o.mesh.vol[:, None] * W, axis=0)
+    for _ in range(3):
+        dia.step(1)
+        o.step(1)
+        v, W = dia.get_state()
+        assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    tot = np.sum(o.mesh.vol[:, None] * W, axis=0)
+    np.testing.assert_allclose(tot[:4], tot0[:4], rtol=1e-13, atol=1e-14)
+    dia.close()
+    cs.close()
+
+
+def test_diatomic_ogrid_wall_and_farfield(avs):
+    """Nitrogen-like gas past a cylinder (O-grid with an isothermal wall and
+    a far field, Ma 2): two steps against the oracle to 1e-12; the context's
+    leaves may not change under the diatomic state."""
+    c = F.cylinder(nr=5, nth=14, Ma=2.0, box=8.0, base=8, max_level=2, r1=2.5, first=0.1)
+    vgas = dict(c['gas'], Pr=0.72, omega=0.74)
+    p = c['prim0']
+    prim = np.concatenate([p[:, :3], p[:, 3:4], 0.9 * p[:, 3:4]], axis=1)
+    cs, dia, o = dia_pair(avs, c['mesh'], c['vspace'], vgas, c['dt'], prim, resolved_tree(c['vspace'], 103), Kv=0.0)
+    dia.step(2)
+    o.step(2)
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    cs.adapt(1e-3, 1e-5)
+    cs.remap(2)
+    with pytest.raises(avs.AvsError):
+        dia.step(1)
+    dia.close()
+    cs.close()
