@@ -597,6 +597,35 @@ def run_rykov(args, reps=5):
     return res
 
 
+def run_diatomic(args, steps=10):
+    """Rykov diatomic steps (2-D FP64, three reduced distributions) on the
+    cylinder workload's mesh and step-0 tree: nitrogen-like gas with
+    T_r = 0.9 T_t initially; cell-node updates per second and the time of
+    each stage."""
+    import numpy as np
+    import torch
+    from paper_2212_05645_amd import avs
+    w = Workload(args, "fp64")
+    n0 = w.tree(args.C1)
+    cs = w.cs
+    p = w.cfg['prim0']
+    prim = np.concatenate([p[:, :3], p[:, 3:4], 0.9 * p[:, 3:4]], axis=1)
+    dia = avs.Diatomic(cs, prim)
+    dia.step(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(cs.stream)
+    dia.step(steps)
+    e1.record(cs.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = {"updates_per_s": cs.nc * n0 * 1e3 / ms, "ms_per_step": ms, "cells": cs.nc, "leaves": n0,
+           "workload": f"Rykov diatomic explicit step, cylinder O-grid {args.nr}x{args.nth}, step-0 tree, FP64"}
+    dia.close()
+    del w
+    return out
+
+
 def run_sphere(args):
     """The 3-D form: supersonic sphere (64 x 64 x 32 cells), octree of 16^3
     roots and 2 levels, FP32 storage; C1 for a step-0 tree of about 20 000
@@ -769,6 +798,11 @@ def main():
             forms["rykov_equilibrium"] = run_rykov(args)
         except Exception as e:
             forms["rykov_equilibrium"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        try:
+            forms["diatomic_step"] = run_diatomic(args)
+        except Exception as e:
+            forms["diatomic_step"] = {"error": repr(e)}
     cpu = None
     if not args.no_cpu:
         try:

@@ -184,7 +184,8 @@ avs_status avs_rykov_equilibrium(avs_ctx *ctx, const avs_rykov *gas, const doubl
  * (1 - 1/Z) rho E_rot + rho R T / Z).  Walls and far field take equilibrium
  * triples (g, R T g, R T g) of their state; the wall's density gives zero net
  * mass flux.  The state lives in a caller region of avs_dia_bytes bytes
- * (device, 256-byte aligned, owned by the caller until avs_dia_destroy).
+ * (device, 256-byte aligned, owned by the caller until avs_dia_destroy),
+ * sized for the context's current leaves.
  * prim0_host: [ncells][5] = (rho, U_x, U_y, T_t, T_r); the initial VDF is
  * the translational part of the Rykov equilibrium at (T_t, T_r) closed onto
  * W.  The context's leaves must not change while the state is used

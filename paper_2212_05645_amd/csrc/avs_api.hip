@@ -1270,7 +1270,8 @@ struct avs_dia {
 namespace {
 size_t dia_layout(const avs_ctx* c, avs_dia* d, char* base) {
   Carver cv{base};
-  const size_t nc = c->nc, nf = c->nf, cap = c->cap;
+  // rows of the current leaf set (the diatomic state refuses a changed one)
+  const size_t nc = c->nc, nf = c->nf, cap = (size_t)c->ld[c->lcur];
   for (int t = 0; t < 2; ++t) {
     double* p = cv.take<double>(3 * nc * cap);
     if (d) d->v[t] = p;
@@ -1345,9 +1346,12 @@ avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim
       hipMemcpyAsync(d->bad, badinit, sizeof badinit, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
     return fin(fail(AVS_E_HIP, "upload of the diatomic state failed"));
   const unsigned gc = (unsigned)((nc + BLOCK - 1) / BLOCK);
+  const size_t shm = (size_t)4 * ctx->vg.numax * sizeof(double);
+  if (shm > 48 * 1024) return fin(fail(AVS_E_INVALID, "velocity grid too fine for the diatomic tables"));
   k_dg_initrec<<<gc, BLOCK, 0, ctx->stream>>>(nc, d->gp, d->W[0], d->tp, d->bad);
-  k_dg_target<<<nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->gp, d->tp, d->W[0], d->lam, 1, d->bad);
-  k_dg_update<<<nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->gp, nullptr, nullptr, d->v[0], d->tp, d->lam, d->q, 1);
+  k_dg_target<<<nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->tp, d->W[0], d->lam, 1, d->bad);
+  k_dg_update<<<nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, nullptr, nullptr, d->v[0], d->tp, d->lam,
+                                               d->q, 1);
   if (hipGetLastError() != hipSuccess) return fin(fail(AVS_E_HIP, "diatomic initialisation launch failed"));
   return fin(dia_check_bad(d));
 }
@@ -1360,19 +1364,21 @@ avs_status avs_dia_step(avs_dia* d, int32_t nsteps) {
   if (nsteps < 0) return fail(AVS_E_INVALID, "nsteps < 0");
   const Leaves L = ctx->leaves(ctx->lcur);
   const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK);
+  const size_t shm = (size_t)4 * ctx->vg.numax * sizeof(double);
   for (int s = 0; s < nsteps; ++s) {
     const int c = d->cur;
     k_dg_recon<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->h, d->v[c], d->fv, d->gp);
     CKL();
-    k_dg_face<<<ctx->nf, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->gas, d->gp, ctx->h, d->fv, d->F, d->bad);
+    k_dg_face<<<ctx->nf, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->gas, d->gp, ctx->h, d->fv, d->F, d->bad);
     CKL();
     k_dg_macro<<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, d->gp, ctx->dt, d->F, d->W[c], d->W[c ^ 1], d->q,
                                               d->tp, d->bad);
     CKL();
-    k_dg_target<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->gp, d->tp, d->W[c ^ 1], d->lam, 0, d->bad);
+    k_dg_target<<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->tp, d->W[c ^ 1], d->lam, 0,
+                                                      d->bad);
     CKL();
-    k_dg_update<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->gp, d->v[c], d->fv, d->v[c ^ 1], d->tp, d->lam,
-                                                    d->q, 0);
+    k_dg_update<<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->v[c], d->fv, d->v[c ^ 1], d->tp,
+                                                      d->lam, d->q, 0);
     CKL();
     d->cur ^= 1;
   }

@@ -25,21 +25,20 @@ struct DiaGas {
 
 // Rykov equilibrium triple at one leaf (c = xi - U), or, with t_only, the
 // translational part at (T_t, T_r) with zero heat fluxes.
+// gt and g are the Maxwellians at T_t and at T = (3 T_t + 2 T_r)/5.
 __device__ __forceinline__ void dg_equilibrium(const DiaGas& gp, double rho, const double (&c)[2], double Tt, double Tr,
-                                               const double* qt, const double* qr, bool t_only, double& G, double& H,
-                                               double& Rr) {
+                                               const double* qt, const double* qr, bool t_only, double gt, double g,
+                                               double& G, double& H, double& Rr) {
   const double R = gp.R;
   const double T = (3.0 * Tt + 2.0 * Tr) / 5.0;
   const double c2 = c[0] * c[0] + c[1] * c[1];
   const double RTt = R * Tt, RT = R * T;
-  const double gt = rho / (2.0 * M_PI * RTt) * exp(-c2 / (2.0 * RTt));
   if (t_only) {
     G = gt;
     H = RTt * gt;
     Rr = R * Tr * gt;
     return;
   }
-  const double g = rho / (2.0 * M_PI * RT) * exp(-c2 / (2.0 * RT));
   const double cqt = c[0] * qt[0] + c[1] * qt[1], cqr = c[0] * qr[0] + c[1] * qr[1];
   const double pt = rho * RTt, p = rho * RT;
   const double at = cqt / (15.0 * pt * RTt), ar = gp.omega0 * cqt / (15.0 * p * RT);
@@ -53,6 +52,25 @@ __device__ __forceinline__ void dg_equilibrium(const DiaGas& gp, double rho, con
   G = wt * Gt + wr * Gr;
   H = wt * Ht + wr * Hr;
   Rr = wt * Rt + wr * Rq;
+}
+
+// Separable per-axis tables of the Maxwellians at T_t and at T (the
+// half-finest grid carries every leaf centre), built by the whole block
+// from a record r = (rho, U0, U1, T_t, T_r, ...); followed by a barrier.
+__device__ __forceinline__ void dg_tables(const double* r, double R, const VGrid& vg, double* tabt, double* tabr,
+                                          double* part, double* parr) {
+  if (threadIdx.x == 0) {
+    const double Tt = r[3], T = (3.0 * r[3] + 2.0 * r[4]) / 5.0;
+    part[P_COEF] = r[0] / (2.0 * M_PI * R * Tt);
+    parr[P_COEF] = r[0] / (2.0 * M_PI * R * T);
+    for (int d = 0; d < 3; ++d) part[P_U + d] = parr[P_U + d] = d < 2 ? r[1 + d] : 0.0;
+    part[P_I2RT] = 0.5 / (R * Tt);
+    parr[P_I2RT] = 0.5 / (R * T);
+  }
+  __syncthreads();
+  build_tab<2>(tabt, part, vg);
+  build_tab<2>(tabr, parr, vg);
+  __syncthreads();
 }
 
 // rho, U, T_t, T_r, T from W = (rho, rho U, rho E, rho E_rot).
@@ -178,10 +196,11 @@ __device__ __forceinline__ void dg_sum(double* v, double* red) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, GasP vgas, DiaGas gp, double h,
+__global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, VGrid vg, GasP vgas, DiaGas gp, double h,
                                                   double* __restrict__ fv, double* __restrict__ F, int* __restrict__ bad) {
+  extern __shared__ double lds_d[];
   __shared__ double red[(BLOCK / 64 + 1) * 8];
-  __shared__ double rec[16];
+  __shared__ double rec[16], part[NPAR], parr[NPAR];
   const int f = blockIdx.x;
   const int Rc = g.f_R[f];
   const size_t fs = (size_t)g.nf * L.ld;
@@ -234,6 +253,9 @@ __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, GasP vgas, D
       rec[10] = h / (tf + h);
     }
     __syncthreads();
+    double* tabt = lds_d;
+    double* tabr = lds_d + 2 * vg.numax;
+    dg_tables(rec, gp.R, vg, tabt, tabr, part, parr);
     double fl[5] = {0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < L.n; k += BLOCK) {
       double xi[2], A;
@@ -241,7 +263,8 @@ __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, GasP vgas, D
       leaf_load<2>(L, k, xi, A, u);
       const double c[2] = {xi[0] - rec[1], xi[1] - rec[2]};
       double Ge, He, Re;
-      dg_equilibrium(gp, rec[0], c, rec[3], rec[4], rec + 5, rec + 7, false, Ge, He, Re);
+      dg_equilibrium(gp, rec[0], c, rec[3], rec[4], rec + 5, rec + 7, false, maxw<2>(part, tabt, vg.numax, u),
+                     maxw<2>(parr, tabr, vg.numax, u), Ge, He, Re);
       const double Gv = rec[9] * row0[k] + rec[10] * Ge;
       const double Hv = rec[9] * row0[fs + k] + rec[10] * He;
       const double Rv = rec[9] * row0[2 * fs + k] + rec[10] * Re;
@@ -334,13 +357,17 @@ __global__ void k_dg_macro(Geo g, GasP vgas, DiaGas gp, double dt, const double*
 // part with zero heat fluxes) plus sum_m lambda_m e_m has the moments
 // target = (rho, rho U, rho E, E_rot target) of W; e_m = (1, c, |c|^2) x
 // (g, R T g, R T g) at T and (0, 0, R T g).
-__global__ __launch_bounds__(BLOCK) void k_dg_target(Geo g, Leaves L, DiaGas gp, const double* __restrict__ tp,
+__global__ __launch_bounds__(BLOCK) void k_dg_target(Geo g, Leaves L, VGrid vg, DiaGas gp, const double* __restrict__ tp,
                                                     const double* __restrict__ Wt, double* __restrict__ lam, int init,
                                                     int* __restrict__ bad) {
+  extern __shared__ double lds_d[];
   __shared__ double red[(BLOCK / 64 + 1) * 32];
-  __shared__ double Jm[25], bv[5], xv[5];
+  __shared__ double Jm[25], bv[5], xv[5], part[NPAR], parr[NPAR];
   const int i = blockIdx.x;
   const double* r = tp + (size_t)i * DG_NT;
+  double* tabt = lds_d;
+  double* tabr = lds_d + 2 * vg.numax;
+  dg_tables(r, gp.R, vg, tabt, tabr, part, parr);
   const double rho = r[0], U[2] = {r[1], r[2]}, Tt = r[3], Tr = r[4], T = r[11];
   const double RT = gp.R * T;
   double acc[30];
@@ -350,10 +377,10 @@ __global__ __launch_bounds__(BLOCK) void k_dg_target(Geo g, Leaves L, DiaGas gp,
     int u[2];
     leaf_load<2>(L, k, xi, A, u);
     const double c[2] = {xi[0] - U[0], xi[1] - U[1]};
+    const double gv = maxw<2>(parr, tabr, vg.numax, u);
     double Ge, He, Re;
-    dg_equilibrium(gp, rho, c, Tt, Tr, r + 5, r + 7, init != 0, Ge, He, Re);
+    dg_equilibrium(gp, rho, c, Tt, Tr, r + 5, r + 7, init != 0, maxw<2>(part, tabt, vg.numax, u), gv, Ge, He, Re);
     dg_mom(acc, A, xi, Ge, He, Re);
-    const double gv = rho / (2.0 * M_PI * RT) * exp(-(c[0] * c[0] + c[1] * c[1]) / (2.0 * RT));
     const double bs[4] = {1.0, c[0], c[1], c[0] * c[0] + c[1] * c[1]};
     for (int e = 0; e < 4; ++e) dg_mom(acc + 5 + 5 * e, A, xi, bs[e] * gv, RT * bs[e] * gv, RT * bs[e] * gv);
     dg_mom(acc + 25, A, xi, 0.0, 0.0, RT * gv);
@@ -379,14 +406,19 @@ __global__ __launch_bounds__(BLOCK) void k_dg_target(Geo g, Leaves L, DiaGas gp,
 
 // phi^{n+1} = (phi^n + dt/tau g~ - dt/V sum sigma A xi.n phi_f) / (1 + dt/tau),
 // or with init the closed initial state; heat fluxes of the result about U.
-__global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, DiaGas gp, const double* __restrict__ vin,
+__global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, DiaGas gp, const double* __restrict__ vin,
                                                     const double* __restrict__ fv, double* __restrict__ vout,
                                                     const double* __restrict__ tp, const double* __restrict__ lam,
                                                     double* __restrict__ q, int init) {
   constexpr int MAXF = MAXF2;
+  extern __shared__ double lds_d[];
   __shared__ double red[(BLOCK / 64 + 1) * 8];
+  __shared__ double part[NPAR], parr[NPAR];
   const int i = blockIdx.x;
   const double* r = tp + (size_t)i * DG_NT;
+  double* tabt = lds_d;
+  double* tabr = lds_d + 2 * vg.numax;
+  dg_tables(r, gp.R, vg, tabt, tabr, part, parr);
   const double rho = r[0], U[2] = {r[1], r[2]}, Tt = r[3], Tr = r[4], T = r[11], dtt = r[9];
   const double RT = gp.R * T, dtv = g.dtv[i];
   double la[5];
@@ -400,9 +432,9 @@ __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, DiaGas gp,
     leaf_load<2>(L, k, xi, A, u);
     const double c[2] = {xi[0] - U[0], xi[1] - U[1]};
     const double c2 = c[0] * c[0] + c[1] * c[1];
+    const double gv = maxw<2>(parr, tabr, vg.numax, u);
     double Ge, He, Re;
-    dg_equilibrium(gp, rho, c, Tt, Tr, r + 5, r + 7, init != 0, Ge, He, Re);
-    const double gv = rho / (2.0 * M_PI * RT) * exp(-c2 / (2.0 * RT));
+    dg_equilibrium(gp, rho, c, Tt, Tr, r + 5, r + 7, init != 0, maxw<2>(part, tabt, vg.numax, u), gv, Ge, He, Re);
     const double poly = la[0] + la[1] * c[0] + la[2] * c[1] + la[3] * c2;
     const double tg[3] = {Ge + poly * gv, He + poly * RT * gv, Re + poly * RT * gv + la[4] * RT * gv};
     double nv[3];
