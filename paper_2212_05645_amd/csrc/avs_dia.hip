@@ -114,21 +114,39 @@ __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, c
   const int i = blockIdx.x;
   const int ns = g.nslot[i];
   const size_t cs = (size_t)g.nc * L.ld, fs = (size_t)g.nf * L.ld;
+  // neighbour rows (a slot without an interior neighbour reads the cell's
+  // own row and is skipped), so that every load of a leaf is issued before
+  // any is used
+  size_t nb[MAXF];
+  unsigned mask = 0;
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) {
+    const int j = s < ns ? g.s_nbr[i * MAXF + s] : -1;
+    if (j >= 0) mask |= 1u << s;
+    nb[s] = (size_t)(j >= 0 ? j : i) * L.ld;
+  }
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
     double xi[2], A;
     int u[2];
     leaf_load<2>(L, k, xi, A, u);
-    double ph[3], gr[3][2], pmax[3], pmin[3];
+    double ph[3], gr[3][2], pmax[3], pmin[3], nv[MAXF][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) ph[p] = vin[p * cs + (size_t)i * L.ld + k];
+#pragma unroll
+    for (int s = 0; s < MAXF; ++s)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) nv[s][p] = vin[p * cs + nb[s] + k];
+#pragma unroll
     for (int p = 0; p < 3; ++p) {
-      ph[p] = vin[p * cs + (size_t)i * L.ld + k];
       gr[p][0] = gr[p][1] = 0.0;
       pmax[p] = pmin[p] = ph[p];
     }
-    for (int s = 0; s < ns; ++s) {
-      const int j = g.s_nbr[i * MAXF + s];
-      if (j < 0) continue;
+#pragma unroll
+    for (int s = 0; s < MAXF; ++s) {
+      if (!(mask & (1u << s))) continue;
+#pragma unroll
       for (int p = 0; p < 3; ++p) {
-        const double v = vin[p * cs + (size_t)j * L.ld + k];
+        const double v = nv[s][p];
         const double dv = v - ph[p];
         gr[p][0] += dv * g.s_lsq[(size_t)(i * MAXF + s) * 2];
         gr[p][1] += dv * g.s_lsq[(size_t)(i * MAXF + s) * 2 + 1];
