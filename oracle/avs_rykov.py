@@ -335,3 +335,66 @@ class DiatomicSolver:
 
     def totals(self):
         return np.sum(self.mesh.vol[:, None] * self.W, axis=0)
+
+
+# ---------------------------------------------------------------------------
+# Adaptation of the diatomic state (Sec. 3.2-3.4 with the diatomic energy)
+# ---------------------------------------------------------------------------
+#
+# Readings: M2 measures the internal energy including rotation,
+# M2 = A (1/2 (|c|^2 G + H) + R) / (rho E - rho |U|^2 / 2); the remap is the
+# consanguinity reconstruction of each component followed by the closure
+# onto W (the diatomic counterpart of correction 2 without its literal
+# equilibrium difference); no probe states.
+
+def criterion_dia(phi, W, tree):
+    """M_k = max over cells of max(M1, M2), in a fixed operation order (no
+    fused multiply-add) so that it can be compared bit for bit."""
+    D = tree.dim
+    xi, A = tree.centres(), tree.weights()
+    Mk = np.full(tree.n, -np.inf)
+    for i in range(phi.shape[1]):
+        rho = W[i, 0]
+        U = [W[i, 1 + d] / rho for d in range(D)]
+        ke = U[0] * U[0]
+        for d in range(1, D):
+            ke = ke + U[d] * U[d]
+        eint = W[i, 1 + D] - 0.5 * rho * ke
+        c = xi[:, 0] - U[0]
+        c2 = c * c
+        for d in range(1, D):
+            c = xi[:, d] - U[d]
+            c2 = c2 + c * c
+        G, H, Rr = phi[0, i], phi[1, i], phi[2, i]
+        M1 = (A * G) / rho
+        M2 = (A * (0.5 * (c2 * G + H) + Rr)) / eint
+        Mk = np.maximum(Mk, np.maximum(M1, M2))
+    return Mk
+
+
+def remap_dia(phi, plan, W, R):
+    """Consanguinity reconstruction of G, H and R, then the closure onto W."""
+    D = plan.tree.dim
+    out = _O.remap(phi, plan, D)
+    xi, A = plan.tree.centres(), plan.tree.weights()
+    for i in range(out.shape[1]):
+        out[:, i] = closure_dia(out[:, i], W[i], W[i], xi, A, R)
+    return out
+
+
+def _adapt(self, C1, C2):
+    Mk = criterion_dia(self.phi, self.W, self.tree)
+    raw = _O.raw_flags(Mk, self.tree, C1, C2)
+    eff = _O.resolve_merges(raw, self.tree)
+    self.plan = _O.make_plan(eff, self.tree)
+    return eff, self.plan, Mk
+
+
+def _remap(self):
+    self.phi = remap_dia(self.phi, self.plan, self.W, self.gas.R)
+    self.tree = self.plan.tree
+    self.plan = None
+
+
+DiatomicSolver.adapt = _adapt
+DiatomicSolver.remap = _remap

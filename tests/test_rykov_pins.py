@@ -117,10 +117,10 @@ def test_interface_rotational_relaxation_limits():
     assert abs(a + b - 1.0) < 1e-15 and abs(b - 0.3 / (0.4 + 0.3)) < 1e-15
 
 
-def periodic_case(nx=5, ny=4, seed=1, omega=0.74, dt=2e-3, Tr_amp=0.1, uamp=0.3):
+def periodic_case(nx=5, ny=4, seed=1, omega=0.74, dt=2e-3, Tr_amp=0.1, uamp=0.3, max_level=0):
     from workloads import meshes as MM
     mesh = MM.box2d(nx, ny, periodic=(True, True))
-    tree = O.base_forest(2, [-6.0, -6.0], [6.0, 6.0], [16, 16], 0)
+    tree = O.base_forest(2, [-6.0, -6.0], [6.0, 6.0], [16, 16], max_level)
     vgas = dict(R=0.5, Pr=2 / 3, omega=omega, mu_ref=0.05, T_ref=1.0, model=1)
     gas = RY.RykovGas(R=0.5, Z_rot=3.5)
     rng = np.random.default_rng(seed)
@@ -163,3 +163,40 @@ def test_homogeneous_rotational_relaxation_closed_form():
         s.step(1)
         np.testing.assert_allclose(s.W[:, 4], Eeq + (E0 - Eeq) * (1 + k) ** -nstep, rtol=1e-13)
         assert abs(RY.temperatures(s.W[0], 0.5)[4] - T) < 1e-14
+
+
+def test_diatomic_criterion_sums_and_remap_conserves():
+    """When M[phi] = W the criterion's terms are fractions: sum_k M1 = sum_k
+    M2 = 1 in every cell (mass and internal energy, rotation included).
+    After an adaptation with splits and merges the remapped state has the
+    moments W to round-off; a split followed by the merge of the same
+    leaves returns the consanguinity values exactly."""
+    s = periodic_case(nx=3, ny=2, max_level=1)
+    xi, A = s.tree.centres(), s.tree.weights()
+    for i in range(s.mesh.nc):
+        Mk = RY.criterion_dia(s.phi[:, i:i + 1], s.W[i:i + 1], s.tree)
+        # one cell: Mk = max(M1, M2); recompute both sums through the definition
+        rho, U, Tt, Tr, T = RY.temperatures(s.W[i], 0.5)
+        c = xi - U[None, :]
+        eint = s.W[i, 3] - 0.5 * rho * U @ U
+        M1 = A * s.phi[0, i] / rho
+        M2 = A * (0.5 * (np.sum(c * c, axis=1) * s.phi[0, i] + s.phi[1, i]) + s.phi[2, i]) / eint
+        assert abs(M1.sum() - 1) < 1e-13 and abs(M2.sum() - 1) < 1e-13
+        assert np.array_equal(Mk, np.maximum(M1, M2)) or np.allclose(Mk, np.maximum(M1, M2), rtol=1e-15)
+    s.step(1)
+    Mk = RY.criterion_dia(s.phi, s.W, s.tree)
+    C1 = np.quantile(Mk, 0.8)
+    eff, plan, _ = s.adapt(C1, np.quantile(Mk, 0.2))
+    assert (eff == 1).any()
+    s.remap()
+    np.testing.assert_allclose(s.vdf_moments(), s.W, rtol=0, atol=1e-13)
+    # split everything, then merge everything back: consanguinity is exact
+    s = periodic_case(nx=3, ny=2, max_level=1)
+    phi0, tree0 = s.phi.copy(), s.tree
+    s.adapt(-1.0, -2.0)
+    p_split = O.remap(s.phi, s.plan, 2)
+    t_split = s.plan.tree
+    eff = O.resolve_merges(O.raw_flags(np.zeros(t_split.n), t_split, 1.0, 0.5), t_split)
+    back = O.make_plan(eff, t_split)
+    assert back.tree.n == tree0.n
+    assert np.array_equal(O.remap(p_split, back, 2), phi0)
