@@ -185,20 +185,34 @@ avs_status avs_rykov_equilibrium(avs_ctx *ctx, const avs_rykov *gas, const doubl
  * triples (g, R T g, R T g) of their state; the wall's density gives zero net
  * mass flux.  The state lives in a caller region of avs_dia_bytes bytes
  * (device, 256-byte aligned, owned by the caller until avs_dia_destroy),
- * sized for the context's current leaves.
+ * sized for at most max_leaves leaves (between the current leaf count and
+ * the context's leaf capacity).
  * prim0_host: [ncells][5] = (rho, U_x, U_y, T_t, T_r); the initial VDF is
  * the translational part of the Rykov equilibrium at (T_t, T_r) closed onto
- * W.  The context's leaves must not change while the state is used
- * (AVS_E_STATE otherwise); the monatomic state of the context is not
- * touched.  avs_dia_step waits for the device and reports AVS_E_NUMERIC for
+ * W.  The context's leaves may change only through avs_dia_remap while the
+ * state is used (AVS_E_STATE otherwise); the monatomic state of the context
+ * is not otherwise touched.  avs_dia_step waits for the device and reports AVS_E_NUMERIC for
  * a non-physical state.  avs_dia_get_state copies [3][ncells][nleaves] and
  * [ncells][5] (either may be NULL). */
 typedef struct avs_dia avs_dia;
-avs_status avs_dia_bytes(const avs_ctx *ctx, size_t *bytes);
-avs_status avs_dia_create(avs_ctx *ctx, const avs_rykov *gas, const double *prim0_host, void *mem_dev,
-                          size_t mem_bytes, avs_dia **out);
+avs_status avs_dia_bytes(const avs_ctx *ctx, int64_t max_leaves, size_t *bytes);
+avs_status avs_dia_create(avs_ctx *ctx, const avs_rykov *gas, const double *prim0_host, int64_t max_leaves,
+                          void *mem_dev, size_t mem_bytes, avs_dia **out);
 avs_status avs_dia_step(avs_dia *dia, int32_t nsteps);
 avs_status avs_dia_get_state(avs_dia *dia, double *vdf_host, double *W_host);
+
+/* Adaptation of the velocity tree driven by the diatomic state (Secs.
+ * 3.2-3.4): M_k = max over cells of max(M1, M2), M1 = A G / rho, M2 =
+ * A (1/2 (|c|^2 G + H) + R) / (rho E - rho |U|^2 / 2) (the internal energy
+ * includes rotation); flags and plan as avs_adapt (no probe states).
+ * flags_dev and n_new_host as in avs_adapt; AVS_E_CAPACITY (plan discarded)
+ * beyond the state's max_leaves or the context's capacity.
+ * avs_dia_remap applies the plan: consanguinity reconstruction of G, H, R
+ * and the closure onto W, the heat fluxes of the result, and avs_remap(ctx,
+ * 0) for the context's own state, which moves the context to the new
+ * leaves; the diatomic state follows them. */
+avs_status avs_dia_adapt(avs_dia *dia, double C1, double C2, int8_t *flags_dev, int64_t *n_new_host);
+avs_status avs_dia_remap(avs_dia *dia);
 void avs_dia_destroy(avs_dia *dia);
 
 /* Bytes of the device region avs_step_implicit needs for the right-hand

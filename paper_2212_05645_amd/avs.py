@@ -29,7 +29,7 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
            "avs_auto_params", "avs_initial_avs", "avs_implicit_bytes", "avs_step_implicit",
            "avs_rykov_equilibrium", "avs_dia_bytes", "avs_dia_create", "avs_dia_step", "avs_dia_get_state",
-           "avs_dia_destroy", "avs_destroy", "avs_last_error")
+           "avs_dia_adapt", "avs_dia_remap", "avs_dia_destroy", "avs_destroy", "avs_last_error")
 
 
 class avs_rykov(C.Structure):
@@ -126,8 +126,10 @@ def _load():
         "avs_initial_avs": (I32, [VP, P(avs_flow), D, D, P(I64)]),
         "avs_implicit_bytes": (I32, [VP, P(C.c_size_t)]),
         "avs_rykov_equilibrium": (I32, [VP, P(avs_rykov), VP, I64, VP, C.c_size_t]),
-        "avs_dia_bytes": (I32, [VP, P(C.c_size_t)]),
-        "avs_dia_create": (I32, [VP, P(avs_rykov), VP, VP, C.c_size_t, P(VP)]),
+        "avs_dia_bytes": (I32, [VP, I64, P(C.c_size_t)]),
+        "avs_dia_create": (I32, [VP, P(avs_rykov), VP, I64, VP, C.c_size_t, P(VP)]),
+        "avs_dia_adapt": (I32, [VP, D, D, VP, P(I64)]),
+        "avs_dia_remap": (I32, [VP]),
         "avs_dia_step": (I32, [VP, I32]),
         "avs_dia_get_state": (I32, [VP, VP, VP]),
         "avs_dia_destroy": (None, [VP]),
@@ -505,17 +507,32 @@ class Diatomic:
     """Explicit steps of the Rykov diatomic model on a Case's mesh and
     current leaves (2-D, FP64).  prim0 rows are (rho, U_x, U_y, T_t, T_r)."""
 
-    def __init__(self, case, prim0, Z_rot=3.5, delta=1.0 / 1.55, omega0=0.2354, omega1=0.3049):
+    def __init__(self, case, prim0, Z_rot=3.5, delta=1.0 / 1.55, omega0=0.2354, omega1=0.3049, max_leaves=None):
         t = case._torch
         self.case = case
+        ml = int(max_leaves if max_leaves is not None else case.nleaves())
         nb = C.c_size_t()
-        _check(lib.avs_dia_bytes(case.ctx, C.byref(nb)))
+        _check(lib.avs_dia_bytes(case.ctx, ml, C.byref(nb)))
         self.mem = t.empty(nb.value, dtype=t.uint8, device=case.device)
         p0 = np.ascontiguousarray(prim0, dtype=np.float64)
         g = avs_rykov(float(Z_rot), float(delta), float(omega0), float(omega1))
         h = C.c_void_p()
-        _check(lib.avs_dia_create(case.ctx, C.byref(g), p0.ctypes.data, self.mem.data_ptr(), nb.value, C.byref(h)))
+        _check(lib.avs_dia_create(case.ctx, C.byref(g), p0.ctypes.data, ml, self.mem.data_ptr(), nb.value,
+                                  C.byref(h)))
         self.h = h
+
+    def adapt(self, C1, C2):
+        """Adaptation driven by the diatomic state; returns (flags, n_new)."""
+        t = self.case._torch
+        n_old = self.case.nleaves()
+        flags = t.empty(max(n_old, 1), dtype=t.int8, device=self.case.device)
+        nn = C.c_int64()
+        _check(lib.avs_dia_adapt(self.h, float(C1), float(C2), flags.data_ptr(), C.byref(nn)))
+        t.cuda.synchronize(self.case.device)
+        return flags[:n_old].cpu().numpy(), nn.value
+
+    def remap(self):
+        _check(lib.avs_dia_remap(self.h))
 
     def step(self, n=1):
         _check(lib.avs_dia_step(self.h, int(n)))

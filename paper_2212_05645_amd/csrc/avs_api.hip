@@ -1257,6 +1257,8 @@ avs_status avs_rykov_equilibrium(avs_ctx* ctx, const avs_rykov* gas, const doubl
 }
 
 // ------------------------------------------------ diatomic (Rykov) path
+static avs_status finish_plan(avs_ctx* ctx, int8_t* flags_dev, int64_t* n_new_host, bool* capacity_ok);
+
 struct avs_dia {
   avs_ctx* ctx = nullptr;
   DiaGas gp{};
@@ -1265,13 +1267,14 @@ struct avs_dia {
   int* bad = nullptr;
   int cur = 0;
   int64_t gen = 0;
+  int64_t max_leaves = 0;
 };
 
 namespace {
-size_t dia_layout(const avs_ctx* c, avs_dia* d, char* base) {
+size_t dia_layout(const avs_ctx* c, int64_t max_leaves, avs_dia* d, char* base) {
   Carver cv{base};
-  // rows of the current leaf set (the diatomic state refuses a changed one)
-  const size_t nc = c->nc, nf = c->nf, cap = (size_t)c->ld[c->lcur];
+  // rows for at most max_leaves leaves
+  const size_t nc = c->nc, nf = c->nf, cap = (size_t)round_up(max_leaves, 64);
   for (int t = 0; t < 2; ++t) {
     double* p = cv.take<double>(3 * nc * cap);
     if (d) d->v[t] = p;
@@ -1300,14 +1303,16 @@ avs_status dia_check_bad(avs_dia* d) {
 }
 }  // namespace
 
-avs_status avs_dia_bytes(const avs_ctx* ctx, size_t* bytes) {
+avs_status avs_dia_bytes(const avs_ctx* ctx, int64_t max_leaves, size_t* bytes) {
   if (!ctx || !bytes) return fail(AVS_E_INVALID, "null argument");
-  *bytes = dia_layout(ctx, nullptr, nullptr);
+  if (max_leaves < ctx->nleaf[ctx->lcur] || max_leaves > ctx->cap)
+    return fail(AVS_E_INVALID, "max_leaves must lie between the current leaf count and the leaf capacity");
+  *bytes = dia_layout(ctx, max_leaves, nullptr, nullptr);
   return AVS_OK;
 }
 
-avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim0_host, void* mem_dev, size_t mem_bytes,
-                          avs_dia** out) {
+avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim0_host, int64_t max_leaves,
+                          void* mem_dev, size_t mem_bytes, avs_dia** out) {
   if (!out) return fail(AVS_E_INVALID, "out is null");
   *out = nullptr;
   if (avs_status st = guard(ctx)) return st;
@@ -1317,7 +1322,9 @@ avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim
   if (!(gas->Z_rot >= 1.0 && std::isfinite(gas->Z_rot)) || !(gas->delta > 0.0 && gas->delta <= 1.0) ||
       !std::isfinite(gas->omega0) || !std::isfinite(gas->omega1))
     return fail(AVS_E_INVALID, "Rykov parameters: Z_rot >= 1, 0 < delta <= 1, finite omega_0 and omega_1");
-  const size_t need = dia_layout(ctx, nullptr, nullptr);
+  if (max_leaves < ctx->nleaf[ctx->lcur] || max_leaves > ctx->cap)
+    return fail(AVS_E_INVALID, "max_leaves must lie between the current leaf count and the leaf capacity");
+  const size_t need = dia_layout(ctx, max_leaves, nullptr, nullptr);
   if (mem_bytes < need) return fail(AVS_E_INVALID, "mem region too small (%zu < %zu)", mem_bytes, need);
   const int nc = ctx->nc;
   const double R = ctx->gas.R;
@@ -1337,8 +1344,9 @@ avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim
   avs_dia* d = new avs_dia();
   d->ctx = ctx;
   d->gp = DiaGas{R, gas->Z_rot, gas->delta, gas->omega0, gas->omega1};
-  dia_layout(ctx, d, (char*)mem_dev);
+  dia_layout(ctx, max_leaves, d, (char*)mem_dev);
   d->gen = ctx->leaf_gen;
+  d->max_leaves = max_leaves;
   const int badinit[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
   const Leaves L = ctx->leaves(ctx->lcur);
   auto fin = [&](avs_status st) { if (st) delete d; else *out = d; return st; };
@@ -1401,6 +1409,63 @@ avs_status avs_dia_get_state(avs_dia* d, double* vdf_host, double* W_host) {
   }
   CK(hipStreamSynchronize(ctx->stream));
   return AVS_OK;
+}
+
+avs_status avs_dia_adapt(avs_dia* d, double C1, double C2, int8_t* flags_dev, int64_t* n_new_host) {
+  if (!d) return fail(AVS_E_INVALID, "null diatomic state");
+  avs_ctx* ctx = d->ctx;
+  if (avs_status st = guard(ctx)) return st;
+  if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
+  if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
+  ctx->plan_valid = false;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int nb = (L.n + BLOCK - 1) / BLOCK;
+  k_dg_crit_partial<<<dim3(nb, ctx->ngrp), BLOCK, 0, ctx->stream>>>(L, ctx->nc, d->v[d->cur], d->W[d->cur],
+                                                                   ctx->crit_part);
+  CKL();
+  k_crit_reduce<2><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->ngrp, ctx->crit_part, 0, ctx->probe_cc, ctx->probe_prim,
+                                                 ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
+  CKL();
+  k_resolve<2><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
+  CKL();
+  k_scan<<<1, BLOCK, 0, ctx->stream>>>(L.n, ctx->cnt, ctx->off);
+  CKL();
+  int64_t nn = 0;
+  if (avs_status st = finish_plan(ctx, flags_dev, &nn, nullptr)) return st;
+  if (n_new_host) *n_new_host = nn;
+  if (nn > d->max_leaves) {
+    ctx->plan_valid = false;
+    return fail(AVS_E_CAPACITY, "adaptation would produce %" PRId64 " leaves > the diatomic state's %" PRId64, nn,
+                d->max_leaves);
+  }
+  return AVS_OK;
+}
+
+avs_status avs_dia_remap(avs_dia* d) {
+  if (!d) return fail(AVS_E_INVALID, "null diatomic state");
+  avs_ctx* ctx = d->ctx;
+  if (avs_status st = guard(ctx)) return st;
+  if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
+  if (!ctx->plan_valid) return fail(AVS_E_STATE, "no adaptation plan (call avs_dia_adapt first)");
+  const Leaves Lo = ctx->leaves(ctx->lcur), Ln = ctx->leaves(ctx->lcur ^ 1);
+  const int c = d->cur;
+  k_dg_gather<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->nc, Lo, Ln, ctx->pkind, ctx->psrc, d->v[c], d->v[c ^ 1]);
+  CKL();
+  const size_t shm = (size_t)4 * ctx->vg.numax * sizeof(double);
+  k_dg_close<<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, Ln, ctx->vg, d->gp, d->W[c], d->v[c ^ 1], d->bad);
+  CKL();
+  // the heat fluxes of the remapped state for the next step's target
+  const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK);
+  k_dg_initrec<<<gc, BLOCK, 0, ctx->stream>>>(ctx->nc, d->gp, d->W[c], d->tp, d->bad);
+  CKL();
+  k_dg_heat<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, Ln, d->v[c ^ 1], d->tp, d->q);
+  CKL();
+  // the context moves to the new leaves with its own (monatomic) state
+  if (avs_status st = avs_remap(ctx, 0)) return st;
+  CK(hipMemcpyAsync(d->W[c ^ 1], d->W[c], sizeof(double) * ctx->nc * DG_N, hipMemcpyDeviceToDevice, ctx->stream));
+  d->cur ^= 1;
+  d->gen = ctx->leaf_gen;
+  return dia_check_bad(d);
 }
 
 void avs_dia_destroy(avs_dia* d) { delete d; }

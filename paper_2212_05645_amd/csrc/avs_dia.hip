@@ -498,4 +498,151 @@ __global__ void k_dg_initrec(int nc, DiaGas gp, const double* __restrict__ W, do
   r[11] = T;
 }
 
+// Heat fluxes q_t, q_r of the state about the U of the record tp.
+__global__ __launch_bounds__(BLOCK) void k_dg_heat(Geo g, Leaves L, const double* __restrict__ v,
+                                                  const double* __restrict__ tp, double* __restrict__ q) {
+  __shared__ double red[(BLOCK / 64 + 1) * 8];
+  const int i = blockIdx.x;
+  const double U0 = tp[(size_t)i * DG_NT + 1], U1 = tp[(size_t)i * DG_NT + 2];
+  const size_t cs = (size_t)g.nc * L.ld;
+  double qa[4] = {0, 0, 0, 0};
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[2], A;
+    int u[2];
+    leaf_load<2>(L, k, xi, A, u);
+    const size_t o = (size_t)i * L.ld + k;
+    const double c0 = xi[0] - U0, c1 = xi[1] - U1, c2 = c0 * c0 + c1 * c1;
+    const double et = A * 0.5 * (c2 * v[o] + v[cs + o]), er = A * v[2 * cs + o];
+    qa[0] += et * c0;
+    qa[1] += et * c1;
+    qa[2] += er * c0;
+    qa[3] += er * c1;
+  }
+  dg_sum<4>(qa, red);
+  if (threadIdx.x < 4) q[(size_t)i * 4 + threadIdx.x] = qa[threadIdx.x];
+}
+
+// --------------------------------------------- adaptation of the state
+// Criterion partials over groups of CRIT_CELLS cells: M1 = A G / rho,
+// M2 = A (1/2 (|c|^2 G + H) + R) / (rho E - rho |U|^2/2), max over the group,
+// in a fixed operation order (no contraction) so that the flags are
+// reproducible bit for bit.
+__global__ __launch_bounds__(BLOCK) void k_dg_crit_partial(Leaves L, int nc, const double* __restrict__ vdf,
+                                                          const double* __restrict__ W, double* __restrict__ part) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  const int grp = blockIdx.y;
+  if (k >= L.n) return;
+  const size_t cs = (size_t)nc * L.ld;
+  double xi[2], A;
+  int u[2];
+  leaf_load<2>(L, k, xi, A, u);
+  double m = -INFINITY;
+  const int i1 = min(nc, (grp + 1) * CRIT_CELLS);
+  for (int i = grp * CRIT_CELLS; i < i1; ++i) {
+    const double* w = W + (size_t)i * DG_N;
+    const double rho = w[0];
+    const double U0 = w[1] / rho, U1 = w[2] / rho;
+    double ke = U0 * U0;
+    ke = ke + U1 * U1;
+    const double eint = w[3] - 0.5 * rho * ke;
+    double c = xi[0] - U0;
+    double c2 = c * c;
+    c = xi[1] - U1;
+    c2 = c2 + c * c;
+    const size_t o = (size_t)i * L.ld + k;
+    const double G = vdf[o], H = vdf[cs + o], Rr = vdf[2 * cs + o];
+    const double M1 = (A * G) / rho;
+    const double M2 = (A * (0.5 * (c2 * G + H) + Rr)) / eint;
+    m = fmax(m, fmax(M1, M2));
+  }
+  part[(size_t)grp * L.cap + k] = m;
+}
+
+// Consanguinity reconstruction of G, H, R onto the new leaves: a kept or
+// split leaf copies its source, a merged parent is the balanced pairwise
+// mean ((f0 + f1) + (f2 + f3)) / 4 of its children.
+__global__ __launch_bounds__(BLOCK) void k_dg_gather(int nc, Leaves Lo, Leaves Ln, const int* __restrict__ kind,
+                                                    const int* __restrict__ src, const double* __restrict__ vin,
+                                                    double* __restrict__ vout) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x;
+  const size_t cso = (size_t)nc * Lo.ld, csn = (size_t)nc * Ln.ld;
+  for (int j = threadIdx.x; j < Ln.n; j += BLOCK) {
+    const int k = src[j];
+    for (int p = 0; p < 3; ++p) {
+      const double* a = vin + p * cso + (size_t)i * Lo.ld;
+      double v;
+      if (kind[j] == 2) v = ((a[k] + a[k + 1]) + (a[k + 2] + a[k + 3])) * 0.25;
+      else v = a[k];
+      vout[p * csn + (size_t)i * Ln.ld + j] = v;
+    }
+  }
+}
+
+// Closure of the state onto W in place: f + sum_m lambda_m e_m with the
+// directions of the target's closure at T of W.
+__global__ __launch_bounds__(BLOCK) void k_dg_close(Geo g, Leaves L, VGrid vg, DiaGas gp, const double* __restrict__ W,
+                                                   double* __restrict__ v, int* __restrict__ bad) {
+  extern __shared__ double lds_d[];
+  __shared__ double red[(BLOCK / 64 + 1) * 32];
+  __shared__ double Jm[25], bv[5], xv[5], part[NPAR], parr[NPAR], rec[5];
+  const int i = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double rho, U[2], Tt, Tr, T;
+    if (!dg_temps(W + (size_t)i * DG_N, gp.R, rho, U, Tt, Tr, T)) atomicMin(bad, i);
+    rec[0] = rho; rec[1] = U[0]; rec[2] = U[1]; rec[3] = Tt; rec[4] = Tr;
+  }
+  __syncthreads();
+  double* tabt = lds_d;
+  double* tabr = lds_d + 2 * vg.numax;
+  dg_tables(rec, gp.R, vg, tabt, tabr, part, parr);
+  const double rho = rec[0], U[2] = {rec[1], rec[2]};
+  const double RT = gp.R * (3.0 * rec[3] + 2.0 * rec[4]) / 5.0;
+  const size_t cs = (size_t)g.nc * L.ld;
+  double acc[30];
+  for (int m = 0; m < 30; ++m) acc[m] = 0.0;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[2], A;
+    int u[2];
+    leaf_load<2>(L, k, xi, A, u);
+    const size_t o = (size_t)i * L.ld + k;
+    dg_mom(acc, A, xi, v[o], v[cs + o], v[2 * cs + o]);
+    const double c[2] = {xi[0] - U[0], xi[1] - U[1]};
+    const double gv = maxw<2>(parr, tabr, vg.numax, u);
+    const double bs[4] = {1.0, c[0], c[1], c[0] * c[0] + c[1] * c[1]};
+    for (int e = 0; e < 4; ++e) dg_mom(acc + 5 + 5 * e, A, xi, bs[e] * gv, RT * bs[e] * gv, RT * bs[e] * gv);
+    dg_mom(acc + 25, A, xi, 0.0, 0.0, RT * gv);
+  }
+  for (int g0 = 0; g0 < 30; g0 += 8) {
+    double vv[8];
+    for (int m = 0; m < 8; ++m) vv[m] = g0 + m < 30 ? acc[g0 + m] : 0.0;
+    dg_sum<8>(vv, red);
+    for (int m = 0; m < 8; ++m)
+      if (g0 + m < 30) acc[g0 + m] = vv[m];
+  }
+  if (threadIdx.x == 0) {
+    for (int l = 0; l < 5; ++l) {
+      for (int e = 0; e < 5; ++e) Jm[l * 5 + e] = acc[5 + 5 * e + l];
+      bv[l] = W[(size_t)i * DG_N + l] - acc[l];
+    }
+    if (!solve_small<5>(Jm, bv, xv)) atomicMin(bad, i);
+  }
+  __syncthreads();
+  const double l0 = xv[0], l1 = xv[1], l2 = xv[2], l3 = xv[3], l4 = xv[4];
+  (void)rho;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+    double xi[2], A;
+    int u[2];
+    leaf_load<2>(L, k, xi, A, u);
+    const double c[2] = {xi[0] - U[0], xi[1] - U[1]};
+    const double gv = maxw<2>(parr, tabr, vg.numax, u);
+    const double poly = l0 + l1 * c[0] + l2 * c[1] + l3 * (c[0] * c[0] + c[1] * c[1]);
+    const size_t o = (size_t)i * L.ld + k;
+    v[o] = v[o] + poly * gv;
+    v[cs + o] = v[cs + o] + poly * RT * gv;
+    v[2 * cs + o] = v[2 * cs + o] + (poly * RT * gv + l4 * RT * gv);
+  }
+}
+
 }  // namespace avs

@@ -310,3 +310,48 @@ def test_diatomic_ogrid_wall_and_farfield(avs):
         dia.step(1)
     dia.close()
     cs.close()
+
+
+def test_diatomic_adaptation_against_oracle(avs):
+    """Adaptation driven by the diatomic state: flags bit exact against the
+    oracle's criterion (splits and merges), the remapped and closed state to
+    1e-12 with moments equal to W, then a step on the new leaves; the
+    context follows the new leaves."""
+    mesh = MM.box2d(5, 4, periodic=(True, True))
+    vs = dict(dim=2, lo=(-6.0, -6.0), hi=(6.0, 6.0), base=(8, 8), max_level=2)
+    vgas = dict(R=0.5, Pr=0.72, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+    rng = np.random.default_rng(111)
+    n = mesh['ncells']
+    prim = np.concatenate([1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.4 * rng.uniform(-1, 1, (n, 2)),
+                           1 + 0.2 * rng.uniform(-1, 1, (n, 1)), 0.7 + 0.1 * rng.uniform(-1, 1, (n, 1))], axis=1)
+    from oracle import avs_rykov as RY
+    tree = random_tree(vs, 112, 2)
+    prim4 = np.concatenate([prim[:, :3], prim[:, 3:4]], axis=1)
+    cs = avs.Case(mesh, vs, vgas, 2e-3, 1.0, prim4)
+    cs.set_leaves(tree.level, tree.idx)
+    dia = avs.Diatomic(cs, prim, max_leaves=1024)
+    o = RY.DiatomicSolver(mesh, tree, vgas, RY.RykovGas(R=0.5, Z_rot=3.5), 2e-3, 1.0, prim)
+    dia.step(1)
+    o.step(1)
+    # thresholds halfway between neighbouring values of M_k, so that the
+    # decisions do not hang on the rounding differences of the two sides
+    Mk = np.sort(RY.criterion_dia(o.phi, o.W, o.tree))
+    j1, j2 = int(0.85 * len(Mk)), int(0.25 * len(Mk))
+    C1, C2 = 0.5 * (Mk[j1] + Mk[j1 + 1]), 0.5 * (Mk[j2] + Mk[j2 + 1])
+    assert Mk[j1 + 1] - Mk[j1] > 1e-9 * Mk[j1] and Mk[j2 + 1] - Mk[j2] > 1e-9 * Mk[j2]
+    flags, nn = dia.adapt(C1, C2)
+    eff, plan, _ = o.adapt(C1, C2)
+    assert np.array_equal(flags, eff) and nn == plan.tree.n
+    assert (eff == 1).any() and (eff == -1).any()
+    dia.remap()
+    o.remap()
+    assert cs.nleaves() == o.tree.n
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-13
+    np.testing.assert_allclose(o.vdf_moments(), W, rtol=0, atol=1e-13)
+    dia.step(1)
+    o.step(1)
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    dia.close()
+    cs.close()
