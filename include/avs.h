@@ -171,8 +171,9 @@ avs_status avs_rykov_equilibrium(avs_ctx *ctx, const avs_rykov *gas, const doubl
                                  void *out_dev, size_t out_bytes);
 
 /* Explicit steps of the Rykov diatomic model on a context's mesh and current
- * leaves: two-dimensional, FP64 contexts only.  Three reduced distributions
- * G, H, R (Eq. equ6) and W = (rho, rho U, rho E, rho E_rot) (Eq. updat_W).
+ * leaves: FP64 contexts, 2-D or 3-D.  Three reduced distributions G, H, R
+ * (Eq. equ6; H is the 3 - D hidden translational degrees of freedom, zero
+ * in 3-D) and W = (rho, rho U, rho E, rho E_rot) (Eq. updat_W).
  * One step: limited upwind reconstruction at x_f - xi h (h as in avs_step);
  * interface moments, the rotational energy relaxed over h towards rho R T
  * (the relation after Eq. w_interface, read with its factor as a divisor)
@@ -187,13 +188,13 @@ avs_status avs_rykov_equilibrium(avs_ctx *ctx, const avs_rykov *gas, const doubl
  * (device, 256-byte aligned, owned by the caller until avs_dia_destroy),
  * sized for at most max_leaves leaves (between the current leaf count and
  * the context's leaf capacity).
- * prim0_host: [ncells][5] = (rho, U_x, U_y, T_t, T_r); the initial VDF is
+ * prim0_host: [ncells][D+3] = (rho, U, T_t, T_r); the initial VDF is
  * the translational part of the Rykov equilibrium at (T_t, T_r) closed onto
  * W.  The context's leaves may change only through avs_dia_remap while the
  * state is used (AVS_E_STATE otherwise); the monatomic state of the context
  * is not otherwise touched.  avs_dia_step waits for the device and reports AVS_E_NUMERIC for
  * a non-physical state.  avs_dia_get_state copies [3][ncells][nleaves] and
- * [ncells][5] (either may be NULL). */
+ * [ncells][D+3] (either may be NULL). */
 typedef struct avs_dia avs_dia;
 avs_status avs_dia_bytes(const avs_ctx *ctx, int64_t max_leaves, size_t *bytes);
 avs_status avs_dia_create(avs_ctx *ctx, const avs_rykov *gas, const double *prim0_host, int64_t max_leaves,

@@ -504,8 +504,8 @@ class Mlp:
 
 
 class Diatomic:
-    """Explicit steps of the Rykov diatomic model on a Case's mesh and
-    current leaves (2-D, FP64).  prim0 rows are (rho, U_x, U_y, T_t, T_r)."""
+    """Explicit steps and adaptation of the Rykov diatomic model on a Case's
+    mesh and leaves (FP64, 2-D or 3-D).  prim0 rows are (rho, U, T_t, T_r)."""
 
     def __init__(self, case, prim0, Z_rot=3.5, delta=1.0 / 1.55, omega0=0.2354, omega1=0.3049, max_leaves=None):
         t = case._torch
@@ -515,6 +515,8 @@ class Diatomic:
         _check(lib.avs_dia_bytes(case.ctx, ml, C.byref(nb)))
         self.mem = t.empty(nb.value, dtype=t.uint8, device=case.device)
         p0 = np.ascontiguousarray(prim0, dtype=np.float64)
+        if p0.shape != (case.nc, case.dim + 3):
+            raise ValueError(f"prim0 must have shape ({case.nc}, {case.dim + 3})")
         g = avs_rykov(float(Z_rot), float(delta), float(omega0), float(omega1))
         h = C.c_void_p()
         _check(lib.avs_dia_create(case.ctx, C.byref(g), p0.ctypes.data, ml, self.mem.data_ptr(), nb.value,
@@ -540,7 +542,7 @@ class Diatomic:
     def get_state(self):
         n = self.case.nleaves()
         vdf = np.zeros((3, self.case.nc, n))
-        W = np.zeros((self.case.nc, 5))
+        W = np.zeros((self.case.nc, self.case.dim + 3))
         _check(lib.avs_dia_get_state(self.h, vdf.ctypes.data, W.ctypes.data))
         return vdf, W
 

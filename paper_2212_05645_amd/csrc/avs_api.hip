@@ -1270,22 +1270,25 @@ struct avs_dia {
   int64_t max_leaves = 0;
 };
 
+}  // extern "C"
+
 namespace {
 size_t dia_layout(const avs_ctx* c, int64_t max_leaves, avs_dia* d, char* base) {
   Carver cv{base};
   // rows for at most max_leaves leaves
   const size_t nc = c->nc, nf = c->nf, cap = (size_t)round_up(max_leaves, 64);
+  const size_t D = c->D, NW = D + 3, NQ = 2 * D, NT = 6 + 3 * D;
   for (int t = 0; t < 2; ++t) {
     double* p = cv.take<double>(3 * nc * cap);
     if (d) d->v[t] = p;
   }
   double* fv = cv.take<double>(3 * (nf + 1) * cap);
-  double* W0 = cv.take<double>(nc * DG_N);
-  double* W1 = cv.take<double>(nc * DG_N);
-  double* q = cv.take<double>(nc * 4);
-  double* F = cv.take<double>((nf + 1) * DG_N);
-  double* tp = cv.take<double>(nc * DG_NT);
-  double* lam = cv.take<double>(nc * DG_N);
+  double* W0 = cv.take<double>(nc * NW);
+  double* W1 = cv.take<double>(nc * NW);
+  double* q = cv.take<double>(nc * NQ);
+  double* F = cv.take<double>((nf + 1) * NW);
+  double* tp = cv.take<double>(nc * NT);
+  double* lam = cv.take<double>(nc * NW);
   int* bad = cv.take<int>(4);
   if (d) {
     d->fv = fv; d->W[0] = W0; d->W[1] = W1; d->q = q; d->F = F; d->tp = tp; d->lam = lam; d->bad = bad;
@@ -1301,7 +1304,92 @@ avs_status dia_check_bad(avs_dia* d) {
   if (bad != INT_MAX) return fail(AVS_E_NUMERIC, "diatomic path: non-physical state or singular closure at %d", bad);
   return AVS_OK;
 }
+
+size_t dia_shm(const avs_ctx* ctx) { return (size_t)2 * ctx->D * ctx->vg.numax * sizeof(double); }
+
+template <int D>
+avs_status dia_init(avs_dia* d) {
+  avs_ctx* ctx = d->ctx;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int nc = ctx->nc;
+  const unsigned gc = (unsigned)((nc + BLOCK - 1) / BLOCK);
+  k_dg_initrec<D><<<gc, BLOCK, 0, ctx->stream>>>(nc, d->gp, d->W[0], d->tp, d->bad);
+  CKL();
+  k_dg_target<D><<<nc, BLOCK, dia_shm(ctx), ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->tp, d->W[0], d->lam, 1,
+                                                           d->bad);
+  CKL();
+  k_dg_update<D><<<nc, BLOCK, dia_shm(ctx), ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, nullptr, nullptr, d->v[0], d->tp,
+                                                           d->lam, d->q, 1);
+  CKL();
+  return AVS_OK;
+}
+
+template <int D>
+avs_status dia_steps(avs_dia* d, int nsteps) {
+  avs_ctx* ctx = d->ctx;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK);
+  const size_t shm = dia_shm(ctx);
+  for (int s = 0; s < nsteps; ++s) {
+    const int c = d->cur;
+    k_dg_recon<D><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->h, d->v[c], d->fv, d->gp);
+    CKL();
+    k_dg_face<D><<<ctx->nf, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->gas, d->gp, ctx->h, d->fv, d->F,
+                                                       d->bad);
+    CKL();
+    k_dg_macro<D><<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, d->gp, ctx->dt, d->F, d->W[c], d->W[c ^ 1], d->q,
+                                                 d->tp, d->bad);
+    CKL();
+    k_dg_target<D><<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->tp, d->W[c ^ 1], d->lam, 0,
+                                                         d->bad);
+    CKL();
+    k_dg_update<D><<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->v[c], d->fv, d->v[c ^ 1], d->tp,
+                                                         d->lam, d->q, 0);
+    CKL();
+    d->cur ^= 1;
+  }
+  return AVS_OK;
+}
+
+template <int D>
+avs_status dia_criterion(avs_dia* d, double C1, double C2) {
+  avs_ctx* ctx = d->ctx;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const int nb = (L.n + BLOCK - 1) / BLOCK;
+  k_dg_crit_partial<D><<<dim3(nb, ctx->ngrp), BLOCK, 0, ctx->stream>>>(L, ctx->nc, d->v[d->cur], d->W[d->cur],
+                                                                      ctx->crit_part);
+  CKL();
+  k_crit_reduce<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->ngrp, ctx->crit_part, 0, ctx->probe_cc, ctx->probe_prim,
+                                                 ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
+  CKL();
+  k_resolve<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
+  CKL();
+  k_scan<<<1, BLOCK, 0, ctx->stream>>>(L.n, ctx->cnt, ctx->off);
+  CKL();
+  return AVS_OK;
+}
+
+template <int D>
+avs_status dia_remap_state(avs_dia* d) {
+  avs_ctx* ctx = d->ctx;
+  const Leaves Lo = ctx->leaves(ctx->lcur), Ln = ctx->leaves(ctx->lcur ^ 1);
+  const int c = d->cur;
+  k_dg_gather<D><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->nc, Lo, Ln, ctx->pkind, ctx->psrc, d->v[c], d->v[c ^ 1]);
+  CKL();
+  k_dg_close<D><<<ctx->nc, BLOCK, dia_shm(ctx), ctx->stream>>>(ctx->geo, Ln, ctx->vg, d->gp, d->W[c], d->v[c ^ 1],
+                                                               d->bad);
+  CKL();
+  // the heat fluxes of the remapped state for the next step's target
+  const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK);
+  k_dg_initrec<D><<<gc, BLOCK, 0, ctx->stream>>>(ctx->nc, d->gp, d->W[c], d->tp, d->bad);
+  CKL();
+  k_dg_heat<D><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, Ln, d->v[c ^ 1], d->tp, d->q);
+  CKL();
+  return AVS_OK;
+}
 }  // namespace
+
+extern "C" {
 
 avs_status avs_dia_bytes(const avs_ctx* ctx, int64_t max_leaves, size_t* bytes) {
   if (!ctx || !bytes) return fail(AVS_E_INVALID, "null argument");
@@ -1316,7 +1404,7 @@ avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim
   if (!out) return fail(AVS_E_INVALID, "out is null");
   *out = nullptr;
   if (avs_status st = guard(ctx)) return st;
-  if (ctx->D != 2 || ctx->prec != AVS_FP64) return fail(AVS_E_INVALID, "the diatomic path is two-dimensional FP64");
+  if (ctx->prec != AVS_FP64) return fail(AVS_E_INVALID, "the diatomic path is FP64");
   if (!gas || !prim0_host || !mem_dev) return fail(AVS_E_INVALID, "null argument");
   if (((uintptr_t)mem_dev & 255)) return fail(AVS_E_INVALID, "mem_dev must be 256-byte aligned");
   if (!(gas->Z_rot >= 1.0 && std::isfinite(gas->Z_rot)) || !(gas->delta > 0.0 && gas->delta <= 1.0) ||
@@ -1324,22 +1412,27 @@ avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim
     return fail(AVS_E_INVALID, "Rykov parameters: Z_rot >= 1, 0 < delta <= 1, finite omega_0 and omega_1");
   if (max_leaves < ctx->nleaf[ctx->lcur] || max_leaves > ctx->cap)
     return fail(AVS_E_INVALID, "max_leaves must lie between the current leaf count and the leaf capacity");
+  if (dia_shm(ctx) > 48 * 1024) return fail(AVS_E_INVALID, "velocity grid too fine for the diatomic tables");
   const size_t need = dia_layout(ctx, max_leaves, nullptr, nullptr);
   if (mem_bytes < need) return fail(AVS_E_INVALID, "mem region too small (%zu < %zu)", mem_bytes, need);
-  const int nc = ctx->nc;
+  const int nc = ctx->nc, D = ctx->D, NW = D + 3;
   const double R = ctx->gas.R;
-  std::vector<double> W0((size_t)nc * DG_N);
+  std::vector<double> W0((size_t)nc * NW);
   for (int i = 0; i < nc; ++i) {
-    const double* p = prim0_host + (size_t)i * 5;
-    const double rho = p[0], u0 = p[1], u1 = p[2], Tt = p[3], Tr = p[4];
-    if (!(rho > 0 && Tt > 0 && Tr > 0) || !std::isfinite(u0) || !std::isfinite(u1))
-      return fail(AVS_E_INVALID, "cell %d: non-physical initial state", i);
-    double* w = W0.data() + (size_t)i * DG_N;
+    const double* p = prim0_host + (size_t)i * NW;
+    const double rho = p[0], Tt = p[1 + D], Tr = p[2 + D];
+    double uu = 0.0;
+    bool fin = std::isfinite(rho) && std::isfinite(Tt) && std::isfinite(Tr);
+    for (int k = 0; k < D; ++k) {
+      fin = fin && std::isfinite(p[1 + k]);
+      uu += p[1 + k] * p[1 + k];
+    }
+    if (!(rho > 0 && Tt > 0 && Tr > 0) || !fin) return fail(AVS_E_INVALID, "cell %d: non-physical initial state", i);
+    double* w = W0.data() + (size_t)i * NW;
     w[0] = rho;
-    w[1] = rho * u0;
-    w[2] = rho * u1;
-    w[4] = rho * R * Tr;
-    w[3] = 0.5 * rho * (u0 * u0 + u1 * u1) + 1.5 * rho * R * Tt + w[4];
+    for (int k = 0; k < D; ++k) w[1 + k] = rho * p[1 + k];
+    w[2 + D] = rho * R * Tr;
+    w[1 + D] = 0.5 * rho * uu + 1.5 * rho * R * Tt + w[2 + D];
   }
   avs_dia* d = new avs_dia();
   d->ctx = ctx;
@@ -1348,20 +1441,13 @@ avs_status avs_dia_create(avs_ctx* ctx, const avs_rykov* gas, const double* prim
   d->gen = ctx->leaf_gen;
   d->max_leaves = max_leaves;
   const int badinit[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
-  const Leaves L = ctx->leaves(ctx->lcur);
-  auto fin = [&](avs_status st) { if (st) delete d; else *out = d; return st; };
+  auto done = [&](avs_status st) { if (st) delete d; else *out = d; return st; };
   if (hipMemcpyAsync(d->W[0], W0.data(), sizeof(double) * W0.size(), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
       hipMemcpyAsync(d->bad, badinit, sizeof badinit, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
-    return fin(fail(AVS_E_HIP, "upload of the diatomic state failed"));
-  const unsigned gc = (unsigned)((nc + BLOCK - 1) / BLOCK);
-  const size_t shm = (size_t)4 * ctx->vg.numax * sizeof(double);
-  if (shm > 48 * 1024) return fin(fail(AVS_E_INVALID, "velocity grid too fine for the diatomic tables"));
-  k_dg_initrec<<<gc, BLOCK, 0, ctx->stream>>>(nc, d->gp, d->W[0], d->tp, d->bad);
-  k_dg_target<<<nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->tp, d->W[0], d->lam, 1, d->bad);
-  k_dg_update<<<nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, nullptr, nullptr, d->v[0], d->tp, d->lam,
-                                               d->q, 1);
-  if (hipGetLastError() != hipSuccess) return fin(fail(AVS_E_HIP, "diatomic initialisation launch failed"));
-  return fin(dia_check_bad(d));
+    return done(fail(AVS_E_HIP, "upload of the diatomic state failed"));
+  avs_status st = D == 2 ? dia_init<2>(d) : dia_init<3>(d);
+  if (!st) st = dia_check_bad(d);
+  return done(st);
 }
 
 avs_status avs_dia_step(avs_dia* d, int32_t nsteps) {
@@ -1370,26 +1456,7 @@ avs_status avs_dia_step(avs_dia* d, int32_t nsteps) {
   if (avs_status st = guard(ctx)) return st;
   if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
   if (nsteps < 0) return fail(AVS_E_INVALID, "nsteps < 0");
-  const Leaves L = ctx->leaves(ctx->lcur);
-  const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK);
-  const size_t shm = (size_t)4 * ctx->vg.numax * sizeof(double);
-  for (int s = 0; s < nsteps; ++s) {
-    const int c = d->cur;
-    k_dg_recon<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->h, d->v[c], d->fv, d->gp);
-    CKL();
-    k_dg_face<<<ctx->nf, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->gas, d->gp, ctx->h, d->fv, d->F, d->bad);
-    CKL();
-    k_dg_macro<<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, d->gp, ctx->dt, d->F, d->W[c], d->W[c ^ 1], d->q,
-                                              d->tp, d->bad);
-    CKL();
-    k_dg_target<<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->tp, d->W[c ^ 1], d->lam, 0,
-                                                      d->bad);
-    CKL();
-    k_dg_update<<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->v[c], d->fv, d->v[c ^ 1], d->tp,
-                                                      d->lam, d->q, 0);
-    CKL();
-    d->cur ^= 1;
-  }
+  if (avs_status st = ctx->D == 2 ? dia_steps<2>(d, nsteps) : dia_steps<3>(d, nsteps)) return st;
   return dia_check_bad(d);
 }
 
@@ -1398,9 +1465,9 @@ avs_status avs_dia_get_state(avs_dia* d, double* vdf_host, double* W_host) {
   avs_ctx* ctx = d->ctx;
   if (avs_status st = guard(ctx)) return st;
   if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
-  const int n = ctx->nleaf[ctx->lcur], ld = ctx->ld[ctx->lcur];
+  const int n = ctx->nleaf[ctx->lcur], ld = ctx->ld[ctx->lcur], NW = ctx->D + 3;
   if (W_host)
-    CK(hipMemcpyAsync(W_host, d->W[d->cur], sizeof(double) * ctx->nc * DG_N, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipMemcpyAsync(W_host, d->W[d->cur], sizeof(double) * ctx->nc * NW, hipMemcpyDeviceToHost, ctx->stream));
   if (vdf_host) {
     for (int p = 0; p < 3; ++p)
       CK(hipMemcpy2DAsync(vdf_host + (size_t)p * ctx->nc * n, n * sizeof(double),
@@ -1418,18 +1485,7 @@ avs_status avs_dia_adapt(avs_dia* d, double C1, double C2, int8_t* flags_dev, in
   if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
   if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
   ctx->plan_valid = false;
-  const Leaves L = ctx->leaves(ctx->lcur);
-  const int nb = (L.n + BLOCK - 1) / BLOCK;
-  k_dg_crit_partial<<<dim3(nb, ctx->ngrp), BLOCK, 0, ctx->stream>>>(L, ctx->nc, d->v[d->cur], d->W[d->cur],
-                                                                   ctx->crit_part);
-  CKL();
-  k_crit_reduce<2><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->ngrp, ctx->crit_part, 0, ctx->probe_cc, ctx->probe_prim,
-                                                 ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
-  CKL();
-  k_resolve<2><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
-  CKL();
-  k_scan<<<1, BLOCK, 0, ctx->stream>>>(L.n, ctx->cnt, ctx->off);
-  CKL();
+  if (avs_status st = ctx->D == 2 ? dia_criterion<2>(d, C1, C2) : dia_criterion<3>(d, C1, C2)) return st;
   int64_t nn = 0;
   if (avs_status st = finish_plan(ctx, flags_dev, &nn, nullptr)) return st;
   if (n_new_host) *n_new_host = nn;
@@ -1447,22 +1503,12 @@ avs_status avs_dia_remap(avs_dia* d) {
   if (avs_status st = guard(ctx)) return st;
   if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
   if (!ctx->plan_valid) return fail(AVS_E_STATE, "no adaptation plan (call avs_dia_adapt first)");
-  const Leaves Lo = ctx->leaves(ctx->lcur), Ln = ctx->leaves(ctx->lcur ^ 1);
-  const int c = d->cur;
-  k_dg_gather<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->nc, Lo, Ln, ctx->pkind, ctx->psrc, d->v[c], d->v[c ^ 1]);
-  CKL();
-  const size_t shm = (size_t)4 * ctx->vg.numax * sizeof(double);
-  k_dg_close<<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, Ln, ctx->vg, d->gp, d->W[c], d->v[c ^ 1], d->bad);
-  CKL();
-  // the heat fluxes of the remapped state for the next step's target
-  const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK);
-  k_dg_initrec<<<gc, BLOCK, 0, ctx->stream>>>(ctx->nc, d->gp, d->W[c], d->tp, d->bad);
-  CKL();
-  k_dg_heat<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, Ln, d->v[c ^ 1], d->tp, d->q);
-  CKL();
+  if (avs_status st = ctx->D == 2 ? dia_remap_state<2>(d) : dia_remap_state<3>(d)) return st;
   // the context moves to the new leaves with its own (monatomic) state
   if (avs_status st = avs_remap(ctx, 0)) return st;
-  CK(hipMemcpyAsync(d->W[c ^ 1], d->W[c], sizeof(double) * ctx->nc * DG_N, hipMemcpyDeviceToDevice, ctx->stream));
+  const int c = d->cur;
+  CK(hipMemcpyAsync(d->W[c ^ 1], d->W[c], sizeof(double) * ctx->nc * (ctx->D + 3), hipMemcpyDeviceToDevice,
+                    ctx->stream));
   d->cur ^= 1;
   d->gen = ctx->leaf_gen;
   return dia_check_bad(d);

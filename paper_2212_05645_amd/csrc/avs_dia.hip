@@ -1,51 +1,74 @@
 // Explicit step of the Rykov diatomic model (Sec. 2.3 in its explicit limit
 // with the equilibrium of Eqs. GHR_equ, equ11-equ13 and the rotational
-// source of Eq. equ19), two-dimensional, FP64, on a fixed velocity tree.
-// Three reduced distributions per cell and leaf, [3][cell][leaf]: G, H (the
-// hidden translational degree of freedom) and R (rotational energy, two
-// degrees of freedom); five conserved variables (rho, rho U, rho E,
+// source of Eq. equ19), FP64, in 2-D and 3-D, and the adaptation of the
+// velocity tree it drives (Secs. 3.2-3.4).  Three reduced distributions per
+// cell and leaf, [3][cell][leaf]: G, H (the 3 - D hidden translational
+// degrees of freedom; identically zero in 3-D) and R (rotational energy,
+// two degrees of freedom); D + 3 conserved variables (rho, rho U, rho E,
 // rho E_rot).  One pass per stage, written for clarity rather than speed:
 //   k_dg_recon   limited least-squares reconstruction at x_f - xi h into the
 //                interface rows (boundary Maxwellian triples on incoming leaves)
 //   k_dg_face    interface moments, rotational and heat-flux relaxation over h,
 //                Rykov equilibrium, characteristic blend in place, flux F_f
 //   k_dg_macro   W* = W - dt/V sum sigma A F, point-implicit rotational exchange
-//   k_dg_target  closure coefficients of the Rykov target (5 x 5 system)
+//   k_dg_target  closure coefficients of the Rykov target ((D+3)^2 system)
 //   k_dg_update  flux divergence, relaxation, heat fluxes of phi^{n+1}
 // Part of the library's single translation unit, after avs_kernels.hip.
 
 namespace avs {
 
-constexpr int DG_N = 5;      // rho, rho U (2), rho E, rho E_rot
-constexpr int DG_NT = 12;    // target record: rho, U0, U1, T_t, T_r, qt0, qt1, qr0, qr1, dt/tau, E_rot target, T
+template <int D>
+struct Dg {
+  static constexpr int NW = D + 3;           // rho, rho U, rho E, rho E_rot
+  static constexpr int NQ = 2 * D;           // q_t, q_r
+  // record: rho, U[D], T_t, T_r, q_t[D], q_r[D], dt/tau, E_rot target, T
+  static constexpr int IT = 1 + D, IR = 2 + D, IQT = 3 + D, IQR = 3 + 2 * D, IDT = 3 + 3 * D, IER = 4 + 3 * D,
+                       IT0 = 5 + 3 * D, NT = 6 + 3 * D;
+  static constexpr int MAXF = Cfg<D>::MAXF;
+  static constexpr int NACC = NW * (1 + NW);   // moments of the base and of the NW closure directions
+};
 
 struct DiaGas {
   double R, Z, delta, omega0, omega1;
 };
 
+// rho (2 pi R T)^(-D/2)
+template <int D>
+__device__ __forceinline__ double dg_norm(double rho, double RT) {
+  return D == 2 ? rho / (2.0 * M_PI * RT) : rho * pow(2.0 * M_PI * RT, -0.5 * D);
+}
+
 // Rykov equilibrium triple at one leaf (c = xi - U), or, with t_only, the
-// translational part at (T_t, T_r) with zero heat fluxes.
-// gt and g are the Maxwellians at T_t and at T = (3 T_t + 2 T_r)/5.
-__device__ __forceinline__ void dg_equilibrium(const DiaGas& gp, double rho, const double (&c)[2], double Tt, double Tr,
+// translational part at (T_t, T_r) with zero heat fluxes; gt and g are the
+// Maxwellians at T_t and at T = (3 T_t + 2 T_r)/5.
+template <int D>
+__device__ __forceinline__ void dg_equilibrium(const DiaGas& gp, double rho, const double (&c)[D], double Tt, double Tr,
                                                const double* qt, const double* qr, bool t_only, double gt, double g,
                                                double& G, double& H, double& Rr) {
   const double R = gp.R;
   const double T = (3.0 * Tt + 2.0 * Tr) / 5.0;
-  const double c2 = c[0] * c[0] + c[1] * c[1];
+  double c2 = 0.0, cqt = 0.0, cqr = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) c2 += c[d] * c[d];
   const double RTt = R * Tt, RT = R * T;
+  const double hid = 3 - D;
   if (t_only) {
     G = gt;
-    H = RTt * gt;
+    H = hid * RTt * gt;
     Rr = R * Tr * gt;
     return;
   }
-  const double cqt = c[0] * qt[0] + c[1] * qt[1], cqr = c[0] * qr[0] + c[1] * qr[1];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    cqt += c[d] * qt[d];
+    cqr += c[d] * qr[d];
+  }
   const double pt = rho * RTt, p = rho * RT;
   const double at = cqt / (15.0 * pt * RTt), ar = gp.omega0 * cqt / (15.0 * p * RT);
-  const double Gt = gt * (1.0 + at * (c2 / RTt - 4.0));
-  const double Gr = g * (1.0 + ar * (c2 / RT - 4.0));
-  const double Ht = RTt * gt * (1.0 + at * (c2 / RTt - 2.0));
-  const double Hr = RT * g * (1.0 + ar * (c2 / RT - 2.0));
+  const double Gt = gt * (1.0 + at * (c2 / RTt - (D + 2.0)));
+  const double Gr = g * (1.0 + ar * (c2 / RT - (D + 2.0)));
+  const double Ht = hid * RTt * gt * (1.0 + at * (c2 / RTt - D));
+  const double Hr = hid * RT * g * (1.0 + ar * (c2 / RT - D));
   const double Rt = R * Tr * (Gt + (1.0 - gp.delta) * cqr / (pt * RTt) * gt);
   const double Rq = RT * (Gr + gp.omega1 * (1.0 - gp.delta) * cqr / (p * RT) * g);
   const double wt = 1.0 - 1.0 / gp.Z, wr = 1.0 / gp.Z;
@@ -56,43 +79,52 @@ __device__ __forceinline__ void dg_equilibrium(const DiaGas& gp, double rho, con
 
 // Separable per-axis tables of the Maxwellians at T_t and at T (the
 // half-finest grid carries every leaf centre), built by the whole block
-// from a record r = (rho, U0, U1, T_t, T_r, ...); followed by a barrier.
+// from a record r = (rho, U[D], T_t, T_r, ...); followed by a barrier.
+template <int D>
 __device__ __forceinline__ void dg_tables(const double* r, double R, const VGrid& vg, double* tabt, double* tabr,
                                           double* part, double* parr) {
   if (threadIdx.x == 0) {
-    const double Tt = r[3], T = (3.0 * r[3] + 2.0 * r[4]) / 5.0;
-    part[P_COEF] = r[0] / (2.0 * M_PI * R * Tt);
-    parr[P_COEF] = r[0] / (2.0 * M_PI * R * T);
-    for (int d = 0; d < 3; ++d) part[P_U + d] = parr[P_U + d] = d < 2 ? r[1 + d] : 0.0;
+    const double Tt = r[Dg<D>::IT], T = (3.0 * r[Dg<D>::IT] + 2.0 * r[Dg<D>::IR]) / 5.0;
+    part[P_COEF] = dg_norm<D>(r[0], R * Tt);
+    parr[P_COEF] = dg_norm<D>(r[0], R * T);
+    for (int d = 0; d < 3; ++d) part[P_U + d] = parr[P_U + d] = d < D ? r[1 + d] : 0.0;
     part[P_I2RT] = 0.5 / (R * Tt);
     parr[P_I2RT] = 0.5 / (R * T);
   }
   __syncthreads();
-  build_tab<2>(tabt, part, vg);
-  build_tab<2>(tabr, parr, vg);
+  build_tab<D>(tabt, part, vg);
+  build_tab<D>(tabr, parr, vg);
   __syncthreads();
 }
 
 // rho, U, T_t, T_r, T from W = (rho, rho U, rho E, rho E_rot).
-__device__ __forceinline__ bool dg_temps(const double* w, double R, double& rho, double (&U)[2], double& Tt, double& Tr,
+template <int D>
+__device__ __forceinline__ bool dg_temps(const double* w, double R, double& rho, double (&U)[D], double& Tt, double& Tr,
                                          double& T) {
   rho = w[0];
-  U[0] = w[1] / rho;
-  U[1] = w[2] / rho;
-  Tr = w[4] / (rho * R);
-  Tt = (w[3] - 0.5 * rho * (U[0] * U[0] + U[1] * U[1]) - w[4]) / (1.5 * rho * R);
+  double uu = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    U[d] = w[1 + d] / rho;
+    uu += U[d] * U[d];
+  }
+  Tr = w[2 + D] / (rho * R);
+  Tt = (w[1 + D] - 0.5 * rho * uu - w[2 + D]) / (1.5 * rho * R);
   T = (3.0 * Tt + 2.0 * Tr) / 5.0;
   return rho > 0.0 && Tt > 0.0 && Tr > 0.0;
 }
 
 // moments (rho, rho U, rho E, rho E_rot) contribution of one leaf
-__device__ __forceinline__ void dg_mom(double* m, double A, const double (&xi)[2], double G, double H, double Rr) {
-  const double xi2 = xi[0] * xi[0] + xi[1] * xi[1];
+template <int D>
+__device__ __forceinline__ void dg_mom(double* m, double A, const double (&xi)[D], double G, double H, double Rr) {
+  double xi2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
   m[0] += A * G;
-  m[1] += A * G * xi[0];
-  m[2] += A * G * xi[1];
-  m[3] += A * (0.5 * (xi2 * G + H) + Rr);
-  m[4] += A * Rr;
+#pragma unroll
+  for (int d = 0; d < D; ++d) m[1 + d] += A * G * xi[d];
+  m[1 + D] += A * (0.5 * (xi2 * G + H) + Rr);
+  m[2 + D] += A * Rr;
 }
 
 // Venkatakrishnan psi for one face, the same branches as its definition
@@ -108,9 +140,10 @@ __device__ __forceinline__ double dg_psi(double d1, double d2, double eps2) {
   return u * (u + 2.0) / (u * u + u + 2.0);
 }
 
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, const double* __restrict__ vin,
                                                    double* __restrict__ fv, DiaGas gp) {
-  constexpr int MAXF = MAXF2;
+  constexpr int MAXF = Dg<D>::MAXF;
   const int i = blockIdx.x;
   const int ns = g.nslot[i];
   const size_t cs = (size_t)g.nc * L.ld, fs = (size_t)g.nf * L.ld;
@@ -126,10 +159,10 @@ __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, c
     nb[s] = (size_t)(j >= 0 ? j : i) * L.ld;
   }
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[2], A;
-    int u[2];
-    leaf_load<2>(L, k, xi, A, u);
-    double ph[3], gr[3][2], pmax[3], pmin[3], nv[MAXF][3];
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    double ph[3], gr[3][D], pmax[3], pmin[3], nv[MAXF][3];
 #pragma unroll
     for (int p = 0; p < 3; ++p) ph[p] = vin[p * cs + (size_t)i * L.ld + k];
 #pragma unroll
@@ -138,7 +171,8 @@ __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, c
       for (int p = 0; p < 3; ++p) nv[s][p] = vin[p * cs + nb[s] + k];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-      gr[p][0] = gr[p][1] = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) gr[p][d] = 0.0;
       pmax[p] = pmin[p] = ph[p];
     }
 #pragma unroll
@@ -148,54 +182,70 @@ __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, c
       for (int p = 0; p < 3; ++p) {
         const double v = nv[s][p];
         const double dv = v - ph[p];
-        gr[p][0] += dv * g.s_lsq[(size_t)(i * MAXF + s) * 2];
-        gr[p][1] += dv * g.s_lsq[(size_t)(i * MAXF + s) * 2 + 1];
+#pragma unroll
+        for (int d = 0; d < D; ++d) gr[p][d] += dv * g.s_lsq[(size_t)(i * MAXF + s) * D + d];
         pmax[p] = fmax(pmax[p], v);
         pmin[p] = fmin(pmin[p], v);
       }
     }
     const double eps2 = g.eps2[i];
-    double lg[3][2];
+    double lg[3][D];
+#pragma unroll
     for (int p = 0; p < 3; ++p) {
       double lim = ns > 0 ? INFINITY : 1.0;
       for (int s = 0; s < ns; ++s) {
-        const double* d = g.s_d + (size_t)(i * MAXF + s) * 2;
-        const double d2 = gr[p][0] * d[0] + gr[p][1] * d[1];
+        const double* dd = g.s_d + (size_t)(i * MAXF + s) * D;
+        double d2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) d2 += gr[p][d] * dd[d];
         const double d1 = d2 > 0.0 ? pmax[p] - ph[p] : pmin[p] - ph[p];
         lim = fmin(lim, dg_psi(d1, d2, eps2));
       }
-      lg[p][0] = lim * gr[p][0];
-      lg[p][1] = lim * gr[p][1];
+#pragma unroll
+      for (int d = 0; d < D; ++d) lg[p][d] = lim * gr[p][d];
     }
     for (int s = 0; s < ns; ++s) {
       const int f = g.s_face[i * MAXF + s];
       const double sig = g.s_sig[i * MAXF + s];
-      const double sn = normal_speed<2>(xi, g.f_nrm + (size_t)f * 2);
+      const double sn = normal_speed<D>(xi, g.f_nrm + (size_t)f * D);
       const bool upwind = sig > 0.0 ? sn >= 0.0 : sn < 0.0;
       const int Rc = g.f_R[f];
       const size_t o = (size_t)f * L.ld + k;
       if (upwind) {
-        const double* d = g.s_d + (size_t)(i * MAXF + s) * 2;
-        const double r0 = d[0] - xi[0] * h, r1 = d[1] - xi[1] * h;
-        for (int p = 0; p < 3; ++p) fv[p * fs + o] = ph[p] + (lg[p][0] * r0 + lg[p][1] * r1);
+        const double* dd = g.s_d + (size_t)(i * MAXF + s) * D;
+        double r[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) r[d] = dd[d] - xi[d] * h;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          double x = 0.0;
+#pragma unroll
+          for (int d = 0; d < D; ++d) x += lg[p][d] * r[d];
+          fv[p * fs + o] = ph[p] + x;
+        }
       } else if (Rc < 0) {
         // incoming leaf of a boundary face: the equilibrium triple of the
         // wall (unit density, scaled by the wall density later) or of the far field
         const int b = -1 - Rc;
-        const double* st = g.bc_prim + (size_t)b * 4;
+        const double* st = g.bc_prim + (size_t)b * (D + 2);
         const double rho = g.bc_kind[b] == 0 ? 1.0 : st[0];
-        const double c[2] = {xi[0] - st[1], xi[1] - st[2]};
-        const double RT = gp.R * st[3];
-        const double gv = rho / (2.0 * M_PI * RT) * exp(-(c[0] * c[0] + c[1] * c[1]) / (2.0 * RT));
+        double c2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const double c = xi[d] - st[1 + d];
+          c2 += c * c;
+        }
+        const double RT = gp.R * st[1 + D];
+        const double gv = dg_norm<D>(rho, RT) * exp(-c2 / (2.0 * RT));
         fv[o] = gv;
-        fv[fs + o] = RT * gv;
+        fv[fs + o] = (3 - D) * RT * gv;
         fv[2 * fs + o] = RT * gv;
       }
     }
   }
 }
 
-// block sum of n doubles per thread into red (LDS), result in red[0..n)
+// block sum of NN doubles per thread; every thread gets the sums
 template <int NN>
 __device__ __forceinline__ void dg_sum(double* v, double* red) {
   for (int m = 0; m < NN; ++m) {
@@ -214,109 +264,126 @@ __device__ __forceinline__ void dg_sum(double* v, double* red) {
   __syncthreads();
 }
 
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, VGrid vg, GasP vgas, DiaGas gp, double h,
                                                   double* __restrict__ fv, double* __restrict__ F, int* __restrict__ bad) {
+  using C = Dg<D>;
+  constexpr int NW = C::NW;
   extern __shared__ double lds_d[];
   __shared__ double red[(BLOCK / 64 + 1) * 8];
-  __shared__ double rec[16], part[NPAR], parr[NPAR];
+  __shared__ double rec[C::NT], part[NPAR], parr[NPAR];
   const int f = blockIdx.x;
   const int Rc = g.f_R[f];
   const size_t fs = (size_t)g.nf * L.ld;
-  const double n[2] = {g.f_nrm[(size_t)f * 2], g.f_nrm[(size_t)f * 2 + 1]};
+  double n[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
   double* row0 = fv + (size_t)f * L.ld;
   if (Rc >= 0) {
-    double m[5] = {0, 0, 0, 0, 0};
+    double m[NW];
+    for (int t = 0; t < NW; ++t) m[t] = 0.0;
     for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-      double xi[2], A;
-      int u[2];
-      leaf_load<2>(L, k, xi, A, u);
-      dg_mom(m, A, xi, row0[k], row0[fs + k], row0[2 * fs + k]);
+      double xi[D], A;
+      int u[D];
+      leaf_load<D>(L, k, xi, A, u);
+      dg_mom<D>(m, A, xi, row0[k], row0[fs + k], row0[2 * fs + k]);
     }
-    dg_sum<5>(m, red);
-    double rho, U[2], Ttb, Trb, T;
-    const bool ok = dg_temps(m, gp.R, rho, U, Ttb, Trb, T);
-    double q[4] = {0, 0, 0, 0};
+    dg_sum<NW>(m, red);
+    double rho, U[D], Ttb, Trb, T;
+    const bool ok = dg_temps<D>(m, gp.R, rho, U, Ttb, Trb, T);
+    double q[C::NQ];
+    for (int t = 0; t < C::NQ; ++t) q[t] = 0.0;
     for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-      double xi[2], A;
-      int u[2];
-      leaf_load<2>(L, k, xi, A, u);
-      const double c0 = xi[0] - U[0], c1 = xi[1] - U[1], c2 = c0 * c0 + c1 * c1;
+      double xi[D], A;
+      int u[D];
+      leaf_load<D>(L, k, xi, A, u);
+      double c[D], c2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        c[d] = xi[d] - U[d];
+        c2 += c[d] * c[d];
+      }
       const double Gv = row0[k], Hv = row0[fs + k], Rv = row0[2 * fs + k];
       const double et = A * 0.5 * (c2 * Gv + Hv), er = A * Rv;
-      q[0] += et * c0;
-      q[1] += et * c1;
-      q[2] += er * c0;
-      q[3] += er * c1;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        q[d] += et * c[d];
+        q[D + d] += er * c[d];
+      }
     }
-    dg_sum<4>(q, red);
+    dg_sum<C::NQ>(q, red);
     if (threadIdx.x == 0) {
       if (!ok) atomicMin(bad, g.nc + f);
       const double tf = ok ? tau_of(rho, Ttb, vgas) : 1.0;
       const double kz = h / (gp.Z * tf);
-      const double ER = (m[4] + kz * (rho * gp.R * T)) / (1.0 + kz);
+      const double ER = (m[2 + D] + kz * (rho * gp.R * T)) / (1.0 + kz);
       const double Tr = ER / (rho * gp.R);
       const double Tt = Ttb + (2.0 / 3.0) * (Trb - Tr);
       const double lt = (1.0 - 1.0 / gp.Z) / 3.0 + gp.omega0 / (3.0 * gp.Z);
       const double lr = (1.0 - gp.delta) * ((1.0 - 1.0 / gp.Z) * Tr / Tt + gp.omega1 / gp.Z);
       rec[0] = rho;
-      rec[1] = U[0];
-      rec[2] = U[1];
-      rec[3] = Tt;
-      rec[4] = Tr;
-      rec[5] = q[0] / (1.0 + (1.0 - lt) * h / tf);
-      rec[6] = q[1] / (1.0 + (1.0 - lt) * h / tf);
-      rec[7] = q[2] / (1.0 + (1.0 - lr) * h / tf);
-      rec[8] = q[3] / (1.0 + (1.0 - lr) * h / tf);
-      rec[9] = tf / (tf + h);
-      rec[10] = h / (tf + h);
+      for (int d = 0; d < D; ++d) {
+        rec[1 + d] = U[d];
+        rec[C::IQT + d] = q[d] / (1.0 + (1.0 - lt) * h / tf);
+        rec[C::IQR + d] = q[D + d] / (1.0 + (1.0 - lr) * h / tf);
+      }
+      rec[C::IT] = Tt;
+      rec[C::IR] = Tr;
+      rec[C::IDT] = tf / (tf + h);      // blend weights a, b in the dt/tau and E_rot slots
+      rec[C::IER] = h / (tf + h);
     }
     __syncthreads();
     double* tabt = lds_d;
-    double* tabr = lds_d + 2 * vg.numax;
-    dg_tables(rec, gp.R, vg, tabt, tabr, part, parr);
-    double fl[5] = {0, 0, 0, 0, 0};
+    double* tabr = lds_d + D * vg.numax;
+    dg_tables<D>(rec, gp.R, vg, tabt, tabr, part, parr);
+    const double a = rec[C::IDT], b = rec[C::IER];
+    double fl[NW];
+    for (int t = 0; t < NW; ++t) fl[t] = 0.0;
     for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-      double xi[2], A;
-      int u[2];
-      leaf_load<2>(L, k, xi, A, u);
-      const double c[2] = {xi[0] - rec[1], xi[1] - rec[2]};
+      double xi[D], A;
+      int u[D];
+      leaf_load<D>(L, k, xi, A, u);
+      double c[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) c[d] = xi[d] - rec[1 + d];
       double Ge, He, Re;
-      dg_equilibrium(gp, rec[0], c, rec[3], rec[4], rec + 5, rec + 7, false, maxw<2>(part, tabt, vg.numax, u),
-                     maxw<2>(parr, tabr, vg.numax, u), Ge, He, Re);
-      const double Gv = rec[9] * row0[k] + rec[10] * Ge;
-      const double Hv = rec[9] * row0[fs + k] + rec[10] * He;
-      const double Rv = rec[9] * row0[2 * fs + k] + rec[10] * Re;
+      dg_equilibrium<D>(gp, rec[0], c, rec[C::IT], rec[C::IR], rec + C::IQT, rec + C::IQR, false,
+                        maxw<D>(part, tabt, vg.numax, u), maxw<D>(parr, tabr, vg.numax, u), Ge, He, Re);
+      const double Gv = a * row0[k] + b * Ge;
+      const double Hv = a * row0[fs + k] + b * He;
+      const double Rv = a * row0[2 * fs + k] + b * Re;
       row0[k] = Gv;
       row0[fs + k] = Hv;
       row0[2 * fs + k] = Rv;
-      dg_mom(fl, A * normal_speed<2>(xi, n), xi, Gv, Hv, Rv);
+      dg_mom<D>(fl, A * normal_speed<D>(xi, n), xi, Gv, Hv, Rv);
     }
-    dg_sum<5>(fl, red);
-    if (threadIdx.x < 5) F[(size_t)f * 5 + threadIdx.x] = fl[threadIdx.x];
+    dg_sum<NW>(fl, red);
+    if (threadIdx.x < NW) F[(size_t)f * NW + threadIdx.x] = fl[threadIdx.x];
     return;
   }
-  const int b = -1 - Rc;
-  const bool wall = g.bc_kind[b] == 0;
+  const int bc = -1 - Rc;
+  const bool wall = g.bc_kind[bc] == 0;
   double sc = 1.0;
   if (wall) {
     double nd[2] = {0.0, 0.0};
     for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-      double xi[2], A;
-      int u[2];
-      leaf_load<2>(L, k, xi, A, u);
-      const double s = normal_speed<2>(xi, n);
+      double xi[D], A;
+      int u[D];
+      leaf_load<D>(L, k, xi, A, u);
+      const double s = normal_speed<D>(xi, n);
       if (s > 0.0) nd[0] += A * s * row0[k];
       if (s < 0.0) nd[1] += A * (-s) * row0[k];
     }
     dg_sum<2>(nd, red);
     sc = nd[0] / nd[1];
   }
-  double fl[5] = {0, 0, 0, 0, 0};
+  double fl[NW];
+  for (int t = 0; t < NW; ++t) fl[t] = 0.0;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[2], A;
-    int u[2];
-    leaf_load<2>(L, k, xi, A, u);
-    const double s = normal_speed<2>(xi, n);
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    const double s = normal_speed<D>(xi, n);
     double Gv = row0[k], Hv = row0[fs + k], Rv = row0[2 * fs + k];
     if (wall && s < 0.0) {
       Gv *= sc;
@@ -326,135 +393,178 @@ __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, VGrid vg, Ga
       row0[fs + k] = Hv;
       row0[2 * fs + k] = Rv;
     }
-    dg_mom(fl, A * s, xi, Gv, Hv, Rv);
+    dg_mom<D>(fl, A * s, xi, Gv, Hv, Rv);
   }
-  dg_sum<5>(fl, red);
-  if (threadIdx.x < 5) F[(size_t)f * 5 + threadIdx.x] = fl[threadIdx.x];
+  dg_sum<NW>(fl, red);
+  if (threadIdx.x < NW) F[(size_t)f * NW + threadIdx.x] = fl[threadIdx.x];
 }
 
 // W* = W - dt/V sum sigma A F; rotational exchange point-implicit with tau
 // of W*; target record of W^{n+1} with the heat fluxes q of phi^n.
+template <int D>
 __global__ void k_dg_macro(Geo g, GasP vgas, DiaGas gp, double dt, const double* __restrict__ F,
                            const double* __restrict__ W, double* __restrict__ Wn, const double* __restrict__ q,
                            double* __restrict__ tp, int* __restrict__ bad) {
-  constexpr int MAXF = MAXF2;
+  using C = Dg<D>;
+  constexpr int MAXF = C::MAXF, NW = C::NW;
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= g.nc) return;
-  double Fs[5] = {0, 0, 0, 0, 0};
+  double Fs[NW];
+  for (int m = 0; m < NW; ++m) Fs[m] = 0.0;
   for (int s = 0; s < g.nslot[i]; ++s) {
     const int f = g.s_face[i * MAXF + s];
     const double sa = g.s_sigA[i * MAXF + s];
-    for (int m = 0; m < 5; ++m) Fs[m] += sa * F[(size_t)f * 5 + m];
+    for (int m = 0; m < NW; ++m) Fs[m] += sa * F[(size_t)f * NW + m];
   }
-  double w[5];
+  double w[NW];
   const double dtv = g.dtv[i];
-  for (int m = 0; m < 5; ++m) w[m] = W[(size_t)i * 5 + m] - dtv * Fs[m];
-  double rho, U[2], Tt, Tr, T;
-  if (!dg_temps(w, gp.R, rho, U, Tt, Tr, T)) {
+  for (int m = 0; m < NW; ++m) w[m] = W[(size_t)i * NW + m] - dtv * Fs[m];
+  double rho, U[D], Tt, Tr, T;
+  if (!dg_temps<D>(w, gp.R, rho, U, Tt, Tr, T)) {
     atomicMin(bad, i);
     rho = 1.0; Tt = Tr = T = 1.0;
   }
   const double tt = tau_of(rho, Tt, vgas);
   const double k = dt / (gp.Z * tt);
-  w[4] = (w[4] + k * (rho * gp.R * T)) / (1.0 + k);
-  for (int m = 0; m < 5; ++m) Wn[(size_t)i * 5 + m] = w[m];
-  dg_temps(w, gp.R, rho, U, Tt, Tr, T);
-  double* r = tp + (size_t)i * DG_NT;
+  w[2 + D] = (w[2 + D] + k * (rho * gp.R * T)) / (1.0 + k);
+  for (int m = 0; m < NW; ++m) Wn[(size_t)i * NW + m] = w[m];
+  dg_temps<D>(w, gp.R, rho, U, Tt, Tr, T);
+  double* r = tp + (size_t)i * C::NT;
   r[0] = rho;
-  r[1] = U[0];
-  r[2] = U[1];
-  r[3] = Tt;
-  r[4] = Tr;
-  for (int d = 0; d < 4; ++d) r[5 + d] = q[(size_t)i * 4 + d];
-  r[9] = dt / tt;
-  r[10] = (1.0 - 1.0 / gp.Z) * w[4] + rho * gp.R * T / gp.Z;
-  r[11] = T;
+  for (int d = 0; d < D; ++d) r[1 + d] = U[d];
+  r[C::IT] = Tt;
+  r[C::IR] = Tr;
+  for (int d = 0; d < C::NQ; ++d) r[C::IQT + d] = q[(size_t)i * C::NQ + d];
+  r[C::IDT] = dt / tt;
+  r[C::IER] = (1.0 - 1.0 / gp.Z) * w[2 + D] + rho * gp.R * T / gp.Z;
+  r[C::IT0] = T;
+}
+
+// Closure accumulators of one leaf: the base triple's moments, then those
+// of the D + 3 directions (1, c, |c|^2) x (g, (3-D) R T g, R T g) at T and
+// (0, 0, R T g).
+template <int D>
+__device__ __forceinline__ void dg_close_acc(double* acc, double A, const double (&xi)[D], const double (&c)[D],
+                                             double RT, double gv, double G, double H, double Rr) {
+  constexpr int NW = Dg<D>::NW;
+  dg_mom<D>(acc, A, xi, G, H, Rr);
+  double c2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) c2 += c[d] * c[d];
+  const double hid = 3 - D;
+  dg_mom<D>(acc + NW, A, xi, gv, hid * RT * gv, RT * gv);
+#pragma unroll
+  for (int d = 0; d < D; ++d) dg_mom<D>(acc + NW * (2 + d), A, xi, c[d] * gv, hid * RT * c[d] * gv, RT * c[d] * gv);
+  dg_mom<D>(acc + NW * (2 + D), A, xi, c2 * gv, hid * RT * c2 * gv, RT * c2 * gv);
+  dg_mom<D>(acc + NW * (3 + D), A, xi, 0.0, 0.0, RT * gv);
+}
+
+// Reduce the closure accumulators and solve J lambda = target - M[base].
+template <int D>
+__device__ __forceinline__ void dg_close_solve(double* acc, double* red, double* Jm, double* bv, double* xv,
+                                               const double* target, double* lam_out, int i, int* bad) {
+  constexpr int NW = Dg<D>::NW, NA = Dg<D>::NACC;
+  for (int g0 = 0; g0 < NA; g0 += 8) {
+    double v[8];
+    for (int m = 0; m < 8; ++m) v[m] = g0 + m < NA ? acc[g0 + m] : 0.0;
+    dg_sum<8>(v, red);
+    for (int m = 0; m < 8; ++m)
+      if (g0 + m < NA) acc[g0 + m] = v[m];
+  }
+  if (threadIdx.x == 0) {
+    for (int l = 0; l < NW; ++l) {
+      for (int e = 0; e < NW; ++e) Jm[l * NW + e] = acc[NW + NW * e + l];
+      bv[l] = target[l] - acc[l];
+    }
+    if (!solve_small<NW>(Jm, bv, xv)) atomicMin(bad, i);
+    if (lam_out)
+      for (int e = 0; e < NW; ++e) lam_out[e] = xv[e];
+  }
+  __syncthreads();
 }
 
 // Closure coefficients: the Rykov target (or, with init, the translational
 // part with zero heat fluxes) plus sum_m lambda_m e_m has the moments
-// target = (rho, rho U, rho E, E_rot target) of W; e_m = (1, c, |c|^2) x
-// (g, R T g, R T g) at T and (0, 0, R T g).
+// (rho, rho U, rho E, E_rot target) of W.
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_target(Geo g, Leaves L, VGrid vg, DiaGas gp, const double* __restrict__ tp,
                                                     const double* __restrict__ Wt, double* __restrict__ lam, int init,
                                                     int* __restrict__ bad) {
+  using C = Dg<D>;
+  constexpr int NW = C::NW;
   extern __shared__ double lds_d[];
-  __shared__ double red[(BLOCK / 64 + 1) * 32];
-  __shared__ double Jm[25], bv[5], xv[5], part[NPAR], parr[NPAR];
+  __shared__ double red[(BLOCK / 64 + 1) * 8];
+  __shared__ double Jm[NW * NW], bv[NW], xv[NW], part[NPAR], parr[NPAR], tg[NW];
   const int i = blockIdx.x;
-  const double* r = tp + (size_t)i * DG_NT;
+  const double* r = tp + (size_t)i * C::NT;
   double* tabt = lds_d;
-  double* tabr = lds_d + 2 * vg.numax;
-  dg_tables(r, gp.R, vg, tabt, tabr, part, parr);
-  const double rho = r[0], U[2] = {r[1], r[2]}, Tt = r[3], Tr = r[4], T = r[11];
-  const double RT = gp.R * T;
-  double acc[30];
-  for (int m = 0; m < 30; ++m) acc[m] = 0.0;
+  double* tabr = lds_d + D * vg.numax;
+  if (threadIdx.x < NW)
+    tg[threadIdx.x] = (threadIdx.x < 2 + D || init) ? Wt[(size_t)i * NW + threadIdx.x] : r[C::IER];
+  dg_tables<D>(r, gp.R, vg, tabt, tabr, part, parr);
+  const double rho = r[0], Tt = r[C::IT], Tr = r[C::IR], RT = gp.R * r[C::IT0];
+  double acc[C::NACC];
+  for (int m = 0; m < C::NACC; ++m) acc[m] = 0.0;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[2], A;
-    int u[2];
-    leaf_load<2>(L, k, xi, A, u);
-    const double c[2] = {xi[0] - U[0], xi[1] - U[1]};
-    const double gv = maxw<2>(parr, tabr, vg.numax, u);
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    double c[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) c[d] = xi[d] - r[1 + d];
+    const double gv = maxw<D>(parr, tabr, vg.numax, u);
     double Ge, He, Re;
-    dg_equilibrium(gp, rho, c, Tt, Tr, r + 5, r + 7, init != 0, maxw<2>(part, tabt, vg.numax, u), gv, Ge, He, Re);
-    dg_mom(acc, A, xi, Ge, He, Re);
-    const double bs[4] = {1.0, c[0], c[1], c[0] * c[0] + c[1] * c[1]};
-    for (int e = 0; e < 4; ++e) dg_mom(acc + 5 + 5 * e, A, xi, bs[e] * gv, RT * bs[e] * gv, RT * bs[e] * gv);
-    dg_mom(acc + 25, A, xi, 0.0, 0.0, RT * gv);
+    dg_equilibrium<D>(gp, rho, c, Tt, Tr, r + C::IQT, r + C::IQR, init != 0, maxw<D>(part, tabt, vg.numax, u), gv,
+                      Ge, He, Re);
+    dg_close_acc<D>(acc, A, xi, c, RT, gv, Ge, He, Re);
   }
-  // reduce 30 sums in groups of 8 (the LDS buffer holds 32 per wave)
-  for (int g0 = 0; g0 < 30; g0 += 8) {
-    double v[8];
-    for (int m = 0; m < 8; ++m) v[m] = g0 + m < 30 ? acc[g0 + m] : 0.0;
-    dg_sum<8>(v, red);
-    for (int m = 0; m < 8; ++m)
-      if (g0 + m < 30) acc[g0 + m] = v[m];
-  }
-  if (threadIdx.x == 0) {
-    for (int l = 0; l < 5; ++l) {
-      for (int e = 0; e < 5; ++e) Jm[l * 5 + e] = acc[5 + 5 * e + l];
-      const double tgt = l < 4 ? Wt[(size_t)i * 5 + l] : (init ? Wt[(size_t)i * 5 + 4] : r[10]);
-      bv[l] = tgt - acc[l];
-    }
-    if (!solve_small<5>(Jm, bv, xv)) atomicMin(bad, i);
-    for (int e = 0; e < 5; ++e) lam[(size_t)i * 5 + e] = xv[e];
-  }
+  dg_close_solve<D>(acc, red, Jm, bv, xv, tg, lam + (size_t)i * NW, i, bad);
 }
 
 // phi^{n+1} = (phi^n + dt/tau g~ - dt/V sum sigma A xi.n phi_f) / (1 + dt/tau),
 // or with init the closed initial state; heat fluxes of the result about U.
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, DiaGas gp, const double* __restrict__ vin,
                                                     const double* __restrict__ fv, double* __restrict__ vout,
                                                     const double* __restrict__ tp, const double* __restrict__ lam,
                                                     double* __restrict__ q, int init) {
-  constexpr int MAXF = MAXF2;
+  using C = Dg<D>;
+  constexpr int MAXF = C::MAXF, NW = C::NW;
   extern __shared__ double lds_d[];
   __shared__ double red[(BLOCK / 64 + 1) * 8];
   __shared__ double part[NPAR], parr[NPAR];
   const int i = blockIdx.x;
-  const double* r = tp + (size_t)i * DG_NT;
+  const double* r = tp + (size_t)i * C::NT;
   double* tabt = lds_d;
-  double* tabr = lds_d + 2 * vg.numax;
-  dg_tables(r, gp.R, vg, tabt, tabr, part, parr);
-  const double rho = r[0], U[2] = {r[1], r[2]}, Tt = r[3], Tr = r[4], T = r[11], dtt = r[9];
-  const double RT = gp.R * T, dtv = g.dtv[i];
-  double la[5];
-  for (int e = 0; e < 5; ++e) la[e] = lam[(size_t)i * 5 + e];
+  double* tabr = lds_d + D * vg.numax;
+  dg_tables<D>(r, gp.R, vg, tabt, tabr, part, parr);
+  const double rho = r[0], Tt = r[C::IT], Tr = r[C::IR], dtt = r[C::IDT];
+  const double RT = gp.R * r[C::IT0], dtv = g.dtv[i], hid = 3 - D;
+  double la[NW];
+  for (int e = 0; e < NW; ++e) la[e] = lam[(size_t)i * NW + e];
   const int ns = g.nslot[i];
   const size_t cs = (size_t)g.nc * L.ld, fs = (size_t)g.nf * L.ld;
-  double qa[4] = {0, 0, 0, 0};
+  double qa[C::NQ];
+  for (int t = 0; t < C::NQ; ++t) qa[t] = 0.0;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[2], A;
-    int u[2];
-    leaf_load<2>(L, k, xi, A, u);
-    const double c[2] = {xi[0] - U[0], xi[1] - U[1]};
-    const double c2 = c[0] * c[0] + c[1] * c[1];
-    const double gv = maxw<2>(parr, tabr, vg.numax, u);
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    double c[D], c2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      c[d] = xi[d] - r[1 + d];
+      c2 += c[d] * c[d];
+    }
+    const double gv = maxw<D>(parr, tabr, vg.numax, u);
     double Ge, He, Re;
-    dg_equilibrium(gp, rho, c, Tt, Tr, r + 5, r + 7, init != 0, maxw<2>(part, tabt, vg.numax, u), gv, Ge, He, Re);
-    const double poly = la[0] + la[1] * c[0] + la[2] * c[1] + la[3] * c2;
-    const double tg[3] = {Ge + poly * gv, He + poly * RT * gv, Re + poly * RT * gv + la[4] * RT * gv};
+    dg_equilibrium<D>(gp, rho, c, Tt, Tr, r + C::IQT, r + C::IQR, init != 0, maxw<D>(part, tabt, vg.numax, u), gv,
+                      Ge, He, Re);
+    double poly = la[0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) poly += la[1 + d] * c[d];
+    poly += la[1 + D] * c2;
+    const double tg[3] = {Ge + poly * gv, He + poly * hid * RT * gv, Re + poly * RT * gv + la[2 + D] * RT * gv};
     double nv[3];
     if (init) {
       for (int p = 0; p < 3; ++p) nv[p] = tg[p];
@@ -462,7 +572,7 @@ __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, 
       double div[3] = {0, 0, 0};
       for (int s = 0; s < ns; ++s) {
         const int f = g.s_face[i * MAXF + s];
-        const double w = g.s_sigA[i * MAXF + s] * normal_speed<2>(xi, g.f_nrm + (size_t)f * 2);
+        const double w = g.s_sigA[i * MAXF + s] * normal_speed<D>(xi, g.f_nrm + (size_t)f * D);
         for (int p = 0; p < 3; ++p) div[p] += w * fv[p * fs + (size_t)f * L.ld + k];
       }
       for (int p = 0; p < 3; ++p)
@@ -470,56 +580,68 @@ __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, 
     }
     for (int p = 0; p < 3; ++p) vout[p * cs + (size_t)i * L.ld + k] = nv[p];
     const double et = A * 0.5 * (c2 * nv[0] + nv[1]), er = A * nv[2];
-    qa[0] += et * c[0];
-    qa[1] += et * c[1];
-    qa[2] += er * c[0];
-    qa[3] += er * c[1];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      qa[d] += et * c[d];
+      qa[D + d] += er * c[d];
+    }
   }
-  dg_sum<4>(qa, red);
-  if (threadIdx.x < 4) q[(size_t)i * 4 + threadIdx.x] = qa[threadIdx.x];
+  dg_sum<C::NQ>(qa, red);
+  if (threadIdx.x < C::NQ) q[(size_t)i * C::NQ + threadIdx.x] = qa[threadIdx.x];
 }
 
-// Initial target record from W (no exchange, zero heat fluxes).
+// Record from W (no exchange, zero heat fluxes): the initial state and the
+// heat fluxes after a remap.
+template <int D>
 __global__ void k_dg_initrec(int nc, DiaGas gp, const double* __restrict__ W, double* __restrict__ tp,
                              int* __restrict__ bad) {
+  using C = Dg<D>;
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= nc) return;
-  double rho, U[2], Tt, Tr, T;
-  if (!dg_temps(W + (size_t)i * 5, gp.R, rho, U, Tt, Tr, T)) atomicMin(bad, i);
-  double* r = tp + (size_t)i * DG_NT;
+  double rho, U[D], Tt, Tr, T;
+  if (!dg_temps<D>(W + (size_t)i * C::NW, gp.R, rho, U, Tt, Tr, T)) atomicMin(bad, i);
+  double* r = tp + (size_t)i * C::NT;
   r[0] = rho;
-  r[1] = U[0];
-  r[2] = U[1];
-  r[3] = Tt;
-  r[4] = Tr;
-  for (int d = 0; d < 4; ++d) r[5 + d] = 0.0;
-  r[9] = 0.0;
-  r[10] = W[(size_t)i * 5 + 4];
-  r[11] = T;
+  for (int d = 0; d < D; ++d) r[1 + d] = U[d];
+  r[C::IT] = Tt;
+  r[C::IR] = Tr;
+  for (int d = 0; d < C::NQ; ++d) r[C::IQT + d] = 0.0;
+  r[C::IDT] = 0.0;
+  r[C::IER] = W[(size_t)i * C::NW + 2 + D];
+  r[C::IT0] = T;
 }
 
 // Heat fluxes q_t, q_r of the state about the U of the record tp.
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_heat(Geo g, Leaves L, const double* __restrict__ v,
                                                   const double* __restrict__ tp, double* __restrict__ q) {
+  using C = Dg<D>;
   __shared__ double red[(BLOCK / 64 + 1) * 8];
   const int i = blockIdx.x;
-  const double U0 = tp[(size_t)i * DG_NT + 1], U1 = tp[(size_t)i * DG_NT + 2];
+  const double* r = tp + (size_t)i * C::NT;
   const size_t cs = (size_t)g.nc * L.ld;
-  double qa[4] = {0, 0, 0, 0};
+  double qa[C::NQ];
+  for (int t = 0; t < C::NQ; ++t) qa[t] = 0.0;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[2], A;
-    int u[2];
-    leaf_load<2>(L, k, xi, A, u);
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
     const size_t o = (size_t)i * L.ld + k;
-    const double c0 = xi[0] - U0, c1 = xi[1] - U1, c2 = c0 * c0 + c1 * c1;
+    double c[D], c2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      c[d] = xi[d] - r[1 + d];
+      c2 += c[d] * c[d];
+    }
     const double et = A * 0.5 * (c2 * v[o] + v[cs + o]), er = A * v[2 * cs + o];
-    qa[0] += et * c0;
-    qa[1] += et * c1;
-    qa[2] += er * c0;
-    qa[3] += er * c1;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      qa[d] += et * c[d];
+      qa[D + d] += er * c[d];
+    }
   }
-  dg_sum<4>(qa, red);
-  if (threadIdx.x < 4) q[(size_t)i * 4 + threadIdx.x] = qa[threadIdx.x];
+  dg_sum<C::NQ>(qa, red);
+  if (threadIdx.x < C::NQ) q[(size_t)i * C::NQ + threadIdx.x] = qa[threadIdx.x];
 }
 
 // --------------------------------------------- adaptation of the state
@@ -527,29 +649,34 @@ __global__ __launch_bounds__(BLOCK) void k_dg_heat(Geo g, Leaves L, const double
 // M2 = A (1/2 (|c|^2 G + H) + R) / (rho E - rho |U|^2/2), max over the group,
 // in a fixed operation order (no contraction) so that the flags are
 // reproducible bit for bit.
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_crit_partial(Leaves L, int nc, const double* __restrict__ vdf,
                                                           const double* __restrict__ W, double* __restrict__ part) {
 #pragma clang fp contract(off)
+  constexpr int NW = Dg<D>::NW;
   const int k = blockIdx.x * BLOCK + threadIdx.x;
   const int grp = blockIdx.y;
   if (k >= L.n) return;
   const size_t cs = (size_t)nc * L.ld;
-  double xi[2], A;
-  int u[2];
-  leaf_load<2>(L, k, xi, A, u);
+  double xi[D], A;
+  int u[D];
+  leaf_load<D>(L, k, xi, A, u);
   double m = -INFINITY;
   const int i1 = min(nc, (grp + 1) * CRIT_CELLS);
   for (int i = grp * CRIT_CELLS; i < i1; ++i) {
-    const double* w = W + (size_t)i * DG_N;
+    const double* w = W + (size_t)i * NW;
     const double rho = w[0];
-    const double U0 = w[1] / rho, U1 = w[2] / rho;
-    double ke = U0 * U0;
-    ke = ke + U1 * U1;
-    const double eint = w[3] - 0.5 * rho * ke;
-    double c = xi[0] - U0;
+    double U[D];
+    for (int d = 0; d < D; ++d) U[d] = w[1 + d] / rho;
+    double ke = U[0] * U[0];
+    for (int d = 1; d < D; ++d) ke = ke + U[d] * U[d];
+    const double eint = w[1 + D] - 0.5 * rho * ke;
+    double c = xi[0] - U[0];
     double c2 = c * c;
-    c = xi[1] - U1;
-    c2 = c2 + c * c;
+    for (int d = 1; d < D; ++d) {
+      c = xi[d] - U[d];
+      c2 = c2 + c * c;
+    }
     const size_t o = (size_t)i * L.ld + k;
     const double G = vdf[o], H = vdf[cs + o], Rr = vdf[2 * cs + o];
     const double M1 = (A * G) / rho;
@@ -561,7 +688,8 @@ __global__ __launch_bounds__(BLOCK) void k_dg_crit_partial(Leaves L, int nc, con
 
 // Consanguinity reconstruction of G, H, R onto the new leaves: a kept or
 // split leaf copies its source, a merged parent is the balanced pairwise
-// mean ((f0 + f1) + (f2 + f3)) / 4 of its children.
+// mean of its 2^D children.
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_gather(int nc, Leaves Lo, Leaves Ln, const int* __restrict__ kind,
                                                     const int* __restrict__ src, const double* __restrict__ vin,
                                                     double* __restrict__ vout) {
@@ -571,10 +699,14 @@ __global__ __launch_bounds__(BLOCK) void k_dg_gather(int nc, Leaves Lo, Leaves L
   for (int j = threadIdx.x; j < Ln.n; j += BLOCK) {
     const int k = src[j];
     for (int p = 0; p < 3; ++p) {
-      const double* a = vin + p * cso + (size_t)i * Lo.ld;
+      const double* a = vin + p * cso + (size_t)i * Lo.ld + k;
       double v;
-      if (kind[j] == 2) v = ((a[k] + a[k + 1]) + (a[k + 2] + a[k + 3])) * 0.25;
-      else v = a[k];
+      if (kind[j] == 2) {
+        v = D == 2 ? ((a[0] + a[1]) + (a[2] + a[3])) * 0.25
+                   : (((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]))) * 0.125;
+      } else {
+        v = a[0];
+      }
       vout[p * csn + (size_t)i * Ln.ld + j] = v;
     }
   }
@@ -582,66 +714,65 @@ __global__ __launch_bounds__(BLOCK) void k_dg_gather(int nc, Leaves Lo, Leaves L
 
 // Closure of the state onto W in place: f + sum_m lambda_m e_m with the
 // directions of the target's closure at T of W.
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_close(Geo g, Leaves L, VGrid vg, DiaGas gp, const double* __restrict__ W,
                                                    double* __restrict__ v, int* __restrict__ bad) {
+  using C = Dg<D>;
+  constexpr int NW = C::NW;
   extern __shared__ double lds_d[];
-  __shared__ double red[(BLOCK / 64 + 1) * 32];
-  __shared__ double Jm[25], bv[5], xv[5], part[NPAR], parr[NPAR], rec[5];
+  __shared__ double red[(BLOCK / 64 + 1) * 8];
+  __shared__ double Jm[NW * NW], bv[NW], xv[NW], part[NPAR], parr[NPAR], rec[C::NT], tg[NW];
   const int i = blockIdx.x;
   if (threadIdx.x == 0) {
-    double rho, U[2], Tt, Tr, T;
-    if (!dg_temps(W + (size_t)i * DG_N, gp.R, rho, U, Tt, Tr, T)) atomicMin(bad, i);
-    rec[0] = rho; rec[1] = U[0]; rec[2] = U[1]; rec[3] = Tt; rec[4] = Tr;
+    double rho, U[D], Tt, Tr, T;
+    if (!dg_temps<D>(W + (size_t)i * NW, gp.R, rho, U, Tt, Tr, T)) atomicMin(bad, i);
+    rec[0] = rho;
+    for (int d = 0; d < D; ++d) rec[1 + d] = U[d];
+    rec[C::IT] = Tt;
+    rec[C::IR] = Tr;
+    rec[C::IT0] = T;
   }
+  if (threadIdx.x < NW) tg[threadIdx.x] = W[(size_t)i * NW + threadIdx.x];
   __syncthreads();
   double* tabt = lds_d;
-  double* tabr = lds_d + 2 * vg.numax;
-  dg_tables(rec, gp.R, vg, tabt, tabr, part, parr);
-  const double rho = rec[0], U[2] = {rec[1], rec[2]};
-  const double RT = gp.R * (3.0 * rec[3] + 2.0 * rec[4]) / 5.0;
+  double* tabr = lds_d + D * vg.numax;
+  dg_tables<D>(rec, gp.R, vg, tabt, tabr, part, parr);
+  const double RT = gp.R * rec[C::IT0], hid = 3 - D;
   const size_t cs = (size_t)g.nc * L.ld;
-  double acc[30];
-  for (int m = 0; m < 30; ++m) acc[m] = 0.0;
+  double acc[C::NACC];
+  for (int m = 0; m < C::NACC; ++m) acc[m] = 0.0;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[2], A;
-    int u[2];
-    leaf_load<2>(L, k, xi, A, u);
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
     const size_t o = (size_t)i * L.ld + k;
-    dg_mom(acc, A, xi, v[o], v[cs + o], v[2 * cs + o]);
-    const double c[2] = {xi[0] - U[0], xi[1] - U[1]};
-    const double gv = maxw<2>(parr, tabr, vg.numax, u);
-    const double bs[4] = {1.0, c[0], c[1], c[0] * c[0] + c[1] * c[1]};
-    for (int e = 0; e < 4; ++e) dg_mom(acc + 5 + 5 * e, A, xi, bs[e] * gv, RT * bs[e] * gv, RT * bs[e] * gv);
-    dg_mom(acc + 25, A, xi, 0.0, 0.0, RT * gv);
+    double c[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) c[d] = xi[d] - rec[1 + d];
+    dg_close_acc<D>(acc, A, xi, c, RT, maxw<D>(parr, tabr, vg.numax, u), v[o], v[cs + o], v[2 * cs + o]);
   }
-  for (int g0 = 0; g0 < 30; g0 += 8) {
-    double vv[8];
-    for (int m = 0; m < 8; ++m) vv[m] = g0 + m < 30 ? acc[g0 + m] : 0.0;
-    dg_sum<8>(vv, red);
-    for (int m = 0; m < 8; ++m)
-      if (g0 + m < 30) acc[g0 + m] = vv[m];
-  }
-  if (threadIdx.x == 0) {
-    for (int l = 0; l < 5; ++l) {
-      for (int e = 0; e < 5; ++e) Jm[l * 5 + e] = acc[5 + 5 * e + l];
-      bv[l] = W[(size_t)i * DG_N + l] - acc[l];
-    }
-    if (!solve_small<5>(Jm, bv, xv)) atomicMin(bad, i);
-  }
-  __syncthreads();
-  const double l0 = xv[0], l1 = xv[1], l2 = xv[2], l3 = xv[3], l4 = xv[4];
-  (void)rho;
+  dg_close_solve<D>(acc, red, Jm, bv, xv, tg, nullptr, i, bad);
+  double la[NW];
+  for (int e = 0; e < NW; ++e) la[e] = xv[e];
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-    double xi[2], A;
-    int u[2];
-    leaf_load<2>(L, k, xi, A, u);
-    const double c[2] = {xi[0] - U[0], xi[1] - U[1]};
-    const double gv = maxw<2>(parr, tabr, vg.numax, u);
-    const double poly = l0 + l1 * c[0] + l2 * c[1] + l3 * (c[0] * c[0] + c[1] * c[1]);
+    double xi[D], A;
+    int u[D];
+    leaf_load<D>(L, k, xi, A, u);
+    double c[D], c2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      c[d] = xi[d] - rec[1 + d];
+      c2 += c[d] * c[d];
+    }
+    const double gv = maxw<D>(parr, tabr, vg.numax, u);
+    double poly = la[0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) poly += la[1 + d] * c[d];
+    poly += la[1 + D] * c2;
     const size_t o = (size_t)i * L.ld + k;
     v[o] = v[o] + poly * gv;
-    v[cs + o] = v[cs + o] + poly * RT * gv;
-    v[2 * cs + o] = v[2 * cs + o] + (poly * RT * gv + l4 * RT * gv);
+    v[cs + o] = v[cs + o] + poly * hid * RT * gv;
+    v[2 * cs + o] = v[2 * cs + o] + (poly * RT * gv + la[2 + D] * RT * gv);
   }
 }
 

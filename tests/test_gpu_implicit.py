@@ -254,12 +254,12 @@ def test_rykov_equilibrium_matches_oracle(avs, D, prec):
     cs.close()
 
 
-def dia_pair(avs, mesh, vs, vgas, dt, prim5, tree, Kv=1.0, Z=3.5):
+def dia_pair(avs, mesh, vs, vgas, dt, prim5, tree, Kv=1.0, Z=3.5, max_leaves=None):
     from oracle import avs_rykov as RY
-    prim4 = np.concatenate([prim5[:, :1], prim5[:, 1:3], prim5[:, 3:4]], axis=1)
-    cs = avs.Case(mesh, vs, vgas, dt, Kv, prim4)
+    D = vs['dim']
+    cs = avs.Case(mesh, vs, vgas, dt, Kv, np.ascontiguousarray(prim5[:, :D + 2]))
     cs.set_leaves(tree.level, tree.idx)
-    dia = avs.Diatomic(cs, prim5, Z_rot=Z)
+    dia = avs.Diatomic(cs, prim5, Z_rot=Z, max_leaves=max_leaves)
     o = RY.DiatomicSolver(mesh, tree, vgas, RY.RykovGas(R=vgas['R'], Z_rot=Z), dt, Kv, prim5)
     return cs, dia, o
 
@@ -287,6 +287,49 @@ def test_diatomic_periodic_against_oracle(avs):
         assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
     tot = np.sum(o.mesh.vol[:, None] * W, axis=0)
     np.testing.assert_allclose(tot[:4], tot0[:4], rtol=1e-13, atol=1e-14)
+    dia.close()
+    cs.close()
+
+
+def test_diatomic_3d_walls_and_adaptation(avs):
+    """The 3-D diatomic path (H identically zero) on a box with isothermal
+    walls in y and periodic x and z: the closed initial state, a step,
+    bit-exact flags of an adaptation with splits and merges, the remapped
+    state, and a step on the new leaves against the oracle; mass is kept."""
+    mesh = MM.box3d(3, 3, 2, periodic=(True, False, True))
+    vs = dict(dim=3, lo=(-5.0,) * 3, hi=(5.0,) * 3, base=(4, 4, 4), max_level=2)
+    vgas = dict(R=0.5, Pr=0.72, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+    rng = np.random.default_rng(121)
+    n = mesh['ncells']
+    prim = np.concatenate([1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.3 * rng.uniform(-1, 1, (n, 3)),
+                           1 + 0.2 * rng.uniform(-1, 1, (n, 1)), 0.7 + 0.1 * rng.uniform(-1, 1, (n, 1))], axis=1)
+    from oracle import avs_rykov as RY
+    cs, dia, o = dia_pair(avs, mesh, vs, vgas, 2e-3, prim, random_tree(vs, 122, 2), max_leaves=2048)
+    v, W = dia.get_state()
+    assert W.shape == (n, 6) and not v[1].any()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-13
+    m0 = np.sum(o.mesh.vol * W[:, 0])
+    dia.step(1)
+    o.step(1)
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    Mk = np.sort(RY.criterion_dia(o.phi, o.W, o.tree))
+    j1, j2 = int(0.85 * len(Mk)), int(0.25 * len(Mk))
+    C1, C2 = 0.5 * (Mk[j1] + Mk[j1 + 1]), 0.5 * (Mk[j2] + Mk[j2 + 1])
+    assert Mk[j1 + 1] - Mk[j1] > 1e-9 * Mk[j1] and Mk[j2 + 1] - Mk[j2] > 1e-9 * Mk[j2]
+    flags, nn = dia.adapt(C1, C2)
+    eff, plan, _ = o.adapt(C1, C2)
+    assert np.array_equal(flags, eff) and nn == plan.tree.n
+    assert (eff == 1).any() and (eff == -1).any()
+    dia.remap()
+    o.remap()
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-13
+    dia.step(1)
+    o.step(1)
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    assert abs(np.sum(o.mesh.vol * W[:, 0]) - m0) < 1e-13 * m0
     dia.close()
     cs.close()
 
