@@ -1332,7 +1332,8 @@ avs_status dia_steps(avs_dia* d, int nsteps) {
   const size_t shm = dia_shm(ctx);
   for (int s = 0; s < nsteps; ++s) {
     const int c = d->cur;
-    k_dg_recon<D><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->h, d->v[c], d->fv, d->gp);
+    k_dg_recon<D><<<dim3((unsigned)round_up(ctx->nc, 8), (unsigned)((L.n + CHUNK - 1) / CHUNK)), BLOCK, 0,
+                    ctx->stream>>>(ctx->geo, L, ctx->h, d->v[c], d->fv, d->gp, CHUNK);
     CKL();
     k_dg_face<D><<<ctx->nf, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->gas, d->gp, ctx->h, d->fv, d->F,
                                                        d->bad);

@@ -140,11 +140,16 @@ __device__ __forceinline__ double dg_psi(double d1, double d2, double eps2) {
   return u * (u + 2.0) / (u * u + u + 2.0);
 }
 
+// Grid (cells in XCD order, leaf chunks) with cells fastest: a cell and its
+// neighbours read the same chunk of their rows at about the same time, so
+// that the neighbour rows come from L2.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, const double* __restrict__ vin,
-                                                   double* __restrict__ fv, DiaGas gp) {
+                                                   double* __restrict__ fv, DiaGas gp, int chunk) {
   constexpr int MAXF = Dg<D>::MAXF;
-  const int i = blockIdx.x;
+  const int i = xcd_cell(g, blockIdx.x);
+  if (i < 0) return;
+  const int k0 = blockIdx.y * chunk, k1 = min(L.n, k0 + chunk);
   const int ns = g.nslot[i];
   const size_t cs = (size_t)g.nc * L.ld, fs = (size_t)g.nf * L.ld;
   // neighbour rows (a slot without an interior neighbour reads the cell's
@@ -158,7 +163,7 @@ __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, c
     if (j >= 0) mask |= 1u << s;
     nb[s] = (size_t)(j >= 0 ? j : i) * L.ld;
   }
-  for (int k = threadIdx.x; k < L.n; k += BLOCK) {
+  for (int k = k0 + threadIdx.x; k < k1; k += BLOCK) {
     double xi[D], A;
     int u[D];
     leaf_load<D>(L, k, xi, A, u);
@@ -270,7 +275,7 @@ __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, VGrid vg, Ga
   using C = Dg<D>;
   constexpr int NW = C::NW;
   extern __shared__ double lds_d[];
-  __shared__ double red[(BLOCK / 64 + 1) * 8];
+  __shared__ double red[(BLOCK / 64 + 1) * (Dg<D>::NW + 2 * D + D * (D + 1) / 2)];
   __shared__ double rec[C::NT], part[NPAR], parr[NPAR];
   const int f = blockIdx.x;
   const int Rc = g.f_R[f];
@@ -280,38 +285,60 @@ __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, VGrid vg, Ga
   for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
   double* row0 = fv + (size_t)f * L.ld;
   if (Rc >= 0) {
-    double m[NW];
-    for (int t = 0; t < NW; ++t) m[t] = 0.0;
+    // one pass of raw moments: the conserved moments, then
+    // e1_d = sum A (xi^2 G + H)/2 xi_d, p_de = sum A G xi_d xi_e (d <= e) and
+    // r1_d = sum A R xi_d, from which the heat fluxes about U follow
+    constexpr int NP = D * (D + 1) / 2, NS = NW + 2 * D + NP;
+    double m[NS];
+    for (int t = 0; t < NS; ++t) m[t] = 0.0;
     for (int k = threadIdx.x; k < L.n; k += BLOCK) {
       double xi[D], A;
       int u[D];
       leaf_load<D>(L, k, xi, A, u);
-      dg_mom<D>(m, A, xi, row0[k], row0[fs + k], row0[2 * fs + k]);
+      const double Gv = row0[k], Hv = row0[fs + k], Rv = row0[2 * fs + k];
+      dg_mom<D>(m, A, xi, Gv, Hv, Rv);
+      double xi2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
+      const double ek = A * 0.5 * (xi2 * Gv + Hv), ag = A * Gv, ar = A * Rv;
+      int t = NW + 2 * D;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        m[NW + d] += ek * xi[d];
+        m[NW + D + d] += ar * xi[d];
+#pragma unroll
+        for (int e = d; e < D; ++e) m[t++] += ag * xi[d] * xi[e];
+      }
     }
-    dg_sum<NW>(m, red);
+    dg_sum<NS>(m, red);
     double rho, U[D], Ttb, Trb, T;
     const bool ok = dg_temps<D>(m, gp.R, rho, U, Ttb, Trb, T);
+    // q_t = sum A (|c|^2 G + H)/2 c and q_r = sum A R c with c = xi - U,
+    // expanded in the raw moments
     double q[C::NQ];
-    for (int t = 0; t < C::NQ; ++t) q[t] = 0.0;
-    for (int k = threadIdx.x; k < L.n; k += BLOCK) {
-      double xi[D], A;
-      int u[D];
-      leaf_load<D>(L, k, xi, A, u);
-      double c[D], c2 = 0.0;
+    {
+      double uu = 0.0, um = 0.0, pu[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        c[d] = xi[d] - U[d];
-        c2 += c[d] * c[d];
+        uu += U[d] * U[d];
+        um += U[d] * m[1 + d];
       }
-      const double Gv = row0[k], Hv = row0[fs + k], Rv = row0[2 * fs + k];
-      const double et = A * 0.5 * (c2 * Gv + Hv), er = A * Rv;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        q[d] += et * c[d];
-        q[D + d] += er * c[d];
+        pu[d] = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+          const int a = d < e ? d : e, b = d < e ? e : d;
+          pu[d] += U[e] * m[NW + 2 * D + a * D - a * (a - 1) / 2 + (b - a)];
+        }
+      }
+      const double e0 = m[1 + D] - m[2 + D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        q[d] = m[NW + d] - U[d] * e0 - pu[d] + U[d] * um + 0.5 * uu * (m[1 + d] - U[d] * m[0]);
+        q[D + d] = m[NW + D + d] - U[d] * m[2 + D];
       }
     }
-    dg_sum<C::NQ>(q, red);
     if (threadIdx.x == 0) {
       if (!ok) atomicMin(bad, g.nc + f);
       const double tf = ok ? tau_of(rho, Ttb, vgas) : 1.0;
