@@ -150,9 +150,13 @@ def is_wall(mesh, f):
     return Rc < 0 and mesh.bc_kind[-1 - Rc] == O.WALL
 
 
-def macro_sgs(mesh, dt, R, W, rhs, r, n_sweeps, order):
+def macro_sgs(mesh, dt, R, W, rhs, r, n_sweeps, order, flux=None, source=None):
     """PRSGS sweeps on the predictor (Eq. SGS_w).  ``rhs[i]`` = -sum_j A_ij
-    F_ij^n (outward normals).  Returns dW."""
+    F_ij^n (outward normals).  ``flux(W, n, R)`` is the Euler flux (the
+    monatomic one by default); ``source(i, W_i + dW_i)``, if given, returns
+    (d, b): an implicit source adds d to the cell's diagonal and b to its
+    right-hand side (Eq. SGS_wrot).  Returns dW."""
+    euler = flux or euler_flux
     nc = mesh.nc
     dW = np.zeros_like(W)
     diag = np.array([mesh.vol[i] / dt + 0.5 * sum(mesh.area[s.face] * r[s.face] for s in mesh.slots[i])
@@ -169,9 +173,13 @@ def macro_sgs(mesh, dt, R, W, rhs, r, n_sweeps, order):
                     Wj, dWj = mirror(W[i], n_out), mirror(dW[i], n_out)
                 else:
                     continue
-                acc -= 0.5 * A * (euler_flux(Wj + dWj, n_out, R) - euler_flux(Wj, n_out, R))
+                acc -= 0.5 * A * (euler(Wj + dWj, n_out, R) - euler(Wj, n_out, R))
                 acc += 0.5 * A * r[s.face] * dWj
-            dW[i] = acc / diag[i]
+            if source is None:
+                dW[i] = acc / diag[i]
+            else:
+                d, b = source(i, W[i] + dW[i])
+                dW[i] = (acc + b) / (diag[i] + d)
     return dW
 
 
@@ -200,10 +208,11 @@ def micro_sgs(mesh, xi, dt, tau_c, res, n_sweeps, order):
     return dphi
 
 
-def implicit_flux(mesh, gas, W, dW, F, r):
+def implicit_flux(mesh, gas, W, dW, F, r, flux=None):
     """Fh_f = F_f + 1/2 [G(W~_L) - G(W_L) + G(W~_R) - G(W_R)] + 1/2 r_f (dW_L - dW_R)
     through the face normal (L to R); the outside of a boundary face as in
     the predictor (mirror state at a wall, increment 0 at the far field)."""
+    euler = flux or euler_flux
     Fh = {}
     for f in F:
         L, Rc = int(mesh.lr[f, 0]), int(mesh.lr[f, 1])
@@ -214,9 +223,9 @@ def implicit_flux(mesh, gas, W, dW, F, r):
             WR, dWR = mirror(W[L], n), mirror(dW[L], n)
         else:
             WR, dWR = None, np.zeros_like(dW[L])
-        v = F[f] + 0.5 * (euler_flux(W[L] + dW[L], n, gas.R) - euler_flux(W[L], n, gas.R))
+        v = F[f] + 0.5 * (euler(W[L] + dW[L], n, gas.R) - euler(W[L], n, gas.R))
         if WR is not None:
-            v = v + 0.5 * (euler_flux(WR + dWR, n, gas.R) - euler_flux(WR, n, gas.R))
+            v = v + 0.5 * (euler(WR + dWR, n, gas.R) - euler(WR, n, gas.R))
         v = v + 0.5 * r[f] * (dW[L] - dWR)
         Fh[f] = v
     return Fh

@@ -26,6 +26,17 @@ Readings (the paper leaves these open):
   printed with its relaxation factor in the numerator) is the implicit
   relaxation over h: rho R T_rot = (int R + h/(Z tau) rho R T) / (1 + h/(Z tau)).
 
+The implicit step (``step_implicit_dia``) extends the monatomic IUGKS of
+``avs_implicit`` with the rotational row.  Readings:
+* the predictor's Euler flux carries rho E_rot U.n and uses the
+  translational pressure rho R T_t, so its sound speed in r_ij is the
+  frozen one, sqrt(5/3 R T_t), and mu/rho = tau R T_t;
+* tau and rho R T of Eq. SGS_wrot are taken at the cell's current iterate
+  W + dW in every sweep (rho R T does not depend on the rotational share);
+* W^{n+1} is the flux form with the implicit flux, followed by the
+  point-implicit rotational exchange of the explicit step, so that the
+  same target and tau~ drive the micro system.
+
 Pins (tests/test_rykov_pins.py): the equilibrium's moments and heat fluxes
 against closed forms of Gaussian moments (mass, momentum, the translational
 energy 3/2 rho R T_t of the t part and 3/2 rho R T of the r part, int R^t =
@@ -217,8 +228,10 @@ def heat_rates(Tt, Tr, gas):
     return lt, lr
 
 
-def face_vdf_dia(f, phi, LG, mesh, xi, A, vgas, gas, h):
-    """Interface VDF (3 components) of face f at t_n + h."""
+def face_vdf_dia(f, phi, LG, mesh, xi, A, vgas, gas, h, state=None):
+    """Interface VDF (3 components) of face f at t_n + h.  For an interior
+    face, ``state`` (a dict, if given) receives the interface moment state
+    (rho, U, T_t) and its tau."""
     D = mesh.dim
     R = gas.R
     L, Rc = int(mesh.lr[f, 0]), int(mesh.lr[f, 1])
@@ -234,6 +247,8 @@ def face_vdf_dia(f, phi, LG, mesh, xi, A, vgas, gas, h):
         rho, U, Tt_b, Tr_b, T = temperatures(Wf, R)
         qt_b, qr_b = heat_fluxes(pbar, xi, A, U)
         tf = tau_t(rho, Tt_b, vgas)
+        if state is not None:
+            state[f] = (rho, U, Tt_b, tf)
         ERf = interface_rotational_energy(Wf[2 + D], rho * R * T, h, tf, gas)
         Tr = ERf / (rho * R)
         Tt = Tt_b + (2.0 / 3.0) * (Tr_b - Tr)
@@ -298,6 +313,111 @@ def step_dia(mesh, tree, vgas, gas, dt, Kv, phi, W):
     return phi_new, W_new
 
 
+def euler_flux_dia(W, n, R):
+    """Euler flux of a diatomic state through n (the flux of the implicit
+    predictor with the rotational row): (rho U.n, rho U U.n + p n,
+    (rho E + p) U.n, rho E_rot U.n) with the translational pressure
+    p = rho R T_t."""
+    D = len(n)
+    rho, U, Tt, _, _ = temperatures(W, R)
+    p = rho * R * Tt
+    un = float(np.dot(U, n))
+    out = np.empty(D + 3)
+    out[0] = rho * un
+    out[1:1 + D] = rho * U * un + p * np.asarray(n)
+    out[1 + D] = (W[1 + D] + p) * un
+    out[2 + D] = W[2 + D] * un
+    return out
+
+
+def roe_radius_dia(rho, U, Tt, tau, n, dl, R):
+    """r = |U.n| + a + 2 mu / (rho dl) with the frozen sound speed
+    a = sqrt(5/3 R T_t) of the flux above (E_rot is only carried) and
+    mu / rho = tau R T_t."""
+    return abs(float(np.dot(U, n))) + math.sqrt(5.0 / 3.0 * R * Tt) + 2.0 * tau * R * Tt / dl
+
+
+def step_implicit_dia(mesh, tree, vgas, gas, dt, Kv, phi, W, n_macro, n_micro, order=None):
+    """One implicit step of the diatomic model (Sec. 2.3.1-2.3.2 with the
+    rotational row of Eqs. S_rot, SGS_wrot); phi [3, Nc, Nv], W [Nc, D+3].
+    Returns (phi_new, W_new, predicted W~)."""
+    from . import avs_implicit as _I
+    D = mesh.dim
+    R = gas.R
+    xi, A = tree.centres(), tree.weights()
+    if order is None:
+        order = _I.sweep_order(_I.cell_colours(mesh))
+    h = _O.half_step(mesh, tree, dt)
+    LG = {c: _O.limited_gradient(c, phi, mesh, Kv) for c in range(mesh.nc)}
+    phif, F, fst = {}, {}, {}
+    for f in range(mesh.nf):
+        phif[f] = face_vdf_dia(f, phi, LG, mesh, xi, A, vgas, gas, h, state=fst)
+        F[f] = flux_moments(phif[f], xi, A, mesh.nrm[f])
+    rhs = np.zeros_like(W)
+    div = np.zeros_like(phi)
+    for i in range(mesh.nc):
+        for s in mesh.slots[i]:
+            af = s.sigma * mesh.area[s.face]
+            rhs[i] -= af * F[s.face]
+            div[:, i, :] += af * _O.normal_speed(xi, mesh.nrm[s.face])[None, :] * phif[s.face]
+    # r_ij from the interface moment state; a boundary face from its cell's W^n
+    r = np.zeros(mesh.nf)
+    for f in range(mesh.nf):
+        L, Rc = int(mesh.lr[f, 0]), int(mesh.lr[f, 1])
+        n = mesh.nrm[f]
+        if Rc >= 0:
+            rho, U, Tt, tf = fst[f]
+            dl = float(np.linalg.norm(mesh.ctr[Rc] + mesh.shift[f] - mesh.ctr[L]))
+        else:
+            rho, U, Tt, _, _ = temperatures(W[L], R)
+            tf = tau_t(rho, Tt, vgas)
+            dl = 2.0 * float(np.dot(mesh.fctr[f] - mesh.ctr[L], n))
+        r[f] = roe_radius_dia(rho, U, Tt, tf, n, dl, R)
+
+    # Eq. SGS_wrot: the rotational row gains V/(Z tau) on its diagonal and
+    # V ((rho R T) - rho E_rot^n)/(Z tau) on its right-hand side, tau and
+    # rho R T taken at the cell's current iterate W + dW
+    def rot_source(i, Wc):
+        rho, _, Tt, _, T = temperatures(Wc, R)
+        k = mesh.vol[i] / (gas.Z_rot * tau_t(rho, Tt, vgas))
+        d = np.zeros(D + 3)
+        b = np.zeros(D + 3)
+        d[2 + D] = k
+        b[2 + D] = k * (rho * R * T - W[i][2 + D])
+        return d, b
+
+    dW = _I.macro_sgs(mesh, dt, R, W, rhs, r, n_macro, order, flux=euler_flux_dia, source=rot_source)
+    Fh = _I.implicit_flux(mesh, gas, W, dW, F, r, flux=euler_flux_dia)
+    res = np.empty_like(phi)
+    tau_c = np.empty(mesh.nc)
+    W_new = np.empty_like(W)
+    for i in range(mesh.nc):
+        _, U_n, _, _, _ = temperatures(W[i], R)
+        qt_n, qr_n = heat_fluxes(phi[:, i, :], xi, A, U_n)
+        Fs = np.zeros(D + 3)
+        for s in mesh.slots[i]:
+            Fs += s.sigma * mesh.area[s.face] * Fh[s.face]
+        # W^{n+1}: flux form with the implicit flux, then the rotational
+        # exchange as in the explicit step
+        Ws = W[i] - dt / mesh.vol[i] * Fs
+        rho, U, Tt_s, Tr_s, T = temperatures(Ws, R)
+        if not (rho > 0 and Tt_s > 0 and Tr_s > 0):
+            raise FloatingPointError(f'non-physical state in cell {i}')
+        tt = tau_t(rho, Tt_s, vgas)
+        k = dt / (gas.Z_rot * tt)
+        Wn = Ws.copy()
+        Wn[2 + D] = (Ws[2 + D] + k * rho * R * T) / (1.0 + k)
+        _, _, Tt, Tr, _ = temperatures(Wn, R)
+        target = Wn.copy()
+        target[2 + D] = (1.0 - 1.0 / gas.Z_rot) * Wn[2 + D] + rho * R * T / gas.Z_rot
+        gt = closure_dia(rykov_equilibrium(rho, U, Tt, Tr, qt_n, qr_n, xi, gas), target, Wn, xi, A, R)
+        tau_c[i] = tt
+        res[:, i, :] = mesh.vol[i] * (gt - phi[:, i, :]) / tt - div[:, i, :]
+        W_new[i] = Wn
+    phi_new = phi + _I.micro_sgs(mesh, xi, dt, tau_c, res, n_micro, order)
+    return phi_new, W_new, W + dW
+
+
 class DiatomicSolver:
     """Explicit diatomic steps on a fixed velocity tree, in FP64.
     ``prim0`` rows are (rho, U, T_t, T_r); the physical gas ``vgas`` gives R
@@ -328,6 +448,11 @@ class DiatomicSolver:
     def step(self, n=1):
         for _ in range(n):
             self.phi, self.W = step_dia(self.mesh, self.tree, self.vgas, self.gas, self.dt, self.Kv, self.phi, self.W)
+
+    def step_implicit(self, n, n_macro, n_micro):
+        for _ in range(n):
+            self.phi, self.W, self.predicted = step_implicit_dia(self.mesh, self.tree, self.vgas, self.gas, self.dt,
+                                                                 self.Kv, self.phi, self.W, n_macro, n_micro)
 
     def vdf_moments(self):
         xi, A = self.tree.centres(), self.tree.weights()

@@ -200,3 +200,79 @@ def test_diatomic_criterion_sums_and_remap_conserves():
     back = O.make_plan(eff, t_split)
     assert back.tree.n == tree0.n
     assert np.array_equal(O.remap(p_split, back, 2), phi0)
+
+
+# ------------------------------------------------------------ implicit step
+@pytest.mark.parametrize("D", [2, 3])
+def test_diatomic_euler_flux_and_its_spectral_radius(D):
+    """With E_rot = 0 the first D + 2 rows are the monatomic Euler flux (an
+    independent function); the rotational row is E_rot U.n; the spectral
+    radius of the flux Jacobian (central differences) is the inviscid r,
+    |U.n| + sqrt(5/3 R T_t): E_rot is only carried and does not enter p."""
+    from oracle import avs_implicit as IM
+    rng = np.random.default_rng(40 + D)
+    R = 0.6
+    n = rng.normal(size=D)
+    n /= np.linalg.norm(n)
+    rho, U, Tt, Tr = 1.3, rng.uniform(-0.5, 0.5, D), 1.1, 0.8
+    W = RY.conserved(rho, U, Tt, Tr, R)
+    W0 = W.copy()
+    W0[1 + D] -= W0[2 + D]
+    W0[2 + D] = 0.0
+    Fm = IM.euler_flux(W0[:D + 2], n, R)
+    np.testing.assert_allclose(RY.euler_flux_dia(W0, n, R)[:D + 2], Fm, rtol=1e-15, atol=1e-15)
+    F = RY.euler_flux_dia(W, n, R)
+    assert abs(F[2 + D] - W[2 + D] * float(U @ n)) < 1e-15
+    J = np.empty((D + 3, D + 3))
+    for m in range(D + 3):
+        e = np.zeros(D + 3)
+        e[m] = 1e-6 * max(1.0, abs(W[m]))
+        J[:, m] = (RY.euler_flux_dia(W + e, n, R) - RY.euler_flux_dia(W - e, n, R)) / (2 * e[m])
+    rad = np.max(np.abs(np.linalg.eigvals(J)))
+    r0 = RY.roe_radius_dia(rho, U, Tt, 0.0, n, 1.0, R)
+    assert abs(rad - r0) < 1e-7 * r0
+    assert abs(r0 - abs(float(U @ n)) - math.sqrt(5 / 3 * R * Tt)) < 1e-14
+
+
+def test_implicit_diatomic_homogeneous_relaxation_closed_form():
+    """A uniform gas at rest with T_r < T_t, omega = 1 (constant tau):
+    converged predictor sweeps give the implicit-Euler increment of Eq.
+    SGS_wrot, dE = k (rho R T - E)/(1 + k) with k = dt/(Z tau), and nothing
+    else moves; W^{n+1} follows the same closed-form sequence; with converged
+    micro sweeps the moments of phi equal W."""
+    s = periodic_case(nx=2, ny=2, omega=1.0, dt=0.01, Tr_amp=0.0, uamp=0.0)
+    s.W[:] = s.W[0]
+    s.phi[:] = s.phi[:, :1]
+    rho, U, Tt, Tr, T = RY.temperatures(s.W[0], 0.5)
+    tau = 0.05 / (rho * 0.5 * 1.0)
+    E0, Eeq = s.W[0, 4], rho * 0.5 * T
+    k = 0.01 / (3.5 * tau)
+    for nstep in range(1, 4):
+        E = s.W[0, 4]
+        W = s.W.copy()
+        s.step_implicit(1, 40, 40)
+        dW = s.predicted - W
+        np.testing.assert_allclose(dW[:, 4], k * (Eeq - E) / (1 + k), rtol=1e-12)
+        assert np.abs(dW[:, :4]).max() < 1e-15
+        np.testing.assert_allclose(s.W[:, 4], Eeq + (E0 - Eeq) * (1 + k) ** -nstep, rtol=1e-13)
+        np.testing.assert_allclose(s.vdf_moments(), s.W, rtol=0, atol=1e-12)
+
+
+def test_implicit_diatomic_conserves_and_tends_to_the_explicit_step():
+    """Periodic box: after two sweeps of each kind the implicit step keeps
+    mass, momentum and total energy to round-off (flux form); its difference
+    from the explicit step, relative to the step's change, halves with dt
+    (both are first order; they differ at O(dt^2))."""
+    s = periodic_case()
+    tot0 = s.totals()
+    s.step_implicit(2, 2, 2)
+    tot = s.totals()
+    np.testing.assert_allclose(tot[:4], tot0[:4], rtol=1e-14, atol=1e-14)
+    e = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        c = periodic_case(dt=dt)
+        pe, We = RY.step_dia(c.mesh, c.tree, c.vgas, c.gas, dt, c.Kv, c.phi, c.W)
+        pi, Wi, _ = RY.step_implicit_dia(c.mesh, c.tree, c.vgas, c.gas, dt, c.Kv, c.phi, c.W, 30, 30)
+        e.append((np.abs(pi - pe).max() / np.abs(pe - c.phi).max(), np.abs(Wi - We).max() / np.abs(We - c.W).max()))
+    for a, b in zip(e, e[1:]):
+        assert 1.8 < a[0] / b[0] < 2.2 and 1.8 < a[1] / b[1] < 2.2
