@@ -600,8 +600,8 @@ def run_rykov(args, reps=5):
 def run_diatomic(args, steps=10):
     """Rykov diatomic steps (2-D FP64, three reduced distributions) on the
     cylinder workload's mesh and step-0 tree: nitrogen-like gas with
-    T_r = 0.9 T_t initially; cell-node updates per second and the time of
-    each stage."""
+    T_r = 0.9 T_t initially; cell-node updates per second, and the time of
+    an implicit step with 20 predictor and 2 micro sweeps."""
     import numpy as np
     import torch
     from paper_2212_05645_amd import avs
@@ -619,7 +619,14 @@ def run_diatomic(args, steps=10):
     e1.record(cs.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    # implicit steps (20 predictor / 2 micro sweeps) at the same dt
+    e0.record(cs.stream)
+    dia.step_implicit(3, 20, 2)
+    e1.record(cs.stream)
+    torch.cuda.synchronize()
+    ms_imp = e0.elapsed_time(e1) / 3
     out = {"updates_per_s": cs.nc * n0 * 1e3 / ms, "ms_per_step": ms, "cells": cs.nc, "leaves": n0,
+           "ms_per_implicit_step_20_2": ms_imp,
            "workload": f"Rykov diatomic explicit step, cylinder O-grid {args.nr}x{args.nth}, step-0 tree, FP64"}
     dia.close()
     del w

@@ -202,6 +202,24 @@ avs_status avs_dia_create(avs_ctx *ctx, const avs_rykov *gas, const double *prim
 avs_status avs_dia_step(avs_dia *dia, int32_t nsteps);
 avs_status avs_dia_get_state(avs_dia *dia, double *vdf_host, double *W_host);
 
+/* Implicit steps of the diatomic model (Secs. 2.3.1-2.3.2 with the
+ * rotational row of Eqs. S_rot and SGS_wrot), at the context's dt.  As
+ * avs_step_implicit, with the interface stage above, and:
+ *  - predictor over the D + 3 variables: the Euler flux carries
+ *    rho E_rot U.n and uses the translational pressure rho R T_t, so r_f
+ *    takes the frozen sound speed sqrt(5/3 R T_t) and mu/rho = tau R T_t;
+ *  - the rotational row's diagonal and right-hand side gain V/(Z tau) and
+ *    V (rho R T - rho E_rot^n)/(Z tau), at the cell's current iterate;
+ *  - W^{n+1} in flux form with the implicit flux, then the rotational
+ *    exchange, target and tau~ as in avs_dia_step;
+ *  - n_micro symmetric Gauss-Seidel sweeps over G, H, R.
+ * No memory beyond the state's region: the micro right-hand side and
+ * increment use the spare state and interface buffers (the mesh needs
+ * ncells <= nfaces + 1, AVS_E_INVALID otherwise).  n_macro = n_micro = 0 is
+ * allowed (zero increments).  Waits for the device; AVS_E_NUMERIC for a
+ * non-physical state. */
+avs_status avs_dia_step_implicit(avs_dia *dia, int32_t nsteps, int32_t n_macro, int32_t n_micro);
+
 /* Adaptation of the velocity tree driven by the diatomic state (Secs.
  * 3.2-3.4): M_k = max over cells of max(M1, M2), M1 = A G / rho, M2 =
  * A (1/2 (|c|^2 G + H) + R) / (rho E - rho |U|^2 / 2) (the internal energy

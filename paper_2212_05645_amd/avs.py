@@ -28,7 +28,7 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
            "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
            "avs_auto_params", "avs_initial_avs", "avs_implicit_bytes", "avs_step_implicit",
-           "avs_rykov_equilibrium", "avs_dia_bytes", "avs_dia_create", "avs_dia_step", "avs_dia_get_state",
+           "avs_rykov_equilibrium", "avs_dia_bytes", "avs_dia_create", "avs_dia_step", "avs_dia_step_implicit", "avs_dia_get_state",
            "avs_dia_adapt", "avs_dia_remap", "avs_dia_destroy", "avs_destroy", "avs_last_error")
 
 
@@ -131,6 +131,7 @@ def _load():
         "avs_dia_adapt": (I32, [VP, D, D, VP, P(I64)]),
         "avs_dia_remap": (I32, [VP]),
         "avs_dia_step": (I32, [VP, I32]),
+        "avs_dia_step_implicit": (I32, [VP, I32, I32, I32]),
         "avs_dia_get_state": (I32, [VP, VP, VP]),
         "avs_dia_destroy": (None, [VP]),
         "avs_step_implicit": (I32, [VP, I32, I32, I32, VP, C.c_size_t, VP]),
@@ -538,6 +539,11 @@ class Diatomic:
 
     def step(self, n=1):
         _check(lib.avs_dia_step(self.h, int(n)))
+
+    def step_implicit(self, n, n_macro, n_micro):
+        """Implicit steps (the context's dt) with n_macro predictor and
+        n_micro micro symmetric sweeps."""
+        _check(lib.avs_dia_step_implicit(self.h, int(n), int(n_macro), int(n_micro)))
 
     def get_state(self):
         n = self.case.nleaves()

@@ -532,7 +532,7 @@ avs_status launch_step_implicit(avs_ctx* ctx, int n_macro, int n_micro, T* res, 
         const int c = t < ncol ? t : 2 * ncol - 1 - t;
         const int cnt = ctx->col_off[c + 1] - ctx->col_off[c];
         k_imp_micro<D, T><<<(unsigned)cnt, BLOCK, 0, ctx->stream>>>(ctx->geo, L, ctx->col_cells + ctx->col_off[c], res,
-                                                                     dphi, ctx->tpar);
+                                                                     dphi, ctx->tpar, NPAR, P_A);
         CKL();
       }
     k_imp_finish<T><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->P, ctx->nc, L, vin, dphi);
@@ -1264,6 +1264,7 @@ struct avs_dia {
   DiaGas gp{};
   double *v[2] = {nullptr, nullptr}, *fv = nullptr, *W[2] = {nullptr, nullptr};
   double *q = nullptr, *F = nullptr, *tp = nullptr, *lam = nullptr;
+  double *rf = nullptr, *irhs = nullptr, *idiag = nullptr, *dW = nullptr;   // implicit predictor
   int* bad = nullptr;
   int cur = 0;
   int64_t gen = 0;
@@ -1289,9 +1290,14 @@ size_t dia_layout(const avs_ctx* c, int64_t max_leaves, avs_dia* d, char* base) 
   double* F = cv.take<double>((nf + 1) * NW);
   double* tp = cv.take<double>(nc * NT);
   double* lam = cv.take<double>(nc * NW);
+  double* rf = cv.take<double>(nf + 1);
+  double* irhs = cv.take<double>(nc * NW);
+  double* idiag = cv.take<double>(nc);
+  double* dW = cv.take<double>(nc * NW);
   int* bad = cv.take<int>(4);
   if (d) {
     d->fv = fv; d->W[0] = W0; d->W[1] = W1; d->q = q; d->F = F; d->tp = tp; d->lam = lam; d->bad = bad;
+    d->rf = rf; d->irhs = irhs; d->idiag = idiag; d->dW = dW;
   }
   return cv.off;
 }
@@ -1336,7 +1342,7 @@ avs_status dia_steps(avs_dia* d, int nsteps) {
                     ctx->stream>>>(ctx->geo, L, ctx->h, d->v[c], d->fv, d->gp, CHUNK);
     CKL();
     k_dg_face<D><<<ctx->nf, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->gas, d->gp, ctx->h, d->fv, d->F,
-                                                       d->bad);
+                                                       d->bad, nullptr, nullptr);
     CKL();
     k_dg_macro<D><<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, d->gp, ctx->dt, d->F, d->W[c], d->W[c ^ 1], d->q,
                                                  d->tp, d->bad);
@@ -1346,6 +1352,69 @@ avs_status dia_steps(avs_dia* d, int nsteps) {
     CKL();
     k_dg_update<D><<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->v[c], d->fv, d->v[c ^ 1], d->tp,
                                                          d->lam, d->q, 0);
+    CKL();
+    d->cur ^= 1;
+  }
+  return AVS_OK;
+}
+
+// Implicit steps: the interface stage of the explicit step (with r_f), the
+// predictor's colour sweeps, the implicit flux, W^{n+1} and the target as in
+// the explicit step, the micro right-hand side into the spare state buffer,
+// the micro colour sweeps with the increment in the interface buffer (free
+// once the right-hand side is formed), phi^{n+1} = phi^n + dphi.
+template <int D>
+avs_status dia_steps_implicit(avs_dia* d, int nsteps, int n_macro, int n_micro) {
+  avs_ctx* ctx = d->ctx;
+  const Leaves L = ctx->leaves(ctx->lcur);
+  const unsigned gc = (unsigned)((ctx->nc + BLOCK - 1) / BLOCK), gf = (unsigned)((ctx->nf + BLOCK - 1) / BLOCK);
+  const size_t shm = dia_shm(ctx);
+  const int ncol = (int)ctx->col_off.size() - 1;
+  for (int st = 0; st < nsteps; ++st) {
+    const int c = d->cur;
+    k_dg_recon<D><<<dim3((unsigned)round_up(ctx->nc, 8), (unsigned)((L.n + CHUNK - 1) / CHUNK)), BLOCK, 0,
+                    ctx->stream>>>(ctx->geo, L, ctx->h, d->v[c], d->fv, d->gp, CHUNK);
+    CKL();
+    k_dg_face<D><<<ctx->nf, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, ctx->gas, d->gp, ctx->h, d->fv, d->F,
+                                                       d->bad, d->W[c], d->rf);
+    CKL();
+    k_imp_rhs<D, D + 3><<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, d->F, d->rf, d->irhs, d->idiag, d->dW);
+    CKL();
+    for (int sw = 0; sw < n_macro; ++sw)
+      for (int t = 0; t < 2 * ncol; ++t) {
+        const int cc = t < ncol ? t : 2 * ncol - 1 - t;
+        const int cnt = ctx->col_off[cc + 1] - ctx->col_off[cc];
+        k_dgi_macro<D><<<(unsigned)((cnt + BLOCK - 1) / BLOCK), BLOCK, 0, ctx->stream>>>(
+            ctx->geo, ctx->gas, d->gp, ctx->dt, ctx->col_cells + ctx->col_off[cc], cnt, d->W[c], d->rf, d->irhs,
+            d->idiag, d->dW, d->bad);
+        CKL();
+      }
+    k_dgi_fhat<D><<<gf, BLOCK, 0, ctx->stream>>>(ctx->geo, d->gp, d->W[c], d->dW, d->rf, d->F);
+    CKL();
+    k_dg_macro<D><<<gc, BLOCK, 0, ctx->stream>>>(ctx->geo, ctx->gas, d->gp, ctx->dt, d->F, d->W[c], d->W[c ^ 1], d->q,
+                                                 d->tp, d->bad);
+    CKL();
+    k_dg_target<D><<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->tp, d->W[c ^ 1], d->lam, 0,
+                                                         d->bad);
+    CKL();
+    double* res = d->v[c ^ 1];
+    double* dphi = d->fv;
+    k_dg_update<D><<<ctx->nc, BLOCK, shm, ctx->stream>>>(ctx->geo, L, ctx->vg, d->gp, d->v[c], d->fv, res, d->tp,
+                                                         d->lam, d->q, 2);
+    CKL();
+    k_imp_zero<double><<<ctx->nc, BLOCK, 0, ctx->stream>>>(3, ctx->nc, L, dphi);
+    CKL();
+    for (int sw = 0; sw < n_micro; ++sw)
+      for (int t = 0; t < 2 * ncol; ++t) {
+        const int cc = t < ncol ? t : 2 * ncol - 1 - t;
+        const int cnt = ctx->col_off[cc + 1] - ctx->col_off[cc];
+        k_imp_micro<D, double, 3><<<(unsigned)cnt, BLOCK, 0, ctx->stream>>>(
+            ctx->geo, L, ctx->col_cells + ctx->col_off[cc], res, dphi, d->tp, Dg<D>::NT, Dg<D>::IDT);
+        CKL();
+      }
+    k_dgi_finish<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->nc, L, d->v[c], dphi, d->v[c ^ 1]);
+    CKL();
+    k_dg_heat<D><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->v[c ^ 1], d->tp, d->q);
     CKL();
     d->cur ^= 1;
   }
@@ -1458,6 +1527,20 @@ avs_status avs_dia_step(avs_dia* d, int32_t nsteps) {
   if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
   if (nsteps < 0) return fail(AVS_E_INVALID, "nsteps < 0");
   if (avs_status st = ctx->D == 2 ? dia_steps<2>(d, nsteps) : dia_steps<3>(d, nsteps)) return st;
+  return dia_check_bad(d);
+}
+
+avs_status avs_dia_step_implicit(avs_dia* d, int32_t nsteps, int32_t n_macro, int32_t n_micro) {
+  if (!d) return fail(AVS_E_INVALID, "null diatomic state");
+  avs_ctx* ctx = d->ctx;
+  if (avs_status st = guard(ctx)) return st;
+  if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
+  if (nsteps < 0 || n_macro < 0 || n_micro < 0) return fail(AVS_E_INVALID, "negative step or sweep count");
+  // the micro increment lives in the interface buffer: [3][ncells][ld] must fit in [3][nfaces + 1][ld]
+  if (ctx->nc > ctx->nf + 1) return fail(AVS_E_INVALID, "mesh has more cells than faces + 1");
+  if (avs_status st = ctx->D == 2 ? dia_steps_implicit<2>(d, nsteps, n_macro, n_micro)
+                                  : dia_steps_implicit<3>(d, nsteps, n_macro, n_micro))
+    return st;
   return dia_check_bad(d);
 }
 

@@ -269,9 +269,14 @@ __device__ __forceinline__ void dg_sum(double* v, double* red) {
   __syncthreads();
 }
 
+// With rf (the implicit step), also r_f = |U.n| + a + 2 mu/(rho dl) of the
+// predictor: interior faces from the interface moment state (rho, U, T_t of
+// the reconstructed rows, its tau), boundary faces from the cell's W^n and
+// dl = 2 (x_f - x_i).n; a = sqrt(5/3 R T_t), mu/rho = tau R T_t.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, VGrid vg, GasP vgas, DiaGas gp, double h,
-                                                  double* __restrict__ fv, double* __restrict__ F, int* __restrict__ bad) {
+                                                  double* __restrict__ fv, double* __restrict__ F, int* __restrict__ bad,
+                                                  const double* __restrict__ W, double* __restrict__ rf) {
   using C = Dg<D>;
   constexpr int NW = C::NW;
   extern __shared__ double lds_d[];
@@ -342,6 +347,17 @@ __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, VGrid vg, Ga
     if (threadIdx.x == 0) {
       if (!ok) atomicMin(bad, g.nc + f);
       const double tf = ok ? tau_of(rho, Ttb, vgas) : 1.0;
+      if (rf) {
+        constexpr int MAXF = Dg<D>::MAXF;
+        const size_t so = (size_t)g.f_L[f] * MAXF + g.f_sL[f];
+        double un = 0.0, dl2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+          un += U[d] * n[d];
+          dl2 += g.s_dx[so * D + d] * g.s_dx[so * D + d];
+        }
+        const double RTt = gp.R * Ttb;
+        rf[f] = fabs(un) + sqrt(5.0 / 3.0 * RTt) + 2.0 * tf * RTt / sqrt(dl2);
+      }
       const double kz = h / (gp.Z * tf);
       const double ER = (m[2 + D] + kz * (rho * gp.R * T)) / (1.0 + kz);
       const double Tr = ER / (rho * gp.R);
@@ -390,6 +406,20 @@ __global__ __launch_bounds__(BLOCK) void k_dg_face(Geo g, Leaves L, VGrid vg, Ga
   }
   const int bc = -1 - Rc;
   const bool wall = g.bc_kind[bc] == 0;
+  if (rf && threadIdx.x == 0) {
+    constexpr int MAXF = Dg<D>::MAXF;
+    const int c = g.f_L[f];
+    const size_t so = (size_t)c * MAXF + g.f_sL[f];
+    double rho, U[D], Tt, Tr, T;
+    if (!dg_temps<D>(W + (size_t)c * NW, gp.R, rho, U, Tt, Tr, T)) atomicMin(bad, c);
+    double un = 0.0, dn = 0.0;
+    for (int d = 0; d < D; ++d) {
+      un += U[d] * n[d];
+      dn += g.s_d[so * D + d] * n[d];
+    }
+    const double RTt = gp.R * Tt;
+    rf[f] = fabs(un) + sqrt(5.0 / 3.0 * RTt) + 2.0 * tau_of(rho, Tt, vgas) * RTt / (2.0 * dn);
+  }
   double sc = 1.0;
   if (wall) {
     double nd[2] = {0.0, 0.0};
@@ -548,8 +578,11 @@ __global__ __launch_bounds__(BLOCK) void k_dg_target(Geo g, Leaves L, VGrid vg, 
   dg_close_solve<D>(acc, red, Jm, bv, xv, tg, lam + (size_t)i * NW, i, bad);
 }
 
-// phi^{n+1} = (phi^n + dt/tau g~ - dt/V sum sigma A xi.n phi_f) / (1 + dt/tau),
-// or with init the closed initial state; heat fluxes of the result about U.
+// phi^{n+1} = (phi^n + dt/tau g~ - dt/V sum sigma A xi.n phi_f) / (1 + dt/tau)
+// (init = 0), the closed initial state (init = 1), or the right-hand side of
+// the implicit micro system scaled by dt/V, dt/tau (g~ - phi^n) - dt/V sum
+// sigma A xi.n phi_f (init = 2); heat fluxes of the result about U (not for
+// a right-hand side).
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, DiaGas gp, const double* __restrict__ vin,
                                                     const double* __restrict__ fv, double* __restrict__ vout,
@@ -585,7 +618,7 @@ __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, 
     }
     const double gv = maxw<D>(parr, tabr, vg.numax, u);
     double Ge, He, Re;
-    dg_equilibrium<D>(gp, rho, c, Tt, Tr, r + C::IQT, r + C::IQR, init != 0, maxw<D>(part, tabt, vg.numax, u), gv,
+    dg_equilibrium<D>(gp, rho, c, Tt, Tr, r + C::IQT, r + C::IQR, init == 1, maxw<D>(part, tabt, vg.numax, u), gv,
                       Ge, He, Re);
     double poly = la[0];
 #pragma unroll
@@ -593,7 +626,7 @@ __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, 
     poly += la[1 + D] * c2;
     const double tg[3] = {Ge + poly * gv, He + poly * hid * RT * gv, Re + poly * RT * gv + la[2 + D] * RT * gv};
     double nv[3];
-    if (init) {
+    if (init == 1) {
       for (int p = 0; p < 3; ++p) nv[p] = tg[p];
     } else {
       double div[3] = {0, 0, 0};
@@ -602,8 +635,10 @@ __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, 
         const double w = g.s_sigA[i * MAXF + s] * normal_speed<D>(xi, g.f_nrm + (size_t)f * D);
         for (int p = 0; p < 3; ++p) div[p] += w * fv[p * fs + (size_t)f * L.ld + k];
       }
-      for (int p = 0; p < 3; ++p)
-        nv[p] = (vin[p * cs + (size_t)i * L.ld + k] + dtt * tg[p] - dtv * div[p]) / (1.0 + dtt);
+      for (int p = 0; p < 3; ++p) {
+        const double ph = vin[p * cs + (size_t)i * L.ld + k];
+        nv[p] = init == 2 ? dtt * (tg[p] - ph) - dtv * div[p] : (ph + dtt * tg[p] - dtv * div[p]) / (1.0 + dtt);
+      }
     }
     for (int p = 0; p < 3; ++p) vout[p * cs + (size_t)i * L.ld + k] = nv[p];
     const double et = A * 0.5 * (c2 * nv[0] + nv[1]), er = A * nv[2];
@@ -613,6 +648,7 @@ __global__ __launch_bounds__(BLOCK) void k_dg_update(Geo g, Leaves L, VGrid vg, 
       qa[D + d] += er * c[d];
     }
   }
+  if (init == 2) return;   // a residual: the heat fluxes follow the micro sweeps
   dg_sum<C::NQ>(qa, red);
   if (threadIdx.x < C::NQ) q[(size_t)i * C::NQ + threadIdx.x] = qa[threadIdx.x];
 }
@@ -801,6 +837,157 @@ __global__ __launch_bounds__(BLOCK) void k_dg_close(Geo g, Leaves L, VGrid vg, D
     v[cs + o] = v[cs + o] + poly * hid * RT * gv;
     v[2 * cs + o] = v[2 * cs + o] + (poly * RT * gv + la[2 + D] * RT * gv);
   }
+}
+
+// ------------------------------------------------- implicit step (IUGKS)
+// Euler flux of a diatomic state through n: (rho U.n, rho U U.n + p n,
+// (rho E + p) U.n, rho E_rot U.n), translational pressure p = rho R T_t.
+template <int D>
+__device__ __forceinline__ void dg_euler(const double (&w)[D + 3], const double (&n)[D], double R, double (&G)[D + 3]) {
+  const double rho = w[0];
+  double U[D], uu = 0.0, un = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    U[d] = w[1 + d] / rho;
+    uu += U[d] * U[d];
+    un += U[d] * n[d];
+  }
+  const double Tt = (w[1 + D] - 0.5 * rho * uu - w[2 + D]) / (1.5 * rho * R);
+  const double p = rho * R * Tt;
+  G[0] = rho * un;
+#pragma unroll
+  for (int d = 0; d < D; ++d) G[1 + d] = rho * U[d] * un + p * n[d];
+  G[1 + D] = (w[1 + D] + p) * un;
+  G[2 + D] = w[2 + D] * un;
+}
+
+// a diatomic state reflected in a wall of unit normal n
+template <int D>
+__device__ __forceinline__ void dg_mirror(const double (&w)[D + 3], const double (&n)[D], double (&o)[D + 3]) {
+  double mn = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) mn += w[1 + d] * n[d];
+#pragma unroll
+  for (int m = 0; m < D + 3; ++m) o[m] = w[m];
+#pragma unroll
+  for (int d = 0; d < D; ++d) o[1 + d] = w[1 + d] - 2.0 * mn * n[d];
+}
+
+// One colour of a PRSGS sweep on Eqs. SGS_w and SGS_wrot: as the monatomic
+// sweep, with the rotational row's diagonal and right-hand side raised by
+// k = V/(Z tau) and k (rho R T - rho E_rot^n), tau and rho R T at the
+// cell's current iterate W + dW.
+template <int D>
+__global__ void k_dgi_macro(Geo g, GasP vgas, DiaGas gp, double dt, const int* __restrict__ cells, int ncells,
+                            const double* __restrict__ W, const double* __restrict__ rf,
+                            const double* __restrict__ rhs, const double* __restrict__ diag, double* __restrict__ dW,
+                            int* __restrict__ bad) {
+  constexpr int MAXF = Dg<D>::MAXF, N = D + 3;
+  const int t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t >= ncells) return;
+  const int i = cells[t];
+  const int ns = g.nslot[i];
+  double acc[N], wi[N], di[N];
+  for (int m = 0; m < N; ++m) {
+    acc[m] = rhs[(size_t)i * N + m];
+    wi[m] = W[(size_t)i * N + m];
+    di[m] = dW[(size_t)i * N + m];
+  }
+  for (int s = 0; s < ns; ++s) {
+    const int j = g.s_nbr[i * MAXF + s];
+    const int f = g.s_face[i * MAXF + s];
+    if (j < 0 && !wall_face(g, f)) continue;
+    const double sa = g.s_sigA[i * MAXF + s];
+    const double sig = g.s_sig[i * MAXF + s];
+    const double halfA = 0.5 * (sa * sig);
+    double n[D];
+    for (int d = 0; d < D; ++d) n[d] = sig * g.f_nrm[(size_t)f * D + d];
+    double w0[N], w1[N], dj[N], G0[N], G1[N];
+    if (j >= 0) {
+      for (int m = 0; m < N; ++m) {
+        w0[m] = W[(size_t)j * N + m];
+        dj[m] = dW[(size_t)j * N + m];
+      }
+    } else {
+      dg_mirror<D>(wi, n, w0);
+      dg_mirror<D>(di, n, dj);
+    }
+    for (int m = 0; m < N; ++m) w1[m] = w0[m] + dj[m];
+    dg_euler<D>(w1, n, gp.R, G1);
+    dg_euler<D>(w0, n, gp.R, G0);
+    const double ra = halfA * rf[f];
+    for (int m = 0; m < N; ++m) {
+      acc[m] -= halfA * (G1[m] - G0[m]);
+      acc[m] += ra * dj[m];
+    }
+  }
+  double wc[N];
+  for (int m = 0; m < N; ++m) wc[m] = wi[m] + di[m];
+  double rho, U[D], Tt, Tr, T, k = 0.0;
+  if (dg_temps<D>(wc, gp.R, rho, U, Tt, Tr, T)) {
+    k = dt / g.dtv[i] / (gp.Z * tau_of(rho, Tt, vgas));
+    acc[2 + D] += k * (rho * gp.R * T - wi[2 + D]);
+  } else {
+    atomicMin(bad, i);
+  }
+  const double dg = diag[i];
+  for (int m = 0; m < N; ++m) dW[(size_t)i * N + m] = acc[m] / (m == 2 + D ? dg + k : dg);
+}
+
+// Implicit flux of a face in place over F^n, as the monatomic one with the
+// diatomic Euler flux.
+template <int D>
+__global__ void k_dgi_fhat(Geo g, DiaGas gp, const double* __restrict__ W, const double* __restrict__ dW,
+                           const double* __restrict__ rf, double* __restrict__ F) {
+  constexpr int N = D + 3;
+  const int f = blockIdx.x * BLOCK + threadIdx.x;
+  if (f >= g.nf) return;
+  const int L = g.f_L[f], R = g.f_R[f];
+  const bool wall = R < 0 && g.bc_kind[-1 - R] == 0;
+  double n[D];
+  for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
+  double v[N], w0[N], w1[N], dL[N], G0[N], G1[N], wl[N];
+  for (int m = 0; m < N; ++m) {
+    v[m] = F[(size_t)f * N + m];
+    wl[m] = w0[m] = W[(size_t)L * N + m];
+    dL[m] = dW[(size_t)L * N + m];
+    w1[m] = w0[m] + dL[m];
+  }
+  dg_euler<D>(w1, n, gp.R, G1);
+  dg_euler<D>(w0, n, gp.R, G0);
+  for (int m = 0; m < N; ++m) v[m] = v[m] + 0.5 * (G1[m] - G0[m]);
+  double dR[N];
+  if (R >= 0 || wall) {
+    if (R >= 0) {
+      for (int m = 0; m < N; ++m) {
+        w0[m] = W[(size_t)R * N + m];
+        dR[m] = dW[(size_t)R * N + m];
+      }
+    } else {
+      dg_mirror<D>(wl, n, w0);
+      dg_mirror<D>(dL, n, dR);
+    }
+    for (int m = 0; m < N; ++m) w1[m] = w0[m] + dR[m];
+    dg_euler<D>(w1, n, gp.R, G1);
+    dg_euler<D>(w0, n, gp.R, G0);
+    for (int m = 0; m < N; ++m) v[m] = v[m] + 0.5 * (G1[m] - G0[m]);
+  } else {
+    for (int m = 0; m < N; ++m) dR[m] = 0.0;
+  }
+  const double hr = 0.5 * rf[f];
+  for (int m = 0; m < N; ++m) F[(size_t)f * N + m] = v[m] + hr * (dL[m] - dR[m]);
+}
+
+// out = vin + dphi over the three components (cells as blocks).
+__global__ void k_dgi_finish(int nc, Leaves L, const double* __restrict__ vin, const double* __restrict__ dphi,
+                             double* __restrict__ out) {
+  const int i = blockIdx.x;
+  const size_t cs = (size_t)nc * L.ld;
+  for (int k = threadIdx.x; k < L.n; k += BLOCK)
+    for (int p = 0; p < 3; ++p) {
+      const size_t o = p * cs + (size_t)i * L.ld + k;
+      out[o] = vin[o] + dphi[o];
+    }
 }
 
 }  // namespace avs

@@ -48,10 +48,10 @@ __global__ void k_imp_rface(Geo g, GasP gas, double h, const double* __restrict_
 
 // Right-hand side -sum_f sigma A F_f^n, diagonal V/dt + 1/2 sum_f A r, and
 // dW = 0.
-template <int D>
+template <int D, int N = D + 2>
 __global__ void k_imp_rhs(Geo g, const double* __restrict__ F, const double* __restrict__ rf, double* __restrict__ rhs,
                           double* __restrict__ diag, double* __restrict__ dW) {
-  constexpr int MAXF = Cfg<D>::MAXF, N = D + 2;
+  constexpr int MAXF = Cfg<D>::MAXF;
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= g.nc) return;
   const int ns = g.nslot[i];
@@ -234,11 +234,12 @@ __global__ void k_imp_zero(int P, int nc, Leaves L, T* __restrict__ x) {
 // dt/V: per leaf, dphi_i = (res_i - dt/V sum_{xi.n<0} sigma A xi.n dphi_j)
 // / (1 + dt/tau~ + dt/V sum_{xi.n>=0} sigma A xi.n), res the right-hand side
 // from pass C.  Boundary faces hold the outside increment at zero.
-template <int D, typename T>
+// P components; dt/tau~ of cell i is tpar[i * tstride + toff].
+template <int D, typename T, int P = Cfg<D>::P>
 __global__ __launch_bounds__(BLOCK) void k_imp_micro(Geo g, Leaves L, const int* __restrict__ cells,
                                                      const T* __restrict__ res, T* __restrict__ dphi,
-                                                     const double* __restrict__ tpar) {
-  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+                                                     const double* __restrict__ tpar, int tstride, int toff) {
+  constexpr int MAXF = Cfg<D>::MAXF;
   __shared__ double snrm[MAXF][D];
   __shared__ double ssa[MAXF];
   __shared__ int snbr[MAXF];
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(BLOCK) void k_imp_micro(Geo g, Leaves L, const int*
     for (int d = 0; d < D; ++d) snrm[s][d] = g.f_nrm[(size_t)f * D + d];
   }
   __syncthreads();
-  const double dtt = tpar[(size_t)i * NPAR + P_A], dtv = g.dtv[i];
+  const double dtt = tpar[(size_t)i * tstride + toff], dtv = g.dtv[i];
   const size_t cs = (size_t)g.nc * L.ld;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
     double xi[D], A;

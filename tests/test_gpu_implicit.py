@@ -398,3 +398,62 @@ def test_diatomic_adaptation_against_oracle(avs):
     assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
     dia.close()
     cs.close()
+
+
+def test_diatomic_implicit_periodic_against_oracle(avs):
+    """Implicit diatomic steps (predictor with the rotational row, micro
+    sweeps over G, H, R) on a periodic box at a step 20x the explicit one:
+    three steps with 4/2 sweeps and one with no sweeps against the oracle
+    to 1e-11; mass, momentum and total energy kept."""
+    from oracle import avs_rykov as RY
+    mesh = MM.box2d(5, 4, periodic=(True, True))
+    vs = dict(dim=2, lo=(-6.0, -6.0), hi=(6.0, 6.0), base=(8, 8), max_level=2)
+    vgas = dict(R=0.5, Pr=0.72, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+    rng = np.random.default_rng(131)
+    n = mesh['ncells']
+    prim = np.concatenate([1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.3 * rng.uniform(-1, 1, (n, 2)),
+                           1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.8 + 0.1 * rng.uniform(-1, 1, (n, 1))], axis=1)
+    cs, dia, o = dia_pair(avs, mesh, vs, vgas, 0.04, prim, random_tree(vs, 132, 2))
+    tot0 = o.totals()
+    for sweeps in [(4, 2), (4, 2), (4, 2), (0, 0)]:
+        dia.step_implicit(1, *sweeps)
+        o.step_implicit(1, *sweeps)
+        v, W = dia.get_state()
+        assert rel(v, o.phi) < 1e-11 and rel(W, o.W) < 1e-11, sweeps
+    tot = o.totals()
+    np.testing.assert_allclose(tot[:4], tot0[:4], rtol=1e-13, atol=1e-13)
+    dia.close()
+    cs.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_diatomic_implicit_walls_against_oracle(avs, dim):
+    """Implicit diatomic steps with boundaries: an O-grid with an isothermal
+    wall and a Ma 2 far field (2-D), a box with walls in y (3-D); two steps
+    against the oracle to 1e-11."""
+    from oracle import avs_rykov as RY
+    if dim == 2:
+        c = F.cylinder(nr=5, nth=14, Ma=2.0, box=8.0, base=8, max_level=2, r1=2.5, first=0.1)
+        vgas = dict(c['gas'], Pr=0.72, omega=0.74)
+        p = c['prim0']
+        prim = np.concatenate([p[:, :3], p[:, 3:4], 0.9 * p[:, 3:4]], axis=1)
+        cs, dia, o = dia_pair(avs, c['mesh'], c['vspace'], vgas, 4 * c['dt'], prim, resolved_tree(c['vspace'], 133),
+                              Kv=0.0)
+    else:
+        mesh = MM.box3d(3, 3, 2, periodic=(True, False, True))
+        vs = dict(dim=3, lo=(-5.0,) * 3, hi=(5.0,) * 3, base=(4, 4, 4), max_level=2)
+        vgas = dict(R=0.5, Pr=0.72, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+        rng = np.random.default_rng(134)
+        n = mesh['ncells']
+        prim = np.concatenate([1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.3 * rng.uniform(-1, 1, (n, 3)),
+                               1 + 0.2 * rng.uniform(-1, 1, (n, 1)), 0.7 + 0.1 * rng.uniform(-1, 1, (n, 1))], axis=1)
+        cs, dia, o = dia_pair(avs, mesh, vs, vgas, 0.02, prim, random_tree(vs, 135, 2))
+    for _ in range(2):
+        dia.step_implicit(1, 3, 2)
+        o.step_implicit(1, 3, 2)
+        v, W = dia.get_state()
+        assert rel(v, o.phi) < 1e-11 and rel(W, o.W) < 1e-11
+    with pytest.raises(avs.AvsError):
+        dia.step_implicit(1, -1, 2)
+    dia.close()
+    cs.close()
