@@ -127,22 +127,6 @@ __device__ __forceinline__ void dg_mom(double* m, double A, const double (&xi)[D
   m[2 + D] += A * Rr;
 }
 
-// Venkatakrishnan psi for one face, the same branches as its definition
-// divided through by D2 (and, for eps = 0, through t = D2/D1 or 1/t).
-__device__ __forceinline__ double dg_psi(double d1, double d2, double eps2) {
-  if (d2 == 0.0) return 1.0;
-  if (eps2 > 0.0) return (d1 * d1 + eps2 + 2.0 * d1 * d2) / (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2);
-  if (fabs(d2) <= fabs(d1)) {
-    const double t = d2 / d1;
-    return (1.0 + 2.0 * t) / (1.0 + t + 2.0 * t * t);
-  }
-  const double u = d1 / d2;
-  return u * (u + 2.0) / (u * u + u + 2.0);
-}
-
-// Grid (cells in XCD order, leaf chunks) with cells fastest: a cell and its
-// neighbours read the same chunk of their rows at about the same time, so
-// that the neighbour rows come from L2.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, const double* __restrict__ vin,
                                                    double* __restrict__ fv, DiaGas gp, int chunk) {
@@ -163,6 +147,16 @@ __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, c
     if (j >= 0) mask |= 1u << s;
     nb[s] = (size_t)(j >= 0 ? j : i) * L.ld;
   }
+  // the cell's LSQ coefficients and face offsets, held for the leaf loop
+  double cf[MAXF][D], dd[MAXF][D];
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s)
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      cf[s][d] = s < ns ? g.s_lsq[(size_t)(i * MAXF + s) * D + d] : 0.0;
+      dd[s][d] = s < ns ? g.s_d[(size_t)(i * MAXF + s) * D + d] : 0.0;
+    }
+  const double eps2 = g.eps2[i];
   for (int k = k0 + threadIdx.x; k < k1; k += BLOCK) {
     double xi[D], A;
     int u[D];
@@ -188,23 +182,55 @@ __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, c
         const double v = nv[s][p];
         const double dv = v - ph[p];
 #pragma unroll
-        for (int d = 0; d < D; ++d) gr[p][d] += dv * g.s_lsq[(size_t)(i * MAXF + s) * D + d];
+        for (int d = 0; d < D; ++d) gr[p][d] += dv * cf[s][d];
         pmax[p] = fmax(pmax[p], v);
         pmin[p] = fmin(pmin[p], v);
       }
     }
-    const double eps2 = g.eps2[i];
+    // Venkatakrishnan psi_f = N/Dn with a = |D2|, b = |D1| (same sign),
+    // N = b^2 + eps^2 + 2ab, Dn = b^2 + 2a^2 + ab + eps^2 (psi = 1 for
+    // D2 = 0); a, b and eps scaled by the power of two above the largest of
+    // them, the minimum over faces kept as a fraction by cross-multiplication
+    // and ended by one division
     double lg[3][D];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-      double lim = ns > 0 ? INFINITY : 1.0;
-      for (int s = 0; s < ns; ++s) {
-        const double* dd = g.s_d + (size_t)(i * MAXF + s) * D;
+      double d2s[MAXF];
+      const double up0 = pmax[p] - ph[p], dn0 = ph[p] - pmin[p];
+      double mx = fmax(up0, dn0);
+#pragma unroll
+      for (int s = 0; s < MAXF; ++s) {
         double d2 = 0.0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) d2 += gr[p][d] * dd[d];
-        const double d1 = d2 > 0.0 ? pmax[p] - ph[p] : pmin[p] - ph[p];
-        lim = fmin(lim, dg_psi(d1, d2, eps2));
+        for (int d = 0; d < D; ++d) d2 += gr[p][d] * dd[s][d];
+        d2s[s] = d2;
+        if (s < ns) mx = fmax(fabs(d2), mx);
+      }
+      double lim = 1.0;
+      // below the smallest normal number the differences carry no
+      // information: the slope stays unlimited
+      if (ns > 0 && mx > 1e-300) {
+        int ex;
+        (void)frexp(mx, &ex);
+        const double inv = ldexp(1.0, -ex);
+        const double e2 = fmin(eps2 * inv * inv, 1e30);
+        const double up = up0 * inv, dn = dn0 * inv;
+        double Nm = 1.0, Dm = 0.0;
+#pragma unroll
+        for (int s = 0; s < MAXF; ++s) {
+          if (s < ns) {
+            const double a = fabs(d2s[s]) * inv;
+            const double b = d2s[s] > 0.0 ? up : dn;
+            const double c = b * b + e2 + 1e-300;
+            const double Nn = c + 2.0 * a * b;
+            const double Dd = c + a * (2.0 * a + b);
+            if (Nn * Dm < Nm * Dd) {
+              Nm = Nn;
+              Dm = Dd;
+            }
+          }
+        }
+        lim = Nm / Dm;
       }
 #pragma unroll
       for (int d = 0; d < D; ++d) lg[p][d] = lim * gr[p][d];
@@ -217,10 +243,9 @@ __global__ __launch_bounds__(BLOCK) void k_dg_recon(Geo g, Leaves L, double h, c
       const int Rc = g.f_R[f];
       const size_t o = (size_t)f * L.ld + k;
       if (upwind) {
-        const double* dd = g.s_d + (size_t)(i * MAXF + s) * D;
         double r[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) r[d] = dd[d] - xi[d] * h;
+        for (int d = 0; d < D; ++d) r[d] = g.s_d[(size_t)(i * MAXF + s) * D + d] - xi[d] * h;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
           double x = 0.0;
