@@ -1408,12 +1408,18 @@ avs_status dia_steps_implicit(avs_dia* d, int nsteps, int n_macro, int n_micro) 
       for (int t = 0; t < 2 * ncol; ++t) {
         const int cc = t < ncol ? t : 2 * ncol - 1 - t;
         const int cnt = ctx->col_off[cc + 1] - ctx->col_off[cc];
+        // the backward half of the last sweep visits every cell for the last
+        // time and writes phi^{n+1} over its right-hand side
+        const bool last = sw == n_micro - 1 && t >= ncol;
         k_imp_micro<D, double, 3><<<(unsigned)cnt, BLOCK, 0, ctx->stream>>>(
-            ctx->geo, L, ctx->col_cells + ctx->col_off[cc], res, dphi, d->tp, Dg<D>::NT, Dg<D>::IDT);
+            ctx->geo, L, ctx->col_cells + ctx->col_off[cc], res, dphi, d->tp, Dg<D>::NT, Dg<D>::IDT,
+            last ? d->v[c] : nullptr, last ? d->v[c ^ 1] : nullptr);
         CKL();
       }
-    k_dgi_finish<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->nc, L, d->v[c], dphi, d->v[c ^ 1]);
-    CKL();
+    if (n_micro == 0) {
+      k_dgi_finish<<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->nc, L, d->v[c], dphi, d->v[c ^ 1]);
+      CKL();
+    }
     k_dg_heat<D><<<ctx->nc, BLOCK, 0, ctx->stream>>>(ctx->geo, L, d->v[c ^ 1], d->tp, d->q);
     CKL();
     d->cur ^= 1;

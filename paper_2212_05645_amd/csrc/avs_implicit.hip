@@ -234,11 +234,15 @@ __global__ void k_imp_zero(int P, int nc, Leaves L, T* __restrict__ x) {
 // dt/V: per leaf, dphi_i = (res_i - dt/V sum_{xi.n<0} sigma A xi.n dphi_j)
 // / (1 + dt/tau~ + dt/V sum_{xi.n>=0} sigma A xi.n), res the right-hand side
 // from pass C.  Boundary faces hold the outside increment at zero.
-// P components; dt/tau~ of cell i is tpar[i * tstride + toff].
+// P components; dt/tau~ of cell i is tpar[i * tstride + toff].  With out
+// (the cell's last visit of the last sweep, when its increment is final),
+// also out = vin + dphi; out may be the buffer of res, which only the cell
+// itself reads.
 template <int D, typename T, int P = Cfg<D>::P>
 __global__ __launch_bounds__(BLOCK) void k_imp_micro(Geo g, Leaves L, const int* __restrict__ cells,
-                                                     const T* __restrict__ res, T* __restrict__ dphi,
-                                                     const double* __restrict__ tpar, int tstride, int toff) {
+                                                     const T* res, T* __restrict__ dphi,
+                                                     const double* __restrict__ tpar, int tstride, int toff,
+                                                     const T* __restrict__ vin = nullptr, T* out = nullptr) {
   constexpr int MAXF = Cfg<D>::MAXF;
   __shared__ double snrm[MAXF][D];
   __shared__ double ssa[MAXF];
@@ -275,7 +279,11 @@ __global__ __launch_bounds__(BLOCK) void k_imp_micro(Geo g, Leaves L, const int*
     }
     const size_t o = (size_t)i * L.ld + k;
 #pragma unroll
-    for (int p = 0; p < P; ++p) dphi[p * cs + o] = (res[p * cs + o] - (T)dtv * off[p]) / (T)dg;
+    for (int p = 0; p < P; ++p) {
+      const T x = (res[p * cs + o] - (T)dtv * off[p]) / (T)dg;
+      dphi[p * cs + o] = x;
+      if (out) out[p * cs + o] = vin[p * cs + o] + x;
+    }
   }
 }
 
