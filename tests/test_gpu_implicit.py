@@ -457,3 +457,25 @@ def test_diatomic_implicit_walls_against_oracle(avs, dim):
         dia.step_implicit(1, -1, 2)
     dia.close()
     cs.close()
+
+
+def test_diatomic_sphere_explicit_and_implicit(avs):
+    """The paper's sphere case with the Rykov gas, small: a spherical grid
+    with an isothermal wall and a Ma 2 far field in 3-D, T_r = 0.9 T_t;
+    two explicit steps, then one implicit step with 3/2 sweeps, against
+    the oracle to 1e-11."""
+    c = F.sphere(nr=3, nth=4, nph=4, Ma=2.0, box=5.0, base=8, max_level=1, r1=1.5, first=0.2)
+    vgas = dict(c['gas'], Pr=0.72, omega=0.74)
+    p = c['prim0']
+    prim = np.concatenate([p[:, :4], p[:, 4:5], 0.9 * p[:, 4:5]], axis=1)
+    cs, dia, o = dia_pair(avs, c['mesh'], c['vspace'], vgas, c['dt'], prim, resolved_tree(c['vspace'], 136), Kv=0.0)
+    dia.step(2)
+    o.step(2)
+    v, W = dia.get_state()
+    assert W.shape[1] == 6 and rel(v, o.phi) < 1e-11 and rel(W, o.W) < 1e-11
+    dia.step_implicit(1, 3, 2)
+    o.step_implicit(1, 3, 2)
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-11 and rel(W, o.W) < 1e-11
+    dia.close()
+    cs.close()
