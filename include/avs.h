@@ -223,14 +223,19 @@ avs_status avs_dia_step_implicit(avs_dia *dia, int32_t nsteps, int32_t n_macro, 
 /* Adaptation of the velocity tree driven by the diatomic state (Secs.
  * 3.2-3.4): M_k = max over cells of max(M1, M2), M1 = A G / rho, M2 =
  * A (1/2 (|c|^2 G + H) + R) / (rho E - rho |U|^2 / 2) (the internal energy
- * includes rotation); flags and plan as avs_adapt (no probe states).
+ * includes rotation), over the cells and over the nprobes probe states:
+ * rows (rho, U, T) [nprobes][D+2] of equilibrium states (T_t = T_r = T)
+ * whose VDF is the equilibrium triple (g, (3 - D) R T g, R T g), internal
+ * energy 5/2 rho R T (at most the context's probe capacity; NULL with 0).
+ * Flags and plan as avs_adapt.
  * flags_dev and n_new_host as in avs_adapt; AVS_E_CAPACITY (plan discarded)
  * beyond the state's max_leaves or the context's capacity.
  * avs_dia_remap applies the plan: consanguinity reconstruction of G, H, R
  * and the closure onto W, the heat fluxes of the result, and avs_remap(ctx,
  * 0) for the context's own state, which moves the context to the new
  * leaves; the diatomic state follows them. */
-avs_status avs_dia_adapt(avs_dia *dia, double C1, double C2, int8_t *flags_dev, int64_t *n_new_host);
+avs_status avs_dia_adapt(avs_dia *dia, double C1, double C2, const double *probes_host, int32_t nprobes,
+                         int8_t *flags_dev, int64_t *n_new_host);
 avs_status avs_dia_remap(avs_dia *dia);
 void avs_dia_destroy(avs_dia *dia);
 

@@ -472,28 +472,41 @@ class DiatomicSolver:
 # onto W (the diatomic counterpart of correction 2 without its literal
 # equilibrium difference); no probe states.
 
-def criterion_dia(phi, W, tree):
-    """M_k = max over cells of max(M1, M2), in a fixed operation order (no
-    fused multiply-add) so that it can be compared bit for bit."""
-    D = tree.dim
+def _crit_dia_one(G, H, Rr, Wi, xi, A):
+    """max(M1, M2) of one state over all leaves, in the fixed operation order."""
+    D = xi.shape[1]
+    rho = Wi[0]
+    U = [Wi[1 + d] / rho for d in range(D)]
+    ke = U[0] * U[0]
+    for d in range(1, D):
+        ke = ke + U[d] * U[d]
+    eint = Wi[1 + D] - 0.5 * rho * ke
+    c = xi[:, 0] - U[0]
+    c2 = c * c
+    for d in range(1, D):
+        c = xi[:, d] - U[d]
+        c2 = c2 + c * c
+    M1 = (A * G) / rho
+    M2 = (A * (0.5 * (c2 * G + H) + Rr)) / eint
+    return np.maximum(M1, M2)
+
+
+def criterion_dia(phi, W, tree, probes=None, R=None):
+    """M_k = max over cells (and over probe states) of max(M1, M2), in a
+    fixed operation order (no fused multiply-add) so that it can be compared
+    bit for bit.  ``probes`` are rows (rho, U, T) of equilibrium states
+    (T_t = T_r = T) whose VDF is the equilibrium triple; R is the gas
+    constant."""
     xi, A = tree.centres(), tree.weights()
     Mk = np.full(tree.n, -np.inf)
     for i in range(phi.shape[1]):
-        rho = W[i, 0]
-        U = [W[i, 1 + d] / rho for d in range(D)]
-        ke = U[0] * U[0]
-        for d in range(1, D):
-            ke = ke + U[d] * U[d]
-        eint = W[i, 1 + D] - 0.5 * rho * ke
-        c = xi[:, 0] - U[0]
-        c2 = c * c
-        for d in range(1, D):
-            c = xi[:, d] - U[d]
-            c2 = c2 + c * c
-        G, H, Rr = phi[0, i], phi[1, i], phi[2, i]
-        M1 = (A * G) / rho
-        M2 = (A * (0.5 * (c2 * G + H) + Rr)) / eint
-        Mk = np.maximum(Mk, np.maximum(M1, M2))
+        Mk = np.maximum(Mk, _crit_dia_one(phi[0, i], phi[1, i], phi[2, i], W[i], xi, A))
+    if probes is not None:
+        D = tree.dim
+        for p in np.atleast_2d(probes):
+            rho, U, T = p[0], np.asarray(p[1:1 + D], np.float64), p[1 + D]
+            tri = triple(rho, U, T, xi, R)
+            Mk = np.maximum(Mk, _crit_dia_one(tri[0], tri[1], tri[2], conserved(rho, U, T, T, R), xi, A))
     return Mk
 
 
@@ -507,8 +520,8 @@ def remap_dia(phi, plan, W, R):
     return out
 
 
-def _adapt(self, C1, C2):
-    Mk = criterion_dia(self.phi, self.W, self.tree)
+def _adapt(self, C1, C2, probes=None):
+    Mk = criterion_dia(self.phi, self.W, self.tree, probes, self.gas.R)
     raw = _O.raw_flags(Mk, self.tree, C1, C2)
     eff = _O.resolve_merges(raw, self.tree)
     self.plan = _O.make_plan(eff, self.tree)

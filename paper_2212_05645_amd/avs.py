@@ -128,7 +128,7 @@ def _load():
         "avs_rykov_equilibrium": (I32, [VP, P(avs_rykov), VP, I64, VP, C.c_size_t]),
         "avs_dia_bytes": (I32, [VP, I64, P(C.c_size_t)]),
         "avs_dia_create": (I32, [VP, P(avs_rykov), VP, I64, VP, C.c_size_t, P(VP)]),
-        "avs_dia_adapt": (I32, [VP, D, D, VP, P(I64)]),
+        "avs_dia_adapt": (I32, [VP, D, D, VP, I32, VP, P(I64)]),
         "avs_dia_remap": (I32, [VP]),
         "avs_dia_step": (I32, [VP, I32]),
         "avs_dia_step_implicit": (I32, [VP, I32, I32, I32]),
@@ -524,13 +524,19 @@ class Diatomic:
                                   C.byref(h)))
         self.h = h
 
-    def adapt(self, C1, C2):
-        """Adaptation driven by the diatomic state; returns (flags, n_new)."""
+    def adapt(self, C1, C2, probes=None):
+        """Adaptation driven by the diatomic state and the optional probe
+        rows (rho, U, T) of equilibrium states; returns (flags, n_new)."""
         t = self.case._torch
         n_old = self.case.nleaves()
         flags = t.empty(max(n_old, 1), dtype=t.int8, device=self.case.device)
         nn = C.c_int64()
-        _check(lib.avs_dia_adapt(self.h, float(C1), float(C2), flags.data_ptr(), C.byref(nn)))
+        pr = np.ascontiguousarray(np.atleast_2d(probes), dtype=np.float64) if probes is not None else None
+        npr = 0 if pr is None else pr.shape[0]
+        if pr is not None and pr.shape[1] != self.case.dim + 2:
+            raise ValueError(f"probe rows must have {self.case.dim + 2} entries")
+        _check(lib.avs_dia_adapt(self.h, float(C1), float(C2), None if pr is None else pr.ctypes.data, npr,
+                                 flags.data_ptr(), C.byref(nn)))
         t.cuda.synchronize(self.case.device)
         return flags[:n_old].cpu().numpy(), nn.value
 

@@ -1258,6 +1258,7 @@ avs_status avs_rykov_equilibrium(avs_ctx* ctx, const avs_rykov* gas, const doubl
 
 // ------------------------------------------------ diatomic (Rykov) path
 static avs_status finish_plan(avs_ctx* ctx, int8_t* flags_dev, int64_t* n_new_host, bool* capacity_ok);
+static avs_status upload_probes(avs_ctx* ctx, const double* probes_host, int32_t nprobes);
 
 struct avs_dia {
   avs_ctx* ctx = nullptr;
@@ -1428,12 +1429,13 @@ avs_status dia_steps_implicit(avs_dia* d, int nsteps, int n_macro, int n_micro) 
 }
 
 template <int D>
-avs_status dia_criterion(avs_dia* d, double C1, double C2) {
+avs_status dia_criterion(avs_dia* d, double C1, double C2, int nprobes) {
   avs_ctx* ctx = d->ctx;
   const Leaves L = ctx->leaves(ctx->lcur);
   const int nb = (L.n + BLOCK - 1) / BLOCK;
   k_dg_crit_partial<D><<<dim3(nb, ctx->ngrp), BLOCK, 0, ctx->stream>>>(L, ctx->nc, d->v[d->cur], d->W[d->cur],
-                                                                      ctx->crit_part);
+                                                                      ctx->crit_part, nprobes, ctx->probe_prim,
+                                                                      ctx->gas.R);
   CKL();
   k_crit_reduce<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->ngrp, ctx->crit_part, 0, ctx->probe_cc, ctx->probe_prim,
                                                  ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
@@ -1568,14 +1570,17 @@ avs_status avs_dia_get_state(avs_dia* d, double* vdf_host, double* W_host) {
   return AVS_OK;
 }
 
-avs_status avs_dia_adapt(avs_dia* d, double C1, double C2, int8_t* flags_dev, int64_t* n_new_host) {
+avs_status avs_dia_adapt(avs_dia* d, double C1, double C2, const double* probes_host, int32_t nprobes,
+                         int8_t* flags_dev, int64_t* n_new_host) {
   if (!d) return fail(AVS_E_INVALID, "null diatomic state");
   avs_ctx* ctx = d->ctx;
   if (avs_status st = guard(ctx)) return st;
   if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
   if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
   ctx->plan_valid = false;
-  if (avs_status st = ctx->D == 2 ? dia_criterion<2>(d, C1, C2) : dia_criterion<3>(d, C1, C2)) return st;
+  if (avs_status st = upload_probes(ctx, probes_host, nprobes)) return st;
+  if (avs_status st = ctx->D == 2 ? dia_criterion<2>(d, C1, C2, nprobes) : dia_criterion<3>(d, C1, C2, nprobes))
+    return st;
   int64_t nn = 0;
   if (avs_status st = finish_plan(ctx, flags_dev, &nn, nullptr)) return st;
   if (n_new_host) *n_new_host = nn;

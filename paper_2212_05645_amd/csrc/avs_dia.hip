@@ -737,9 +737,13 @@ __global__ __launch_bounds__(BLOCK) void k_dg_heat(Geo g, Leaves L, const double
 // M2 = A (1/2 (|c|^2 G + H) + R) / (rho E - rho |U|^2/2), max over the group,
 // in a fixed operation order (no contraction) so that the flags are
 // reproducible bit for bit.
+// The first group also takes the nprobe probe states (rho, U, T) with the
+// equilibrium triple (g, (3-D) R T g, R T g) and internal energy 5/2 rho R T.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_crit_partial(Leaves L, int nc, const double* __restrict__ vdf,
-                                                          const double* __restrict__ W, double* __restrict__ part) {
+                                                          const double* __restrict__ W, double* __restrict__ part,
+                                                          int nprobe, const double* __restrict__ probe_prim,
+                                                          double R) {
 #pragma clang fp contract(off)
   constexpr int NW = Dg<D>::NW;
   const int k = blockIdx.x * BLOCK + threadIdx.x;
@@ -770,6 +774,22 @@ __global__ __launch_bounds__(BLOCK) void k_dg_crit_partial(Leaves L, int nc, con
     const double M1 = (A * G) / rho;
     const double M2 = (A * (0.5 * (c2 * G + H) + Rr)) / eint;
     m = fmax(m, fmax(M1, M2));
+  }
+  if (grp == 0) {
+    for (int p = 0; p < nprobe; ++p) {
+      const double* pr = probe_prim + (size_t)p * (D + 2);
+      const double rho = pr[0], RT = R * pr[1 + D];
+      double c = xi[0] - pr[1];
+      double c2 = c * c;
+      for (int d = 1; d < D; ++d) {
+        c = xi[d] - pr[1 + d];
+        c2 = c2 + c * c;
+      }
+      const double G = rho * pow(2.0 * M_PI * RT, -0.5 * D) * exp(-c2 / (2.0 * RT));
+      const double M1 = (A * G) / rho;
+      const double M2 = (A * (0.5 * (c2 * G + (3 - D) * RT * G) + RT * G)) / (2.5 * rho * RT);
+      m = fmax(m, fmax(M1, M2));
+    }
   }
   part[(size_t)grp * L.cap + k] = m;
 }

@@ -479,3 +479,39 @@ def test_diatomic_sphere_explicit_and_implicit(avs):
     assert rel(v, o.phi) < 1e-11 and rel(W, o.W) < 1e-11
     dia.close()
     cs.close()
+
+
+def test_diatomic_adaptation_with_probe_states(avs):
+    """Probe states in the diatomic criterion: a fast, hot equilibrium
+    probe outside the cells' states adds splits where no cell needs them;
+    flags bit exact against the oracle (thresholds between neighbouring
+    M_k), and different from the flags without the probe."""
+    from oracle import avs_rykov as RY
+    mesh = MM.box2d(4, 3, periodic=(True, True))
+    vs = dict(dim=2, lo=(-8.0, -8.0), hi=(8.0, 8.0), base=(8, 8), max_level=2)
+    vgas = dict(R=0.5, Pr=0.72, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+    rng = np.random.default_rng(141)
+    n = mesh['ncells']
+    prim = np.concatenate([1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.2 * rng.uniform(-1, 1, (n, 2)),
+                           1 + 0.1 * rng.uniform(-1, 1, (n, 1)), 0.9 + 0.05 * rng.uniform(-1, 1, (n, 1))], axis=1)
+    probe = np.array([[0.7, 3.0, 1.0, 1.6]])
+    cs, dia, o = dia_pair(avs, mesh, vs, vgas, 2e-3, prim, random_tree(vs, 142, 1), max_leaves=1024)
+    Mk = np.sort(RY.criterion_dia(o.phi, o.W, o.tree, probe, 0.5))
+
+    def gap(j):                      # the nearest index above j with a gap to the next value
+        while not Mk[j + 1] - Mk[j] > 1e-9 * Mk[j]:
+            j += 1
+        return j
+    j1, j2 = gap(int(0.8 * len(Mk))), gap(int(0.2 * len(Mk)))
+    C1, C2 = 0.5 * (Mk[j1] + Mk[j1 + 1]), 0.5 * (Mk[j2] + Mk[j2 + 1])
+    flags0, _ = dia.adapt(C1, C2)
+    flags, nn = dia.adapt(C1, C2, probes=probe)
+    eff, plan, _ = o.adapt(C1, C2, probe)
+    assert np.array_equal(flags, eff) and nn == plan.tree.n
+    assert not np.array_equal(flags, flags0)
+    dia.remap()
+    o.remap()
+    v, W = dia.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-13
+    dia.close()
+    cs.close()

@@ -276,3 +276,21 @@ def test_implicit_diatomic_conserves_and_tends_to_the_explicit_step():
         e.append((np.abs(pi - pe).max() / np.abs(pe - c.phi).max(), np.abs(Wi - We).max() / np.abs(We - c.W).max()))
     for a, b in zip(e, e[1:]):
         assert 1.8 < a[0] / b[0] < 2.2 and 1.8 < a[1] / b[1] < 2.2
+
+
+def test_diatomic_criterion_probe_equals_an_equilibrium_cell():
+    """A probe state is counted as an equilibrium cell: with one cell set to
+    the equilibrium triple of (rho, U, T), the criterion of that cell alone
+    equals the criterion of the probe (rho, U, T) alone to round-off, and a
+    probe only ever raises M_k."""
+    s = periodic_case(nx=2, ny=2, max_level=1)
+    xi = s.tree.centres()
+    rho, U, T = 0.8, np.array([0.3, -0.2]), 1.2
+    phi = RY.triple(rho, U, T, xi, 0.5)[:, None, :]
+    W = RY.conserved(rho, U, T, T, 0.5)[None, :]
+    m_cell = RY.criterion_dia(phi, W, s.tree)
+    m_probe = RY.criterion_dia(phi[:, :0], W[:0], s.tree, probes=[[rho, *U, T]], R=0.5)
+    np.testing.assert_allclose(m_probe, m_cell, rtol=1e-14)
+    base = RY.criterion_dia(s.phi, s.W, s.tree)
+    both = RY.criterion_dia(s.phi, s.W, s.tree, probes=[[rho, *U, T]], R=0.5)
+    assert np.all(both >= base) and np.array_equal(both, np.maximum(base, m_probe))
