@@ -515,3 +515,39 @@ def test_diatomic_adaptation_with_probe_states(avs):
     assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-13
     dia.close()
     cs.close()
+
+
+def test_diatomic_argument_errors(avs):
+    """The diatomic entry points refuse bad arguments with an error and
+    leave the state usable: Rykov parameters out of range, a non-physical
+    or misshaped initial state, max_leaves beyond the capacity, negative
+    step or sweep counts, probe rows of the wrong width."""
+    mesh = MM.box2d(3, 3, periodic=(True, True))
+    vs = dict(dim=2, lo=(-6.0, -6.0), hi=(6.0, 6.0), base=(8, 8), max_level=1)
+    vgas = dict(R=0.5, Pr=0.72, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+    n = mesh['ncells']
+    prim = np.tile([1.0, 0.1, 0.0, 1.0, 0.9], (n, 1))
+    cs = avs.Case(mesh, vs, vgas, 2e-3, 1.0, np.ascontiguousarray(prim[:, :4]))
+    for kw in (dict(Z_rot=0.5), dict(delta=0.0), dict(delta=1.5), dict(omega0=float('nan'))):
+        with pytest.raises(avs.AvsError):
+            avs.Diatomic(cs, prim, **kw)
+    bad = prim.copy()
+    bad[4, 4] = -1.0
+    with pytest.raises(avs.AvsError):
+        avs.Diatomic(cs, bad)
+    with pytest.raises(ValueError):
+        avs.Diatomic(cs, prim[:, :4])
+    with pytest.raises(avs.AvsError):
+        avs.Diatomic(cs, prim, max_leaves=10 ** 6)
+    dia = avs.Diatomic(cs, prim)
+    for call in (lambda: dia.step(-1), lambda: dia.step_implicit(1, 2, -1), lambda: dia.step_implicit(-1, 2, 2)):
+        with pytest.raises(avs.AvsError):
+            call()
+    with pytest.raises(ValueError):
+        dia.adapt(1e-3, 1e-6, probes=[[1.0, 0.0, 1.0]])
+    dia.step(1)
+    dia.step_implicit(1, 2, 2)
+    v, W = dia.get_state()
+    assert np.isfinite(v).all() and np.allclose(W[:, 0], 1.0, rtol=1e-12)
+    dia.close()
+    cs.close()
