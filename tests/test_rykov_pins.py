@@ -294,3 +294,13 @@ def test_diatomic_criterion_probe_equals_an_equilibrium_cell():
     base = RY.criterion_dia(s.phi, s.W, s.tree)
     both = RY.criterion_dia(s.phi, s.W, s.tree, probes=[[rho, *U, T]], R=0.5)
     assert np.all(both >= base) and np.array_equal(both, np.maximum(base, m_probe))
+
+
+def test_implicit_diatomic_without_sweeps_is_the_explicit_macro_update():
+    """No sweeps: dW = 0, so the implicit flux is F^n exactly and W^{n+1}
+    equals the explicit step's bit for bit (transport, then the same
+    rotational exchange); with no micro sweeps phi is unchanged."""
+    s = periodic_case()
+    pe, We = RY.step_dia(s.mesh, s.tree, s.vgas, s.gas, s.dt, s.Kv, s.phi, s.W)
+    pi, Wi, Wp = RY.step_implicit_dia(s.mesh, s.tree, s.vgas, s.gas, s.dt, s.Kv, s.phi, s.W, 0, 0)
+    assert np.array_equal(Wi, We) and np.array_equal(Wp, s.W) and np.array_equal(pi, s.phi)
