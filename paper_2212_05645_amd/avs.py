@@ -225,6 +225,7 @@ class Case:
             vs.hi[d] = float(vspace["hi"][d])
         nroot = int(np.prod([vs.base[d] for d in range(D)]))
         vs.leaf_capacity = int(leaf_capacity if leaf_capacity is not None else nroot * (2 ** D) ** vs.max_level)
+        self.leaf_capacity = vs.leaf_capacity
         g = avs_gas()
         g.R, g.Pr, g.omega, g.T_ref = (float(gas[k]) for k in ("R", "Pr", "omega", "T_ref"))
         g.mu_ref = float(gas["mu_ref"]) if gas.get("mu_ref") is not None else mu_ref_from_kn(
