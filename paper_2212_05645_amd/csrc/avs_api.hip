@@ -96,6 +96,10 @@ struct avs_ctx {
   int nprobe_max = 64;
   int plan_n = 0;
   bool plan_valid = false;
+  // the diatomic state whose adaptation made the current plan (nullptr: a
+  // monatomic adaptation made it); a diatomic remap needs its own plan,
+  // whose leaf count its rows were checked against
+  const void* plan_owner = nullptr;
 
   // optional per-kernel timing with HIP events (measurement only)
   bool prof = false;
@@ -353,6 +357,20 @@ void conserved_host(int D, double R, const double* prim, double* W) {
   W[0] = rho;
   for (int d = 0; d < D; ++d) W[1 + d] = rho * prim[1 + d];
   W[1 + D] = ke + 1.5 * rho * R * prim[1 + D];
+}
+
+// Diatomic conserved state (rho, rho U, rho E, rho E_rot) of an equilibrium
+// probe (T_t = T_r = T), in the oracle's operation order: rho E_rot = rho R T,
+// rho E = rho|U|^2/2 + 3/2 rho R T + rho E_rot.
+void conserved_dia_host(int D, double R, const double* prim, double* W) {
+#pragma clang fp contract(off)
+  const double rho = prim[0], T = prim[1 + D];
+  double ss = prim[1] * prim[1];
+  for (int d = 1; d < D; ++d) ss = ss + prim[1 + d] * prim[1 + d];
+  W[0] = rho;
+  for (int d = 0; d < D; ++d) W[1 + d] = rho * prim[1 + d];
+  W[2 + D] = rho * R * T;
+  W[1 + D] = 0.5 * rho * ss + 1.5 * rho * R * T + W[2 + D];
 }
 
 void crit_consts_host(int D, const double* W, double* o) {
@@ -1258,7 +1276,7 @@ avs_status avs_rykov_equilibrium(avs_ctx* ctx, const avs_rykov* gas, const doubl
 
 // ------------------------------------------------ diatomic (Rykov) path
 static avs_status finish_plan(avs_ctx* ctx, int8_t* flags_dev, int64_t* n_new_host, bool* capacity_ok);
-static avs_status upload_probes(avs_ctx* ctx, const double* probes_host, int32_t nprobes);
+static avs_status upload_probes(avs_ctx* ctx, const double* probes_host, int32_t nprobes, bool diatomic = false);
 
 struct avs_dia {
   avs_ctx* ctx = nullptr;
@@ -1434,8 +1452,8 @@ avs_status dia_criterion(avs_dia* d, double C1, double C2, int nprobes) {
   const Leaves L = ctx->leaves(ctx->lcur);
   const int nb = (L.n + BLOCK - 1) / BLOCK;
   k_dg_crit_partial<D><<<dim3(nb, ctx->ngrp), BLOCK, 0, ctx->stream>>>(L, ctx->nc, d->v[d->cur], d->W[d->cur],
-                                                                      ctx->crit_part, nprobes, ctx->probe_prim,
-                                                                      ctx->gas.R);
+                                                                      ctx->crit_part, nprobes, ctx->probe_cc,
+                                                                      ctx->probe_prim, ctx->gas.R);
   CKL();
   k_crit_reduce<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->ngrp, ctx->crit_part, 0, ctx->probe_cc, ctx->probe_prim,
                                                  ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
@@ -1578,7 +1596,7 @@ avs_status avs_dia_adapt(avs_dia* d, double C1, double C2, const double* probes_
   if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
   if (std::isnan(C1) || std::isnan(C2)) return fail(AVS_E_INVALID, "C1/C2 must not be NaN");
   ctx->plan_valid = false;
-  if (avs_status st = upload_probes(ctx, probes_host, nprobes)) return st;
+  if (avs_status st = upload_probes(ctx, probes_host, nprobes, true)) return st;
   if (avs_status st = ctx->D == 2 ? dia_criterion<2>(d, C1, C2, nprobes) : dia_criterion<3>(d, C1, C2, nprobes))
     return st;
   int64_t nn = 0;
@@ -1589,6 +1607,7 @@ avs_status avs_dia_adapt(avs_dia* d, double C1, double C2, const double* probes_
     return fail(AVS_E_CAPACITY, "adaptation would produce %" PRId64 " leaves > the diatomic state's %" PRId64, nn,
                 d->max_leaves);
   }
+  ctx->plan_owner = d;
   return AVS_OK;
 }
 
@@ -1598,6 +1617,12 @@ avs_status avs_dia_remap(avs_dia* d) {
   if (avs_status st = guard(ctx)) return st;
   if (ctx->leaf_gen != d->gen) return fail(AVS_E_STATE, "the context's leaves changed since the diatomic state was made");
   if (!ctx->plan_valid) return fail(AVS_E_STATE, "no adaptation plan (call avs_dia_adapt first)");
+  // a plan made by another adaptation (monatomic, batched, learned or another
+  // diatomic state) was bounded by the context's capacity, not by these rows
+  if (ctx->plan_owner != d)
+    return fail(AVS_E_STATE, "the current plan was not made by avs_dia_adapt on this diatomic state");
+  if (ctx->plan_n > d->max_leaves)
+    return fail(AVS_E_CAPACITY, "plan of %d leaves > the diatomic state's %" PRId64, ctx->plan_n, d->max_leaves);
   if (avs_status st = ctx->D == 2 ? dia_remap_state<2>(d) : dia_remap_state<3>(d)) return st;
   // the context moves to the new leaves with its own (monatomic) state
   if (avs_status st = avs_remap(ctx, 0)) return st;
@@ -1633,15 +1658,20 @@ avs_status avs_moments(avs_ctx* ctx, double* fields_dev, double* totals_host) {
   return AVS_OK;
 }
 
-static avs_status upload_probes(avs_ctx* ctx, const double* probes_host, int32_t nprobes) {
+static avs_status upload_probes(avs_ctx* ctx, const double* probes_host, int32_t nprobes, bool diatomic) {
   if (nprobes < 0 || nprobes > ctx->nprobe_max) return fail(AVS_E_INVALID, "nprobes must be in [0, %d]", ctx->nprobe_max);
   if (nprobes > 0 && !probes_host) return fail(AVS_E_INVALID, "probes_host is null");
   const int D = ctx->D, N = D + 2;
-  std::vector<double> pcc((size_t)std::max(nprobes, 1) * N), Wp(N);
+  std::vector<double> pcc((size_t)std::max(nprobes, 1) * N), Wp(N + 1);
   for (int p = 0; p < nprobes; ++p) {
     const double* pr = probes_host + (size_t)p * N;
     if (!(pr[0] > 0 && pr[1 + D] > 0)) return fail(AVS_E_INVALID, "probe %d is not a physical state", p);
-    conserved_host(D, ctx->gas.R, pr, Wp.data());
+    // the criterion's constants (rho, U, internal energy) come from the
+    // probe's conserved state, as a cell's come from its W
+    if (diatomic)
+      conserved_dia_host(D, ctx->gas.R, pr, Wp.data());
+    else
+      conserved_host(D, ctx->gas.R, pr, Wp.data());
     crit_consts_host(D, Wp.data(), &pcc[(size_t)p * N]);
   }
   if (nprobes > 0) {
@@ -1676,6 +1706,7 @@ static avs_status finish_plan(avs_ctx* ctx, int8_t* flags_dev, int64_t* n_new_ho
   CK(hipStreamSynchronize(ctx->stream));
   ctx->plan_n = n_new;
   ctx->plan_valid = true;
+  ctx->plan_owner = nullptr;
   return AVS_OK;
 }
 
@@ -2001,6 +2032,7 @@ avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2
   for (int i = 0; i < n; ++i) {
     b->cases[i]->plan_n = nn[i];
     b->cases[i]->plan_valid = true;
+    b->cases[i]->plan_owner = nullptr;
   }
   return AVS_OK;
 }

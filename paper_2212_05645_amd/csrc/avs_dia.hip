@@ -738,12 +738,17 @@ __global__ __launch_bounds__(BLOCK) void k_dg_heat(Geo g, Leaves L, const double
 // in a fixed operation order (no contraction) so that the flags are
 // reproducible bit for bit.
 // The first group also takes the nprobe probe states (rho, U, T) with the
-// equilibrium triple (g, (3-D) R T g, R T g) and internal energy 5/2 rho R T.
+// equilibrium triple (g, (3-D) R T g, R T g).  Their criterion constants
+// (rho, U and the internal energy from the probe's conserved state, which
+// holds 5/2 rho R T) come from the host; the triple is evaluated in the
+// oracle's association.  exp and pow are this library's, so probe values of
+// M_k agree with the oracle's to rounding, not bit for bit: flags are equal
+// away from ties with C1 and C2.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_dg_crit_partial(Leaves L, int nc, const double* __restrict__ vdf,
                                                           const double* __restrict__ W, double* __restrict__ part,
-                                                          int nprobe, const double* __restrict__ probe_prim,
-                                                          double R) {
+                                                          int nprobe, const double* __restrict__ probe_cc,
+                                                          const double* __restrict__ probe_prim, double R) {
 #pragma clang fp contract(off)
   constexpr int NW = Dg<D>::NW;
   const int k = blockIdx.x * BLOCK + threadIdx.x;
@@ -778,16 +783,26 @@ __global__ __launch_bounds__(BLOCK) void k_dg_crit_partial(Leaves L, int nc, con
   if (grp == 0) {
     for (int p = 0; p < nprobe; ++p) {
       const double* pr = probe_prim + (size_t)p * (D + 2);
-      const double rho = pr[0], RT = R * pr[1 + D];
+      const double* cc = probe_cc + (size_t)p * (D + 2);
+      const double rho = pr[0], T = pr[1 + D];
+      // the triple about the probe's own U
       double c = xi[0] - pr[1];
-      double c2 = c * c;
+      double cg2 = c * c;
       for (int d = 1; d < D; ++d) {
         c = xi[d] - pr[1 + d];
+        cg2 = cg2 + c * c;
+      }
+      const double G = rho * pow(2.0 * M_PI * R * T, -0.5 * D) * exp(-cg2 / (2.0 * R * T));
+      const double H = (double)(3 - D) * R * T * G, Rr = R * T * G;
+      // the criterion about U of the conserved state
+      c = xi[0] - cc[1];
+      double c2 = c * c;
+      for (int d = 1; d < D; ++d) {
+        c = xi[d] - cc[1 + d];
         c2 = c2 + c * c;
       }
-      const double G = rho * pow(2.0 * M_PI * RT, -0.5 * D) * exp(-c2 / (2.0 * RT));
-      const double M1 = (A * G) / rho;
-      const double M2 = (A * (0.5 * (c2 * G + (3 - D) * RT * G) + RT * G)) / (2.5 * rho * RT);
+      const double M1 = (A * G) / cc[0];
+      const double M2 = (A * (0.5 * (c2 * G + H) + Rr)) / cc[1 + D];
       m = fmax(m, fmax(M1, M2));
     }
   }

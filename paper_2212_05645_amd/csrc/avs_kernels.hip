@@ -1372,6 +1372,7 @@ template <int D>
 __global__ void k_crit_reduce(Leaves L, int ngrp, const double* __restrict__ part, int nprobe,
                               const double* __restrict__ probe_cc, const double* __restrict__ probe_prim, GasP gas,
                               double C1, double C2, int lmax, double* __restrict__ Mk, int8_t* __restrict__ raw) {
+#pragma clang fp contract(off)
   const int k = blockIdx.x * BLOCK + threadIdx.x;
   if (k >= L.n) return;
   double m = -INFINITY;
@@ -1381,14 +1382,17 @@ __global__ void k_crit_reduce(Leaves L, int ngrp, const double* __restrict__ par
   leaf_load<D>(L, k, xi, A, u);
   for (int p = 0; p < nprobe; ++p) {
     const double* pr = probe_prim + (size_t)p * (D + 2);
-    const double rho = pr[0], T = pr[1 + D], RT = gas.R * T;
-    double c2 = 0.0;
-    for (int d = 0; d < D; ++d) {
-      const double c = xi[d] - pr[1 + d];
-      c2 += c * c;
+    // the discrete Maxwellian pair in the oracle's association (exp and pow
+    // are this library's: probe values agree to rounding, flags away from ties)
+    const double rho = pr[0], T = pr[1 + D], R = gas.R;
+    double c = xi[0] - pr[1];
+    double c2 = c * c;
+    for (int d = 1; d < D; ++d) {
+      c = xi[d] - pr[1 + d];
+      c2 = c2 + c * c;
     }
-    const double gv = rho * pow(2.0 * M_PI * RT, -0.5 * D) * exp(-c2 / (2.0 * RT));
-    m = fmax(m, crit_one<D>(xi, A, gv, D == 2 ? RT * gv : 0.0, probe_cc + (size_t)p * (D + 2)));
+    const double gv = rho * pow(2.0 * M_PI * R * T, -0.5 * D) * exp(-c2 / (2.0 * R * T));
+    m = fmax(m, crit_one<D>(xi, A, gv, D == 2 ? (double)(3 - D) * R * T * gv : 0.0, probe_cc + (size_t)p * (D + 2)));
   }
   Mk[k] = m;
   const int l = L.level[k];

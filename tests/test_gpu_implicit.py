@@ -551,3 +551,43 @@ def test_diatomic_argument_errors(avs):
     assert np.isfinite(v).all() and np.allclose(W[:, 0], 1.0, rtol=1e-12)
     dia.close()
     cs.close()
+
+
+def test_diatomic_remap_refuses_a_plan_it_did_not_make(avs):
+    """A plan made by the monatomic adaptation of the context (bounded only
+    by the context's leaf capacity) is refused by the diatomic remap before
+    any device work, also when it would outgrow the diatomic rows; the
+    diatomic state stays usable and its own plan is accepted afterwards."""
+    mesh = MM.box2d(3, 3, periodic=(True, True))
+    vs = dict(dim=2, lo=(-6.0, -6.0), hi=(6.0, 6.0), base=(8, 8), max_level=2)
+    vgas = dict(R=0.5, Pr=0.72, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1)
+    n = mesh['ncells']
+    prim = np.tile([1.0, 0.1, 0.0, 1.0, 0.9], (n, 1))
+    cs = avs.Case(mesh, vs, vgas, 2e-3, 1.0, np.ascontiguousarray(prim[:, :4]), leaf_capacity=1024)
+    dia = avs.Diatomic(cs, prim)                # rows for the current 64 leaves only
+    n0 = cs.nleaves()
+    _, nn = cs.adapt(-1.0, -2.0)                # split everything: 256 leaves > 64 rows
+    assert nn == 4 * n0
+    with pytest.raises(avs.AvsError, match="not made by avs_dia_adapt"):
+        dia.remap()
+    assert cs.nleaves() == n0
+    dia.step(1)
+    v, W = dia.get_state()
+    assert np.isfinite(v).all() and np.allclose(W[:, 0], 1.0, rtol=1e-12)
+    # its own plan (merge-free, no split: keeps the leaf count) is accepted
+    _, nn2 = dia.adapt(1e30, -1.0)
+    assert nn2 == n0
+    dia.remap()
+    dia.step(1)
+    v2, _ = dia.get_state()
+    assert np.isfinite(v2).all() and v2.shape == v.shape
+    # a diatomic plan is not taken by another diatomic state
+    dia_b = avs.Diatomic(cs, prim)
+    dia.adapt(1e30, -1.0)
+    with pytest.raises(avs.AvsError, match="not made by avs_dia_adapt"):
+        dia_b.remap()
+    dia.remap()
+    dia_b.close()
+    dia.close()
+    cs.close()
+

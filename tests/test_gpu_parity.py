@@ -29,7 +29,26 @@ def avs():
 
 
 def rel(a, b):
-    return float(np.max(np.abs(np.asarray(a) - b)) / max(float(np.max(np.abs(b))), 1e-300))
+    """Largest error of a row relative to that row's largest reference
+    value; a row is the last axis (the leaves of one cell and component, or
+    one cell's W), so a cell of small density is judged on its own scale."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    if b.ndim < 2:
+        return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+    a2, b2 = a.reshape(-1, b.shape[-1]), b.reshape(-1, b.shape[-1])
+    den = np.maximum(np.max(np.abs(b2), axis=1), 1e-300)
+    return float(np.max(np.max(np.abs(a2 - b2), axis=1) / den))
+
+
+def tailrel(a, b, floor=1e-8):
+    """Elementwise error relative to the value itself, floored at ``floor``
+    times its row's largest value: a leaf down to 1e-8 of the row's peak is
+    judged on its own size, so a wrong upwind side or boundary branch on a
+    tail leaf is seen (it changes the value by order one)."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    a2, b2 = a.reshape(-1, b.shape[-1]), b.reshape(-1, b.shape[-1])
+    den = np.abs(b2) + floor * np.max(np.abs(b2), axis=1, keepdims=True) + 1e-300
+    return float(np.max(np.abs(a2 - b2) / den))
 
 
 def fieldrel(a, b):
@@ -324,6 +343,7 @@ def test_3d_steps(avs, which):
     o.step(3)
     v, W = cs.get_state()
     assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    assert tailrel(v, o.phi) < 1e-6
 
 
 def test_3d_fp32_form_against_fp64_oracle(avs):
@@ -564,7 +584,47 @@ def test_full_size_cylinder_sampled(avs):
     loc = [int(np.searchsorted(keep, i)) for i in sample]
     phi1, W1, _ = O.step(o.mesh, t, gas, c['dt'], c['venkat_K'], o.phi, o.W, cells=loc)
     assert rel(got, phi1[:, loc]) < 1e-12
+    assert tailrel(got, phi1[:, loc]) < 1e-6
     assert rel(Wg, W1[loc]) < 1e-13
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_sphere_sampled(avs, prec):
+    """The sphere workload at full size (64 x 64 x 32 spherical grid, 16^3
+    roots, 2 levels), one step in the launch configuration the benchmark
+    times, on a seeded random tree (about 11 k leaves), FP64 and the FP32
+    form.  Sampled cells (wall, pole, shock layer, wake, outer boundary) are
+    recomputed by the FP64 oracle from their two-ring neighbourhood: FP64
+    row by row to 1e-12, FP32 within 1e-5 of each row (its storage rounding
+    is 6e-8)."""
+    c = F.sphere()
+    vs = c['vspace']
+    t = random_tree(vs, 79, 1, p=0.25)
+    assert 8000 < t.n < 16000
+    gas = O.gas_from(c['gas'])
+    cs = avs.Case(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'], precision=prec, leaf_capacity=t.n)
+    cs.set_leaves(t.level, t.idx)
+    cs.step(1)
+    nr, nth, nph = c['mesh']['shape']
+    cell = lambda ir, it, ip: (ir * nth + it) * nph + ip
+    sample = [cell(0, 0, 0), cell(0, 31, 5), cell(0, 63, 31), cell(10, 20, 17), cell(30, 32, 8),
+              cell(40, 5, 30), cell(63, 0, 0), cell(63, 40, 12)]
+    got = cs.get_cells(sample)
+    Wg = cs.get_W()[sample]
+    sub, keep = MM.submesh(c['mesh'], sample, halo=2)
+    o = O.Solver(sub, vs, gas, c['dt'], c['venkat_K'], c['prim0'][keep])
+    o.tree = t
+    o.phi = o.initial_vdf(o.W)
+    loc = [int(np.searchsorted(keep, i)) for i in sample]
+    phi1, W1, _ = O.step(o.mesh, t, gas, c['dt'], c['venkat_K'], o.phi, o.W, cells=loc)
+    if prec == 0:
+        assert rel(got, phi1[:, loc]) < 1e-12
+        assert tailrel(got, phi1[:, loc]) < 1e-6
+        assert rel(Wg, W1[loc]) < 1e-13
+    else:
+        assert rel(got, phi1[:, loc]) < 1e-5
+        assert rel(Wg, W1[loc]) < 1e-6
+    cs.close()
 
 
 # ------------------------------------------------------------ batched form --
@@ -628,4 +688,98 @@ def test_batch_matches_single_cases_bit_for_bit(avs, prec):
             va, Wa = a.get_state()
             vb, Wb = b.get_state()
             assert np.array_equal(va, vb) and np.array_equal(Wa, Wb)
+        batch.close()
+
+
+def _gap_thresholds(Mk, lo_q, hi_q, rgap):
+    """C1, C2 halfway between neighbouring values of M_k with a relative
+    gap above rgap, near the given quantiles (no leaf sits near either)."""
+    m = np.sort(Mk)
+
+    def gap(j):
+        while not m[j + 1] - m[j] > rgap * m[j + 1]:
+            j += 1
+        return j
+    j1, j2 = gap(int(hi_q * len(m))), gap(int(lo_q * len(m)))
+    return 0.5 * (m[j1] + m[j1 + 1]), 0.5 * (m[j2] + m[j2 + 1])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_members_match_the_oracle(avs, prec):
+    """A mixed batch (cavity, cylinder, periodic box; different Kn, Ma and
+    leaf counts) advanced by the batched kernels against the FP64 oracle
+    advancing each case alone: FP64 members row by row to 1e-12, FP32
+    members within 1e-5 field-normalised with FP64 totals; then one batched
+    adaptation with per-case thresholds placed in gaps of the oracle's M_k:
+    flags and leaf counts bit exact, and after the batched remap and two
+    more batched steps the states again within the same tolerances."""
+    import torch
+    stream = torch.cuda.Stream()
+    specs = []
+    c = F.cavity(n=8, Kn=0.3, Ma=0.4, base=8, max_level=2)
+    specs.append((c['mesh'], c['vspace'], c['gas'], c['dt'], 1.0, c['prim0'], random_tree(c['vspace'], 81, 2)))
+    c = F.cylinder(nr=6, nth=24, Ma=3.0, Kn=0.05, box=8.0, base=16, max_level=2, r1=2.5, first=0.1)
+    specs.append((c['mesh'], c['vspace'], c['gas'], c['dt'], 0.0, c['prim0'], resolved_tree(c['vspace'], 82)))
+    mesh = MM.box2d(5, 4, periodic=(True, True))
+    vs = dict(dim=2, lo=(-6, -6), hi=(6, 6), base=(4, 4), max_level=3)
+    specs.append((mesh, vs, dict(R=1.0, Pr=2 / 3, omega=0.5, mu_ref=0.2, T_ref=1.0, model=1), 0.004, 1.0,
+                  F.perturbed_uniform(mesh['ncells'], 2, 83, amp=0.1, uamp=0.4), random_tree(vs, 84, 3)))
+    with torch.cuda.stream(stream):
+        members, oracles = [], []
+        for mesh, vs, gas, dt, K, prim, tree in specs:
+            cs = avs.Case(mesh, vs, gas, dt, K, prim, precision=prec, stream=stream)
+            cs.set_leaves(tree.level, tree.idx)
+            o = O.Solver(mesh, vs, gas, dt, K, prim)
+            o.tree = tree
+            o.phi = o.initial_vdf(o.W)
+            members.append(cs)
+            oracles.append(o)
+        assert len({cs.nleaves() for cs in members}) == len(members)
+        batch = avs.Batch(members)
+
+        def compare():
+            for cs, o in zip(members, oracles):
+                v, W = cs.get_state()
+                if prec == 0:
+                    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+                else:
+                    f, tot = cs.moments()
+                    assert fieldrel(f.cpu().numpy(), o.fields()) < 1e-5
+                    ot = o.totals()
+                    assert np.max(np.abs(tot - ot)) <= 1e-12 * np.max(np.abs(ot)) + 1e-5 * np.max(np.abs(ot))
+        batch.step(3, graph=False)
+        for o in oracles:
+            o.step(3)
+        compare()
+        batch.step(2, graph=True)
+        for o in oracles:
+            o.step(2)
+        compare()
+        C1, C2 = [], []
+        for o in oracles:
+            Mk = O.criterion(o.phi, o.W, o.tree, o.gas.R)
+            a, b = _gap_thresholds(Mk, 0.2, 0.85, 1e-9 if prec == 0 else 1e-4)
+            C1.append(a)
+            C2.append(b)
+        nn = batch.adapt(C1, C2)
+        nsplit = nmerge = 0
+        for cs, o, a, b, n in zip(members, oracles, C1, C2, nn):
+            eff, plan, _ = o.adapt(a, b)
+            assert n == plan.tree.n
+            kind, src, child = cs.plan(int(n))      # the plan follows from the effective flags
+            assert np.array_equal(kind, plan.kind) and np.array_equal(src, plan.src)
+            assert np.array_equal(child, plan.child)
+            nsplit += int((eff == 1).sum())
+            nmerge += int((eff == -1).sum())
+        assert nsplit > 0 and nmerge > 0
+        batch.remap(2)
+        for o in oracles:
+            o.remap(2)
+        for cs, o in zip(members, oracles):
+            lv = cs.leaves()
+            assert np.array_equal(lv['level'], o.tree.level) and np.array_equal(lv['idx'], o.tree.idx)
+        batch.step(2, graph=True)
+        for o in oracles:
+            o.step(2)
+        compare()
         batch.close()

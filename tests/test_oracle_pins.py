@@ -265,11 +265,22 @@ def brute_force_adapt(tree, raw):
             return
         for c in range(2 ** D):
             visit(l + 1, tuple(2 * ix[d] + ((c >> d) & 1) for d in range(D)))
-    roots = sorted({(0, tuple(v >> l for v in ix)) for (l, ix) in out},
-                   key=lambda r: O.Tree(D, tree.lo, tree.hi, tree.base, tree.max_level,
-                                        np.array([0]), np.array([r[1]])).morton()[0])
-    for _, ix in roots:
-        visit(0, ix)
+    # the roots' own order (Z14: Morton order) without the oracle's key: the
+    # base^D roots are the leaves of one virtual tree, log2(base) levels
+    # above them, visited depth first with children in x-fastest binary order
+    base = [int(b) for b in tree.base]
+    top = max(base).bit_length() - 1
+    assert all(1 << top >= b for b in base)
+
+    def visit_virtual(l, ix):
+        if any(v << -l >= base[d] for d, v in enumerate(ix)):
+            return                               # wholly outside the root grid
+        if l == 0:
+            visit(0, ix)
+            return
+        for c in range(2 ** D):
+            visit_virtual(l + 1, tuple(2 * ix[d] + ((c >> d) & 1) for d in range(D)))
+    visit_virtual(-top, (0,) * D)
     return order
 
 
@@ -294,6 +305,20 @@ def test_flags_and_plan_match_brute_force_tree(D, seed):
         elif plan.kind[j] == O.COPY or plan.child[j] == 0:
             cover[k] += 1
     assert np.all(cover == 1)
+
+
+@pytest.mark.parametrize("D,base", [(2, (4, 4)), (2, (8, 2)), (3, (2, 4, 2))])
+def test_root_order_is_the_virtual_tree_depth_first_order(D, base):
+    """The level-0 roots (Z12, Z14) come in the depth-first order of one
+    virtual tree above them, children in x-fastest binary order; checked
+    with base counts that differ per axis."""
+    t = O.base_forest(D, [-1.0] * D, [1.0] * D, list(base), 2)
+    got = [tuple(int(v) for v in ix) for ix in t.idx]
+    expect = brute_force_adapt(t, np.zeros(t.n, np.int8))
+    assert got == [ix for _, ix in expect]
+    # 2-D base (4, 4): the first quadrant's four roots, then the second's
+    if D == 2 and base == (4, 4):
+        assert got[:8] == [(0, 0), (1, 0), (0, 1), (1, 1), (2, 0), (3, 0), (2, 1), (3, 1)]
 
 
 # ------------------------------------------------------ stepping pins -----
@@ -438,6 +463,99 @@ def test_remap_correction_restores_W():
     W = s.W.copy()
     s.remap(correction=2)
     np.testing.assert_allclose(s.vdf_moments(), W, rtol=1e-12, atol=1e-13)
+
+
+def _moments_by_hand(phi, xi, A):
+    """Sum A (G, xi G, (|xi|^2 G + H)/2) written out per leaf (Eq. updat_W)."""
+    D = xi.shape[1]
+    G = phi[0]
+    H = phi[1] if D == 2 else np.zeros_like(G)
+    out = [float(np.sum(A * G))]
+    out += [float(np.sum(A * xi[:, d] * G)) for d in range(D)]
+    out.append(float(np.sum(0.5 * A * (np.sum(xi * xi, axis=1) * G + H))))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("D,n,half", [(2, 48, 12.0), (3, 28, 9.0)])
+def test_literal_correction_conserves_exactly_where_the_quadrature_is_exact(D, n, half):
+    """The literal correction of Sec. 3.3 alone (no closure): f = f' + g(W) -
+    g(W') has moments W' + M[g(W)] - M[g(W')].  On a uniform mesh over a box
+    of many thermal speeds the mid-point rule integrates a Maxwellian to
+    round-off (its error decays like exp(-2 pi^2 sigma^2 / h^2)), so M[f] = W
+    there for any f' and any W.  A flipped sign would give 2 W' - W, a
+    dropped term W' or M[g(W)], a wrong H pairing a wrong energy."""
+    R = 1.0
+    t = O.base_forest(D, [-half] * D, [half] * D, [n] * D, 0)
+    xi, A = t.centres(), t.weights()
+    rng = np.random.default_rng(31 + D)
+    Ub = np.array([0.3, -0.2, 0.1][:D])
+    base = O.eq_pair(1.0, Ub, 1.0, xi, R)
+    ncell = 3
+    fp = np.stack([base * (1.0 + 0.2 * rng.random(base.shape)) for _ in range(ncell)], axis=1)
+    Wp = np.array([_moments_by_hand(fp[:, i], xi, A) for i in range(ncell)])
+    W = Wp * (1.0 + 0.01 * rng.uniform(-1, 1, Wp.shape))          # a different authoritative state
+    W[:, 1 + D] = np.abs(W[:, 1 + D]) + 0.05                      # keep it hot enough to be physical
+    out = O.correct(fp, W, t, R, close=False)
+    for i in range(ncell):
+        np.testing.assert_allclose(_moments_by_hand(out[:, i], xi, A), W[i], rtol=1e-11, atol=1e-12)
+        assert np.max(np.abs(Wp[i] - W[i])) > 1e-4                 # the correction had work to do
+
+
+def test_literal_correction_after_split_and_merge_on_a_fine_mesh():
+    """The same through the remap of Sec. 3.2-3.3: a uniform fine mesh,
+    every brother group merged (the new mesh is uniform too), literal
+    correction without the closure: the moments return to W to round-off,
+    while the consanguinity reconstruction alone moves them (momentum of a
+    merge, P2)."""
+    R = 1.0
+    t = O.base_forest(2, [-12.0] * 2, [12.0] * 2, [48] * 2, 1)
+    t = O.make_plan(np.ones(t.n, np.int8), t).tree                   # 96 x 96 uniform at level 1
+    xi, A = t.centres(), t.weights()
+    rng = np.random.default_rng(5)
+    phi = O.eq_pair(1.1, np.array([0.4, 0.1]), 0.9, xi, R)[:, None, :] * (1 + 0.3 * rng.random((2, 2, t.n)))
+    W = np.array([_moments_by_hand(phi[:, i], xi, A) for i in range(2)])
+    plan = O.make_plan(-np.ones(t.n, np.int8), t)
+    assert plan.tree.n * 4 == t.n
+    fp = O.remap(phi, plan, 2)
+    xn, An = plan.tree.centres(), plan.tree.weights()
+    Wp = np.array([_moments_by_hand(fp[:, i], xn, An) for i in range(2)])
+    assert np.max(np.abs(Wp - W)) > 1e-4
+    out = O.correct(fp, W, plan.tree, R, close=False)
+    for i in range(2):
+        np.testing.assert_allclose(_moments_by_hand(out[:, i], xn, An), W[i], rtol=1e-11, atol=1e-12)
+
+
+def test_criterion_is_the_max_over_cells_and_probes():
+    """M_k runs over the whole physical mesh (text of Sec. 3.4): the
+    criterion of a mesh is the leafwise maximum of the criteria of its cells
+    taken one at a time, and a probe state counts as one more cell holding its
+    discrete Maxwellian.  Two cells with Maxwellians far apart: at the leaf
+    under each peak the criterion takes that cell's value, which exceeds the
+    other cell's by orders of magnitude, and the peak value is A_k times the
+    Maxwellian's peak density over rho, 1/(2 pi R T) (M1 with G at c = 0)."""
+    R = 1.0
+    t = O.base_forest(2, [-8.0] * 2, [8.0] * 2, [16, 16], 1)
+    xi, A = t.centres(), t.weights()
+    T = 0.25
+    Ua, Ub = np.array([-4.5, 0.5]), np.array([4.5, 0.5])       # leaf centres: the peaks sit on leaves
+    ea, eb = O.eq_pair(1.0, Ua, T, xi, R), O.eq_pair(2.0, Ub, T, xi, R)
+    phi = np.stack([ea, eb], axis=1)
+    pa, pb = np.array([1.0, Ua[0], Ua[1], T]), np.array([2.0, Ub[0], Ub[1], T])
+    W = np.array([O.conserved(pa, R), O.conserved(pb, R)])     # exact states (the coarse mesh is not)
+    both = O.criterion(phi, W, t, R)
+    one_a = O.criterion(phi[:, :1], W[:1], t, R)
+    one_b = O.criterion(phi[:, 1:], W[1:], t, R)
+    assert np.array_equal(both, np.maximum(one_a, one_b))
+    ka = int(np.argmin(np.sum((xi - Ua) ** 2, 1)))
+    kb = int(np.argmin(np.sum((xi - Ub) ** 2, 1)))
+    assert np.allclose(xi[ka], Ua) and np.allclose(xi[kb], Ub)
+    assert both[ka] == one_a[ka] and both[kb] == one_b[kb]
+    assert one_a[ka] > 1e6 * one_b[ka] and one_b[kb] > 1e6 * one_a[kb]
+    for k, i in ((ka, 0), (kb, 1)):
+        np.testing.assert_allclose(both[k], A[k] / (2 * math.pi * R * T), rtol=1e-14)
+    # a probe holding cell b's state adds cell b's criterion to a one-cell mesh
+    with_probe = O.criterion(phi[:, :1], W[:1], t, R, probes=pb)
+    assert np.array_equal(with_probe, np.maximum(one_a, one_b))
 
 
 def test_equilibrium_bypass():
