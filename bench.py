@@ -48,6 +48,7 @@ def parse():
     p.add_argument("--train-epochs", type=int, default=4)
     p.add_argument("--sphere-C1", type=float, default=1.0076e-4, help="splitting threshold of the 3-D form (~20k leaves)")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--one-form", action="store_true", help="time only --precision (not also the other precision)")
     p.add_argument("--no-sweep", action="store_true", help="skip the extra sweep-only timing (profiling runs)")
     p.add_argument("--copy-probe", type=float, default=0.0,
                    help="GiB copied device-to-device by torch before the run (calibrates HBM byte counters)")
@@ -197,15 +198,28 @@ def measured_copy_bandwidth(torch, nbytes=2 ** 31, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def vdf_bytes_per_node(P, es, rows_per_cell):
-    """Algorithmic HBM bytes per (cell, leaf) of one launch of each VDF
-    kernel: every distinct byte it must read or write, once.  A leaf row of
-    one cell holds P*es bytes; ``rows_per_cell`` = interface rows (faces)
-    per cell, each written once by pass A and read by the face reduction and
-    by pass C."""
+def vdf_bytes_per_node(P, es):
+    """Algorithmic HBM bytes per (cell, leaf) node of one launch of each VDF
+    kernel, from the minimum traffic of the method: a step reads the VDF
+    twice and writes it once (a leaf row of one cell holds P*es bytes).  The
+    reconstruction pass owns one read, the update pass one read and the
+    write; interface storage is this design's choice, not algorithmic, and
+    counts zero.  Per adaptation: the criterion reads the VDF once, the
+    remap and its correction each read and write it once."""
     r = P * es
-    return {"passA": r * (1.0 + rows_per_cell), "face": r * rows_per_cell, "passC": r * (2.0 + rows_per_cell),
-            "criterion": r, "remap_gather": 2 * r, "remap_correct": 2 * r, "moments": r}
+    return {"passA": r, "passC": 2 * r, "face": 0.0, "criterion": r, "remap_gather": 2 * r,
+            "remap_correct": 2 * r, "moments": r}
+
+
+def design_bytes_per_node(P, es, rows_per_cell, fused_face):
+    """Bytes per node this design moves at least: the reconstruction writes
+    every interface row once, the update reads each once (and, without the
+    fused face moments, the face reduction reads each once more)."""
+    r = P * es
+    out = {"passA": r * (1.0 + rows_per_cell), "passC": r * (2.0 + rows_per_cell)}
+    if not fused_face:
+        out["face"] = r * rows_per_cell
+    return out
 
 
 def passA_flops_per_node(D, P, slots, interior):
@@ -225,30 +239,92 @@ def passA_flops_per_node(D, P, slots, interior):
             + slots * (2 * D - 1) + slots / 2 * (2 * D + P * 2 * D))
 
 
-def cpu_baseline(w, ncell_sample=512):
-    """Oracle (FP64 NumPy) updating a contiguous block of cells of the same
-    workload and leaf set, given its two-ring neighbourhood."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample_worker(job):
+    """One oracle step of a block of cells of the cylinder workload with the
+    given leaf set (run in a child process, one thread, BLAS included).
+    Returns (updates, t_start, t_end) on the wall clock."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import avs_oracle as O
+    from workloads import fields as F
     from workloads import meshes
-    c = w.cfg
-    L = w.cs.leaves()
-    mid = w.nc // 2
-    sample = list(range(mid, mid + ncell_sample))
+    nr, nth, first, ncell, level, idx, barrier = job
+    c = F.cylinder(nr=nr, nth=nth)
+    sample = list(range(first, first + ncell))
     sub, keep = meshes.submesh(c['mesh'], sample, halo=2)
     o = O.Solver(sub, c['vspace'], c['gas'], c['dt'], c['venkat_K'], c['prim0'][keep])
-    o.tree = O.Tree(2, o.tree.lo, o.tree.hi, o.tree.base, o.tree.max_level, L['level'].astype(np.int64),
-                    L['idx'].astype(np.int64))
+    o.tree = O.Tree(2, o.tree.lo, o.tree.hi, o.tree.base, o.tree.max_level, np.asarray(level, np.int64),
+                    np.asarray(idx, np.int64))
     o.phi = o.initial_vdf(o.W)
     loc = [int(np.searchsorted(keep, g)) for g in sample]
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):          # the oracle runs on one core, BLAS included
-        t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        if barrier is not None:
+            barrier.wait(timeout=300)      # a process that failed before this point ends the wait
+        t0 = time.time()
         O.step(o.mesh, o.tree, o.gas, o.dt, o.Kv, o.phi, o.W, cells=loc)
-        dt = time.perf_counter() - t0
-    return {"value": len(sample) * L['n'] / dt, "unit": "cell-node updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one explicit step of {len(sample)} contiguous cells x {L['n']} leaves of the same workload "
-                      f"(NumPy FP64, one thread, BLAS limited to one thread), {dt:.2f} s"}
+        t1 = time.time()
+    return len(sample) * len(level), t0, t1
+
+
+def _proc_job(job, queue):
+    try:
+        queue.put(_oracle_sample_worker(job))
+    except Exception as e:          # reported by the parent
+        queue.put(repr(e))
+
+
+def cpu_baseline(w, args, ncell_sample=256, workers=None):
+    """The oracle (FP64 NumPy, as it stands) stepping blocks of cells of the
+    same workload and leaf set, given their two-ring neighbourhood, on the
+    host: one process on one thread, then one process per core (up to 16,
+    the host share of one GPU) each on its own block, all started together
+    behind a barrier.  Rates are cell-node updates per second of wall time."""
+    import multiprocessing as mp
+    L = w.cs.leaves()
+    level, idx = L['level'].tolist(), L['idx'].tolist()
+    nth = args.nth
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nw = workers or max(1, min(16, ncpu))
+    # blocks spread over the radial range (shock layer, wake, far field), all of one size
+    firsts = [((w.nc // 2 + k * (w.nc // (2 * nw))) // nth) * nth + (k * 37) % nth for k in range(nw)]
+    firsts = [min(f, w.nc - ncell_sample) for f in firsts]
+    t0 = time.perf_counter()
+    u1, a, b = _oracle_sample_worker((args.nr, nth, firsts[0], ncell_sample, level, idx, None))
+    one = u1 / (b - a)
+    ctx = mp.get_context("spawn")          # child interpreters: nothing of this process's GPU state
+    barrier = ctx.Barrier(nw)
+    queue = ctx.Queue()
+    procs = [ctx.Process(target=_proc_job, args=((args.nr, nth, f, ncell_sample, level, idx, barrier), queue))
+             for f in firsts]
+    for pr in procs:
+        pr.start()
+    res = [queue.get(timeout=900) for _ in procs]
+    for pr in procs:
+        pr.join()
+    bad = [r for r in res if isinstance(r, str)]
+    if bad:
+        raise RuntimeError(f"oracle worker failed: {bad[0]}")
+    total = sum(r[0] for r in res)
+    span = max(r[2] for r in res) - min(r[1] for r in res)
+    allc = total / span
+    log(f"cpu baseline: one thread {one:.3e}, {nw} processes {allc:.3e} updates/s "
+        f"({time.perf_counter() - t0:.1f} s with set-up)")
+    return {"value": allc, "unit": "cell-node updates/s", "cores": nw, "kind": "oracle",
+            "sample": f"one explicit FP64 step of {ncell_sample} contiguous cells x {L['n']} leaves of the same "
+                      f"workload per process ({nw} processes, one thread each, BLAS limited to one thread, "
+                      f"started together; rate over the span of all), NumPy oracle as it stands",
+            "one_thread": {"value": one, "cores": 1, "seconds": b - a},
+            "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity": ncpu}}
 
 
 def run_batched(args):
@@ -677,6 +753,70 @@ def run_sphere(args):
     return out
 
 
+def roofline_of(w, r, precision, copy_gbps):
+    """Roofline object of the dominant sweep kernel of one form (the longest
+    mean launch in the timed cycles), from HIP-event times of the library's
+    stream; bytes are the method's algorithmic bytes (2 reads + 1 write of
+    the VDF per step), the design's own bytes are reported beside them."""
+    P, es = 2, (8 if precision == "fp64" else 4)
+    prof = r["prof"]
+    nv = r["prof_leaves"]
+    nodes = w.nc * nv
+    kern = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1]} for k, v in prof.items()}
+    bpn = vdf_bytes_per_node(P, es)
+    fused = "face" not in prof
+    dbn = design_bytes_per_node(P, es, w.nf / w.nc, fused)
+    for k in kern:
+        if bpn.get(k):
+            kern[k]["GB/s"] = bpn[k] * nodes / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
+        if k in dbn:
+            kern[k]["design_GB/s"] = dbn[k] * nodes / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
+    sweep_k = [k for k in ("passA", "face", "face_eqflux", "macro", "target", "passC") if k in kern]
+    dom = max(sweep_k, key=lambda k: kern[k]["ms_per_launch"])
+    t_launch = kern[dom]["ms_per_launch"] * 1e-3
+    tpn = measured_traffic(f"cylinder_{precision}", dom)
+    traffic = None if tpn is None else tpn * nodes / 1e9
+    if dom != "passA":
+        k = "passC"
+        alg = bpn[k] * nodes
+        achieved = alg / (kern[k]["ms_per_launch"] * 1e-3)
+        roofline = {"bound": "hbm", "kernel": k, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
+                    "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    "bytes_per_launch": alg, "algorithmic_bytes_per_node": bpn[k],
+                    "design_bytes_per_node": dbn.get(k), "dominant_kernel": dom}
+    else:
+        # the reconstruction pass is bound by vector-ALU issue (the limiter):
+        # its roofline is the FP vector peak (packed FP32 is not used, so both
+        # forms issue at the FP64 rate: 256 CU x 64 lanes x 2 flop x 2.4 GHz)
+        lr = w.cfg['mesh']['face_lr']
+        nint = int((lr[:, 1] >= 0).sum())
+        slots, interior = (2 * nint + (w.nf - nint)) / w.nc, 2 * nint / w.nc
+        fpn = passA_flops_per_node(2, P, slots, interior)
+        alg = fpn * nodes
+        achieved = alg / t_launch
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
+                    "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    "flops_per_launch": alg, "algorithmic_flops_per_node": fpn,
+                    "hbm_GBps": kern[dom].get("GB/s"), "dominant_kernel": dom}
+    pc = kern["passC"]
+    roofline["passC"] = {"algorithmic_bytes_per_node": bpn["passC"], "GB/s": pc["GB/s"],
+                         "frac": pc["GB/s"] * 1e9 / HBM_PEAK, "design_bytes_per_node": dbn["passC"],
+                         "design_frac": pc["design_GB/s"] * 1e9 / HBM_PEAK,
+                         "frac_of_measured_copy": pc["design_GB/s"] / copy_gbps}
+    roofline["measured_copy_GBps"] = copy_gbps
+    # the whole sweep (every kernel of one step) against the method's minimum
+    # bytes (read the VDF twice, write it once) and against this design's
+    sweep_s = sum(kern[k]["ms_per_launch"] for k in sweep_k) * 1e-3
+    design_b = sum(dbn.get(k, 0.0) for k in sweep_k)
+    min_b = 3 * P * es
+    roofline["sweep"] = {"ms": sweep_s * 1e3, "kernels": sweep_k, "algorithmic_bytes_per_node": min_b,
+                         "frac": min_b * nodes / sweep_s / HBM_PEAK, "target_frac": 0.60,
+                         "design_bytes_per_node": design_b, "design_frac": design_b * nodes / sweep_s / HBM_PEAK}
+    return roofline, kern
+
+
 def run_form(args, precision, C1=None):
     w = Workload(args, precision)
     if C1 is None:
@@ -708,74 +848,34 @@ def main():
         del a, b
     copy_gbps = measured_copy_bandwidth(torch)
     w, C1, r = run_form(args, args.precision)
-    P, es = 2, (8 if args.precision == "fp64" else 4)
-    prof = r["prof"]
-    nv = r["prof_leaves"]
-    kern = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1]} for k, v in prof.items()}
-    bpn = vdf_bytes_per_node(P, es, w.nf / w.nc)
-    dom = max(prof, key=lambda k: prof[k][0])
-    roof_k = dom if dom in bpn else "passC"
-    t_launch = prof[roof_k][0] / prof[roof_k][1] * 1e-3
-    tpn = measured_traffic(f"cylinder_{args.precision}", roof_k)
-    traffic = None if tpn is None else tpn * w.nc * nv / 1e9
-    for k in kern:
-        if k in bpn:
-            kern[k]["GB/s"] = bpn[k] * w.nc * nv / (kern[k]["ms_per_launch"] * 1e-3) / 1e9
-    if roof_k == "passA":
-        # pass A is bound by vector-ALU issue (the limiter), not by HBM: its
-        # roofline is the FP vector peak (packed FP32 is not used, so both
-        # forms issue at the FP64 rate: 256 CU x 64 lanes x 2 flop x 2.4 GHz)
-        lr = w.cfg['mesh']['face_lr']
-        nint = int((lr[:, 1] >= 0).sum())
-        slots, interior = (2 * nint + (w.nf - nint)) / w.nc, 2 * nint / w.nc
-        fpn = passA_flops_per_node(2, P, slots, interior)
-        alg = fpn * w.nc * nv
-        achieved = alg / t_launch
-        roofline = {"bound": "alu", "kernel": roof_k, "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
-                    "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                    "flops_per_launch": alg, "algorithmic_flops_per_node": fpn,
-                    "hbm_GBps": kern[roof_k]["GB/s"], "hbm_frac": kern[roof_k]["GB/s"] * 1e9 / HBM_PEAK,
-                    "dominant_kernel": dom}
-        hbm_ach = kern[roof_k]["GB/s"] * 1e9
-    else:
-        alg = bpn[roof_k] * w.nc * nv
-        achieved = hbm_ach = alg / t_launch
-        roofline = {"bound": "hbm", "kernel": roof_k, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
-                    "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                    "bytes_per_launch": alg, "algorithmic_bytes_per_node": bpn[roof_k], "dominant_kernel": dom}
-    roofline["measured_copy_GBps"] = copy_gbps
-    roofline["frac_of_copy"] = hbm_ach / 1e9 / copy_gbps
-    # the whole sweep (all step kernels of one step) against two byte counts:
-    # this design's (interface rows written once, read twice) and the minimum
-    # of any implementation (read the VDF twice, write it once)
-    sweep_k = [k for k in ("passA", "face", "face_eqflux", "macro", "target", "passC") if k in kern]
-    sweep_s = sum(kern[k]["ms_per_launch"] for k in sweep_k) * 1e-3
-    design_b = sum(bpn.get(k, 0.0) for k in sweep_k)
-    min_b = 3 * P * es
-    roofline["sweep"] = {"ms": sweep_s * 1e3, "kernels": sweep_k,
-                         "design_bytes_per_node": design_b, "design_frac": design_b * w.nc * nv / sweep_s / HBM_PEAK,
-                         "min_bytes_per_node": min_b, "min_frac": min_b * w.nc * nv / sweep_s / HBM_PEAK}
+    roofline, kern = roofline_of(w, r, args.precision, copy_gbps)
     value = r["updates"] / (r["ms"] * 1e-3)
     forms = {args.precision: {"cycle_updates_per_s": value, "sweep_updates_per_s": r["sweep_rate"],
                               "sweep_ms": r["sweep_ms"], "leaves": r["sweep_leaves"]}}
-    if args.forms:
-        if args.precision == "fp64":
-            try:
-                forms["learned_fp64"] = run_learned(args, w, C1)
-            except Exception as e:
-                forms["learned_fp64"] = {"error": repr(e)}
+    if args.forms and args.precision == "fp64":
+        try:
+            forms["learned_fp64"] = run_learned(args, w, C1)
+        except Exception as e:
+            forms["learned_fp64"] = {"error": repr(e)}
+    if not args.one_form:
+        # the other precision on the same workload and thresholds, in this run
         other = "fp32" if args.precision == "fp64" else "fp64"
         del w
         torch.cuda.empty_cache()
         w2, _, r2 = run_form(args, other, C1=C1)
+        roof2, kern2 = roofline_of(w2, r2, other, copy_gbps)
         forms[other] = {"cycle_updates_per_s": r2["updates"] / (r2["ms"] * 1e-3), "sweep_updates_per_s": r2["sweep_rate"],
-                        "sweep_ms": r2["sweep_ms"], "leaves": r2["sweep_leaves"],
-                        "kernels": {k: v[0] / v[1] for k, v in r2["prof"].items()}}
+                        "sweep_ms": r2["sweep_ms"], "leaves": r2["sweep_leaves"], "ms_per_step": r2["ms"] / args.steps,
+                        "roofline": {"frac": roof2["frac"], "kernel": roof2["kernel"], "bound": roof2["bound"],
+                                     "passC": roof2["passC"], "sweep": roof2["sweep"]},
+                        "kernels": {k: v["ms_per_launch"] for k, v in kern2.items()}}
+        f32, f64 = forms.get("fp32"), forms.get("fp64")
+        forms["fp32_over_fp64"] = {"cycle": f32["cycle_updates_per_s"] / f64["cycle_updates_per_s"],
+                                   "sweep": f32["sweep_updates_per_s"] / f64["sweep_updates_per_s"]}
         w = w2
         del w2
         torch.cuda.empty_cache()
+    if args.forms:
         try:
             forms["batched_fp32"] = run_batched(args)
         except Exception as e:
@@ -813,7 +913,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         try:
-            cpu = cpu_baseline(w)
+            cpu = cpu_baseline(w, args)
         except Exception as e:  # the baseline is informative only
             cpu = {"error": repr(e)}
     out = {
