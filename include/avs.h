@@ -274,6 +274,19 @@ avs_status avs_step_implicit(avs_ctx *ctx, int32_t nsteps, int32_t macro_sweeps,
  * totals_host [dim+2] (waits).  Either pointer may be NULL. */
 avs_status avs_moments(avs_ctx *ctx, double *fields_dev, double *totals_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * outputs as avs_moments, with the partial sums of the totals in a static
+ * device array of the library (5 125 doubles, about 40 KiB per device, held
+ * until the process ends) instead of the context's workspace.  It calls no
+ * allocating routine.  Limit: at most 1 048 576 cells when totals_host is
+ * non-NULL, else AVS_E_CAPACITY before any device work; AVS_E_HIP if the
+ * array has no address on the context's device.  All calls on one device
+ * share the array: calls that overlap on one device (other streams or
+ * threads) race; calls in order on one stream do not.  Totals agree with
+ * avs_moments to rounding (another summation order); fields bit for bit. */
+avs_status avs_moments_noalloc(avs_ctx *ctx, double *fields_dev, double *totals_host);
+
 /* Adaptation (Sec. 3.4): M_k = max over cells (and over the nprobes probe
  * states, primitive rows whose VDF is the discrete Maxwellian) of
  * max(M1, M2) (Eqs. criterion_rho, criterion_e, criterion_mk); split if

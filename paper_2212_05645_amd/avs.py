@@ -21,7 +21,7 @@ AVS_FP64, AVS_FP32 = 0, 1
 AVS_COPY, AVS_SPLIT, AVS_MERGE = 0, 1, 2
 
 EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_init_mesh", "avs_step",
-           "avs_moments", "avs_adapt", "avs_remap", "avs_leaves", "avs_plan", "avs_criterion",
+           "avs_moments", "avs_moments_noalloc", "avs_adapt", "avs_remap", "avs_leaves", "avs_plan", "avs_criterion",
            "avs_set_leaves", "avs_get_state", "avs_set_state", "avs_get_cells", "avs_profile",
            "avs_profile_read", "avs_batch_workspace_bytes", "avs_batch_create", "avs_batch_step",
            "avs_batch_check", "avs_batch_tune", "avs_batch_adapt", "avs_batch_remap", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
@@ -91,6 +91,7 @@ def _load():
                                 C.c_size_t, VP, P(VP)]),
         "avs_step": (I32, [VP, I32, VP]),
         "avs_moments": (I32, [VP, VP, VP]),
+        "avs_moments_noalloc": (I32, [VP, VP, VP]),
         "avs_adapt": (I32, [VP, D, D, VP, I32, VP, P(I64)]),
         "avs_remap": (I32, [VP, I32]),
         "avs_leaves": (I32, [VP, P(I64), P(I64), VP, VP, VP, VP]),
@@ -294,6 +295,18 @@ class Case:
         f = self._torch.empty((self.nc, 2 * self.dim + 2), dtype=self._torch.float64, device=self.device) if fields else None
         t = np.zeros(self.dim + 2) if totals else None
         _check(lib.avs_moments(self.ctx, f.data_ptr() if f is not None else None, _ptr(t)))
+        return f, t
+
+    def moments_noalloc(self, fields_out=None, totals=True):
+        """avs_moments through the entry point that allocates nothing (its
+        partial sums live in the library's static device array); fields go
+        into ``fields_out`` (a float64 device tensor [nc, 2*dim+2]) if given."""
+        f = fields_out
+        if f is not None and (tuple(f.shape) != (self.nc, 2 * self.dim + 2) or f.dtype != self._torch.float64
+                              or not f.is_contiguous()):
+            raise ValueError(f"fields_out must be a contiguous float64 tensor of shape ({self.nc}, {2 * self.dim + 2})")
+        t = np.zeros(self.dim + 2) if totals else None
+        _check(lib.avs_moments_noalloc(self.ctx, f.data_ptr() if f is not None else None, _ptr(t)))
         return f, t
 
     def adapt(self, C1, C2, probes=None, flags_out=None):

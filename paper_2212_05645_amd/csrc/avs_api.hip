@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,7 @@ struct avs_ctx {
   double dt, h, Kv;
   VGrid vg;
   hipStream_t stream;
+  int device = 0;         // current device at init: the device of the caller's memory and stream
   bool failed = false;
   std::vector<double> vol_host;
 
@@ -843,6 +845,43 @@ avs_status batch_run(avs_batch* b, int nsteps, bool graph) {
 
 }  // namespace
 
+// ------------------------------------- no-allocation totals (static scratch)
+// Device memory of avs_moments_noalloc: per-block partial sums of
+// sum_i V_i W_i, then the totals staged for the host copy.  One array per
+// device (each GPU holds its own copy for the life of the process); every
+// call on a device shares it, so calls that overlap on one device race.
+constexpr int NOALLOC_CELLS_PER_BLOCK = 1024;
+constexpr int NOALLOC_MAX_BLOCKS = 1024;                                   // at most 1 048 576 cells
+constexpr int NOALLOC_DOUBLES = (NOALLOC_MAX_BLOCKS + 1) * (3 + 2);        // D + 2 <= 5 per partial
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};   // the array's device address, per device
+
+// Resolve the array's address on device dev (made current for the call);
+// done once per device, at context set-up.  The array's name in host code
+// is a host-side stand-in, never a device address: only these pointers are
+// handed to kernels.
+hipError_t resolve_scratch(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();     // keep the failure out of later launch checks
+    return e;
+  }
+  g_scratch_dev[dev] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
 // ---------------------------------------------- automatic velocity space
 // Sec. 3.5: parameters of the velocity space from the freestream.
 avs_status auto_params_host(const avs_flow* f, avs_auto* p, avs_vspace* vs) {
@@ -938,6 +977,11 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   if (workspace_bytes < avs_workspace_bytes(vs, pm, op))
     return fail(AVS_E_INVALID, "workspace too small (%zu < %zu)", workspace_bytes, avs_workspace_bytes(vs, pm, op));
   if (((uintptr_t)vdf_dev & 255) || ((uintptr_t)workspace_dev & 255)) return fail(AVS_E_INVALID, "device regions must be 256-byte aligned");
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(AVS_E_HIP, "hipGetDevice failed");
+  // the no-allocation entry point's array on this device: a failure here only
+  // disables that entry point (it reports it), the context is unaffected
+  (void)resolve_scratch(device);
   const int D = vs->dim, N = D + 2;
   const int64_t nc = pm->ncells, nf = pm->nfaces;
   if (!pm->cell_vol || !pm->cell_ctr || (nf > 0 && (!pm->face_lr || !pm->face_area || !pm->face_nrm || !pm->face_ctr)))
@@ -1112,6 +1156,7 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   x.h = h_flux;
   x.Kv = op->venkat_K;
   x.stream = (hipStream_t)hip_stream;
+  x.device = device;
   x.vol_host.assign(pm->cell_vol, pm->cell_vol + nc);
   x.vdf_buf_bytes = (size_t)x.P * x.nc * x.cap * x.esize();
   x.vdf[0] = vdf_dev;
@@ -1653,6 +1698,53 @@ avs_status avs_moments(avs_ctx* ctx, double* fields_dev, double* totals_host) {
       k_totals<3><<<1, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->geo.vol, ctx->W, ctx->tot);
     CKL();
     CK(hipMemcpyAsync(totals_host, ctx->tot, sizeof(double) * (ctx->D + 2), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+  }
+  return AVS_OK;
+}
+
+avs_status avs_moments_noalloc(avs_ctx* ctx, double* fields_dev, double* totals_host) {
+  if (avs_status st = guard(ctx)) return st;
+  if (totals_host) {
+    const int nblk = (ctx->nc + NOALLOC_CELLS_PER_BLOCK - 1) / NOALLOC_CELLS_PER_BLOCK;
+    if (nblk > NOALLOC_MAX_BLOCKS)
+      return fail(AVS_E_CAPACITY, "avs_moments_noalloc: %d cells > its limit of %d", ctx->nc,
+                  NOALLOC_MAX_BLOCKS * NOALLOC_CELLS_PER_BLOCK);
+  }
+  double* scr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < NOALLOC_MAX_DEVICES) scr = g_scratch_dev[ctx->device];
+  }
+  if (totals_host && !scr)
+    return fail(AVS_E_HIP, "avs_moments_noalloc: the static scratch of device %d has no device address", ctx->device);
+  if (fields_dev) {
+    if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
+    if (ctx->D == 2)
+      k_fields<2><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->gas, ctx->W, ctx->q, fields_dev);
+    else
+      k_fields<3><<<(ctx->nc + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(ctx->nc, ctx->gas, ctx->W, ctx->q, fields_dev);
+    CKL();
+  }
+  if (totals_host) {
+    // partials of NOALLOC_CELLS_PER_BLOCK cells each, then their sum in block
+    // order, staged at the end of the partials for the host copy; every
+    // entry read is written first in the same call
+    const int N = ctx->D + 2;
+    const int nblk = (ctx->nc + NOALLOC_CELLS_PER_BLOCK - 1) / NOALLOC_CELLS_PER_BLOCK;
+    double* part = scr;
+    double* out = scr + (size_t)NOALLOC_MAX_BLOCKS * 5;
+    if (ctx->D == 2) {
+      k_totals_part<2><<<nblk, BLOCK, 0, ctx->stream>>>(ctx->nc, NOALLOC_CELLS_PER_BLOCK, ctx->geo.vol, ctx->W, part);
+      CKL();
+      k_totals<2><<<1, BLOCK, 0, ctx->stream>>>(nblk, nullptr, part, out);
+    } else {
+      k_totals_part<3><<<nblk, BLOCK, 0, ctx->stream>>>(ctx->nc, NOALLOC_CELLS_PER_BLOCK, ctx->geo.vol, ctx->W, part);
+      CKL();
+      k_totals<3><<<1, BLOCK, 0, ctx->stream>>>(nblk, nullptr, part, out);
+    }
+    CKL();
+    CK(hipMemcpyAsync(totals_host, out, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
   }
   return AVS_OK;

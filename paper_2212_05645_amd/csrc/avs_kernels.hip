@@ -1620,15 +1620,33 @@ __global__ __launch_bounds__(BLOCK) void k_residual(int nc, const double* __rest
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_totals(int nc, const double* __restrict__ vol, const double* __restrict__ W,
                                                    double* __restrict__ out) {
+  // vol == nullptr: rows of W summed as they are (a second reduction level)
   constexpr int N = D + 2;
   __shared__ double red[4 * N];
   double acc[N];
   for (int m = 0; m < N; ++m) acc[m] = 0.0;
   for (int i = threadIdx.x; i < nc; i += BLOCK)
-    for (int m = 0; m < N; ++m) acc[m] += vol[i] * W[(size_t)i * N + m];
+    for (int m = 0; m < N; ++m) acc[m] += (vol ? vol[i] : 1.0) * W[(size_t)i * N + m];
   block_sum<N>(acc, red);
   if (threadIdx.x == 0)
     for (int m = 0; m < N; ++m) out[m] = acc[m];
+}
+
+// Partial sums of V_i W_i over consecutive blocks of per cells: block b
+// writes row b of part (N doubles).
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_totals_part(int nc, int per, const double* __restrict__ vol,
+                                                        const double* __restrict__ W, double* __restrict__ part) {
+  constexpr int N = D + 2;
+  __shared__ double red[4 * N];
+  double acc[N];
+  for (int m = 0; m < N; ++m) acc[m] = 0.0;
+  const int i0 = blockIdx.x * per, i1 = min(nc, i0 + per);
+  for (int i = i0 + threadIdx.x; i < i1; i += BLOCK)
+    for (int m = 0; m < N; ++m) acc[m] += vol[i] * W[(size_t)i * N + m];
+  block_sum<N>(acc, red);
+  if (threadIdx.x == 0)
+    for (int m = 0; m < N; ++m) part[(size_t)blockIdx.x * N + m] = acc[m];
 }
 
 template <int D>
