@@ -85,6 +85,8 @@ struct avs_ctx {
   int ld[2] = {0, 0};
 
   double *W, *Wn, *q, *mom, *tpar, *lam, *fpar, *F, *bden, *bfin, *bcpair, *momp, *res, *tot;
+  double* fmom;           // face-moment partials of pass A: [nf+1][2 sides][nchs chunks][NM]
+  int nchs;               // chunk stride of fmom: ceil(capacity / CHUNK_MIN)
   double *cc, *crit_part, *Mk, *probe_cc, *probe_prim;
   int8_t *raw, *eff;
   int *cnt, *off, *pkind, *psrc, *pchild, *bad;
@@ -248,6 +250,8 @@ void carve(avs_ctx& x, Carver& c) {
   x.tpar = c.take<double>(nc * NPAR);
   x.lam = c.take<double>(nc * N);
   x.fpar = c.take<double>((nf + 1) * NPAR);
+  x.nchs = (int)((cap + CHUNK_MIN - 1) / CHUNK_MIN);
+  x.fmom = c.take<double>((nf + 1) * 2 * (size_t)x.nchs * (D == 2 ? NM2 : NM3));
   x.F = c.take<double>((nf + 1) * N);
   x.bden = c.take<double>(nf + 1);
   x.bfin = c.take<double>((nf + 1) * N);
@@ -436,22 +440,20 @@ avs_status launch_interfaces(avs_ctx* ctx) {
   const Leaves L = ctx->leaves(ctx->lcur);
   const int nu = ctx->vg.numax;
   const T* vin = (const T*)ctx->vdf[ctx->cur];
+  const int nch = (L.n + CHUNK - 1) / CHUNK;
   {
+    // reconstruction, interface rows and the faces' moment partials
     ProfScope ps(ctx, K_PASSA);
-    const int nch = (L.n + CHUNK - 1) / CHUNK;
     const int gx = (int)round_up(ctx->nc, 8);
-    k_passA<D, T><<<dim3(gx, nch), BLOCK, 0, ctx->stream>>>(ctx->geo, L, vin, ctx->bcpair, ctx->h, (T*)ctx->fv, CHUNK);
-    CKL();
-  }
-  {
-    ProfScope ps(ctx, K_FACE);
-    k_face<D, T><<<ctx->nf, BLOCK, 0, ctx->stream>>>(ctx->geo, L, (const T*)ctx->fv, ctx->fpar);
+    k_passA<D, T><<<dim3(gx, nch), passA_threads<D>(), 0, ctx->stream>>>(ctx->geo, L, vin, ctx->bcpair, ctx->h, (T*)ctx->fv,
+                                                            ctx->fmom, ctx->nchs, CHUNK);
     CKL();
   }
   {
     ProfScope ps(ctx, K_FACE_EQFLUX);
     k_face_eq<D, T><<<ctx->nf, BLOCK, (size_t)D * nu * sizeof(T), ctx->stream>>>(
-        ctx->geo, L, ctx->vg, ctx->gas, ctx->h, ctx->bden, ctx->bfin, ctx->fpar, ctx->F, ctx->bad);
+        ctx->geo, L, ctx->vg, ctx->gas, ctx->h, ctx->bden, ctx->bfin, ctx->fmom, ctx->nchs, nch, ctx->fpar, ctx->F,
+        ctx->bad);
     CKL();
   }
   return AVS_OK;
@@ -745,6 +747,8 @@ CaseArgs<T> case_args(avs_ctx* c, int flip, int chunk) {
   a.bcpair = c->bcpair;
   a.mom = c->mom;
   a.bad = c->bad;
+  a.fmom = c->fmom;
+  a.nchs = c->nchs;
   a.chunk = chunk;
   a.gx = (int)round_up(c->nc, 8);
   return a;
@@ -766,7 +770,7 @@ avs_status batch_upload(avs_batch* b) {
     args[n + i] = case_args<T>(c, 1, ch);
     const int nl = c->nleaf[c->lcur];
     const int gx = (int)round_up(c->nc, 8);
-    const int cnt[BK_N] = {gx * ((nl + ch - 1) / ch), c->nf, c->nf, (c->nc + BLOCK - 1) / BLOCK, c->nc, gx};
+    const int cnt[BK_N] = {gx * ((nl + ch - 1) / ch), c->nf, (c->nc + BLOCK - 1) / BLOCK, c->nc, gx};
     for (int k = 0; k < BK_N; ++k) off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + cnt[k];
   }
   for (int k = 0; k < BK_N; ++k) b->nblk[k] = off[k * (n + 1) + n];
@@ -786,9 +790,7 @@ avs_status batch_launch(avs_batch* b, int nsteps) {
   constexpr int MAXF = Cfg<D>::MAXF;
   for (int s = 0; s < nsteps; ++s) {
     const CaseArgs<T>* a = args + (s & 1) * n;
-    kb_passA<D, T><<<b->nblk[BK_PASSA], BLOCK, 0, b->stream>>>(a, off + BK_PASSA * (n + 1), n);
-    CKL();
-    kb_face<D, T><<<b->nblk[BK_FACE], BLOCK, 0, b->stream>>>(a, off + BK_FACE * (n + 1), n);
+    kb_passA<D, T><<<b->nblk[BK_PASSA], passA_threads<D>(), 0, b->stream>>>(a, off + BK_PASSA * (n + 1), n);
     CKL();
     kb_face_eq<D, T><<<b->nblk[BK_FACEQ], BLOCK, (size_t)D * numax * sizeof(T), b->stream>>>(a, off + BK_FACEQ * (n + 1), n);
     CKL();

@@ -19,6 +19,7 @@ constexpr int CRIT_CELLS = 256;  // cells per criterion partial
 #define AVS_CHUNK 8192
 #endif
 constexpr int CHUNK = AVS_CHUNK;  // leaves per workgroup of pass A
+constexpr int CHUNK_MIN = 512;    // smallest pass-A chunk (sizes the face-moment partials)
 
 // Equilibrium parameter record (face or cell), NPAR doubles:
 //   [0] coef = rho (2 pi R T)^(-D/2)   [1..3] U   [4] RT   [5] 1/(2RT)   [6] 1/RT

@@ -78,6 +78,28 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
   __syncthreads();
 }
 
+// Block total of each of N per-thread values, returned to thread t < N for
+// entry t (other threads get 0); the same association as block_sum.
+template <int N>
+__device__ __forceinline__ double block_sum_pick(double (&v)[N], double* red) {
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[m] += __shfl_xor(v[m], o);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) red[w * N + m] = v[m];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const double r = t < N ? (red[t] + red[N + t]) + (red[2 * N + t] + red[3 * N + t]) : 0.0;
+  __syncthreads();
+  return r;
+}
+
 // ------------------------------------------------------------- equilibria
 template <int D>
 __device__ __forceinline__ void build_tab(double* tab, const double* par, const VGrid& vg) {
@@ -507,12 +529,14 @@ __device__ __forceinline__ void load_stencil(const Geo& g, const T* __restrict__
 }
 
 // Least-squares gradient and Venkatakrishnan limiter at leaf k, in T.
-template <int D, typename T>
+// FULL: every one of the MAXF slots is a face with an interior neighbour
+// (known at compile time, so the slot tests vanish from the leaf loop).
+template <int D, typename T, bool FULL = false>
 __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi)[Cfg<D>::P],
                                          T (&lg)[Cfg<D>::P][D]) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
   const unsigned ko = (unsigned)k * (unsigned)sizeof(T);
-  const int ns = st.ns;
+  const int ns = FULL ? MAXF : st.ns;
   // the neighbour extrema are kept as differences from phi (rounding is
   // monotone, so max_j(v_j - phi) equals max_j(v_j) - phi exactly, and the
   // differences, being arithmetic results, need no NaN canonicalisation)
@@ -535,7 +559,7 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
     for (int p = 0; p < P; ++p) nv[s][p] = at_(st.nb[s][p], ko);
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
-    if (st.nbmask & (1u << s)) {
+    if (FULL || (st.nbmask & (1u << s))) {
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         const T v = nv[s][p];
@@ -569,7 +593,7 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
     T lim = 1;
     // below the smallest normal number the stencil differences carry no
     // information (and the scale would overflow): leave the slope unlimited
-    if (ns > 0 && m > (sizeof(T) == 8 ? (T)1e-300 : (T)1e-36)) {
+    if ((FULL || ns > 0) && m > (sizeof(T) == 8 ? (T)1e-300 : (T)1e-36)) {
       int ex;
       (void)frexp(m, &ex);                             // m = f 2^ex, f in [0.5, 1)
       const T inv = ldexp((T)1, -ex);                  // scaled values lie in [0, 1)
@@ -580,7 +604,7 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
       T Nm = 1, Dm = 0;                                // running minimum, starts at +inf
 #pragma unroll
       for (int s = 0; s < MAXF; ++s) {
-        if (s < ns) {
+        if (FULL || s < ns) {
           // D2 = 0 gives a = 0 and N = Dn = c exactly (psi = 1); the tiny term
           // keeps c > 0 where b and eps vanish too
           const T a = fabs(d2s[s]) * inv;
@@ -601,16 +625,78 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
 // ------------------------------------------------------------ pass A (S4)
 // Per cell and leaf: limited gradient, and the upwind reconstruction at
 // x_f - xi h for every face where this cell is upwind, stored to the
-// interface buffer (exactly one writer per face and leaf).  Grid (cells,
-// leaf chunks) with cells fastest, so that a cell and its neighbours read
-// the same chunk of their rows at about the same time.
+// interface buffer (exactly one writer per face and leaf), and the raw
+// moments of those reconstructions over the workgroup's leaves (Eq.
+// w_interface), one partial per (face, side, leaf chunk): the face's moments
+// are the sum of its two sides' partials over the chunks, each leaf counted
+// once (on its upwind side).  Grid (cells, leaf chunks) with cells fastest,
+// so that a cell and its neighbours read the same chunk of their rows at
+// about the same time.
+//
+// Raw moment slots (NM per face): m0, m1[D], m2[D(D+1)/2] (upper triangle,
+// row by row), e = sum A (|xi|^2 G + H)/2, e1[D] = sum A xi (|xi|^2 G + H)/2.
+
+// Threads of a pass-A workgroup: one wave per face slot, so that after the
+// reconstruction of a block of NT leaves (one leaf per thread) wave s sums
+// the moments of face s over the block (MAXF leaves per lane, from LDS).
+template <int D>
+constexpr int passA_threads() { return 64 * Cfg<D>::MAXF; }
+
+// Sums of the face moments: FP64 in the FP64 form; in the FP32 form FP32
+// lane sums of at most chunk/64 terms per face (a blocked sum whose rounding
+// stays at the order of the FP32 storage's), added across lanes, workgroups
+// and chunks in FP64.
+template <typename T> struct MomAcc { using type = double; };
+template <> struct MomAcc<float> { using type = float; };
+
+template <int D, typename A>
+__device__ __forceinline__ void face_mom_acc(A* m, A aw, A hw, const A (&x)[D], A G, A H) {
+  A x2 = x[0] * x[0];
+#pragma unroll
+  for (int d = 1; d < D; ++d) x2 += x[d] * x[d];
+  const A aG = aw * G;
+  int t = 0;
+  m[t++] += aG;
+#pragma unroll
+  for (int d = 0; d < D; ++d) m[t++] += aG * x[d];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int e = d; e < D; ++e) m[t++] += (aG * x[d]) * x[e];
+  const A eh = hw * (x2 * G + H);
+  m[t++] += eh;
+#pragma unroll
+  for (int d = 0; d < D; ++d) m[t++] += eh * x[d];
+}
+
+// LDS of one pass-A workgroup: the per-cell constants, and one block of
+// reconstructions for the face sums: the upwind value of each face (0 where
+// the cell is downwind), the leaf centre and weight.
 template <int D, typename T>
-__device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ vdf, const double* __restrict__ bcpair,
-                                        double h, T* __restrict__ fv, int chunk, int bx, int by) {
-  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
-  const int i = xcd_cell(g, bx);
-  if (i < 0) return;
-  const int k0 = by * chunk, k1 = min(L.n, k0 + chunk);
+struct PassAShared {
+  static constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF, NT = passA_threads<D>();
+  using A = typename MomAcc<T>::type;
+  T cf[MAXF * D], dd[MAXF * D];
+  double nrm[MAXF * D], sig[MAXF];
+  A u[MAXF][P][NT];
+  A x[D][NT];
+  A a[NT];
+};
+
+template <int D, typename T, bool FULL>
+__device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, const Leaves& L,
+                                           const T* __restrict__ vdf, const double* __restrict__ bcpair, double h,
+                                           T* __restrict__ fv, double* __restrict__ fmom, int nchs, int i, int k0,
+                                           int k1, int by) {
+  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF, NM = Cfg<D>::NM, NT = passA_threads<D>();
+  using A = typename MomAcc<T>::type;
+  T* const s_cf = sh.cf;
+  T* const s_dd = sh.dd;
+  double* const s_nrm = sh.nrm;
+  double* const s_sig = sh.sig;
+  auto& s_u = sh.u;
+  auto& s_x = sh.x;
+  auto& s_a = sh.a;
   const size_t cs = (size_t)g.nc * L.ld;
   const size_t fs = (size_t)g.nf * L.ld;   // component stride of the interface buffer
   // where the per-cell constants live: scalar registers (loaded from global
@@ -620,8 +706,6 @@ __device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ v
   // registers bound the occupancy).
   constexpr bool lds_consts = D == 2 && sizeof(T) == 4;
   constexpr bool lds_nrm = D == 2;
-  __shared__ T s_cf[MAXF * D], s_dd[MAXF * D];
-  __shared__ double s_nrm[MAXF * D], s_sig[MAXF];
   Stencil<D, T> st;
   double nrm[MAXF][D];
   unsigned lside = 0;          // bit s: the cell is the L side of face s
@@ -646,60 +730,147 @@ __device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ v
   } else {
     load_stencil<D, T>(g, vdf, cs, L.ld, i, st);
   }
+  const int ns = FULL ? MAXF : st.ns;
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
-    const int f = s < st.ns ? g.s_face[i * MAXF + s] : 0;
+    const int f = (FULL || s < ns) ? g.s_face[i * MAXF + s] : 0;
     if constexpr (lds_nrm) {
       if (s_sig[s] > 0.0) lside |= 1u << s;
 #pragma unroll
       for (int d = 0; d < D; ++d) nrm[s][d] = s_nrm[s * D + d];
     } else {
-      if (s < st.ns && g.s_sig[i * MAXF + s] > 0.0) lside |= 1u << s;
+      if ((FULL || s < ns) && g.s_sig[i * MAXF + s] > 0.0) lside |= 1u << s;
 #pragma unroll
       for (int d = 0; d < D; ++d) nrm[s][d] = g.f_nrm[(size_t)f * D + d];
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) row[s][p] = fv + p * fs + (size_t)f * L.ld;
   }
+  // wave w sums face w: its moment accumulators (NM per lane)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  A acc[NM];
+#pragma unroll
+  for (int t = 0; t < NM; ++t) acc[t] = 0;
   const T th = (T)h;
-  for (int k = k0 + threadIdx.x; k < k1; k += BLOCK) {
-    double xi[D];
+  for (int kb = k0; kb < k1; kb += NT) {
+    const int k = kb + threadIdx.x;
+    if (k < k1) {
+      double xi[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) xi[d] = at_(L.xi + (size_t)d * L.cap, (unsigned)k * 8u);
-    T phi[P], lg[P][D];
-    lim_grad<D, T>(st, k, phi, lg);
+      for (int d = 0; d < D; ++d) xi[d] = at_(L.xi + (size_t)d * L.cap, (unsigned)k * 8u);
+      T phi[P], lg[P][D];
+      lim_grad<D, T, FULL>(st, k, phi, lg);
 #pragma unroll
-    for (int s = 0; s < MAXF; ++s) {
-      if (s < st.ns) {
-        const double sn = normal_speed<D>(xi, nrm[s]);
-        const bool up = (lside >> s) & 1u ? (sn >= 0.0) : (sn < 0.0);
-        if (up) {
+      for (int s = 0; s < MAXF; ++s) {
+        A u[P];
 #pragma unroll
-          for (int p = 0; p < P; ++p) {
-            T v = 0;
+        for (int p = 0; p < P; ++p) u[p] = 0;
+        if (FULL || s < ns) {
+          const double sn = normal_speed<D>(xi, nrm[s]);
+          const bool up = (lside >> s) & 1u ? (sn >= 0.0) : (sn < 0.0);
+          if (up) {
 #pragma unroll
-            for (int d = 0; d < D; ++d) v += lg[p][d] * (st.dd[s][d] - (T)xi[d] * th);
-            __builtin_nontemporal_store((T)(phi[p] + v), ptr_at_(row[s][p], (unsigned)k * (unsigned)sizeof(T)));   // read by later kernels only
+            for (int p = 0; p < P; ++p) {
+              T dv = 0;
+#pragma unroll
+              for (int d = 0; d < D; ++d) dv += lg[p][d] * (st.dd[s][d] - (T)xi[d] * th);
+              const T v = phi[p] + dv;
+              __builtin_nontemporal_store(v, ptr_at_(row[s][p], (unsigned)k * (unsigned)sizeof(T)));   // read by pass C only
+              u[p] = (A)v;
+            }
+          } else if (!FULL && !((st.nbmask >> s) & 1u)) {
+            // incoming leaf of a boundary face: the wall or far-field
+            // Maxwellian, unscaled (the wall density ratio is applied in pass C)
+            const int bc = -1 - g.f_R[g.s_face[i * MAXF + s]];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+              __builtin_nontemporal_store((T)bcpair[((size_t)bc * P + p) * L.cap + k],
+                                          ptr_at_(row[s][p], (unsigned)k * (unsigned)sizeof(T)));
           }
-        } else if (!((st.nbmask >> s) & 1u)) {
-          // incoming leaf of a boundary face: the wall or far-field
-          // Maxwellian, unscaled (the wall density ratio is applied in pass C)
-          const int bc = -1 - g.f_R[g.s_face[i * MAXF + s]];
-#pragma unroll
-          for (int p = 0; p < P; ++p)
-            __builtin_nontemporal_store((T)bcpair[((size_t)bc * P + p) * L.cap + k],
-                                        ptr_at_(row[s][p], (unsigned)k * (unsigned)sizeof(T)));
         }
+#pragma unroll
+        for (int p = 0; p < P; ++p) s_u[s][p][threadIdx.x] = u[p];
       }
+#pragma unroll
+      for (int d = 0; d < D; ++d) s_x[d][threadIdx.x] = (A)xi[d];
+      s_a[threadIdx.x] = (A)at_(L.w, (unsigned)k * 8u);
+    } else {
+#pragma unroll
+      for (int s = 0; s < MAXF; ++s)
+#pragma unroll
+        for (int p = 0; p < P; ++p) s_u[s][p][threadIdx.x] = 0;
+      s_a[threadIdx.x] = 0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) s_x[d][threadIdx.x] = 0;
+    }
+    __syncthreads();
+    // the face of this wave: moments of its upwind values over the block
+    if (FULL || wave < ns) {
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) {
+        const int j = q * 64 + lane;
+        A x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = s_x[d][j];
+        const A aw = s_a[j];
+        face_mom_acc<D, A>(acc, aw, (A)0.5 * aw, x, s_u[wave][0][j], P == 2 ? s_u[wave][P - 1][j] : (A)0);
+      }
+    }
+    __syncthreads();
+  }
+  // one partial per (face, side, chunk): the wave's lanes added in FP64
+  if (FULL || wave < ns) {
+    double tot[NM];
+#pragma unroll
+    for (int t = 0; t < NM; ++t) {
+      tot[t] = (double)acc[t];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) tot[t] += __shfl_xor(tot[t], o);
+    }
+    if (lane < NM) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < NM; ++t)
+        if (t == lane) v = tot[t];
+      const int f = g.s_face[i * MAXF + wave];
+      const int side = g.s_sig[i * MAXF + wave] > 0.0 ? 0 : 1;
+      fmom[(((size_t)f * 2 + side) * nchs + by) * NM + lane] = v;
     }
   }
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passA(Geo g, Leaves L, const T* __restrict__ vdf,
+__device__ __forceinline__ void d_passA(Geo g, Leaves L, const T* __restrict__ vdf, const double* __restrict__ bcpair,
+                                        double h, T* __restrict__ fv, double* __restrict__ fmom, int nchs, int chunk,
+                                        int bx, int by) {
+  constexpr int MAXF = Cfg<D>::MAXF;
+  const int i = xcd_cell(g, bx);
+  if (i < 0) return;
+  const int k0 = by * chunk, k1 = min(L.n, k0 + chunk);
+  // a cell whose every slot is a face with an interior neighbour takes the
+  // specialised loop (no slot tests); others (boundary cells, cells with
+  // fewer faces) the general one
+  bool full = g.nslot[i] == MAXF;
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s) full = full && g.s_nbr[i * MAXF + s] >= 0;
+  __shared__ PassAShared<D, T> sh;
+  if (full)
+    passA_cell<D, T, true>(sh, g, L, vdf, bcpair, h, fv, fmom, nchs, i, k0, k1, by);
+  else
+    passA_cell<D, T, false>(sh, g, L, vdf, bcpair, h, fv, fmom, nchs, i, k0, k1, by);
+}
+
+// Waves per SIMD pass A asks for: the face-moment accumulators (MAXF x NM
+// lane sums) and the limiter's live values share the vector registers.
+template <int D, typename T>
+constexpr int passA_waves() { return D == 2 ? (sizeof(T) == 8 ? 3 : 5) : (sizeof(T) == 8 ? 3 : 4); }
+
+template <int D, typename T>
+__global__ __launch_bounds__(passA_threads<D>(), (passA_waves<D, T>())) void k_passA(Geo g, Leaves L, const T* __restrict__ vdf,
                                                                       const double* __restrict__ bcpair, double h,
-                                                                      T* __restrict__ fv, int chunk) {
-  d_passA<D, T>(g, L, vdf, bcpair, h, fv, chunk, blockIdx.x, blockIdx.y);
+                                                                      T* __restrict__ fv, double* __restrict__ fmom,
+                                                                      int nchs, int chunk) {
+  d_passA<D, T>(g, L, vdf, bcpair, h, fv, fmom, nchs, chunk, blockIdx.x, blockIdx.y);
 }
 
 // Flux of a raw-moment set through normal n: (n.m1, n.m2, n.e1).
@@ -723,86 +894,19 @@ __device__ __forceinline__ void raw_flux(const double* m, const double* n, doubl
 }
 
 // ------------------------------------------------------ interface (S5-S8)
-// Two kernels per step.  d_face: one workgroup per face streams the face's
-// row of the interface buffer and sums the raw moments of the reconstructed
-// VDF (Eq. w_interface; on a boundary face over the outgoing leaves only)
-// into the face's record slot.  d_face_eq: from those moments, interior
-// face: interface state, tau, heat flux relaxed over h at rate Pr/tau,
-// Shakhov record and blend weights, then the flux F = a sum A s psi phibar
-// + b sum A s psi g_f with g_f evaluated in R from the record.  Boundary
-// face: outgoing flux plus the incoming wall (zero net mass flux, rho_w) or
-// far-field Maxwellian flux.  Splitting the reduction from the record and
-// the equilibrium sum keeps both kernels at a small register footprint.
-#ifndef AVS_FACE_LEAVES
-#define AVS_FACE_LEAVES 2
-#endif
-template <int D, typename R>
-constexpr int face_leaves() { return AVS_FACE_LEAVES; }
-
-template <int D, typename R>
-__device__ __forceinline__ void d_face(Geo g, Leaves L, const R* __restrict__ fv, double* __restrict__ fpar, int bx) {
-  constexpr int P = Cfg<D>::P, NM = Cfg<D>::NM;
-  __shared__ double red[4 * NM];
-  const int f = bx;
-  const int Rc = g.f_R[f];
-  const size_t fs = (size_t)g.nf * L.ld;
-  double n[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
-  double m[NM];
-#pragma unroll
-  for (int t = 0; t < NM; ++t) m[t] = 0.0;
-  // U leaves per thread and iteration, all loaded before any is summed (the
-  // tail reads leaf n-1 again and skips it), so that a wave keeps U rows of
-  // memory traffic in flight; each thread still adds its leaves in
-  // increasing order, so the sums do not depend on U
-  constexpr int U = face_leaves<D, R>();
-  const unsigned rs = (unsigned)sizeof(R);
-  const R* row0 = fv + (size_t)f * L.ld;
-  const R* row1 = fv + fs + (size_t)f * L.ld;
-  for (int k0 = threadIdx.x; k0 < L.n; k0 += U * BLOCK) {
-    double xi[U][D], A[U], G[U], H[U];
-#pragma unroll
-    for (int v = 0; v < U; ++v) {
-      const unsigned kk = (unsigned)min(k0 + v * BLOCK, L.n - 1);
-#pragma unroll
-      for (int d = 0; d < D; ++d) xi[v][d] = at_(L.xi + (size_t)d * L.cap, kk * 8u);
-      A[v] = at_(L.w, kk * 8u);
-      G[v] = (double)at_(row0, kk * rs);
-      H[v] = P == 2 ? (double)at_(row1, kk * rs) : 0.0;
-    }
-#pragma unroll
-    for (int v = 0; v < U; ++v) {
-      if (k0 + v * BLOCK >= L.n) break;
-      if (Rc < 0 && normal_speed<D>(xi[v], n) < 0.0) continue;     // incoming leaf of a boundary face
-      double xi2 = 0.0;
-#pragma unroll
-      for (int d = 0; d < D; ++d) xi2 += xi[v][d] * xi[v][d];
-      const double aG = A[v] * G[v];
-      int t = 0;
-      m[t++] += aG;
-#pragma unroll
-      for (int d = 0; d < D; ++d) m[t++] += aG * xi[v][d];
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-#pragma unroll
-        for (int e = d; e < D; ++e) m[t++] += aG * xi[v][d] * xi[v][e];
-      }
-      const double eh = 0.5 * A[v] * (xi2 * G[v] + H[v]);
-      m[t++] += eh;
-#pragma unroll
-      for (int d = 0; d < D; ++d) m[t++] += eh * xi[v][d];
-    }
-  }
-  block_sum<NM>(m, red);
-  if (threadIdx.x == 0)
-    for (int t = 0; t < NM; ++t) fpar[(size_t)f * NPAR + t] = m[t];
-}
+// d_face_eq: from the raw moments of the reconstructed VDF (Eq.
+// w_interface; on a boundary face over the outgoing leaves only), summed
+// from the partials pass A wrote: interior face: interface state, tau, heat
+// flux relaxed over h at rate Pr/tau, Shakhov record and blend weights, then
+// the flux F = a sum A s psi phibar + b sum A s psi g_f with g_f evaluated in
+// R from the record.  Boundary face: outgoing flux plus the incoming wall
+// (zero net mass flux, rho_w) or far-field Maxwellian flux.
 
 template <int D, typename R>
 __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, double h, const double* __restrict__ bden,
-                                          const double* __restrict__ bfin, double* __restrict__ fpar,
-                                          double* __restrict__ F, int* __restrict__ bad, int bx) {
+                                          const double* __restrict__ bfin, const double* __restrict__ fmom, int nchs,
+                                          int nch, double* __restrict__ fpar, double* __restrict__ F,
+                                          int* __restrict__ bad, int bx) {
   constexpr int NM = Cfg<D>::NM, N = D + 2;
   extern __shared__ double lds_d[];
   R* tab = reinterpret_cast<R*>(lds_d);
@@ -810,15 +914,29 @@ __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, d
   __shared__ double spar[NPAR];
   __shared__ R rp[NPAR];
   __shared__ double sF[N];
+  __shared__ double sm[NM];
   __shared__ int interior_ok;
   const int f = bx;
   const int Rc = g.f_R[f];
   double n[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
+  // raw moments of the interface VDF: the partials of pass A, chunk by chunk,
+  // L side then R side (a boundary face has its interior side only)
+  if (threadIdx.x < NM) {
+    const double* p0 = fmom + (size_t)f * 2 * nchs * NM + threadIdx.x;
+    const double* p1 = p0 + (size_t)nchs * NM;
+    double v = 0.0;
+    for (int c = 0; c < nch; ++c) {
+      v += p0[(size_t)c * NM];
+      if (Rc >= 0) v += p1[(size_t)c * NM];
+    }
+    sm[threadIdx.x] = v;
+  }
+  __syncthreads();
   double m[NM];
   if (threadIdx.x == 0)
-    for (int t = 0; t < NM; ++t) m[t] = fpar[(size_t)f * NPAR + t];
+    for (int t = 0; t < NM; ++t) m[t] = sm[t];
   if (threadIdx.x == 0) {
     interior_ok = 0;
     if (Rc >= 0) {
@@ -902,15 +1020,12 @@ __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, d
 template <int D, typename R>
 __global__ __launch_bounds__(BLOCK) void k_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, double h,
                                                   const double* __restrict__ bden, const double* __restrict__ bfin,
+                                                  const double* __restrict__ fmom, int nchs, int nch,
                                                   double* __restrict__ fpar, double* __restrict__ F,
                                                   int* __restrict__ bad) {
-  d_face_eq<D, R>(g, L, vg, gas, h, bden, bfin, fpar, F, bad, blockIdx.x);
+  d_face_eq<D, R>(g, L, vg, gas, h, bden, bfin, fmom, nchs, nch, fpar, F, bad, blockIdx.x);
 }
 
-template <int D, typename R>
-__global__ __launch_bounds__(BLOCK) void k_face(Geo g, Leaves L, const R* __restrict__ fv, double* __restrict__ fpar) {
-  d_face<D, R>(g, L, fv, fpar, blockIdx.x);
-}
 
 // ------------------------------------------------------ macro update (S8-S9)
 // Cell record of the relaxation target from the new state w of cell i:
@@ -1695,10 +1810,12 @@ struct CaseArgs {
   const double* bcpair;
   double* mom;
   int* bad;
+  double* fmom;    // face-moment partials of pass A [nf][2][nchs][NM]
+  int nchs;        // their chunk stride
   int chunk, gx;   // pass A: leaves per workgroup, round_up(nc, 8)
 };
 
-enum { BK_PASSA, BK_FACE, BK_FACEQ, BK_MACRO, BK_TARGET, BK_PASSC, BK_N };
+enum { BK_PASSA, BK_FACEQ, BK_MACRO, BK_TARGET, BK_PASSC, BK_N };
 
 // Largest c with off[c] <= b (off has ncase + 1 increasing entries).
 __device__ __forceinline__ int find_case(const int* __restrict__ off, int ncase, int b) {
@@ -1733,21 +1850,13 @@ __device__ __forceinline__ Leaves global_leaves(Leaves L) {
 #undef AVS_G
 
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passA(const CaseArgs<T>* __restrict__ args,
+__global__ __launch_bounds__(passA_threads<D>(), (passA_waves<D, T>())) void kb_passA(const CaseArgs<T>* __restrict__ args,
                                                                        const int* __restrict__ off, int ncase) {
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
   const int lb = blockIdx.x - off[c];
-  d_passA<D, T>(global_geo(a->g), global_leaves(a->L), gptr(a->vin), gptr(a->bcpair), a->h, gptr(a->fv), a->chunk,
-                lb % a->gx, lb / a->gx);
-}
-
-template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void kb_face(const CaseArgs<T>* __restrict__ args, const int* __restrict__ off,
-                                                int ncase) {
-  const int c = find_case(off, ncase, blockIdx.x);
-  const CaseArgs<T>* a = args + c;
-  d_face<D, T>(global_geo(a->g), global_leaves(a->L), gptr(a->fv), gptr(a->fpar), blockIdx.x - off[c]);
+  d_passA<D, T>(global_geo(a->g), global_leaves(a->L), gptr(a->vin), gptr(a->bcpair), a->h, gptr(a->fv),
+                gptr(a->fmom), a->nchs, a->chunk, lb % a->gx, lb / a->gx);
 }
 
 template <int D, typename T>
@@ -1756,7 +1865,8 @@ __global__ __launch_bounds__(BLOCK) void kb_face_eq(const CaseArgs<T>* __restric
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
   d_face_eq<D, T>(global_geo(a->g), global_leaves(a->L), a->vg, a->gas, a->h, gptr(a->bden), gptr(a->bfin),
-                  gptr(a->fpar), gptr(a->F), gptr(a->bad), blockIdx.x - off[c]);
+                  gptr(a->fmom), a->nchs, (a->L.n + a->chunk - 1) / a->chunk, gptr(a->fpar), gptr(a->F),
+                  gptr(a->bad), blockIdx.x - off[c]);
 }
 
 template <int D, typename T>
