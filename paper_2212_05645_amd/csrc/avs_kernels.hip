@@ -528,14 +528,46 @@ __device__ __forceinline__ void load_stencil(const Geo& g, const T* __restrict__
   }
 }
 
+// The stencil values of leaf k: the cell's own value and every neighbour's
+// (a slot without an interior neighbour points at the cell's own row),
+// loaded together so that they are in flight at once.
+template <int D, typename T>
+struct StencilVals {
+  T phi[Cfg<D>::P];
+  T nv[Cfg<D>::MAXF][Cfg<D>::P];
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void load_vals(const Stencil<D, T>& st, int k, StencilVals<D, T>& v) {
+  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+  const unsigned ko = (unsigned)k * (unsigned)sizeof(T);
+#pragma unroll
+  for (int p = 0; p < P; ++p) v.phi[p] = at_(st.own[p], ko);
+#pragma unroll
+  for (int s = 0; s < MAXF; ++s)
+#pragma unroll
+    for (int p = 0; p < P; ++p) v.nv[s][p] = at_(st.nb[s][p], ko);
+}
+
 // Least-squares gradient and Venkatakrishnan limiter at leaf k, in T.
 // FULL: every one of the MAXF slots is a face with an interior neighbour
 // (known at compile time, so the slot tests vanish from the leaf loop).
 template <int D, typename T, bool FULL = false>
+__device__ __forceinline__ void lim_grad_of(const Stencil<D, T>& st, const StencilVals<D, T>& sv, T (&phi)[Cfg<D>::P],
+                                            T (&lg)[Cfg<D>::P][D]);
+
+template <int D, typename T, bool FULL = false>
 __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi)[Cfg<D>::P],
                                          T (&lg)[Cfg<D>::P][D]) {
+  StencilVals<D, T> sv;
+  load_vals<D, T>(st, k, sv);
+  lim_grad_of<D, T, FULL>(st, sv, phi, lg);
+}
+
+template <int D, typename T, bool FULL>
+__device__ __forceinline__ void lim_grad_of(const Stencil<D, T>& st, const StencilVals<D, T>& sv, T (&phi)[Cfg<D>::P],
+                                            T (&lg)[Cfg<D>::P][D]) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
-  const unsigned ko = (unsigned)k * (unsigned)sizeof(T);
   const int ns = FULL ? MAXF : st.ns;
   // the neighbour extrema are kept as differences from phi (rounding is
   // monotone, so max_j(v_j - phi) equals max_j(v_j) - phi exactly, and the
@@ -543,20 +575,13 @@ __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi
   T dmax[P], dmin[P], grad[P][D];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    phi[p] = at_(st.own[p], ko);
+    phi[p] = sv.phi[p];
     dmax[p] = 0;
     dmin[p] = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d) grad[p][d] = 0;
   }
-  // every neighbour value is loaded before any is used, so that the loads of
-  // a leaf are in flight together (a slot without an interior neighbour
-  // points at the cell's own row and is skipped below)
-  T nv[MAXF][P];
-#pragma unroll
-  for (int s = 0; s < MAXF; ++s)
-#pragma unroll
-    for (int p = 0; p < P; ++p) nv[s][p] = at_(st.nb[s][p], ko);
+  const auto& nv = sv.nv;
 #pragma unroll
   for (int s = 0; s < MAXF; ++s) {
     if (FULL || (st.nbmask & (1u << s))) {
@@ -655,14 +680,17 @@ __device__ __forceinline__ void face_mom_acc(A* m, A aw, A hw, const A (&x)[D], 
 #pragma unroll
   for (int d = 1; d < D; ++d) x2 += x[d] * x[d];
   const A aG = aw * G;
+  A ax[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) ax[d] = aG * x[d];
   int t = 0;
   m[t++] += aG;
 #pragma unroll
-  for (int d = 0; d < D; ++d) m[t++] += aG * x[d];
+  for (int d = 0; d < D; ++d) m[t++] += ax[d];
 #pragma unroll
   for (int d = 0; d < D; ++d)
 #pragma unroll
-    for (int e = d; e < D; ++e) m[t++] += (aG * x[d]) * x[e];
+    for (int e = d; e < D; ++e) m[t++] += ax[d] * x[e];
   const A eh = hw * (x2 * G + H);
   m[t++] += eh;
 #pragma unroll
@@ -752,14 +780,26 @@ __device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, 
 #pragma unroll
   for (int t = 0; t < NM; ++t) acc[t] = 0;
   const T th = (T)h;
+  // the loads of the next block are issued before the face sums of this one,
+  // so that they are in flight across the barriers
+  StencilVals<D, T> sv;
+  double xi_n[D], aw_n = 0.0;
+  auto load_leaf = [&](int k) {
+    load_vals<D, T>(st, k, sv);
+#pragma unroll
+    for (int d = 0; d < D; ++d) xi_n[d] = at_(L.xi + (size_t)d * L.cap, (unsigned)k * 8u);
+    aw_n = at_(L.w, (unsigned)k * 8u);
+  };
+  if (k0 + (int)threadIdx.x < k1) load_leaf(k0 + threadIdx.x);
   for (int kb = k0; kb < k1; kb += NT) {
     const int k = kb + threadIdx.x;
     if (k < k1) {
       double xi[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) xi[d] = at_(L.xi + (size_t)d * L.cap, (unsigned)k * 8u);
+      for (int d = 0; d < D; ++d) xi[d] = xi_n[d];
+      const double aw_k = aw_n;
       T phi[P], lg[P][D];
-      lim_grad<D, T, FULL>(st, k, phi, lg);
+      lim_grad_of<D, T, FULL>(st, sv, phi, lg);
 #pragma unroll
       for (int s = 0; s < MAXF; ++s) {
         A u[P];
@@ -793,7 +833,8 @@ __device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, 
       }
 #pragma unroll
       for (int d = 0; d < D; ++d) s_x[d][threadIdx.x] = (A)xi[d];
-      s_a[threadIdx.x] = (A)at_(L.w, (unsigned)k * 8u);
+      s_a[threadIdx.x] = (A)aw_k;
+      if (k + NT < k1) load_leaf(k + NT);
     } else {
 #pragma unroll
       for (int s = 0; s < MAXF; ++s)
