@@ -553,26 +553,39 @@ __device__ __forceinline__ void load_vals(const Stencil<D, T>& st, int k, Stenci
 // FULL: every one of the MAXF slots is a face with an interior neighbour
 // (known at compile time, so the slot tests vanish from the leaf loop).
 template <int D, typename T, bool FULL = false>
-__device__ __forceinline__ void lim_grad_of(const Stencil<D, T>& st, const StencilVals<D, T>& sv, T (&phi)[Cfg<D>::P],
-                                            T (&lg)[Cfg<D>::P][D]);
+__device__ __forceinline__ void lim_parts(const Stencil<D, T>& st, const StencilVals<D, T>& sv, T (&phi)[Cfg<D>::P],
+                                          T (&lim)[Cfg<D>::P], T (&grad)[Cfg<D>::P][D],
+                                          T (&d2s)[Cfg<D>::P][Cfg<D>::MAXF]);
 
+// The limited gradient L grad phi of leaf k (loads and arithmetic together).
 template <int D, typename T, bool FULL = false>
 __device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi)[Cfg<D>::P],
                                          T (&lg)[Cfg<D>::P][D]) {
+  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
   StencilVals<D, T> sv;
   load_vals<D, T>(st, k, sv);
-  lim_grad_of<D, T, FULL>(st, sv, phi, lg);
+  T lim[P], grad[P][D], d2s[P][MAXF];
+  lim_parts<D, T, FULL>(st, sv, phi, lim, grad, d2s);
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int d = 0; d < D; ++d) lg[p][d] = lim[p] * grad[p][d];
 }
 
+// Least-squares gradient, its increments grad . (x_f - x_i) towards the face
+// midpoints (D2 of the limiter, d2s) and the Venkatakrishnan limiter L, per
+// VDF component, in T.  FULL: every one of the MAXF slots is a face with an
+// interior neighbour (known at compile time, so the slot tests vanish).
 template <int D, typename T, bool FULL>
-__device__ __forceinline__ void lim_grad_of(const Stencil<D, T>& st, const StencilVals<D, T>& sv, T (&phi)[Cfg<D>::P],
-                                            T (&lg)[Cfg<D>::P][D]) {
+__device__ __forceinline__ void lim_parts(const Stencil<D, T>& st, const StencilVals<D, T>& sv, T (&phi)[Cfg<D>::P],
+                                          T (&lim)[Cfg<D>::P], T (&grad)[Cfg<D>::P][D],
+                                          T (&d2s)[Cfg<D>::P][Cfg<D>::MAXF]) {
   constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
   const int ns = FULL ? MAXF : st.ns;
   // the neighbour extrema are kept as differences from phi (rounding is
   // monotone, so max_j(v_j - phi) equals max_j(v_j) - phi exactly, and the
   // differences, being arithmetic results, need no NaN canonicalisation)
-  T dmax[P], dmin[P], grad[P][D];
+  T dmax[P], dmin[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     phi[p] = sv.phi[p];
@@ -604,7 +617,6 @@ __device__ __forceinline__ void lim_grad_of(const Stencil<D, T>& st, const Stenc
   // one division ends it.
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    T d2s[MAXF];
     const T up0 = dmax[p], dn0 = -dmin[p];
     T m = fmax(up0, dn0);
 #pragma unroll
@@ -612,10 +624,10 @@ __device__ __forceinline__ void lim_grad_of(const Stencil<D, T>& st, const Stenc
       T d2 = 0;
 #pragma unroll
       for (int d = 0; d < D; ++d) d2 += grad[p][d] * st.dd[s][d];
-      d2s[s] = d2;
+      d2s[p][s] = d2;
       m = fmax(fabs(d2), m);
     }
-    T lim = 1;
+    lim[p] = 1;
     // below the smallest normal number the stencil differences carry no
     // information (and the scale would overflow): leave the slope unlimited
     if ((FULL || ns > 0) && m > (sizeof(T) == 8 ? (T)1e-300 : (T)1e-36)) {
@@ -623,27 +635,33 @@ __device__ __forceinline__ void lim_grad_of(const Stencil<D, T>& st, const Stenc
       (void)frexp(m, &ex);                             // m = f 2^ex, f in [0.5, 1)
       const T inv = ldexp((T)1, -ex);                  // scaled values lie in [0, 1)
       // eps^2 beyond this makes psi = 1 to working precision; the clamp keeps
-      // the cross products below the overflow threshold of T
-      const T e2 = fmin(st.eps2 * inv * inv, sizeof(T) == 8 ? (T)1e30 : (T)1e15);
+      // the cross products below the overflow threshold of T.  The tiny term
+      // keeps c > 0 where b and eps vanish (D2 = 0 gives a = 0 and N = Dn = c
+      // exactly, psi = 1).
+      const T e2 = fmin(st.eps2 * inv * inv, sizeof(T) == 8 ? (T)1e30 : (T)1e15) +
+                   (sizeof(T) == 8 ? (T)1e-300 : (T)1e-30);
       const T up = up0 * inv, dn = dn0 * inv;
       T Nm = 1, Dm = 0;                                // running minimum, starts at +inf
 #pragma unroll
       for (int s = 0; s < MAXF; ++s) {
         if (FULL || s < ns) {
-          // D2 = 0 gives a = 0 and N = Dn = c exactly (psi = 1); the tiny term
-          // keeps c > 0 where b and eps vanish too
-          const T a = fabs(d2s[s]) * inv;
-          const T b = d2s[s] > (T)0 ? up : dn;
-          const T c = b * b + e2 + (sizeof(T) == 8 ? (T)1e-300 : (T)1e-30);
-          const T Nn = c + (T)2 * a * b;
-          const T Dd = c + a * ((T)2 * a + b);
-          if (Nn * Dm < Nm * Dd) { Nm = Nn; Dm = Dd; }
+          const T a = fabs(d2s[p][s]) * inv;
+          const T b = d2s[p][s] > (T)0 ? up : dn;
+          const T c = b * b + e2;
+          const T a2 = a + a;
+          const T Nn = a2 * b + c;
+          const T Dd = a * (a2 + b) + c;
+          if (FULL && s == 0) {
+            Nm = Nn;
+            Dm = Dd;
+          } else if (Nn * Dm < Nm * Dd) {
+            Nm = Nn;
+            Dm = Dd;
+          }
         }
       }
-      lim = Nm / Dm;
+      lim[p] = Nm / Dm;
     }
-#pragma unroll
-    for (int d = 0; d < D; ++d) lg[p][d] = lim * grad[p][d];
   }
 }
 
@@ -798,8 +816,18 @@ __device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, 
 #pragma unroll
       for (int d = 0; d < D; ++d) xi[d] = xi_n[d];
       const double aw_k = aw_n;
-      T phi[P], lg[P][D];
-      lim_grad_of<D, T, FULL>(st, sv, phi, lg);
+      T phi[P], lim[P], grad[P][D], d2s[P][MAXF];
+      lim_parts<D, T, FULL>(st, sv, phi, lim, grad, d2s);
+      // phibar = phi + L grad . (x_f - x_i) - h L grad . xi: the first product
+      // is the limiter's D2 of the face, the second is shared by the faces
+      T base[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        T gx = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) gx += grad[p][d] * (T)xi[d];
+        base[p] = phi[p] - th * lim[p] * gx;
+      }
 #pragma unroll
       for (int s = 0; s < MAXF; ++s) {
         A u[P];
@@ -811,10 +839,7 @@ __device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, 
           if (up) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-              T dv = 0;
-#pragma unroll
-              for (int d = 0; d < D; ++d) dv += lg[p][d] * (st.dd[s][d] - (T)xi[d] * th);
-              const T v = phi[p] + dv;
+              const T v = base[p] + lim[p] * d2s[p][s];
               __builtin_nontemporal_store(v, ptr_at_(row[s][p], (unsigned)k * (unsigned)sizeof(T)));   // read by pass C only
               u[p] = (A)v;
             }
