@@ -413,7 +413,10 @@ def run_batched(args):
         batch.close()
     return {"cycle_updates_per_s": updates / (ms * 1e-3), "sweep_updates_per_s": nodes / (sweep_ms * 1e-3),
             "sweep_ms": sweep_ms, "sequential_sweep_updates_per_s": nodes / (seq_ms * 1e-3),
-            "sequential_sweep_ms": seq_ms, "cases": len(cases), "cell_leaf_nodes": nodes, "tuned_chunk": chunk,
+            "sequential_sweep_ms": seq_ms, "cases": len(cases), "cell_leaf_nodes": nodes,
+            "tuned": {"passA_chunk_per_bucket": chunk[:4], "passC_leaves_in_flight": chunk[4]},
+            "roofline_sweep": {"algorithmic_bytes_per_node": 24, "frac": 24 * nodes / (sweep_ms * 1e-3) / HBM_PEAK},
+            "cycles_timed": args.steps,
             "workload": "64 seeded cavity/cylinder cases, Kn 1e-3..1, Ma 0.1..6, grids 32^2..96^2, "
                         "256..16k leaves, FP32, one graph per adaptation cycle"}
 
@@ -875,12 +878,18 @@ def main():
         w = w2
         del w2
         torch.cuda.empty_cache()
+    # the batched form (64 seeded cases, FP32) in every run, a few cycles
+    try:
+        bargs = argparse.Namespace(**vars(args))
+        if not args.forms:
+            bargs.steps, bargs.warmup = min(args.steps, 3), 1
+        b = run_batched(bargs)
+        b["over_fp64_sweep"] = b["sweep_updates_per_s"] / forms["fp64"]["sweep_updates_per_s"] if "fp64" in forms else None
+        forms["batched_fp32"] = b
+    except Exception as e:
+        forms["batched_fp32"] = {"error": repr(e)}
+    torch.cuda.empty_cache()
     if args.forms:
-        try:
-            forms["batched_fp32"] = run_batched(args)
-        except Exception as e:
-            forms["batched_fp32"] = {"error": repr(e)}
-        torch.cuda.empty_cache()
         try:
             forms["sphere_fp32"] = run_sphere(args)
         except Exception as e:

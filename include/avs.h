@@ -354,11 +354,14 @@ int32_t avs_profile_read(avs_ctx *ctx, int32_t nmax, char *names_host, double *m
  * is replayed until a case's leaf count or the tile choice changes.  The
  * members stay usable on their own (adapt, remap, moments) between batch
  * steps.  The batch workspace (device, avs_batch_workspace_bytes) holds the
- * per-case argument tables.  avs_batch_tune chooses the leaf chunk of pass A
- * (512..8192 leaves per workgroup) per leaf-count bucket of the members
- * (< 1024, < 4096, < 16384, more leaves): one bucket at a time, two timed
- * steps per candidate, the fastest kept; chunk_host (or NULL) receives the
- * four choices; the batch advances two steps per timed candidate.
+ * per-case argument tables.  avs_batch_tune chooses two tile parameters
+ * by timing: the leaf chunk of pass A (512..8192 leaves per workgroup) per
+ * leaf-count bucket of the members (< 1024, < 4096, < 16384, more leaves),
+ * one bucket at a time, then whether pass C keeps one or two leaves' loads
+ * in flight; each candidate is timed on two steps computed into the spare
+ * buffers and not taken, so the members' state is the same afterwards
+ * (their implicit-predictor and remap scratch is overwritten).  chunk_host
+ * (or NULL) receives five ints: the four chunks and the pass-C choice (0/1).
  * avs_batch_check waits and reports a non-physical state in any member. */
 typedef struct avs_batch avs_batch;
 size_t avs_batch_workspace_bytes(int32_t ncase);

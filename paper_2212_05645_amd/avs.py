@@ -618,10 +618,12 @@ class Batch:
         _check(lib.avs_batch_remap(self.b, int(correction)))
 
     def tune(self):
-        """Pass-A leaf chunk per leaf-count bucket (<1024, <4096, <16384, more)."""
-        ch = (C.c_int32 * 4)()
+        """Tile choice by timing on the members' own state (left unchanged):
+        pass-A leaf chunk per leaf-count bucket (<1024, <4096, <16384, more)
+        and pass C's leaves in flight (1 or 2); returns the five choices."""
+        ch = (C.c_int32 * 5)()
         _check(lib.avs_batch_tune(self.b, ch))
-        return list(ch)
+        return list(ch[:4]) + [int(ch[4]) + 1]
 
     def close(self):
         if getattr(self, "b", None):

@@ -702,12 +702,14 @@ struct avs_batch {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   int chunk[4] = {CHUNK, CHUNK, CHUNK, CHUNK};   // pass-A leaves per workgroup, per leaf-count bucket
+  int passc_two = -1;                           // pass C with two leaves in flight (1), one (0), default (-1)
   int nblk[BK_N] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_steps = -1;
   int graph_nblk[BK_N] = {};   // compared only once a graph exists
   int graph_chunk[4] = {-1, -1, -1, -1};
+  int graph_passc = -2;
   std::vector<char> host_args;
   ~avs_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -798,9 +800,36 @@ avs_status batch_launch(avs_batch* b, int nsteps) {
     CKL();
     kb_target<D, T><<<b->nblk[BK_TARGET], BLOCK, (size_t)D * numax * sizeof(T), b->stream>>>(a, off + BK_TARGET * (n + 1), n);
     CKL();
-    kb_passC<D, T><<<b->nblk[BK_PASSC], BLOCK, (size_t)(MAXF + 1) * D * numax * sizeof(T), b->stream>>>(
-        a, off + BK_PASSC * (n + 1), n);
+    const size_t shc = (size_t)(MAXF + 1) * D * numax * sizeof(T);
+    const bool two = b->passc_two < 0 ? passc_two_leaves<D, T>() : b->passc_two == 1;
+    if (two)
+      kb_passC<D, T, true><<<b->nblk[BK_PASSC], BLOCK, shc, b->stream>>>(a, off + BK_PASSC * (n + 1), n);
+    else
+      kb_passC<D, T, false><<<b->nblk[BK_PASSC], BLOCK, shc, b->stream>>>(a, off + BK_PASSC * (n + 1), n);
     CKL();
+  }
+  return AVS_OK;
+}
+
+// One step of every case computed into the spare buffers without taking it
+// (the state W, phi^n stays where it is); the heat flux and moments that
+// pass C overwrites are saved in each case's implicit-predictor and remap
+// scratch and put back.  Used to time tile choices on the cases' own state.
+avs_status batch_dry_step(avs_batch* b) {
+  avs_ctx* ctx = nullptr;
+  const bool f64 = b->prec == AVS_FP64;
+  for (avs_ctx* c : b->cases) {
+    CK(hipMemcpyAsync(c->irhs, c->q, sizeof(double) * c->nc * c->D, hipMemcpyDeviceToDevice, b->stream));
+    CK(hipMemcpyAsync(c->momp, c->mom, sizeof(double) * c->nc * (c->D + 2), hipMemcpyDeviceToDevice, b->stream));
+  }
+  avs_status st = f64 ? batch_upload<double>(b) : batch_upload<float>(b);
+  if (st) return st;
+  st = b->D == 2 ? (f64 ? batch_launch<2, double>(b, 1) : batch_launch<2, float>(b, 1))
+                 : (f64 ? batch_launch<3, double>(b, 1) : batch_launch<3, float>(b, 1));
+  if (st) return st;
+  for (avs_ctx* c : b->cases) {
+    CK(hipMemcpyAsync(c->q, c->irhs, sizeof(double) * c->nc * c->D, hipMemcpyDeviceToDevice, b->stream));
+    CK(hipMemcpyAsync(c->mom, c->momp, sizeof(double) * c->nc * (c->D + 2), hipMemcpyDeviceToDevice, b->stream));
   }
   return AVS_OK;
 }
@@ -814,7 +843,7 @@ avs_status batch_run(avs_batch* b, int nsteps, bool graph) {
     st = b->D == 2 ? (f64 ? batch_launch<2, double>(b, nsteps) : batch_launch<2, float>(b, nsteps))
                    : (f64 ? batch_launch<3, double>(b, nsteps) : batch_launch<3, float>(b, nsteps));
   } else {
-    bool same = b->exec && b->graph_steps == nsteps;
+    bool same = b->exec && b->graph_steps == nsteps && b->graph_passc == b->passc_two;
     for (int q = 0; q < 4; ++q) same = same && b->graph_chunk[q] == b->chunk[q];
     for (int k = 0; k < BK_N; ++k) same = same && b->graph_nblk[k] == b->nblk[k];
     if (!same) {
@@ -830,6 +859,7 @@ avs_status batch_run(avs_batch* b, int nsteps, bool graph) {
       b->graph = gr;
       CK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
       b->graph_steps = nsteps;
+      b->graph_passc = b->passc_two;
       for (int q = 0; q < 4; ++q) b->graph_chunk[q] = b->chunk[q];
       for (int k = 0; k < BK_N; ++k) b->graph_nblk[k] = b->nblk[k];
     }
@@ -2169,19 +2199,27 @@ avs_status avs_batch_tune(avs_batch* b, int32_t* chunk_host) {
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  // one bucket at a time, the others at their current choice
+  // time of two dry steps (the cases' state is left as it was)
+  auto timed = [&](float& ms) -> avs_status {
+    if (avs_status st = batch_dry_step(b)) return st;     // warm the choice
+    CK(hipEventRecord(e0, b->stream));
+    for (int r = 0; r < 2; ++r)
+      if (avs_status st = batch_dry_step(b)) return st;
+    CK(hipEventRecord(e1, b->stream));
+    CK(hipEventSynchronize(e1));
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    return AVS_OK;
+  };
+  // knob 1: pass-A leaf chunk, one bucket at a time, the others at their
+  // current choice
   for (int q = 0; q < 4; ++q) {
     if (!present[q]) continue;
     float best = 1e30f;
     int arg = b->chunk[q];
     for (int c : cand) {
       b->chunk[q] = c;
-      CK(hipEventRecord(e0, b->stream));
-      if (avs_status st = batch_run(b, 2, false)) return st;
-      CK(hipEventRecord(e1, b->stream));
-      CK(hipEventSynchronize(e1));
       float ms = 0.f;
-      CK(hipEventElapsedTime(&ms, e0, e1));
+      if (avs_status st = timed(ms)) return st;
       if (ms < best) {
         best = ms;
         arg = c;
@@ -2189,10 +2227,28 @@ avs_status avs_batch_tune(avs_batch* b, int32_t* chunk_host) {
     }
     b->chunk[q] = arg;
   }
+  // knob 2: pass C with one or two leaves' loads in flight
+  {
+    float best = 1e30f;
+    int arg = b->passc_two;
+    for (int v : {0, 1}) {
+      b->passc_two = v;
+      float ms = 0.f;
+      if (avs_status st = timed(ms)) return st;
+      if (ms < best) {
+        best = ms;
+        arg = v;
+      }
+    }
+    b->passc_two = arg;
+  }
+  CK(hipStreamSynchronize(b->stream));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (chunk_host)
+  if (chunk_host) {
     for (int q = 0; q < 4; ++q) chunk_host[q] = b->chunk[q];
+    chunk_host[4] = b->passc_two;
+  }
   return AVS_OK;
 }
 

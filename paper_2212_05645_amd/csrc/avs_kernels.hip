@@ -1227,7 +1227,7 @@ struct LeafIn {
 // With RES set, the kernel stores the explicit increment of the implicit
 // micro system instead, (dt/tau~)(g~ - phi^n) - (dt/V) sum_f sigma A xi.n
 // phi_f (Eq. SGS_phi's right-hand side times dt/V), and skips the moments.
-template <int D, typename T, bool RES = false>
+template <int D, typename T, bool RES = false, bool TWO = passc_two_leaves<D, T>()>
 __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __restrict__ vin,
                                         const T* __restrict__ fv, T* __restrict__ vout,
                                         const double* __restrict__ fpar, const double* __restrict__ tpar,
@@ -1404,7 +1404,7 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
     for (int d = 0; d < D; ++d) acc[N + d] += e * cd[d];
   };
 
-  if constexpr (!passc_two_leaves<D, T>()) {
+  if constexpr (!TWO) {
     for (int k = threadIdx.x; k < L.n; k += BLOCK) {
       LeafIn<D, T> x;
       load(k, x);
@@ -1952,12 +1952,13 @@ __global__ __launch_bounds__(BLOCK) void kb_target(const CaseArgs<T>* __restrict
                  blockIdx.x - off[c], 0);
 }
 
-template <int D, typename T>
+// TWO: two leaves' loads in flight per thread (the batched tuner picks)
+template <int D, typename T, bool TWO = passc_two_leaves<D, T>()>
 __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passC(const CaseArgs<T>* __restrict__ args,
                                                                        const int* __restrict__ off, int ncase) {
   const int c = find_case(off, ncase, blockIdx.x);
   const CaseArgs<T>* a = args + c;
-  d_passC<D, T>(global_geo(a->g), global_leaves(a->L), a->vg, gptr(a->vin), gptr(a->fv), gptr(a->vout), gptr(a->fpar),
+  d_passC<D, T, false, TWO>(global_geo(a->g), global_leaves(a->L), a->vg, gptr(a->vin), gptr(a->fv), gptr(a->vout), gptr(a->fpar),
                 gptr(a->tpar), gptr(a->lam), gptr(a->mom), gptr(a->q), blockIdx.x - off[c]);
 }
 

@@ -691,6 +691,47 @@ def test_batch_matches_single_cases_bit_for_bit(avs, prec):
         batch.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_tuning_leaves_the_state_unchanged(avs, prec):
+    """avs_batch_tune times its candidates on steps it does not take: the
+    members' state (VDF, W, and the heat flux the next step's target uses)
+    is bit for bit what it was, and tuned batched steps agree with the same
+    cases advanced alone (to rounding: pass A's leaf chunk sets the order in
+    which a face's moments are summed)."""
+    import torch
+    stream = torch.cuda.Stream()
+    c = F.cavity(n=8, base=8, max_level=2)
+    specs = [(c['mesh'], c['vspace'], c['gas'], c['dt'], 1.0, c['prim0'], random_tree(c['vspace'], 91, 2))]
+    c = F.cylinder(nr=6, nth=24, Ma=2.0, box=8.0, base=16, max_level=2, r1=2.5, first=0.1)
+    specs.append((c['mesh'], c['vspace'], c['gas'], c['dt'], 0.0, c['prim0'], resolved_tree(c['vspace'], 92)))
+    with torch.cuda.stream(stream):
+        solo, grouped = [], []
+        for dst in (solo, grouped):
+            for mesh, vs, gas, dt, K, prim, tree in specs:
+                cs = avs.Case(mesh, vs, gas, dt, K, prim, precision=prec, stream=stream)
+                cs.set_leaves(tree.level, tree.idx)
+                cs.step(1)
+                dst.append(cs)
+        batch = avs.Batch(grouped)
+        choice = batch.tune()
+        assert len(choice) == 5 and choice[4] in (1, 2)
+        for a, b in zip(solo, grouped):
+            va, Wa = a.get_state()
+            vb, Wb = b.get_state()
+            assert np.array_equal(va, vb) and np.array_equal(Wa, Wb)
+        batch.step(3, graph=True)
+        for cs in solo:
+            cs.step(3)
+        for a, b in zip(solo, grouped):
+            va, Wa = a.get_state()
+            vb, Wb = b.get_state()
+            if prec == 0:
+                assert rel(vb, va) < 1e-12 and rel(Wb, Wa) < 1e-12
+            else:
+                assert rel(vb, va) < 1e-5 and rel(Wb, Wa) < 1e-6
+        batch.close()
+
+
 def _gap_thresholds(Mk, lo_q, hi_q, rgap):
     """C1, C2 halfway between neighbouring values of M_k with a relative
     gap above rgap, near the given quantiles (no leaf sits near either)."""
