@@ -443,7 +443,7 @@ def run_learned(args, w, C1):
     split = ds.events[int(0.9 * nev)][0] if nev > 1 else ds.n
     t0 = time.perf_counter()
     losses = learned.train(mlp, ds, epochs=args.train_epochs, batch=8192, lr=2e-3, seed=0,
-                           rows=np.arange(split), log_every=50)
+                           rows=np.arange(split), log_every=50, balance=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     cm = learned.confusion(mlp, ds, rows=np.arange(split, ds.n))

@@ -88,15 +88,38 @@ def collect(case, mlp, ds, C1, C2, events, sweeps_between, base, levels=(0, 1, 2
             case.step(sweeps_between)
 
 
-def train(mlp, ds, epochs=3, batch=8192, lr=2e-3, seed=0, rows=None, log_every=0):
+def balanced_epoch(flags, pool, g, torch):
+    """One epoch's row order in which every class (keep, split, merge) present
+    in ``pool`` is drawn as often as the largest one: the rows of the smaller
+    classes repeat (drawn with replacement from the seeded generator ``g``),
+    so that the mean cross-entropy weighs the three decisions alike."""
+    lab = flags[pool.long()]
+    parts = [pool[lab == c] for c in (0, 1, -1)]
+    parts = [p for p in parts if len(p) > 0]
+    n = max(len(p) for p in parts)
+    out = []
+    for p in parts:
+        if len(p) == n:
+            out.append(p)
+        else:
+            out.append(p[torch.randint(len(p), (n,), generator=g)])
+    cat = torch.cat(out)
+    return cat[torch.randperm(len(cat), generator=g)]
+
+
+def train(mlp, ds, epochs=3, batch=8192, lr=2e-3, seed=0, rows=None, log_every=0, balance=False):
     """Adam over shuffled minibatches of the dataset rows ``rows`` (all rows
-    by default).  Returns the losses sampled every ``log_every`` steps."""
+    by default); with ``balance`` each epoch draws the three decisions
+    equally often (balanced_epoch).  Returns the losses sampled every
+    ``log_every`` steps."""
     torch = ds.torch
     g = torch.Generator().manual_seed(seed)
     pool = torch.arange(ds.n, dtype=torch.int32) if rows is None else torch.as_tensor(rows, dtype=torch.int32)
+    flags = ds.flags[:ds.n].cpu() if balance else None
     losses, step = [], 0
     for _ in range(epochs):
-        perm = pool[torch.randperm(len(pool), generator=g)].to(ds.feat.device)
+        order = balanced_epoch(flags, pool, g, torch) if balance else pool[torch.randperm(len(pool), generator=g)]
+        perm = order.to(ds.feat.device)
         for s in range(0, len(perm), batch):
             r = perm[s:s + batch]
             want = log_every and step % log_every == 0
