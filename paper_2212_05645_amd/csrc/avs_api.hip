@@ -653,6 +653,29 @@ avs_status launch_remap(avs_ctx* ctx, int correction) {
   return AVS_OK;
 }
 
+// Dynamic LDS of the sweep and remap kernels beyond the default 64 KiB (up
+// to kLdsMax per workgroup on gfx950): the per-axis Maxwellian tables grow
+// with the finest velocity grid.  Set once per kernel instantiation.
+constexpr size_t kLdsMax = 160 * 1024 - 16 * 1024;   // room for the kernels' static LDS
+
+template <int D, typename T>
+hipError_t raise_lds() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  const int b = (int)kLdsMax;
+  const void* fns[] = {(const void*)k_passC<D, T>,        (const void*)k_passC_res<D, T>,
+                       (const void*)kb_passC<D, T, true>, (const void*)kb_passC<D, T, false>,
+                       (const void*)k_face_eq<D, T>,      (const void*)kb_face_eq<D, T>,
+                       (const void*)k_target<D, T>,       (const void*)kb_target<D, T>,
+                       (const void*)k_remap_correct<D, T>, (const void*)k_init_vdf<D, T>};
+  for (const void* fn : fns) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+  }
+  done = true;
+  return hipSuccess;
+}
+
 // Dispatch on (dimension, storage type).
 #define DISPATCH(ctx, FN, ...)                                                       \
   ((ctx)->D == 2 ? ((ctx)->prec == AVS_FP64 ? FN<2, double>(__VA_ARGS__) : FN<2, float>(__VA_ARGS__)) \
@@ -1197,10 +1220,20 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   Carver cv{(char*)workspace_dev};
   carve(x, cv);
   const int P = x.P;
-  // LDS budget of the sweep kernels
-  if ((size_t)(x.maxf + 1) * D * x.vg.numax * sizeof(double) + 8192 > 64 * 1024) {
+  // LDS budget of the sweep kernels (pass C holds MAXF + 1 tables of D rows)
+  const size_t lds_need = (size_t)(x.maxf + 1) * D * x.vg.numax * x.esize();
+  if (lds_need > kLdsMax) {
     delete ctx;
-    return fail(AVS_E_INVALID, "velocity grid too fine for the LDS tables (2 base 2^max_level = %d)", x.vg.numax);
+    return fail(AVS_E_INVALID, "velocity grid too fine for the LDS tables (2 base 2^max_level = %d needs %zu B > %zu B)",
+                x.vg.numax, lds_need, kLdsMax);
+  }
+  if (lds_need + 8192 > 64 * 1024) {
+    const hipError_t e = D == 2 ? (x.prec == AVS_FP64 ? raise_lds<2, double>() : raise_lds<2, float>())
+                                : (x.prec == AVS_FP64 ? raise_lds<3, double>() : raise_lds<3, float>());
+    if (e != hipSuccess) {
+      delete ctx;
+      return fail(AVS_E_HIP, "hipFuncSetAttribute (dynamic LDS %zu B): %s", kLdsMax, hipGetErrorString(e));
+    }
   }
   auto H2D = [&](void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, x.stream);

@@ -824,3 +824,31 @@ def test_batch_members_match_the_oracle(avs, prec):
             o.step(2)
         compare()
         batch.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fine_velocity_grids_beyond_64_kib_of_lds(avs, dim):
+    """Velocity grids whose per-axis Maxwellian tables need more than the
+    default 64 KiB of LDS per workgroup in pass C (2-D: 2 x 16 x 2^5 = 1024
+    half-finest points per axis, 80 KiB; 3-D: 2 x 8 x 2^5 = 512, 86 KiB) step
+    like the oracle (1e-12 per step); a grid beyond gfx950's 160 KiB is
+    refused at set-up."""
+    if dim == 2:
+        mesh = MM.box2d(3, 2, periodic=(True, True))
+        vs = dict(dim=2, lo=(-6.0, -6.0), hi=(6.0, 6.0), base=(16, 16), max_level=5)
+    else:
+        mesh = MM.box3d(2, 2, 2, periodic=(True, True, True))
+        vs = dict(dim=3, lo=(-5.0,) * 3, hi=(5.0,) * 3, base=(8, 8, 8), max_level=5)
+    gas = dict(R=1.0, Pr=2 / 3, omega=0.81, mu_ref=0.05, T_ref=1.0, model=1)
+    prim = F.perturbed_uniform(mesh['ncells'], dim, 17, amp=0.05, uamp=0.3)
+    tree = random_tree(vs, 18, 2, p=0.03)
+    cs, o = make_pair(avs, mesh, vs, gas, 2e-3, prim, tree=tree, noise=0.01, seed=19, cap=4096)
+    cs.step(2)
+    o.step(2)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    cs.close()
+    if dim == 2:
+        too_fine = dict(dim=2, lo=(-6.0, -6.0), hi=(6.0, 6.0), base=(32, 32), max_level=6)
+        with pytest.raises(avs.AvsError, match="too fine"):
+            avs.Case(mesh, too_fine, gas, 2e-3, 1.0, prim, leaf_capacity=4096)
