@@ -597,6 +597,36 @@ def raw_flags(Mk, tree, C1, C2):
     return raw
 
 
+def separated_floor(raw, tree, zone):
+    """The separated-zone level of Sec. 3.5 as a floor on the raw flags.
+    ``zone = (r_lo, r_hi, S)``: an element whose discrete velocity (its
+    centre) lies in the open annulus r_lo < |xi| < r_hi about the origin
+    keeps at least level S (relative to the roots).  A leaf in the annulus
+    below S is split (below the maximum level); a merge candidate whose
+    parent would sit in the annulus below S is kept.  Radii are compared
+    squared, |xi|^2 summed axis by axis."""
+    r_lo, r_hi, S = zone
+    lo2, hi2 = r_lo * r_lo, r_hi * r_hi
+    out = raw.copy()
+    xi = tree.centres()
+    for k in range(tree.n):
+        l = int(tree.level[k])
+        s = 0.0
+        for d in range(tree.dim):
+            s = s + xi[k, d] * xi[k, d]
+        if lo2 < s < hi2 and l < S and l < tree.max_level:
+            out[k] = 1
+        if out[k] == -1 and l - 1 < S:
+            s = 0.0
+            for d in range(tree.dim):
+                h = (tree.hi[d] - tree.lo[d]) / float(int(tree.base[d]) << (l - 1))
+                c = tree.lo[d] + (float(int(tree.idx[k, d]) >> 1) + 0.5) * h
+                s = s + c * c
+            if lo2 < s < hi2:
+                out[k] = 0
+    return out
+
+
 def resolve_merges(raw, tree):
     """A brother group merges only if all 2^D brothers are leaves and all are
     merge candidates (Sec. 3.1); other candidates are kept."""
@@ -724,6 +754,7 @@ class Solver:
         self.W = conserved(prim0, self.gas.R)
         self.phi = self.initial_vdf(self.W)
         self.plan = None
+        self.separated = None    # (r_lo, r_hi, level) floor of every adaptation, or None
 
     @property
     def dim(self):
@@ -777,6 +808,8 @@ class Solver:
     def adapt(self, C1, C2, probes=None):
         Mk = criterion(self.phi, self.W, self.tree, self.gas.R, probes)
         raw = raw_flags(Mk, self.tree, C1, C2)
+        if self.separated is not None:
+            raw = separated_floor(raw, self.tree, self.separated)
         eff = resolve_merges(raw, self.tree)
         self.plan = make_plan(eff, self.tree)
         return eff, self.plan, Mk

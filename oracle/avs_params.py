@@ -25,7 +25,10 @@ wall temperature and the gas (R, gamma):
   the other way up);
 * the step-0 velocity space: one element of half-width R_dv split L_w - 1
   times, then one adaptation whose criterion runs over the freestream and
-  the static state (rho_inf, 0, T_inf) only.
+  the static state (rho_inf, 0, T_inf) only;
+* for a flow that separates, the separated zone: elements whose discrete
+  velocity lies in 3 sigma_w < |xi| < 5 sigma_w keep at least L_sep
+  (a floor on the flags of every adaptation, ``avs_oracle.separated_floor``).
 
 Mapping onto the forest of the solver (Sec. 3.1 reading: level-0 roots that
 never merge): the paper's single root with levels L_min..L_max is a forest
@@ -36,8 +39,9 @@ count below L_min gives the roots themselves.
 Pinned by the values the paper prints (tests/golden): the L_max column of
 the cylinder table, the h_inf column of the sphere table, the C1 values the
 runs quote from Eq. C1_Ma, the normal-density constants and the sphere's
-total temperatures.  Parity unpinned: the separated-zone level (the paper
-gives no value to check it against) and the element counts of the step-0
+total temperatures.  The separated-zone floor is pinned by hand-counted
+trees (which centre decides, split below the level, merge kept) and by the
+invariant it guarantees.  Parity unpinned: the element counts of the step-0
 space (they depend on the normalisation of the criterion against C1).
 """
 from __future__ import annotations
@@ -64,6 +68,7 @@ class Flow:
     direction: tuple = (1.0, 0.0, 0.0)   # unit vector of the freestream velocity
     rdv_sigmas: float = 4.0              # R_dv in units of sigma_0
     h_std: float = H_STD
+    separated: bool = False              # the flow separates: refine the separated zone
 
 
 def total_temperature(T_inf, gamma, Ma):
@@ -147,6 +152,14 @@ def vspace_of(p, dim):
     return dict(dim=dim, lo=lo, hi=hi, base=(1 << lr,) * dim, max_level=p['L_max'] - lr)
 
 
+def separated_zone(p):
+    """The separated zone of Sec. 3.5 on the solver's forest: the annulus
+    3 sigma_w < |xi| < 5 sigma_w about the origin (the wall is at rest) and
+    its level L_sep relative to the roots at min(L_min, L_max)."""
+    lr = min(p['L_min'], p['L_max'])
+    return (3.0 * p['sigma_w'], 5.0 * p['sigma_w'], p['L_sep'] - lr)
+
+
 def uniform_tree(vs, level):
     """Every cell of the forest at ``level`` (relative to the roots), in
     depth-first order."""
@@ -172,7 +185,8 @@ def probe_states(flow: Flow, p):
 def initial_tree(flow: Flow, p=None, C1=None, C2=None):
     """The step-0 velocity space of Sec. 3.5: one element of half-width R_dv
     centred at 0.4 U_inf, split L_w - 1 times, then one adaptation over the
-    two probe states only (no cell contributes).  C1 and C2 default to the
+    two probe states only (no cell contributes; for a separating flow the
+    separated zone's level is a floor on its flags).  C1 and C2 default to the
     fit of Eq. C1_Ma and k_sigma C1; with the criterion as printed (M_k at
     most the mass fraction of one element) that C1 never splits, so callers
     pass the threshold their normalisation needs.
@@ -188,5 +202,7 @@ def initial_tree(flow: Flow, p=None, C1=None, C2=None):
     no_cells = np.zeros((P, 0, t0.n))
     Mk = O.criterion(no_cells, np.zeros((0, flow.dim + 2)), t0, flow.R, probes=probe_states(flow, p))
     raw = O.raw_flags(Mk, t0, C1, C2)
+    if flow.separated:
+        raw = O.separated_floor(raw, t0, separated_zone(p))
     eff = O.resolve_merges(raw, t0)
     return t0, eff, O.make_plan(eff, t0).tree

@@ -523,6 +523,8 @@ def remap_dia(phi, plan, W, R):
 def _adapt(self, C1, C2, probes=None):
     Mk = criterion_dia(self.phi, self.W, self.tree, probes, self.gas.R)
     raw = _O.raw_flags(Mk, self.tree, C1, C2)
+    if getattr(self, 'separated', None) is not None:
+        raw = _O.separated_floor(raw, self.tree, self.separated)
     eff = _O.resolve_merges(raw, self.tree)
     self.plan = _O.make_plan(eff, self.tree)
     return eff, self.plan, Mk

@@ -133,3 +133,87 @@ def test_initial_tree_structure(dim, Ma):
     near = np.minimum(np.linalg.norm(xi - p['U_inf'] * e, axis=1), np.linalg.norm(xi, axis=1))
     s = p['sigma_inf']
     assert np.all(near[eff == 1] < 4 * s) and np.all(near[eff == -1] > 2 * s)
+
+
+def _tree(lo, hi, level, idx, max_level=3):
+    from oracle import avs_oracle as O
+    return O.Tree(2, np.asarray(lo, np.float64), np.asarray(hi, np.float64), np.array([1, 1], np.int64), max_level,
+                  np.full(len(idx), level, np.int64), np.asarray(idx, np.int64)).sorted()
+
+
+QUAD = [(0, 0), (1, 0), (0, 1), (1, 1)]
+
+
+def test_separated_floor_hand_counts():
+    """The separated-zone floor (Sec. 3.5) on one root split once, counted by
+    hand.  On [-1, 1]^2 the four leaf centres sit at |xi|^2 = 1/2 and the
+    parent's at the origin; on [-0.9, 1.1]^2 the parent's centre is
+    (0.1, 0.1), |xi|^2 = 0.02, and the leaves' are at least 0.52."""
+    from oracle import avs_oracle as O
+    t = _tree((-1.0, -1.0), (1.0, 1.0), 1, QUAD)
+    merge, keep = -np.ones(4, np.int8), np.zeros(4, np.int8)
+    # leaves in the annulus at the zone's level, parent outside: the merge stands
+    out = O.separated_floor(merge, t, (0.6, 0.8, 1))
+    assert np.array_equal(out, merge)
+    assert O.make_plan(O.resolve_merges(out, t), t).tree.n == 1
+    # leaves in the annulus below the zone's level: all four split (16 leaves)
+    out = O.separated_floor(keep, t, (0.6, 0.8, 2))
+    assert np.array_equal(out, np.ones(4, np.int8))
+    assert O.make_plan(O.resolve_merges(out, t), t).tree.n == 16
+    # ... but not beyond the maximum level, and not outside the annulus
+    assert np.array_equal(O.separated_floor(keep, _tree((-1.0, -1.0), (1.0, 1.0), 1, QUAD, max_level=1),
+                                            (0.6, 0.8, 2)), keep)
+    assert np.array_equal(O.separated_floor(keep, t, (0.8, 0.9, 2)), keep)
+    # |xi| = 0.70710678... against an outer radius just below and just above it
+    assert np.array_equal(O.separated_floor(keep, t, (0.6, 0.7071067, 2)), keep)
+    assert np.array_equal(O.separated_floor(keep, t, (0.6, 0.7071068, 2)), np.ones(4, np.int8))
+    assert np.array_equal(O.separated_floor(keep, t, (0.7071068, 0.8, 2)), keep)
+    # the parent's centre decides a merge: in the annulus below the level, kept
+    s = _tree((-0.9, -0.9), (1.1, 1.1), 1, QUAD)
+    out = O.separated_floor(merge, s, (0.1, 0.2, 1))
+    assert np.array_equal(out, keep)
+    assert O.make_plan(O.resolve_merges(out, s), s).tree.n == 4
+    # at the parent's own level the zone does not hold the merge back
+    assert np.array_equal(O.separated_floor(merge, s, (0.1, 0.2, 0)), merge)
+
+
+@pytest.mark.parametrize("dim,Ma,Tw", [(2, 6.0, 3.0), (2, 8.1, 3.0), (3, 4.25, 3.0), (3, 8.0, 315.0 / 43.22)])
+def test_initial_tree_separated_zone(dim, Ma, Tw):
+    """Step-0 space of a separating flow with a warm wall: every element
+    whose centre lies in 3 sigma_w < |xi| < 5 sigma_w holds at least L_sep,
+    and the space differs from the plain one only there: each plain-only
+    leaf is centred in the annulus below L_sep, and each leaf that only the
+    separating flow has is a child of one.  Centres are taken from the
+    finest grid here, not from the oracle's formula."""
+    gamma = 5.0 / 3.0 if dim == 2 else 1.4
+    kw = dict(dim=dim, R=R_PAPER, gamma=gamma, Ma=Ma, T_inf=1.0, T_wall=Tw)
+    p = AP.auto_params(AP.Flow(**kw))
+    _, _, plain = AP.initial_tree(AP.Flow(**kw), p, C1=1e-3)
+    _, _, sep = AP.initial_tree(AP.Flow(**kw, separated=True), p, C1=1e-3)
+    r_lo, r_hi, S = AP.separated_zone(p)
+    assert math.isclose(r_lo, 3.0 * math.sqrt(R_PAPER * Tw)) and math.isclose(r_hi, 5.0 * math.sqrt(R_PAPER * Tw))
+    assert S == max(p['L_min'], p['L_w'] - 1) - min(p['L_min'], p['L_max'])
+    vs = AP.vspace_of(p, dim)
+    lo, hi = np.asarray(vs['lo'], np.float64), np.asarray(vs['hi'], np.float64)
+    fine = np.asarray(vs['base'], np.int64) << (vs['max_level'] + 1)
+
+    def centre(level, idx):
+        u = (2 * np.asarray(idx, np.int64) + 1) << (vs['max_level'] - level)
+        return lo + u * (hi - lo) / fine
+
+    def in_zone(level, idx):
+        r = np.linalg.norm(centre(level, idx))
+        return r_lo < r < r_hi
+
+    for l, ix in zip(sep.level, sep.idx):
+        if in_zone(int(l), ix):
+            assert l >= min(S, vs['max_level'])
+    a = {(int(l),) + tuple(int(v) for v in ix) for l, ix in zip(plain.level, plain.idx)}
+    b = {(int(l),) + tuple(int(v) for v in ix) for l, ix in zip(sep.level, sep.idx)}
+    assert a != b
+    for key in a - b:
+        assert key[0] < S and in_zone(key[0], key[1:])
+    for key in b - a:
+        assert (key[0] - 1,) + tuple(v >> 1 for v in key[1:]) in a - b
+    cover = np.sum(2.0 ** (-dim * sep.level.astype(np.float64)))
+    assert abs(cover - np.prod(vs['base'])) < 1e-9
