@@ -129,7 +129,10 @@ size_t avs_workspace_bytes(const avs_vspace *vs, const avs_pmesh *pm, const avs_
 /* Create a context on the level-0 forest and set phi = closure(g_eq(W0), W0)
  * per cell (conservative discrete Maxwellian of the initial state), with W0
  * built from prim0_host [ncells][dim+2].  Copies every host array; waits for
- * the device before returning. */
+ * the device before returning.  The descriptors, the mesh (face ranges, at
+ * most 4 / 6 faces per cell, areas, volumes) and the initial states are
+ * checked on the host, and the per-cell tables built there, before any HIP
+ * call: those errors are AVS_E_INVALID with no device work done. */
 avs_status avs_init_mesh(const avs_vspace *vs, const avs_pmesh *pm, const avs_gas *gas, const avs_opts *op,
                          const double *prim0_host, void *vdf_dev, size_t vdf_bytes, void *workspace_dev,
                          size_t workspace_bytes, void *hip_stream, avs_ctx **out);
@@ -462,6 +465,7 @@ typedef struct {
   double direction[3];    /* freestream direction, normalised here; non-zero when Ma > 0 */
   double rdv_sigmas;      /* R_dv in units of sigma_0 (> 0; the paper uses 4, up to 7 for hot walls) */
   double h_std;           /* standard velocity interval (> 0; the paper uses 0.6) */
+  int32_t separated;      /* non-zero: the flow separates, and avs_initial_avs refines the separated zone */
 } avs_flow;
 
 typedef struct {
@@ -495,6 +499,21 @@ avs_status avs_auto_params(const avs_flow *flow, avs_auto *params_out, avs_vspac
  * closure(g_eq(W), W) on the new leaves for the current W.  Writes the leaf
  * count to *n_leaves_host (may be NULL).  Waits for the device. */
 avs_status avs_initial_avs(avs_ctx *ctx, const avs_flow *flow, double C1, double C2, int64_t *n_leaves_host);
+/* With flow->separated non-zero, avs_initial_avs first installs the
+ * separated zone of Sec. 3.5, avs_set_separated(ctx, 3 sigma_w, 5 sigma_w,
+ * L_sep - min(L_min, L_max)), which then holds for its adaptation and every
+ * later one on the context; with it zero, it clears any zone. */
+
+/* Separated zone (Sec. 3.5): a floor on the flags of every later adaptation
+ * of the context (avs_adapt, avs_adapt_learned, the batched and diatomic
+ * adaptations).  An element whose discrete velocity (its centre) lies in
+ * the open annulus r_lo < |xi| < r_hi about the origin keeps at least
+ * `level`, counted from the forest's roots: such a leaf below it is flagged
+ * to split (below max_level), and a merge whose parent would be centred
+ * there below it does not happen.  Radii are compared squared, |xi|^2
+ * summed axis by axis in FP64.  level < 0 removes the zone.  Host only;
+ * AVS_E_INVALID unless 0 <= r_lo < r_hi < inf. */
+avs_status avs_set_separated(avs_ctx *ctx, double r_lo, double r_hi, int32_t level);
 
 /* Release the context (never frees caller memory). */
 void avs_destroy(avs_ctx *ctx);

@@ -27,7 +27,7 @@ EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_in
            "avs_batch_check", "avs_batch_tune", "avs_batch_adapt", "avs_batch_remap", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
            "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
            "avs_mlp_adam", "avs_mlp_train_step", "avs_mlp_destroy", "avs_features", "avs_adapt_learned",
-           "avs_auto_params", "avs_initial_avs", "avs_implicit_bytes", "avs_step_implicit",
+           "avs_auto_params", "avs_initial_avs", "avs_set_separated", "avs_implicit_bytes", "avs_step_implicit",
            "avs_rykov_equilibrium", "avs_dia_bytes", "avs_dia_create", "avs_dia_step", "avs_dia_step_implicit", "avs_dia_get_state",
            "avs_dia_adapt", "avs_dia_remap", "avs_dia_destroy", "avs_destroy", "avs_last_error")
 
@@ -64,7 +64,8 @@ class avs_adam(C.Structure):
 class avs_flow(C.Structure):
     _fields_ = [("dim", C.c_int32), ("R", C.c_double), ("gamma", C.c_double), ("Ma", C.c_double),
                 ("T_inf", C.c_double), ("T_wall", C.c_double), ("rho_inf", C.c_double),
-                ("direction", C.c_double * 3), ("rdv_sigmas", C.c_double), ("h_std", C.c_double)]
+                ("direction", C.c_double * 3), ("rdv_sigmas", C.c_double), ("h_std", C.c_double),
+                ("separated", C.c_int32)]
 
 
 class avs_auto(C.Structure):
@@ -125,6 +126,7 @@ def _load():
         "avs_adapt_learned": (I32, [VP, VP, D, D, VP, I32, D, VP, P(I64), P(I32)]),
         "avs_auto_params": (I32, [P(avs_flow), P(avs_auto), P(avs_vspace)]),
         "avs_initial_avs": (I32, [VP, P(avs_flow), D, D, P(I64)]),
+        "avs_set_separated": (I32, [VP, D, D, I32]),
         "avs_implicit_bytes": (I32, [VP, P(C.c_size_t)]),
         "avs_rykov_equilibrium": (I32, [VP, P(avs_rykov), VP, I64, VP, C.c_size_t]),
         "avs_dia_bytes": (I32, [VP, I64, P(C.c_size_t)]),
@@ -168,10 +170,11 @@ def mu_ref_from_kn(Kn, omega, R, T_ref=1.0, rho_ref=1.0, L_ref=1.0):
     return lib.avs_mu_ref_from_kn(Kn, omega, R, T_ref, rho_ref, L_ref)
 
 
-def _flow(dim, R, gamma, Ma, T_inf, T_wall, rho_inf=1.0, direction=(1.0, 0.0, 0.0), rdv_sigmas=4.0, h_std=0.6):
+def _flow(dim, R, gamma, Ma, T_inf, T_wall, rho_inf=1.0, direction=(1.0, 0.0, 0.0), rdv_sigmas=4.0, h_std=0.6,
+          separated=False):
     d = tuple(float(x) for x in direction) + (0.0,) * (3 - len(direction))
     return avs_flow(int(dim), float(R), float(gamma), float(Ma), float(T_inf), float(T_wall), float(rho_inf),
-                    (C.c_double * 3)(*d[:3]), float(rdv_sigmas), float(h_std))
+                    (C.c_double * 3)(*d[:3]), float(rdv_sigmas), float(h_std), int(bool(separated)))
 
 
 def auto_params(**flow):
@@ -382,10 +385,17 @@ class Case:
     def initial_avs(self, C1, C2, **flow):
         """Step-0 velocity space for the freestream ``flow`` (keywords of
         avs_flow; the case must use the velocity space auto_params gives for
-        it); returns the leaf count."""
+        it; ``separated=True`` for a flow that separates); returns the leaf
+        count."""
         n = C.c_int64()
         _check(lib.avs_initial_avs(self.ctx, C.byref(_flow(**flow)), float(C1), float(C2), C.byref(n)))
         return n.value
+
+    def set_separated(self, r_lo, r_hi, level):
+        """Separated-zone floor on every later adaptation: elements centred in
+        r_lo < |xi| < r_hi keep at least ``level`` (from the roots); a level
+        below 0 removes it."""
+        _check(lib.avs_set_separated(self.ctx, float(r_lo), float(r_hi), int(level)))
 
     def set_leaves(self, level, idx):
         lev = np.ascontiguousarray(level, np.int32)

@@ -104,6 +104,10 @@ struct avs_ctx {
   // monatomic adaptation made it); a diatomic remap needs its own plan,
   // whose leaf count its rows were checked against
   const void* plan_owner = nullptr;
+  // separated zone (Sec. 3.5): a floor on the flags of every adaptation;
+  // sep_level < 0 when unset
+  double sep_lo = 0.0, sep_hi = 0.0;
+  int sep_level = -1;
 
   // optional per-kernel timing with HIP events (measurement only)
   bool prof = false;
@@ -587,6 +591,17 @@ avs_status launch_leaf_geom(avs_ctx* ctx, int t) {
   return AVS_OK;
 }
 
+// The separated-zone floor on the raw flags, when the context has a zone.
+template <int D>
+avs_status launch_sep_floor(avs_ctx* ctx, const Leaves& L) {
+  if (ctx->sep_level < 0 || L.n == 0) return AVS_OK;
+  k_sep_floor<D><<<(L.n + BLOCK - 1) / BLOCK, BLOCK, 0, ctx->stream>>>(
+      L, ctx->lmax, ctx->base[0], ctx->base[1], ctx->base[2], ctx->lo[0], ctx->lo[1], ctx->lo[2], ctx->hi[0],
+      ctx->hi[1], ctx->hi[2], ctx->sep_lo * ctx->sep_lo, ctx->sep_hi * ctx->sep_hi, ctx->sep_level, ctx->raw);
+  CKL();
+  return AVS_OK;
+}
+
 // Criterion, raw and effective flags, and their scan.  cells == false: the
 // criterion runs over the probe states only (step-0 velocity space).
 template <int D, typename T>
@@ -604,6 +619,7 @@ avs_status launch_adapt(avs_ctx* ctx, double C1, double C2, int nprobe, bool cel
   k_crit_reduce<D><<<nb, BLOCK, 0, ctx->stream>>>(L, cells ? ctx->ngrp : 0, ctx->crit_part, nprobe, ctx->probe_cc,
                                                  ctx->probe_prim, ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
   CKL();
+  if (avs_status st = launch_sep_floor<D>(ctx, L)) return st;
   k_resolve<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
   CKL();
   k_scan<<<1, BLOCK, 0, ctx->stream>>>(L.n, ctx->cnt, ctx->off);
@@ -1032,11 +1048,6 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   if (workspace_bytes < avs_workspace_bytes(vs, pm, op))
     return fail(AVS_E_INVALID, "workspace too small (%zu < %zu)", workspace_bytes, avs_workspace_bytes(vs, pm, op));
   if (((uintptr_t)vdf_dev & 255) || ((uintptr_t)workspace_dev & 255)) return fail(AVS_E_INVALID, "device regions must be 256-byte aligned");
-  int device = 0;
-  if (hipGetDevice(&device) != hipSuccess) return fail(AVS_E_HIP, "hipGetDevice failed");
-  // the no-allocation entry point's array on this device: a failure here only
-  // disables that entry point (it reports it), the context is unaffected
-  (void)resolve_scratch(device);
   const int D = vs->dim, N = D + 2;
   const int64_t nc = pm->ncells, nf = pm->nfaces;
   if (!pm->cell_vol || !pm->cell_ctr || (nf > 0 && (!pm->face_lr || !pm->face_area || !pm->face_nrm || !pm->face_ctr)))
@@ -1190,6 +1201,12 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
     if (!(pr[0] > 0 && pr[1 + D] > 0)) return fail(AVS_E_INVALID, "initial state of cell %" PRId64 " is not physical", i);
     conserved_host(D, gas->R, pr, &W0[i * N]);
   }
+  // ---- device: everything above is host work on the caller's arrays
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(AVS_E_HIP, "hipGetDevice failed");
+  // the no-allocation entry point's array on this device: a failure here only
+  // disables that entry point (it reports it), the context is unaffected
+  (void)resolve_scratch(device);
   // ---- context
   ctx = new avs_ctx();
   avs_ctx& x = *ctx;
@@ -1568,6 +1585,7 @@ avs_status dia_criterion(avs_dia* d, double C1, double C2, int nprobes) {
   k_crit_reduce<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->ngrp, ctx->crit_part, 0, ctx->probe_cc, ctx->probe_prim,
                                                  ctx->gas, C1, C2, ctx->lmax, ctx->Mk, ctx->raw);
   CKL();
+  if (avs_status st = launch_sep_floor<D>(ctx, L)) return st;
   k_resolve<D><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
   CKL();
   k_scan<<<1, BLOCK, 0, ctx->stream>>>(L.n, ctx->cnt, ctx->off);
@@ -2540,6 +2558,7 @@ avs_status avs_adapt_learned(avs_ctx* ctx, avs_mlp* mlp, double C1, double C2, c
         L.n, ctx->feat, nullptr, mlp->wbf, mlp->prm, nullptr, L.level, ctx->lmax, ctx->raw, nullptr, 0.f, nullptr,
         nullptr);
     CKL();
+    if (avs_status st = launch_sep_floor<2>(ctx, L)) return st;
     k_resolve<2><<<nb, BLOCK, 0, ctx->stream>>>(L, ctx->raw, ctx->eff, ctx->cnt);
     CKL();
     k_scan<<<1, BLOCK, 0, ctx->stream>>>(L.n, ctx->cnt, ctx->off);
@@ -2571,6 +2590,20 @@ avs_status avs_adapt_learned(avs_ctx* ctx, avs_mlp* mlp, double C1, double C2, c
   ctx->plan_valid = false;
   if (avs_status st = DISPATCH(ctx, launch_adapt, ctx, C1, C2, nprobes)) return st;
   return finish_plan(ctx, flags_dev, n_new_host);
+}
+
+avs_status avs_set_separated(avs_ctx* ctx, double r_lo, double r_hi, int32_t level) {
+  if (avs_status st = guard(ctx)) return st;
+  if (level < 0) {
+    ctx->sep_level = -1;
+    return AVS_OK;
+  }
+  if (!(r_lo >= 0.0) || !(r_hi > r_lo) || !std::isfinite(r_hi))
+    return fail(AVS_E_INVALID, "separated zone needs 0 <= r_lo < r_hi < inf");
+  ctx->sep_lo = r_lo;
+  ctx->sep_hi = r_hi;
+  ctx->sep_level = level;
+  return AVS_OK;
 }
 
 avs_status avs_auto_params(const avs_flow* flow, avs_auto* params_out, avs_vspace* vspace_out) {
@@ -2624,6 +2657,15 @@ avs_status avs_initial_avs(avs_ctx* ctx, const avs_flow* flow, double C1, double
   norm = std::sqrt(norm);
   for (int d = 0; d < D; ++d) probes[1 + d] = norm > 0.0 ? a.U_inf * (flow->direction[d] / norm) : 0.0;
   if (avs_status st = upload_probes(ctx, probes.data(), 2)) return st;
+  // the separated zone: 3 sigma_w < |xi| < 5 sigma_w at L_sep, for this and
+  // every later adaptation (the flow decides: cleared when it does not separate)
+  if (flow->separated) {
+    ctx->sep_lo = 3.0 * a.sigma_w;
+    ctx->sep_hi = 5.0 * a.sigma_w;
+    ctx->sep_level = a.L_sep - lr;
+  } else {
+    ctx->sep_level = -1;
+  }
   ctx->plan_valid = false;
   if (avs_status st = DISPATCH(ctx, launch_adapt, ctx, C1, C2, 2, false)) return st;
   int64_t n_new = 0;

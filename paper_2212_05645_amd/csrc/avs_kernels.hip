@@ -1583,6 +1583,42 @@ __global__ void k_crit_reduce(Leaves L, int ngrp, const double* __restrict__ par
   raw[k] = r;
 }
 
+// Separated-zone floor (Sec. 3.5) on the raw flags: an element centred in
+// the open annulus lo2 < |xi|^2 < hi2 about the origin keeps at least level
+// S.  A leaf there below S splits (below lmax); a merge candidate whose
+// parent would be centred there below S is kept.  |xi|^2 is summed axis by
+// axis, the parent's centre taken as the leaf geometry takes a centre.
+template <int D>
+__global__ void k_sep_floor(Leaves L, int lmax, int b0, int b1, int b2, double lo0, double lo1, double lo2,
+                            double hi0, double hi1, double hi2, double r2lo, double r2hi, int S,
+                            int8_t* __restrict__ raw) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= L.n) return;
+  const int base[3] = {b0, b1, b2};
+  const double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+  const int l = L.level[k];
+  int8_t r = raw[k];
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double x = L.xi[d * L.cap + k];
+    s = s + x * x;
+  }
+  if (r2lo < s && s < r2hi && l < S && l < lmax) r = 1;
+  if (r == -1 && l - 1 < S) {
+    s = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double h = (hi[d] - lo[d]) / (double)(base[d] << (l - 1));
+      const double c = lo[d] + ((double)(L.idx[d * L.cap + k] >> 1) + 0.5) * h;
+      s = s + c * c;
+    }
+    if (r2lo < s && s < r2hi) r = 0;
+  }
+  raw[k] = r;
+}
+
 // Effective flags (a brother group merges only if complete and unanimous)
 // and the number of new leaves each old leaf produces.
 template <int D>

@@ -94,3 +94,84 @@ def test_null_context_calls_fail_cleanly(avs):
     assert avs.lib.avs_step(None, 1, None) == avs.AVS_E_INVALID
     assert avs.lib.avs_remap(None, 2) == avs.AVS_E_INVALID
     avs.lib.avs_destroy(None)
+
+
+def _cpu_only():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-side checks of avs_init_mesh use host pointers: CPU only")
+
+
+def _init(avs, mesh, prim, dim=2):
+    """avs_init_mesh on host stand-ins for the device regions (never reached:
+    every call here stops in the host checks, or at the first HIP call on a
+    machine without a GPU)."""
+    vs, pm, op, keep, _ = descriptors(avs, dim=dim)
+    keep.append(mesh)
+
+    def p(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+    pm = avs.avs_pmesh(dim=dim, ncells=len(mesh["cell_vol"]), nfaces=len(mesh["face_area"]),
+                       cell_vol=p(mesh["cell_vol"], np.float64), cell_ctr=p(mesh["cell_ctr"], np.float64),
+                       face_lr=p(mesh["face_lr"], np.int64), face_area=p(mesh["face_area"], np.float64),
+                       face_nrm=p(mesh["face_nrm"], np.float64), face_ctr=p(mesh["face_ctr"], np.float64),
+                       face_shift=p(mesh["face_shift"], np.float64), nbc=0, bc_kind=None, bc_state=None)
+    nv = avs.lib.avs_vdf_bytes(C.byref(vs), C.byref(pm), C.byref(op))
+    nw = avs.lib.avs_workspace_bytes(C.byref(vs), C.byref(pm), C.byref(op))
+    assert nv > 0 and nw > 0
+    gas = avs.avs_gas(R=1.0, Pr=2 / 3, omega=0.5, mu_ref=0.05, T_ref=1.0, model=1)
+    out = C.c_void_p(123)
+    # 256-byte aligned addresses that are never dereferenced by the host checks
+    fake = 1 << 40
+    st = avs.lib.avs_init_mesh(C.byref(vs), C.byref(pm), C.byref(gas), C.byref(op),
+                               p(prim, np.float64), fake, nv, fake + ((nv + 255) // 256) * 256, nw, None,
+                               C.byref(out))
+    assert not out.value
+    return st, avs.lib.avs_last_error().decode()
+
+
+def test_mesh_is_checked_on_the_host_before_device_work(avs):
+    """Malformed meshes and states are refused by the host checks of
+    avs_init_mesh with a message that names the fault; a well-formed mesh
+    gets through them and stops at the first HIP call (no GPU here).  Run
+    under the sanitizers, this walks the slot tables, least-squares
+    coefficients, colouring and locality order of the host code."""
+    _cpu_only()
+    from workloads import meshes
+    good = {k: np.array(v, copy=True) for k, v in meshes.box2d(4, 3, periodic=(True, True)).items()
+            if isinstance(v, np.ndarray)}
+    prim = np.tile([1.0, 0.0, 0.0, 1.0], (len(good["cell_vol"]), 1))
+
+    def case(mutate, pr=prim):
+        m = {k: v.copy() for k, v in good.items()}
+        mutate(m)
+        return _init(avs, m, pr)
+    st, msg = case(lambda m: m["face_lr"].__setitem__((0, 0), 99))
+    assert st == avs.AVS_E_INVALID and "L out of range" in msg
+    st, msg = case(lambda m: m["face_lr"].__setitem__((1, 1), -5))
+    assert st == avs.AVS_E_INVALID and "R out of range" in msg
+    st, msg = case(lambda m: m["face_area"].__setitem__(2, -1.0))
+    assert st == avs.AVS_E_INVALID and "negative area" in msg
+    st, msg = case(lambda m: m["cell_vol"].__setitem__(3, 0.0))
+    assert st == avs.AVS_E_INVALID and "non-positive volume" in msg
+    # a fifth face on cell 0 (a duplicate of its first)
+    def extra_face(m):
+        for k in ("face_lr", "face_area", "face_nrm", "face_ctr", "face_shift"):
+            m[k] = np.concatenate([m[k], m[k][:1]])
+        f = int(np.nonzero((m["face_lr"] == 0).any(1))[0][0])
+        m["face_lr"][-1] = m["face_lr"][f]
+    st, msg = case(extra_face)
+    assert st == avs.AVS_E_INVALID and "more than 4 faces" in msg
+    bad = prim.copy()
+    bad[5, 3] = -1.0
+    st, msg = case(lambda m: None, bad)
+    assert st == avs.AVS_E_INVALID and "not physical" in msg
+    st, msg = case(lambda m: None)
+    assert st == avs.AVS_E_HIP and "hipGetDevice" in msg
+
+
+def test_separated_zone_arguments(avs):
+    assert avs.lib.avs_set_separated(None, 1.0, 2.0, 1) == avs.AVS_E_INVALID
+    assert "null context" in avs.lib.avs_last_error().decode()

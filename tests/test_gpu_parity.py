@@ -240,6 +240,56 @@ def test_initial_avs_matches_oracle(avs, dim, Ma):
     cs.close()
 
 
+@pytest.mark.parametrize("dim,Ma,Tw", [(2, 6.0, 3.0), (3, 4.25, 3.0)])
+def test_initial_avs_separated_matches_oracle(avs, dim, Ma, Tw):
+    """Separating flow with a warm wall: the step-0 velocity space with the
+    separated zone of Sec. 3.5 equals the oracle's leaf for leaf (and is not
+    the plain one); the zone stays on the context, so after two steps the
+    next adaptation's flags equal the oracle's under the same floor; a zone
+    with crossed radii is refused and a negative level removes it."""
+    from oracle import avs_params as AP
+    if dim == 2:
+        c = F.cylinder(nr=6, nth=16, Ma=Ma, box=13.0, base=16, max_level=2, r1=2.5, first=0.1)
+        gamma = 5.0 / 3.0
+    else:
+        c = F.sphere(nr=3, nth=4, nph=4, Ma=Ma, box=8.0, base=8, max_level=1, r1=1.5, first=0.2)
+        gamma = 1.4
+    flow = dict(dim=dim, R=c['gas']['R'], gamma=gamma, Ma=Ma, T_inf=1.0, T_wall=Tw)
+    params, vs = avs.auto_params(**flow)
+    C1 = 1e-3
+    C2 = params['k_sigma'] * C1
+    cs = avs.Case(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'], leaf_capacity=vs['leaf_capacity'])
+    n = cs.initial_avs(C1, C2, **flow, separated=True)
+    p = AP.auto_params(AP.Flow(**flow))
+    _, _, t1 = AP.initial_tree(AP.Flow(**flow, separated=True), p, C1=C1, C2=C2)
+    _, _, plain = AP.initial_tree(AP.Flow(**flow), p, C1=C1, C2=C2)
+    L = cs.leaves()
+    assert n == t1.n and np.array_equal(L['level'], t1.level) and np.array_equal(L['idx'], t1.idx)
+    assert t1.n != plain.n
+    o = O.Solver(c['mesh'], vs, c['gas'], c['dt'], c['venkat_K'], c['prim0'])
+    o.tree = t1
+    o.phi = o.initial_vdf(o.W)
+    o.separated = AP.separated_zone(p)
+    cs.step(2)
+    o.step(2)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    # thresholds under which the zone holds merges back after the steps
+    C1b, C2b = 1e-2, 3e-3
+    flags, nn = cs.adapt(C1b, C2b)
+    eff, plan, _ = o.adapt(C1b, C2b)
+    assert np.array_equal(flags, eff) and nn == plan.tree.n
+    o.separated = None
+    eff0, _, _ = o.adapt(C1b, C2b)
+    assert not np.array_equal(eff0, eff)
+    with pytest.raises(avs.AvsError):
+        cs.set_separated(2.0, 1.0, 1)
+    cs.set_separated(0.0, 1.0, -1)
+    flags0, _ = cs.adapt(C1b, C2b)
+    assert np.array_equal(flags0, eff0)
+    cs.close()
+
+
 # ------------------------------------------------ unstructured meshes ------
 def test_unstructured_triangles(avs):
     """Triangles of a jittered lattice with random diagonals (three faces
