@@ -152,6 +152,7 @@ def sweep_only(w, nsweep):
     e1.record(cs.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    cs.check()               # a non-physical state in the timed sweeps fails the run
     return w.nc * nv * nsweep / (ms * 1e-3), ms / nsweep, nv
 
 
@@ -403,6 +404,7 @@ def run_batched(args):
         e1.record(stream)
         torch.cuda.synchronize()
         sweep_ms = e0.elapsed_time(e1) / args.nu
+        batch.check()
         # the same cases one after another through the single-case entry point
         e0.record(stream)
         for cs in cases:
@@ -410,6 +412,8 @@ def run_batched(args):
         e1.record(stream)
         torch.cuda.synchronize()
         seq_ms = e0.elapsed_time(e1) / args.nu
+        for cs in cases:
+            cs.check()
         batch.close()
     return {"cycle_updates_per_s": updates / (ms * 1e-3), "sweep_updates_per_s": nodes / (sweep_ms * 1e-3),
             "sweep_ms": sweep_ms, "sequential_sweep_updates_per_s": nodes / (seq_ms * 1e-3),

@@ -127,8 +127,11 @@ size_t avs_vdf_bytes(const avs_vspace *vs, const avs_pmesh *pm, const avs_opts *
 size_t avs_workspace_bytes(const avs_vspace *vs, const avs_pmesh *pm, const avs_opts *op);
 
 /* Create a context on the level-0 forest and set phi = closure(g_eq(W0), W0)
- * per cell (conservative discrete Maxwellian of the initial state), with W0
- * built from prim0_host [ncells][dim+2].  Copies every host array; waits for
+ * per cell, with W0 built from prim0_host [ncells][dim+2]: the initial
+ * distribution is the Maxwellian of Eq. Maxwell_df (in 2-D the reduced pair
+ * G and H = (3 - D) R T G) of each cell's initial state, as Sec. 3.5
+ * starts the adaptive run, sampled at the leaf centres and corrected so that
+ * its discrete moments equal W0 (the conservation correction of Sec. 3.3).  Copies every host array; waits for
  * the device before returning.  The descriptors, the mesh (face ranges, at
  * most 4 / 6 faces per cell, areas, volumes) and the initial states are
  * checked on the host, and the per-cell tables built there, before any HIP
@@ -150,6 +153,14 @@ avs_status avs_init_mesh(const avs_vspace *vs, const avs_pmesh *pm, const avs_ga
  * non-NULL residual makes the call wait and report AVS_E_NUMERIC if any cell
  * went non-physical. */
 avs_status avs_step(avs_ctx *ctx, int32_t nsteps, double *residual_host);
+
+/* Wait for the context's stream and report what the kernels found since the
+ * context was made: AVS_E_NUMERIC (and the failed state) if some cell's
+ * state became non-physical or its moment system singular, or some
+ * interface state non-physical.  avs_step reports this only when it
+ * returns a residual; avs_remap always does.  Use it after steps timed
+ * without a residual. */
+avs_status avs_check(avs_ctx *ctx);
 
 /* Rykov model constants of a diatomic gas (Sec. 2.2; nitrogen: delta =
  * 1/1.55, omega_0 = 0.2354, omega_1 = 0.3049); Z_rot, the rotational

@@ -22,7 +22,7 @@ AVS_COPY, AVS_SPLIT, AVS_MERGE = 0, 1, 2
 
 EXPORTS = ("avs_mu_ref_from_kn", "avs_vdf_bytes", "avs_workspace_bytes", "avs_init_mesh", "avs_step",
            "avs_moments", "avs_moments_noalloc", "avs_adapt", "avs_remap", "avs_leaves", "avs_plan", "avs_criterion",
-           "avs_set_leaves", "avs_get_state", "avs_set_state", "avs_get_cells", "avs_profile",
+           "avs_check", "avs_set_leaves", "avs_get_state", "avs_set_state", "avs_get_cells", "avs_profile",
            "avs_profile_read", "avs_batch_workspace_bytes", "avs_batch_create", "avs_batch_step",
            "avs_batch_check", "avs_batch_tune", "avs_batch_adapt", "avs_batch_remap", "avs_batch_destroy", "avs_mlp_param_count", "avs_mlp_state_bytes",
            "avs_mlp_create", "avs_mlp_get_params", "avs_mlp_set_params", "avs_mlp_forward", "avs_mlp_grad",
@@ -91,6 +91,7 @@ def _load():
         "avs_init_mesh": (I32, [P(avs_vspace), P(avs_pmesh), P(avs_gas), P(avs_opts), VP, VP, C.c_size_t, VP,
                                 C.c_size_t, VP, P(VP)]),
         "avs_step": (I32, [VP, I32, VP]),
+        "avs_check": (I32, [VP]),
         "avs_moments": (I32, [VP, VP, VP]),
         "avs_moments_noalloc": (I32, [VP, VP, VP]),
         "avs_adapt": (I32, [VP, D, D, VP, I32, VP, P(I64)]),
@@ -293,6 +294,11 @@ class Case:
                                          out.numel() * out.element_size()))
         t.cuda.synchronize(self.device)
         return out
+
+    def check(self):
+        """Raise AvsError if a kernel found a non-physical state since the
+        context was made (waits for the stream)."""
+        _check(lib.avs_check(self.ctx))
 
     def moments(self, fields=True, totals=True):
         f = self._torch.empty((self.nc, 2 * self.dim + 2), dtype=self._torch.float64, device=self.device) if fields else None

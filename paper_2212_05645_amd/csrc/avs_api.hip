@@ -1345,6 +1345,11 @@ avs_status avs_step(avs_ctx* ctx, int32_t nsteps, double* residual_host) {
   return AVS_OK;
 }
 
+avs_status avs_check(avs_ctx* ctx) {
+  if (avs_status st = guard(ctx)) return st;
+  return check_bad(ctx);
+}
+
 avs_status avs_implicit_bytes(const avs_ctx* ctx, size_t* bytes) {
   if (!ctx || !bytes) return fail(AVS_E_INVALID, "null argument");
   *bytes = ctx->vdf_buf_bytes;
