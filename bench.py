@@ -50,6 +50,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--one-form", action="store_true", help="time only --precision (not also the other precision)")
     p.add_argument("--no-sweep", action="store_true", help="skip the extra sweep-only timing (profiling runs)")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched form (profiling runs)")
+    p.add_argument("--only", choices=["sphere", "learned", "batched"],
+                   help="run only this form and print its record (profiling runs; not the benchmark line)")
     p.add_argument("--copy-probe", type=float, default=0.0,
                    help="GiB copied device-to-device by torch before the run (calibrates HBM byte counters)")
     p.add_argument("--nr", type=int, default=128)
@@ -235,9 +238,11 @@ def passA_flops_per_node(D, P, slots, interior):
                                                          numerator, denominator, cross products
       per component            P * (5 + D)               scaling, one division, limited gradient
       upwind sign              slots * (2D - 1)          xi . n in FP64
-      reconstruction           slots / 2 * (2D + P * 2D) x_f - xi h - x_i, dot product, + phi"""
+      reconstruction           slots / 2 * (2D + P * 2D) x_f - xi h - x_i, dot product, + phi
+      face moments             slots / 2 * (D^2 + 7D + 5) |xi|^2, A G, A G xi, the (D+1)D/2 second
+                                                         moments, energy weight, energy flux terms"""
     return (interior * P * (1 + 2 * D) + slots * P * (2 * D - 1) + slots * P * 12 + P * (5 + D)
-            + slots * (2 * D - 1) + slots / 2 * (2 * D + P * 2 * D))
+            + slots * (2 * D - 1) + slots / 2 * (2 * D + P * 2 * D) + slots / 2 * (D * D + 7 * D + 5))
 
 
 def _cpu_model():
@@ -853,6 +858,16 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.only:
+        if args.only == "sphere":
+            rec = run_sphere(args)
+        elif args.only == "batched":
+            rec = run_batched(args)
+        else:
+            w, C1, _ = run_form(args, "fp64")
+            rec = run_learned(args, w, C1)
+        print(json.dumps({"form": args.only, **rec}, default=float), flush=True)
+        return
     copy_gbps = measured_copy_bandwidth(torch)
     w, C1, r = run_form(args, args.precision)
     roofline, kern = roofline_of(w, r, args.precision, copy_gbps)
@@ -884,6 +899,8 @@ def main():
         torch.cuda.empty_cache()
     # the batched form (64 seeded cases, FP32) in every run, a few cycles
     try:
+        if args.no_batched:
+            raise RuntimeError("skipped (--no-batched)")
         bargs = argparse.Namespace(**vars(args))
         if not args.forms:
             bargs.steps, bargs.warmup = min(args.steps, 3), 1

@@ -455,7 +455,8 @@ avs_status launch_interfaces(avs_ctx* ctx) {
   }
   {
     ProfScope ps(ctx, K_FACE_EQFLUX);
-    k_face_eq<D, T><<<ctx->nf, BLOCK, (size_t)D * nu * sizeof(T), ctx->stream>>>(
+    k_face_eq<D, T><<<(ctx->nf + face_batch<D>() - 1) / face_batch<D>(), BLOCK, (size_t)face_batch<D>() * D * nu * sizeof(T),
+                      ctx->stream>>>(
         ctx->geo, L, ctx->vg, ctx->gas, ctx->h, ctx->bden, ctx->bfin, ctx->fmom, ctx->nchs, nch, ctx->fpar, ctx->F,
         ctx->bad);
     CKL();
@@ -811,7 +812,9 @@ avs_status batch_upload(avs_batch* b) {
     args[n + i] = case_args<T>(c, 1, ch);
     const int nl = c->nleaf[c->lcur];
     const int gx = (int)round_up(c->nc, 8);
-    const int cnt[BK_N] = {gx * ((nl + ch - 1) / ch), c->nf, (c->nc + BLOCK - 1) / BLOCK, c->nc, gx};
+    const int fb = c->D == 2 ? face_batch<2>() : face_batch<3>();
+    const int cnt[BK_N] = {gx * ((nl + ch - 1) / ch), (c->nf + fb - 1) / fb, (c->nc + BLOCK - 1) / BLOCK,
+                           c->nc, gx};
     for (int k = 0; k < BK_N; ++k) off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + cnt[k];
   }
   for (int k = 0; k < BK_N; ++k) b->nblk[k] = off[k * (n + 1) + n];
@@ -833,7 +836,8 @@ avs_status batch_launch(avs_batch* b, int nsteps) {
     const CaseArgs<T>* a = args + (s & 1) * n;
     kb_passA<D, T><<<b->nblk[BK_PASSA], passA_threads<D>(), 0, b->stream>>>(a, off + BK_PASSA * (n + 1), n);
     CKL();
-    kb_face_eq<D, T><<<b->nblk[BK_FACEQ], BLOCK, (size_t)D * numax * sizeof(T), b->stream>>>(a, off + BK_FACEQ * (n + 1), n);
+    kb_face_eq<D, T><<<b->nblk[BK_FACEQ], BLOCK, (size_t)face_batch<D>() * D * numax * sizeof(T), b->stream>>>(
+        a, off + BK_FACEQ * (n + 1), n);
     CKL();
     kb_macro<D, T><<<b->nblk[BK_MACRO], BLOCK, 0, b->stream>>>(a, off + BK_MACRO * (n + 1), n);
     CKL();
@@ -1237,8 +1241,10 @@ avs_status avs_init_mesh(const avs_vspace* vs, const avs_pmesh* pm, const avs_ga
   Carver cv{(char*)workspace_dev};
   carve(x, cv);
   const int P = x.P;
-  // LDS budget of the sweep kernels (pass C holds MAXF + 1 tables of D rows)
-  const size_t lds_need = (size_t)(x.maxf + 1) * D * x.vg.numax * x.esize();
+  // LDS budget of the sweep kernels (pass C holds MAXF + 1 tables of D rows,
+  // the face equilibrium one per face of its batch)
+  const int ntab = std::max(x.maxf + 1, D == 2 ? face_batch<2>() : face_batch<3>());
+  const size_t lds_need = (size_t)ntab * D * x.vg.numax * x.esize();
   if (lds_need > kLdsMax) {
     delete ctx;
     return fail(AVS_E_INVALID, "velocity grid too fine for the LDS tables (2 base 2^max_level = %d needs %zu B > %zu B)",

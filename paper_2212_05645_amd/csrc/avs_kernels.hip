@@ -968,98 +968,131 @@ __device__ __forceinline__ void raw_flux(const double* m, const double* n, doubl
 // R from the record.  Boundary face: outgoing flux plus the incoming wall
 // (zero net mass flux, rho_w) or far-field Maxwellian flux.
 
+// Faces per face_eq workgroup: each leaf is loaded once for all of them and
+// their records are formed in parallel, one thread per face.
+#ifndef AVS_FACE_BATCH2
+#define AVS_FACE_BATCH2 2
+#endif
+#ifndef AVS_FACE_BATCH3
+#define AVS_FACE_BATCH3 4
+#endif
+template <int D>
+constexpr int face_batch() { return D == 2 ? AVS_FACE_BATCH2 : AVS_FACE_BATCH3; }
+
 template <int D, typename R>
 __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, double h, const double* __restrict__ bden,
                                           const double* __restrict__ bfin, const double* __restrict__ fmom, int nchs,
                                           int nch, double* __restrict__ fpar, double* __restrict__ F,
                                           int* __restrict__ bad, int bx) {
-  constexpr int NM = Cfg<D>::NM, N = D + 2;
+  constexpr int NM = Cfg<D>::NM, N = D + 2, FB = face_batch<D>();
   extern __shared__ double lds_d[];
-  R* tab = reinterpret_cast<R*>(lds_d);
-  __shared__ double red[4 * N];
-  __shared__ double spar[NPAR];
-  __shared__ R rp[NPAR];
-  __shared__ double sF[N];
-  __shared__ double sm[NM];
-  __shared__ int interior_ok;
-  const int f = bx;
-  const int Rc = g.f_R[f];
-  double n[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
-  // raw moments of the interface VDF: the partials of pass A, chunk by chunk,
+  R* tab = reinterpret_cast<R*>(lds_d);       // FB tables of D x numax
+  __shared__ double red[4 * FB * N];
+  __shared__ double spar[FB][NPAR];
+  __shared__ R rp[FB][NPAR];
+  __shared__ double sF[FB][N];
+  __shared__ double sm[FB][NM];
+  __shared__ double snrm[FB][D];
+  __shared__ int sok[FB];
+  const int f0 = bx * FB;
+  const int nfb = min(FB, g.nf - f0);
+  // raw moments of each interface VDF: the partials of pass A, chunk by chunk,
   // L side then R side (a boundary face has its interior side only)
-  if (threadIdx.x < NM) {
-    const double* p0 = fmom + (size_t)f * 2 * nchs * NM + threadIdx.x;
-    const double* p1 = p0 + (size_t)nchs * NM;
+  if (threadIdx.x < FB * NM) {
+    const int s = threadIdx.x / NM, t = threadIdx.x - s * NM;
     double v = 0.0;
-    for (int c = 0; c < nch; ++c) {
-      v += p0[(size_t)c * NM];
-      if (Rc >= 0) v += p1[(size_t)c * NM];
+    if (s < nfb) {
+      const int f = f0 + s;
+      const double* p0 = fmom + (size_t)f * 2 * nchs * NM + t;
+      const double* p1 = p0 + (size_t)nchs * NM;
+      const bool two = g.f_R[f] >= 0;
+      for (int c = 0; c < nch; ++c) {
+        v += p0[(size_t)c * NM];
+        if (two) v += p1[(size_t)c * NM];
+      }
     }
-    sm[threadIdx.x] = v;
+    sm[s][t] = v;
   }
   __syncthreads();
-  double m[NM];
-  if (threadIdx.x == 0)
-    for (int t = 0; t < NM; ++t) m[t] = sm[t];
-  if (threadIdx.x == 0) {
-    interior_ok = 0;
-    if (Rc >= 0) {
-      const double rho = m[0];
-      double U[D], ke = 0.0;
-      for (int d = 0; d < D; ++d) { U[d] = m[1 + d] / rho; ke += U[d] * U[d]; }
-      const int ie = 1 + D + D * (D + 1) / 2;
-      const double E = m[ie];
-      const double T = (E - 0.5 * rho * ke) / (1.5 * rho * gas.R);
-      if (!(rho > 0.0 && T > 0.0)) {
-        atomicMin(bad, g.nc + f);
-      } else {
-        // q about U from raw moments: e1_d - U_d E - sum_e U_e (m2_de - rho U_d U_e) + |U|^2/2 (m1_d - U_d rho)
-        int idx[3][3];
-        int t = 1 + D;
-        for (int d = 0; d < D; ++d)
-          for (int e = d; e < D; ++e) { idx[d][e] = t; idx[e][d] = t; ++t; }
-        double q[D];
-        for (int d = 0; d < D; ++d) {
-          double v = m[ie + 1 + d] - U[d] * E;
-          for (int e = 0; e < D; ++e) v -= U[e] * (m[idx[d][e]] - rho * U[d] * U[e]);
-          v += 0.5 * ke * (m[1 + d] - U[d] * rho);
-          q[d] = v;
+  // one thread per face: interface state, tau, relaxed heat flux, record and
+  // blend weights (interior), or the boundary flux
+  if (threadIdx.x < FB) {
+    const int s = threadIdx.x;
+    int ok = 0;
+    if (s < nfb) {
+      const int f = f0 + s;
+      const int Rc = g.f_R[f];
+      double n[D], m[NM];
+      for (int d = 0; d < D; ++d) {
+        n[d] = g.f_nrm[(size_t)f * D + d];
+        snrm[s][d] = n[d];
+      }
+      for (int t = 0; t < NM; ++t) m[t] = sm[s][t];
+      if (Rc >= 0) {
+        const double rho = m[0];
+        double U[D], ke = 0.0;
+        for (int d = 0; d < D; ++d) { U[d] = m[1 + d] / rho; ke += U[d] * U[d]; }
+        const int ie = 1 + D + D * (D + 1) / 2;
+        const double E = m[ie];
+        const double T = (E - 0.5 * rho * ke) / (1.5 * rho * gas.R);
+        if (!(rho > 0.0 && T > 0.0)) {
+          atomicMin(bad, g.nc + f);
+        } else {
+          // q about U from raw moments: e1_d - U_d E - sum_e U_e (m2_de - rho U_d U_e) + |U|^2/2 (m1_d - U_d rho)
+          int idx[3][3];
+          int t = 1 + D;
+          for (int d = 0; d < D; ++d)
+            for (int e = d; e < D; ++e) { idx[d][e] = t; idx[e][d] = t; ++t; }
+          double q[D];
+          for (int d = 0; d < D; ++d) {
+            double v = m[ie + 1 + d] - U[d] * E;
+            for (int e = 0; e < D; ++e) v -= U[e] * (m[idx[d][e]] - rho * U[d] * U[e]);
+            v += 0.5 * ke * (m[1 + d] - U[d] * rho);
+            q[d] = v;
+          }
+          const double tf = tau_of(rho, T, gas);
+          const double qs = tf / (tf + h * gas.Pr);
+          for (int d = 0; d < D; ++d) q[d] *= qs;
+          eq_record<D>(spar[s], rho, U, T, q, gas);
+          spar[s][P_A] = tf / (tf + h);
+          spar[s][P_B] = h / (tf + h);
+          raw_flux<D>(m, n, sF[s]);
+          ok = 1;
         }
-        const double tf = tau_of(rho, T, gas);
-        const double qs = tf / (tf + h * gas.Pr);
-        for (int d = 0; d < D; ++d) q[d] *= qs;
-        eq_record<D>(spar, rho, U, T, q, gas);
-        spar[P_A] = tf / (tf + h);
-        spar[P_B] = h / (tf + h);
-        raw_flux<D>(m, n, sF);
-        interior_ok = 1;
+      } else {
+        const int bc = -1 - Rc;
+        double Fo[N];
+        raw_flux<D>(m, n, Fo);
+        const double* fin = bfin + (size_t)f * N;
+        double scale = 1.0;
+        if (g.bc_kind[bc] == 0) {
+          scale = Fo[0] / bden[f];
+          fpar[(size_t)f * NPAR] = scale;
+        }
+        for (int t = 0; t < N; ++t) F[(size_t)f * N + t] = Fo[t] + scale * fin[t];
       }
-    } else {
-      const int bc = -1 - Rc;
-      double Fo[N];
-      raw_flux<D>(m, n, Fo);
-      const double* fin = bfin + (size_t)f * N;
-      double scale = 1.0;
-      if (g.bc_kind[bc] == 0) {
-        scale = Fo[0] / bden[f];
-        fpar[(size_t)f * NPAR] = scale;
-      }
-      for (int t = 0; t < N; ++t) F[(size_t)f * N + t] = Fo[t] + scale * fin[t];
+    }
+    sok[s] = ok;
+  }
+  __syncthreads();
+  int any = 0;
+#pragma unroll
+  for (int s = 0; s < FB; ++s) any |= sok[s];
+  if (!any) return;
+  for (int t = threadIdx.x; t < FB * NPAR; t += BLOCK) {
+    const int s = t / NPAR, m = t - s * NPAR;
+    if (sok[s]) {
+      fpar[(size_t)(f0 + s) * NPAR + m] = spar[s][m];
+      rp[s][m] = (R)spar[s][m];
     }
   }
-  __syncthreads();
-  if (!interior_ok) return;
-  if (threadIdx.x < NPAR) {
-    fpar[(size_t)f * NPAR + threadIdx.x] = spar[threadIdx.x];
-    rp[threadIdx.x] = (R)spar[threadIdx.x];
-  }
-  build_tab_r<D, R>(tab, spar, vg);
-  __syncthreads();
-  double acc[N];
 #pragma unroll
-  for (int t = 0; t < N; ++t) acc[t] = 0.0;
+  for (int s = 0; s < FB; ++s)
+    if (sok[s]) build_tab_r<D, R>(tab + s * D * vg.numax, spar[s], vg);
+  __syncthreads();
+  double acc[FB * N];
+#pragma unroll
+  for (int t = 0; t < FB * N; ++t) acc[t] = 0.0;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
     double xi[D], A;
     int u[D];
@@ -1067,19 +1100,28 @@ __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, d
     R xr[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) xr[d] = (R)xi[d];
-    const R gv = maxw_r<D, R>(rp, tab, vg.numax, u);
-    R G, H;
-    shakhov_r<D, R>(rp, gv, xr, G, H);
-    const double sn = normal_speed<D>(xi, n);
     double xi2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
-    mom_acc<D>(acc, A * sn, xi, xi2, (double)G, (double)H);
+#pragma unroll
+    for (int s = 0; s < FB; ++s) {
+      if (!sok[s]) continue;
+      const R gv = maxw_r<D, R>(rp[s], tab + s * D * vg.numax, vg.numax, u);
+      R G, H;
+      shakhov_r<D, R>(rp[s], gv, xr, G, H);
+      const double sn = normal_speed<D>(xi, snrm[s]);
+      mom_acc<D>(acc + s * N, A * sn, xi, xi2, (double)G, (double)H);
+    }
   }
-  block_sum<N>(acc, red);
-  if (threadIdx.x == 0) {
-    const double a = spar[P_A], b = spar[P_B];
-    for (int t = 0; t < N; ++t) F[(size_t)f * N + t] = a * sF[t] + b * acc[t];
+  block_sum<FB * N>(acc, red);
+  // static indices into acc (a dynamic one would move it to scratch memory)
+#pragma unroll
+  for (int s = 0; s < FB; ++s) {
+    if (threadIdx.x == s && sok[s]) {
+      const double a = spar[s][P_A], b = spar[s][P_B];
+#pragma unroll
+      for (int t = 0; t < N; ++t) F[(size_t)(f0 + s) * N + t] = a * sF[s][t] + b * acc[s * N + t];
+    }
   }
 }
 
