@@ -419,13 +419,32 @@ def run_batched(args):
         seq_ms = e0.elapsed_time(e1) / args.nu
         for cs in cases:
             cs.check()
+        # one more cycle with a wait after each phase: adaptation, remap, the
+        # first step after it (graph capture + run), a replayed step
+        torch.cuda.synchronize()
+        t = [time.perf_counter()]
+        batch.adapt(C1s, C2s)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        batch.remap(2)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        for _ in range(2):
+            batch.step(args.nu, graph=True)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter())
+        batch.check()
+        phases = {"adapt_ms": 1e3 * (t[1] - t[0]), "remap_ms": 1e3 * (t[2] - t[1]),
+                  "first_steps_ms": 1e3 * (t[3] - t[2]), "replayed_steps_ms": 1e3 * (t[4] - t[3]),
+                  "sweeps": args.nu}
+        log(f"batched phases: {phases}")
         batch.close()
     return {"cycle_updates_per_s": updates / (ms * 1e-3), "sweep_updates_per_s": nodes / (sweep_ms * 1e-3),
             "sweep_ms": sweep_ms, "sequential_sweep_updates_per_s": nodes / (seq_ms * 1e-3),
             "sequential_sweep_ms": seq_ms, "cases": len(cases), "cell_leaf_nodes": nodes,
             "tuned": {"passA_chunk_per_bucket": chunk[:4], "passC_leaves_in_flight": chunk[4]},
             "roofline_sweep": {"algorithmic_bytes_per_node": 24, "frac": 24 * nodes / (sweep_ms * 1e-3) / HBM_PEAK},
-            "cycles_timed": args.steps,
+            "cycles_timed": args.steps, "phases": phases,
             "workload": "64 seeded cavity/cylinder cases, Kn 1e-3..1, Ma 0.1..6, grids 32^2..96^2, "
                         "256..16k leaves, FP32, one graph per adaptation cycle"}
 

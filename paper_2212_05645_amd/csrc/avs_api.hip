@@ -751,9 +751,16 @@ struct avs_batch {
   int graph_chunk[4] = {-1, -1, -1, -1};
   int graph_passc = -2;
   std::vector<char> host_args;
+  // side streams (default priority) for the per-case adaptation and remap
+  // kernels: small cases' launches run side by side instead of one after
+  // another; joined back to `stream` with events
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_ev;   // [0, side.size()): joins; last: the fork
   ~avs_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : side_ev) (void)hipEventDestroy(e);
+    for (hipStream_t q : side) (void)hipStreamDestroy(q);
   }
 };
 
@@ -2180,6 +2187,51 @@ avs_status avs_batch_step(avs_batch* b, int32_t nsteps, int32_t use_graph) {
   return st;
 }
 
+namespace {
+
+constexpr int kSideStreams = 4;
+
+// Make the side streams wait for the work enqueued so far on the batch's
+// stream (created on first use).
+avs_status side_fork(avs_batch* b) {
+  avs_ctx* ctx = nullptr;
+  if (b->side.empty()) {
+    for (int j = 0; j < kSideStreams; ++j) {
+      hipStream_t q = nullptr;
+      CK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+      b->side.push_back(q);
+    }
+    for (int j = 0; j <= kSideStreams; ++j) {
+      hipEvent_t e = nullptr;
+      CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->side_ev.push_back(e);
+    }
+  }
+  CK(hipEventRecord(b->side_ev[kSideStreams], b->stream));
+  for (hipStream_t q : b->side) CK(hipStreamWaitEvent(q, b->side_ev[kSideStreams], 0));
+  return AVS_OK;
+}
+
+// Make the batch's stream wait for everything enqueued on the side streams.
+avs_status side_join(avs_batch* b) {
+  avs_ctx* ctx = nullptr;
+  for (int j = 0; j < (int)b->side.size(); ++j) {
+    CK(hipEventRecord(b->side_ev[j], b->side[j]));
+    CK(hipStreamWaitEvent(b->stream, b->side_ev[j], 0));
+  }
+  return AVS_OK;
+}
+
+// A case's launches go to side stream i % kSideStreams while this lives.
+struct OnSide {
+  avs_ctx* c;
+  hipStream_t keep;
+  OnSide(avs_batch* b, int i) : c(b->cases[i]), keep(c->stream) { c->stream = b->side[i % b->side.size()]; }
+  ~OnSide() { c->stream = keep; }
+};
+
+}  // namespace
+
 avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2_host, int64_t* n_new_host) {
   avs_ctx* ctx = nullptr;
   if (!b) return fail(AVS_E_INVALID, "null batch");
@@ -2189,12 +2241,15 @@ avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2
     if (avs_status st = guard(b->cases[i])) return st;
     if (std::isnan(C1_host[i]) || std::isnan(C2_host[i])) return fail(AVS_E_INVALID, "case %d: C1/C2 must not be NaN", i);
   }
-  // criterion, flags, scan of every case back to back; one wait for the counts
+  // criterion, flags, scan of every case, side by side; one wait for the counts
   for (avs_ctx* c : b->cases) c->plan_valid = false;
+  if (avs_status st = side_fork(b)) return st;
   for (int i = 0; i < n; ++i) {
+    OnSide on(b, i);
     avs_ctx* c = b->cases[i];
     if (avs_status st = DISPATCH(c, launch_adapt, c, C1_host[i], C2_host[i], 0)) return st;
   }
+  if (avs_status st = side_join(b)) return st;
   std::vector<int> nn(n, 0);
   for (int i = 0; i < n; ++i) {
     avs_ctx* c = b->cases[i];
@@ -2207,13 +2262,16 @@ avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2
       return fail(AVS_E_CAPACITY, "case %d: adaptation would produce %d leaves > leaf_capacity %" PRId64, i, nn[i],
                   b->cases[i]->cap);
   }
+  if (avs_status st = side_fork(b)) return st;
   for (int i = 0; i < n; ++i) {
+    OnSide on(b, i);
     avs_ctx* c = b->cases[i];
     const int t = c->lcur ^ 1;
     c->nleaf[t] = nn[i];
     c->ld[t] = (int)round_up(nn[i], 64);
     if (avs_status st = DISPATCH_D(c, launch_scatter, c)) return st;
   }
+  if (avs_status st = side_join(b)) return st;
   CK(hipStreamSynchronize(b->stream));
   for (int i = 0; i < n; ++i) {
     b->cases[i]->plan_n = nn[i];
@@ -2231,7 +2289,11 @@ avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
     if (avs_status st = guard(b->cases[i])) return st;
     if (!b->cases[i]->plan_valid) return fail(AVS_E_STATE, "case %d: no adaptation plan", i);
   }
-  for (avs_ctx* c : b->cases) {
+  avs_ctx* ctx = nullptr;
+  if (avs_status st = side_fork(b)) return st;
+  for (int i = 0; i < n; ++i) {
+    OnSide on(b, i);
+    avs_ctx* c = b->cases[i];
     if (avs_status st = DISPATCH(c, launch_remap, c, correction)) return st;
     c->lcur ^= 1;
     c->cur ^= 1;
@@ -2240,6 +2302,8 @@ avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
     if (avs_status st = DISPATCH_D(c, launch_bc_tables, c)) return st;
     if (avs_status st = DISPATCH(c, launch_moments, c)) return st;
   }
+  if (avs_status st = side_join(b)) return st;
+  CK(hipStreamSynchronize(b->stream));
   for (avs_ctx* c : b->cases)
     if (avs_status st = check_bad(c)) return st;
   return AVS_OK;
