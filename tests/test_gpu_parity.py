@@ -876,6 +876,58 @@ def test_batch_members_match_the_oracle(avs, prec):
         batch.close()
 
 
+def test_full_batch_sampled_members(avs):
+    """The batched workload at full size: the 64 seeded cases (cavities and
+    cylinders, grids 32^2..96^2, FP32) on seeded random trees of 16^2 roots
+    and 3 levels spanning the workload's leaf counts, tuned like the
+    benchmark (pass-A chunk per bucket, pass-C leaves in flight), one step
+    through the captured graph.  In every eighth member and the largest one,
+    a wall or lid cell and an interior cell are recomputed by the FP64
+    oracle from their two-ring neighbourhood: within 1e-5 of each row (the
+    FP32 storage rounding is 6e-8), W within 1e-6."""
+    import torch
+    specs = F.batch_cases(seed=0, ncase=64)
+    stream = torch.cuda.Stream()
+    lo, hi = math.log(256.0), math.log(16384.0)
+    with torch.cuda.stream(stream):
+        members, trees = [], []
+        for i, c in enumerate(specs):
+            p = 0.05 + 0.85 * (math.log(c['target_leaves']) - lo) / (hi - lo)
+            t = random_tree(c['vspace'], 900 + i, 3, p=p)
+            cs = avs.Case(c['mesh'], c['vspace'], c['gas'], c['dt'], c['venkat_K'], c['prim0'], precision=1,
+                          leaf_capacity=t.n, stream=stream)
+            cs.set_leaves(t.level, t.idx)
+            members.append(cs)
+            trees.append(t)
+        n = [t.n for t in trees]
+        assert min(n) < 1000 and max(n) > 8000
+        batch = avs.Batch(members)
+        batch.tune()
+        batch.step(1, graph=True)
+        torch.cuda.synchronize()
+        pick = sorted(set(range(0, 64, 8)) | {int(np.argmax(n))})
+        for i in pick:
+            c, cs, t = specs[i], members[i], trees[i]
+            m = c['mesh']
+            lr = np.asarray(m['face_lr'])
+            wall = int(lr[lr[:, 1] == -1, 0][0])
+            sample = sorted({wall, m['ncells'] // 2 + 3})
+            got = cs.get_cells(sample)
+            Wg = cs.get_W()[sample]
+            sub, keep = MM.submesh(m, sample, halo=2)
+            gas = O.gas_from(c['gas'])
+            o = O.Solver(sub, c['vspace'], gas, c['dt'], c['venkat_K'], c['prim0'][keep])
+            o.tree = t
+            o.phi = o.initial_vdf(o.W)
+            loc = [int(np.searchsorted(keep, j)) for j in sample]
+            phi1, W1, _ = O.step(o.mesh, t, gas, c['dt'], c['venkat_K'], o.phi, o.W, cells=loc)
+            assert rel(got, phi1[:, loc]) < 1e-5, (i, c['geometry'], t.n)
+            assert rel(Wg, W1[loc]) < 1e-6, (i, c['geometry'], t.n)
+        batch.close()
+        for cs in members:
+            cs.close()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_fine_velocity_grids_beyond_64_kib_of_lds(avs, dim):
     """Velocity grids whose per-axis Maxwellian tables need more than the
