@@ -1341,6 +1341,9 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
   build_tab_r<D, T>(lds + MAXF * D * nu, tpar + (size_t)i * NPAR, vg);
   __syncthreads();
   const T* tp = spar + MAXF * NPAR;
+  bool full = ns == MAXF;
+#pragma unroll
+  for (int q = 0; q < MAXF; ++q) full = full && snbr[q] >= 0;
   const T dtt = tp[P_A], dtv = (T)g.dtv[i];
   const T inv = (T)1 / ((T)1 + dtt);
   double acc[N + D];
@@ -1366,6 +1369,37 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
     T div[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) div[p] = 0;
+    if (full) {
+      // every slot an interior face: the face loop unrolled, rows taken by
+      // static index.  The empty asm with a memory clobber makes each face
+      // read its record from LDS where it is used; without it the compiler
+      // keeps all the faces' records live across the leaf loop (168-256
+      // VGPRs).
+#pragma unroll
+      for (int s = 0; s < MAXF; ++s) {
+        __asm__ volatile("" ::: "memory");
+        T pf[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) pf[p] = x.row[s][p];
+        const T* par = spar + s * NPAR;
+        const T gv = maxw_r<D, T>(par, lds + s * D * nu, nu, x.u);
+        T G, H;
+        shakhov_r<D, T>(par, gv, xr, G, H);
+        pf[0] = par[P_A] * pf[0] + par[P_B] * G;
+        if (P == 2) pf[P - 1] = par[P_A] * pf[P - 1] + par[P_B] * H;
+        T sw;
+        if constexpr (sizeof(T) == 8) {
+          sw = normal_speed<D>(x.xi, snrm[s]);
+        } else {
+          sw = xr[0] * snrt[s][0];
+#pragma unroll
+          for (int d = 1; d < D; ++d) sw += xr[d] * snrt[s][d];
+        }
+        const T w = ssa[s] * sw;
+#pragma unroll
+        for (int p = 0; p < P; ++p) div[p] += w * pf[p];
+      }
+    } else
     // one face at a time: its record is read from LDS inside the loop, so
     // only one face's parameters are live in registers
 #pragma unroll 1
