@@ -487,19 +487,31 @@ __global__ __launch_bounds__(BLOCK) void k_cell_moments(Geo g, Leaves L, const T
 template <int D, typename T>
 struct Stencil {
   static constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
+  // 3-D: the LSQ coefficients and face offsets stay in LDS and are read
+  // where they are used (held in scalar registers, the six faces' constants
+  // spilled and were reloaded lane by lane on every leaf)
+  static constexpr bool kLds = D == 3;
   int ns;
   unsigned nbmask;            // bit s: face s has an interior neighbour
   const T* own[P];
   const T* nb[MAXF][P];
-  T cf[MAXF][D];
-  T dd[MAXF][D];
+  T cf[kLds ? 1 : MAXF][D];
+  T dd[kLds ? 1 : MAXF][D];
+  const T* lcf = nullptr;
+  const T* ldd = nullptr;
   T eps2;
+  __device__ __forceinline__ T CF(int s, int d) const {
+    if constexpr (kLds) return lcf[s * D + d]; else return cf[s][d];
+  }
+  __device__ __forceinline__ T DD(int s, int d) const {
+    if constexpr (kLds) return ldd[s * D + d]; else return dd[s][d];
+  }
 };
 
 // The per-cell constants come from global memory (uniform loads, scalar
-// registers) or, with lcf/ldd non-null, from LDS (vector registers): 2-D FP32
-// has vector registers to spare and runs faster with them there, the other
-// forms would lose occupancy.
+// registers) or, with lcf/ldd non-null, from LDS: copied to vector registers
+// in 2-D FP32 (registers to spare), read at their use in 3-D (Stencil::kLds,
+// which needs lcf/ldd).
 template <int D, typename T>
 __device__ __forceinline__ void load_stencil(const Geo& g, const T* __restrict__ vdf, size_t cs, int ld, int c,
                                              Stencil<D, T>& st, const T* lcf = nullptr, const T* ldd = nullptr) {
@@ -517,7 +529,10 @@ __device__ __forceinline__ void load_stencil(const Geo& g, const T* __restrict__
     for (int p = 0; p < P; ++p) st.nb[s][p] = j >= 0 ? vdf + p * cs + (size_t)j * ld : st.own[p];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      if (lcf) {
+      if constexpr (Stencil<D, T>::kLds) {
+        st.lcf = lcf;
+        st.ldd = ldd;
+      } else if (lcf) {
         st.cf[s][d] = lcf[s * D + d];
         st.dd[s][d] = ldd[s * D + d];
       } else {
@@ -557,21 +572,6 @@ __device__ __forceinline__ void lim_parts(const Stencil<D, T>& st, const Stencil
                                           T (&lim)[Cfg<D>::P], T (&grad)[Cfg<D>::P][D],
                                           T (&d2s)[Cfg<D>::P][Cfg<D>::MAXF]);
 
-// The limited gradient L grad phi of leaf k (loads and arithmetic together).
-template <int D, typename T, bool FULL = false>
-__device__ __forceinline__ void lim_grad(const Stencil<D, T>& st, int k, T (&phi)[Cfg<D>::P],
-                                         T (&lg)[Cfg<D>::P][D]) {
-  constexpr int P = Cfg<D>::P, MAXF = Cfg<D>::MAXF;
-  StencilVals<D, T> sv;
-  load_vals<D, T>(st, k, sv);
-  T lim[P], grad[P][D], d2s[P][MAXF];
-  lim_parts<D, T, FULL>(st, sv, phi, lim, grad, d2s);
-#pragma unroll
-  for (int p = 0; p < P; ++p)
-#pragma unroll
-    for (int d = 0; d < D; ++d) lg[p][d] = lim[p] * grad[p][d];
-}
-
 // Least-squares gradient, its increments grad . (x_f - x_i) towards the face
 // midpoints (D2 of the limiter, d2s) and the Venkatakrishnan limiter L, per
 // VDF component, in T.  FULL: every one of the MAXF slots is a face with an
@@ -603,7 +603,7 @@ __device__ __forceinline__ void lim_parts(const Stencil<D, T>& st, const Stencil
         const T v = nv[s][p];
         const T dv = v - phi[p];
 #pragma unroll
-        for (int d = 0; d < D; ++d) grad[p][d] += dv * st.cf[s][d];
+        for (int d = 0; d < D; ++d) grad[p][d] += dv * st.CF(s, d);
         dmax[p] = fmax(dv, dmax[p]);
         dmin[p] = fmin(dv, dmin[p]);
       }
@@ -623,7 +623,7 @@ __device__ __forceinline__ void lim_parts(const Stencil<D, T>& st, const Stencil
     for (int s = 0; s < MAXF; ++s) {
       T d2 = 0;
 #pragma unroll
-      for (int d = 0; d < D; ++d) d2 += grad[p][d] * st.dd[s][d];
+      for (int d = 0; d < D; ++d) d2 += grad[p][d] * st.DD(s, d);
       d2s[p][s] = d2;
       m = fmax(fabs(d2), m);
     }
@@ -746,12 +746,14 @@ __device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, 
   const size_t cs = (size_t)g.nc * L.ld;
   const size_t fs = (size_t)g.nf * L.ld;   // component stride of the interface buffer
   // where the per-cell constants live: scalar registers (loaded from global
-  // memory) or vector registers (staged through LDS).  In 2-D the face
-  // normals go through LDS (fewer scalar spills), and in 2-D FP32 also the
-  // LSQ coefficients and face offsets; 3-D keeps them all scalar (its vector
-  // registers bound the occupancy).
-  constexpr bool lds_consts = D == 2 && sizeof(T) == 4;
-  constexpr bool lds_nrm = D == 2;
+  // memory), vector registers (staged through LDS) or LDS itself.  In 2-D
+  // the face normals go through LDS (fewer scalar spills), and in 2-D FP32
+  // also the LSQ coefficients and face offsets.  3-D reads all of them from
+  // LDS at their use, behind a compiler memory barrier per leaf, so they
+  // occupy neither scalar nor vector registers across the leaf loop
+  // (sphere FP32 pass A 38.7 -> 33.3 ms).
+  constexpr bool lds_consts = (D == 2 && sizeof(T) == 4) || Stencil<D, T>::kLds;
+  constexpr bool lds_nrm = D == 2 || Stencil<D, T>::kLds;
   Stencil<D, T> st;
   double nrm[MAXF][D];
   unsigned lside = 0;          // bit s: the cell is the L side of face s
@@ -817,6 +819,8 @@ __device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, 
       for (int d = 0; d < D; ++d) xi[d] = xi_n[d];
       const double aw_k = aw_n;
       T phi[P], lim[P], grad[P][D], d2s[P][MAXF];
+      // re-read the LDS constants below instead of keeping them live
+      if constexpr (Stencil<D, T>::kLds) __asm__ volatile("" ::: "memory");
       lim_parts<D, T, FULL>(st, sv, phi, lim, grad, d2s);
       // phibar = phi + L grad . (x_f - x_i) - h L grad . xi: the first product
       // is the limiter's D2 of the face, the second is shared by the faces
@@ -834,7 +838,7 @@ __device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, 
 #pragma unroll
         for (int p = 0; p < P; ++p) u[p] = 0;
         if (FULL || s < ns) {
-          const double sn = normal_speed<D>(xi, nrm[s]);
+          const double sn = normal_speed<D>(xi, Stencil<D, T>::kLds ? s_nrm + s * D : nrm[s]);
           const bool up = (lside >> s) & 1u ? (sn >= 0.0) : (sn < 0.0);
           if (up) {
 #pragma unroll
