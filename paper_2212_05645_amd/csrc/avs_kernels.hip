@@ -1345,7 +1345,9 @@ __device__ __forceinline__ void d_passC(Geo g, Leaves L, VGrid vg, const T* __re
   build_tab_r<D, T>(lds + MAXF * D * nu, tpar + (size_t)i * NPAR, vg);
   __syncthreads();
   const T* tp = spar + MAXF * NPAR;
-  bool full = ns == MAXF;
+  // the unrolled face loop in 3-D and FP32 (2-D FP64, bound by HBM, is no
+  // faster with it and fetches more)
+  bool full = (D == 3 || sizeof(T) == 4) && ns == MAXF;
 #pragma unroll
   for (int q = 0; q < MAXF; ++q) full = full && snbr[q] >= 0;
   const T dtt = tp[P_A], dtv = (T)g.dtv[i];
