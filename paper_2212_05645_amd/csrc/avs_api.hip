@@ -2222,6 +2222,13 @@ avs_status side_join(avs_batch* b) {
   return AVS_OK;
 }
 
+// Joins the side streams back on every way out of a call that forked them,
+// so that the batch's stream never runs ahead of side-stream work.
+struct SideJoin {
+  avs_batch* b;
+  ~SideJoin() { (void)side_join(b); }
+};
+
 // A case's launches go to side stream i % kSideStreams while this lives.
 struct OnSide {
   avs_ctx* c;
@@ -2244,12 +2251,14 @@ avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2
   // criterion, flags, scan of every case, side by side; one wait for the counts
   for (avs_ctx* c : b->cases) c->plan_valid = false;
   if (avs_status st = side_fork(b)) return st;
-  for (int i = 0; i < n; ++i) {
-    OnSide on(b, i);
-    avs_ctx* c = b->cases[i];
-    if (avs_status st = DISPATCH(c, launch_adapt, c, C1_host[i], C2_host[i], 0)) return st;
+  {
+    SideJoin join{b};
+    for (int i = 0; i < n; ++i) {
+      OnSide on(b, i);
+      avs_ctx* c = b->cases[i];
+      if (avs_status st = DISPATCH(c, launch_adapt, c, C1_host[i], C2_host[i], 0)) return st;
+    }
   }
-  if (avs_status st = side_join(b)) return st;
   std::vector<int> nn(n, 0);
   for (int i = 0; i < n; ++i) {
     avs_ctx* c = b->cases[i];
@@ -2263,15 +2272,17 @@ avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2
                   b->cases[i]->cap);
   }
   if (avs_status st = side_fork(b)) return st;
-  for (int i = 0; i < n; ++i) {
-    OnSide on(b, i);
-    avs_ctx* c = b->cases[i];
-    const int t = c->lcur ^ 1;
-    c->nleaf[t] = nn[i];
-    c->ld[t] = (int)round_up(nn[i], 64);
-    if (avs_status st = DISPATCH_D(c, launch_scatter, c)) return st;
+  {
+    SideJoin join{b};
+    for (int i = 0; i < n; ++i) {
+      OnSide on(b, i);
+      avs_ctx* c = b->cases[i];
+      const int t = c->lcur ^ 1;
+      c->nleaf[t] = nn[i];
+      c->ld[t] = (int)round_up(nn[i], 64);
+      if (avs_status st = DISPATCH_D(c, launch_scatter, c)) return st;
+    }
   }
-  if (avs_status st = side_join(b)) return st;
   CK(hipStreamSynchronize(b->stream));
   for (int i = 0; i < n; ++i) {
     b->cases[i]->plan_n = nn[i];
@@ -2291,18 +2302,20 @@ avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
   }
   avs_ctx* ctx = nullptr;
   if (avs_status st = side_fork(b)) return st;
-  for (int i = 0; i < n; ++i) {
-    OnSide on(b, i);
-    avs_ctx* c = b->cases[i];
-    if (avs_status st = DISPATCH(c, launch_remap, c, correction)) return st;
-    c->lcur ^= 1;
-    c->cur ^= 1;
-    ++c->leaf_gen;
-    c->plan_valid = false;
-    if (avs_status st = DISPATCH_D(c, launch_bc_tables, c)) return st;
-    if (avs_status st = DISPATCH(c, launch_moments, c)) return st;
+  {
+    SideJoin join{b};
+    for (int i = 0; i < n; ++i) {
+      OnSide on(b, i);
+      avs_ctx* c = b->cases[i];
+      if (avs_status st = DISPATCH(c, launch_remap, c, correction)) return st;
+      c->lcur ^= 1;
+      c->cur ^= 1;
+      ++c->leaf_gen;
+      c->plan_valid = false;
+      if (avs_status st = DISPATCH_D(c, launch_bc_tables, c)) return st;
+      if (avs_status st = DISPATCH(c, launch_moments, c)) return st;
+    }
   }
-  if (avs_status st = side_join(b)) return st;
   CK(hipStreamSynchronize(b->stream));
   for (avs_ctx* c : b->cases)
     if (avs_status st = check_bad(c)) return st;

@@ -1688,7 +1688,7 @@ __global__ void k_sep_floor(Leaves L, int lmax, int b0, int b1, int b2, double l
     s = s + x * x;
   }
   if (r2lo < s && s < r2hi && l < S && l < lmax) r = 1;
-  if (r == -1 && l - 1 < S) {
+  if (r == -1 && l > 0 && l - 1 < S) {
     s = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
