@@ -876,6 +876,43 @@ def test_batch_members_match_the_oracle(avs, prec):
         batch.close()
 
 
+def test_degenerate_cases(avs):
+    """Degenerate inputs: zero steps leave the state bit for bit and a
+    residual over zero steps is refused; a velocity space without levels
+    (4^2 roots, 16 leaves: one ragged chunk) steps like the oracle, and its
+    adaptation can neither split (maximum level) nor merge (roots); an
+    adaptation that flags nothing (C1 = inf, C2 = 0) keeps every leaf and
+    its copy remap returns the state bit for bit."""
+    c = F.cavity(n=8, base=4, max_level=0)
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'], Kv=1.0)
+    assert cs.nleaves() == 16
+    v0, W0 = cs.get_state()
+    cs.step(0)
+    v1, W1 = cs.get_state()
+    assert np.array_equal(v0, v1) and np.array_equal(W0, W1)
+    with pytest.raises(avs.AvsError):
+        cs.step(0, residual=True)
+    cs.step(2)
+    o.step(2)
+    v, W = cs.get_state()
+    assert rel(v, o.phi) < 1e-12 and rel(W, o.W) < 1e-12
+    flags, nn = cs.adapt(0.0, 1e300)         # every leaf over C1 and under C2
+    assert nn == 16 and not flags.any()
+    cs.remap(0)
+    c = F.cavity(n=8, base=8, max_level=2)
+    cs, o = make_pair(avs, c['mesh'], c['vspace'], c['gas'], c['dt'], c['prim0'],
+                      tree=random_tree(c['vspace'], 71, 2), Kv=1.0)
+    cs.step(1)
+    v0, W0 = cs.get_state()
+    n0 = cs.nleaves()
+    flags, nn = cs.adapt(math.inf, 0.0)
+    assert nn == n0 and not flags.any()
+    cs.remap(0)
+    v1, W1 = cs.get_state()
+    assert np.array_equal(v0, v1) and np.array_equal(W0, W1)
+    cs.close()
+
+
 def test_full_batch_sampled_members(avs):
     """The batched workload at full size: the 64 seeded cases (cavities and
     cylinders, grids 32^2..96^2, FP32) on seeded random trees of 16^2 roots
