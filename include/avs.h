@@ -386,12 +386,14 @@ avs_status avs_batch_check(avs_batch *batch);
 avs_status avs_batch_tune(avs_batch *batch, int32_t *chunk_host);
 /* avs_adapt (no probe states, no flags) for every member, case i with
  * thresholds C1_host[i], C2_host[i]: the criterion, flags and scan of all
- * cases are enqueued back to back, the new leaf counts (n_new_host[i], or
- * NULL) are read with one wait, then every new leaf list and remap plan is
- * built.  AVS_E_CAPACITY names the first case over its leaf_capacity; no
- * plan is then valid.  avs_batch_remap applies avs_remap(correction) to every
- * member and reports a non-physical state in any of them.  Results are those
- * of the per-case calls, bit for bit. */
+ * cases are enqueued on four side streams (forked from and joined back to
+ * the batch's stream), the new leaf counts (n_new_host[i], or NULL) are read
+ * with one wait, then every new leaf list and remap plan is built.
+ * AVS_E_CAPACITY names the first case over its leaf_capacity; no plan is
+ * then valid.  avs_batch_remap applies avs_remap(correction) to every member
+ * (corrections 0-2 as launches spanning all members, 3-4 per member) and
+ * reports a non-physical state in any of them.  Results are those of the
+ * per-case calls, bit for bit.  Both wait for the device. */
 avs_status avs_batch_adapt(avs_batch *batch, const double *C1_host, const double *C2_host, int64_t *n_new_host);
 avs_status avs_batch_remap(avs_batch *batch, int32_t correction);
 void avs_batch_destroy(avs_batch *batch);

@@ -684,7 +684,8 @@ hipError_t raise_lds() {
                        (const void*)kb_passC<D, T, true>, (const void*)kb_passC<D, T, false>,
                        (const void*)k_face_eq<D, T>,      (const void*)kb_face_eq<D, T>,
                        (const void*)k_target<D, T>,       (const void*)kb_target<D, T>,
-                       (const void*)k_remap_correct<D, T>, (const void*)k_init_vdf<D, T>};
+                       (const void*)k_remap_correct<D, T>, (const void*)kb_remap_correct<D, T>,
+                       (const void*)k_init_vdf<D, T>};
   for (const void* fn : fns) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
@@ -751,6 +752,7 @@ struct avs_batch {
   int graph_chunk[4] = {-1, -1, -1, -1};
   int graph_passc = -2;
   std::vector<char> host_args;
+  std::vector<char> host_remap;   // records of the batched remap
   // side streams (default priority) for the per-case adaptation and remap
   // kernels: small cases' launches run side by side instead of one after
   // another; joined back to `stream` with events
@@ -770,6 +772,9 @@ namespace {
 int leaf_bucket(int nleaves) { return nleaves < 1024 ? 0 : nleaves < 4096 ? 1 : nleaves < 16384 ? 2 : 3; }
 
 size_t batch_args_bytes(int ncase) { return (size_t)round_up(2 * (size_t)ncase * sizeof(CaseArgs<double>), 256); }
+size_t batch_offs_bytes(int ncase) { return (size_t)round_up(sizeof(int) * BK_N * (ncase + 1), 256); }
+size_t remap_args_bytes(int ncase) { return (size_t)round_up((size_t)ncase * sizeof(RemapArgs<double>), 256); }
+size_t remap_offs_bytes(int ncase) { return (size_t)round_up(sizeof(int) * BR_N * (ncase + 1), 256); }
 
 template <typename T>
 CaseArgs<T> case_args(avs_ctx* c, int flip, int chunk) {
@@ -2145,7 +2150,7 @@ int32_t avs_profile_read(avs_ctx* ctx, int32_t nmax, char* names_host, double* m
 
 size_t avs_batch_workspace_bytes(int32_t ncase) {
   if (ncase < 1 || ncase > 4096) return 0;
-  return batch_args_bytes(ncase) + round_up(sizeof(int) * BK_N * (ncase + 1), 256);
+  return batch_args_bytes(ncase) + batch_offs_bytes(ncase) + remap_args_bytes(ncase) + remap_offs_bytes(ncase);
 }
 
 avs_status avs_batch_create(int32_t ncase, avs_ctx* const* ctxs, void* workspace_dev, size_t workspace_bytes,
@@ -2292,6 +2297,88 @@ avs_status avs_batch_adapt(avs_batch* b, const double* C1_host, const double* C2
   return AVS_OK;
 }
 
+extern "C++" {
+namespace {
+
+// The remap of every member in five launches over all members' workgroups:
+// gather (+ W'), correction (correction 1, 2), the boundary pair and face
+// tables of the new leaves, the moments of the new state.  The members'
+// leaf and state buffers flip as after avs_remap.
+template <int D, typename T>
+avs_status batch_remap_launch(avs_batch* b, int correction) {
+  avs_ctx* ctx = nullptr;
+  const int n = (int)b->cases.size();
+  char* base = b->ws + batch_args_bytes(n) + batch_offs_bytes(n);
+  b->host_remap.resize(remap_args_bytes(n) + remap_offs_bytes(n));
+  RemapArgs<T>* args = reinterpret_cast<RemapArgs<T>*>(b->host_remap.data());
+  int* off = reinterpret_cast<int*>(b->host_remap.data() + remap_args_bytes(n));
+  for (int k = 0; k < BR_N; ++k) off[k * (n + 1)] = 0;
+  int numax = 0;
+  for (int i = 0; i < n; ++i) {
+    avs_ctx* c = b->cases[i];
+    RemapArgs<T> a;
+    a.g = c->geo;
+    a.Lo = c->leaves(c->lcur);
+    a.Ln = c->leaves(c->lcur ^ 1);
+    a.vg = c->vg;
+    a.gas = c->gas;
+    a.pkind = c->pkind;
+    a.psrc = c->psrc;
+    a.vin = (const T*)c->vdf[c->cur];
+    a.vout = (T*)c->vdf[c->cur ^ 1];
+    a.momp = c->momp;
+    a.W = c->W;
+    a.mom = c->mom;
+    a.q = c->q;
+    a.bad = c->bad;
+    a.bcpair = c->bcpair;
+    a.bden = c->bden;
+    a.bfin = c->bfin;
+    a.nbl = (a.Ln.n + BLOCK - 1) / BLOCK;
+    args[i] = a;
+    numax = std::max(numax, c->vg.numax);
+    const int cnt[BR_N] = {c->nc, correction > 0 ? c->nc : 0, c->nbc > 0 ? a.nbl * c->nbc : 0, c->n_bnd, c->nc};
+    for (int k = 0; k < BR_N; ++k) off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + cnt[k];
+  }
+  CK(hipMemcpyAsync(base, b->host_remap.data(), b->host_remap.size(), hipMemcpyHostToDevice, b->stream));
+  const RemapArgs<T>* a = reinterpret_cast<const RemapArgs<T>*>(base);
+  const int* o = reinterpret_cast<const int*>(base + remap_args_bytes(n));
+  auto nb = [&](int k) { return off[k * (n + 1) + n]; };
+  if (nb(BR_GATHER) > 0) {
+    kb_remap_gather<D, T><<<nb(BR_GATHER), BLOCK, 0, b->stream>>>(a, o + BR_GATHER * (n + 1), n);
+    CKL();
+  }
+  if (nb(BR_CORRECT) > 0) {
+    kb_remap_correct<D, T><<<nb(BR_CORRECT), BLOCK, (size_t)2 * D * numax * sizeof(double), b->stream>>>(
+        a, o + BR_CORRECT * (n + 1), n, correction);
+    CKL();
+  }
+  if (nb(BR_PAIRS) > 0) {
+    kb_bc_pairs<D, T><<<nb(BR_PAIRS), BLOCK, 0, b->stream>>>(a, o + BR_PAIRS * (n + 1), n);
+    CKL();
+  }
+  if (nb(BR_BND) > 0) {
+    kb_bnd_tables<D, T><<<nb(BR_BND), BLOCK, 0, b->stream>>>(a, o + BR_BND * (n + 1), n);
+    CKL();
+  }
+  if (nb(BR_MOM) > 0) {
+    kb_cell_moments<D, T><<<nb(BR_MOM), BLOCK, 0, b->stream>>>(a, o + BR_MOM * (n + 1), n);
+    CKL();
+  }
+  for (avs_ctx* c : b->cases) {
+    c->lcur ^= 1;
+    c->cur ^= 1;
+    ++c->leaf_gen;
+    c->plan_valid = false;
+  }
+  // the host records stay in use until the copy has read them
+  CK(hipStreamSynchronize(b->stream));
+  return AVS_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
 avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
   if (!b) return fail(AVS_E_INVALID, "null batch");
   if (correction < 0 || correction > 4) return fail(AVS_E_INVALID, "correction must be 0 to 4");
@@ -2301,6 +2388,18 @@ avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
     if (!b->cases[i]->plan_valid) return fail(AVS_E_STATE, "case %d: no adaptation plan", i);
   }
   avs_ctx* ctx = nullptr;
+  if (correction <= 2) {
+    // one set of launches over all members
+    if (avs_status st = b->D == 2 ? (b->prec == AVS_FP64 ? batch_remap_launch<2, double>(b, correction)
+                                                          : batch_remap_launch<2, float>(b, correction))
+                                  : (b->prec == AVS_FP64 ? batch_remap_launch<3, double>(b, correction)
+                                                          : batch_remap_launch<3, float>(b, correction)))
+      return st;
+    for (avs_ctx* c : b->cases)
+      if (avs_status st = check_bad(c)) return st;
+    return AVS_OK;
+  }
+  // the equilibrium bypass: each member's own kernels, side by side
   if (avs_status st = side_fork(b)) return st;
   {
     SideJoin join{b};

@@ -446,12 +446,10 @@ __global__ __launch_bounds__(BLOCK) void k_init_vdf(Geo g, Leaves L, VGrid vg, G
 // ------------------------------------------------------- cell moments / q
 // M[phi_i] and q_i = 1/2 sum A c (c^2 G + H), c = xi - U(W_i) (Eqs. updat_W, equ8).
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void k_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf,
-                                                         const double* __restrict__ W, double* __restrict__ mom,
-                                                         double* __restrict__ q) {
+__device__ __forceinline__ void d_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf, const double* __restrict__ W, double* __restrict__ mom, double* __restrict__ q, int bx) {
   constexpr int N = D + 2;
   __shared__ double red[4 * (N + D)];
-  const int i = blockIdx.x;
+  const int i = bx;
   const size_t cs = (size_t)g.nc * L.ld;
   double U[D];
 #pragma unroll
@@ -478,6 +476,11 @@ __global__ __launch_bounds__(BLOCK) void k_cell_moments(Geo g, Leaves L, const T
     for (int m = 0; m < N; ++m) mom[(size_t)i * N + m] = acc[m];
     for (int d = 0; d < D; ++d) q[(size_t)i * D + d] = acc[N + d];
   }
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf, const double* __restrict__ W, double* __restrict__ mom, double* __restrict__ q) {
+  d_cell_moments<D, T>(g, L, vdf, W, mom, q, blockIdx.x);
 }
 
 // ------------------------------------------------- limited gradient (S2-S3)
@@ -1524,11 +1527,10 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passC(Geo g, Le
 // ----------------------------------------------- boundary Maxwellians (S7)
 // Per bc and leaf: the incoming Maxwellian pair (unit density for walls).
 template <int D>
-__global__ void k_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ kind, const double* __restrict__ prim,
-                           double* __restrict__ pair) {
+__device__ __forceinline__ void d_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ kind, const double* __restrict__ prim, double* __restrict__ pair, int bx, int by) {
   constexpr int P = Cfg<D>::P;
-  const int k = blockIdx.x * BLOCK + threadIdx.x;
-  const int b = blockIdx.y;
+  const int k = bx * BLOCK + threadIdx.x;
+  const int b = by;
   if (k >= L.n) return;
   const double* st = prim + (size_t)b * (D + 2);
   const double rho = kind[b] == 0 ? 1.0 : st[0];
@@ -1543,13 +1545,17 @@ __global__ void k_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ 
   if (P == 2) pair[((size_t)b * P + 1) * L.cap + k] = RT * gv;
 }
 
+template <int D>
+__global__ void k_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ kind, const double* __restrict__ prim, double* __restrict__ pair) {
+  d_bc_pairs<D>(L, gas, nbc, kind, prim, pair, blockIdx.x, blockIdx.y);
+}
+
 // Per boundary face: den = sum_{s<0} A |s| g_wall and Fin = sum_{s<0} A s psi pair.
 template <int D>
-__global__ __launch_bounds__(BLOCK) void k_bnd_tables(Geo g, Leaves L, const double* __restrict__ pair,
-                                                       double* __restrict__ bden, double* __restrict__ bfin) {
+__device__ __forceinline__ void d_bnd_tables(Geo g, Leaves L, const double* __restrict__ pair, double* __restrict__ bden, double* __restrict__ bfin, int bx) {
   constexpr int P = Cfg<D>::P, N = D + 2;
   __shared__ double red[4 * (N + 1)];
-  const int f = g.f_bnd[blockIdx.x];
+  const int f = g.f_bnd[bx];
   const int bc = -1 - g.f_R[f];
   double n[D];
   for (int d = 0; d < D; ++d) n[d] = g.f_nrm[(size_t)f * D + d];
@@ -1574,6 +1580,11 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_tables(Geo g, Leaves L, const dou
     for (int m = 0; m < N; ++m) bfin[(size_t)f * N + m] = acc[m];
     bden[f] = acc[N];
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_bnd_tables(Geo g, Leaves L, const double* __restrict__ pair, double* __restrict__ bden, double* __restrict__ bfin) {
+  d_bnd_tables<D>(g, L, pair, bden, bfin, blockIdx.x);
 }
 
 // ----------------------------------------------------- criterion (Sec. 3.4)
@@ -1784,13 +1795,11 @@ __global__ void k_scatter(Leaves L, const int8_t* __restrict__ eff, const int* _
 // Gather the new rows (copy or pairwise mean of 2^D brothers) and the
 // moments W' of the result.
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void k_remap_gather(Geo g, Leaves Lo, Leaves Ln, const int* __restrict__ kind,
-                                                         const int* __restrict__ src, const T* __restrict__ vin,
-                                                         T* __restrict__ vout, double* __restrict__ momp) {
+__device__ __forceinline__ void d_remap_gather(Geo g, Leaves Lo, Leaves Ln, const int* __restrict__ kind, const int* __restrict__ src, const T* __restrict__ vin, T* __restrict__ vout, double* __restrict__ momp, int bx) {
 #pragma clang fp contract(off)
   constexpr int P = Cfg<D>::P, N = D + 2;
   __shared__ double red[4 * N];
-  const int i = blockIdx.x;
+  const int i = bx;
   const size_t cso = (size_t)g.nc * Lo.ld, csn = (size_t)g.nc * Ln.ld;
   double acc[N];
   for (int m = 0; m < N; ++m) acc[m] = 0.0;
@@ -1823,13 +1832,15 @@ __global__ __launch_bounds__(BLOCK) void k_remap_gather(Geo g, Leaves Lo, Leaves
     for (int m = 0; m < N; ++m) momp[(size_t)i * N + m] = acc[m];
 }
 
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_remap_gather(Geo g, Leaves Lo, Leaves Ln, const int* __restrict__ kind, const int* __restrict__ src, const T* __restrict__ vin, T* __restrict__ vout, double* __restrict__ momp) {
+  d_remap_gather<D, T>(g, Lo, Ln, kind, src, vin, vout, momp, blockIdx.x);
+}
+
 // Conservation correction of Sec. 3.3: f = f' + g_eq(W) - g_eq(W'), then
 // (mode 2) the closure that restores M[f] = W.  In place on the new rows.
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode,
-                                                          const double* __restrict__ W,
-                                                          const double* __restrict__ momp, T* __restrict__ vdf,
-                                                          int* __restrict__ bad) {
+__device__ __forceinline__ void d_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode, const double* __restrict__ W, const double* __restrict__ momp, T* __restrict__ vdf, int* __restrict__ bad, int bx) {
   constexpr int P = Cfg<D>::P, N = D + 2, NS = Cfg<D>::NS;
   extern __shared__ double lds[];
   double* tabA = lds;
@@ -1838,7 +1849,7 @@ __global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid 
   __shared__ double parA[NPAR], parB[NPAR];
   __shared__ double lam[N];
   __shared__ ClosureWork<D> cw;
-  const int i = blockIdx.x;
+  const int i = bx;
   if (threadIdx.x == 0) {
     double rho, U[D], T_;
     if (!prim_from_W<D>(W + (size_t)i * N, gas, rho, U, T_)) atomicMin(bad, i);
@@ -1896,6 +1907,11 @@ __global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid 
     r[0] = (T)(ld_(r) + (ga - gb) + poly * ga);
     if (P == 2) r[cs] = (T)(ld_(r + cs) + (parA[P_RT] * ga - parB[P_RT] * gb) + poly * parA[P_RT] * ga);
   }
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode, const double* __restrict__ W, const double* __restrict__ momp, T* __restrict__ vdf, int* __restrict__ bad) {
+  d_remap_correct<D, T>(g, L, vg, gas, mode, W, momp, vdf, bad, blockIdx.x);
 }
 
 // -------------------------------------------------- residual, totals, fields
@@ -2078,6 +2094,79 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void kb_passC(const Ca
   const CaseArgs<T>* a = args + c;
   d_passC<D, T, false, TWO>(global_geo(a->g), global_leaves(a->L), a->vg, gptr(a->vin), gptr(a->fv), gptr(a->vout), gptr(a->fpar),
                 gptr(a->tpar), gptr(a->lam), gptr(a->mom), gptr(a->q), blockIdx.x - off[c]);
+}
+
+
+// ------------------------------------------- batched remap (all members)
+// One record per member for the remap of a batched adaptation: the old and
+// new leaves, the state buffers (in: the old rows, out: the new), and what
+// the boundary tables and moments of the new leaves need.
+template <typename T>
+struct RemapArgs {
+  Geo g;
+  Leaves Lo, Ln;
+  VGrid vg;
+  GasP gas;
+  const int* pkind;
+  const int* psrc;
+  const T* vin;
+  T* vout;
+  double* momp;
+  const double* W;
+  double* mom;
+  double* q;
+  int* bad;
+  double* bcpair;
+  double* bden;
+  double* bfin;
+  int nbl;         // ceil(new leaves / BLOCK): blocks per boundary condition of the pair tables
+};
+
+enum { BR_GATHER, BR_CORRECT, BR_PAIRS, BR_BND, BR_MOM, BR_N };
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void kb_remap_gather(const RemapArgs<T>* __restrict__ args,
+                                                         const int* __restrict__ off, int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const RemapArgs<T>* a = args + c;
+  d_remap_gather<D, T>(global_geo(a->g), global_leaves(a->Lo), global_leaves(a->Ln), gptr(a->pkind), gptr(a->psrc),
+                       gptr(a->vin), gptr(a->vout), gptr(a->momp), blockIdx.x - off[c]);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void kb_remap_correct(const RemapArgs<T>* __restrict__ args,
+                                                          const int* __restrict__ off, int ncase, int mode) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const RemapArgs<T>* a = args + c;
+  d_remap_correct<D, T>(global_geo(a->g), global_leaves(a->Ln), a->vg, a->gas, mode, gptr(a->W), gptr(a->momp),
+                        gptr(a->vout), gptr(a->bad), blockIdx.x - off[c]);
+}
+
+template <int D, typename T>
+__global__ void kb_bc_pairs(const RemapArgs<T>* __restrict__ args, const int* __restrict__ off, int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const RemapArgs<T>* a = args + c;
+  const int lb = blockIdx.x - off[c];
+  const Geo g = global_geo(a->g);
+  d_bc_pairs<D>(global_leaves(a->Ln), a->gas, g.nbc, g.bc_kind, g.bc_prim, gptr(a->bcpair), lb % a->nbl, lb / a->nbl);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void kb_bnd_tables(const RemapArgs<T>* __restrict__ args,
+                                                       const int* __restrict__ off, int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const RemapArgs<T>* a = args + c;
+  d_bnd_tables<D>(global_geo(a->g), global_leaves(a->Ln), gptr(a->bcpair), gptr(a->bden), gptr(a->bfin),
+                  blockIdx.x - off[c]);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(BLOCK) void kb_cell_moments(const RemapArgs<T>* __restrict__ args,
+                                                         const int* __restrict__ off, int ncase) {
+  const int c = find_case(off, ncase, blockIdx.x);
+  const RemapArgs<T>* a = args + c;
+  d_cell_moments<D, T>(global_geo(a->g), global_leaves(a->Ln), gptr(a->vout), gptr(a->W), gptr(a->mom), gptr(a->q),
+                       blockIdx.x - off[c]);
 }
 
 }  // namespace avs
