@@ -446,7 +446,9 @@ __global__ __launch_bounds__(BLOCK) void k_init_vdf(Geo g, Leaves L, VGrid vg, G
 // ------------------------------------------------------- cell moments / q
 // M[phi_i] and q_i = 1/2 sum A c (c^2 G + H), c = xi - U(W_i) (Eqs. updat_W, equ8).
 template <int D, typename T>
-__device__ __forceinline__ void d_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf, const double* __restrict__ W, double* __restrict__ mom, double* __restrict__ q, int bx) {
+__device__ __forceinline__ void d_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf,
+                                               const double* __restrict__ W, double* __restrict__ mom,
+                                               double* __restrict__ q, int bx) {
   constexpr int N = D + 2;
   __shared__ double red[4 * (N + D)];
   const int i = bx;
@@ -479,7 +481,8 @@ __device__ __forceinline__ void d_cell_moments(Geo g, Leaves L, const T* __restr
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void k_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf, const double* __restrict__ W, double* __restrict__ mom, double* __restrict__ q) {
+__global__ __launch_bounds__(BLOCK) void k_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf,
+                             const double* __restrict__ W, double* __restrict__ mom, double* __restrict__ q) {
   d_cell_moments<D, T>(g, L, vdf, W, mom, q, blockIdx.x);
 }
 
@@ -1527,7 +1530,9 @@ __global__ __launch_bounds__(BLOCK, (waves_hint<D, T>())) void k_passC(Geo g, Le
 // ----------------------------------------------- boundary Maxwellians (S7)
 // Per bc and leaf: the incoming Maxwellian pair (unit density for walls).
 template <int D>
-__device__ __forceinline__ void d_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ kind, const double* __restrict__ prim, double* __restrict__ pair, int bx, int by) {
+__device__ __forceinline__ void d_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ kind,
+                                           const double* __restrict__ prim, double* __restrict__ pair, int bx,
+                                           int by) {
   constexpr int P = Cfg<D>::P;
   const int k = bx * BLOCK + threadIdx.x;
   const int b = by;
@@ -1546,13 +1551,15 @@ __device__ __forceinline__ void d_bc_pairs(Leaves L, GasP gas, int nbc, const in
 }
 
 template <int D>
-__global__ void k_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ kind, const double* __restrict__ prim, double* __restrict__ pair) {
+__global__ void k_bc_pairs(Leaves L, GasP gas, int nbc, const int* __restrict__ kind, const double* __restrict__ prim,
+                           double* __restrict__ pair) {
   d_bc_pairs<D>(L, gas, nbc, kind, prim, pair, blockIdx.x, blockIdx.y);
 }
 
 // Per boundary face: den = sum_{s<0} A |s| g_wall and Fin = sum_{s<0} A s psi pair.
 template <int D>
-__device__ __forceinline__ void d_bnd_tables(Geo g, Leaves L, const double* __restrict__ pair, double* __restrict__ bden, double* __restrict__ bfin, int bx) {
+__device__ __forceinline__ void d_bnd_tables(Geo g, Leaves L, const double* __restrict__ pair,
+                                             double* __restrict__ bden, double* __restrict__ bfin, int bx) {
   constexpr int P = Cfg<D>::P, N = D + 2;
   __shared__ double red[4 * (N + 1)];
   const int f = g.f_bnd[bx];
@@ -1583,7 +1590,8 @@ __device__ __forceinline__ void d_bnd_tables(Geo g, Leaves L, const double* __re
 }
 
 template <int D>
-__global__ __launch_bounds__(BLOCK) void k_bnd_tables(Geo g, Leaves L, const double* __restrict__ pair, double* __restrict__ bden, double* __restrict__ bfin) {
+__global__ __launch_bounds__(BLOCK) void k_bnd_tables(Geo g, Leaves L, const double* __restrict__ pair,
+                             double* __restrict__ bden, double* __restrict__ bfin) {
   d_bnd_tables<D>(g, L, pair, bden, bfin, blockIdx.x);
 }
 
@@ -1795,7 +1803,9 @@ __global__ void k_scatter(Leaves L, const int8_t* __restrict__ eff, const int* _
 // Gather the new rows (copy or pairwise mean of 2^D brothers) and the
 // moments W' of the result.
 template <int D, typename T>
-__device__ __forceinline__ void d_remap_gather(Geo g, Leaves Lo, Leaves Ln, const int* __restrict__ kind, const int* __restrict__ src, const T* __restrict__ vin, T* __restrict__ vout, double* __restrict__ momp, int bx) {
+__device__ __forceinline__ void d_remap_gather(Geo g, Leaves Lo, Leaves Ln, const int* __restrict__ kind,
+                                               const int* __restrict__ src, const T* __restrict__ vin,
+                                               T* __restrict__ vout, double* __restrict__ momp, int bx) {
 #pragma clang fp contract(off)
   constexpr int P = Cfg<D>::P, N = D + 2;
   __shared__ double red[4 * N];
@@ -1833,14 +1843,18 @@ __device__ __forceinline__ void d_remap_gather(Geo g, Leaves Lo, Leaves Ln, cons
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void k_remap_gather(Geo g, Leaves Lo, Leaves Ln, const int* __restrict__ kind, const int* __restrict__ src, const T* __restrict__ vin, T* __restrict__ vout, double* __restrict__ momp) {
+__global__ __launch_bounds__(BLOCK) void k_remap_gather(Geo g, Leaves Lo, Leaves Ln, const int* __restrict__ kind,
+                             const int* __restrict__ src, const T* __restrict__ vin, T* __restrict__ vout,
+                             double* __restrict__ momp) {
   d_remap_gather<D, T>(g, Lo, Ln, kind, src, vin, vout, momp, blockIdx.x);
 }
 
 // Conservation correction of Sec. 3.3: f = f' + g_eq(W) - g_eq(W'), then
 // (mode 2) the closure that restores M[f] = W.  In place on the new rows.
 template <int D, typename T>
-__device__ __forceinline__ void d_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode, const double* __restrict__ W, const double* __restrict__ momp, T* __restrict__ vdf, int* __restrict__ bad, int bx) {
+__device__ __forceinline__ void d_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode,
+                                                const double* __restrict__ W, const double* __restrict__ momp,
+                                                T* __restrict__ vdf, int* __restrict__ bad, int bx) {
   constexpr int P = Cfg<D>::P, N = D + 2, NS = Cfg<D>::NS;
   extern __shared__ double lds[];
   double* tabA = lds;
@@ -1910,7 +1924,9 @@ __device__ __forceinline__ void d_remap_correct(Geo g, Leaves L, VGrid vg, GasP 
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode, const double* __restrict__ W, const double* __restrict__ momp, T* __restrict__ vdf, int* __restrict__ bad) {
+__global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode,
+                             const double* __restrict__ W, const double* __restrict__ momp, T* __restrict__ vdf,
+                             int* __restrict__ bad) {
   d_remap_correct<D, T>(g, L, vg, gas, mode, W, momp, vdf, bad, blockIdx.x);
 }
 
