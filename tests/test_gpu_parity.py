@@ -738,6 +738,21 @@ def test_batch_matches_single_cases_bit_for_bit(avs, prec):
             va, Wa = a.get_state()
             vb, Wb = b.get_state()
             assert np.array_equal(va, vb) and np.array_equal(Wa, Wb)
+        # every correction of the batched remap (0-2 span all members, 3-4 per member)
+        for corr in (0, 1, 3, 4):
+            batch.step(1)
+            for cs in solo:
+                cs.step(1)
+            C1 = [0.01, 2e-3, 0.004]
+            for cs, c1 in zip(solo, C1):
+                cs.adapt(c1, math.exp(-8) * c1)
+                cs.remap(corr)
+            batch.adapt(C1, [math.exp(-8) * c1 for c1 in C1])
+            batch.remap(corr)
+            for a, b in zip(solo, grouped):
+                va, Wa = a.get_state()
+                vb, Wb = b.get_state()
+                assert np.array_equal(va, vb) and np.array_equal(Wa, Wb), corr
         batch.close()
 
 
