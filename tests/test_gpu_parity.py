@@ -757,6 +757,60 @@ def test_batch_matches_single_cases_bit_for_bit(avs, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_batch_3d_matches_single_cases_bit_for_bit(avs, prec):
+    """Three 3-D cases (a box with walls, a small sphere grid, tetrahedra)
+    advanced by the batched kernels through the captured graph, then one
+    batched adaptation and the batched remap: states, leaf counts and leaves
+    equal the same cases advanced one by one, bit for bit."""
+    import torch
+    stream = torch.cuda.Stream()
+    specs = []
+    mesh = MM.box3d(3, 3, 2, periodic=(True, False, True))
+    vs = dict(dim=3, lo=(-5,) * 3, hi=(5,) * 3, base=(4,) * 3, max_level=1)
+    specs.append((mesh, vs, dict(R=1.0, Pr=2 / 3, omega=0.74, mu_ref=0.05, T_ref=1.0, model=1), 0.004, 1.0,
+                  F.perturbed_uniform(mesh['ncells'], 3, 9, amp=0.05, uamp=0.3), random_tree(vs, 6, 1, p=0.25)))
+    c = F.sphere(nr=3, nth=4, nph=4, Ma=2.0, box=5.0, base=8, max_level=1, r1=1.5, first=0.2)
+    specs.append((c['mesh'], c['vspace'], c['gas'], c['dt'], 0.0, c['prim0'], resolved_tree(c['vspace'], 6)))
+    mesh = MM.tet_box(2, 2, 2, 51)
+    vs = dict(dim=3, lo=(-5.0,) * 3, hi=(5.0,) * 3, base=(4, 4, 4), max_level=1)
+    specs.append((mesh, vs, dict(R=1.0, Pr=2 / 3, omega=0.5, mu_ref=0.05, T_ref=1.0, model=1), 1e-3, 1.0,
+                  F.perturbed_uniform(mesh['ncells'], 3, 52, amp=0.1, uamp=0.4), random_tree(vs, 53, 1)))
+
+    def build():
+        out = []
+        for mesh, vs, gas, dt, K, prim, tree in specs:
+            cs = avs.Case(mesh, vs, gas, dt, K, prim, precision=prec, stream=stream)
+            cs.set_leaves(tree.level, tree.idx)
+            out.append(cs)
+        return out
+    with torch.cuda.stream(stream):
+        solo, grouped = build(), build()
+        batch = avs.Batch(grouped)
+        batch.step(3, graph=True)
+        for cs in solo:
+            cs.step(3)
+        C1 = [1e-3, 2e-3, 5e-4]
+        n0 = [cs.nleaves() for cs in grouped]
+        nn_solo = []
+        for cs, c1 in zip(solo, C1):
+            nn_solo.append(cs.adapt(c1, math.exp(-8) * c1)[1])
+            cs.remap(2)
+        nn = batch.adapt(C1, [math.exp(-8) * c1 for c1 in C1])
+        batch.remap(2)
+        assert list(nn) == nn_solo and list(nn) != n0
+        batch.step(2, graph=True)
+        for cs in solo:
+            cs.step(2)
+        for a, b in zip(solo, grouped):
+            la, lb = a.leaves(), b.leaves()
+            assert np.array_equal(la['level'], lb['level']) and np.array_equal(la['idx'], lb['idx'])
+            va, Wa = a.get_state()
+            vb, Wb = b.get_state()
+            assert np.array_equal(va, vb) and np.array_equal(Wa, Wb)
+        batch.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_batch_tuning_leaves_the_state_unchanged(avs, prec):
     """avs_batch_tune times its candidates on steps it does not take: the
     members' state (VDF, W, and the heat flux the next step's target uses)
