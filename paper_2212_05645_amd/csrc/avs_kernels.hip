@@ -666,7 +666,12 @@ __device__ __forceinline__ void lim_parts(const Stencil<D, T>& st, const Stencil
           }
         }
       }
-      lim[p] = Nm / Dm;
+      // FP32: the hardware reciprocal (1 ulp) and one product in place of the
+      // correctly rounded quotient; Dm lies in [1e-30, 1e16], a normal range
+      if constexpr (sizeof(T) == 4)
+        lim[p] = Nm * __builtin_amdgcn_rcpf(Dm);
+      else
+        lim[p] = Nm / Dm;
     }
   }
 }
@@ -845,7 +850,10 @@ __device__ __forceinline__ void passA_cell(PassAShared<D, T>& sh, const Geo& g, 
         for (int p = 0; p < P; ++p) u[p] = 0;
         if (FULL || s < ns) {
           const double sn = normal_speed<D>(xi, Stencil<D, T>::kLds ? s_nrm + s * D : nrm[s]);
-          const bool up = (lside >> s) & 1u ? (sn >= 0.0) : (sn < 0.0);
+          // L side: upwind for sn >= 0; R side: for sn < 0, the complement
+          // (sn is finite).  One compare and a lane-mask xor with the
+          // uniform side bit.
+          const bool up = (sn >= 0.0) != !((lside >> s) & 1u);
           if (up) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
