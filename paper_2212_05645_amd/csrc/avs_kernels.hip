@@ -73,8 +73,16 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
     for (int m = 0; m < N; ++m) red[w * N + m] = v[m];
   }
   __syncthreads();
+  // one entry's four partials at a time: the empty asm that takes the sum
+  // as an operand, with a memory clobber, forms each total before the next
+  // entry is read (otherwise all 4N reads are issued at once and the sums
+  // sunk past the barrier: for N = 25 that held 200 registers and set the
+  // occupancy of the whole kernel)
 #pragma unroll
-  for (int m = 0; m < N; ++m) v[m] = (red[m] + red[N + m]) + (red[2 * N + m] + red[3 * N + m]);
+  for (int m = 0; m < N; ++m) {
+    v[m] = (red[m] + red[N + m]) + (red[2 * N + m] + red[3 * N + m]);
+    __asm__ volatile("" : "+v"(v[m]) : : "memory");
+  }
   __syncthreads();
 }
 
