@@ -662,13 +662,19 @@ avs_status launch_remap(avs_ctx* ctx, int correction) {
     CKL();
   }
   if (correction > 0) {
+    // the correction also leaves the moments and heat flux of the new state
+    // (remap_leaves_moments)
     ProfScope ps(ctx, K_REMAP_CORRECT);
     k_remap_correct<D, T><<<ctx->nc, BLOCK, (size_t)2 * D * ctx->vg.numax * sizeof(double), ctx->stream>>>(
-        ctx->geo, Ln, ctx->vg, ctx->gas, correction, ctx->W, ctx->momp, vout, ctx->bad);
+        ctx->geo, Ln, ctx->vg, ctx->gas, correction, ctx->W, ctx->momp, vout, ctx->bad, ctx->mom, ctx->q);
     CKL();
   }
   return AVS_OK;
 }
+
+// Corrections 1 and 2 form the moments of the new state in the correction
+// kernel; the others need the moments pass after the remap.
+inline bool remap_leaves_moments(int correction) { return correction == 1 || correction == 2; }
 
 // Dynamic LDS of the sweep and remap kernels beyond the default 64 KiB (up
 // to kLdsMax per workgroup on gfx950): the per-axis Maxwellian tables grow
@@ -1928,7 +1934,8 @@ avs_status avs_remap(avs_ctx* ctx, int32_t correction) {
   ++ctx->leaf_gen;
   ctx->plan_valid = false;
   if (avs_status st = DISPATCH_D(ctx, launch_bc_tables, ctx)) return st;
-  if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
+  if (!remap_leaves_moments(correction))
+    if (avs_status st = DISPATCH(ctx, launch_moments, ctx)) return st;
   return check_bad(ctx);
 }
 
@@ -2337,7 +2344,9 @@ avs_status batch_remap_launch(avs_batch* b, int correction) {
     a.nbl = (a.Ln.n + BLOCK - 1) / BLOCK;
     args[i] = a;
     numax = std::max(numax, c->vg.numax);
-    const int cnt[BR_N] = {c->nc, correction > 0 ? c->nc : 0, c->nbc > 0 ? a.nbl * c->nbc : 0, c->n_bnd, c->nc};
+    // the correction kernel forms the moments of the new state itself
+    const int cnt[BR_N] = {c->nc, correction > 0 ? c->nc : 0, c->nbc > 0 ? a.nbl * c->nbc : 0, c->n_bnd,
+                           remap_leaves_moments(correction) ? 0 : c->nc};
     for (int k = 0; k < BR_N; ++k) off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + cnt[k];
   }
   CK(hipMemcpyAsync(base, b->host_remap.data(), b->host_remap.size(), hipMemcpyHostToDevice, b->stream));
@@ -2412,7 +2421,8 @@ avs_status avs_batch_remap(avs_batch* b, int32_t correction) {
       ++c->leaf_gen;
       c->plan_valid = false;
       if (avs_status st = DISPATCH_D(c, launch_bc_tables, c)) return st;
-      if (avs_status st = DISPATCH(c, launch_moments, c)) return st;
+      if (!remap_leaves_moments(correction))
+        if (avs_status st = DISPATCH(c, launch_moments, c)) return st;
     }
   }
   CK(hipStreamSynchronize(b->stream));

@@ -453,6 +453,21 @@ __global__ __launch_bounds__(BLOCK) void k_init_vdf(Geo g, Leaves L, VGrid vg, G
 
 // ------------------------------------------------------- cell moments / q
 // M[phi_i] and q_i = 1/2 sum A c (c^2 G + H), c = xi - U(W_i) (Eqs. updat_W, equ8).
+// One leaf's share of a cell's moments (rho, m, rho E) and heat flux q
+// about U: acc[0..N) and acc[N..N+D).
+template <int D>
+__device__ __forceinline__ void state_mom_acc(double* acc, const double (&xi)[D], double A, const double (&U)[D],
+                                              double G, double H) {
+  constexpr int N = D + 2;
+  double xi2 = 0.0, c[D], c2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) { xi2 += xi[d] * xi[d]; c[d] = xi[d] - U[d]; c2 += c[d] * c[d]; }
+  mom_acc<D>(acc, A, xi, xi2, G, H);
+  const double e = 0.5 * A * (c2 * G + H);
+#pragma unroll
+  for (int d = 0; d < D; ++d) acc[N + d] += e * c[d];
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void d_cell_moments(Geo g, Leaves L, const T* __restrict__ vdf,
                                                const double* __restrict__ W, double* __restrict__ mom,
@@ -473,13 +488,7 @@ __device__ __forceinline__ void d_cell_moments(Geo g, Leaves L, const T* __restr
     leaf_load<D>(L, k, xi, A, u);
     const double G = ld_(vdf + (size_t)i * L.ld + k);
     const double H = (D == 2) ? ld_(vdf + cs + (size_t)i * L.ld + k) : 0.0;
-    double xi2 = 0.0, c[D], c2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) { xi2 += xi[d] * xi[d]; c[d] = xi[d] - U[d]; c2 += c[d] * c[d]; }
-    mom_acc<D>(acc, A, xi, xi2, G, H);
-    const double e = 0.5 * A * (c2 * G + H);
-#pragma unroll
-    for (int d = 0; d < D; ++d) acc[N + d] += e * c[d];
+    state_mom_acc<D>(acc, xi, A, U, G, H);
   }
   block_sum<N + D>(acc, red);
   if (threadIdx.x == 0) {
@@ -1867,10 +1876,13 @@ __global__ __launch_bounds__(BLOCK) void k_remap_gather(Geo g, Leaves Lo, Leaves
 
 // Conservation correction of Sec. 3.3: f = f' + g_eq(W) - g_eq(W'), then
 // (mode 2) the closure that restores M[f] = W.  In place on the new rows.
+// With mom non-null, also the moments and heat flux of the corrected rows
+// (those of d_cell_moments: same leaf order per thread, same sums).
 template <int D, typename T>
 __device__ __forceinline__ void d_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode,
                                                 const double* __restrict__ W, const double* __restrict__ momp,
-                                                T* __restrict__ vdf, int* __restrict__ bad, int bx) {
+                                                T* __restrict__ vdf, int* __restrict__ bad, double* __restrict__ mom,
+                                                double* __restrict__ q, int bx) {
   constexpr int P = Cfg<D>::P, N = D + 2, NS = Cfg<D>::NS;
   extern __shared__ double lds[];
   double* tabA = lds;
@@ -1921,6 +1933,12 @@ __device__ __forceinline__ void d_remap_correct(Geo g, Leaves L, VGrid vg, GasP 
   }
   __syncthreads();
   const size_t cs = (size_t)g.nc * L.ld;
+  double U[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) U[d] = W[(size_t)i * N + 1 + d] / W[(size_t)i * N];
+  double macc[N + D];
+#pragma unroll
+  for (int m = 0; m < N + D; ++m) macc[m] = 0.0;
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
     double xi[D], A;
     int u[D];
@@ -1934,16 +1952,29 @@ __device__ __forceinline__ void d_remap_correct(Geo g, Leaves L, VGrid vg, GasP 
     }
     poly += lam[D + 1] * c2;
     T* r = vdf + (size_t)i * L.ld + k;
-    r[0] = (T)(ld_(r) + (ga - gb) + poly * ga);
-    if (P == 2) r[cs] = (T)(ld_(r + cs) + (parA[P_RT] * ga - parB[P_RT] * gb) + poly * parA[P_RT] * ga);
+    const T G = (T)(ld_(r) + (ga - gb) + poly * ga);
+    r[0] = G;
+    T H = 0;
+    if (P == 2) {
+      H = (T)(ld_(r + cs) + (parA[P_RT] * ga - parB[P_RT] * gb) + poly * parA[P_RT] * ga);
+      r[cs] = H;
+    }
+    if (mom) state_mom_acc<D>(macc, xi, A, U, (double)G, (double)H);
+  }
+  if (mom) {
+    block_sum<N + D>(macc, red);
+    if (threadIdx.x == 0) {
+      for (int m = 0; m < N; ++m) mom[(size_t)i * N + m] = macc[m];
+      for (int d = 0; d < D; ++d) q[(size_t)i * D + d] = macc[N + d];
+    }
   }
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(BLOCK) void k_remap_correct(Geo g, Leaves L, VGrid vg, GasP gas, int mode,
                              const double* __restrict__ W, const double* __restrict__ momp, T* __restrict__ vdf,
-                             int* __restrict__ bad) {
-  d_remap_correct<D, T>(g, L, vg, gas, mode, W, momp, vdf, bad, blockIdx.x);
+                             int* __restrict__ bad, double* __restrict__ mom, double* __restrict__ q) {
+  d_remap_correct<D, T>(g, L, vg, gas, mode, W, momp, vdf, bad, mom, q, blockIdx.x);
 }
 
 // -------------------------------------------------- residual, totals, fields
@@ -2171,7 +2202,7 @@ __global__ __launch_bounds__(BLOCK) void kb_remap_correct(const RemapArgs<T>* __
   const int c = find_case(off, ncase, blockIdx.x);
   const RemapArgs<T>* a = args + c;
   d_remap_correct<D, T>(global_geo(a->g), global_leaves(a->Ln), a->vg, a->gas, mode, gptr(a->W), gptr(a->momp),
-                        gptr(a->vout), gptr(a->bad), blockIdx.x - off[c]);
+                        gptr(a->vout), gptr(a->bad), gptr(a->mom), gptr(a->q), blockIdx.x - off[c]);
 }
 
 template <int D, typename T>
