@@ -1838,29 +1838,50 @@ __device__ __forceinline__ void d_remap_gather(Geo g, Leaves Lo, Leaves Ln, cons
   const size_t cso = (size_t)g.nc * Lo.ld, csn = (size_t)g.nc * Ln.ld;
   double acc[N];
   for (int m = 0; m < N; ++m) acc[m] = 0.0;
-  for (int j = threadIdx.x; j < Ln.n; j += BLOCK) {
-    const int k = src[j];
-    const bool mg = kind[j] == 2;
-    T v[P];
-    for (int p = 0; p < P; ++p) {
-      const T* r = vin + p * cso + (size_t)i * Lo.ld + k;
-      if (mg) {
-        if (D == 2) {
-          v[p] = ((r[0] + r[1]) + (r[2] + r[3])) * (T)0.25;
-        } else {
-          v[p] = (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]))) * (T)0.125;
-        }
-      } else {
-        v[p] = r[0];
-      }
-      vout[p * csn + (size_t)i * Ln.ld + j] = v[p];
+  // four leaves per thread in flight: the source indices and leaf data of
+  // the group first, then every leaf's first source value, and only then
+  // the other children of merged leaves, the stores and the sums (a leaf at
+  // a time made each row read wait on its index load).  The sums keep the
+  // order of one leaf after another; a slot past the end re-reads the last
+  // leaf and is dropped.
+  constexpr int U = 4;
+  for (int j0 = threadIdx.x; j0 < Ln.n; j0 += U * BLOCK) {
+    int kk[U];
+    bool mg[U];
+    double xi[U][D], A[U];
+    T v[U][P];
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const int j = min(j0 + t * BLOCK, Ln.n - 1);
+      kk[t] = src[j];
+      mg[t] = kind[j] == 2;
+      int u[D];
+      leaf_load<D>(Ln, j, xi[t], A[t], u);
     }
-    double xi[D], A;
-    int u[D];
-    leaf_load<D>(Ln, j, xi, A, u);
-    double xi2 = 0.0;
-    for (int d = 0; d < D; ++d) xi2 += xi[d] * xi[d];
-    mom_acc<D>(acc, A, xi, xi2, (double)v[0], P == 2 ? (double)v[P - 1] : 0.0);
+#pragma unroll
+    for (int t = 0; t < U; ++t)
+#pragma unroll
+      for (int p = 0; p < P; ++p) v[t][p] = vin[p * cso + (size_t)i * Lo.ld + kk[t]];
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const int j = j0 + t * BLOCK;
+      if (j >= Ln.n) break;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if (mg[t]) {
+          const T* r = vin + p * cso + (size_t)i * Lo.ld + kk[t];
+          if (D == 2) {
+            v[t][p] = ((v[t][p] + r[1]) + (r[2] + r[3])) * (T)0.25;
+          } else {
+            v[t][p] = (((v[t][p] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]))) * (T)0.125;
+          }
+        }
+        vout[p * csn + (size_t)i * Ln.ld + j] = v[t][p];
+      }
+      double xi2 = 0.0;
+      for (int d = 0; d < D; ++d) xi2 += xi[t][d] * xi[t][d];
+      mom_acc<D>(acc, A[t], xi[t], xi2, (double)v[t][0], P == 2 ? (double)v[t][P - 1] : 0.0);
+    }
   }
   block_sum<N>(acc, red);
   if (threadIdx.x == 0)
