@@ -1006,7 +1006,7 @@ __device__ __forceinline__ void raw_flux(const double* m, const double* n, doubl
 // Faces per face_eq workgroup: each leaf is loaded once for all of them and
 // their records are formed in parallel, one thread per face.
 #ifndef AVS_FACE_BATCH2
-#define AVS_FACE_BATCH2 2
+#define AVS_FACE_BATCH2 4
 #endif
 #ifndef AVS_FACE_BATCH3
 #define AVS_FACE_BATCH3 4
