@@ -444,9 +444,10 @@ avs_status launch_interfaces(avs_ctx* ctx) {
   const Leaves L = ctx->leaves(ctx->lcur);
   const int nu = ctx->vg.numax;
   const T* vin = (const T*)ctx->vdf[ctx->cur];
-  // pass-A leaves per workgroup: twice the chunk in the FP32 form (its
-  // workgroups are half as long per leaf; 16384 measured 1 % faster there,
-  // no faster in FP64)
+  // pass-A leaves per workgroup: twice the chunk in the FP32 form, where a
+  // leaf costs about half as much, so that the per-workgroup set-up and
+  // reductions keep the same share (16384 measured 1 % faster there, no
+  // faster in FP64)
   const int chunk = sizeof(T) == 4 ? 2 * CHUNK : CHUNK;
   const int nch = (L.n + chunk - 1) / chunk;
   {
