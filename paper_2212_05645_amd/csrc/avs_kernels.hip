@@ -1128,10 +1128,23 @@ __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, d
   double acc[FB * N];
 #pragma unroll
   for (int t = 0; t < FB * N; ++t) acc[t] = 0.0;
+  // 2-D: the next leaf's entry is loaded while this one is used (in 3-D the
+  // registers it takes would cost a wave per SIMD)
+  constexpr bool PRE = D == 2;
+  double xi_n[D], A_n = 0.0;
+  int u_n[D];
+  if (PRE && (int)threadIdx.x < L.n) leaf_load<D>(L, threadIdx.x, xi_n, A_n, u_n);
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
     double xi[D], A;
     int u[D];
-    leaf_load<D>(L, k, xi, A, u);
+    if constexpr (PRE) {
+      A = A_n;
+#pragma unroll
+      for (int d = 0; d < D; ++d) { xi[d] = xi_n[d]; u[d] = u_n[d]; }
+      if (k + BLOCK < L.n) leaf_load<D>(L, k + BLOCK, xi_n, A_n, u_n);
+    } else {
+      leaf_load<D>(L, k, xi, A, u);
+    }
     R xr[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) xr[d] = (R)xi[d];
