@@ -333,6 +333,16 @@ __device__ __forceinline__ double normal_speed(const double (&xi)[D], const doub
   return s;
 }
 
+// xi . n where it only weighs a flux (no side is chosen from it): fused
+// multiply-adds, one instruction fewer per dimension than normal_speed.
+template <int D>
+__device__ __forceinline__ double flux_weight(const double (&xi)[D], const double* n) {
+  double s = xi[0] * n[0];
+#pragma unroll
+  for (int d = 1; d < D; ++d) s = fma(xi[d], n[d], s);
+  return s;
+}
+
 // Moment contribution sum A (G, xi G, (|xi|^2 G + H)/2).
 template <int D>
 __device__ __forceinline__ void mom_acc(double* M, double A, const double (&xi)[D], double xi2, double G, double H) {
@@ -1157,7 +1167,7 @@ __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, d
       const R gv = maxw_r<D, R>(rp[s], tab + s * D * vg.numax, vg.numax, u);
       R G, H;
       shakhov_r<D, R>(rp[s], gv, xr, G, H);
-      const double sn = normal_speed<D>(xi, snrm[s]);
+      const double sn = flux_weight<D>(xi, snrm[s]);
       mom_acc<D>(acc + s * N, A * sn, xi, xi2, (double)G, (double)H);
     }
   }
