@@ -369,7 +369,7 @@ int32_t avs_profile_read(avs_ctx *ctx, int32_t nmax, char *names_host, double *m
  * members stay usable on their own (adapt, remap, moments) between batch
  * steps.  The batch workspace (device, avs_batch_workspace_bytes) holds the
  * per-case argument tables.  avs_batch_tune chooses two tile parameters
- * by timing: the leaf chunk of pass A (512..8192 leaves per workgroup) per
+ * by timing: the leaf chunk of pass A (512..16384 leaves per workgroup) per
  * leaf-count bucket of the members (< 1024, < 4096, < 16384, more leaves),
  * one bucket at a time, then whether pass C keeps one or two leaves' loads
  * in flight; each candidate is timed on two steps computed into the spare

@@ -2447,7 +2447,7 @@ avs_status avs_batch_check(avs_batch* b) {
 avs_status avs_batch_tune(avs_batch* b, int32_t* chunk_host) {
   if (!b) return fail(AVS_E_INVALID, "null batch");
   avs_ctx* ctx = nullptr;
-  const int cand[] = {512, 1024, 2048, 4096, 8192};
+  const int cand[] = {512, 1024, 2048, 4096, 8192, 16384};
   bool present[4] = {false, false, false, false};
   for (avs_ctx* c : b->cases) present[leaf_bucket(c->nleaf[c->lcur])] = true;
   hipEvent_t e0, e1;
