@@ -125,6 +125,10 @@ struct avs_ctx {
     L.u = lt[t].u;
     L.xi = lt[t].xi;
     L.w = lt[t].w;
+    for (int d = 0; d < 3; ++d) {
+      L.xd[d] = lt[t].xi + (d < D ? (size_t)d * cap : 0);
+      L.ud[d] = lt[t].u + (d < D ? (size_t)d * cap : 0);
+    }
     return L;
   }
   size_t esize() const { return prec == AVS_FP32 ? 4 : 8; }

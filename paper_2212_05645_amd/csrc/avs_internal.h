@@ -64,6 +64,11 @@ struct Leaves {
   const int* u;       // [D*cap] centre on the half-finest grid: (2 idx + 1) << (Lmax - level)
   const double* xi;   // [D*cap]
   const double* w;    // [cap]
+  // rows of each dimension, xi + d cap and u + d cap (the first row beyond
+  // D): passed as such, a load is a scalar base plus the lane's 32-bit
+  // offset, where base + d cap + offset became a 64-bit vector add per load
+  const double* xd[3];
+  const int* ud[3];
 };
 
 struct VGrid {          // the half-finest grid that carries every leaf centre

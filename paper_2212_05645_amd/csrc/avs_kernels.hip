@@ -363,6 +363,19 @@ __device__ __forceinline__ void leaf_load(const Leaves& L, int k, double (&xi)[D
   A = at_(L.w, (unsigned)k * 8u);
 }
 
+// The same from the per-dimension row pointers: each load a scalar base
+// plus the lane offset (in the kernels whose scalar registers have room:
+// face_eq and the target; pass A and pass C run out of them).
+template <int D>
+__device__ __forceinline__ void leaf_load_rows(const Leaves& L, int k, double (&xi)[D], double& A, int (&u)[D]) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    xi[d] = at_(L.xd[d], (unsigned)k * 8u);
+    u[d] = at_(L.ud[d], (unsigned)k * 4u);
+  }
+  A = at_(L.w, (unsigned)k * 8u);
+}
+
 // ---------------------------------------------------------- leaf geometry
 // xi = lo + (idx + 1/2) h_l, A = prod h_l, h_l = (hi - lo)/(base 2^l); the
 // operation order matches the oracle exactly (no contraction) so that the
@@ -1143,7 +1156,7 @@ __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, d
   constexpr bool PRE = D == 2;
   double xi_n[D], A_n = 0.0;
   int u_n[D];
-  if (PRE && (int)threadIdx.x < L.n) leaf_load<D>(L, threadIdx.x, xi_n, A_n, u_n);
+  if (PRE && (int)threadIdx.x < L.n) leaf_load_rows<D>(L, threadIdx.x, xi_n, A_n, u_n);
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
     double xi[D], A;
     int u[D];
@@ -1151,9 +1164,9 @@ __device__ __forceinline__ void d_face_eq(Geo g, Leaves L, VGrid vg, GasP gas, d
       A = A_n;
 #pragma unroll
       for (int d = 0; d < D; ++d) { xi[d] = xi_n[d]; u[d] = u_n[d]; }
-      if (k + BLOCK < L.n) leaf_load<D>(L, k + BLOCK, xi_n, A_n, u_n);
+      if (k + BLOCK < L.n) leaf_load_rows<D>(L, k + BLOCK, xi_n, A_n, u_n);
     } else {
-      leaf_load<D>(L, k, xi, A, u);
+      leaf_load_rows<D>(L, k, xi, A, u);
     }
     R xr[D];
 #pragma unroll
@@ -1265,7 +1278,7 @@ __device__ __forceinline__ void d_target(Geo g, Leaves L, VGrid vg, const double
   for (int k = threadIdx.x; k < L.n; k += BLOCK) {
     double xi[D], A;
     int u[D];
-    leaf_load<D>(L, k, xi, A, u);
+    leaf_load_rows<D>(L, k, xi, A, u);
     R xr[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) xr[d] = (R)xi[d];
@@ -2152,6 +2165,7 @@ __device__ __forceinline__ Geo global_geo(Geo g) {
 }
 __device__ __forceinline__ Leaves global_leaves(Leaves L) {
   AVS_G(L.level); AVS_G(L.idx); AVS_G(L.u); AVS_G(L.xi); AVS_G(L.w);
+  AVS_G(L.xd[0]); AVS_G(L.xd[1]); AVS_G(L.xd[2]); AVS_G(L.ud[0]); AVS_G(L.ud[1]); AVS_G(L.ud[2]);
   return L;
 }
 #undef AVS_G
